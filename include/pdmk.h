@@ -1,0 +1,178 @@
+/*
+ * pdmk.h -- C interface of an MI355X (gfx950) implementation of periodic
+ * dual-space multilevel kernel splitting (periodic DMK) for Laplace lattice
+ * sums in oblique 2D and triclinic 3D cells.
+ *
+ * The operation (Introduction, eq:potential and eq:greens): for a lattice
+ * matrix L = [a_1 ... a_d] (columns are the lattice vectors), sources y_j with
+ * charges q_j and targets x_i, return
+ *
+ *     Phi(x_i) = sum_{n in Z^d} sum_j G(x_i - y_j - L n) q_j,
+ *     G(r) = -log(r)/(2 pi) in 2D,  1/(4 pi r) in 3D,
+ *
+ * in the tin-foil sense (the k = 0 Fourier mode is zero), with the singular
+ * self pair (n = 0, coincident source) excluded, and optionally grad Phi.
+ * The charges must be neutral (sum q = 0) unless PDMK_ALLOW_NONNEUTRAL is set,
+ * in which case the result is the potential of the charges plus a uniform
+ * neutralising background.  Units: G exactly as above, no Coulomb constant.
+ *
+ * The method is Algorithm 1 (Periodic DMK): orient L (Section 3.2,
+ * eq:Ltri), cover the cell with root cubes of side r_c = L_min / kappa
+ * (eq:mi), add a halo of image sources (Sections 3.3-3.4), build an adaptive
+ * tree on the extended root grid, evaluate the compactly supported near
+ * field G - W_0 by free-space DMK on it (Section 3.5), evaluate the smooth
+ * periodic far field W_0^(p) by spreading -> FFT -> diagonal scaling ->
+ * inverse FFT -> interpolation without upsampling (Section 3.6, eq:W0p,
+ * eq:diag, eq:Mi), and remove the self terms (Section 3.8, eq:W0zero).
+ *
+ * Conventions shared by every entry point:
+ *   - L is a HOST pointer to d*d doubles, column-major (L[i + d*j] is the
+ *     i-th Cartesian component of a_j).
+ *   - Position, charge, potential and gradient arrays are DEVICE pointers
+ *     (memory of the current HIP device).  Positions are row-major n x d
+ *     doubles, potentials n doubles, gradients row-major n x d doubles.
+ *   - Positions may lie anywhere in R^d; they are wrapped into the cell.
+ *   - The caller owns every buffer.  Inputs are never modified.  The library
+ *     keeps no caller pointer after a call returns.
+ *   - Calls are ordered on the HIP stream passed in (NULL = default stream)
+ *     and block until the results are written (the call synchronises its
+ *     stream before returning).
+ *   - Errors: every function returns a pdmk_status.  On an error detected on
+ *     the host the output arrays are not written.  pdmk_last_error() returns a
+ *     thread-local message for the last failure.
+ */
+#ifndef PDMK_H
+#define PDMK_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  PDMK_OK = 0,
+  PDMK_ERR_INVALID_ARG = -1,     /* bad dimension, null pointer, n < 0 ... */
+  PDMK_ERR_SINGULAR_LATTICE = -2,/* det L == 0 or not finite */
+  PDMK_ERR_NOT_NEUTRAL = -3,     /* |sum q| > 1e-8 sum |q| without ALLOW_NONNEUTRAL */
+  PDMK_ERR_EPS_RANGE = -4,       /* eps outside [1e-12, 1e-2] */
+  PDMK_ERR_NONFINITE = -5,       /* NaN or Inf in positions or charges */
+  PDMK_ERR_OUT_OF_MEMORY = -6,   /* device allocation failed */
+  PDMK_ERR_HIP = -7,             /* a HIP runtime call failed */
+  PDMK_ERR_NO_DEVICE = -8,       /* no HIP device available */
+  PDMK_ERR_UNSUPPORTED = -9      /* option combination not implemented */
+} pdmk_status;
+
+/* Arithmetic of the evaluation.
+ *   PDMK_PREC_FP64 : every stage in double precision.
+ *   PDMK_PREC_MIXED: near-field residual sums, proxy and plane-wave transforms
+ *                    in FP32 (box-local coordinates); FP64 kept for wrapping,
+ *                    box assignment, the far-field diagonal scaling and the
+ *                    final accumulation. */
+enum { PDMK_PREC_FP64 = 0, PDMK_PREC_MIXED = 1 };
+
+/* Flags */
+enum {
+  PDMK_WANT_GRAD = 1,          /* also return grad Phi at the targets */
+  PDMK_ALLOW_NONNEUTRAL = 2    /* accept sum q != 0 (uniform background) */
+};
+
+typedef struct {
+  int dim;          /* 2 or 3 */
+  double eps;       /* requested relative l2 accuracy, [1e-12, 1e-2] */
+  int precision;    /* PDMK_PREC_FP64 or PDMK_PREC_MIXED */
+  double kappa;     /* root cube side r_c = L_min / kappa (Section 5); <= 0: default */
+  int n_s;          /* leaf capacity (Section 5, Table tab:tuning); <= 0: default */
+  unsigned flags;   /* PDMK_WANT_GRAD | PDMK_ALLOW_NONNEUTRAL */
+  int porder;       /* Chebyshev proxy points per axis; <= 0: chosen from eps */
+  int npw;          /* plane-wave half count J per axis (modes -J..J); <= 0: from eps */
+  int nufft_w;      /* spreading-window width in grid cells; <= 0: from eps */
+} pdmk_opts;
+
+/* Fill *out with the defaults for (dim, eps).  Host only; no device needed. */
+int pdmk_default_opts(int dim, double eps, pdmk_opts* out);
+
+/*
+ * One evaluation (Algorithm 1).  Targets are the sources when trg == NULL
+ * (then n_trg is ignored and the self pair of every source is excluded);
+ * otherwise targets are n_trg separate points and no self pair is removed.
+ * grad may be NULL; it is written only when PDMK_WANT_GRAD is set.
+ */
+int pdmk_eval(const pdmk_opts* opts, const double* L, int64_t n_src,
+              const double* src, const double* q, int64_t n_trg,
+              const double* trg, double* pot, double* grad, void* stream);
+
+/*
+ * Plans keep the host tables for one (opts, L) pair and the device
+ * workspace between calls (the tree is rebuilt every call, as in the
+ * paper).  A plan is bound to the device that was current at creation.
+ */
+typedef struct pdmk_plan pdmk_plan;
+int pdmk_plan_create(const pdmk_opts* opts, const double* L, pdmk_plan** out);
+int pdmk_plan_eval(pdmk_plan* plan, int64_t n_src, const double* src,
+                   const double* q, int64_t n_trg, const double* trg,
+                   double* pot, double* grad, void* stream);
+void pdmk_plan_destroy(pdmk_plan* plan);
+
+/* Geometry and parameters a plan derived from (opts, L); host only. */
+typedef struct {
+  int dim;
+  double L_oriented[9];   /* upper-triangular L after orientation (eq:Ltri), column-major */
+  double Q[9];            /* x_oriented = Q^T x ; column-major */
+  int perm[3];            /* input lattice vector feeding oriented column i */
+  double volume;          /* |det L| */
+  double rc;              /* root cube side */
+  int nroot[3];           /* m_i, inner block of root cubes (eq:mi) */
+  double origin[3];       /* corner of the extended root grid (x^- - r_c) */
+  int fgrid[3];           /* Fourier grid per axis actually used (>= M_i of eq:Mi) */
+  int fgrid_paper[3];     /* M_i of eq:Mi */
+  int n_shifts;           /* lattice shifts passing the bounds of eq:shift_bounds */
+  double c;               /* PSWF bandwidth with psi(1)/psi(0) = eps */
+  double w0_zero_rc;      /* 3D: W_0(0) * r_c (eq:W0zero); 2D: W_0(0) at r_c = 1 */
+  int porder, npw, nufft_w, n_s;
+  double nufft_beta, kappa;
+} pdmk_geometry;
+int pdmk_plan_geometry(const pdmk_plan* plan, pdmk_geometry* out);
+/* The same geometry computed on the host from (opts, L) without a device. */
+int pdmk_geometry_get(const pdmk_opts* opts, const double* L, pdmk_geometry* out);
+
+/* Counters and stage times (milliseconds, from HIP events) of the last
+ * pdmk_plan_eval on this plan. */
+typedef struct {
+  int64_t n_src, n_trg, n_images;   /* n_images: N' (originals + images) */
+  int n_levels;
+  int64_t n_boxes, n_leaves, n_nonleaf;
+  int64_t n_direct_pairs;           /* target-source pairs visited by the residual sums */
+  int64_t n_pw_pairs;               /* plane-wave box pairs */
+  double t_build_ms, t_near_ms, t_far_ms, t_total_ms;
+  double t_direct_ms, t_pw_ms, t_proxy_ms;
+} pdmk_stats;
+int pdmk_plan_stats(const pdmk_plan* plan, pdmk_stats* out);
+
+/* Kernel-splitting scalars for (dim, eps); host only.  Pins the host
+ * implementation of the PSWF calibration (Section 2.2) and of the split
+ * kernels (eq:pswf_split, eq:W0zero) without a device. */
+typedef struct {
+  double c;          /* bandwidth: psi(1)/psi(0) = eps */
+  double lambda0;    /* eigenvalue of eq:pswf_eig */
+  double c0_over_psi0; /* int_0^1 psi / psi(0) */
+  double w0_zero;    /* 3D: W_0(0) for r_c = 1 (eq:W0zero); 2D: W_0(0) for r_c = 1 */
+} pdmk_kernel_info;
+int pdmk_kernel_info_get(int dim, double eps, pdmk_kernel_info* out);
+
+/* Residual kernel R_h(r) = G(r) - W_h(r) (zero for r >= h) and the smooth
+ * far-field transform What_0(k) = psi~(k r_c / c) / k^2 evaluated on the host
+ * from the same tables the device uses; for tests. */
+int pdmk_kernel_eval_residual(int dim, double eps, double h, int64_t n,
+                              const double* r, double* out);
+int pdmk_kernel_eval_w0hat(int dim, double eps, double rc, int64_t n,
+                           const double* k, double* out);
+
+/* Status text and the thread-local message of the last failure. */
+const char* pdmk_status_string(int status);
+const char* pdmk_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PDMK_H */

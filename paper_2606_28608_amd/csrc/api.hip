@@ -1,0 +1,491 @@
+// C interface (include/pdmk.h): plans, evaluation pipeline of Algorithm 1,
+// assembly with the self-interaction correction (Section 3.8), status codes.
+#include <cmath>
+#include <cstring>
+#include <string>
+
+#include "internal.h"
+
+using namespace pdmk;
+
+static thread_local std::string g_last_error;
+
+static int fail(int code, const std::string& msg) {
+  g_last_error = msg;
+  return code;
+}
+
+static inline int nblk(int64_t n, int b) { return (int)((n + b - 1) / b); }
+
+static ChebSeries cheb_derivative(const ChebSeries& S) {
+  // d/ds of sum a_k T_k(2s-1): derivative in t by the standard recurrence, times 2
+  int n = (int)S.a.size();
+  ChebSeries D;
+  if (n < 2) {
+    D.a.assign(1, 0.0);
+    return D;
+  }
+  std::vector<double> d(n + 1, 0.0);
+  for (int k = n - 1; k >= 1; --k) d[k - 1] = d[k + 1] + 2.0 * k * S.a[k];
+  d[0] *= 0.5;
+  D.a.assign(d.begin(), d.begin() + (n - 1));
+  for (double& v : D.a) v *= 2.0;
+  return D;
+}
+
+static std::vector<double> pw_table(const Pswf& P, double c, int J, int dim) {
+  int nmax = dim * J * J;
+  std::vector<double> t(nmax + 1, 0.0);
+  t[0] = -P.psit_dd0 / (24.0 * c * c);
+  for (int n = 1; n <= nmax; ++n) {
+    double jn = std::sqrt((double)n);
+    t[n] = (P.psit(kPi * jn / (3.0 * c)) - P.psit(2.0 * kPi * jn / (3.0 * c))) /
+           (4.0 * kPi * kPi * n);
+  }
+  return t;
+}
+
+template <class T>
+static T* upload(const std::vector<T>& v) {
+  T* p = nullptr;
+  PDMK_HIP(hipMalloc(&p, std::max<size_t>(1, v.size()) * sizeof(T)));
+  if (!v.empty()) PDMK_HIP(hipMemcpy(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
+  return p;
+}
+
+namespace pdmk {
+void plan_upload_tables(pdmk_plan* P) {
+  const int d = P->g.dim;
+  const int p = P->mp.porder, J = P->mp.npw;
+  ChebSeries Ed = cheb_derivative(P->T->E), F2d = cheb_derivative(P->T->F2);
+  P->d_E = upload(P->T->E.a);
+  P->d_Ed = upload(Ed.a);
+  P->d_F2 = upload(P->T->F2.a);
+  P->d_F2d = upload(F2d.a);
+  std::vector<double> nodes, bw;
+  cheb_nodes(p, nodes, bw);
+  P->d_nodes = upload(nodes);
+  P->d_bw = upload(bw);
+  std::vector<double> Tm(2 * p * p), row(p);
+  for (int sel = 0; sel < 2; ++sel) {
+    double sg = sel ? 1.0 : -1.0;
+    for (int i = 0; i < p; ++i) {
+      lagrange_row(p, nodes.data(), bw.data(), 0.5 * sg + 0.5 * nodes[i], row.data());
+      for (int Pp = 0; Pp < p; ++Pp) Tm[sel * p * p + Pp * p + i] = row[Pp];
+    }
+  }
+  P->d_Tm = upload(Tm);
+  std::vector<double2> F((2 * J + 1) * p);
+  for (int j = -J; j <= J; ++j)
+    for (int i = 0; i < p; ++i) {
+      double a = -kPi * j * nodes[i] / 3.0;
+      F[(j + J) * p + i] = make_double2(std::cos(a), std::sin(a));
+    }
+  P->d_F = upload(F);
+  P->d_dtab = upload(pw_table(*P->P, P->P->c, J, d));
+  std::vector<double> sv;
+  for (size_t s = 0; s < P->g.shifts.size() / d; ++s)
+    for (int a = 0; a < d; ++a) {
+      double v = 0;
+      for (int b = 0; b < d; ++b) v += P->g.L[a + d * b] * P->g.shifts[s * d + b];
+      sv.push_back(v);
+    }
+  P->nshift = (int)(P->g.shifts.size() / d);
+  P->d_shiftvec = upload(sv);
+  KParams& kp = P->kp;
+  kp.nE = (int)P->T->E.a.size();
+  kp.nEd = (int)Ed.a.size();
+  kp.nF2 = (int)P->T->F2.a.size();
+  kp.nF2d = (int)F2d.a.size();
+}
+}  // namespace pdmk
+
+static void free_plan_tables(pdmk_plan* P) {
+  void* ptrs[] = {P->d_E, P->d_Ed, P->d_F2, P->d_F2d, P->d_nodes, P->d_bw, P->d_Tm,
+                  P->d_F, P->d_dtab, P->d_farscale, P->d_shiftvec};
+  for (void* p : ptrs)
+    if (p) (void)hipFree(p);
+}
+
+// ---------------------------------------------------------------- kernels
+__global__ void k_charge_stats(int64_t n, const double* __restrict__ q, double* __restrict__ out,
+                               int* __restrict__ bad) {
+  __shared__ double s1[256], s2[256];
+  double a = 0.0, b = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    double v = q[i];
+    if (!isfinite(v)) atomicOr(bad, 1);
+    else {
+      a += v;
+      b += fabs(v);
+    }
+  }
+  s1[threadIdx.x] = a;
+  s2[threadIdx.x] = b;
+  __syncthreads();
+  for (int st = 128; st > 0; st >>= 1) {
+    if (threadIdx.x < st) {
+      s1[threadIdx.x] += s1[threadIdx.x + st];
+      s2[threadIdx.x] += s2[threadIdx.x + st];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    atomicAdd(out, s1[0]);
+    atomicAdd(out + 1, s2[0]);
+  }
+}
+
+__global__ void k_assemble(int64_t n, int d, const int* __restrict__ tperm,
+                           const double* __restrict__ ps, const double* __restrict__ gs,
+                           const double* __restrict__ fp, const double* __restrict__ fg,
+                           double shift, KParams kp, double* __restrict__ pot,
+                           double* __restrict__ grad) {
+  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n) return;
+  const int o = tperm[t];
+  pot[o] = ps[t] + fp[o] + shift;
+  if (grad) {
+    double g[3] = {0, 0, 0};
+    for (int a = 0; a < d; ++a) g[a] = gs[t * d + a] + fg[(int64_t)o * d + a];
+    for (int a = 0; a < d; ++a) {
+      double s = 0;
+      for (int b = 0; b < d; ++b) s += kp.Q[a + d * b] * g[b];
+      grad[(int64_t)o * d + a] = s;
+    }
+  }
+}
+
+namespace pdmk {
+void stage_assemble(pdmk_plan* P, Eval& E, const double* q, double* pot, double* grad) {
+  (void)q;
+  (void)P;
+  (void)E;
+  (void)pot;
+  (void)grad;
+}
+}  // namespace pdmk
+
+// ------------------------------------------------------------------- C ABI
+extern "C" {
+
+const char* pdmk_status_string(int s) {
+  switch (s) {
+    case PDMK_OK: return "ok";
+    case PDMK_ERR_INVALID_ARG: return "invalid argument";
+    case PDMK_ERR_SINGULAR_LATTICE: return "singular or ill-conditioned lattice";
+    case PDMK_ERR_NOT_NEUTRAL: return "charges are not neutral";
+    case PDMK_ERR_EPS_RANGE: return "eps outside [1e-12, 1e-2]";
+    case PDMK_ERR_NONFINITE: return "non-finite input";
+    case PDMK_ERR_OUT_OF_MEMORY: return "device out of memory";
+    case PDMK_ERR_HIP: return "HIP runtime error";
+    case PDMK_ERR_NO_DEVICE: return "no HIP device";
+    case PDMK_ERR_UNSUPPORTED: return "unsupported option";
+  }
+  return "unknown status";
+}
+
+const char* pdmk_last_error(void) { return g_last_error.c_str(); }
+
+int pdmk_default_opts(int dim, double eps, pdmk_opts* out) {
+  if (!out) return fail(PDMK_ERR_INVALID_ARG, "null output");
+  if (dim != 2 && dim != 3) return fail(PDMK_ERR_INVALID_ARG, "dim must be 2 or 3");
+  if (!(eps >= 1e-12 && eps <= 1e-2)) return fail(PDMK_ERR_EPS_RANGE, "eps out of range");
+  MethodParams m = default_params(dim, eps);
+  std::memset(out, 0, sizeof(*out));
+  out->dim = dim;
+  out->eps = eps;
+  out->precision = PDMK_PREC_FP64;
+  out->kappa = m.kappa;
+  out->n_s = m.n_s;
+  out->porder = m.porder;
+  out->npw = m.npw;
+  out->nufft_w = m.nufft_w;
+  return PDMK_OK;
+}
+
+int pdmk_kernel_info_get(int dim, double eps, pdmk_kernel_info* out) {
+  if (!out || (dim != 2 && dim != 3)) return fail(PDMK_ERR_INVALID_ARG, "bad argument");
+  if (!(eps >= 1e-12 && eps <= 1e-2)) return fail(PDMK_ERR_EPS_RANGE, "eps out of range");
+  const Pswf& P = pswf_for_eps(eps);
+  const SplitTables& T = tables_for_eps(eps);
+  out->c = P.c;
+  out->lambda0 = P.lambda0;
+  out->c0_over_psi0 = P.c0 / P.psi0;
+  out->w0_zero = T.w0_unit(dim);
+  return PDMK_OK;
+}
+
+int pdmk_kernel_eval_residual(int dim, double eps, double h, int64_t n, const double* r,
+                              double* out) {
+  if ((dim != 2 && dim != 3) || n < 0 || (n > 0 && (!r || !out)) || !(h > 0))
+    return fail(PDMK_ERR_INVALID_ARG, "bad argument");
+  if (!(eps >= 1e-12 && eps <= 1e-2)) return fail(PDMK_ERR_EPS_RANGE, "eps out of range");
+  const SplitTables& T = tables_for_eps(eps);
+  for (int64_t i = 0; i < n; ++i) out[i] = T.residual(dim, r[i], h);
+  return PDMK_OK;
+}
+
+int pdmk_kernel_eval_w0hat(int dim, double eps, double rc, int64_t n, const double* k,
+                           double* out) {
+  if ((dim != 2 && dim != 3) || n < 0 || (n > 0 && (!k || !out)) || !(rc > 0))
+    return fail(PDMK_ERR_INVALID_ARG, "bad argument");
+  if (!(eps >= 1e-12 && eps <= 1e-2)) return fail(PDMK_ERR_EPS_RANGE, "eps out of range");
+  const Pswf& P = pswf_for_eps(eps);
+  for (int64_t i = 0; i < n; ++i) out[i] = P.psit(k[i] * rc / P.c) / (k[i] * k[i]);
+  return PDMK_OK;
+}
+
+static int validate_opts(const pdmk_opts* o) {
+  if (!o) return fail(PDMK_ERR_INVALID_ARG, "null options");
+  if (o->dim != 2 && o->dim != 3) return fail(PDMK_ERR_INVALID_ARG, "dim must be 2 or 3");
+  if (!(o->eps >= 1e-12 && o->eps <= 1e-2)) return fail(PDMK_ERR_EPS_RANGE, "eps out of range");
+  if (o->precision != PDMK_PREC_FP64 && o->precision != PDMK_PREC_MIXED)
+    return fail(PDMK_ERR_INVALID_ARG, "unknown precision");
+  if (o->precision == PDMK_PREC_MIXED)
+    return fail(PDMK_ERR_UNSUPPORTED, "mixed precision not available in this build");
+  if (o->porder > 64 || o->npw > 64 || o->nufft_w > 16)
+    return fail(PDMK_ERR_INVALID_ARG, "porder/npw <= 64 and nufft_w <= 16");
+  return PDMK_OK;
+}
+
+int pdmk_plan_create(const pdmk_opts* opts, const double* L, pdmk_plan** out) {
+  if (!out || !L) return fail(PDMK_ERR_INVALID_ARG, "null argument");
+  *out = nullptr;
+  int st = validate_opts(opts);
+  if (st) return st;
+  for (int i = 0; i < opts->dim * opts->dim; ++i)
+    if (!std::isfinite(L[i])) return fail(PDMK_ERR_SINGULAR_LATTICE, "non-finite lattice");
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev == 0)
+    return fail(PDMK_ERR_NO_DEVICE, "no HIP device");
+  pdmk_plan* P = new pdmk_plan();
+  try {
+    P->o = *opts;
+    const int d = opts->dim;
+    P->mp = default_params(d, opts->eps);
+    if (opts->kappa > 0) P->mp.kappa = opts->kappa;
+    if (opts->n_s > 0) P->mp.n_s = opts->n_s;
+    if (opts->porder > 0) P->mp.porder = opts->porder;
+    if (opts->npw > 0) P->mp.npw = opts->npw;
+    if (opts->nufft_w > 0) {
+      P->mp.nufft_w = opts->nufft_w;
+      P->mp.beta = 2.0 * opts->nufft_w;
+    }
+    P->nufft_beta = P->mp.beta;
+    P->P = &pswf_for_eps(opts->eps);
+    P->T = &tables_for_eps(opts->eps);
+    std::string msg = make_geometry(d, L, P->mp.kappa, P->P->c, P->g);
+    if (!msg.empty()) {
+      delete P;
+      return fail(msg.find("kappa") != std::string::npos ? PDMK_ERR_INVALID_ARG
+                                                          : PDMK_ERR_SINGULAR_LATTICE,
+                  msg);
+    }
+    PDMK_HIP(hipGetDevice(&P->device));
+    KParams& kp = P->kp;
+    std::memset(&kp, 0, sizeof(kp));
+    kp.dim = d;
+    kp.p = P->mp.porder;
+    kp.J = P->mp.npw;
+    kp.rc = P->g.rc;
+    kp.precision = opts->precision;
+    int64_t nroot = 1;
+    for (int a = 0; a < 3; ++a) {
+      kp.next[a] = a < d ? P->g.next[a] : 1;
+      kp.origin[a] = a < d ? P->g.origin[a] : 0.0;
+      nroot *= kp.next[a];
+    }
+    int rootbits = 1;
+    while ((1ll << rootbits) < nroot) ++rootbits;
+    if (rootbits > 40) throw Error{PDMK_ERR_UNSUPPORTED, "root grid too large"};
+    kp.B = std::min(d == 3 ? 20 : 30, (64 - rootbits) / d);
+    for (int k = 0; k < 9; ++k) {
+      kp.L[k] = P->g.L[k];
+      kp.Li[k] = P->g.Li[k];
+      kp.Q[k] = P->g.Q[k];
+    }
+    kp.w0unit = P->T->w0_unit(d);
+    plan_upload_tables(P);
+    far_build_scale(P);
+  } catch (const Error& e) {
+    free_plan_tables(P);
+    delete P;
+    return fail(e.code, e.msg);
+  }
+  *out = P;
+  return PDMK_OK;
+}
+
+void pdmk_plan_destroy(pdmk_plan* P) {
+  if (!P) return;
+  free_plan_tables(P);
+  delete P;
+}
+
+int pdmk_plan_geometry(const pdmk_plan* P, pdmk_geometry* out) {
+  if (!P || !out) return fail(PDMK_ERR_INVALID_ARG, "null argument");
+  std::memset(out, 0, sizeof(*out));
+  const Geometry& g = P->g;
+  out->dim = g.dim;
+  for (int k = 0; k < g.dim * g.dim; ++k) {
+    out->L_oriented[k] = g.L[k];
+    out->Q[k] = g.Q[k];
+  }
+  for (int a = 0; a < g.dim; ++a) {
+    out->perm[a] = g.perm[a];
+    out->nroot[a] = g.nroot[a];
+    out->origin[a] = g.origin[a];
+    out->fgrid[a] = g.fgrid[a];
+    out->fgrid_paper[a] = g.fgrid_paper[a];
+  }
+  out->volume = g.volume;
+  out->rc = g.rc;
+  out->n_shifts = (int)(g.shifts.size() / g.dim);
+  out->c = P->P->c;
+  out->w0_zero_rc = P->T->w0_unit(g.dim);
+  out->porder = P->mp.porder;
+  out->npw = P->mp.npw;
+  out->nufft_w = P->mp.nufft_w;
+  out->n_s = P->mp.n_s;
+  out->nufft_beta = P->nufft_beta;
+  out->kappa = P->mp.kappa;
+  return PDMK_OK;
+}
+
+int pdmk_geometry_get(const pdmk_opts* opts, const double* L, pdmk_geometry* out) {
+  if (!L || !out) return fail(PDMK_ERR_INVALID_ARG, "null argument");
+  int st = validate_opts(opts);
+  if (st) return st;
+  pdmk_plan tmp;
+  tmp.o = *opts;
+  tmp.mp = default_params(opts->dim, opts->eps);
+  if (opts->kappa > 0) tmp.mp.kappa = opts->kappa;
+  if (opts->n_s > 0) tmp.mp.n_s = opts->n_s;
+  if (opts->porder > 0) tmp.mp.porder = opts->porder;
+  if (opts->npw > 0) tmp.mp.npw = opts->npw;
+  if (opts->nufft_w > 0) {
+    tmp.mp.nufft_w = opts->nufft_w;
+    tmp.mp.beta = 2.0 * opts->nufft_w;
+  }
+  tmp.nufft_beta = tmp.mp.beta;
+  tmp.P = &pswf_for_eps(opts->eps);
+  tmp.T = &tables_for_eps(opts->eps);
+  std::string msg = make_geometry(opts->dim, L, tmp.mp.kappa, tmp.P->c, tmp.g);
+  if (!msg.empty())
+    return fail(msg.find("kappa") != std::string::npos ? PDMK_ERR_INVALID_ARG
+                                                        : PDMK_ERR_SINGULAR_LATTICE,
+                msg);
+  return pdmk_plan_geometry(&tmp, out);
+}
+
+int pdmk_plan_stats(const pdmk_plan* P, pdmk_stats* out) {
+  if (!P || !out) return fail(PDMK_ERR_INVALID_ARG, "null argument");
+  *out = P->last;
+  return PDMK_OK;
+}
+
+int pdmk_plan_eval(pdmk_plan* P, int64_t n_src, const double* src, const double* q,
+                   int64_t n_trg, const double* trg, double* pot, double* grad, void* stream) {
+  if (!P) return fail(PDMK_ERR_INVALID_ARG, "null plan");
+  const int d = P->g.dim;
+  const bool self_t = (trg == nullptr);
+  if (self_t) n_trg = n_src;
+  const bool want_grad = (P->o.flags & PDMK_WANT_GRAD) != 0;
+  if (n_src < 0 || n_trg < 0) return fail(PDMK_ERR_INVALID_ARG, "negative count");
+  if (n_src > (int64_t)1 << 30 || n_trg > (int64_t)1 << 30)
+    return fail(PDMK_ERR_INVALID_ARG, "more than 2^30 points");
+  if ((n_src > 0 && (!src || !q)) || (n_trg > 0 && !pot) || (want_grad && n_trg > 0 && !grad))
+    return fail(PDMK_ERR_INVALID_ARG, "null array");
+  hipStream_t s = (hipStream_t)stream;
+  Eval E;
+  E.s = s;
+  E.n_src = n_src;
+  E.n_trg = n_trg;
+  E.self_targets = self_t;
+  E.q = q;
+  try {
+    int cur = -1;
+    PDMK_HIP(hipGetDevice(&cur));
+    if (cur != P->device) throw Error{PDMK_ERR_INVALID_ARG, "plan bound to another device"};
+    if (n_trg == 0) return PDMK_OK;
+    if (n_src == 0) {
+      PDMK_HIP(hipMemsetAsync(pot, 0, n_trg * sizeof(double), s));
+      if (want_grad) PDMK_HIP(hipMemsetAsync(grad, 0, n_trg * d * sizeof(double), s));
+      PDMK_HIP(hipStreamSynchronize(s));
+      return PDMK_OK;
+    }
+    hipEvent_t ev[5];
+    for (auto& e : ev) PDMK_HIP(hipEventCreate(&e));
+    PDMK_HIP(hipEventRecord(ev[0], s));
+    // charge checks
+    double* qs = E.alloc<double>(2);
+    int* bad = E.alloc<int>(1);
+    PDMK_HIP(hipMemsetAsync(qs, 0, 2 * sizeof(double), s));
+    PDMK_HIP(hipMemsetAsync(bad, 0, sizeof(int), s));
+    hipLaunchKernelGGL(k_charge_stats, dim3(std::min(1024, nblk(n_src, 256))), dim3(256), 0, s,
+                       n_src, q, qs, bad);
+    double hq[2];
+    int hbad = 0;
+    PDMK_HIP(hipMemcpyAsync(hq, qs, sizeof(hq), hipMemcpyDeviceToHost, s));
+    PDMK_HIP(hipMemcpyAsync(&hbad, bad, sizeof(int), hipMemcpyDeviceToHost, s));
+    PDMK_HIP(hipStreamSynchronize(s));
+    if (hbad) throw Error{PDMK_ERR_NONFINITE, "non-finite charge"};
+    if (std::fabs(hq[0]) > 1e-8 * hq[1] && !(P->o.flags & PDMK_ALLOW_NONNEUTRAL))
+      throw Error{PDMK_ERR_NOT_NEUTRAL, "sum of charges is not zero"};
+    stage_prepare(P, E, src, trg);
+    stage_images(P, E, q);
+    stage_tree(P, E);
+    stage_lists(P, E);
+    PDMK_HIP(hipEventRecord(ev[1], s));
+    stage_near(P, E, want_grad);
+    PDMK_HIP(hipEventRecord(ev[2], s));
+    stage_far(P, E, q, want_grad);
+    PDMK_HIP(hipEventRecord(ev[3], s));
+    // uniform-background constant: the method with m = 0 dropped returns the
+    // tin-foil potential plus (sum q) * Rhat_0(0) / V
+    const double cc = P->P->c;
+    const double cnn = -P->P->psit_dd0 * P->g.rc * P->g.rc / (2.0 * cc * cc * P->g.volume);
+    const double shift = -hq[0] * cnn;
+    hipLaunchKernelGGL(k_assemble, dim3(nblk(n_trg, 256)), dim3(256), 0, s, n_trg, d, E.tperm,
+                       E.pot_sorted, E.grad_sorted, E.far_pot, E.far_grad, shift, P->kp, pot,
+                       want_grad ? grad : nullptr);
+    PDMK_HIP(hipEventRecord(ev[4], s));
+    PDMK_HIP(hipEventSynchronize(ev[4]));
+    float t1, t2, t3, t4;
+    PDMK_HIP(hipEventElapsedTime(&t1, ev[0], ev[1]));
+    PDMK_HIP(hipEventElapsedTime(&t2, ev[1], ev[2]));
+    PDMK_HIP(hipEventElapsedTime(&t3, ev[2], ev[3]));
+    PDMK_HIP(hipEventElapsedTime(&t4, ev[0], ev[4]));
+    for (auto& e : ev) (void)hipEventDestroy(e);
+    E.st.n_src = n_src;
+    E.st.n_trg = n_trg;
+    E.st.n_images = E.n_img;
+    E.st.t_build_ms = t1;
+    E.st.t_near_ms = t2;
+    E.st.t_far_ms = t3;
+    E.st.t_total_ms = t4;
+    P->last = E.st;
+    dfree_all(E.allocs, s);
+    PDMK_HIP(hipStreamSynchronize(s));
+  } catch (const Error& e) {
+    dfree_all(E.allocs, s);
+    (void)hipStreamSynchronize(s);
+    return fail(e.code, e.msg);
+  }
+  return PDMK_OK;
+}
+
+int pdmk_eval(const pdmk_opts* opts, const double* L, int64_t n_src, const double* src,
+              const double* q, int64_t n_trg, const double* trg, double* pot, double* grad,
+              void* stream) {
+  pdmk_plan* P = nullptr;
+  int st = pdmk_plan_create(opts, L, &P);
+  if (st) return st;
+  st = pdmk_plan_eval(P, n_src, src, q, n_trg, trg, pot, grad, stream);
+  pdmk_plan_destroy(P);
+  return st;
+}
+
+}  // extern "C"

@@ -1,0 +1,341 @@
+// Far field W_0^(p) (Section 3.6): spreading -> FFT -> diagonal scaling ->
+// inverse FFT -> interpolation on the Fourier grid M_0 x M_1 (x M_2), with no
+// upsampling (rem:no_upsampling), in fractional coordinates.
+//
+// With the spreading window phi (exp(beta(sqrt(1-z^2)-1)), w cells wide) and its
+// per-axis transform phi^(m), the scaling of eq:diag becomes
+//   S(m) = What_0(|k_m|) / (V phi^(m)^2),  k_m = 2 pi L^{-T} m,  S(0) = 0,
+// What_0(k) = psi~(k r_c / c) / k^2 (eq:W0hat), computed once per plan in FP64.
+// The FFT is a hand-written mixed-radix (2, 3, 4, 5) Stockham transform; each
+// workgroup transforms one grid line held in LDS.
+#include "internal.h"
+
+namespace pdmk {
+
+static inline int nblk(int64_t n, int b) { return (int)((n + b - 1) / b); }
+
+struct Radices {
+  int n;
+  int r[24];
+};
+
+static Radices factorize(int M) {
+  Radices R{};
+  int m = M;
+  while (m % 4 == 0) { R.r[R.n++] = 4; m /= 4; }
+  while (m % 2 == 0) { R.r[R.n++] = 2; m /= 2; }
+  while (m % 3 == 0) { R.r[R.n++] = 3; m /= 3; }
+  while (m % 5 == 0) { R.r[R.n++] = 5; m /= 5; }
+  if (m != 1) throw Error{PDMK_ERR_UNSUPPORTED, "FFT size not 2,3,5-smooth"};
+  return R;
+}
+
+__device__ inline double2 cmul(double2 a, double2 b) {
+  return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+
+// y[k] = sum_r v[r] exp(sign 2 pi i r k / R), R <= 5
+__device__ inline void small_dft(double2* v, int R, int sign) {
+  double2 y[5];
+  for (int k = 0; k < R; ++k) {
+    double sr = 0, si = 0;
+    for (int r = 0; r < R; ++r) {
+      double c, s;
+      sincospi(2.0 * (double)((r * k) % R) / (double)R, &s, &c);
+      s *= sign;
+      sr += v[r].x * c - v[r].y * s;
+      si += v[r].x * s + v[r].y * c;
+    }
+    y[k] = make_double2(sr, si);
+  }
+  for (int k = 0; k < R; ++k) v[k] = y[k];
+}
+
+// One workgroup per grid line of length M along one axis.
+__global__ void k_fft_lines(double2* __restrict__ data, int M, int64_t stride, int nl0,
+                            int64_t so0, int64_t so1, int sign, Radices rad) {
+  extern __shared__ double2 sh[];
+  double2* b0 = sh;
+  double2* b1 = sh + M;
+  const int line = blockIdx.x;
+  const int64_t base = (int64_t)(line % nl0) * so0 + (int64_t)(line / nl0) * so1;
+  for (int i = threadIdx.x; i < M; i += blockDim.x) b0[i] = data[base + i * stride];
+  __syncthreads();
+  int Ns = 1;
+  for (int pass = 0; pass < rad.n; ++pass) {
+    const int R = rad.r[pass];
+    const int nb = M / R;
+    for (int j = threadIdx.x; j < nb; j += blockDim.x) {
+      double2 v[5];
+      for (int r = 0; r < R; ++r) v[r] = b0[j + r * nb];
+      const int jm = j % Ns;
+      if (Ns > 1) {
+        double s, c;
+        sincospi(2.0 * (double)jm / (double)(Ns * R), &s, &c);
+        const double2 w1 = make_double2(c, sign * s);
+        double2 w = w1;
+        for (int r = 1; r < R; ++r) {
+          v[r] = cmul(v[r], w);
+          w = cmul(w, w1);
+        }
+      }
+      small_dft(v, R, sign);
+      const int idx = (j / Ns) * Ns * R + jm;
+      for (int r = 0; r < R; ++r) b1[idx + r * Ns] = v[r];
+    }
+    __syncthreads();
+    double2* t = b0;
+    b0 = b1;
+    b1 = t;
+    Ns *= R;
+  }
+  for (int i = threadIdx.x; i < M; i += blockDim.x) data[base + i * stride] = b0[i];
+}
+
+static void fft3(double2* g, const int* M, int dim, int sign, hipStream_t s) {
+  const int64_t M0 = M[0], M1 = M[1], M2 = dim == 3 ? M[2] : 1;
+  for (int ax = 0; ax < dim; ++ax) {
+    int Ma = M[ax];
+    if (Ma == 1) continue;
+    if (Ma > 4096) throw Error{PDMK_ERR_UNSUPPORTED, "Fourier grid axis longer than 4096"};
+    Radices R = factorize(Ma);
+    int64_t stride, so0, so1;
+    int nl0, nlines;
+    if (ax == 0) { stride = 1; nl0 = (int)M1; so0 = M0; so1 = M0 * M1; nlines = (int)(M1 * M2); }
+    else if (ax == 1) { stride = M0; nl0 = (int)M0; so0 = 1; so1 = M0 * M1; nlines = (int)(M0 * M2); }
+    else { stride = M0 * M1; nl0 = (int)M0; so0 = 1; so1 = M0; nlines = (int)(M0 * M1); }
+    size_t smem = 2 * (size_t)Ma * sizeof(double2);
+    hipLaunchKernelGGL(k_fft_lines, dim3(nlines), dim3(256), smem, s, g, Ma, stride, nl0, so0,
+                       so1, sign, R);
+  }
+}
+
+__device__ inline double es_win(double z, double beta) {
+  double t = 1.0 - z * z;
+  return t >= 0.0 ? exp(beta * (sqrt(t) - 1.0)) : 0.0;
+}
+
+// Spread charges onto the real grid (FP64 atomics).
+template <int D>
+__global__ void k_spread(int64_t n, const double* __restrict__ u, const double* __restrict__ q,
+                         int M0, int M1, int M2, int w, double beta, double* __restrict__ grid) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int Ms[3] = {M0, M1, M2};
+  const double hw = 0.5 * w;
+  double wt[D][16];
+  int ix[D][16];
+  for (int a = 0; a < D; ++a) {
+    const double g = u[a * n + i] * Ms[a];
+    const int i0 = (int)ceil(g - hw);
+    for (int k = 0; k < w; ++k) {
+      int id = i0 + k;
+      wt[a][k] = es_win((id - g) / hw, beta);
+      id %= Ms[a];
+      if (id < 0) id += Ms[a];
+      ix[a][k] = id;
+    }
+  }
+  const double qi = q[i];
+  if (D == 3) {
+    for (int k2 = 0; k2 < w; ++k2)
+      for (int k1 = 0; k1 < w; ++k1) {
+        const double w12 = qi * wt[2][k2] * wt[1][k1];
+        const int64_t row = (int64_t)M0 * (ix[1][k1] + (int64_t)M1 * ix[2][k2]);
+        for (int k0 = 0; k0 < w; ++k0) atomicAdd(grid + row + ix[0][k0], w12 * wt[0][k0]);
+      }
+  } else {
+    for (int k1 = 0; k1 < w; ++k1) {
+      const double w1 = qi * wt[1][k1];
+      const int64_t row = (int64_t)M0 * ix[1][k1];
+      for (int k0 = 0; k0 < w; ++k0) atomicAdd(grid + row + ix[0][k0], w1 * wt[0][k0]);
+    }
+  }
+}
+
+__global__ void k_to_complex(int64_t n, const double* __restrict__ g, double2* __restrict__ c) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) c[i] = make_double2(g[i], 0.0);
+}
+
+__global__ void k_scale(int64_t n, double2* __restrict__ c, const double* __restrict__ s) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) {
+    double v = s[i];
+    c[i] = make_double2(c[i].x * v, c[i].y * v);
+  }
+}
+
+// Interpolate the real part of the grid at the targets (and its gradient,
+// mapped to the oriented Cartesian frame by L^{-T}).
+template <int D>
+__global__ void k_interp(KParams kp, int64_t n, const double* __restrict__ u, int M0, int M1,
+                         int M2, int w, double beta, const double2* __restrict__ grid,
+                         double* __restrict__ pot, double* __restrict__ grad, int want_grad) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int Ms[3] = {M0, M1, M2};
+  const double hw = 0.5 * w;
+  double wt[D][16], dw[D][16];
+  int ix[D][16];
+  for (int a = 0; a < D; ++a) {
+    const double g = u[a * n + i] * Ms[a];
+    const int i0 = (int)ceil(g - hw);
+    for (int k = 0; k < w; ++k) {
+      int id = i0 + k;
+      const double z = (id - g) / hw;
+      const double v = es_win(z, beta);
+      wt[a][k] = v;
+      const double t = 1.0 - z * z;
+      dw[a][k] = (t > 0.0) ? v * beta * (-z / sqrt(t)) * (-Ms[a] / hw) : 0.0;
+      id %= Ms[a];
+      if (id < 0) id += Ms[a];
+      ix[a][k] = id;
+    }
+  }
+  double acc = 0.0, gu[3] = {0, 0, 0};
+  if (D == 3) {
+    for (int k2 = 0; k2 < w; ++k2)
+      for (int k1 = 0; k1 < w; ++k1) {
+        const int64_t row = (int64_t)M0 * (ix[1][k1] + (int64_t)M1 * ix[2][k2]);
+        double s0 = 0.0, sd0 = 0.0;
+        for (int k0 = 0; k0 < w; ++k0) {
+          const double v = grid[row + ix[0][k0]].x;
+          s0 = fma(v, wt[0][k0], s0);
+          if (want_grad) sd0 = fma(v, dw[0][k0], sd0);
+        }
+        acc = fma(s0, wt[1][k1] * wt[2][k2], acc);
+        if (want_grad) {
+          gu[0] = fma(sd0, wt[1][k1] * wt[2][k2], gu[0]);
+          gu[1] = fma(s0, dw[1][k1] * wt[2][k2], gu[1]);
+          gu[2] = fma(s0, wt[1][k1] * dw[2][k2], gu[2]);
+        }
+      }
+  } else {
+    for (int k1 = 0; k1 < w; ++k1) {
+      const int64_t row = (int64_t)M0 * ix[1][k1];
+      double s0 = 0.0, sd0 = 0.0;
+      for (int k0 = 0; k0 < w; ++k0) {
+        const double v = grid[row + ix[0][k0]].x;
+        s0 = fma(v, wt[0][k0], s0);
+        if (want_grad) sd0 = fma(v, dw[0][k0], sd0);
+      }
+      acc = fma(s0, wt[1][k1], acc);
+      if (want_grad) {
+        gu[0] = fma(sd0, wt[1][k1], gu[0]);
+        gu[1] = fma(s0, dw[1][k1], gu[1]);
+      }
+    }
+  }
+  pot[i] = acc;
+  if (want_grad)
+    for (int b = 0; b < D; ++b) {
+      double s = 0.0;
+      for (int a = 0; a < D; ++a) s += kp.Li[a + D * b] * gu[a];
+      grad[i * D + b] = s;
+    }
+}
+
+// Diagonal scaling table (FP64), once per plan.
+__global__ void k_farscale(KParams kp, int M0, int M1, int M2, const double* __restrict__ wf0,
+                           const double* __restrict__ wf1, const double* __restrict__ wf2,
+                           const double* __restrict__ gx, const double* __restrict__ gwpsi, int nq,
+                           double c, double c0, double V, double* __restrict__ out) {
+  const int64_t n = (int64_t)M0 * M1 * M2;
+  int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= n) return;
+  const int d = kp.dim;
+  int ii[3] = {(int)(idx % M0), (int)((idx / M0) % M1), (int)(idx / ((int64_t)M0 * M1))};
+  const int Ms[3] = {M0, M1, M2};
+  int m[3] = {0, 0, 0};
+  bool nyq = false, zero = true;
+  for (int a = 0; a < d; ++a) {
+    m[a] = ii[a] < Ms[a] / 2 ? ii[a] : ii[a] - Ms[a];
+    if (Ms[a] > 1 && Ms[a] % 2 == 0 && ii[a] == Ms[a] / 2) nyq = true;
+    if (m[a] != 0) zero = false;
+  }
+  if (nyq || zero) { out[idx] = 0.0; return; }
+  double k2 = 0.0;
+  for (int b = 0; b < d; ++b) {
+    double s = 0.0;
+    for (int a = 0; a < d; ++a) s += kp.Li[a + d * b] * m[a];
+    s *= 2.0 * 3.14159265358979323846;
+    k2 += s * s;
+  }
+  const double x = sqrt(k2) * kp.rc / c;
+  double ps = 0.0;
+  for (int j = 0; j < nq; ++j) ps += gwpsi[j] * cos(c * x * gx[j]);
+  ps /= 2.0 * c0;
+  double den = wf0[ii[0]] * wf1[ii[1]];
+  if (d == 3) den *= wf2[ii[2]];
+  out[idx] = ps / k2 / V / (den * den);
+}
+
+void far_build_scale(pdmk_plan* P) {
+  const Geometry& g = P->g;
+  const int d = g.dim;
+  int M[3] = {g.fgrid[0], g.fgrid[1], d == 3 ? g.fgrid[2] : 1};
+  int64_t n = (int64_t)M[0] * M[1] * M[2];
+  std::vector<double> wf[3];
+  for (int a = 0; a < 3; ++a)
+    wf[a] = (a < d) ? window_ft(M[a], P->mp.nufft_w, P->nufft_beta) : std::vector<double>(1, 1.0);
+  const Pswf& ps = *P->P;
+  std::vector<double> gwpsi(ps.qx.size());
+  for (size_t i = 0; i < ps.qx.size(); ++i) gwpsi[i] = ps.qw[i] * ps.qpsi[i];
+  std::vector<void*> tmp;
+  auto up = [&](const std::vector<double>& v) {
+    double* p;
+    PDMK_HIP(hipMalloc(&p, v.size() * sizeof(double)));
+    PDMK_HIP(hipMemcpy(p, v.data(), v.size() * sizeof(double), hipMemcpyHostToDevice));
+    tmp.push_back(p);
+    return p;
+  };
+  double* d0 = up(wf[0]);
+  double* d1 = up(wf[1]);
+  double* d2 = up(wf[2]);
+  double* dgx = up(ps.qx);
+  double* dgw = up(gwpsi);
+  PDMK_HIP(hipMalloc(&P->d_farscale, n * sizeof(double)));
+  hipLaunchKernelGGL(k_farscale, dim3(nblk(n, 256)), dim3(256), 0, 0, P->kp, M[0], M[1], M[2], d0,
+                     d1, d2, dgx, dgw, (int)ps.qx.size(), ps.c, ps.c0, g.volume, P->d_farscale);
+  PDMK_HIP(hipDeviceSynchronize());
+  for (void* p : tmp) (void)hipFree(p);
+}
+
+void stage_far(pdmk_plan* P, Eval& E, const double* q, bool want_grad) {
+  const Geometry& g = P->g;
+  const int d = g.dim;
+  int M[3] = {g.fgrid[0], g.fgrid[1], d == 3 ? g.fgrid[2] : 1};
+  int64_t n = (int64_t)M[0] * M[1] * M[2];
+  const int w = P->mp.nufft_w;
+  const double beta = P->nufft_beta;
+  double* grid = E.alloc<double>(n);
+  double2* cg = E.alloc<double2>(n);
+  PDMK_HIP(hipMemsetAsync(grid, 0, n * sizeof(double), E.s));
+  if (E.n_src > 0) {
+    if (d == 3)
+      hipLaunchKernelGGL(k_spread<3>, dim3(nblk(E.n_src, 256)), dim3(256), 0, E.s, E.n_src, E.us,
+                         q, M[0], M[1], M[2], w, beta, grid);
+    else
+      hipLaunchKernelGGL(k_spread<2>, dim3(nblk(E.n_src, 256)), dim3(256), 0, E.s, E.n_src, E.us,
+                         q, M[0], M[1], M[2], w, beta, grid);
+  }
+  hipLaunchKernelGGL(k_to_complex, dim3(nblk(n, 256)), dim3(256), 0, E.s, n, grid, cg);
+  fft3(cg, M, d, -1, E.s);
+  hipLaunchKernelGGL(k_scale, dim3(nblk(n, 256)), dim3(256), 0, E.s, n, cg, P->d_farscale);
+  fft3(cg, M, d, +1, E.s);
+  E.far_pot = E.alloc<double>(E.n_trg);
+  E.far_grad = want_grad ? E.alloc<double>(E.n_trg * d) : nullptr;
+  if (E.n_trg > 0) {
+    if (d == 3)
+      hipLaunchKernelGGL(k_interp<3>, dim3(nblk(E.n_trg, 256)), dim3(256), 0, E.s, P->kp, E.n_trg,
+                         E.ut, M[0], M[1], M[2], w, beta, cg, E.far_pot, E.far_grad,
+                         want_grad ? 1 : 0);
+    else
+      hipLaunchKernelGGL(k_interp<2>, dim3(nblk(E.n_trg, 256)), dim3(256), 0, E.s, P->kp, E.n_trg,
+                         E.ut, M[0], M[1], M[2], w, beta, cg, E.far_pot, E.far_grad,
+                         want_grad ? 1 : 0);
+  }
+}
+
+}  // namespace pdmk

@@ -1,0 +1,159 @@
+// Internal declarations shared by the HIP translation units of libpdmk.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/pdmk.h"
+#include "planner.h"
+
+namespace pdmk {
+
+// ---------------------------------------------------------------- errors
+struct Error {
+  int code;
+  std::string msg;
+};
+#define PDMK_HIP(call)                                                          \
+  do {                                                                          \
+    hipError_t e_ = (call);                                                     \
+    if (e_ != hipSuccess)                                                       \
+      throw ::pdmk::Error{e_ == hipErrorOutOfMemory ? PDMK_ERR_OUT_OF_MEMORY    \
+                                                    : PDMK_ERR_HIP,             \
+                          std::string(#call) + ": " + hipGetErrorString(e_)};   \
+  } while (0)
+
+// Stream-ordered device allocation from the default memory pool.
+template <class T>
+T* dalloc(size_t n, hipStream_t s) {
+  void* p = nullptr;
+  if (n == 0) n = 1;
+  PDMK_HIP(hipMallocAsync(&p, n * sizeof(T), s));
+  return static_cast<T*>(p);
+}
+void dfree_all(std::vector<void*>& v, hipStream_t s);
+
+// ------------------------------------------------------- device constants
+// Everything a kernel needs about the method, passed by value.
+struct KParams {
+  int dim;
+  int p;            // proxy points per axis
+  int J;            // plane-wave half count
+  int nE, nF2;      // Chebyshev series lengths
+  int nEd, nF2d;
+  int B;            // Morton bits per axis
+  int next[3];      // extended root grid dims
+  double rc;
+  double origin[3];
+  double L[9], Li[9], Q[9];
+  double w0unit;    // W_h(0) for h = 1
+  int precision;
+};
+
+// One tree level (device arrays; counts on host).
+struct Level {
+  int n = 0;                 // boxes
+  uint64_t* key = nullptr;   // smallest point key in the box
+  int* coord = nullptr;      // dim ints per box
+  int* sbeg = nullptr;       // source range in sorted sources
+  int* send = nullptr;
+  int* tbeg = nullptr;       // target range in sorted targets
+  int* tend = nullptr;
+  int* parent = nullptr;
+  int* child0 = nullptr;     // first of 2^d children at the next level, -1 = leaf
+  int* coll = nullptr;       // 3^d colleague indices, -1 = none
+  int* nlid = nullptr;       // index among non-leaf boxes of this level, -1 = leaf
+  int nnl = 0;               // non-leaf count
+  int* nl_box = nullptr;     // non-leaf index -> box index
+  double* proxy_q = nullptr; // nnl * p^d outgoing proxy charges
+  double* proxy_phi = nullptr; // nnl * p^d incoming proxy potentials
+};
+
+// Per-evaluation state.
+struct Eval {
+  hipStream_t s = nullptr;
+  std::vector<void*> allocs;
+  template <class T>
+  T* alloc(size_t n) {
+    T* p = dalloc<T>(n, s);
+    allocs.push_back(p);
+    return p;
+  }
+  int64_t n_src = 0, n_trg = 0, n_img = 0;
+  bool self_targets = true;
+  // sources after orientation and wrap (SoA, FP64)
+  double* xs = nullptr;   // dim * n_src
+  double* us = nullptr;   // fractional
+  double* xt = nullptr;   // targets (== xs when self_targets)
+  double* ut = nullptr;
+  const double* q = nullptr;
+  // sorted sources (originals + images) and sorted targets
+  double* sx = nullptr;   // dim * n_img
+  double* sq = nullptr;
+  uint64_t* skey = nullptr;
+  double* tx = nullptr;   // dim * n_trg
+  uint64_t* tkey = nullptr;
+  int* tperm = nullptr;   // sorted target -> original target index
+  std::vector<Level> lev;
+  Level* d_lev = nullptr;   // device copy of lev (for list building)
+  // target leaves
+  int nleaf_t = 0;
+  int* lf_box = nullptr;    // (level << 26 | box) packed as two arrays
+  int* lf_level = nullptr;
+  int* lf_boxid = nullptr;
+  int* lf_list_beg = nullptr;
+  int4* list = nullptr;     // {sbeg, send, level, 0}
+  int64_t nlist = 0;
+  double* pot_sorted = nullptr;   // near field per sorted target
+  double* grad_sorted = nullptr;
+  double* far_pot = nullptr;      // far field per original target
+  double* far_grad = nullptr;
+  pdmk_stats st{};
+};
+
+}  // namespace pdmk
+
+// The plan (C-ABI opaque type).
+struct pdmk_plan {
+  pdmk_opts o{};
+  pdmk::MethodParams mp{};
+  pdmk::Geometry g;
+  const pdmk::SplitTables* T = nullptr;
+  const pdmk::Pswf* P = nullptr;
+  int device = 0;
+  pdmk::KParams kp{};
+  // device tables
+  double* d_E = nullptr;
+  double* d_Ed = nullptr;       // dE/ds series
+  double* d_F2d = nullptr;      // dF2/ds series
+  double* d_F2 = nullptr;
+  double* d_nodes = nullptr;   // p
+  double* d_bw = nullptr;      // p
+  double* d_Tm = nullptr;      // [2][p][p]: parent basis at child nodes, sigma = -1, +1
+  double2* d_F = nullptr;      // [2J+1][p]: exp(-i pi j xi_p / 3)
+  double* d_dtab = nullptr;    // |j|^2 table
+  double* d_farscale = nullptr;// M0*M1*M2
+  double* d_shiftvec = nullptr;  // nshift * dim lattice translations L n
+  int nshift = 0;
+  double nufft_beta = 0;
+  pdmk_stats last{};
+};
+
+namespace pdmk {
+// stages (implemented in tree.hip / near.hip / far.hip)
+void stage_prepare(pdmk_plan* P, Eval& E, const double* src, const double* trg);
+void stage_images(pdmk_plan* P, Eval& E, const double* q);
+void stage_tree(pdmk_plan* P, Eval& E);
+void stage_lists(pdmk_plan* P, Eval& E);
+void stage_near(pdmk_plan* P, Eval& E, bool want_grad);
+void stage_far(pdmk_plan* P, Eval& E, const double* q, bool want_grad);
+void stage_assemble(pdmk_plan* P, Eval& E, const double* q, double* pot, double* grad);
+void plan_upload_tables(pdmk_plan* P);
+void far_build_scale(pdmk_plan* P);
+
+// scans (rocprim)
+void exclusive_scan_int(const int* in, int* out, int n, hipStream_t s, std::vector<void*>& allocs);
+int read_int(const int* dptr, hipStream_t s);
+}  // namespace pdmk

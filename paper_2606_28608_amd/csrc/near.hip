@@ -1,0 +1,599 @@
+// Near field: free-space DMK on the extended root grid with the root-level
+// W_0 step omitted (Section 3.5, Algorithm 1 near-field step).
+//
+// Kernel split per level l (box side h_l = r_c / 2^l), eq:tele / eq:W0hat:
+//   G - W_0 = sum_{l < L} D_l + R_L,
+// D_l is exchanged as plane waves between colleague boxes that both have
+// children; every target leaf sums the residual R directly over its list
+// (built in tree.hip).  Plane waves of level l have period 3 h_l, modes
+// k_j = 2 pi j / (3 h_l), |j_a| <= J, and carry D_l's Fourier multiplier
+// divided by the period volume.  Boxes represent their sources by proxy
+// charges on a p^d tensor Chebyshev grid, and their incoming field by proxy
+// potentials on the same grid.
+#include "internal.h"
+
+namespace pdmk {
+
+static inline int nblk(int64_t n, int b) { return (int)((n + b - 1) / b); }
+constexpr double kInv4Pi = 0.07957747154594767;
+constexpr double kInv2Pi = 0.15915494309189535;
+
+__device__ inline double clenshaw(const double* __restrict__ a, int n, double s) {
+  double t = 2.0 * s - 1.0, b1 = 0.0, b2 = 0.0;
+  for (int k = n - 1; k >= 1; --k) {
+    double b0 = fma(2.0 * t, b1, a[k] - b2);
+    b2 = b1;
+    b1 = b0;
+  }
+  return fma(t, b1, a[0] - b2);
+}
+
+// Lagrange basis at the p Chebyshev nodes (barycentric form), and optionally
+// its derivative.  x exactly at a node is moved by 1e-13.
+__device__ inline void lagrange_rows(int p, const double* __restrict__ nodes,
+                                     const double* __restrict__ bw, double x,
+                                     double* row, double* drow) {
+  for (int j = 0; j < p; ++j)
+    if (x == nodes[j]) { x += 1e-13; break; }
+  double s = 0.0, s1 = 0.0;
+  for (int j = 0; j < p; ++j) {
+    double inv = 1.0 / (x - nodes[j]);
+    double t = bw[j] * inv;
+    row[j] = t;
+    s += t;
+    s1 += t * inv;
+  }
+  double is = 1.0 / s;
+  if (drow) {
+    // l_j' = l_j (-1/(x - x_j) + S1/S),  S1 = sum w_k/(x-x_k)^2
+    for (int j = 0; j < p; ++j) {
+      double lj = row[j] * is;
+      drow[j] = lj * (-1.0 / (x - nodes[j]) + s1 * is);
+    }
+  }
+  for (int j = 0; j < p; ++j) row[j] *= is;
+}
+
+// ------------------------------------------------------------- residual sums
+// One 64-thread block per target leaf; sources of each list entry are staged
+// through LDS in tiles of 64.
+template <int D>
+__global__ __launch_bounds__(64) void k_direct(
+    KParams kp, int nleaf, const Level* __restrict__ lev, const int* __restrict__ lf_level,
+    const int* __restrict__ lf_box, const int* __restrict__ lbeg, const int4* __restrict__ list,
+    const double* __restrict__ sx, const double* __restrict__ sq, int64_t nimg,
+    const double* __restrict__ tx, int64_t ntrg, const int* __restrict__ tperm,
+    const double* __restrict__ qorig, int self_targets, const double* __restrict__ Ec,
+    const double* __restrict__ Edc, double* __restrict__ pot, double* __restrict__ grad,
+    int want_grad) {
+  __shared__ double shx[D][64];
+  __shared__ double shq[64];
+  const int i = blockIdx.x;
+  if (i >= nleaf) return;
+  const int lvl = lf_level[i], b = lf_box[i];
+  const Level& T = lev[lvl];
+  const int tb = T.tbeg[b], te = T.tend[b];
+  const int lb = lbeg[i], le = lbeg[i + 1];
+  const double hT = kp.rc / (double)(1 << lvl);
+  const int nc = D == 3 ? kp.nE : kp.nF2;
+  const int ncd = D == 3 ? kp.nEd : kp.nF2d;
+  for (int t0 = tb; t0 < te; t0 += 64) {
+    const int t = t0 + threadIdx.x;
+    const bool valid = t < te;
+    double x[D];
+    for (int a = 0; a < D; ++a) x[a] = valid ? tx[a * ntrg + t] : 0.0;
+    double acc = 0.0, g[D];
+    for (int a = 0; a < D; ++a) g[a] = 0.0;
+    for (int e = lb; e < le; ++e) {
+      const int4 en = list[e];
+      const double hh = kp.rc / (double)(1 << en.z);
+      const double h2 = hh * hh, ih = 1.0 / hh, ih2 = ih * ih;
+      for (int s0 = en.x; s0 < en.y; s0 += 64) {
+        const int sidx = s0 + threadIdx.x;
+        __syncthreads();
+        if (sidx < en.y) {
+          for (int a = 0; a < D; ++a) shx[a][threadIdx.x] = sx[a * nimg + sidx];
+          shq[threadIdx.x] = sq[sidx];
+        }
+        __syncthreads();
+        const int ns = min(64, en.y - s0);
+        if (valid) {
+          for (int k = 0; k < ns; ++k) {
+            double dx[D], r2 = 0.0;
+            for (int a = 0; a < D; ++a) {
+              dx[a] = x[a] - shx[a][k];
+              r2 = fma(dx[a], dx[a], r2);
+            }
+            if (r2 < h2 && r2 > 0.0) {
+              const double s = r2 * ih2;
+              const double qs = shq[k];
+              if (D == 3) {
+                const double ir_exact = 1.0 / sqrt(r2);
+                const double Es = clenshaw(Ec, nc, s);
+                acc = fma(qs, ir_exact - Es * ih, acc);
+                if (want_grad) {
+                  const double Ed = clenshaw(Edc, ncd, s);
+                  const double f = qs * (-ir_exact * ir_exact * ir_exact - 2.0 * Ed * ih2 * ih);
+                  for (int a = 0; a < D; ++a) g[a] = fma(f, dx[a], g[a]);
+                }
+              } else {
+                const double F = clenshaw(Ec, nc, s);
+                acc = fma(qs, -0.5 * log(s) + F, acc);
+                if (want_grad) {
+                  const double Fd = clenshaw(Edc, ncd, s);
+                  const double f = qs * (-1.0 / r2 + 2.0 * Fd * ih2);
+                  for (int a = 0; a < D; ++a) g[a] = fma(f, dx[a], g[a]);
+                }
+              }
+            }
+          }
+        }
+      }
+    }
+    if (valid) {
+      const double cst = D == 3 ? kInv4Pi : kInv2Pi;
+      double v = acc * cst;
+      if (self_targets) {
+        const double w0 = D == 3 ? kp.w0unit / hT : kp.w0unit - log(hT) * kInv2Pi;
+        v -= qorig[tperm[t]] * w0;
+      }
+      pot[t] = v;
+      if (want_grad)
+        for (int a = 0; a < D; ++a) grad[(int64_t)t * D + a] = g[a] * cst;
+    }
+  }
+}
+
+// ------------------------------------------------------ source -> proxy charge
+// Q_B[i0,i1,i2] = sum_s q_s l_i0(xi_0) l_i1(xi_1) l_i2(xi_2) over the sources of
+// the childless children of the non-leaf box B, in B's scaled coordinates.
+// Grid (nnl, chunks of 1024 outputs); 256 threads, 4 outputs each.
+template <int D>
+__global__ __launch_bounds__(256) void k_anterp(KParams kp, Level L, Level C, int lvl,
+                                                const double* __restrict__ sx,
+                                                const double* __restrict__ sq, int64_t nimg,
+                                                const double* __restrict__ nodes,
+                                                const double* __restrict__ bw,
+                                                double* __restrict__ Q) {
+  extern __shared__ double sm[];
+  const int p = kp.p;
+  double* rows = sm;                // [64][D][p]
+  double* qs = sm + 64 * D * p;     // [64]
+  const int k = blockIdx.x;
+  const int b = L.nl_box[k];
+  const int pD = D == 3 ? p * p * p : p * p;
+  const double h = kp.rc / (double)(1 << lvl);
+  double cen[D];
+  for (int a = 0; a < D; ++a) cen[a] = kp.origin[a] + (L.coord[b * D + a] + 0.5) * h;
+  const double sc = 2.0 / h;
+  int eidx[4][3];
+  bool eval[4];
+  for (int r = 0; r < 4; ++r) {
+    int e = blockIdx.y * 1024 + r * 256 + threadIdx.x;
+    eval[r] = e < pD;
+    if (!eval[r]) e = 0;
+    if (D == 3) {
+      eidx[r][0] = e / (p * p); eidx[r][1] = (e / p) % p; eidx[r][2] = e % p;
+    } else {
+      eidx[r][0] = e / p; eidx[r][1] = e % p; eidx[r][2] = 0;
+    }
+  }
+  double acc[4] = {0, 0, 0, 0};
+  const int c0 = L.child0[b];
+  for (int o = 0; o < (1 << D); ++o) {
+    const int c = c0 + o;
+    if (C.child0[c] >= 0) continue;   // non-leaf child: handled by the transfer
+    const int sb = C.sbeg[c], se = C.send[c];
+    for (int s0 = sb; s0 < se; s0 += 64) {
+      const int ns = min(64, se - s0);
+      __syncthreads();
+      if (threadIdx.x < ns * D) {
+        const int si = threadIdx.x / D, a = threadIdx.x % D;
+        const double xi = (sx[a * nimg + s0 + si] - cen[a]) * sc;
+        lagrange_rows(p, nodes, bw, xi, rows + (si * D + a) * p, nullptr);
+      }
+      if (threadIdx.x < ns) qs[threadIdx.x] = sq[s0 + threadIdx.x];
+      __syncthreads();
+      for (int si = 0; si < ns; ++si) {
+        const double* rw = rows + si * D * p;
+        const double qv = qs[si];
+        for (int r = 0; r < 4; ++r) {
+          double v = qv * rw[eidx[r][0]] * rw[p + eidx[r][1]];
+          if (D == 3) v *= rw[2 * p + eidx[r][2]];
+          acc[r] += v;
+        }
+      }
+    }
+  }
+  for (int r = 0; r < 4; ++r) {
+    int e = blockIdx.y * 1024 + r * 256 + threadIdx.x;
+    if (eval[r]) Q[(int64_t)k * pD + e] = acc[r];
+  }
+}
+
+// ------------------------------------------- tensor-product child <-> parent
+// One axis of the transfer of proxy data between a non-leaf child (level l+1,
+// index kc among non-leaf boxes) and its parent (level l).
+//   up   : out[P] = sum_i T_sigma[P][i] in[i]    (charges, child -> parent)
+//   down : out[i] = sum_P T_sigma[P][i] in[P]    (potentials, parent -> child)
+// stage 0 reads the source tensor, stage D-1 writes the destination
+// (atomicAdd for up, since siblings share a parent).
+template <int D>
+__global__ void k_transfer(KParams kp, Level Lp, Level Lc, int up, int axis, int first,
+                           int last, const double* __restrict__ src, double* __restrict__ dst,
+                           const double* __restrict__ tmp_in, double* __restrict__ tmp_out,
+                           const double* __restrict__ Tm) {
+  const int p = kp.p;
+  const int pD = D == 3 ? p * p * p : p * p;
+  const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int kc = (int)(gid / pD);
+  if (kc >= Lc.nnl) return;
+  const int e = (int)(gid % pD);
+  const int c = Lc.nl_box[kc];
+  const int pb = Lc.parent[c];
+  const int kp_ = Lp.nlid[pb];
+  const int oct = c - Lp.child0[pb];
+  const int sel = (oct >> axis) & 1;
+  const double* M = Tm + sel * p * p;
+  int ix[3];
+  if (D == 3) { ix[0] = e / (p * p); ix[1] = (e / p) % p; ix[2] = e % p; }
+  else { ix[0] = e / p; ix[1] = e % p; ix[2] = 0; }
+  const int stride = D == 3 ? (axis == 0 ? p * p : (axis == 1 ? p : 1)) : (axis == 0 ? p : 1);
+  const int base = e - ix[axis] * stride;
+  const double* in;
+  if (first) in = src + (int64_t)(up ? kc : kp_) * pD;
+  else in = tmp_in + (int64_t)kc * pD;
+  double s = 0.0;
+  const int o = ix[axis];
+  for (int i = 0; i < p; ++i) {
+    double m = up ? M[o * p + i] : M[i * p + o];
+    s = fma(m, in[base + i * stride], s);
+  }
+  if (last) {
+    if (up) atomicAdd(dst + (int64_t)kp_ * pD + e, s);
+    else dst[(int64_t)kc * pD + e] += s;
+  } else {
+    tmp_out[(int64_t)kc * pD + e] = s;
+  }
+}
+
+// --------------------------------------------------- plane-wave transforms
+// Contract one axis of a batch of tensors with a complex matrix.
+// in : [nitems][n0][n1][n2] (real or complex), out: same with dim[ax] = mout.
+// Coefficient for output index o and contracted index i:
+//   trans = 0: M[(row0 + o) * ld + i]     trans = 1: M[(row0 + i) * ld + o]
+// optionally conjugated.  MODE 0 stores complex; MODE 1 adds the weighted real
+// part to a real output (weight 1 for contracted index 0, 2 otherwise: the
+// Hermitian half of the first axis).
+template <bool IN_CPLX, int MODE>
+__global__ void k_axis(int nitems, int n0, int n1, int n2, int ax, int mout,
+                       const void* __restrict__ in_, void* __restrict__ out_,
+                       const double2* __restrict__ M, int row0, int ld, int trans, int conj) {
+  int dims[3] = {n0, n1, n2};
+  int od[3] = {n0, n1, n2};
+  od[ax] = mout;
+  const int64_t osz = (int64_t)od[0] * od[1] * od[2];
+  const int64_t isz = (int64_t)n0 * n1 * n2;
+  const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (gid >= osz * nitems) return;
+  const int64_t item = gid / osz;
+  const int64_t e = gid % osz;
+  int o[3];
+  o[2] = (int)(e % od[2]);
+  o[1] = (int)((e / od[2]) % od[1]);
+  o[0] = (int)(e / ((int64_t)od[2] * od[1]));
+  int istr[3] = {n1 * n2, n2, 1};
+  int64_t ibase = item * isz;
+  for (int a = 0; a < 3; ++a)
+    if (a != ax) ibase += (int64_t)o[a] * istr[a];
+  const int oi = o[ax];
+  double sr = 0.0, si = 0.0;
+  for (int i = 0; i < dims[ax]; ++i) {
+    double2 m = trans ? M[(row0 + i) * ld + oi] : M[(row0 + oi) * ld + i];
+    if (conj) m.y = -m.y;
+    if (IN_CPLX) {
+      const double2 v = reinterpret_cast<const double2*>(in_)[ibase + (int64_t)i * istr[ax]];
+      if (MODE == 1) {
+        const double w = i == 0 ? 1.0 : 2.0;
+        sr += w * (m.x * v.x - m.y * v.y);
+      } else {
+        sr += m.x * v.x - m.y * v.y;
+        si += m.x * v.y + m.y * v.x;
+      }
+    } else {
+      const double v = reinterpret_cast<const double*>(in_)[ibase + (int64_t)i * istr[ax]];
+      sr += m.x * v;
+      si += m.y * v;
+    }
+  }
+  if (MODE == 1) reinterpret_cast<double*>(out_)[gid] += sr;
+  else reinterpret_cast<double2*>(out_)[gid] = make_double2(sr, si);
+}
+
+// Incoming expansion of every non-leaf box B of a level:
+//   I_B(j) = c_l(|j|^2) sum_{C} omega^{j.(c_B - c_C)/h} S_C(j),
+// over the non-leaf colleagues C (including B), omega = exp(2 pi i / 3).
+template <int D>
+__global__ void k_translate(Level L, int J, const double2* __restrict__ S,
+                            double2* __restrict__ I, const double* __restrict__ dtab,
+                            double levfac, unsigned long long* __restrict__ npairs) {
+  const int n1 = 2 * J + 1;
+  const int msz = D == 3 ? (J + 1) * n1 * n1 : (J + 1) * n1;
+  const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (gid >= (int64_t)msz * L.nnl) return;
+  const int k = (int)(gid / msz), m = (int)(gid % msz);
+  int j[3] = {0, 0, 0};
+  if (D == 3) {
+    j[2] = m % n1 - J;
+    j[1] = (m / n1) % n1 - J;
+    j[0] = m / (n1 * n1);
+  } else {
+    j[1] = m % n1 - J;
+    j[0] = m / n1;
+  }
+  const int b = L.nl_box[k];
+  const int ncoll = D == 3 ? 27 : 9;
+  const double2 w3[3] = {make_double2(1.0, 0.0), make_double2(-0.5, 0.8660254037844386),
+                         make_double2(-0.5, -0.8660254037844386)};
+  double sr = 0.0, si = 0.0;
+  int cnt = 0;
+  for (int sl = 0; sl < ncoll; ++sl) {
+    const int c = L.coll[b * ncoll + sl];
+    if (c < 0) continue;
+    const int kc = L.nlid[c];
+    if (kc < 0) continue;
+    ++cnt;
+    // slot encodes coord(C) - coord(B) + 1 per axis; delta = coord(B) - coord(C)
+    int ph = 0, t = sl;
+    for (int a = 0; a < D; ++a) {
+      const int dl = t % 3 - 1;
+      t /= 3;
+      ph -= j[a] * dl;
+    }
+    ph %= 3;
+    if (ph < 0) ph += 3;
+    const double2 v = S[(int64_t)kc * msz + m];
+    const double2 w = w3[ph];
+    sr += w.x * v.x - w.y * v.y;
+    si += w.x * v.y + w.y * v.x;
+  }
+  const int nn = j[0] * j[0] + j[1] * j[1] + j[2] * j[2];
+  const double cf = levfac * dtab[nn];
+  I[gid] = make_double2(cf * sr, cf * si);
+  if (m == 0 && npairs) atomicAdd(npairs, (unsigned long long)cnt);
+}
+
+// -------------------------------------------------- proxy potential -> targets
+// Targets of a leaf (level >= 1) evaluate the proxy potential of its parent.
+template <int D>
+__global__ __launch_bounds__(64) void k_eval_leaf(
+    KParams kp, int nleaf, const Level* __restrict__ lev, const int* __restrict__ lf_level,
+    const int* __restrict__ lf_box, const double* __restrict__ tx, int64_t ntrg,
+    const double* __restrict__ nodes, const double* __restrict__ bw,
+    double* __restrict__ pot, double* __restrict__ grad, int want_grad) {
+  extern __shared__ double sm[];
+  const int p = kp.p;
+  const int i = blockIdx.x;
+  if (i >= nleaf) return;
+  const int lvl = lf_level[i];
+  if (lvl == 0) return;
+  const int b = lf_box[i];
+  const Level& T = lev[lvl];
+  const Level& Pl = lev[lvl - 1];
+  const int pb = T.parent[b];
+  const int kq = Pl.nlid[pb];
+  const int pD = D == 3 ? p * p * p : p * p;
+  const double* Phi = Pl.proxy_phi + (int64_t)kq * pD;
+  const double hP = kp.rc / (double)(1 << (lvl - 1));
+  double cen[D];
+  for (int a = 0; a < D; ++a) cen[a] = kp.origin[a] + (Pl.coord[pb * D + a] + 0.5) * hP;
+  const double sc = 2.0 / hP;
+  double* row = sm + threadIdx.x * (2 * D * p);
+  double* drow = row + D * p;
+  const int tb = T.tbeg[b], te = T.tend[b];
+  for (int t0 = tb; t0 < te; t0 += 64) {
+    const int t = t0 + threadIdx.x;
+    if (t >= te) continue;
+    for (int a = 0; a < D; ++a) {
+      const double xi = (tx[a * ntrg + t] - cen[a]) * sc;
+      lagrange_rows(p, nodes, bw, xi, row + a * p, want_grad ? drow + a * p : nullptr);
+    }
+    double acc = 0.0, g0 = 0.0, g1 = 0.0, g2 = 0.0;
+    if (D == 3) {
+      for (int i0 = 0; i0 < p; ++i0) {
+        double a1 = 0.0, a1g1 = 0.0, a1g2 = 0.0;
+        for (int i1 = 0; i1 < p; ++i1) {
+          const double* ph = Phi + (i0 * p + i1) * p;
+          double a2 = 0.0, a2d = 0.0;
+          for (int i2 = 0; i2 < p; ++i2) {
+            a2 = fma(ph[i2], row[2 * p + i2], a2);
+            if (want_grad) a2d = fma(ph[i2], drow[2 * p + i2], a2d);
+          }
+          a1 = fma(row[p + i1], a2, a1);
+          if (want_grad) {
+            a1g1 = fma(drow[p + i1], a2, a1g1);
+            a1g2 = fma(row[p + i1], a2d, a1g2);
+          }
+        }
+        acc = fma(row[i0], a1, acc);
+        if (want_grad) {
+          g0 = fma(drow[i0], a1, g0);
+          g1 = fma(row[i0], a1g1, g1);
+          g2 = fma(row[i0], a1g2, g2);
+        }
+      }
+    } else {
+      for (int i0 = 0; i0 < p; ++i0) {
+        double a1 = 0.0, a1d = 0.0;
+        for (int i1 = 0; i1 < p; ++i1) {
+          a1 = fma(Phi[i0 * p + i1], row[p + i1], a1);
+          if (want_grad) a1d = fma(Phi[i0 * p + i1], drow[p + i1], a1d);
+        }
+        acc = fma(row[i0], a1, acc);
+        if (want_grad) {
+          g0 = fma(drow[i0], a1, g0);
+          g1 = fma(row[i0], a1d, g1);
+        }
+      }
+    }
+    pot[t] += acc;
+    if (want_grad) {
+      grad[(int64_t)t * D + 0] += g0 * sc;
+      grad[(int64_t)t * D + 1] += g1 * sc;
+      if (D == 3) grad[(int64_t)t * D + 2] += g2 * sc;
+    }
+  }
+}
+
+template <int D>
+static void near_impl(pdmk_plan* P, Eval& E, bool want_grad) {
+  const KParams& kp = P->kp;
+  hipStream_t s = E.s;
+  const int p = kp.p, J = kp.J;
+  const int pD = D == 3 ? p * p * p : p * p;
+  const int n1 = 2 * J + 1;
+  const int nlev = (int)E.lev.size();
+  hipEvent_t e0, e1, e2, e3;
+  PDMK_HIP(hipEventCreate(&e0));
+  PDMK_HIP(hipEventCreate(&e1));
+  PDMK_HIP(hipEventCreate(&e2));
+  PDMK_HIP(hipEventCreate(&e3));
+  PDMK_HIP(hipEventRecord(e0, s));
+  // residual sums (write pot_sorted)
+  if (E.nleaf_t > 0)
+    hipLaunchKernelGGL(k_direct<D>, dim3(E.nleaf_t), dim3(64), 0, s, kp, E.nleaf_t, E.d_lev,
+                       E.lf_level, E.lf_box, E.lf_list_beg, E.list, E.sx, E.sq, E.n_img, E.tx,
+                       E.n_trg, E.tperm, E.q, E.self_targets ? 1 : 0,
+                       D == 3 ? P->d_E : P->d_F2, D == 3 ? P->d_Ed : P->d_F2d, E.pot_sorted,
+                       E.grad_sorted, want_grad ? 1 : 0);
+  PDMK_HIP(hipEventRecord(e1, s));
+  // proxies
+  int maxnl = 0;
+  for (int l = 0; l < nlev; ++l) maxnl = std::max(maxnl, E.lev[l].nnl);
+  for (int l = 0; l < nlev; ++l) {
+    Level& L = E.lev[l];
+    if (L.nnl == 0) continue;
+    L.proxy_q = E.alloc<double>((size_t)L.nnl * pD);
+    L.proxy_phi = E.alloc<double>((size_t)L.nnl * pD);
+    PDMK_HIP(hipMemsetAsync(L.proxy_phi, 0, sizeof(double) * (size_t)L.nnl * pD, s));
+  }
+  if (maxnl > 0) {
+    double* tA = E.alloc<double>((size_t)maxnl * pD);
+    double* tB = E.alloc<double>((size_t)maxnl * pD);
+    const size_t smem = (size_t)(64 * D * p + 64) * sizeof(double);
+    // upward pass
+    for (int l = nlev - 2; l >= 0; --l) {
+      Level& L = E.lev[l];
+      if (L.nnl == 0) continue;
+      Level& C = E.lev[l + 1];
+      hipLaunchKernelGGL(k_anterp<D>, dim3(L.nnl, nblk(pD, 1024)), dim3(256), smem, s, kp, L, C,
+                         l, E.sx, E.sq, E.n_img, P->d_nodes, P->d_bw, L.proxy_q);
+      if (C.nnl > 0) {
+        int64_t nt = (int64_t)C.nnl * pD;
+        for (int ax = 0; ax < D; ++ax) {
+          const double* tin = (ax % 2 == 1) ? tA : tB;
+          double* tout = (ax % 2 == 0) ? tA : tB;
+          hipLaunchKernelGGL(k_transfer<D>, dim3(nblk(nt, 256)), dim3(256), 0, s, kp, L, C, 1,
+                             ax, ax == 0 ? 1 : 0, ax == D - 1 ? 1 : 0, C.proxy_q, L.proxy_q,
+                             tin, tout, P->d_Tm);
+        }
+      }
+    }
+    // plane waves, level by level
+    const int64_t s1 = (int64_t)(J + 1) * p * (D == 3 ? p : 1);
+    const int64_t s2 = D == 3 ? (int64_t)(J + 1) * n1 * p : 0;
+    const int64_t s3 = D == 3 ? (int64_t)(J + 1) * n1 * n1 : (int64_t)(J + 1) * n1;
+    double2* bA = E.alloc<double2>((size_t)maxnl * s1);
+    double2* bB = D == 3 ? E.alloc<double2>((size_t)maxnl * s2) : nullptr;
+    double2* bS = E.alloc<double2>((size_t)maxnl * s3);
+    double2* bI = E.alloc<double2>((size_t)maxnl * s3);
+    unsigned long long* npairs = E.alloc<unsigned long long>(1);
+    PDMK_HIP(hipMemsetAsync(npairs, 0, sizeof(unsigned long long), s));
+    for (int l = 0; l < nlev; ++l) {
+      Level& L = E.lev[l];
+      if (L.nnl == 0) continue;
+      const int nn = L.nnl;
+      const double h = kp.rc / (double)(1 << l);
+      const double levfac = D == 3 ? 1.0 / (3.0 * h) : 1.0;
+      const int zz = D == 3 ? p : 1;
+      // outgoing: proxy charges -> plane waves (Hermitian half on axis 0)
+      hipLaunchKernelGGL((k_axis<false, 0>), dim3(nblk(nn * s1, 256)), dim3(256), 0, s, nn, p,
+                         p, zz, 0, J + 1, (const void*)L.proxy_q, (void*)bA, P->d_F, J, p, 0, 0);
+      if (D == 3) {
+        hipLaunchKernelGGL((k_axis<true, 0>), dim3(nblk(nn * s2, 256)), dim3(256), 0, s, nn,
+                           J + 1, p, p, 1, n1, (const void*)bA, (void*)bB, P->d_F, 0, p, 0, 0);
+        hipLaunchKernelGGL((k_axis<true, 0>), dim3(nblk(nn * s3, 256)), dim3(256), 0, s, nn,
+                           J + 1, n1, p, 2, n1, (const void*)bB, (void*)bS, P->d_F, 0, p, 0, 0);
+      } else {
+        hipLaunchKernelGGL((k_axis<true, 0>), dim3(nblk(nn * s3, 256)), dim3(256), 0, s, nn,
+                           J + 1, p, 1, 1, n1, (const void*)bA, (void*)bS, P->d_F, 0, p, 0, 0);
+      }
+      // translation between colleagues with the difference-kernel multiplier
+      hipLaunchKernelGGL(k_translate<D>, dim3(nblk(nn * s3, 256)), dim3(256), 0, s, L, J, bS, bI,
+                         P->d_dtab, levfac, npairs);
+      // incoming: plane waves -> proxy potentials
+      if (D == 3) {
+        hipLaunchKernelGGL((k_axis<true, 0>), dim3(nblk(nn * s2, 256)), dim3(256), 0, s, nn,
+                           J + 1, n1, n1, 2, p, (const void*)bI, (void*)bB, P->d_F, 0, p, 1, 1);
+        hipLaunchKernelGGL((k_axis<true, 0>), dim3(nblk(nn * s1, 256)), dim3(256), 0, s, nn,
+                           J + 1, n1, p, 1, p, (const void*)bB, (void*)bA, P->d_F, 0, p, 1, 1);
+      } else {
+        hipLaunchKernelGGL((k_axis<true, 0>), dim3(nblk(nn * s1, 256)), dim3(256), 0, s, nn,
+                           J + 1, n1, 1, 1, p, (const void*)bI, (void*)bA, P->d_F, 0, p, 1, 1);
+      }
+      hipLaunchKernelGGL((k_axis<true, 1>), dim3(nblk((int64_t)nn * pD, 256)), dim3(256), 0, s,
+                         nn, J + 1, p, zz, 0, p, (const void*)bA, (void*)L.proxy_phi, P->d_F, J,
+                         p, 1, 1);
+    }
+    // downward pass: parent proxy potential -> non-leaf child proxy potential
+    for (int l = 1; l < nlev; ++l) {
+      Level& C = E.lev[l];
+      Level& L = E.lev[l - 1];
+      if (C.nnl == 0) continue;
+      int64_t nt = (int64_t)C.nnl * pD;
+      for (int ax = 0; ax < D; ++ax) {
+        const double* tin = (ax % 2 == 1) ? tA : tB;
+        double* tout = (ax % 2 == 0) ? tA : tB;
+        hipLaunchKernelGGL(k_transfer<D>, dim3(nblk(nt, 256)), dim3(256), 0, s, kp, L, C, 0, ax,
+                           ax == 0 ? 1 : 0, ax == D - 1 ? 1 : 0, L.proxy_phi, C.proxy_phi, tin,
+                           tout, P->d_Tm);
+      }
+    }
+    PDMK_HIP(hipMemcpyAsync(E.d_lev, E.lev.data(), sizeof(Level) * E.lev.size(),
+                            hipMemcpyHostToDevice, s));
+    unsigned long long np = 0;
+    PDMK_HIP(hipMemcpyAsync(&np, npairs, sizeof(np), hipMemcpyDeviceToHost, s));
+    PDMK_HIP(hipStreamSynchronize(s));
+    E.st.n_pw_pairs = (int64_t)np;
+  }
+  PDMK_HIP(hipEventRecord(e2, s));
+  // leaf targets evaluate their parent's proxy potential
+  if (E.nleaf_t > 0 && maxnl > 0) {
+    const size_t smem = (size_t)64 * 2 * D * p * sizeof(double);
+    hipLaunchKernelGGL(k_eval_leaf<D>, dim3(E.nleaf_t), dim3(64), smem, s, kp, E.nleaf_t,
+                       E.d_lev, E.lf_level, E.lf_box, E.tx, E.n_trg, P->d_nodes, P->d_bw,
+                       E.pot_sorted, E.grad_sorted, want_grad ? 1 : 0);
+  }
+  PDMK_HIP(hipEventRecord(e3, s));
+  PDMK_HIP(hipEventSynchronize(e3));
+  float t01, t12, t23;
+  PDMK_HIP(hipEventElapsedTime(&t01, e0, e1));
+  PDMK_HIP(hipEventElapsedTime(&t12, e1, e2));
+  PDMK_HIP(hipEventElapsedTime(&t23, e2, e3));
+  E.st.t_direct_ms = t01;
+  E.st.t_pw_ms = t12;
+  E.st.t_proxy_ms = t23;
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  (void)hipEventDestroy(e2);
+  (void)hipEventDestroy(e3);
+}
+
+void stage_near(pdmk_plan* P, Eval& E, bool want_grad) {
+  E.pot_sorted = E.alloc<double>(E.n_trg);
+  E.grad_sorted = want_grad ? E.alloc<double>(E.n_trg * P->kp.dim) : nullptr;
+  if (P->kp.dim == 3) near_impl<3>(P, E, want_grad);
+  else near_impl<2>(P, E, want_grad);
+}
+
+}  // namespace pdmk

@@ -1,0 +1,530 @@
+// Preprocessing and tree construction (Algorithm 1, preprocessing and tree
+// construction steps):
+//   - orientation x' = Q^T x and wrap into the cell in FP64 (Section 3.2,
+//     fractional coordinates eq:fractional_coords),
+//   - image sources of the extended root grid (Sections 3.3-3.4),
+//   - keys = root cube index + Morton code inside the cube, radix sort,
+//   - level-synchronous adaptive refinement of every box holding more than
+//     n_s sources, colleague lists (boxes at the same level sharing a
+//     boundary point, bounded by the rectangular root grid),
+//   - the residual interaction lists of the target leaves.
+#include <cstring>
+#include <rocprim/rocprim.hpp>
+
+#include "internal.h"
+
+namespace pdmk {
+
+void dfree_all(std::vector<void*>& v, hipStream_t s) {
+  for (void* p : v) (void)hipFreeAsync(p, s);
+  v.clear();
+}
+
+void exclusive_scan_int(const int* in, int* out, int n, hipStream_t s,
+                        std::vector<void*>& allocs) {
+  if (n <= 0) return;
+  size_t tb = 0;
+  PDMK_HIP(rocprim::exclusive_scan(nullptr, tb, in, out, 0, (size_t)n,
+                                   rocprim::plus<int>(), s));
+  void* tmp = dalloc<char>(tb, s);
+  allocs.push_back(tmp);
+  PDMK_HIP(rocprim::exclusive_scan(tmp, tb, in, out, 0, (size_t)n,
+                                   rocprim::plus<int>(), s));
+}
+
+int read_int(const int* dptr, hipStream_t s) {
+  int v = 0;
+  PDMK_HIP(hipMemcpyAsync(&v, dptr, sizeof(int), hipMemcpyDeviceToHost, s));
+  PDMK_HIP(hipStreamSynchronize(s));
+  return v;
+}
+
+static inline int nblk(int64_t n, int b) { return (int)((n + b - 1) / b); }
+
+// ------------------------------------------------------------- orientation
+// x' = Q^T x ; u = L^{-1} x' wrapped to [0,1) ; x' = L u  (FP64)
+__global__ void k_prepare(KParams kp, int64_t n, const double* __restrict__ xin,
+                          double* __restrict__ xo, double* __restrict__ uo,
+                          int* __restrict__ bad) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int d = kp.dim;
+  double x[3] = {0, 0, 0}, xr[3] = {0, 0, 0}, u[3] = {0, 0, 0};
+  bool ok = true;
+  for (int a = 0; a < d; ++a) {
+    x[a] = xin[i * d + a];
+    ok = ok && isfinite(x[a]);
+  }
+  if (!ok) {
+    atomicOr(bad, 1);
+    for (int a = 0; a < d; ++a) x[a] = 0.0;
+  }
+  for (int a = 0; a < d; ++a) {
+    double s = 0;
+    for (int b = 0; b < d; ++b) s += kp.Q[b + d * a] * x[b];
+    xr[a] = s;
+  }
+  for (int a = 0; a < d; ++a) {
+    double s = 0;
+    for (int b = 0; b < d; ++b) s += kp.Li[a + d * b] * xr[b];
+    s -= floor(s);
+    if (s >= 1.0 || s < 0.0) s = 0.0;
+    u[a] = s;
+  }
+  for (int a = 0; a < d; ++a) {
+    double s = 0;
+    for (int b = a; b < d; ++b) s += kp.L[a + d * b] * u[b];
+    xo[a * n + i] = s;
+    uo[a * n + i] = u[a];
+  }
+}
+
+// ------------------------------------------------------------------ images
+__device__ inline bool in_extended(const KParams& kp, const double* y) {
+  for (int a = 0; a < kp.dim; ++a) {
+    double t = (y[a] - kp.origin[a]) / kp.rc;
+    if (!(t >= 0.0 && t < (double)kp.next[a])) return false;
+  }
+  return true;
+}
+
+__global__ void k_img_count(KParams kp, int64_t n, const double* __restrict__ xs,
+                            const double* __restrict__ sv, int nsh, int* __restrict__ cnt) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int d = kp.dim;
+  double x[3] = {0, 0, 0};
+  for (int a = 0; a < d; ++a) x[a] = xs[a * n + i];
+  int c = 0;
+  for (int s = 0; s < nsh; ++s) {
+    double y[3];
+    for (int a = 0; a < d; ++a) y[a] = x[a] + sv[s * d + a];
+    c += in_extended(kp, y) ? 1 : 0;
+  }
+  cnt[i] = c;
+}
+
+__global__ void k_img_emit(KParams kp, int64_t n, const double* __restrict__ xs,
+                           const double* __restrict__ q, const double* __restrict__ sv,
+                           int nsh, const int* __restrict__ off, int64_t nimg,
+                           double* __restrict__ xi, double* __restrict__ qi) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int d = kp.dim;
+  double x[3] = {0, 0, 0};
+  for (int a = 0; a < d; ++a) x[a] = xs[a * n + i];
+  double qq = q[i];
+  int64_t o = off[i];
+  for (int s = 0; s < nsh; ++s) {
+    double y[3];
+    for (int a = 0; a < d; ++a) y[a] = x[a] + sv[s * d + a];
+    if (in_extended(kp, y)) {
+      for (int a = 0; a < d; ++a) xi[a * nimg + o] = y[a];
+      qi[o] = qq;
+      ++o;
+    }
+  }
+}
+
+// -------------------------------------------------------------------- keys
+__device__ inline uint64_t morton_interleave(const uint32_t* c, int d, int B) {
+  uint64_t k = 0;
+  for (int b = 0; b < B; ++b)
+    for (int a = 0; a < d; ++a) k |= (uint64_t)((c[a] >> b) & 1u) << (d * b + a);
+  return k;
+}
+
+__global__ void k_keys(KParams kp, int64_t n, const double* __restrict__ x,
+                       uint64_t* __restrict__ key, int* __restrict__ idx) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int d = kp.dim;
+  const double scale = (double)(1ull << kp.B);
+  uint32_t c[3] = {0, 0, 0};
+  int r[3] = {0, 0, 0};
+  for (int a = 0; a < d; ++a) {
+    double t = (x[a * n + i] - kp.origin[a]) / kp.rc;
+    int ra = (int)floor(t);
+    ra = ra < 0 ? 0 : (ra >= kp.next[a] ? kp.next[a] - 1 : ra);
+    double f = (t - ra) * scale;
+    long long qa = (long long)floor(f);
+    if (qa < 0) qa = 0;
+    if (qa >= (1ll << kp.B)) qa = (1ll << kp.B) - 1;
+    c[a] = (uint32_t)qa;
+    r[a] = ra;
+  }
+  uint64_t root = (uint64_t)r[0] + (uint64_t)kp.next[0] * ((uint64_t)r[1] + (uint64_t)kp.next[1] * (uint64_t)r[2]);
+  key[i] = (root << (d * kp.B)) | morton_interleave(c, d, kp.B);
+  idx[i] = (int)i;
+}
+
+__global__ void k_gather(int64_t n, int d, const int* __restrict__ perm,
+                         const double* __restrict__ xin, int64_t nin,
+                         const double* __restrict__ qin, double* __restrict__ xout,
+                         double* __restrict__ qout) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  int j = perm[i];
+  for (int a = 0; a < d; ++a) xout[a * n + i] = xin[a * nin + j];
+  if (qout) qout[i] = qin[j];
+}
+
+static void sort_points(pdmk_plan* P, Eval& E, int64_t n, const double* x_in,
+                        const double* q_in, uint64_t*& key_sorted, double*& x_sorted,
+                        double*& q_sorted, int*& perm) {
+  const KParams& kp = P->kp;
+  hipStream_t s = E.s;
+  uint64_t* k0 = E.alloc<uint64_t>(n);
+  int* i0 = E.alloc<int>(n);
+  key_sorted = E.alloc<uint64_t>(n);
+  perm = E.alloc<int>(n);
+  if (n > 0) {
+    hipLaunchKernelGGL(k_keys, dim3(nblk(n, 256)), dim3(256), 0, s, kp, n, x_in, k0, i0);
+    int rootbits = 1;
+    int64_t nroot = (int64_t)kp.next[0] * kp.next[1] * (kp.dim == 3 ? kp.next[2] : 1);
+    while ((1ll << rootbits) < nroot) ++rootbits;
+    unsigned end_bit = (unsigned)(rootbits + kp.dim * kp.B);
+    if (end_bit > 64) end_bit = 64;
+    size_t tb = 0;
+    PDMK_HIP(rocprim::radix_sort_pairs(nullptr, tb, k0, key_sorted, i0, perm, (size_t)n, 0u,
+                                       end_bit, s));
+    void* tmp = E.alloc<char>(tb);
+    PDMK_HIP(rocprim::radix_sort_pairs(tmp, tb, k0, key_sorted, i0, perm, (size_t)n, 0u,
+                                       end_bit, s));
+  }
+  x_sorted = E.alloc<double>(n * kp.dim);
+  q_sorted = q_in ? E.alloc<double>(n) : nullptr;
+  if (n > 0)
+    hipLaunchKernelGGL(k_gather, dim3(nblk(n, 256)), dim3(256), 0, s, n, kp.dim, perm, x_in, n,
+                       q_in, x_sorted, q_sorted);
+}
+
+void stage_prepare(pdmk_plan* P, Eval& E, const double* src, const double* trg) {
+  const KParams& kp = P->kp;
+  int* bad = E.alloc<int>(1);
+  PDMK_HIP(hipMemsetAsync(bad, 0, sizeof(int), E.s));
+  E.xs = E.alloc<double>(E.n_src * kp.dim);
+  E.us = E.alloc<double>(E.n_src * kp.dim);
+  if (E.n_src > 0)
+    hipLaunchKernelGGL(k_prepare, dim3(nblk(E.n_src, 256)), dim3(256), 0, E.s, kp, E.n_src, src,
+                       E.xs, E.us, bad);
+  if (E.self_targets) {
+    E.xt = E.xs;
+    E.ut = E.us;
+  } else {
+    E.xt = E.alloc<double>(E.n_trg * kp.dim);
+    E.ut = E.alloc<double>(E.n_trg * kp.dim);
+    if (E.n_trg > 0)
+      hipLaunchKernelGGL(k_prepare, dim3(nblk(E.n_trg, 256)), dim3(256), 0, E.s, kp, E.n_trg,
+                         trg, E.xt, E.ut, bad);
+  }
+  if (read_int(bad, E.s)) throw Error{PDMK_ERR_NONFINITE, "non-finite position"};
+}
+
+void stage_images(pdmk_plan* P, Eval& E, const double* q) {
+  const KParams& kp = P->kp;
+  int64_t n = E.n_src;
+  int* cnt = E.alloc<int>(n + 1);
+  int* off = E.alloc<int>(n + 1);
+  PDMK_HIP(hipMemsetAsync(cnt + n, 0, sizeof(int), E.s));
+  if (n > 0)
+    hipLaunchKernelGGL(k_img_count, dim3(nblk(n, 256)), dim3(256), 0, E.s, kp, n, E.xs,
+                       P->d_shiftvec, P->nshift, cnt);
+  exclusive_scan_int(cnt, off, (int)(n + 1), E.s, E.allocs);
+  E.n_img = read_int(off + n, E.s);
+  double* xi = E.alloc<double>(E.n_img * kp.dim);
+  double* qi = E.alloc<double>(E.n_img);
+  if (n > 0)
+    hipLaunchKernelGGL(k_img_emit, dim3(nblk(n, 256)), dim3(256), 0, E.s, kp, n, E.xs, q,
+                       P->d_shiftvec, P->nshift, off, E.n_img, xi, qi);
+  int* perm = nullptr;
+  sort_points(P, E, E.n_img, xi, qi, E.skey, E.sx, E.sq, perm);
+  double* dummyq = nullptr;
+  sort_points(P, E, E.n_trg, E.xt, nullptr, E.tkey, E.tx, dummyq, E.tperm);
+}
+
+// -------------------------------------------------------------------- tree
+__device__ inline int lower_bound_u64(const uint64_t* __restrict__ a, int lo, int hi, uint64_t v) {
+  while (lo < hi) {
+    int mid = (lo + hi) >> 1;
+    if (a[mid] < v) lo = mid + 1; else hi = mid;
+  }
+  return lo;
+}
+
+// Range [beg, end) of keys in [kbeg, kbeg + 2^span) within a[lo, hi).
+__device__ inline void key_range(const uint64_t* a, int lo, int hi, uint64_t kbeg, int span,
+                                 int& beg, int& end) {
+  beg = lower_bound_u64(a, lo, hi, kbeg);
+  uint64_t kend = kbeg + (span >= 64 ? 0ull : (1ull << span));
+  if (span >= 64 || kend <= kbeg) end = hi;
+  else end = lower_bound_u64(a, beg, hi, kend);
+}
+
+__device__ inline int coll_slot(const int* dl, int d) {
+  int s = 0, m = 1;
+  for (int a = 0; a < d; ++a) {
+    s += (dl[a] + 1) * m;
+    m *= 3;
+  }
+  return s;
+}
+
+__global__ void k_level0(KParams kp, Level L, const uint64_t* __restrict__ skey, int nimg,
+                         const uint64_t* __restrict__ tkey, int ntrg) {
+  int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= L.n) return;
+  const int d = kp.dim;
+  int r[3] = {b % kp.next[0], (b / kp.next[0]) % kp.next[1], d == 3 ? b / (kp.next[0] * kp.next[1]) : 0};
+  uint64_t key = (uint64_t)b << (d * kp.B);
+  L.key[b] = key;
+  for (int a = 0; a < d; ++a) L.coord[b * d + a] = r[a];
+  int sb, se, tb, te;
+  key_range(skey, 0, nimg, key, d * kp.B, sb, se);
+  key_range(tkey, 0, ntrg, key, d * kp.B, tb, te);
+  L.sbeg[b] = sb; L.send[b] = se; L.tbeg[b] = tb; L.tend[b] = te;
+  L.parent[b] = -1;
+  L.child0[b] = -1;
+  L.nlid[b] = -1;
+  int ncoll = d == 3 ? 27 : 9;
+  for (int sl = 0; sl < ncoll; ++sl) {
+    int dl[3] = {sl % 3 - 1, (sl / 3) % 3 - 1, sl / 9 - 1};
+    int idx = 0, m = 1;
+    bool ok = true;
+    for (int a = 0; a < d; ++a) {
+      int c = r[a] + dl[a];
+      ok = ok && c >= 0 && c < kp.next[a];
+      idx += c * m;
+      m *= kp.next[a];
+    }
+    L.coll[b * ncoll + sl] = ok ? idx : -1;
+  }
+}
+
+__global__ void k_split_flags(Level L, int lvl, int ns, int maxlev, int* __restrict__ flag) {
+  int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b > L.n) return;
+  if (b == L.n) { flag[b] = 0; return; }
+  flag[b] = (L.send[b] - L.sbeg[b] > ns && lvl < maxlev) ? 1 : 0;
+}
+
+__global__ void k_mark_parents(Level L, const int* __restrict__ flag, const int* __restrict__ off,
+                               int d) {
+  int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= L.n) return;
+  if (flag[b]) {
+    int s = off[b];
+    L.nlid[b] = s;
+    L.child0[b] = s << d;
+    L.nl_box[s] = b;
+  } else {
+    L.nlid[b] = -1;
+    L.child0[b] = -1;
+  }
+}
+
+__global__ void k_make_children(KParams kp, Level P, Level C, int lvl,
+                                const uint64_t* __restrict__ skey,
+                                const uint64_t* __restrict__ tkey) {
+  int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= C.n) return;
+  const int d = kp.dim;
+  int s = c >> d, o = c & ((1 << d) - 1);
+  int b = P.nl_box[s];
+  int shift = d * (kp.B - lvl - 1);
+  uint64_t key = P.key[b] | ((uint64_t)o << shift);
+  C.key[c] = key;
+  for (int a = 0; a < d; ++a) C.coord[c * d + a] = 2 * P.coord[b * d + a] + ((o >> a) & 1);
+  int sb, se, tb, te;
+  key_range(skey, P.sbeg[b], P.send[b], key, shift, sb, se);
+  key_range(tkey, P.tbeg[b], P.tend[b], key, shift, tb, te);
+  C.sbeg[c] = sb; C.send[c] = se; C.tbeg[c] = tb; C.tend[c] = te;
+  C.parent[c] = b;
+  C.child0[c] = -1;
+  C.nlid[c] = -1;
+}
+
+__global__ void k_colleagues(Level P, Level C, int d) {
+  int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= C.n) return;
+  int ncoll = d == 3 ? 27 : 9;
+  int g[3] = {0, 0, 0};
+  for (int a = 0; a < d; ++a) g[a] = C.coord[c * d + a];
+  int out[27];
+  for (int sl = 0; sl < ncoll; ++sl) out[sl] = -1;
+  int b = C.parent[c];
+  for (int sl = 0; sl < ncoll; ++sl) {
+    int pb = P.coll[b * ncoll + sl];
+    if (pb < 0) continue;
+    int c0 = P.child0[pb];
+    if (c0 < 0) continue;
+    for (int o = 0; o < (1 << d); ++o) {
+      int cc = c0 + o;
+      int dl[3] = {0, 0, 0};
+      bool ok = true;
+      for (int a = 0; a < d; ++a) {
+        dl[a] = C.coord[cc * d + a] - g[a];
+        ok = ok && dl[a] >= -1 && dl[a] <= 1;
+      }
+      if (ok) out[coll_slot(dl, d)] = cc;
+    }
+  }
+  for (int sl = 0; sl < ncoll; ++sl) C.coll[c * ncoll + sl] = out[sl];
+}
+
+static void alloc_level(Eval& E, Level& L, int n, int d) {
+  L.n = n;
+  int ncoll = d == 3 ? 27 : 9;
+  L.key = E.alloc<uint64_t>(n);
+  L.coord = E.alloc<int>((size_t)n * d);
+  L.sbeg = E.alloc<int>(n);
+  L.send = E.alloc<int>(n);
+  L.tbeg = E.alloc<int>(n);
+  L.tend = E.alloc<int>(n);
+  L.parent = E.alloc<int>(n);
+  L.child0 = E.alloc<int>(n);
+  L.coll = E.alloc<int>((size_t)n * ncoll);
+  L.nlid = E.alloc<int>(n);
+}
+
+void stage_tree(pdmk_plan* P, Eval& E) {
+  const KParams& kp = P->kp;
+  const int d = kp.dim;
+  E.lev.clear();
+  int n0 = kp.next[0] * kp.next[1] * (d == 3 ? kp.next[2] : 1);
+  Level L0;
+  alloc_level(E, L0, n0, d);
+  hipLaunchKernelGGL(k_level0, dim3(nblk(n0, 128)), dim3(128), 0, E.s, kp, L0, E.skey,
+                     (int)E.n_img, E.tkey, (int)E.n_trg);
+  E.lev.push_back(L0);
+  const int maxlev = kp.B;
+  for (int l = 0;; ++l) {
+    Level& Lp = E.lev[l];
+    int* flag = E.alloc<int>(Lp.n + 1);
+    int* off = E.alloc<int>(Lp.n + 1);
+    hipLaunchKernelGGL(k_split_flags, dim3(nblk(Lp.n + 1, 256)), dim3(256), 0, E.s, Lp, l,
+                       P->mp.n_s, maxlev, flag);
+    exclusive_scan_int(flag, off, Lp.n + 1, E.s, E.allocs);
+    int nsplit = read_int(off + Lp.n, E.s);
+    Lp.nnl = nsplit;
+    Lp.nl_box = E.alloc<int>(nsplit);
+    hipLaunchKernelGGL(k_mark_parents, dim3(nblk(Lp.n, 256)), dim3(256), 0, E.s, Lp, flag, off,
+                       d);
+    if (nsplit == 0) break;
+    Level C;
+    alloc_level(E, C, nsplit << d, d);
+    Level Pcopy = E.lev[l];
+    hipLaunchKernelGGL(k_make_children, dim3(nblk(C.n, 128)), dim3(128), 0, E.s, kp, Pcopy, C, l,
+                       E.skey, E.tkey);
+    hipLaunchKernelGGL(k_colleagues, dim3(nblk(C.n, 128)), dim3(128), 0, E.s, Pcopy, C, d);
+    E.lev.push_back(C);
+  }
+  E.d_lev = E.alloc<Level>(E.lev.size());
+  PDMK_HIP(hipMemcpyAsync(E.d_lev, E.lev.data(), sizeof(Level) * E.lev.size(),
+                          hipMemcpyHostToDevice, E.s));
+  int64_t nb = 0, nnl = 0;
+  for (auto& L : E.lev) {
+    nb += L.n;
+    nnl += L.nnl;
+  }
+  E.st.n_levels = (int)E.lev.size();
+  E.st.n_boxes = nb;
+  E.st.n_nonleaf = nnl;
+  E.st.n_leaves = nb - nnl;
+}
+
+// ------------------------------------------------------------------- lists
+// Target leaves: boxes without children that hold targets.
+__global__ void k_collect_leaves(Level L, int lvl, int* __restrict__ counter,
+                                 int* __restrict__ lf_level, int* __restrict__ lf_box) {
+  int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= L.n) return;
+  if (L.child0[b] < 0 && L.tend[b] > L.tbeg[b]) {
+    int k = atomicAdd(counter, 1);
+    lf_level[k] = lvl;
+    lf_box[k] = b;
+  }
+}
+
+// Residual interaction list of a target leaf T at level i (plane waves are
+// exchanged only between colleagues that both have children):
+//   (a) every colleague C of T: all sources of C, residual R_i;
+//   (b) for every ancestor A of T at level j < i: every colleague D of A
+//       without children: all sources of D, residual R_j.
+// Mode 0 counts entries (and direct pairs), mode 1 writes them.
+__global__ void k_leaf_lists(int d, int nleaf, const Level* __restrict__ lev,
+                             const int* __restrict__ lf_level, const int* __restrict__ lf_box,
+                             int* __restrict__ cnt, const int* __restrict__ beg,
+                             int4* __restrict__ list, unsigned long long* __restrict__ pairs) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nleaf) return;
+  const int ncoll = d == 3 ? 27 : 9;
+  int lvl = lf_level[i], b = lf_box[i];
+  const Level& T = lev[lvl];
+  int k = 0;
+  long long np = 0;
+  int o = beg ? beg[i] : 0;
+  for (int sl = 0; sl < ncoll; ++sl) {
+    int c = T.coll[b * ncoll + sl];
+    if (c < 0) continue;
+    int sb = T.sbeg[c], se = T.send[c];
+    if (se <= sb) continue;
+    if (list) list[o + k] = make_int4(sb, se, lvl, 0);
+    ++k;
+    np += se - sb;
+  }
+  int a = T.parent[b];
+  for (int l = lvl - 1; l >= 0 && a >= 0; --l) {
+    const Level& A = lev[l];
+    for (int sl = 0; sl < ncoll; ++sl) {
+      int D = A.coll[a * ncoll + sl];
+      if (D < 0 || A.child0[D] >= 0) continue;
+      int sb = A.sbeg[D], se = A.send[D];
+      if (se <= sb) continue;
+      if (list) list[o + k] = make_int4(sb, se, l, 0);
+      ++k;
+      np += se - sb;
+    }
+    a = A.parent[a];
+  }
+  if (cnt) {
+    cnt[i] = k;
+    atomicAdd(pairs, (unsigned long long)(np * (long long)(T.tend[b] - T.tbeg[b])));
+  }
+}
+
+void stage_lists(pdmk_plan* P, Eval& E) {
+  const int d = P->kp.dim;
+  int total = 0;
+  for (auto& L : E.lev) total += L.n;
+  int* counter = E.alloc<int>(1);
+  PDMK_HIP(hipMemsetAsync(counter, 0, sizeof(int), E.s));
+  E.lf_level = E.alloc<int>(total);
+  E.lf_box = E.alloc<int>(total);
+  for (size_t l = 0; l < E.lev.size(); ++l)
+    hipLaunchKernelGGL(k_collect_leaves, dim3(nblk(E.lev[l].n, 256)), dim3(256), 0, E.s,
+                       E.lev[l], (int)l, counter, E.lf_level, E.lf_box);
+  E.nleaf_t = read_int(counter, E.s);
+  int n = E.nleaf_t;
+  int* cnt = E.alloc<int>(n + 1);
+  E.lf_list_beg = E.alloc<int>(n + 1);
+  unsigned long long* pairs = E.alloc<unsigned long long>(1);
+  PDMK_HIP(hipMemsetAsync(pairs, 0, sizeof(unsigned long long), E.s));
+  PDMK_HIP(hipMemsetAsync(cnt + n, 0, sizeof(int), E.s));
+  if (n > 0)
+    hipLaunchKernelGGL(k_leaf_lists, dim3(nblk(n, 128)), dim3(128), 0, E.s, d, n, E.d_lev,
+                       E.lf_level, E.lf_box, cnt, (const int*)nullptr, (int4*)nullptr, pairs);
+  exclusive_scan_int(cnt, E.lf_list_beg, n + 1, E.s, E.allocs);
+  E.nlist = read_int(E.lf_list_beg + n, E.s);
+  E.list = E.alloc<int4>(E.nlist);
+  if (n > 0)
+    hipLaunchKernelGGL(k_leaf_lists, dim3(nblk(n, 128)), dim3(128), 0, E.s, d, n, E.d_lev,
+                       E.lf_level, E.lf_box, (int*)nullptr, E.lf_list_beg, E.list,
+                       (unsigned long long*)nullptr);
+  unsigned long long np = 0;
+  PDMK_HIP(hipMemcpyAsync(&np, pairs, sizeof(np), hipMemcpyDeviceToHost, E.s));
+  PDMK_HIP(hipStreamSynchronize(E.s));
+  E.st.n_direct_pairs = (int64_t)np;
+}
+
+}  // namespace pdmk

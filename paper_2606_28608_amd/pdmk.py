@@ -1,0 +1,255 @@
+"""Python binding of libpdmk (include/pdmk.h): argument marshalling only.
+
+Every step of the evaluation runs in the HIP library; PyTorch provides device
+memory and the stream.  If libpdmk.so is missing the functions raise: there is
+no fallback implementation.
+
+    from paper_2606_28608_amd import pdmk
+    pot = pdmk.pdmk_eval(L, src, q, eps=1e-6)            # targets = sources
+    pot, grad = pdmk.pdmk_eval(L, src, q, eps=1e-6, grad=True)
+    plan = pdmk.Plan(L, dim=3, eps=1e-6); pot = plan.eval(src, q)
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libpdmk.so")
+
+PDMK_PREC_FP64 = 0
+PDMK_PREC_MIXED = 1
+PDMK_WANT_GRAD = 1
+PDMK_ALLOW_NONNEUTRAL = 2
+
+STATUS = {0: "PDMK_OK", -1: "PDMK_ERR_INVALID_ARG", -2: "PDMK_ERR_SINGULAR_LATTICE",
+          -3: "PDMK_ERR_NOT_NEUTRAL", -4: "PDMK_ERR_EPS_RANGE", -5: "PDMK_ERR_NONFINITE",
+          -6: "PDMK_ERR_OUT_OF_MEMORY", -7: "PDMK_ERR_HIP", -8: "PDMK_ERR_NO_DEVICE",
+          -9: "PDMK_ERR_UNSUPPORTED"}
+
+
+class PdmkError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("%s (%d): %s" % (STATUS.get(code, "?"), code, msg))
+        self.code = code
+
+
+class Opts(ctypes.Structure):
+    _fields_ = [("dim", ctypes.c_int), ("eps", ctypes.c_double), ("precision", ctypes.c_int),
+                ("kappa", ctypes.c_double), ("n_s", ctypes.c_int), ("flags", ctypes.c_uint),
+                ("porder", ctypes.c_int), ("npw", ctypes.c_int), ("nufft_w", ctypes.c_int)]
+
+
+class Geometry(ctypes.Structure):
+    _fields_ = [("dim", ctypes.c_int), ("L_oriented", ctypes.c_double * 9),
+                ("Q", ctypes.c_double * 9), ("perm", ctypes.c_int * 3),
+                ("volume", ctypes.c_double), ("rc", ctypes.c_double),
+                ("nroot", ctypes.c_int * 3), ("origin", ctypes.c_double * 3),
+                ("fgrid", ctypes.c_int * 3), ("fgrid_paper", ctypes.c_int * 3),
+                ("n_shifts", ctypes.c_int), ("c", ctypes.c_double),
+                ("w0_zero_rc", ctypes.c_double), ("porder", ctypes.c_int),
+                ("npw", ctypes.c_int), ("nufft_w", ctypes.c_int), ("n_s", ctypes.c_int),
+                ("nufft_beta", ctypes.c_double), ("kappa", ctypes.c_double)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("n_src", ctypes.c_int64), ("n_trg", ctypes.c_int64),
+                ("n_images", ctypes.c_int64), ("n_levels", ctypes.c_int),
+                ("n_boxes", ctypes.c_int64), ("n_leaves", ctypes.c_int64),
+                ("n_nonleaf", ctypes.c_int64), ("n_direct_pairs", ctypes.c_int64),
+                ("n_pw_pairs", ctypes.c_int64), ("t_build_ms", ctypes.c_double),
+                ("t_near_ms", ctypes.c_double), ("t_far_ms", ctypes.c_double),
+                ("t_total_ms", ctypes.c_double), ("t_direct_ms", ctypes.c_double),
+                ("t_pw_ms", ctypes.c_double), ("t_proxy_ms", ctypes.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class KernelInfo(ctypes.Structure):
+    _fields_ = [("c", ctypes.c_double), ("lambda0", ctypes.c_double),
+                ("c0_over_psi0", ctypes.c_double), ("w0_zero", ctypes.c_double)]
+
+
+_lib = None
+_dp = ctypes.POINTER(ctypes.c_double)
+_vp = ctypes.c_void_p
+
+
+def lib():
+    """Load libpdmk.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError("libpdmk.so is not built (run paper_2606_28608_amd.build.build())")
+        L = ctypes.CDLL(LIB_PATH)
+        L.pdmk_default_opts.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.POINTER(Opts)]
+        L.pdmk_eval.argtypes = [ctypes.POINTER(Opts), _dp, ctypes.c_int64, _vp, _vp,
+                                ctypes.c_int64, _vp, _vp, _vp, _vp]
+        L.pdmk_plan_create.argtypes = [ctypes.POINTER(Opts), _dp, ctypes.POINTER(_vp)]
+        L.pdmk_plan_eval.argtypes = [_vp, ctypes.c_int64, _vp, _vp, ctypes.c_int64, _vp, _vp, _vp,
+                                     _vp]
+        L.pdmk_plan_destroy.argtypes = [_vp]
+        L.pdmk_plan_destroy.restype = None
+        L.pdmk_plan_geometry.argtypes = [_vp, ctypes.POINTER(Geometry)]
+        L.pdmk_geometry_get.argtypes = [ctypes.POINTER(Opts), _dp, ctypes.POINTER(Geometry)]
+        L.pdmk_plan_stats.argtypes = [_vp, ctypes.POINTER(Stats)]
+        L.pdmk_kernel_info_get.argtypes = [ctypes.c_int, ctypes.c_double,
+                                           ctypes.POINTER(KernelInfo)]
+        L.pdmk_kernel_eval_residual.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_double,
+                                                ctypes.c_int64, _dp, _dp]
+        L.pdmk_kernel_eval_w0hat.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_double,
+                                             ctypes.c_int64, _dp, _dp]
+        L.pdmk_status_string.argtypes = [ctypes.c_int]
+        L.pdmk_status_string.restype = ctypes.c_char_p
+        L.pdmk_last_error.restype = ctypes.c_char_p
+        _lib = L
+    return _lib
+
+
+def _check(code):
+    if code != 0:
+        raise PdmkError(code, lib().pdmk_last_error().decode())
+
+
+def default_opts(dim, eps, precision="fp64", grad=False, allow_nonneutral=False, **over):
+    o = Opts()
+    _check(lib().pdmk_default_opts(int(dim), float(eps), ctypes.byref(o)))
+    o.precision = PDMK_PREC_MIXED if precision == "mixed" else PDMK_PREC_FP64
+    o.flags = (PDMK_WANT_GRAD if grad else 0) | (PDMK_ALLOW_NONNEUTRAL if allow_nonneutral else 0)
+    for k, v in over.items():
+        if v is not None:
+            setattr(o, k, v)
+    return o
+
+
+def _lattice(L, dim):
+    L = np.asarray(L, dtype=np.float64)
+    if L.shape != (dim, dim):
+        raise ValueError("L must be %dx%d with lattice vectors as columns" % (dim, dim))
+    return np.asfortranarray(L).ravel(order="F").copy()
+
+
+def geometry(L, dim=None, eps=1e-6, **over):
+    """Host-only planning quantities for (L, eps) (no device needed)."""
+    L = np.asarray(L, dtype=np.float64)
+    dim = dim or L.shape[0]
+    o = default_opts(dim, eps, **over)
+    g = Geometry()
+    Lf = _lattice(L, dim)
+    _check(lib().pdmk_geometry_get(ctypes.byref(o), Lf.ctypes.data_as(_dp), ctypes.byref(g)))
+    return g
+
+
+def kernel_info(dim, eps):
+    k = KernelInfo()
+    _check(lib().pdmk_kernel_info_get(int(dim), float(eps), ctypes.byref(k)))
+    return k
+
+
+def residual(dim, eps, h, r):
+    r = np.ascontiguousarray(r, dtype=np.float64)
+    out = np.empty_like(r)
+    _check(lib().pdmk_kernel_eval_residual(int(dim), float(eps), float(h), r.size,
+                                           r.ctypes.data_as(_dp), out.ctypes.data_as(_dp)))
+    return out
+
+
+def w0hat(dim, eps, rc, k):
+    k = np.ascontiguousarray(k, dtype=np.float64)
+    out = np.empty_like(k)
+    _check(lib().pdmk_kernel_eval_w0hat(int(dim), float(eps), float(rc), k.size,
+                                        k.ctypes.data_as(_dp), out.ctypes.data_as(_dp)))
+    return out
+
+
+def _dev(t, torch, dim=None):
+    if not (isinstance(t, torch.Tensor) and t.is_cuda):
+        raise TypeError("expected a torch tensor on the GPU")
+    t = t.to(torch.float64).contiguous()
+    return t
+
+
+def _stream(torch):
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+class Plan:
+    """A pdmk_plan: host tables and geometry for one (L, options) pair."""
+
+    def __init__(self, L, dim=None, eps=1e-6, precision="fp64", grad=False,
+                 allow_nonneutral=False, **over):
+        L = np.asarray(L, dtype=np.float64)
+        self.dim = dim or L.shape[0]
+        self.opts = default_opts(self.dim, eps, precision, grad, allow_nonneutral, **over)
+        self.want_grad = grad
+        self._h = _vp()
+        Lf = _lattice(L, self.dim)
+        _check(lib().pdmk_plan_create(ctypes.byref(self.opts), Lf.ctypes.data_as(_dp),
+                                      ctypes.byref(self._h)))
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value and _lib is not None:
+            _lib.pdmk_plan_destroy(h)
+            self._h = None
+
+    def eval(self, src, q, trg=None, out=None):
+        import torch
+        src = _dev(src, torch)
+        q = _dev(q, torch)
+        n = src.shape[0]
+        if src.shape != (n, self.dim) or q.shape != (n,):
+            raise ValueError("src must be (N, dim) and q (N,)")
+        if trg is not None:
+            trg = _dev(trg, torch)
+            m = trg.shape[0]
+        else:
+            m = n
+        pot = torch.empty(m, dtype=torch.float64, device=src.device) if out is None else out
+        grad = torch.empty((m, self.dim), dtype=torch.float64, device=src.device) \
+            if self.want_grad else None
+        _check(lib().pdmk_plan_eval(self._h, n, ctypes.c_void_p(src.data_ptr()),
+                                    ctypes.c_void_p(q.data_ptr()), m,
+                                    ctypes.c_void_p(trg.data_ptr()) if trg is not None else None,
+                                    ctypes.c_void_p(pot.data_ptr()),
+                                    ctypes.c_void_p(grad.data_ptr()) if grad is not None else None,
+                                    _stream(torch)))
+        return (pot, grad) if self.want_grad else pot
+
+    def geometry(self):
+        g = Geometry()
+        _check(lib().pdmk_plan_geometry(self._h, ctypes.byref(g)))
+        return g
+
+    def stats(self):
+        s = Stats()
+        _check(lib().pdmk_plan_stats(self._h, ctypes.byref(s)))
+        return s.as_dict()
+
+
+def pdmk_eval(L, src, q, trg=None, eps=1e-6, precision="fp64", grad=False,
+              allow_nonneutral=False, **over):
+    """One evaluation through pdmk_eval (plan created and destroyed inside)."""
+    import torch
+    L = np.asarray(L, dtype=np.float64)
+    dim = L.shape[0]
+    o = default_opts(dim, eps, precision, grad, allow_nonneutral, **over)
+    src = _dev(src, torch)
+    q = _dev(q, torch)
+    n = src.shape[0]
+    m = trg.shape[0] if trg is not None else n
+    if trg is not None:
+        trg = _dev(trg, torch)
+    pot = torch.empty(m, dtype=torch.float64, device=src.device)
+    g = torch.empty((m, dim), dtype=torch.float64, device=src.device) if grad else None
+    Lf = _lattice(L, dim)
+    _check(lib().pdmk_eval(ctypes.byref(o), Lf.ctypes.data_as(_dp), n,
+                           ctypes.c_void_p(src.data_ptr()), ctypes.c_void_p(q.data_ptr()), m,
+                           ctypes.c_void_p(trg.data_ptr()) if trg is not None else None,
+                           ctypes.c_void_p(pot.data_ptr()),
+                           ctypes.c_void_p(g.data_ptr()) if g is not None else None,
+                           _stream(torch)))
+    return (pot, g) if grad else pot
