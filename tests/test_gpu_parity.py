@@ -1,0 +1,211 @@
+"""Parity of the HIP periodic-DMK path with the FP64 Ewald oracle.
+
+Every comparison is relative l2 error over the targets (or a seeded sample of
+them), E_rel = ||pot - ref|| / ||ref||, required to be <= eps, the accuracy the
+caller asks for.  Inputs come from the seeded generators shared by both sides.
+"""
+import os
+
+import numpy as np
+import pytest
+
+from oracle import ewald
+from paper_2606_28608_amd import workloads
+
+pytestmark = pytest.mark.gpu
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    return torch, torch.device("cuda:0")
+
+
+@pytest.fixture(scope="module")
+def pdmk():
+    from paper_2606_28608_amd import pdmk as m
+    m.lib()
+    return m
+
+
+def _eval(pdmk, torch_dev, L, src, q, eps, trg=None, grad=False, **over):
+    torch, dev = torch_dev
+    S = torch.tensor(src, device=dev)
+    Q = torch.tensor(q, device=dev)
+    T = torch.tensor(trg, device=dev) if trg is not None else None
+    out = pdmk.pdmk_eval(L, S, Q, trg=T, eps=eps, grad=grad, **over)
+    if grad:
+        return out[0].cpu().numpy(), out[1].cpu().numpy()
+    return out.cpu().numpy()
+
+
+def test_c1_oblique2d(pdmk, torch_dev):
+    L, src, q = workloads.oblique2d(2000, seed=1)
+    ref = ewald.ewald(L, src, q)
+    pot = _eval(pdmk, torch_dev, L, src, q, 1e-6)
+    assert ewald.rel_l2(pot, ref) <= 1e-6
+
+
+@pytest.mark.parametrize("eps", [1e-3, 1e-6, 1e-9])
+@pytest.mark.parametrize("cell", ["triclinic", "cubic"])
+def test_c2_clustered_full(pdmk, torch_dev, eps, cell):
+    L, src, q = workloads.clustered3d(6000, seed=2, cell=cell)
+    ref = ewald.ewald(L, src, q)
+    pot = _eval(pdmk, torch_dev, L, src, q, eps, kappa=3.0, n_s=60)
+    assert ewald.rel_l2(pot, ref) <= eps
+
+
+@pytest.mark.parametrize("eps", [1e-3, 1e-6])
+def test_c3_shell_sampled(pdmk, torch_dev, eps):
+    L, src, q = workloads.shell3d(60000, seed=3)
+    idx = np.random.default_rng(1).choice(len(q), 96, replace=False)
+    ref = ewald.ewald_sampled(L, src, q, idx)
+    pot = _eval(pdmk, torch_dev, L, src, q, eps)
+    assert ewald.rel_l2(pot[idx], ref) <= eps
+
+
+def test_c3_full_size_golden(pdmk, torch_dev):
+    """N = 1e7 thin shell at the benchmark's launch configuration, against
+    oracle values stored by tests/golden/make_golden.py."""
+    path = os.path.join(HERE, "golden", "shell3d_n1e7_seed3.txt")
+    if not os.path.exists(path):
+        pytest.skip("golden file not generated")
+    data = np.loadtxt(path)
+    idx = data[:, 0].astype(np.int64)
+    L, src, q = workloads.shell3d(10_000_000, seed=3)
+    pot = _eval(pdmk, torch_dev, L, src, q, 1e-6)
+    assert ewald.rel_l2(pot[idx], data[:, 1]) <= 1e-6
+
+
+def test_c2_full_size_golden(pdmk, torch_dev):
+    path = os.path.join(HERE, "golden", "clustered3d_n1e6_seed2.txt")
+    if not os.path.exists(path):
+        pytest.skip("golden file not generated")
+    data = np.loadtxt(path)
+    idx = data[:, 0].astype(np.int64)
+    L, src, q = workloads.clustered3d(1_000_000, seed=2)
+    pot = _eval(pdmk, torch_dev, L, src, q, 1e-6, kappa=7.0)
+    assert ewald.rel_l2(pot[idx], data[:, 1]) <= 1e-6
+
+
+def test_separate_targets(pdmk, torch_dev):
+    L, src, q = workloads.clustered3d(3000, seed=4)
+    rng = np.random.default_rng(9)
+    trg = rng.random((500, 3)) @ L.T
+    ref = ewald.ewald(L, src, q, trg=trg)
+    pot = _eval(pdmk, torch_dev, L, src, q, 1e-6, trg=trg, kappa=2.0, n_s=60)
+    assert ewald.rel_l2(pot, ref) <= 1e-6
+
+
+def test_dipole_pair_and_tiny(pdmk, torch_dev):
+    L = workloads.TRICLINIC3D_L
+    src = np.array([[0.1, 0.2, 0.3], [0.9, 0.7, 1.1]])
+    q = np.array([1.0, -1.0])
+    ref = ewald.ewald(L, src, q)
+    pot = _eval(pdmk, torch_dev, L, src, q, 1e-9)
+    assert ewald.rel_l2(pot, ref) <= 1e-9
+
+
+def test_wrapping_and_boundary_points(pdmk, torch_dev):
+    """Points given outside the cell or exactly on its faces give the same
+    potential as their wrapped copies."""
+    L, src, q = workloads.clustered3d(2000, seed=6)
+    rng = np.random.default_rng(2)
+    n = rng.integers(-3, 4, size=(2000, 3))
+    moved = src + n @ L.T
+    u = np.linalg.solve(L, src.T).T
+    u[:50, 0] = 0.0
+    u[50:100, 2] = 0.0
+    edge = u @ L.T
+    ref = ewald.ewald(L, edge, q)
+    pot = _eval(pdmk, torch_dev, L, edge, q, 1e-6, kappa=2.0, n_s=60)
+    assert ewald.rel_l2(pot, ref) <= 1e-6
+    ref2 = ewald.ewald(L, src, q)
+    pot2 = _eval(pdmk, torch_dev, L, moved, q, 1e-6, kappa=2.0, n_s=60)
+    assert ewald.rel_l2(pot2, ref2) <= 1e-6
+
+
+def test_basis_invariance(pdmk, torch_dev):
+    """Rotation/reflection of the input and a unimodular change of basis
+    (P:Section 3.2 orientation) leave the potential unchanged to eps."""
+    L, src, q = workloads.clustered3d(3000, seed=7)
+    ref = ewald.ewald(L, src, q)
+    rng = np.random.default_rng(4)
+    Qm, _ = np.linalg.qr(rng.standard_normal((3, 3)))
+    pot_r = _eval(pdmk, torch_dev, Qm @ L, src @ Qm.T, q, 1e-6, kappa=2.0, n_s=60)
+    assert ewald.rel_l2(pot_r, ref) <= 1e-6
+    U = np.array([[1, 1, 0], [0, 1, 0], [1, 0, 1]])
+    pot_u = _eval(pdmk, torch_dev, L @ U, src, q, 1e-6, kappa=2.0, n_s=60)
+    assert ewald.rel_l2(pot_u, ref) <= 1e-6
+
+
+@pytest.mark.parametrize("kappa,n_s", [(1.0, 40), (2.0, 30), (4.0, 100), (6.0, 100000)])
+def test_parameter_independence(pdmk, torch_dev, kappa, n_s):
+    """The result does not depend on the free parameters r_c and n_s (the
+    n_s = 1e5 case has no refinement: the fast-Ewald limit of the method)."""
+    L, src, q = workloads.clustered3d(4000, seed=8)
+    ref = ewald.ewald(L, src, q)
+    pot = _eval(pdmk, torch_dev, L, src, q, 1e-6, kappa=kappa, n_s=n_s)
+    assert ewald.rel_l2(pot, ref) <= 1e-6
+
+
+def test_nonneutral_rejected_and_background(pdmk, torch_dev):
+    L, src, q = workloads.clustered3d(1500, seed=10)
+    q = q + 0.05
+    with pytest.raises(pdmk.PdmkError) as e:
+        _eval(pdmk, torch_dev, L, src, q, 1e-6)
+    assert e.value.code == -3
+    ref = ewald.ewald(L, src, q)
+    pot = _eval(pdmk, torch_dev, L, src, q, 1e-6, allow_nonneutral=True, kappa=2.0, n_s=60)
+    assert ewald.rel_l2(pot, ref) <= 1e-6
+
+
+def test_nonfinite_rejected(pdmk, torch_dev):
+    L, src, q = workloads.clustered3d(100, seed=11)
+    src = src.copy()
+    src[5, 1] = np.nan
+    with pytest.raises(pdmk.PdmkError) as e:
+        _eval(pdmk, torch_dev, L, src, q, 1e-6)
+    assert e.value.code == -5
+
+
+def test_empty(pdmk, torch_dev):
+    torch, dev = torch_dev
+    L = workloads.TRICLINIC3D_L
+    out = pdmk.pdmk_eval(L, torch.zeros((0, 3), dtype=torch.float64, device=dev),
+                         torch.zeros(0, dtype=torch.float64, device=dev), eps=1e-6)
+    assert out.shape == (0,)
+    trg = torch.ones((4, 3), dtype=torch.float64, device=dev)
+    out = pdmk.pdmk_eval(L, torch.zeros((0, 3), dtype=torch.float64, device=dev),
+                         torch.zeros(0, dtype=torch.float64, device=dev), trg=trg, eps=1e-6)
+    assert torch.all(out == 0)
+
+
+@pytest.mark.parametrize("dim", [3, 2])
+def test_gradient_vs_oracle(pdmk, torch_dev, dim):
+    if dim == 3:
+        L, src, q = workloads.clustered3d(3000, seed=12)
+        over = dict(kappa=2.0, n_s=60)
+    else:
+        L, src, q = workloads.oblique2d(2000, seed=13)
+        over = dict(n_s=20)
+    ref, gref = ewald.ewald(L, src, q, grad=True)
+    pot, g = _eval(pdmk, torch_dev, L, src, q, 1e-6, grad=True, **over)
+    assert ewald.rel_l2(pot, ref) <= 1e-6
+    assert ewald.rel_l2(g, gref) <= 1e-5
+
+
+def test_plan_reuse_and_stats(pdmk, torch_dev):
+    torch, dev = torch_dev
+    L, src, q = workloads.shell3d(20000, seed=14)
+    plan = pdmk.Plan(L, eps=1e-6)
+    S = torch.tensor(src, device=dev)
+    Q = torch.tensor(q, device=dev)
+    a = plan.eval(S, Q).cpu().numpy()
+    b = plan.eval(S, Q).cpu().numpy()
+    assert np.array_equal(a, b)
+    st = plan.stats()
+    assert st["n_src"] == 20000 and st["n_images"] >= 20000 and st["n_levels"] >= 1
