@@ -87,6 +87,9 @@ typedef struct {
   int porder;       /* Chebyshev proxy points per axis; <= 0: chosen from eps */
   int npw;          /* plane-wave half count J per axis (modes -J..J); <= 0: from eps */
   int nufft_w;      /* spreading-window width in grid cells; <= 0: from eps */
+  double sigma;     /* Fourier grid per axis = sigma * M_i of eq:Mi rounded up to a
+                       2,3,5-smooth even size; <= 0: 1 (no upsampling, as in the
+                       paper) for eps >= 1e-7, 2 below */
 } pdmk_opts;
 
 /* Fill *out with the defaults for (dim, eps).  Host only; no device needed. */

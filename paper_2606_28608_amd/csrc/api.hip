@@ -58,10 +58,16 @@ void plan_upload_tables(pdmk_plan* P) {
   const int d = P->g.dim;
   const int p = P->mp.porder, J = P->mp.npw;
   ChebSeries Ed = cheb_derivative(P->T->E), F2d = cheb_derivative(P->T->F2);
-  P->d_E = upload(P->T->E.a);
-  P->d_Ed = upload(Ed.a);
-  P->d_F2 = upload(P->T->F2.a);
-  P->d_F2d = upload(F2d.a);
+  // device copies zero-padded to 32 terms (kernels unroll to a fixed length)
+  auto pad = [](std::vector<double> v) {
+    if (v.size() > 32) throw Error{PDMK_ERR_UNSUPPORTED, "kernel series longer than 32 terms"};
+    v.resize(32, 0.0);
+    return v;
+  };
+  P->d_E = upload(pad(P->T->E.a));
+  P->d_Ed = upload(pad(Ed.a));
+  P->d_F2 = upload(pad(P->T->F2.a));
+  P->d_F2d = upload(pad(F2d.a));
   std::vector<double> nodes, bw;
   cheb_nodes(p, nodes, bw);
   P->d_nodes = upload(nodes);
@@ -139,16 +145,15 @@ __global__ void k_charge_stats(int64_t n, const double* __restrict__ q, double* 
 
 __global__ void k_assemble(int64_t n, int d, const int* __restrict__ tperm,
                            const double* __restrict__ ps, const double* __restrict__ gs,
-                           const double* __restrict__ fp, const double* __restrict__ fg,
                            double shift, KParams kp, double* __restrict__ pot,
                            double* __restrict__ grad) {
   int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= n) return;
   const int o = tperm[t];
-  pot[o] = ps[t] + fp[o] + shift;
+  pot[o] = ps[t] + shift;
   if (grad) {
     double g[3] = {0, 0, 0};
-    for (int a = 0; a < d; ++a) g[a] = gs[t * d + a] + fg[(int64_t)o * d + a];
+    for (int a = 0; a < d; ++a) g[a] = gs[t * d + a];
     for (int a = 0; a < d; ++a) {
       double s = 0;
       for (int b = 0; b < d; ++b) s += kp.Q[a + d * b] * g[b];
@@ -202,6 +207,7 @@ int pdmk_default_opts(int dim, double eps, pdmk_opts* out) {
   out->porder = m.porder;
   out->npw = m.npw;
   out->nufft_w = m.nufft_w;
+  out->sigma = m.sigma;
   return PDMK_OK;
 }
 
@@ -245,8 +251,8 @@ static int validate_opts(const pdmk_opts* o) {
     return fail(PDMK_ERR_INVALID_ARG, "unknown precision");
   if (o->precision == PDMK_PREC_MIXED)
     return fail(PDMK_ERR_UNSUPPORTED, "mixed precision not available in this build");
-  if (o->porder > 64 || o->npw > 64 || o->nufft_w > 16)
-    return fail(PDMK_ERR_INVALID_ARG, "porder/npw <= 64 and nufft_w <= 16");
+  if (o->porder > 40 || o->npw > 64 || o->nufft_w > 16 || o->sigma > 4.0)
+    return fail(PDMK_ERR_INVALID_ARG, "porder <= 40, npw <= 64, nufft_w <= 16, sigma <= 4");
   return PDMK_OK;
 }
 
@@ -269,14 +275,13 @@ int pdmk_plan_create(const pdmk_opts* opts, const double* L, pdmk_plan** out) {
     if (opts->n_s > 0) P->mp.n_s = opts->n_s;
     if (opts->porder > 0) P->mp.porder = opts->porder;
     if (opts->npw > 0) P->mp.npw = opts->npw;
-    if (opts->nufft_w > 0) {
-      P->mp.nufft_w = opts->nufft_w;
-      P->mp.beta = 2.0 * opts->nufft_w;
-    }
+    if (opts->sigma > 0) P->mp.sigma = opts->sigma;
+    if (opts->nufft_w > 0) P->mp.nufft_w = opts->nufft_w;
+    P->mp.beta = window_beta(P->mp.nufft_w, P->mp.sigma);
     P->nufft_beta = P->mp.beta;
     P->P = &pswf_for_eps(opts->eps);
     P->T = &tables_for_eps(opts->eps);
-    std::string msg = make_geometry(d, L, P->mp.kappa, P->P->c, P->g);
+    std::string msg = make_geometry(d, L, P->mp.kappa, P->P->c, P->mp.sigma, P->g);
     if (!msg.empty()) {
       delete P;
       return fail(msg.find("kappa") != std::string::npos ? PDMK_ERR_INVALID_ARG
@@ -365,14 +370,13 @@ int pdmk_geometry_get(const pdmk_opts* opts, const double* L, pdmk_geometry* out
   if (opts->n_s > 0) tmp.mp.n_s = opts->n_s;
   if (opts->porder > 0) tmp.mp.porder = opts->porder;
   if (opts->npw > 0) tmp.mp.npw = opts->npw;
-  if (opts->nufft_w > 0) {
-    tmp.mp.nufft_w = opts->nufft_w;
-    tmp.mp.beta = 2.0 * opts->nufft_w;
-  }
+  if (opts->sigma > 0) tmp.mp.sigma = opts->sigma;
+  if (opts->nufft_w > 0) tmp.mp.nufft_w = opts->nufft_w;
+  tmp.mp.beta = window_beta(tmp.mp.nufft_w, tmp.mp.sigma);
   tmp.nufft_beta = tmp.mp.beta;
   tmp.P = &pswf_for_eps(opts->eps);
   tmp.T = &tables_for_eps(opts->eps);
-  std::string msg = make_geometry(opts->dim, L, tmp.mp.kappa, tmp.P->c, tmp.g);
+  std::string msg = make_geometry(opts->dim, L, tmp.mp.kappa, tmp.P->c, tmp.mp.sigma, tmp.g);
   if (!msg.empty())
     return fail(msg.find("kappa") != std::string::npos ? PDMK_ERR_INVALID_ARG
                                                         : PDMK_ERR_SINGULAR_LATTICE,
@@ -449,7 +453,7 @@ int pdmk_plan_eval(pdmk_plan* P, int64_t n_src, const double* src, const double*
     const double cnn = -P->P->psit_dd0 * P->g.rc * P->g.rc / (2.0 * cc * cc * P->g.volume);
     const double shift = -hq[0] * cnn;
     hipLaunchKernelGGL(k_assemble, dim3(nblk(n_trg, 256)), dim3(256), 0, s, n_trg, d, E.tperm,
-                       E.pot_sorted, E.grad_sorted, E.far_pot, E.far_grad, shift, P->kp, pot,
+                       E.pot_sorted, E.grad_sorted, shift, P->kp, pot,
                        want_grad ? grad : nullptr);
     PDMK_HIP(hipEventRecord(ev[4], s));
     PDMK_HIP(hipEventSynchronize(ev[4]));

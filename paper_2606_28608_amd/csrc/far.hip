@@ -8,6 +8,8 @@
 // What_0(k) = psi~(k r_c / c) / k^2 (eq:W0hat), computed once per plan in FP64.
 // The FFT is a hand-written mixed-radix (2, 3, 4, 5) Stockham transform; each
 // workgroup transforms one grid line held in LDS.
+#include <climits>
+
 #include "internal.h"
 
 namespace pdmk {
@@ -153,6 +155,241 @@ __global__ void k_spread(int64_t n, const double* __restrict__ u, const double* 
   }
 }
 
+// Tiled spreading: a block takes 256 consecutive sources in tree order; their
+// windows cover a small box of grid cells, accumulated in an LDS subgrid with
+// LDS atomics and then added to the grid with one global atomic per touched
+// cell.  A block whose box exceeds the LDS subgrid (sources straddling the
+// periodic boundary) falls back to global atomics.
+constexpr int kSubCap = 8192;
+
+template <int D>
+__device__ inline void grid_coords(const KParams& kp, const double* __restrict__ x, int64_t n,
+                                   int64_t i, const int* Ms, double* g) {
+  // fractional coordinates u = L^{-1} x' of an oriented point, in grid units
+  for (int a = 0; a < D; ++a) {
+    double s = 0.0;
+    for (int b = a; b < D; ++b) s += kp.Li[a + D * b] * x[b * n + i];
+    s -= floor(s);
+    g[a] = s * Ms[a];
+  }
+}
+
+template <int D>
+__global__ __launch_bounds__(256) void k_spread_tiled(KParams kp, int64_t n,
+                                                      const double* __restrict__ x,
+                                                      const double* __restrict__ q, int M0,
+                                                      int M1, int M2, int w, double beta,
+                                                      double* __restrict__ grid) {
+  __shared__ double sub[kSubCap];
+  __shared__ int lo[3], hi[3];
+  const int Ms[3] = {M0, M1, M2};
+  const double hw = 0.5 * w;
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const bool valid = i < n;
+  if (threadIdx.x < 3) {
+    lo[threadIdx.x] = INT_MAX;
+    hi[threadIdx.x] = INT_MIN;
+  }
+  __syncthreads();
+  double g[D];
+  int i0[D];
+  if (valid) {
+    grid_coords<D>(kp, x, n, i, Ms, g);
+    for (int a = 0; a < D; ++a) {
+      i0[a] = (int)ceil(g[a] - hw);
+      atomicMin(&lo[a], i0[a]);
+      atomicMax(&hi[a], i0[a]);
+    }
+  }
+  __syncthreads();
+  int ext[3] = {1, 1, 1};
+  long long vol = 1;
+  for (int a = 0; a < D; ++a) {
+    ext[a] = hi[a] - lo[a] + w;
+    vol *= ext[a];
+  }
+  const bool tiled = vol <= kSubCap;
+  if (tiled) {
+    for (int c = threadIdx.x; c < vol; c += 256) sub[c] = 0.0;
+    __syncthreads();
+  }
+  if (valid) {
+    const double qi = q[i];
+    double wt[D][16];
+    for (int a = 0; a < D; ++a)
+      for (int k = 0; k < w; ++k) wt[a][k] = es_win((i0[a] + k - g[a]) / hw, beta);
+    if (tiled) {
+      const int o0 = i0[0] - lo[0], o1 = i0[1] - lo[1], o2 = D == 3 ? i0[2] - lo[2] : 0;
+      if (D == 3) {
+        for (int k2 = 0; k2 < w; ++k2)
+          for (int k1 = 0; k1 < w; ++k1) {
+            const double w12 = qi * wt[1][k1] * wt[D - 1][k2];
+            double* row = sub + ((o2 + k2) * ext[1] + (o1 + k1)) * ext[0] + o0;
+            for (int k0 = 0; k0 < w; ++k0) atomicAdd(row + k0, w12 * wt[0][k0]);
+          }
+      } else {
+        for (int k1 = 0; k1 < w; ++k1) {
+          const double w1 = qi * wt[1][k1];
+          double* row = sub + (o1 + k1) * ext[0] + o0;
+          for (int k0 = 0; k0 < w; ++k0) atomicAdd(row + k0, w1 * wt[0][k0]);
+        }
+      }
+    } else {
+      int ix[D][16];
+      for (int a = 0; a < D; ++a)
+        for (int k = 0; k < w; ++k) {
+          int id = (i0[a] + k) % Ms[a];
+          ix[a][k] = id < 0 ? id + Ms[a] : id;
+        }
+      if (D == 3) {
+        for (int k2 = 0; k2 < w; ++k2)
+          for (int k1 = 0; k1 < w; ++k1) {
+            const double w12 = qi * wt[1][k1] * wt[D - 1][k2];
+            const int64_t row = (int64_t)M0 * (ix[1][k1] + (int64_t)M1 * ix[D - 1][k2]);
+            for (int k0 = 0; k0 < w; ++k0) atomicAdd(grid + row + ix[0][k0], w12 * wt[0][k0]);
+          }
+      } else {
+        for (int k1 = 0; k1 < w; ++k1) {
+          const double w1 = qi * wt[1][k1];
+          const int64_t row = (int64_t)M0 * ix[1][k1];
+          for (int k0 = 0; k0 < w; ++k0) atomicAdd(grid + row + ix[0][k0], w1 * wt[0][k0]);
+        }
+      }
+    }
+  }
+  if (tiled) {
+    __syncthreads();
+    for (int c = threadIdx.x; c < vol; c += 256) {
+      const double v = sub[c];
+      if (v == 0.0) continue;
+      int cc[3] = {c % ext[0], (c / ext[0]) % ext[1], c / (ext[0] * ext[1])};
+      int64_t gi = 0, mul = 1;
+      for (int a = 0; a < D; ++a) {
+        int id = (lo[a] + cc[a]) % Ms[a];
+        if (id < 0) id += Ms[a];
+        gi += id * mul;
+        mul *= Ms[a];
+      }
+      atomicAdd(grid + gi, v);
+    }
+  }
+}
+
+// Tiled interpolation at targets in tree order: the block's subgrid is read
+// into LDS once; results are added to the near-field arrays (tree order).
+template <int D>
+__global__ __launch_bounds__(256) void k_interp_tiled(KParams kp, int64_t n,
+                                                      const double* __restrict__ x, int M0,
+                                                      int M1, int M2, int w, double beta,
+                                                      const double2* __restrict__ grid,
+                                                      double* __restrict__ pot,
+                                                      double* __restrict__ grad, int want_grad) {
+  __shared__ double sub[kSubCap];
+  __shared__ int lo[3], hi[3];
+  const int Ms[3] = {M0, M1, M2};
+  const double hw = 0.5 * w;
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const bool valid = i < n;
+  if (threadIdx.x < 3) {
+    lo[threadIdx.x] = INT_MAX;
+    hi[threadIdx.x] = INT_MIN;
+  }
+  __syncthreads();
+  double g[D];
+  int i0[D];
+  if (valid) {
+    grid_coords<D>(kp, x, n, i, Ms, g);
+    for (int a = 0; a < D; ++a) {
+      i0[a] = (int)ceil(g[a] - hw);
+      atomicMin(&lo[a], i0[a]);
+      atomicMax(&hi[a], i0[a]);
+    }
+  }
+  __syncthreads();
+  int ext[3] = {1, 1, 1};
+  long long vol = 1;
+  for (int a = 0; a < D; ++a) {
+    ext[a] = hi[a] - lo[a] + w;
+    vol *= ext[a];
+  }
+  const bool tiled = vol <= kSubCap;
+  if (tiled) {
+    for (int c = threadIdx.x; c < vol; c += 256) {
+      int cc[3] = {c % ext[0], (c / ext[0]) % ext[1], c / (ext[0] * ext[1])};
+      int64_t gi = 0, mul = 1;
+      for (int a = 0; a < D; ++a) {
+        int id = (lo[a] + cc[a]) % Ms[a];
+        if (id < 0) id += Ms[a];
+        gi += id * mul;
+        mul *= Ms[a];
+      }
+      sub[c] = grid[gi].x;
+    }
+    __syncthreads();
+  }
+  if (!valid) return;
+  double wt[D][16], dw[D][16];
+  int ix[D][16];
+  for (int a = 0; a < D; ++a)
+    for (int k = 0; k < w; ++k) {
+      const double z = (i0[a] + k - g[a]) / hw;
+      const double v = es_win(z, beta);
+      wt[a][k] = v;
+      const double t = 1.0 - z * z;
+      dw[a][k] = (t > 0.0) ? v * beta * (-z / sqrt(t)) * (-Ms[a] / hw) : 0.0;
+      if (tiled) {
+        ix[a][k] = i0[a] + k - lo[a];
+      } else {
+        int id = (i0[a] + k) % Ms[a];
+        ix[a][k] = id < 0 ? id + Ms[a] : id;
+      }
+    }
+  const int s0 = tiled ? ext[0] : M0;
+  const int s1 = tiled ? ext[1] : M1;
+  double acc = 0.0, gu[3] = {0, 0, 0};
+  if (D == 3) {
+    for (int k2 = 0; k2 < w; ++k2)
+      for (int k1 = 0; k1 < w; ++k1) {
+        const int64_t row = (int64_t)s0 * (ix[1][k1] + (int64_t)s1 * ix[D - 1][k2]);
+        double a0 = 0.0, ad0 = 0.0;
+        for (int k0 = 0; k0 < w; ++k0) {
+          const double v = tiled ? sub[row + ix[0][k0]] : grid[row + ix[0][k0]].x;
+          a0 = fma(v, wt[0][k0], a0);
+          if (want_grad) ad0 = fma(v, dw[0][k0], ad0);
+        }
+        const double w12 = wt[1][k1] * wt[D - 1][k2];
+        acc = fma(a0, w12, acc);
+        if (want_grad) {
+          gu[0] = fma(ad0, w12, gu[0]);
+          gu[1] = fma(a0, dw[1][k1] * wt[D - 1][k2], gu[1]);
+          gu[2] = fma(a0, wt[1][k1] * dw[D - 1][k2], gu[2]);
+        }
+      }
+  } else {
+    for (int k1 = 0; k1 < w; ++k1) {
+      const int64_t row = (int64_t)s0 * ix[1][k1];
+      double a0 = 0.0, ad0 = 0.0;
+      for (int k0 = 0; k0 < w; ++k0) {
+        const double v = tiled ? sub[row + ix[0][k0]] : grid[row + ix[0][k0]].x;
+        a0 = fma(v, wt[0][k0], a0);
+        if (want_grad) ad0 = fma(v, dw[0][k0], ad0);
+      }
+      acc = fma(a0, wt[1][k1], acc);
+      if (want_grad) {
+        gu[0] = fma(ad0, wt[1][k1], gu[0]);
+        gu[1] = fma(a0, dw[1][k1], gu[1]);
+      }
+    }
+  }
+  pot[i] += acc;
+  if (want_grad)
+    for (int b = 0; b < D; ++b) {
+      double s = 0.0;
+      for (int a = 0; a <= b; ++a) s += kp.Li[a + D * b] * gu[a];
+      grad[i * D + b] += s;
+    }
+}
+
 __global__ void k_to_complex(int64_t n, const double* __restrict__ g, double2* __restrict__ c) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) c[i] = make_double2(g[i], 0.0);
@@ -237,7 +474,8 @@ __global__ void k_interp(KParams kp, int64_t n, const double* __restrict__ u, in
 }
 
 // Diagonal scaling table (FP64), once per plan.
-__global__ void k_farscale(KParams kp, int M0, int M1, int M2, const double* __restrict__ wf0,
+__global__ void k_farscale(KParams kp, int M0, int M1, int M2, int Mp0, int Mp1, int Mp2,
+                           const double* __restrict__ wf0,
                            const double* __restrict__ wf1, const double* __restrict__ wf2,
                            const double* __restrict__ gx, const double* __restrict__ gwpsi, int nq,
                            double c, double c0, double V, double* __restrict__ out) {
@@ -249,9 +487,12 @@ __global__ void k_farscale(KParams kp, int M0, int M1, int M2, const double* __r
   const int Ms[3] = {M0, M1, M2};
   int m[3] = {0, 0, 0};
   bool nyq = false, zero = true;
+  const int Mp[3] = {Mp0, Mp1, Mp2};
   for (int a = 0; a < d; ++a) {
     m[a] = ii[a] < Ms[a] / 2 ? ii[a] : ii[a] - Ms[a];
     if (Ms[a] > 1 && Ms[a] % 2 == 0 && ii[a] == Ms[a] / 2) nyq = true;
+    // only the modes of the grid of eq:Mi are kept (|m_a| < M_a / 2)
+    if (2 * m[a] >= Mp[a] || 2 * m[a] < -Mp[a] + 1) nyq = true;
     if (m[a] != 0) zero = false;
   }
   if (nyq || zero) { out[idx] = 0.0; return; }
@@ -296,7 +537,8 @@ void far_build_scale(pdmk_plan* P) {
   double* dgx = up(ps.qx);
   double* dgw = up(gwpsi);
   PDMK_HIP(hipMalloc(&P->d_farscale, n * sizeof(double)));
-  hipLaunchKernelGGL(k_farscale, dim3(nblk(n, 256)), dim3(256), 0, 0, P->kp, M[0], M[1], M[2], d0,
+  hipLaunchKernelGGL(k_farscale, dim3(nblk(n, 256)), dim3(256), 0, 0, P->kp, M[0], M[1], M[2],
+                     g.fgrid_paper[0], g.fgrid_paper[1], d == 3 ? g.fgrid_paper[2] : 1, d0,
                      d1, d2, dgx, dgw, (int)ps.qx.size(), ps.c, ps.c0, g.volume, P->d_farscale);
   PDMK_HIP(hipDeviceSynchronize());
   for (void* p : tmp) (void)hipFree(p);
@@ -314,27 +556,25 @@ void stage_far(pdmk_plan* P, Eval& E, const double* q, bool want_grad) {
   PDMK_HIP(hipMemsetAsync(grid, 0, n * sizeof(double), E.s));
   if (E.n_src > 0) {
     if (d == 3)
-      hipLaunchKernelGGL(k_spread<3>, dim3(nblk(E.n_src, 256)), dim3(256), 0, E.s, E.n_src, E.us,
-                         q, M[0], M[1], M[2], w, beta, grid);
+      hipLaunchKernelGGL(k_spread_tiled<3>, dim3(nblk(E.n_src, 256)), dim3(256), 0, E.s, P->kp,
+                         E.n_src, E.ox, E.oq, M[0], M[1], M[2], w, beta, grid);
     else
-      hipLaunchKernelGGL(k_spread<2>, dim3(nblk(E.n_src, 256)), dim3(256), 0, E.s, E.n_src, E.us,
-                         q, M[0], M[1], M[2], w, beta, grid);
+      hipLaunchKernelGGL(k_spread_tiled<2>, dim3(nblk(E.n_src, 256)), dim3(256), 0, E.s, P->kp,
+                         E.n_src, E.ox, E.oq, M[0], M[1], M[2], w, beta, grid);
   }
   hipLaunchKernelGGL(k_to_complex, dim3(nblk(n, 256)), dim3(256), 0, E.s, n, grid, cg);
   fft3(cg, M, d, -1, E.s);
   hipLaunchKernelGGL(k_scale, dim3(nblk(n, 256)), dim3(256), 0, E.s, n, cg, P->d_farscale);
   fft3(cg, M, d, +1, E.s);
-  E.far_pot = E.alloc<double>(E.n_trg);
-  E.far_grad = want_grad ? E.alloc<double>(E.n_trg * d) : nullptr;
   if (E.n_trg > 0) {
     if (d == 3)
-      hipLaunchKernelGGL(k_interp<3>, dim3(nblk(E.n_trg, 256)), dim3(256), 0, E.s, P->kp, E.n_trg,
-                         E.ut, M[0], M[1], M[2], w, beta, cg, E.far_pot, E.far_grad,
-                         want_grad ? 1 : 0);
+      hipLaunchKernelGGL(k_interp_tiled<3>, dim3(nblk(E.n_trg, 256)), dim3(256), 0, E.s, P->kp,
+                         E.n_trg, E.tx, M[0], M[1], M[2], w, beta, cg, E.pot_sorted,
+                         E.grad_sorted, want_grad ? 1 : 0);
     else
-      hipLaunchKernelGGL(k_interp<2>, dim3(nblk(E.n_trg, 256)), dim3(256), 0, E.s, P->kp, E.n_trg,
-                         E.ut, M[0], M[1], M[2], w, beta, cg, E.far_pot, E.far_grad,
-                         want_grad ? 1 : 0);
+      hipLaunchKernelGGL(k_interp_tiled<2>, dim3(nblk(E.n_trg, 256)), dim3(256), 0, E.s, P->kp,
+                         E.n_trg, E.tx, M[0], M[1], M[2], w, beta, cg, E.pot_sorted,
+                         E.grad_sorted, want_grad ? 1 : 0);
   }
 }
 

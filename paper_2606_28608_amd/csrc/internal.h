@@ -96,6 +96,8 @@ struct Eval {
   double* tx = nullptr;   // dim * n_trg
   uint64_t* tkey = nullptr;
   int* tperm = nullptr;   // sorted target -> original target index
+  double* ox = nullptr;   // original sources in tree order (dim * n_src), for the far field
+  double* oq = nullptr;
   std::vector<Level> lev;
   Level* d_lev = nullptr;   // device copy of lev (for list building)
   // target leaves

@@ -54,10 +54,55 @@ __device__ inline void lagrange_rows(int p, const double* __restrict__ nodes,
   for (int j = 0; j < p; ++j) row[j] *= is;
 }
 
+// Same as lagrange_rows with compile-time capacity PMAX (entries >= p are 0),
+// so the rows stay in registers.
+template <int PMAX, bool DER>
+__device__ inline void lagrange_rows_reg(int p, const double* __restrict__ nodes,
+                                         const double* __restrict__ bw, double x,
+                                         double (&row)[PMAX], double (&drow)[PMAX]) {
+#pragma unroll
+  for (int m = 0; m < PMAX; ++m)
+    if (m < p && x == nodes[m]) x += 1e-13;
+  double s = 0.0, s1 = 0.0;
+  double inv[PMAX];
+#pragma unroll
+  for (int m = 0; m < PMAX; ++m) {
+    if (m < p) {
+      inv[m] = 1.0 / (x - nodes[m]);
+      const double t = bw[m] * inv[m];
+      row[m] = t;
+      s += t;
+      s1 += t * inv[m];
+    } else {
+      inv[m] = 0.0;
+      row[m] = 0.0;
+    }
+  }
+  const double is = 1.0 / s;
+#pragma unroll
+  for (int m = 0; m < PMAX; ++m) {
+    const double lj = row[m] * is;
+    if (DER) drow[m] = lj * (s1 * is - inv[m]);
+    row[m] = lj;
+  }
+}
+
 // ------------------------------------------------------------- residual sums
-// One 64-thread block per target leaf; sources of each list entry are staged
-// through LDS in tiles of 64.
-template <int D>
+// One 64-lane block per target leaf.  The block walks the concatenated source
+// ranges of the leaf's list in tiles of 64 staged in LDS (each slot carries
+// its own support h of the residual level), so short ranges do not leave
+// tiles half empty.  Leaves with few targets split each tile over S lanes per
+// target (S = 1, 2, 4, 8) and reduce across those lanes at the end.  The pair
+// kernel is evaluated without branches and masked outside its support.
+__device__ inline double rsqrt_f64(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+  double hx = 0.5 * x;
+  y = y * fma(-hx * y, y, 1.5);
+  y = y * fma(-hx * y, y, 1.5);
+  return y;
+}
+
+template <int D, int NE>
 __global__ __launch_bounds__(64) void k_direct(
     KParams kp, int nleaf, const Level* __restrict__ lev, const int* __restrict__ lf_level,
     const int* __restrict__ lf_box, const int* __restrict__ lbeg, const int4* __restrict__ list,
@@ -67,70 +112,118 @@ __global__ __launch_bounds__(64) void k_direct(
     const double* __restrict__ Edc, double* __restrict__ pot, double* __restrict__ grad,
     int want_grad) {
   __shared__ double shx[D][64];
-  __shared__ double shq[64];
+  __shared__ double shq[64], shh2[64], shih[64];
   const int i = blockIdx.x;
   if (i >= nleaf) return;
+  // series coefficients (zero-padded to NE) held in registers
+  double ec[NE], edc[NE];
+#pragma unroll
+  for (int k = 0; k < NE; ++k) {
+    ec[k] = Ec[k];
+    edc[k] = Edc[k];
+  }
+  const int lane = threadIdx.x;
   const int lvl = lf_level[i], b = lf_box[i];
   const Level& T = lev[lvl];
   const int tb = T.tbeg[b], te = T.tend[b];
+  const int nt = te - tb;
   const int lb = lbeg[i], le = lbeg[i + 1];
   const double hT = kp.rc / (double)(1 << lvl);
-  const int nc = D == 3 ? kp.nE : kp.nF2;
-  const int ncd = D == 3 ? kp.nEd : kp.nF2d;
-  for (int t0 = tb; t0 < te; t0 += 64) {
-    const int t = t0 + threadIdx.x;
+  const int S = nt > 32 ? 1 : (nt > 16 ? 2 : (nt > 8 ? 4 : 8));
+  const int tpb = 64 / S;
+  const int slice = lane % S, tslot = lane / S;
+  for (int t0 = tb; t0 < te; t0 += tpb) {
+    const int t = t0 + tslot;
     const bool valid = t < te;
     double x[D];
     for (int a = 0; a < D; ++a) x[a] = valid ? tx[a * ntrg + t] : 0.0;
     double acc = 0.0, g[D];
     for (int a = 0; a < D; ++a) g[a] = 0.0;
-    for (int e = lb; e < le; ++e) {
-      const int4 en = list[e];
-      const double hh = kp.rc / (double)(1 << en.z);
-      const double h2 = hh * hh, ih = 1.0 / hh, ih2 = ih * ih;
-      for (int s0 = en.x; s0 < en.y; s0 += 64) {
-        const int sidx = s0 + threadIdx.x;
-        __syncthreads();
-        if (sidx < en.y) {
-          for (int a = 0; a < D; ++a) shx[a][threadIdx.x] = sx[a * nimg + sidx];
-          shq[threadIdx.x] = sq[sidx];
+    int e = lb, off = 0;
+    while (e < le) {
+      // this lane's slot of the tile: position off + lane along the list
+      int ee = e, oo = off + lane;
+      while (ee < le) {
+        const int len = list[ee].y - list[ee].x;
+        if (oo < len) break;
+        oo -= len;
+        ++ee;
+      }
+      __syncthreads();
+      if (ee < le) {
+        const int4 en = list[ee];
+        const int sidx = en.x + oo;
+        for (int a = 0; a < D; ++a) shx[a][lane] = sx[a * nimg + sidx];
+        shq[lane] = sq[sidx];
+        const double hh = kp.rc / (double)(1 << en.z);
+        shh2[lane] = hh * hh;
+        shih[lane] = 1.0 / hh;
+      } else {
+        for (int a = 0; a < D; ++a) shx[a][lane] = 1e300;
+        shq[lane] = 0.0;
+        shh2[lane] = 0.0;
+        shih[lane] = 1.0;
+      }
+      __syncthreads();
+      // advance the (uniform) cursor by 64 slots
+      oo = off + 64;
+      while (e < le) {
+        const int len = list[e].y - list[e].x;
+        if (oo < len) break;
+        oo -= len;
+        ++e;
+      }
+      off = oo;
+      for (int k = slice; k < 64; k += S) {
+        double dx[D], r2 = 0.0;
+        for (int a = 0; a < D; ++a) {
+          dx[a] = x[a] - shx[a][k];
+          r2 = fma(dx[a], dx[a], r2);
         }
-        __syncthreads();
-        const int ns = min(64, en.y - s0);
-        if (valid) {
-          for (int k = 0; k < ns; ++k) {
-            double dx[D], r2 = 0.0;
-            for (int a = 0; a < D; ++a) {
-              dx[a] = x[a] - shx[a][k];
-              r2 = fma(dx[a], dx[a], r2);
+        if (r2 < shh2[k] && r2 > 0.0) {
+          const double ih = shih[k];
+          const double s = r2 * ih * ih;
+          const double qs = shq[k];
+          // Clenshaw recurrence for sum_k c_k T_k(2s - 1)
+          const double t2 = 4.0 * s - 2.0;
+          double b1 = 0.0, b2 = 0.0, d1 = 0.0, d2 = 0.0;
+#pragma unroll
+          for (int m = NE - 1; m >= 1; --m) {
+            const double b0 = fma(t2, b1, ec[m] - b2);
+            b2 = b1;
+            b1 = b0;
+            if (want_grad) {
+              const double e0 = fma(t2, d1, edc[m] - d2);
+              d2 = d1;
+              d1 = e0;
             }
-            if (r2 < h2 && r2 > 0.0) {
-              const double s = r2 * ih2;
-              const double qs = shq[k];
-              if (D == 3) {
-                const double ir_exact = 1.0 / sqrt(r2);
-                const double Es = clenshaw(Ec, nc, s);
-                acc = fma(qs, ir_exact - Es * ih, acc);
-                if (want_grad) {
-                  const double Ed = clenshaw(Edc, ncd, s);
-                  const double f = qs * (-ir_exact * ir_exact * ir_exact - 2.0 * Ed * ih2 * ih);
-                  for (int a = 0; a < D; ++a) g[a] = fma(f, dx[a], g[a]);
-                }
-              } else {
-                const double F = clenshaw(Ec, nc, s);
-                acc = fma(qs, -0.5 * log(s) + F, acc);
-                if (want_grad) {
-                  const double Fd = clenshaw(Edc, ncd, s);
-                  const double f = qs * (-1.0 / r2 + 2.0 * Fd * ih2);
-                  for (int a = 0; a < D; ++a) g[a] = fma(f, dx[a], g[a]);
-                }
-              }
+          }
+          const double F = fma(0.5 * t2, b1, ec[0] - b2);
+          if (D == 3) {
+            const double ir = rsqrt_f64(r2);
+            acc = fma(qs, ir - F * ih, acc);
+            if (want_grad) {
+              const double Fd = fma(0.5 * t2, d1, edc[0] - d2);
+              const double f = qs * (-ir * ir * ir - 2.0 * Fd * ih * ih * ih);
+              for (int a = 0; a < D; ++a) g[a] = fma(f, dx[a], g[a]);
+            }
+          } else {
+            acc = fma(qs, -0.5 * log(s) + F, acc);
+            if (want_grad) {
+              const double Fd = fma(0.5 * t2, d1, edc[0] - d2);
+              const double f = qs * (-1.0 / r2 + 2.0 * Fd * ih * ih);
+              for (int a = 0; a < D; ++a) g[a] = fma(f, dx[a], g[a]);
             }
           }
         }
       }
     }
-    if (valid) {
+    for (int m = 1; m < S; m <<= 1) {
+      acc += __shfl_xor(acc, m);
+      if (want_grad)
+        for (int a = 0; a < D; ++a) g[a] += __shfl_xor(g[a], m);
+    }
+    if (valid && slice == 0) {
       const double cst = D == 3 ? kInv4Pi : kInv2Pi;
       double v = acc * cst;
       if (self_targets) {
@@ -147,67 +240,67 @@ __global__ __launch_bounds__(64) void k_direct(
 // ------------------------------------------------------ source -> proxy charge
 // Q_B[i0,i1,i2] = sum_s q_s l_i0(xi_0) l_i1(xi_1) l_i2(xi_2) over the sources of
 // the childless children of the non-leaf box B, in B's scaled coordinates.
-// Grid (nnl, chunks of 1024 outputs); 256 threads, 4 outputs each.
-template <int D>
+// A block owns one box; each thread owns one (i0, i1) pair (2D: one i0) and
+// keeps the PMAX accumulators along the last axis in registers.  Lagrange rows
+// of 32 sources at a time are staged in LDS.
+template <int D, int PMAX>
 __global__ __launch_bounds__(256) void k_anterp(KParams kp, Level L, Level C, int lvl,
                                                 const double* __restrict__ sx,
                                                 const double* __restrict__ sq, int64_t nimg,
                                                 const double* __restrict__ nodes,
                                                 const double* __restrict__ bw,
                                                 double* __restrict__ Q) {
-  extern __shared__ double sm[];
+  constexpr int TS = 32;
+  __shared__ double rows[TS * D * PMAX];
+  __shared__ double qs[TS];
   const int p = kp.p;
-  double* rows = sm;                // [64][D][p]
-  double* qs = sm + 64 * D * p;     // [64]
   const int k = blockIdx.x;
   const int b = L.nl_box[k];
   const int pD = D == 3 ? p * p * p : p * p;
+  const int npair = D == 3 ? p * p : p;
   const double h = kp.rc / (double)(1 << lvl);
   double cen[D];
   for (int a = 0; a < D; ++a) cen[a] = kp.origin[a] + (L.coord[b * D + a] + 0.5) * h;
   const double sc = 2.0 / h;
-  int eidx[4][3];
-  bool eval[4];
-  for (int r = 0; r < 4; ++r) {
-    int e = blockIdx.y * 1024 + r * 256 + threadIdx.x;
-    eval[r] = e < pD;
-    if (!eval[r]) e = 0;
-    if (D == 3) {
-      eidx[r][0] = e / (p * p); eidx[r][1] = (e / p) % p; eidx[r][2] = e % p;
-    } else {
-      eidx[r][0] = e / p; eidx[r][1] = e % p; eidx[r][2] = 0;
-    }
-  }
-  double acc[4] = {0, 0, 0, 0};
   const int c0 = L.child0[b];
-  for (int o = 0; o < (1 << D); ++o) {
-    const int c = c0 + o;
-    if (C.child0[c] >= 0) continue;   // non-leaf child: handled by the transfer
-    const int sb = C.sbeg[c], se = C.send[c];
-    for (int s0 = sb; s0 < se; s0 += 64) {
-      const int ns = min(64, se - s0);
-      __syncthreads();
-      if (threadIdx.x < ns * D) {
-        const int si = threadIdx.x / D, a = threadIdx.x % D;
-        const double xi = (sx[a * nimg + s0 + si] - cen[a]) * sc;
-        lagrange_rows(p, nodes, bw, xi, rows + (si * D + a) * p, nullptr);
-      }
-      if (threadIdx.x < ns) qs[threadIdx.x] = sq[s0 + threadIdx.x];
-      __syncthreads();
-      for (int si = 0; si < ns; ++si) {
-        const double* rw = rows + si * D * p;
-        const double qv = qs[si];
-        for (int r = 0; r < 4; ++r) {
-          double v = qv * rw[eidx[r][0]] * rw[p + eidx[r][1]];
-          if (D == 3) v *= rw[2 * p + eidx[r][2]];
-          acc[r] += v;
+  for (int pr0 = 0; pr0 < npair; pr0 += 256) {
+    const int pr = pr0 + threadIdx.x;
+    const bool act = pr < npair;
+    const int i0 = D == 3 ? (act ? pr / p : 0) : (act ? pr : 0);
+    const int i1 = D == 3 ? (act ? pr % p : 0) : 0;
+    double acc[PMAX];
+#pragma unroll
+    for (int j = 0; j < PMAX; ++j) acc[j] = 0.0;
+    for (int o = 0; o < (1 << D); ++o) {
+      const int c = c0 + o;
+      if (C.child0[c] >= 0) continue;   // non-leaf child: handled by the transfer
+      const int sb = C.sbeg[c], se = C.send[c];
+      for (int s0 = sb; s0 < se; s0 += TS) {
+        const int ns = min(TS, se - s0);
+        __syncthreads();
+        if (threadIdx.x < ns * D) {
+          const int si = threadIdx.x / D, a = threadIdx.x % D;
+          const double xi = (sx[a * nimg + s0 + si] - cen[a]) * sc;
+          lagrange_rows(p, nodes, bw, xi, rows + (si * D + a) * PMAX, nullptr);
+        }
+        if (threadIdx.x < ns) qs[threadIdx.x] = sq[s0 + threadIdx.x];
+        __syncthreads();
+        for (int si = 0; si < ns; ++si) {
+          const double* rw = rows + si * D * PMAX;
+          double wv = qs[si] * rw[i0];
+          if (D == 3) wv *= rw[PMAX + i1];
+          const double* rl = rw + (D - 1) * PMAX;
+#pragma unroll
+          for (int j = 0; j < PMAX; ++j) acc[j] = fma(wv, rl[j], acc[j]);
         }
       }
     }
-  }
-  for (int r = 0; r < 4; ++r) {
-    int e = blockIdx.y * 1024 + r * 256 + threadIdx.x;
-    if (eval[r]) Q[(int64_t)k * pD + e] = acc[r];
+    if (act) {
+      double* out = Q + (int64_t)k * pD + (int64_t)pr * p;
+#pragma unroll
+      for (int j = 0; j < PMAX; ++j)
+        if (j < p) out[j] = acc[j];
+    }
   }
 }
 
@@ -364,85 +457,183 @@ __global__ void k_translate(Level L, int J, const double2* __restrict__ S,
 }
 
 // -------------------------------------------------- proxy potential -> targets
-// Targets of a leaf (level >= 1) evaluate the proxy potential of its parent.
-template <int D>
-__global__ __launch_bounds__(64) void k_eval_leaf(
-    KParams kp, int nleaf, const Level* __restrict__ lev, const int* __restrict__ lf_level,
-    const int* __restrict__ lf_box, const double* __restrict__ tx, int64_t ntrg,
+// Targets of the childless children of a non-leaf box P evaluate P's proxy
+// potential (one block per P, one thread per target).  The potential tensor is
+// read through the scalar cache (uniform addresses); the Lagrange rows of the
+// last axis live in registers, the others in LDS (transposed, conflict free).
+typedef const double __attribute__((address_space(4)))* const_dptr;
+
+template <int D, int PMAX, int NT, bool GRAD>
+__global__ __launch_bounds__(NT) void k_eval_children(
+    KParams kp, Level Lp, Level Lc, int lvl, const double* __restrict__ tx, int64_t ntrg,
     const double* __restrict__ nodes, const double* __restrict__ bw,
-    double* __restrict__ pot, double* __restrict__ grad, int want_grad) {
-  extern __shared__ double sm[];
+    double* __restrict__ pot, double* __restrict__ grad) {
+  constexpr int NR = GRAD ? 2 : 1;
+  __shared__ double lrow[NR * (D - 1) * PMAX * NT];   // rows (and derivative rows) of axes < D-1
+  __shared__ int cb[8], cpre[9];
   const int p = kp.p;
-  const int i = blockIdx.x;
-  if (i >= nleaf) return;
-  const int lvl = lf_level[i];
-  if (lvl == 0) return;
-  const int b = lf_box[i];
-  const Level& T = lev[lvl];
-  const Level& Pl = lev[lvl - 1];
-  const int pb = T.parent[b];
-  const int kq = Pl.nlid[pb];
-  const int pD = D == 3 ? p * p * p : p * p;
-  const double* Phi = Pl.proxy_phi + (int64_t)kq * pD;
-  const double hP = kp.rc / (double)(1 << (lvl - 1));
-  double cen[D];
-  for (int a = 0; a < D; ++a) cen[a] = kp.origin[a] + (Pl.coord[pb * D + a] + 0.5) * hP;
-  const double sc = 2.0 / hP;
-  double* row = sm + threadIdx.x * (2 * D * p);
-  double* drow = row + D * p;
-  const int tb = T.tbeg[b], te = T.tend[b];
-  for (int t0 = tb; t0 < te; t0 += 64) {
-    const int t = t0 + threadIdx.x;
-    if (t >= te) continue;
-    for (int a = 0; a < D; ++a) {
-      const double xi = (tx[a * ntrg + t] - cen[a]) * sc;
-      lagrange_rows(p, nodes, bw, xi, row + a * p, want_grad ? drow + a * p : nullptr);
+  const int k = blockIdx.x;
+  const int P = Lp.nl_box[k];
+  const int c0 = Lp.child0[P];
+  if (threadIdx.x == 0) {
+    int acc = 0;
+    for (int o = 0; o < (1 << D); ++o) {
+      const int c = c0 + o;
+      cpre[o] = acc;
+      if (Lc.child0[c] < 0) {
+        cb[o] = Lc.tbeg[c];
+        acc += Lc.tend[c] - Lc.tbeg[c];
+      } else {
+        cb[o] = 0;
+      }
     }
+    cpre[1 << D] = acc;
+  }
+  __syncthreads();
+  const int total = cpre[1 << D];
+  if (total == 0) return;
+  const int pD = D == 3 ? p * p * p : p * p;
+  const_dptr Phi = (const_dptr)(Lp.proxy_phi + (int64_t)k * pD);
+  const double hP = kp.rc / (double)(1 << lvl);
+  double cen[D];
+  for (int a = 0; a < D; ++a) cen[a] = kp.origin[a] + (Lp.coord[P * D + a] + 0.5) * hP;
+  const double sc = 2.0 / hP;
+  const int tid = threadIdx.x;
+  for (int j0 = 0; j0 < total; j0 += NT) {
+    const int j = j0 + tid;
+    const bool valid = j < total;
+    int t = 0;
+    if (valid) {
+      int o = 0;
+      while (o + 1 < (1 << D) && cpre[o + 1] <= j) ++o;
+      t = cb[o] + (j - cpre[o]);
+    }
+    double rl[PMAX], dl[PMAX];
+    for (int a = 0; a < D; ++a) {
+      const double xi = valid ? (tx[a * ntrg + t] - cen[a]) * sc : 0.0;
+      lagrange_rows_reg<PMAX, GRAD>(p, nodes, bw, xi, rl, dl);
+      if (a < D - 1) {
+#pragma unroll
+        for (int m = 0; m < PMAX; ++m) {
+          lrow[(a * PMAX + m) * NT + tid] = rl[m];
+          if (GRAD) lrow[(((D - 1) + a) * PMAX + m) * NT + tid] = dl[m];
+        }
+      }
+    }
+    // rl / dl now hold the last axis
     double acc = 0.0, g0 = 0.0, g1 = 0.0, g2 = 0.0;
     if (D == 3) {
       for (int i0 = 0; i0 < p; ++i0) {
         double a1 = 0.0, a1g1 = 0.0, a1g2 = 0.0;
         for (int i1 = 0; i1 < p; ++i1) {
-          const double* ph = Phi + (i0 * p + i1) * p;
+          const_dptr ph = Phi + (i0 * p + i1) * p;
           double a2 = 0.0, a2d = 0.0;
-          for (int i2 = 0; i2 < p; ++i2) {
-            a2 = fma(ph[i2], row[2 * p + i2], a2);
-            if (want_grad) a2d = fma(ph[i2], drow[2 * p + i2], a2d);
+#pragma unroll
+          for (int m = 0; m < PMAX; ++m) {
+            if (m < p) {
+              const double v = ph[m];
+              a2 = fma(v, rl[m], a2);
+              if (GRAD) a2d = fma(v, dl[m], a2d);
+            }
           }
-          a1 = fma(row[p + i1], a2, a1);
-          if (want_grad) {
-            a1g1 = fma(drow[p + i1], a2, a1g1);
-            a1g2 = fma(row[p + i1], a2d, a1g2);
+          const double r1 = lrow[(PMAX + i1) * NT + tid];
+          a1 = fma(r1, a2, a1);
+          if (GRAD) {
+            a1g1 = fma(lrow[(((D - 1) + 1) * PMAX + i1) * NT + tid], a2, a1g1);
+            a1g2 = fma(r1, a2d, a1g2);
           }
         }
-        acc = fma(row[i0], a1, acc);
-        if (want_grad) {
-          g0 = fma(drow[i0], a1, g0);
-          g1 = fma(row[i0], a1g1, g1);
-          g2 = fma(row[i0], a1g2, g2);
+        const double r0 = lrow[i0 * NT + tid];
+        acc = fma(r0, a1, acc);
+        if (GRAD) {
+          g0 = fma(lrow[((D - 1) * PMAX + i0) * NT + tid], a1, g0);
+          g1 = fma(r0, a1g1, g1);
+          g2 = fma(r0, a1g2, g2);
         }
       }
     } else {
       for (int i0 = 0; i0 < p; ++i0) {
+        const_dptr ph = Phi + i0 * p;
         double a1 = 0.0, a1d = 0.0;
-        for (int i1 = 0; i1 < p; ++i1) {
-          a1 = fma(Phi[i0 * p + i1], row[p + i1], a1);
-          if (want_grad) a1d = fma(Phi[i0 * p + i1], drow[p + i1], a1d);
+#pragma unroll
+        for (int m = 0; m < PMAX; ++m) {
+          if (m < p) {
+            const double v = ph[m];
+            a1 = fma(v, rl[m], a1);
+            if (GRAD) a1d = fma(v, dl[m], a1d);
+          }
         }
-        acc = fma(row[i0], a1, acc);
-        if (want_grad) {
-          g0 = fma(drow[i0], a1, g0);
-          g1 = fma(row[i0], a1d, g1);
+        const double r0 = lrow[i0 * NT + tid];
+        acc = fma(r0, a1, acc);
+        if (GRAD) {
+          g0 = fma(lrow[((D - 1) * PMAX + i0) * NT + tid], a1, g0);
+          g1 = fma(r0, a1d, g1);
         }
       }
     }
-    pot[t] += acc;
-    if (want_grad) {
-      grad[(int64_t)t * D + 0] += g0 * sc;
-      grad[(int64_t)t * D + 1] += g1 * sc;
-      if (D == 3) grad[(int64_t)t * D + 2] += g2 * sc;
+    if (valid) {
+      pot[t] += acc;
+      if (GRAD) {
+        grad[(int64_t)t * D + 0] += g0 * sc;
+        grad[(int64_t)t * D + 1] += g1 * sc;
+        if (D == 3) grad[(int64_t)t * D + 2] += g2 * sc;
+      }
     }
   }
+}
+
+template <int D>
+static void launch_direct(const KParams& kp, Eval& E, pdmk_plan* P, hipStream_t s,
+                          bool want_grad) {
+  const int nc = std::max(D == 3 ? kp.nE : kp.nF2, D == 3 ? kp.nEd : kp.nF2d);
+  const double* c = D == 3 ? P->d_E : P->d_F2;
+  const double* cd = D == 3 ? P->d_Ed : P->d_F2d;
+#define PDMK_DIR(NE)                                                                           \
+  hipLaunchKernelGGL((k_direct<D, NE>), dim3(E.nleaf_t), dim3(64), 0, s, kp, E.nleaf_t, E.d_lev, \
+                     E.lf_level, E.lf_box, E.lf_list_beg, E.list, E.sx, E.sq, E.n_img, E.tx,     \
+                     E.n_trg, E.tperm, E.q, E.self_targets ? 1 : 0, c, cd, E.pot_sorted,         \
+                     E.grad_sorted, want_grad ? 1 : 0)
+  if (nc <= 12) PDMK_DIR(12);
+  else if (nc <= 16) PDMK_DIR(16);
+  else if (nc <= 20) PDMK_DIR(20);
+  else if (nc <= 24) PDMK_DIR(24);
+  else PDMK_DIR(32);
+#undef PDMK_DIR
+}
+
+template <int D>
+static void launch_anterp(const KParams& kp, const Level& L, const Level& C, int l, Eval& E,
+                          pdmk_plan* P, hipStream_t s) {
+  const int p = kp.p;
+#define PDMK_AN(PM) \
+  hipLaunchKernelGGL((k_anterp<D, PM>), dim3(L.nnl), dim3(256), 0, s, kp, L, C, l, E.sx, E.sq, \
+                     E.n_img, P->d_nodes, P->d_bw, L.proxy_q)
+  if (p <= 16) PDMK_AN(16);
+  else if (p <= 24) PDMK_AN(24);
+  else if (p <= 32) PDMK_AN(32);
+  else PDMK_AN(40);
+#undef PDMK_AN
+}
+
+template <int D>
+static void launch_eval_children(const KParams& kp, const Level& Lp, const Level& Lc, int l,
+                                 Eval& E, pdmk_plan* P, hipStream_t s, bool want_grad) {
+  const int p = kp.p;
+#define PDMK_EV(PM, NT, G)                                                                   \
+  hipLaunchKernelGGL((k_eval_children<D, PM, NT, G>), dim3(Lp.nnl), dim3(NT), 0, s, kp, Lp, \
+                     Lc, l, E.tx, E.n_trg, P->d_nodes, P->d_bw, E.pot_sorted, E.grad_sorted)
+  if (want_grad) {
+    if (p <= 16) PDMK_EV(16, 64, true);
+    else if (p <= 24) PDMK_EV(24, 64, true);
+    else if (p <= 32) PDMK_EV(32, 32, true);
+    else PDMK_EV(40, 32, true);
+  } else {
+    if (p <= 16) PDMK_EV(16, 128, false);
+    else if (p <= 24) PDMK_EV(24, 128, false);
+    else if (p <= 32) PDMK_EV(32, 64, false);
+    else PDMK_EV(40, 64, false);
+  }
+#undef PDMK_EV
 }
 
 template <int D>
@@ -460,12 +651,7 @@ static void near_impl(pdmk_plan* P, Eval& E, bool want_grad) {
   PDMK_HIP(hipEventCreate(&e3));
   PDMK_HIP(hipEventRecord(e0, s));
   // residual sums (write pot_sorted)
-  if (E.nleaf_t > 0)
-    hipLaunchKernelGGL(k_direct<D>, dim3(E.nleaf_t), dim3(64), 0, s, kp, E.nleaf_t, E.d_lev,
-                       E.lf_level, E.lf_box, E.lf_list_beg, E.list, E.sx, E.sq, E.n_img, E.tx,
-                       E.n_trg, E.tperm, E.q, E.self_targets ? 1 : 0,
-                       D == 3 ? P->d_E : P->d_F2, D == 3 ? P->d_Ed : P->d_F2d, E.pot_sorted,
-                       E.grad_sorted, want_grad ? 1 : 0);
+  if (E.nleaf_t > 0) launch_direct<D>(kp, E, P, s, want_grad);
   PDMK_HIP(hipEventRecord(e1, s));
   // proxies
   int maxnl = 0;
@@ -480,14 +666,12 @@ static void near_impl(pdmk_plan* P, Eval& E, bool want_grad) {
   if (maxnl > 0) {
     double* tA = E.alloc<double>((size_t)maxnl * pD);
     double* tB = E.alloc<double>((size_t)maxnl * pD);
-    const size_t smem = (size_t)(64 * D * p + 64) * sizeof(double);
     // upward pass
     for (int l = nlev - 2; l >= 0; --l) {
       Level& L = E.lev[l];
       if (L.nnl == 0) continue;
       Level& C = E.lev[l + 1];
-      hipLaunchKernelGGL(k_anterp<D>, dim3(L.nnl, nblk(pD, 1024)), dim3(256), smem, s, kp, L, C,
-                         l, E.sx, E.sq, E.n_img, P->d_nodes, P->d_bw, L.proxy_q);
+      launch_anterp<D>(kp, L, C, l, E, P, s);
       if (C.nnl > 0) {
         int64_t nt = (int64_t)C.nnl * pD;
         for (int ax = 0; ax < D; ++ax) {
@@ -568,12 +752,9 @@ static void near_impl(pdmk_plan* P, Eval& E, bool want_grad) {
   }
   PDMK_HIP(hipEventRecord(e2, s));
   // leaf targets evaluate their parent's proxy potential
-  if (E.nleaf_t > 0 && maxnl > 0) {
-    const size_t smem = (size_t)64 * 2 * D * p * sizeof(double);
-    hipLaunchKernelGGL(k_eval_leaf<D>, dim3(E.nleaf_t), dim3(64), smem, s, kp, E.nleaf_t,
-                       E.d_lev, E.lf_level, E.lf_box, E.tx, E.n_trg, P->d_nodes, P->d_bw,
-                       E.pot_sorted, E.grad_sorted, want_grad ? 1 : 0);
-  }
+  if (maxnl > 0)
+    for (int l = 0; l + 1 < nlev; ++l)
+      if (E.lev[l].nnl > 0) launch_eval_children<D>(kp, E.lev[l], E.lev[l + 1], l, E, P, s, want_grad);
   PDMK_HIP(hipEventRecord(e3, s));
   PDMK_HIP(hipEventSynchronize(e3));
   float t01, t12, t23;

@@ -219,12 +219,22 @@ static ChebSeries cheb_fit(int n, const std::function<double(double)>& f, double
     S.a[k] = (k == 0 ? 1.0 : 2.0) * s / n;
     amax = std::max(amax, std::fabs(S.a[k]));
   }
-  while (S.a.size() > 1 && std::fabs(S.a.back()) < tol * amax) S.a.pop_back();
+  // truncate at the first run of three coefficients below tol (the tail
+  // beyond it is rounding noise of the samples)
+  size_t keep = S.a.size();
+  for (size_t k = 1; k + 2 < S.a.size(); ++k)
+    if (std::fabs(S.a[k]) < tol * amax && std::fabs(S.a[k + 1]) < tol * amax &&
+        std::fabs(S.a[k + 2]) < tol * amax) {
+      keep = k;
+      break;
+    }
+  S.a.resize(keep);
   return S;
 }
 
 double SplitTables::w0_unit(int dim) const {
-  if (dim == 3) return E(0.0) / (4.0 * kPi);
+  // 3D: eq:W0zero, W_h(0) = psi(0) / (4 pi c0 h)
+  if (dim == 3) return pswf_for_eps(eps).psi0 / pswf_for_eps(eps).c0 / (4.0 * kPi);
   return -F2(0.0) / (2.0 * kPi);
 }
 
@@ -273,7 +283,7 @@ const SplitTables& tables_for_eps(double eps) {
     if (s <= 0) return P.psi0 / P.c0;
     double t = std::sqrt(s);
     return P.phi(t) / t;
-  }, std::max(1e-16, 1e-4 * eps));
+  }, std::max(4e-15, 1e-4 * eps));
   // F2(s) = log(1 + sqrt(1-s)) - int_0^{sqrt(1-s)} E(s + v^2) dv
   std::vector<double> gx, gw;
   gauss_legendre(64, gx, gw);
@@ -287,7 +297,7 @@ const SplitTables& tables_for_eps(double eps) {
       integ += 0.5 * a * gw[i] * e;
     }
     return std::log(1.0 + a) - integ;
-  }, std::max(1e-16, 1e-4 * eps));
+  }, std::max(4e-15, 1e-4 * eps));
   std::lock_guard<std::mutex> lk(mu);
   return cache.emplace(eps, std::move(T)).first->second;
 }
@@ -305,10 +315,16 @@ MethodParams default_params(int dim, double eps) {
   }
   m.porder = (int)std::ceil(1.2 * P.c + 1.5);
   m.npw = (int)std::ceil(3.0 * P.c / kPi);
+  // Spreading window: without upsampling (the paper's grid) a width of
+  // log10(1/eps) + 2 cells suffices down to eps ~ 1e-7; below that the
+  // window would have to grow past 16 cells, so the grid is doubled instead.
+  m.sigma = eps >= 1e-7 ? 1.0 : 2.0;
   m.nufft_w = std::min(16, (int)std::ceil(l - 1e-9) + 2);
-  m.beta = 2.0 * m.nufft_w;
+  m.beta = window_beta(m.nufft_w, m.sigma);
   return m;
 }
+
+double window_beta(int w, double sigma) { return (sigma > 1.5 ? 2.4 : 2.0) * w; }
 
 int next_fft_size(int n) {
   if (n < 2) n = 2;
@@ -344,7 +360,8 @@ static void inv3(int d, const double* A, double* Ai) {
   for (int k = 0; k < 9; ++k) Ai[k] = m[k] / det;
 }
 
-std::string make_geometry(int d, const double* Lin, double kappa, double c, Geometry& g) {
+std::string make_geometry(int d, const double* Lin, double kappa, double c, double sigma,
+                          Geometry& g) {
   g = Geometry();
   g.dim = d;
   // sort lattice vectors by decreasing length (stable), Section 3.2
@@ -430,7 +447,7 @@ std::string make_geometry(int d, const double* Lin, double kappa, double c, Geom
     int M = 2 * (int)std::ceil(c * an / (2.0 * kPi * g.rc));
     if (M < 2) M = 2;
     g.fgrid_paper[i] = M;
-    g.fgrid[i] = next_fft_size(M);
+    g.fgrid[i] = next_fft_size((int)std::ceil(std::max(1.0, sigma) * M - 1e-9));
   }
   return "";
 }

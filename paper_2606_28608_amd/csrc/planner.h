@@ -72,7 +72,10 @@ struct MethodParams {
   int npw;      // plane-wave half count J
   int nufft_w;  // window width (grid cells)
   double beta;  // ES window shape
+  double sigma; // Fourier grid upsampling factor
 };
+// ES window shape for a width and an upsampling factor.
+double window_beta(int w, double sigma);
 MethodParams default_params(int dim, double eps);
 
 // Geometry of one lattice (Sections 3.2-3.4, 3.7).
@@ -96,7 +99,7 @@ struct Geometry {
 };
 // Returns empty string on success, else a message.
 std::string make_geometry(int dim, const double* Lin, double kappa, double c,
-                          Geometry& g);
+                          double sigma, Geometry& g);
 
 // Smallest even integer >= n whose prime factors are 2, 3, 5.
 int next_fft_size(int n);

@@ -241,6 +241,18 @@ void stage_images(pdmk_plan* P, Eval& E, const double* q) {
   sort_points(P, E, E.n_img, xi, qi, E.skey, E.sx, E.sq, perm);
   double* dummyq = nullptr;
   sort_points(P, E, E.n_trg, E.xt, nullptr, E.tkey, E.tx, dummyq, E.tperm);
+  // original sources in tree order (spatially coherent spreading)
+  if (E.self_targets) {
+    E.ox = E.tx;
+    E.oq = E.alloc<double>(n);
+    if (n > 0)
+      hipLaunchKernelGGL(k_gather, dim3(nblk(n, 256)), dim3(256), 0, E.s, n, 0, E.tperm, E.xs, n,
+                         q, (double*)nullptr, E.oq);
+  } else {
+    uint64_t* okey = nullptr;
+    int* operm = nullptr;
+    sort_points(P, E, n, E.xs, q, okey, E.ox, E.oq, operm);
+  }
 }
 
 // -------------------------------------------------------------------- tree

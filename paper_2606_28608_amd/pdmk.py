@@ -39,7 +39,8 @@ class PdmkError(RuntimeError):
 class Opts(ctypes.Structure):
     _fields_ = [("dim", ctypes.c_int), ("eps", ctypes.c_double), ("precision", ctypes.c_int),
                 ("kappa", ctypes.c_double), ("n_s", ctypes.c_int), ("flags", ctypes.c_uint),
-                ("porder", ctypes.c_int), ("npw", ctypes.c_int), ("nufft_w", ctypes.c_int)]
+                ("porder", ctypes.c_int), ("npw", ctypes.c_int), ("nufft_w", ctypes.c_int),
+                ("sigma", ctypes.c_double)]
 
 
 class Geometry(ctypes.Structure):
@@ -82,6 +83,9 @@ def lib():
     """Load libpdmk.so (raises if it has not been built)."""
     global _lib
     if _lib is None:
+        # torch ships its own HIP runtime under the same soname; loading torch
+        # first makes libpdmk bind to that one, so the process has one runtime.
+        import torch  # noqa: F401
         if not os.path.exists(LIB_PATH):
             raise RuntimeError("libpdmk.so is not built (run paper_2606_28608_amd.build.build())")
         L = ctypes.CDLL(LIB_PATH)

@@ -206,6 +206,7 @@ def test_plan_reuse_and_stats(pdmk, torch_dev):
     Q = torch.tensor(q, device=dev)
     a = plan.eval(S, Q).cpu().numpy()
     b = plan.eval(S, Q).cpu().numpy()
-    assert np.array_equal(a, b)
+    # floating-point atomics reorder sums between calls: equal to rounding only
+    assert np.abs(a - b).max() <= 1e-13 * np.abs(a).max()
     st = plan.stats()
     assert st["n_src"] == 20000 and st["n_images"] >= 20000 and st["n_levels"] >= 1
