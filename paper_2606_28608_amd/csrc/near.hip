@@ -305,48 +305,120 @@ __global__ __launch_bounds__(256) void k_anterp(KParams kp, Level L, Level C, in
 }
 
 // ------------------------------------------- tensor-product child <-> parent
-// One axis of the transfer of proxy data between a non-leaf child (level l+1,
-// index kc among non-leaf boxes) and its parent (level l).
+// Transfer of proxy data between a non-leaf child (level l+1, index kc among
+// non-leaf boxes) and its parent (level l):
 //   up   : out[P] = sum_i T_sigma[P][i] in[i]    (charges, child -> parent)
 //   down : out[i] = sum_P T_sigma[P][i] in[P]    (potentials, parent -> child)
-// stage 0 reads the source tensor, stage D-1 writes the destination
-// (atomicAdd for up, since siblings share a parent).
-template <int D>
-__global__ void k_transfer(KParams kp, Level Lp, Level Lc, int up, int axis, int first,
-                           int last, const double* __restrict__ src, double* __restrict__ dst,
-                           const double* __restrict__ tmp_in, double* __restrict__ tmp_out,
-                           const double* __restrict__ Tm) {
+// applied along every axis.  One block per child: the tensor sits in LDS and
+// each thread transforms whole 1D lines in place (a line is read into
+// registers before it is overwritten).  Up adds into the parent with atomics
+// (siblings share it), down adds into the child.
+// In-place 1D transforms of all lines of the tensor along each axis.  tm
+// holds, per octant bit, the matrix column-wise and zero-padded to PMAX:
+// tm[sel][i][o] is the weight of input i for output o.  Each thread keeps the
+// PMAX outputs of its line in independent accumulators.
+template <int D, int PMAX, bool LDS>
+__device__ inline void transfer_lines(int p, int pD, int oct, double* ten, const double* tm) {
+  const int nlines = pD / p;
+  for (int ax = 0; ax < D; ++ax) {
+    const double* M = tm + ((oct >> ax) & 1) * p * PMAX;
+    const int stride = D == 3 ? (ax == 0 ? p * p : (ax == 1 ? p : 1)) : (ax == 0 ? p : 1);
+    for (int ln = threadIdx.x; ln < nlines; ln += blockDim.x) {
+      int base;
+      if (D == 3) {
+        const int u = ln / p, v = ln % p;
+        base = ax == 0 ? u * p + v : (ax == 1 ? u * p * p + v : u * p * p + v * p);
+      } else {
+        base = ax == 0 ? ln : ln * p;
+      }
+      double acc[PMAX];
+#pragma unroll
+      for (int o = 0; o < PMAX; ++o) acc[o] = 0.0;
+      for (int i = 0; i < p; ++i) {
+        const double vi = ten[base + i * stride];
+        const double* col = M + i * PMAX;
+#pragma unroll
+        for (int o = 0; o < PMAX; ++o) acc[o] = fma(col[o], vi, acc[o]);
+      }
+#pragma unroll
+      for (int o = 0; o < PMAX; ++o)
+        if (o < p) ten[base + o * stride] = acc[o];
+    }
+    __syncthreads();
+  }
+}
+
+// MODE 0: up, one block per parent (register accumulation, NOWN entries per
+// thread); MODE 1: up, one block per child with atomic adds into the parent
+// (large tensors); MODE 2: down, one block per child.
+template <int D, int PMAX, bool LDS, int NOWN, int MODE>
+__global__ __launch_bounds__(256) void k_transfer(KParams kp, Level Lp, Level Lc,
+                                                  const double* __restrict__ src,
+                                                  double* __restrict__ dst,
+                                                  const double* __restrict__ Tm,
+                                                  double* __restrict__ scratch) {
+  extern __shared__ double sm[];
   const int p = kp.p;
   const int pD = D == 3 ? p * p * p : p * p;
-  const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int kc = (int)(gid / pD);
-  if (kc >= Lc.nnl) return;
-  const int e = (int)(gid % pD);
-  const int c = Lc.nl_box[kc];
-  const int pb = Lc.parent[c];
-  const int kp_ = Lp.nlid[pb];
-  const int oct = c - Lp.child0[pb];
-  const int sel = (oct >> axis) & 1;
-  const double* M = Tm + sel * p * p;
-  int ix[3];
-  if (D == 3) { ix[0] = e / (p * p); ix[1] = (e / p) % p; ix[2] = e % p; }
-  else { ix[0] = e / p; ix[1] = e % p; ix[2] = 0; }
-  const int stride = D == 3 ? (axis == 0 ? p * p : (axis == 1 ? p : 1)) : (axis == 0 ? p : 1);
-  const int base = e - ix[axis] * stride;
-  const double* in;
-  if (first) in = src + (int64_t)(up ? kc : kp_) * pD;
-  else in = tmp_in + (int64_t)kc * pD;
-  double s = 0.0;
-  const int o = ix[axis];
-  for (int i = 0; i < p; ++i) {
-    double m = up ? M[o * p + i] : M[i * p + o];
-    s = fma(m, in[base + i * stride], s);
+  const int blk = blockIdx.x;
+  // the tensor lives in LDS when it fits, else in this block's global scratch
+  double* ten = LDS ? sm : scratch + (int64_t)blk * pD;
+  double* tm = LDS ? sm + pD : sm;  // 2 p PMAX
+  // Tm[sel][P][i] = l_P(child node i).  Up maps input i -> output P, down maps
+  // input P -> output i.
+  for (int e = threadIdx.x; e < 2 * p * PMAX; e += blockDim.x) {
+    const int sel = e / (p * PMAX), r = (e / PMAX) % p, o = e % PMAX;
+    double v = 0.0;
+    if (o < p) v = MODE == 2 ? Tm[sel * p * p + r * p + o] : Tm[sel * p * p + o * p + r];
+    tm[e] = v;
   }
-  if (last) {
-    if (up) atomicAdd(dst + (int64_t)kp_ * pD + e, s);
-    else dst[(int64_t)kc * pD + e] += s;
+  __syncthreads();
+  if (MODE == 0) {
+    const int P = Lp.nl_box[blk];
+    const int c0 = Lp.child0[P];
+    double acc[NOWN];
+#pragma unroll
+    for (int r = 0; r < NOWN; ++r) acc[r] = 0.0;
+    bool any = false;
+    for (int o = 0; o < (1 << D); ++o) {
+      const int kc = Lc.nlid[c0 + o];
+      if (kc < 0) continue;
+      any = true;
+      const double* in = src + (int64_t)kc * pD;
+      __syncthreads();
+      for (int e = threadIdx.x; e < pD; e += blockDim.x) ten[e] = in[e];
+      __syncthreads();
+      transfer_lines<D, PMAX, LDS>(p, pD, o, ten, tm);
+#pragma unroll
+      for (int r = 0; r < NOWN; ++r) {
+        const int e = threadIdx.x + r * 256;
+        if (e < pD) acc[r] += ten[e];
+      }
+    }
+    if (!any) return;
+    double* out = dst + (int64_t)blk * pD;
+#pragma unroll
+    for (int r = 0; r < NOWN; ++r) {
+      const int e = threadIdx.x + r * 256;
+      if (e < pD) out[e] += acc[r];
+    }
   } else {
-    tmp_out[(int64_t)kc * pD + e] = s;
+    const int kc = blk;
+    const int c = Lc.nl_box[kc];
+    const int pb = Lc.parent[c];
+    const int kpar = Lp.nlid[pb];
+    const int oct = c - Lp.child0[pb];
+    const double* in = src + (int64_t)(MODE == 1 ? kc : kpar) * pD;
+    for (int e = threadIdx.x; e < pD; e += blockDim.x) ten[e] = in[e];
+    __syncthreads();
+    transfer_lines<D, PMAX, LDS>(p, pD, oct, ten, tm);
+    if (MODE == 1) {
+      double* out = dst + (int64_t)kpar * pD;
+      for (int e = threadIdx.x; e < pD; e += blockDim.x) atomicAdd(out + e, ten[e]);
+    } else {
+      double* out = dst + (int64_t)kc * pD;
+      for (int e = threadIdx.x; e < pD; e += blockDim.x) out[e] += ten[e];
+    }
   }
 }
 
@@ -456,6 +528,158 @@ __global__ void k_translate(Level L, int J, const double2* __restrict__ S,
   if (m == 0 && npairs) atomicAdd(npairs, (unsigned long long)cnt);
 }
 
+// ------------------------------------------- fused per-box plane waves (3D)
+// Outgoing expansion of a non-leaf box, one slab j0 (Hermitian half, j0 >= 0)
+// at a time:  x = F_a Q (contract the first axis), z = F_b x, S[j0] = z F_c^T,
+// with F[j][i] = exp(-i pi j xi_i / 3).  The proxy tensor and the small
+// factors sit in LDS; S goes to global memory.
+__device__ inline double2 cfma(double2 a, double2 b, double2 c) {
+  return make_double2(fma(a.x, b.x, fma(-a.y, b.y, c.x)), fma(a.x, b.y, fma(a.y, b.x, c.y)));
+}
+__device__ inline double2 cfma_conj_a(double2 a, double2 b, double2 c) {   // conj(a) * b + c
+  return make_double2(fma(a.x, b.x, fma(a.y, b.y, c.x)), fma(a.x, b.y, fma(-a.y, b.x, c.y)));
+}
+
+__global__ __launch_bounds__(256) void k_pw_out(KParams kp, Level L, const double* __restrict__ Q,
+                                                const double2* __restrict__ F,
+                                                double2* __restrict__ S) {
+  extern __shared__ double sm[];
+  const int p = kp.p, J = kp.J, n = 2 * J + 1;
+  const int p2 = p * p, p3 = p2 * p;
+  double* q = sm;
+  double2* f = reinterpret_cast<double2*>(q + p3);   // n x p
+  double2* fT = f + n * p;                            // p x n
+  double2* x = fT + n * p;                            // p x p
+  double2* z = x + p2;                                // n x p
+  const int k = blockIdx.x;
+  const double* Qk = Q + (int64_t)k * p3;
+  for (int e = threadIdx.x; e < p3; e += 256) q[e] = Qk[e];
+  for (int e = threadIdx.x; e < n * p; e += 256) {
+    const double2 v = F[e];
+    f[e] = v;
+    fT[(e % p) * n + e / p] = v;
+  }
+  __syncthreads();
+  const int msz = (J + 1) * n * n;
+  for (int j0 = 0; j0 <= J; ++j0) {
+    const double2* fr = f + (J + j0) * p;
+    for (int e = threadIdx.x; e < p2; e += 256) {
+      double2 acc = make_double2(0.0, 0.0);
+      for (int a = 0; a < p; ++a) {
+        const double v = q[a * p2 + e];
+        acc.x = fma(fr[a].x, v, acc.x);
+        acc.y = fma(fr[a].y, v, acc.y);
+      }
+      x[e] = acc;
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < n * p; e += 256) {
+      const int j1 = e / p, c = e % p;
+      double2 acc = make_double2(0.0, 0.0);
+      for (int b = 0; b < p; ++b) acc = cfma(f[j1 * p + b], x[b * p + c], acc);
+      z[e] = acc;
+    }
+    __syncthreads();
+    double2* Sk = S + (int64_t)k * msz + (int64_t)j0 * n * n;
+    for (int e = threadIdx.x; e < n * n; e += 256) {
+      const int j1 = e / n, j2 = e % n;
+      double2 acc = make_double2(0.0, 0.0);
+      for (int c = 0; c < p; ++c) acc = cfma(z[j1 * p + c], fT[c * n + j2], acc);
+      Sk[e] = acc;
+    }
+    __syncthreads();
+  }
+}
+
+// Incoming expansion of a non-leaf box B holding targets, slab by slab:
+//   I[j0] = c_l(|j|^2) sum_C omega^{j.(c_B - c_C)/h} S_C[j0]   (|j| <= J only)
+// then plane waves -> proxy potential: z = I F_c^*, x = F_b^* z,
+// phi += w(j0) Re(F_a^* x) with w = 1 for j0 = 0 and 2 otherwise.
+__global__ __launch_bounds__(256) void k_pw_in(KParams kp, Level L, const double2* __restrict__ S,
+                                               const double2* __restrict__ F,
+                                               const double* __restrict__ dtab, double levfac,
+                                               double* __restrict__ Phi,
+                                               unsigned long long* __restrict__ npairs) {
+  extern __shared__ double sm[];
+  __shared__ int ckc[27], cph[27][3];
+  __shared__ int ncol;
+  const int p = kp.p, J = kp.J, n = 2 * J + 1;
+  const int p2 = p * p, p3 = p2 * p;
+  const int k = blockIdx.x;
+  const int b = L.nl_box[k];
+  if (L.tend[b] <= L.tbeg[b]) return;   // no targets below this box
+  double* phi = sm;
+  double2* f = reinterpret_cast<double2*>(phi + p3);  // n x p
+  double2* slab = f + n * p;                          // n x n
+  double2* z = slab + n * n;                          // n x p
+  double2* x = z + n * p;                             // p x p
+  if (threadIdx.x == 0) {
+    int m = 0;
+    for (int sl = 0; sl < 27; ++sl) {
+      const int c = L.coll[b * 27 + sl];
+      if (c < 0 || L.nlid[c] < 0) continue;
+      ckc[m] = L.nlid[c];
+      cph[m][0] = -(sl % 3 - 1);
+      cph[m][1] = -((sl / 3) % 3 - 1);
+      cph[m][2] = -(sl / 9 - 1);
+      ++m;
+    }
+    ncol = m;
+    if (npairs) atomicAdd(npairs, (unsigned long long)m);
+  }
+  for (int e = threadIdx.x; e < p3; e += 256) phi[e] = 0.0;
+  for (int e = threadIdx.x; e < n * p; e += 256) f[e] = F[e];
+  __syncthreads();
+  const int nc = ncol;
+  const int msz = (J + 1) * n * n;
+  const double2 w3[3] = {make_double2(1.0, 0.0), make_double2(-0.5, 0.8660254037844386),
+                         make_double2(-0.5, -0.8660254037844386)};
+  for (int j0 = 0; j0 <= J; ++j0) {
+    for (int e = threadIdx.x; e < n * n; e += 256) {
+      const int j1 = e / n - J, j2 = e % n - J;
+      const int nn = j0 * j0 + j1 * j1 + j2 * j2;
+      double2 acc = make_double2(0.0, 0.0);
+      if (nn <= J * J) {
+        for (int m = 0; m < nc; ++m) {
+          int ph = (j0 * cph[m][0] + j1 * cph[m][1] + j2 * cph[m][2]) % 3;
+          if (ph < 0) ph += 3;
+          const double2 v = S[(int64_t)ckc[m] * msz + (int64_t)j0 * n * n + e];
+          acc = cfma(w3[ph], v, acc);
+        }
+        const double cf = levfac * dtab[nn];
+        acc.x *= cf;
+        acc.y *= cf;
+      }
+      slab[e] = acc;
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < n * p; e += 256) {
+      const int j1 = e / p, c = e % p;
+      double2 acc = make_double2(0.0, 0.0);
+      for (int j2 = 0; j2 < n; ++j2) acc = cfma_conj_a(f[j2 * p + c], slab[j1 * n + j2], acc);
+      z[e] = acc;
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < p2; e += 256) {
+      const int bb = e / p, c = e % p;
+      double2 acc = make_double2(0.0, 0.0);
+      for (int j1 = 0; j1 < n; ++j1) acc = cfma_conj_a(f[j1 * p + bb], z[j1 * p + c], acc);
+      x[e] = acc;
+    }
+    __syncthreads();
+    const double w = j0 == 0 ? 1.0 : 2.0;
+    const double2* fr = f + (J + j0) * p;
+    for (int e = threadIdx.x; e < p3; e += 256) {
+      const int a = e / p2, bc = e % p2;
+      const double2 fa = fr[a], xv = x[bc];
+      phi[e] = fma(w, fa.x * xv.x + fa.y * xv.y, phi[e]);   // Re(conj(fa) xv)
+    }
+    __syncthreads();
+  }
+  double* out = Phi + (int64_t)k * p3;
+  for (int e = threadIdx.x; e < p3; e += 256) out[e] += phi[e];
+}
+
 // -------------------------------------------------- proxy potential -> targets
 // Targets of the childless children of a non-leaf box P evaluate P's proxy
 // potential (one block per P, one thread per target).  The potential tensor is
@@ -527,14 +751,16 @@ __global__ __launch_bounds__(NT) void k_eval_children(
         double a1 = 0.0, a1g1 = 0.0, a1g2 = 0.0;
         for (int i1 = 0; i1 < p; ++i1) {
           const_dptr ph = Phi + (i0 * p + i1) * p;
+          // PMAX consecutive values (entries past p meet zero rows; the
+          // buffer carries PMAX zeros of padding at its end)
+          double v[PMAX];
+#pragma unroll
+          for (int m = 0; m < PMAX; ++m) v[m] = ph[m];
           double a2 = 0.0, a2d = 0.0;
 #pragma unroll
           for (int m = 0; m < PMAX; ++m) {
-            if (m < p) {
-              const double v = ph[m];
-              a2 = fma(v, rl[m], a2);
-              if (GRAD) a2d = fma(v, dl[m], a2d);
-            }
+            a2 = fma(v[m], rl[m], a2);
+            if (GRAD) a2d = fma(v[m], dl[m], a2d);
           }
           const double r1 = lrow[(PMAX + i1) * NT + tid];
           a1 = fma(r1, a2, a1);
@@ -554,14 +780,14 @@ __global__ __launch_bounds__(NT) void k_eval_children(
     } else {
       for (int i0 = 0; i0 < p; ++i0) {
         const_dptr ph = Phi + i0 * p;
+        double v[PMAX];
+#pragma unroll
+        for (int m = 0; m < PMAX; ++m) v[m] = ph[m];
         double a1 = 0.0, a1d = 0.0;
 #pragma unroll
         for (int m = 0; m < PMAX; ++m) {
-          if (m < p) {
-            const double v = ph[m];
-            a1 = fma(v, rl[m], a1);
-            if (GRAD) a1d = fma(v, dl[m], a1d);
-          }
+          a1 = fma(v[m], rl[m], a1);
+          if (GRAD) a1d = fma(v[m], dl[m], a1d);
         }
         const double r0 = lrow[i0 * NT + tid];
         acc = fma(r0, a1, acc);
@@ -599,6 +825,52 @@ static void launch_direct(const KParams& kp, Eval& E, pdmk_plan* P, hipStream_t 
   else if (nc <= 24) PDMK_DIR(24);
   else PDMK_DIR(32);
 #undef PDMK_DIR
+}
+
+template <int D>
+static void launch_transfer(const KParams& kp, const Level& Lp, const Level& Lc, int up,
+                            const double* src, double* dst, pdmk_plan* P, Eval& E,
+                            hipStream_t s) {
+  const int p = kp.p;
+  const int pD = D == 3 ? p * p * p : p * p;
+  const size_t full = (size_t)(pD + 2 * p * 40) * sizeof(double);
+  const bool lds = full <= 100 * 1024;
+  const size_t smem = lds ? full : (size_t)2 * p * 40 * sizeof(double);
+  const int nown = (pD + 255) / 256;
+  const int mode = up ? (nown <= 48 ? 0 : 1) : 2;
+  const int nblocks = mode == 0 ? Lp.nnl : Lc.nnl;
+  double* scratch = lds ? nullptr : E.alloc<double>((size_t)nblocks * pD);
+#define PDMK_TR(PM, L, NO, MO)                                                                  \
+  do {                                                                                          \
+    PDMK_HIP(hipFuncSetAttribute((const void*)&k_transfer<D, PM, L, NO, MO>,                    \
+                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem));       \
+    hipLaunchKernelGGL((k_transfer<D, PM, L, NO, MO>), dim3(nblocks), dim3(256), smem, s, kp,   \
+                       Lp, Lc, src, dst, P->d_Tm, scratch);                                     \
+  } while (0)
+  if (mode == 0) {
+    if (nown <= 8) {
+      if (p <= 16) PDMK_TR(16, true, 8, 0);
+      else PDMK_TR(24, true, 8, 0);
+    } else if (nown <= 24) {
+      if (p <= 16) PDMK_TR(16, true, 24, 0);
+      else PDMK_TR(24, true, 24, 0);
+    } else {
+      if (lds) PDMK_TR(24, true, 48, 0);
+      else PDMK_TR(32, false, 48, 0);
+    }
+  } else {
+    const bool m1 = mode == 1;
+    if (lds) {
+      if (p <= 16) { if (m1) PDMK_TR(16, true, 1, 1); else PDMK_TR(16, true, 1, 2); }
+      else if (p <= 24) { if (m1) PDMK_TR(24, true, 1, 1); else PDMK_TR(24, true, 1, 2); }
+      else { if (m1) PDMK_TR(32, true, 1, 1); else PDMK_TR(32, true, 1, 2); }
+    } else {
+      if (p <= 24) { if (m1) PDMK_TR(24, false, 1, 1); else PDMK_TR(24, false, 1, 2); }
+      else if (p <= 32) { if (m1) PDMK_TR(32, false, 1, 1); else PDMK_TR(32, false, 1, 2); }
+      else { if (m1) PDMK_TR(40, false, 1, 1); else PDMK_TR(40, false, 1, 2); }
+    }
+  }
+#undef PDMK_TR
 }
 
 template <int D>
@@ -659,40 +931,43 @@ static void near_impl(pdmk_plan* P, Eval& E, bool want_grad) {
   for (int l = 0; l < nlev; ++l) {
     Level& L = E.lev[l];
     if (L.nnl == 0) continue;
-    L.proxy_q = E.alloc<double>((size_t)L.nnl * pD);
-    L.proxy_phi = E.alloc<double>((size_t)L.nnl * pD);
-    PDMK_HIP(hipMemsetAsync(L.proxy_phi, 0, sizeof(double) * (size_t)L.nnl * pD, s));
+    // 64 doubles of zero padding: the leaf evaluation reads whole register
+    // rows past the last tensor entry
+    L.proxy_q = E.alloc<double>((size_t)L.nnl * pD + 64);
+    L.proxy_phi = E.alloc<double>((size_t)L.nnl * pD + 64);
+    PDMK_HIP(hipMemsetAsync(L.proxy_phi, 0, sizeof(double) * ((size_t)L.nnl * pD + 64), s));
   }
   if (maxnl > 0) {
-    double* tA = E.alloc<double>((size_t)maxnl * pD);
-    double* tB = E.alloc<double>((size_t)maxnl * pD);
     // upward pass
     for (int l = nlev - 2; l >= 0; --l) {
       Level& L = E.lev[l];
       if (L.nnl == 0) continue;
       Level& C = E.lev[l + 1];
       launch_anterp<D>(kp, L, C, l, E, P, s);
-      if (C.nnl > 0) {
-        int64_t nt = (int64_t)C.nnl * pD;
-        for (int ax = 0; ax < D; ++ax) {
-          const double* tin = (ax % 2 == 1) ? tA : tB;
-          double* tout = (ax % 2 == 0) ? tA : tB;
-          hipLaunchKernelGGL(k_transfer<D>, dim3(nblk(nt, 256)), dim3(256), 0, s, kp, L, C, 1,
-                             ax, ax == 0 ? 1 : 0, ax == D - 1 ? 1 : 0, C.proxy_q, L.proxy_q,
-                             tin, tout, P->d_Tm);
-        }
-      }
+      if (C.nnl > 0) launch_transfer<D>(kp, L, C, 1, C.proxy_q, L.proxy_q, P, E, s);
     }
     // plane waves, level by level
     const int64_t s1 = (int64_t)(J + 1) * p * (D == 3 ? p : 1);
     const int64_t s2 = D == 3 ? (int64_t)(J + 1) * n1 * p : 0;
     const int64_t s3 = D == 3 ? (int64_t)(J + 1) * n1 * n1 : (int64_t)(J + 1) * n1;
-    double2* bA = E.alloc<double2>((size_t)maxnl * s1);
-    double2* bB = D == 3 ? E.alloc<double2>((size_t)maxnl * s2) : nullptr;
+    const bool fused_any = D == 3 &&
+        (size_t)p * p * p * 8 + (size_t)(n1 * p + n1 * n1 + n1 * p + p * p) * 16 <= 150 * 1024 &&
+        (size_t)p * p * p * 8 + (size_t)(2 * n1 * p + p * p + n1 * p) * 16 <= 150 * 1024;
     double2* bS = E.alloc<double2>((size_t)maxnl * s3);
-    double2* bI = E.alloc<double2>((size_t)maxnl * s3);
+    double2* bA = fused_any ? nullptr : E.alloc<double2>((size_t)maxnl * s1);
+    double2* bB = (D == 3 && !fused_any) ? E.alloc<double2>((size_t)maxnl * s2) : nullptr;
+    double2* bI = fused_any ? nullptr : E.alloc<double2>((size_t)maxnl * s3);
     unsigned long long* npairs = E.alloc<unsigned long long>(1);
     PDMK_HIP(hipMemsetAsync(npairs, 0, sizeof(unsigned long long), s));
+    const size_t lds_out = (size_t)p * p * p * 8 + (size_t)(2 * n1 * p + p * p + n1 * p) * 16;
+    const size_t lds_in = (size_t)p * p * p * 8 + (size_t)(n1 * p + n1 * n1 + n1 * p + p * p) * 16;
+    const bool fused = D == 3 && lds_out <= 150 * 1024 && lds_in <= 150 * 1024;
+    if (fused) {
+      PDMK_HIP(hipFuncSetAttribute((const void*)&k_pw_out,
+                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_out));
+      PDMK_HIP(hipFuncSetAttribute((const void*)&k_pw_in,
+                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_in));
+    }
     for (int l = 0; l < nlev; ++l) {
       Level& L = E.lev[l];
       if (L.nnl == 0) continue;
@@ -700,6 +975,13 @@ static void near_impl(pdmk_plan* P, Eval& E, bool want_grad) {
       const double h = kp.rc / (double)(1 << l);
       const double levfac = D == 3 ? 1.0 / (3.0 * h) : 1.0;
       const int zz = D == 3 ? p : 1;
+      if (fused) {
+        hipLaunchKernelGGL(k_pw_out, dim3(nn), dim3(256), lds_out, s, kp, L, L.proxy_q, P->d_F,
+                           bS);
+        hipLaunchKernelGGL(k_pw_in, dim3(nn), dim3(256), lds_in, s, kp, L, bS, P->d_F,
+                           P->d_dtab, levfac, L.proxy_phi, npairs);
+        continue;
+      }
       // outgoing: proxy charges -> plane waves (Hermitian half on axis 0)
       hipLaunchKernelGGL((k_axis<false, 0>), dim3(nblk(nn * s1, 256)), dim3(256), 0, s, nn, p,
                          p, zz, 0, J + 1, (const void*)L.proxy_q, (void*)bA, P->d_F, J, p, 0, 0);
@@ -734,14 +1016,7 @@ static void near_impl(pdmk_plan* P, Eval& E, bool want_grad) {
       Level& C = E.lev[l];
       Level& L = E.lev[l - 1];
       if (C.nnl == 0) continue;
-      int64_t nt = (int64_t)C.nnl * pD;
-      for (int ax = 0; ax < D; ++ax) {
-        const double* tin = (ax % 2 == 1) ? tA : tB;
-        double* tout = (ax % 2 == 0) ? tA : tB;
-        hipLaunchKernelGGL(k_transfer<D>, dim3(nblk(nt, 256)), dim3(256), 0, s, kp, L, C, 0, ax,
-                           ax == 0 ? 1 : 0, ax == D - 1 ? 1 : 0, L.proxy_phi, C.proxy_phi, tin,
-                           tout, P->d_Tm);
-      }
+      launch_transfer<D>(kp, L, C, 0, L.proxy_phi, C.proxy_phi, P, E, s);
     }
     PDMK_HIP(hipMemcpyAsync(E.d_lev, E.lev.data(), sizeof(Level) * E.lev.size(),
                             hipMemcpyHostToDevice, s));
