@@ -88,6 +88,9 @@ void plan_upload_tables(pdmk_plan* P) {
       F[(j + J) * p + i] = make_double2(std::cos(a), std::sin(a));
     }
   P->d_F = upload(F);
+  std::vector<float2> Ff(F.size());
+  for (size_t i = 0; i < F.size(); ++i) Ff[i] = make_float2((float)F[i].x, (float)F[i].y);
+  P->d_Ff = upload(Ff);
   P->d_dtab = upload(pw_table(*P->P, P->P->c, J, d));
   std::vector<double> sv;
   for (size_t s = 0; s < P->g.shifts.size() / d; ++s)
@@ -108,7 +111,7 @@ void plan_upload_tables(pdmk_plan* P) {
 
 static void free_plan_tables(pdmk_plan* P) {
   void* ptrs[] = {P->d_E, P->d_Ed, P->d_F2, P->d_F2d, P->d_nodes, P->d_bw, P->d_Tm,
-                  P->d_F, P->d_dtab, P->d_farscale, P->d_shiftvec};
+                  P->d_F, P->d_Ff, P->d_dtab, P->d_farscale, P->d_shiftvec};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
 }
@@ -249,8 +252,6 @@ static int validate_opts(const pdmk_opts* o) {
   if (!(o->eps >= 1e-12 && o->eps <= 1e-2)) return fail(PDMK_ERR_EPS_RANGE, "eps out of range");
   if (o->precision != PDMK_PREC_FP64 && o->precision != PDMK_PREC_MIXED)
     return fail(PDMK_ERR_INVALID_ARG, "unknown precision");
-  if (o->precision == PDMK_PREC_MIXED)
-    return fail(PDMK_ERR_UNSUPPORTED, "mixed precision not available in this build");
   if (o->porder > 40 || o->npw > 64 || o->nufft_w > 16 || o->sigma > 4.0)
     return fail(PDMK_ERR_INVALID_ARG, "porder <= 40, npw <= 64, nufft_w <= 16, sigma <= 4");
   return PDMK_OK;

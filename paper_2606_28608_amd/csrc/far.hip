@@ -116,43 +116,9 @@ __device__ inline double es_win(double z, double beta) {
   double t = 1.0 - z * z;
   return t >= 0.0 ? exp(beta * (sqrt(t) - 1.0)) : 0.0;
 }
-
-// Spread charges onto the real grid (FP64 atomics).
-template <int D>
-__global__ void k_spread(int64_t n, const double* __restrict__ u, const double* __restrict__ q,
-                         int M0, int M1, int M2, int w, double beta, double* __restrict__ grid) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const int Ms[3] = {M0, M1, M2};
-  const double hw = 0.5 * w;
-  double wt[D][16];
-  int ix[D][16];
-  for (int a = 0; a < D; ++a) {
-    const double g = u[a * n + i] * Ms[a];
-    const int i0 = (int)ceil(g - hw);
-    for (int k = 0; k < w; ++k) {
-      int id = i0 + k;
-      wt[a][k] = es_win((id - g) / hw, beta);
-      id %= Ms[a];
-      if (id < 0) id += Ms[a];
-      ix[a][k] = id;
-    }
-  }
-  const double qi = q[i];
-  if (D == 3) {
-    for (int k2 = 0; k2 < w; ++k2)
-      for (int k1 = 0; k1 < w; ++k1) {
-        const double w12 = qi * wt[2][k2] * wt[1][k1];
-        const int64_t row = (int64_t)M0 * (ix[1][k1] + (int64_t)M1 * ix[2][k2]);
-        for (int k0 = 0; k0 < w; ++k0) atomicAdd(grid + row + ix[0][k0], w12 * wt[0][k0]);
-      }
-  } else {
-    for (int k1 = 0; k1 < w; ++k1) {
-      const double w1 = qi * wt[1][k1];
-      const int64_t row = (int64_t)M0 * ix[1][k1];
-      for (int k0 = 0; k0 < w; ++k0) atomicAdd(grid + row + ix[0][k0], w1 * wt[0][k0]);
-    }
-  }
+__device__ inline float es_win(float z, float beta) {
+  float t = 1.0f - z * z;
+  return t >= 0.0f ? __expf(beta * (sqrtf(t) - 1.0f)) : 0.0f;
 }
 
 // Tiled spreading: a block takes 256 consecutive sources in tree order; their
@@ -174,7 +140,7 @@ __device__ inline void grid_coords(const KParams& kp, const double* __restrict__
   }
 }
 
-template <int D>
+template <int D, class Real>
 __global__ __launch_bounds__(256) void k_spread_tiled(KParams kp, int64_t n,
                                                       const double* __restrict__ x,
                                                       const double* __restrict__ q, int M0,
@@ -217,7 +183,8 @@ __global__ __launch_bounds__(256) void k_spread_tiled(KParams kp, int64_t n,
     const double qi = q[i];
     double wt[D][16];
     for (int a = 0; a < D; ++a)
-      for (int k = 0; k < w; ++k) wt[a][k] = es_win((i0[a] + k - g[a]) / hw, beta);
+      for (int k = 0; k < w; ++k)
+        wt[a][k] = (double)es_win((Real)((i0[a] + k - g[a]) / hw), (Real)beta);
     if (tiled) {
       const int o0 = i0[0] - lo[0], o1 = i0[1] - lo[1], o2 = D == 3 ? i0[2] - lo[2] : 0;
       if (D == 3) {
@@ -277,7 +244,7 @@ __global__ __launch_bounds__(256) void k_spread_tiled(KParams kp, int64_t n,
 
 // Tiled interpolation at targets in tree order: the block's subgrid is read
 // into LDS once; results are added to the near-field arrays (tree order).
-template <int D>
+template <int D, class Real>
 __global__ __launch_bounds__(256) void k_interp_tiled(KParams kp, int64_t n,
                                                       const double* __restrict__ x, int M0,
                                                       int M1, int M2, int w, double beta,
@@ -332,11 +299,11 @@ __global__ __launch_bounds__(256) void k_interp_tiled(KParams kp, int64_t n,
   int ix[D][16];
   for (int a = 0; a < D; ++a)
     for (int k = 0; k < w; ++k) {
-      const double z = (i0[a] + k - g[a]) / hw;
-      const double v = es_win(z, beta);
-      wt[a][k] = v;
-      const double t = 1.0 - z * z;
-      dw[a][k] = (t > 0.0) ? v * beta * (-z / sqrt(t)) * (-Ms[a] / hw) : 0.0;
+      const Real z = (Real)((i0[a] + k - g[a]) / hw);
+      const Real v = es_win(z, (Real)beta);
+      wt[a][k] = (double)v;
+      const Real t = (Real)1 - z * z;
+      dw[a][k] = (t > (Real)0) ? (double)(v * (Real)beta * (-z / sqrt(t))) * (-Ms[a] / hw) : 0.0;
       if (tiled) {
         ix[a][k] = i0[a] + k - lo[a];
       } else {
@@ -401,76 +368,6 @@ __global__ void k_scale(int64_t n, double2* __restrict__ c, const double* __rest
     double v = s[i];
     c[i] = make_double2(c[i].x * v, c[i].y * v);
   }
-}
-
-// Interpolate the real part of the grid at the targets (and its gradient,
-// mapped to the oriented Cartesian frame by L^{-T}).
-template <int D>
-__global__ void k_interp(KParams kp, int64_t n, const double* __restrict__ u, int M0, int M1,
-                         int M2, int w, double beta, const double2* __restrict__ grid,
-                         double* __restrict__ pot, double* __restrict__ grad, int want_grad) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const int Ms[3] = {M0, M1, M2};
-  const double hw = 0.5 * w;
-  double wt[D][16], dw[D][16];
-  int ix[D][16];
-  for (int a = 0; a < D; ++a) {
-    const double g = u[a * n + i] * Ms[a];
-    const int i0 = (int)ceil(g - hw);
-    for (int k = 0; k < w; ++k) {
-      int id = i0 + k;
-      const double z = (id - g) / hw;
-      const double v = es_win(z, beta);
-      wt[a][k] = v;
-      const double t = 1.0 - z * z;
-      dw[a][k] = (t > 0.0) ? v * beta * (-z / sqrt(t)) * (-Ms[a] / hw) : 0.0;
-      id %= Ms[a];
-      if (id < 0) id += Ms[a];
-      ix[a][k] = id;
-    }
-  }
-  double acc = 0.0, gu[3] = {0, 0, 0};
-  if (D == 3) {
-    for (int k2 = 0; k2 < w; ++k2)
-      for (int k1 = 0; k1 < w; ++k1) {
-        const int64_t row = (int64_t)M0 * (ix[1][k1] + (int64_t)M1 * ix[2][k2]);
-        double s0 = 0.0, sd0 = 0.0;
-        for (int k0 = 0; k0 < w; ++k0) {
-          const double v = grid[row + ix[0][k0]].x;
-          s0 = fma(v, wt[0][k0], s0);
-          if (want_grad) sd0 = fma(v, dw[0][k0], sd0);
-        }
-        acc = fma(s0, wt[1][k1] * wt[2][k2], acc);
-        if (want_grad) {
-          gu[0] = fma(sd0, wt[1][k1] * wt[2][k2], gu[0]);
-          gu[1] = fma(s0, dw[1][k1] * wt[2][k2], gu[1]);
-          gu[2] = fma(s0, wt[1][k1] * dw[2][k2], gu[2]);
-        }
-      }
-  } else {
-    for (int k1 = 0; k1 < w; ++k1) {
-      const int64_t row = (int64_t)M0 * ix[1][k1];
-      double s0 = 0.0, sd0 = 0.0;
-      for (int k0 = 0; k0 < w; ++k0) {
-        const double v = grid[row + ix[0][k0]].x;
-        s0 = fma(v, wt[0][k0], s0);
-        if (want_grad) sd0 = fma(v, dw[0][k0], sd0);
-      }
-      acc = fma(s0, wt[1][k1], acc);
-      if (want_grad) {
-        gu[0] = fma(sd0, wt[1][k1], gu[0]);
-        gu[1] = fma(s0, dw[1][k1], gu[1]);
-      }
-    }
-  }
-  pot[i] = acc;
-  if (want_grad)
-    for (int b = 0; b < D; ++b) {
-      double s = 0.0;
-      for (int a = 0; a < D; ++a) s += kp.Li[a + D * b] * gu[a];
-      grad[i * D + b] = s;
-    }
 }
 
 // Diagonal scaling table (FP64), once per plan.
@@ -554,28 +451,28 @@ void stage_far(pdmk_plan* P, Eval& E, const double* q, bool want_grad) {
   double* grid = E.alloc<double>(n);
   double2* cg = E.alloc<double2>(n);
   PDMK_HIP(hipMemsetAsync(grid, 0, n * sizeof(double), E.s));
+  const bool f32 = P->kp.precision == PDMK_PREC_MIXED;
+#define PDMK_SP(DD, R)                                                                        \
+  hipLaunchKernelGGL((k_spread_tiled<DD, R>), dim3(nblk(E.n_src, 256)), dim3(256), 0, E.s, \
+                     P->kp, E.n_src, E.ox, E.oq, M[0], M[1], M[2], w, beta, grid)
+#define PDMK_IN(DD, R)                                                                        \
+  hipLaunchKernelGGL((k_interp_tiled<DD, R>), dim3(nblk(E.n_trg, 256)), dim3(256), 0, E.s, \
+                     P->kp, E.n_trg, E.tx, M[0], M[1], M[2], w, beta, cg, E.pot_sorted,     \
+                     E.grad_sorted, want_grad ? 1 : 0)
   if (E.n_src > 0) {
-    if (d == 3)
-      hipLaunchKernelGGL(k_spread_tiled<3>, dim3(nblk(E.n_src, 256)), dim3(256), 0, E.s, P->kp,
-                         E.n_src, E.ox, E.oq, M[0], M[1], M[2], w, beta, grid);
-    else
-      hipLaunchKernelGGL(k_spread_tiled<2>, dim3(nblk(E.n_src, 256)), dim3(256), 0, E.s, P->kp,
-                         E.n_src, E.ox, E.oq, M[0], M[1], M[2], w, beta, grid);
+    if (d == 3) { if (f32) PDMK_SP(3, float); else PDMK_SP(3, double); }
+    else { if (f32) PDMK_SP(2, float); else PDMK_SP(2, double); }
   }
   hipLaunchKernelGGL(k_to_complex, dim3(nblk(n, 256)), dim3(256), 0, E.s, n, grid, cg);
   fft3(cg, M, d, -1, E.s);
   hipLaunchKernelGGL(k_scale, dim3(nblk(n, 256)), dim3(256), 0, E.s, n, cg, P->d_farscale);
   fft3(cg, M, d, +1, E.s);
   if (E.n_trg > 0) {
-    if (d == 3)
-      hipLaunchKernelGGL(k_interp_tiled<3>, dim3(nblk(E.n_trg, 256)), dim3(256), 0, E.s, P->kp,
-                         E.n_trg, E.tx, M[0], M[1], M[2], w, beta, cg, E.pot_sorted,
-                         E.grad_sorted, want_grad ? 1 : 0);
-    else
-      hipLaunchKernelGGL(k_interp_tiled<2>, dim3(nblk(E.n_trg, 256)), dim3(256), 0, E.s, P->kp,
-                         E.n_trg, E.tx, M[0], M[1], M[2], w, beta, cg, E.pot_sorted,
-                         E.grad_sorted, want_grad ? 1 : 0);
+    if (d == 3) { if (f32) PDMK_IN(3, float); else PDMK_IN(3, double); }
+    else { if (f32) PDMK_IN(2, float); else PDMK_IN(2, double); }
   }
+#undef PDMK_SP
+#undef PDMK_IN
 }
 
 }  // namespace pdmk

@@ -67,8 +67,8 @@ struct Level {
   int* nlid = nullptr;       // index among non-leaf boxes of this level, -1 = leaf
   int nnl = 0;               // non-leaf count
   int* nl_box = nullptr;     // non-leaf index -> box index
-  double* proxy_q = nullptr; // nnl * p^d outgoing proxy charges
-  double* proxy_phi = nullptr; // nnl * p^d incoming proxy potentials
+  void* proxy_q = nullptr;   // nnl * p^d outgoing proxy charges (FP64 or FP32)
+  void* proxy_phi = nullptr; // nnl * p^d incoming proxy potentials
 };
 
 // Per-evaluation state.
@@ -135,6 +135,7 @@ struct pdmk_plan {
   double* d_bw = nullptr;      // p
   double* d_Tm = nullptr;      // [2][p][p]: parent basis at child nodes, sigma = -1, +1
   double2* d_F = nullptr;      // [2J+1][p]: exp(-i pi j xi_p / 3)
+  float2* d_Ff = nullptr;      // FP32 copy
   double* d_dtab = nullptr;    // |j|^2 table
   double* d_farscale = nullptr;// M0*M1*M2
   double* d_shiftvec = nullptr;  // nshift * dim lattice translations L n

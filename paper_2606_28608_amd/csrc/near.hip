@@ -30,28 +30,27 @@ __device__ inline double clenshaw(const double* __restrict__ a, int n, double s)
 
 // Lagrange basis at the p Chebyshev nodes (barycentric form), and optionally
 // its derivative.  x exactly at a node is moved by 1e-13.
+template <class T>
 __device__ inline void lagrange_rows(int p, const double* __restrict__ nodes,
                                      const double* __restrict__ bw, double x,
-                                     double* row, double* drow) {
+                                     T* row, T* drow) {
   for (int j = 0; j < p; ++j)
     if (x == nodes[j]) { x += 1e-13; break; }
   double s = 0.0, s1 = 0.0;
   for (int j = 0; j < p; ++j) {
     double inv = 1.0 / (x - nodes[j]);
     double t = bw[j] * inv;
-    row[j] = t;
     s += t;
     s1 += t * inv;
   }
   double is = 1.0 / s;
-  if (drow) {
-    // l_j' = l_j (-1/(x - x_j) + S1/S),  S1 = sum w_k/(x-x_k)^2
-    for (int j = 0; j < p; ++j) {
-      double lj = row[j] * is;
-      drow[j] = lj * (-1.0 / (x - nodes[j]) + s1 * is);
-    }
+  for (int j = 0; j < p; ++j) {
+    // l_j = (w_j/(x - x_j)) / S;  l_j' = l_j (-1/(x - x_j) + S1/S),  S1 = sum w_k/(x-x_k)^2
+    const double inv = 1.0 / (x - nodes[j]);
+    const double lj = bw[j] * inv * is;
+    row[j] = (T)lj;
+    if (drow) drow[j] = (T)(lj * (-inv + s1 * is));
   }
-  for (int j = 0; j < p; ++j) row[j] *= is;
 }
 
 // Same as lagrange_rows with compile-time capacity PMAX (entries >= p are 0),
@@ -101,8 +100,71 @@ __device__ inline double rsqrt_f64(double x) {
   y = y * fma(-hx * y, y, 1.5);
   return y;
 }
+__device__ inline double rsqrt_r(double x) { return rsqrt_f64(x); }
+__device__ inline float rsqrt_r(float x) { return __builtin_amdgcn_rsqf(x); }
+__device__ inline double log_r(double x) { return log(x); }
+__device__ inline float log_r(float x) { return __logf(x); }
 
-template <int D, int NE>
+// Real = double: FP64 throughout.  Real = float: FP32 pair arithmetic on
+// offsets from the target leaf's centre (each formed in FP64, then rounded),
+// FP32 sums over one tile of 64 sources, FP64 across tiles.
+template <class Real> struct Vec4Of;
+template <> struct Vec4Of<double> { using T = double4; };
+template <> struct Vec4Of<float> { using T = float4; };
+
+template <int D, int NE, class Real>
+__device__ inline void residual_pair(const Real* x, const typename Vec4Of<Real>::T& sv, Real h2,
+                                     Real ih, const Real* ec, const Real* edc, bool want_grad,
+                                     Real& acc, Real* g) {
+  Real dx[3];
+  dx[0] = x[0] - sv.x;
+  dx[1] = x[1] - sv.y;
+  dx[2] = D == 3 ? x[2] - sv.z : (Real)0;
+  Real r2 = dx[0] * dx[0];
+  r2 = fma(dx[1], dx[1], r2);
+  if (D == 3) r2 = fma(dx[2], dx[2], r2);
+  if (r2 < h2 && r2 > (Real)0) {
+    const Real s = r2 * ih * ih;
+    const Real qs = sv.w;
+    // Clenshaw recurrence for sum_k c_k T_k(2s - 1)
+    const Real t2 = (Real)4 * s - (Real)2;
+    Real b1 = 0, b2 = 0, d1 = 0, d2 = 0;
+#pragma unroll
+    for (int m = NE - 1; m >= 1; --m) {
+      const Real b0 = fma(t2, b1, ec[m] - b2);
+      b2 = b1;
+      b1 = b0;
+      if (want_grad) {
+        const Real e0 = fma(t2, d1, edc[m] - d2);
+        d2 = d1;
+        d1 = e0;
+      }
+    }
+    const Real F = fma((Real)0.5 * t2, b1, ec[0] - b2);
+    if (D == 3) {
+      const Real ir = rsqrt_r(r2);
+      acc = fma(qs, ir - F * ih, acc);
+      if (want_grad) {
+        const Real Fd = fma((Real)0.5 * t2, d1, edc[0] - d2);
+        const Real f = qs * (-ir * ir * ir - (Real)2 * Fd * ih * ih * ih);
+        for (int a = 0; a < D; ++a) g[a] = fma(f, dx[a], g[a]);
+      }
+    } else {
+      acc = fma(qs, (Real)-0.5 * log_r(s) + F, acc);
+      if (want_grad) {
+        const Real Fd = fma((Real)0.5 * t2, d1, edc[0] - d2);
+        const Real f = qs * (-(Real)1 / r2 + (Real)2 * Fd * ih * ih);
+        for (int a = 0; a < D; ++a) g[a] = fma(f, dx[a], g[a]);
+      }
+    }
+  }
+}
+
+// Real = double: FP64 throughout.  Real = float: FP32 pair arithmetic on
+// offsets from the target leaf's centre (each formed in FP64, then rounded),
+// FP32 sums over one tile of 64 sources, FP64 across tiles.  Each LDS slot
+// holds (x, y, z, q) of one source and the support of its residual level.
+template <int D, int NE, class Real>
 __global__ __launch_bounds__(64) void k_direct(
     KParams kp, int nleaf, const Level* __restrict__ lev, const int* __restrict__ lf_level,
     const int* __restrict__ lf_box, const int* __restrict__ lbeg, const int4* __restrict__ list,
@@ -111,32 +173,36 @@ __global__ __launch_bounds__(64) void k_direct(
     const double* __restrict__ qorig, int self_targets, const double* __restrict__ Ec,
     const double* __restrict__ Edc, double* __restrict__ pot, double* __restrict__ grad,
     int want_grad) {
-  __shared__ double shx[D][64];
-  __shared__ double shq[64], shh2[64], shih[64];
+  using V4 = typename Vec4Of<Real>::T;
+  __shared__ V4 shv[64];
+  __shared__ Real shh2[64], shih[64];
   const int i = blockIdx.x;
   if (i >= nleaf) return;
   // series coefficients (zero-padded to NE) held in registers
-  double ec[NE], edc[NE];
+  Real ec[NE], edc[NE];
 #pragma unroll
   for (int k = 0; k < NE; ++k) {
-    ec[k] = Ec[k];
-    edc[k] = Edc[k];
+    ec[k] = (Real)Ec[k];
+    edc[k] = (Real)Edc[k];
   }
   const int lane = threadIdx.x;
   const int lvl = lf_level[i], b = lf_box[i];
   const Level& T = lev[lvl];
   const int tb = T.tbeg[b], te = T.tend[b];
-  const int nt = te - tb;
   const int lb = lbeg[i], le = lbeg[i + 1];
   const double hT = kp.rc / (double)(1 << lvl);
-  const int S = nt > 32 ? 1 : (nt > 16 ? 2 : (nt > 8 ? 4 : 8));
-  const int tpb = 64 / S;
-  const int slice = lane % S, tslot = lane / S;
-  for (int t0 = tb; t0 < te; t0 += tpb) {
+  double cT[D];
+  for (int a = 0; a < D; ++a) cT[a] = kp.origin[a] + (T.coord[b * D + a] + 0.5) * hT;
+  for (int t0 = tb; t0 < te;) {
+    // lanes per target for this pass, from the targets still to do
+    const int rem = te - t0;
+    const int S = rem > 32 ? 1 : (rem > 16 ? 2 : (rem > 8 ? 4 : 8));
+    const int tpb = 64 / S;
+    const int slice = lane % S, tslot = lane / S;
     const int t = t0 + tslot;
     const bool valid = t < te;
-    double x[D];
-    for (int a = 0; a < D; ++a) x[a] = valid ? tx[a * ntrg + t] : 0.0;
+    Real x[3] = {0, 0, 0};
+    for (int a = 0; a < D; ++a) x[a] = valid ? (Real)(tx[a * ntrg + t] - cT[a]) : (Real)0;
     double acc = 0.0, g[D];
     for (int a = 0; a < D; ++a) g[a] = 0.0;
     int e = lb, off = 0;
@@ -153,16 +219,22 @@ __global__ __launch_bounds__(64) void k_direct(
       if (ee < le) {
         const int4 en = list[ee];
         const int sidx = en.x + oo;
-        for (int a = 0; a < D; ++a) shx[a][lane] = sx[a * nimg + sidx];
-        shq[lane] = sq[sidx];
+        V4 v;
+        v.x = (Real)(sx[sidx] - cT[0]);
+        v.y = (Real)(sx[nimg + sidx] - cT[1]);
+        v.z = D == 3 ? (Real)(sx[2 * nimg + sidx] - cT[2]) : (Real)0;
+        v.w = (Real)sq[sidx];
+        shv[lane] = v;
         const double hh = kp.rc / (double)(1 << en.z);
-        shh2[lane] = hh * hh;
-        shih[lane] = 1.0 / hh;
+        shh2[lane] = (Real)(hh * hh);
+        shih[lane] = (Real)(1.0 / hh);
       } else {
-        for (int a = 0; a < D; ++a) shx[a][lane] = 1e300;
-        shq[lane] = 0.0;
-        shh2[lane] = 0.0;
-        shih[lane] = 1.0;
+        V4 v;
+        v.x = v.y = v.z = (Real)1e30;
+        v.w = 0;
+        shv[lane] = v;
+        shh2[lane] = 0;
+        shih[lane] = 1;
       }
       __syncthreads();
       // advance the (uniform) cursor by 64 slots
@@ -174,49 +246,18 @@ __global__ __launch_bounds__(64) void k_direct(
         ++e;
       }
       off = oo;
-      for (int k = slice; k < 64; k += S) {
-        double dx[D], r2 = 0.0;
-        for (int a = 0; a < D; ++a) {
-          dx[a] = x[a] - shx[a][k];
-          r2 = fma(dx[a], dx[a], r2);
-        }
-        if (r2 < shh2[k] && r2 > 0.0) {
-          const double ih = shih[k];
-          const double s = r2 * ih * ih;
-          const double qs = shq[k];
-          // Clenshaw recurrence for sum_k c_k T_k(2s - 1)
-          const double t2 = 4.0 * s - 2.0;
-          double b1 = 0.0, b2 = 0.0, d1 = 0.0, d2 = 0.0;
-#pragma unroll
-          for (int m = NE - 1; m >= 1; --m) {
-            const double b0 = fma(t2, b1, ec[m] - b2);
-            b2 = b1;
-            b1 = b0;
-            if (want_grad) {
-              const double e0 = fma(t2, d1, edc[m] - d2);
-              d2 = d1;
-              d1 = e0;
-            }
-          }
-          const double F = fma(0.5 * t2, b1, ec[0] - b2);
-          if (D == 3) {
-            const double ir = rsqrt_f64(r2);
-            acc = fma(qs, ir - F * ih, acc);
-            if (want_grad) {
-              const double Fd = fma(0.5 * t2, d1, edc[0] - d2);
-              const double f = qs * (-ir * ir * ir - 2.0 * Fd * ih * ih * ih);
-              for (int a = 0; a < D; ++a) g[a] = fma(f, dx[a], g[a]);
-            }
-          } else {
-            acc = fma(qs, -0.5 * log(s) + F, acc);
-            if (want_grad) {
-              const double Fd = fma(0.5 * t2, d1, edc[0] - d2);
-              const double f = qs * (-1.0 / r2 + 2.0 * Fd * ih * ih);
-              for (int a = 0; a < D; ++a) g[a] = fma(f, dx[a], g[a]);
-            }
-          }
-        }
+      Real ta = 0, tbb = 0, tg[3] = {0, 0, 0}, tg2[3] = {0, 0, 0};
+      // two independent pair chains per iteration
+      for (int k = slice; k < 64; k += 2 * S) {
+        residual_pair<D, NE, Real>(x, shv[k], shh2[k], shih[k], ec, edc, want_grad, ta, tg);
+        const int k2 = k + S;
+        if (k2 < 64)
+          residual_pair<D, NE, Real>(x, shv[k2], shh2[k2], shih[k2], ec, edc, want_grad, tbb,
+                                     tg2);
       }
+      acc += (double)ta + (double)tbb;
+      if (want_grad)
+        for (int a = 0; a < D; ++a) g[a] += (double)tg[a] + (double)tg2[a];
     }
     for (int m = 1; m < S; m <<= 1) {
       acc += __shfl_xor(acc, m);
@@ -234,6 +275,7 @@ __global__ __launch_bounds__(64) void k_direct(
       if (want_grad)
         for (int a = 0; a < D; ++a) grad[(int64_t)t * D + a] = g[a] * cst;
     }
+    t0 += tpb;
   }
 }
 
@@ -243,16 +285,16 @@ __global__ __launch_bounds__(64) void k_direct(
 // A block owns one box; each thread owns one (i0, i1) pair (2D: one i0) and
 // keeps the PMAX accumulators along the last axis in registers.  Lagrange rows
 // of 32 sources at a time are staged in LDS.
-template <int D, int PMAX>
+template <int D, int PMAX, class Real>
 __global__ __launch_bounds__(256) void k_anterp(KParams kp, Level L, Level C, int lvl,
                                                 const double* __restrict__ sx,
                                                 const double* __restrict__ sq, int64_t nimg,
                                                 const double* __restrict__ nodes,
                                                 const double* __restrict__ bw,
-                                                double* __restrict__ Q) {
+                                                Real* __restrict__ Q) {
   constexpr int TS = 32;
-  __shared__ double rows[TS * D * PMAX];
-  __shared__ double qs[TS];
+  __shared__ Real rows[TS * D * PMAX];
+  __shared__ Real qs[TS];
   const int p = kp.p;
   const int k = blockIdx.x;
   const int b = L.nl_box[k];
@@ -268,9 +310,9 @@ __global__ __launch_bounds__(256) void k_anterp(KParams kp, Level L, Level C, in
     const bool act = pr < npair;
     const int i0 = D == 3 ? (act ? pr / p : 0) : (act ? pr : 0);
     const int i1 = D == 3 ? (act ? pr % p : 0) : 0;
-    double acc[PMAX];
+    Real acc[PMAX];
 #pragma unroll
-    for (int j = 0; j < PMAX; ++j) acc[j] = 0.0;
+    for (int j = 0; j < PMAX; ++j) acc[j] = 0;
     for (int o = 0; o < (1 << D); ++o) {
       const int c = c0 + o;
       if (C.child0[c] >= 0) continue;   // non-leaf child: handled by the transfer
@@ -281,22 +323,22 @@ __global__ __launch_bounds__(256) void k_anterp(KParams kp, Level L, Level C, in
         if (threadIdx.x < ns * D) {
           const int si = threadIdx.x / D, a = threadIdx.x % D;
           const double xi = (sx[a * nimg + s0 + si] - cen[a]) * sc;
-          lagrange_rows(p, nodes, bw, xi, rows + (si * D + a) * PMAX, nullptr);
+          lagrange_rows<Real>(p, nodes, bw, xi, rows + (si * D + a) * PMAX, (Real*)nullptr);
         }
-        if (threadIdx.x < ns) qs[threadIdx.x] = sq[s0 + threadIdx.x];
+        if (threadIdx.x < ns) qs[threadIdx.x] = (Real)sq[s0 + threadIdx.x];
         __syncthreads();
         for (int si = 0; si < ns; ++si) {
-          const double* rw = rows + si * D * PMAX;
-          double wv = qs[si] * rw[i0];
+          const Real* rw = rows + si * D * PMAX;
+          Real wv = qs[si] * rw[i0];
           if (D == 3) wv *= rw[PMAX + i1];
-          const double* rl = rw + (D - 1) * PMAX;
+          const Real* rl = rw + (D - 1) * PMAX;
 #pragma unroll
           for (int j = 0; j < PMAX; ++j) acc[j] = fma(wv, rl[j], acc[j]);
         }
       }
     }
     if (act) {
-      double* out = Q + (int64_t)k * pD + (int64_t)pr * p;
+      Real* out = Q + (int64_t)k * pD + (int64_t)pr * p;
 #pragma unroll
       for (int j = 0; j < PMAX; ++j)
         if (j < p) out[j] = acc[j];
@@ -317,11 +359,11 @@ __global__ __launch_bounds__(256) void k_anterp(KParams kp, Level L, Level C, in
 // holds, per octant bit, the matrix column-wise and zero-padded to PMAX:
 // tm[sel][i][o] is the weight of input i for output o.  Each thread keeps the
 // PMAX outputs of its line in independent accumulators.
-template <int D, int PMAX, bool LDS>
-__device__ inline void transfer_lines(int p, int pD, int oct, double* ten, const double* tm) {
+template <int D, int PMAX, bool LDS, class Real>
+__device__ inline void transfer_lines(int p, int pD, int oct, Real* ten, const Real* tm) {
   const int nlines = pD / p;
   for (int ax = 0; ax < D; ++ax) {
-    const double* M = tm + ((oct >> ax) & 1) * p * PMAX;
+    const Real* M = tm + ((oct >> ax) & 1) * p * PMAX;
     const int stride = D == 3 ? (ax == 0 ? p * p : (ax == 1 ? p : 1)) : (ax == 0 ? p : 1);
     for (int ln = threadIdx.x; ln < nlines; ln += blockDim.x) {
       int base;
@@ -331,12 +373,12 @@ __device__ inline void transfer_lines(int p, int pD, int oct, double* ten, const
       } else {
         base = ax == 0 ? ln : ln * p;
       }
-      double acc[PMAX];
+      Real acc[PMAX];
 #pragma unroll
-      for (int o = 0; o < PMAX; ++o) acc[o] = 0.0;
+      for (int o = 0; o < PMAX; ++o) acc[o] = 0;
       for (int i = 0; i < p; ++i) {
-        const double vi = ten[base + i * stride];
-        const double* col = M + i * PMAX;
+        const Real vi = ten[base + i * stride];
+        const Real* col = M + i * PMAX;
 #pragma unroll
         for (int o = 0; o < PMAX; ++o) acc[o] = fma(col[o], vi, acc[o]);
       }
@@ -351,44 +393,45 @@ __device__ inline void transfer_lines(int p, int pD, int oct, double* ten, const
 // MODE 0: up, one block per parent (register accumulation, NOWN entries per
 // thread); MODE 1: up, one block per child with atomic adds into the parent
 // (large tensors); MODE 2: down, one block per child.
-template <int D, int PMAX, bool LDS, int NOWN, int MODE>
+template <int D, int PMAX, bool LDS, int NOWN, int MODE, class Real>
 __global__ __launch_bounds__(256) void k_transfer(KParams kp, Level Lp, Level Lc,
-                                                  const double* __restrict__ src,
-                                                  double* __restrict__ dst,
+                                                  const Real* __restrict__ src,
+                                                  Real* __restrict__ dst,
                                                   const double* __restrict__ Tm,
-                                                  double* __restrict__ scratch) {
-  extern __shared__ double sm[];
+                                                  Real* __restrict__ scratch) {
+  extern __shared__ __align__(16) unsigned char smraw[];
+  Real* sm = reinterpret_cast<Real*>(smraw);
   const int p = kp.p;
   const int pD = D == 3 ? p * p * p : p * p;
   const int blk = blockIdx.x;
   // the tensor lives in LDS when it fits, else in this block's global scratch
-  double* ten = LDS ? sm : scratch + (int64_t)blk * pD;
-  double* tm = LDS ? sm + pD : sm;  // 2 p PMAX
+  Real* ten = LDS ? sm : scratch + (int64_t)blk * pD;
+  Real* tm = LDS ? sm + pD : sm;  // 2 p PMAX
   // Tm[sel][P][i] = l_P(child node i).  Up maps input i -> output P, down maps
   // input P -> output i.
   for (int e = threadIdx.x; e < 2 * p * PMAX; e += blockDim.x) {
     const int sel = e / (p * PMAX), r = (e / PMAX) % p, o = e % PMAX;
     double v = 0.0;
     if (o < p) v = MODE == 2 ? Tm[sel * p * p + r * p + o] : Tm[sel * p * p + o * p + r];
-    tm[e] = v;
+    tm[e] = (Real)v;
   }
   __syncthreads();
   if (MODE == 0) {
     const int P = Lp.nl_box[blk];
     const int c0 = Lp.child0[P];
-    double acc[NOWN];
+    Real acc[NOWN];
 #pragma unroll
-    for (int r = 0; r < NOWN; ++r) acc[r] = 0.0;
+    for (int r = 0; r < NOWN; ++r) acc[r] = 0;
     bool any = false;
     for (int o = 0; o < (1 << D); ++o) {
       const int kc = Lc.nlid[c0 + o];
       if (kc < 0) continue;
       any = true;
-      const double* in = src + (int64_t)kc * pD;
+      const Real* in = src + (int64_t)kc * pD;
       __syncthreads();
       for (int e = threadIdx.x; e < pD; e += blockDim.x) ten[e] = in[e];
       __syncthreads();
-      transfer_lines<D, PMAX, LDS>(p, pD, o, ten, tm);
+      transfer_lines<D, PMAX, LDS, Real>(p, pD, o, ten, tm);
 #pragma unroll
       for (int r = 0; r < NOWN; ++r) {
         const int e = threadIdx.x + r * 256;
@@ -396,7 +439,7 @@ __global__ __launch_bounds__(256) void k_transfer(KParams kp, Level Lp, Level Lc
       }
     }
     if (!any) return;
-    double* out = dst + (int64_t)blk * pD;
+    Real* out = dst + (int64_t)blk * pD;
 #pragma unroll
     for (int r = 0; r < NOWN; ++r) {
       const int e = threadIdx.x + r * 256;
@@ -408,15 +451,15 @@ __global__ __launch_bounds__(256) void k_transfer(KParams kp, Level Lp, Level Lc
     const int pb = Lc.parent[c];
     const int kpar = Lp.nlid[pb];
     const int oct = c - Lp.child0[pb];
-    const double* in = src + (int64_t)(MODE == 1 ? kc : kpar) * pD;
+    const Real* in = src + (int64_t)(MODE == 1 ? kc : kpar) * pD;
     for (int e = threadIdx.x; e < pD; e += blockDim.x) ten[e] = in[e];
     __syncthreads();
-    transfer_lines<D, PMAX, LDS>(p, pD, oct, ten, tm);
+    transfer_lines<D, PMAX, LDS, Real>(p, pD, oct, ten, tm);
     if (MODE == 1) {
-      double* out = dst + (int64_t)kpar * pD;
+      Real* out = dst + (int64_t)kpar * pD;
       for (int e = threadIdx.x; e < pD; e += blockDim.x) atomicAdd(out + e, ten[e]);
     } else {
-      double* out = dst + (int64_t)kc * pD;
+      Real* out = dst + (int64_t)kc * pD;
       for (int e = threadIdx.x; e < pD; e += blockDim.x) out[e] += ten[e];
     }
   }
@@ -533,40 +576,56 @@ __global__ void k_translate(Level L, int J, const double2* __restrict__ S,
 // at a time:  x = F_a Q (contract the first axis), z = F_b x, S[j0] = z F_c^T,
 // with F[j][i] = exp(-i pi j xi_i / 3).  The proxy tensor and the small
 // factors sit in LDS; S goes to global memory.
-__device__ inline double2 cfma(double2 a, double2 b, double2 c) {
-  return make_double2(fma(a.x, b.x, fma(-a.y, b.y, c.x)), fma(a.x, b.y, fma(a.y, b.x, c.y)));
+template <class R> struct CplxOf;
+template <> struct CplxOf<double> { using T = double2; };
+template <> struct CplxOf<float> { using T = float2; };
+template <class R> using Cx = typename CplxOf<R>::T;
+
+template <class C>
+__device__ inline C cfma(C a, C b, C c) {   // a * b + c
+  C r;
+  r.x = fma(a.x, b.x, fma(-a.y, b.y, c.x));
+  r.y = fma(a.x, b.y, fma(a.y, b.x, c.y));
+  return r;
 }
-__device__ inline double2 cfma_conj_a(double2 a, double2 b, double2 c) {   // conj(a) * b + c
-  return make_double2(fma(a.x, b.x, fma(a.y, b.y, c.x)), fma(a.x, b.y, fma(-a.y, b.x, c.y)));
+template <class C>
+__device__ inline C cfma_conj_a(C a, C b, C c) {   // conj(a) * b + c
+  C r;
+  r.x = fma(a.x, b.x, fma(a.y, b.y, c.x));
+  r.y = fma(a.x, b.y, fma(-a.y, b.x, c.y));
+  return r;
 }
 
-__global__ __launch_bounds__(256) void k_pw_out(KParams kp, Level L, const double* __restrict__ Q,
-                                                const double2* __restrict__ F,
-                                                double2* __restrict__ S) {
-  extern __shared__ double sm[];
+template <class Real>
+__global__ __launch_bounds__(256) void k_pw_out(KParams kp, Level L, const Real* __restrict__ Q,
+                                                const Cx<Real>* __restrict__ F,
+                                                Cx<Real>* __restrict__ S) {
+  using C = Cx<Real>;
+  extern __shared__ __align__(16) unsigned char smraw[];
   const int p = kp.p, J = kp.J, n = 2 * J + 1;
   const int p2 = p * p, p3 = p2 * p;
-  double* q = sm;
-  double2* f = reinterpret_cast<double2*>(q + p3);   // n x p
-  double2* fT = f + n * p;                            // p x n
-  double2* x = fT + n * p;                            // p x p
-  double2* z = x + p2;                                // n x p
+  C* f = reinterpret_cast<C*>(smraw);                 // n x p
+  C* fT = f + n * p;                                  // p x n
+  C* x = fT + n * p;                                  // p x p
+  C* z = x + p2;                                      // n x p
+  Real* q = reinterpret_cast<Real*>(z + n * p);       // p^3
   const int k = blockIdx.x;
-  const double* Qk = Q + (int64_t)k * p3;
+  const Real* Qk = Q + (int64_t)k * p3;
   for (int e = threadIdx.x; e < p3; e += 256) q[e] = Qk[e];
   for (int e = threadIdx.x; e < n * p; e += 256) {
-    const double2 v = F[e];
+    const C v = F[e];
     f[e] = v;
     fT[(e % p) * n + e / p] = v;
   }
   __syncthreads();
   const int msz = (J + 1) * n * n;
+  const C zero = {0, 0};
   for (int j0 = 0; j0 <= J; ++j0) {
-    const double2* fr = f + (J + j0) * p;
+    const C* fr = f + (J + j0) * p;
     for (int e = threadIdx.x; e < p2; e += 256) {
-      double2 acc = make_double2(0.0, 0.0);
+      C acc = zero;
       for (int a = 0; a < p; ++a) {
-        const double v = q[a * p2 + e];
+        const Real v = q[a * p2 + e];
         acc.x = fma(fr[a].x, v, acc.x);
         acc.y = fma(fr[a].y, v, acc.y);
       }
@@ -575,15 +634,15 @@ __global__ __launch_bounds__(256) void k_pw_out(KParams kp, Level L, const doubl
     __syncthreads();
     for (int e = threadIdx.x; e < n * p; e += 256) {
       const int j1 = e / p, c = e % p;
-      double2 acc = make_double2(0.0, 0.0);
+      C acc = zero;
       for (int b = 0; b < p; ++b) acc = cfma(f[j1 * p + b], x[b * p + c], acc);
       z[e] = acc;
     }
     __syncthreads();
-    double2* Sk = S + (int64_t)k * msz + (int64_t)j0 * n * n;
+    C* Sk = S + (int64_t)k * msz + (int64_t)j0 * n * n;
     for (int e = threadIdx.x; e < n * n; e += 256) {
       const int j1 = e / n, j2 = e % n;
-      double2 acc = make_double2(0.0, 0.0);
+      C acc = zero;
       for (int c = 0; c < p; ++c) acc = cfma(z[j1 * p + c], fT[c * n + j2], acc);
       Sk[e] = acc;
     }
@@ -595,12 +654,14 @@ __global__ __launch_bounds__(256) void k_pw_out(KParams kp, Level L, const doubl
 //   I[j0] = c_l(|j|^2) sum_C omega^{j.(c_B - c_C)/h} S_C[j0]   (|j| <= J only)
 // then plane waves -> proxy potential: z = I F_c^*, x = F_b^* z,
 // phi += w(j0) Re(F_a^* x) with w = 1 for j0 = 0 and 2 otherwise.
-__global__ __launch_bounds__(256) void k_pw_in(KParams kp, Level L, const double2* __restrict__ S,
-                                               const double2* __restrict__ F,
+template <class Real>
+__global__ __launch_bounds__(256) void k_pw_in(KParams kp, Level L, const Cx<Real>* __restrict__ S,
+                                               const Cx<Real>* __restrict__ F,
                                                const double* __restrict__ dtab, double levfac,
-                                               double* __restrict__ Phi,
+                                               Real* __restrict__ Phi,
                                                unsigned long long* __restrict__ npairs) {
-  extern __shared__ double sm[];
+  using C = Cx<Real>;
+  extern __shared__ __align__(16) unsigned char smraw[];
   __shared__ int ckc[27], cph[27][3];
   __shared__ int ncol;
   const int p = kp.p, J = kp.J, n = 2 * J + 1;
@@ -608,11 +669,11 @@ __global__ __launch_bounds__(256) void k_pw_in(KParams kp, Level L, const double
   const int k = blockIdx.x;
   const int b = L.nl_box[k];
   if (L.tend[b] <= L.tbeg[b]) return;   // no targets below this box
-  double* phi = sm;
-  double2* f = reinterpret_cast<double2*>(phi + p3);  // n x p
-  double2* slab = f + n * p;                          // n x n
-  double2* z = slab + n * n;                          // n x p
-  double2* x = z + n * p;                             // p x p
+  C* f = reinterpret_cast<C*>(smraw);                 // n x p
+  C* slab = f + n * p;                                // n x n
+  C* z = slab + n * n;                                // n x p
+  C* x = z + n * p;                                   // p x p
+  Real* phi = reinterpret_cast<Real*>(x + p2);        // p^3
   if (threadIdx.x == 0) {
     int m = 0;
     for (int sl = 0; sl < 27; ++sl) {
@@ -627,26 +688,27 @@ __global__ __launch_bounds__(256) void k_pw_in(KParams kp, Level L, const double
     ncol = m;
     if (npairs) atomicAdd(npairs, (unsigned long long)m);
   }
-  for (int e = threadIdx.x; e < p3; e += 256) phi[e] = 0.0;
+  for (int e = threadIdx.x; e < p3; e += 256) phi[e] = 0;
   for (int e = threadIdx.x; e < n * p; e += 256) f[e] = F[e];
   __syncthreads();
   const int nc = ncol;
   const int msz = (J + 1) * n * n;
-  const double2 w3[3] = {make_double2(1.0, 0.0), make_double2(-0.5, 0.8660254037844386),
-                         make_double2(-0.5, -0.8660254037844386)};
+  const C zero = {0, 0};
+  const C w3[3] = {{(Real)1, (Real)0}, {(Real)-0.5, (Real)0.8660254037844386},
+                   {(Real)-0.5, (Real)-0.8660254037844386}};
   for (int j0 = 0; j0 <= J; ++j0) {
     for (int e = threadIdx.x; e < n * n; e += 256) {
       const int j1 = e / n - J, j2 = e % n - J;
       const int nn = j0 * j0 + j1 * j1 + j2 * j2;
-      double2 acc = make_double2(0.0, 0.0);
+      C acc = zero;
       if (nn <= J * J) {
         for (int m = 0; m < nc; ++m) {
           int ph = (j0 * cph[m][0] + j1 * cph[m][1] + j2 * cph[m][2]) % 3;
           if (ph < 0) ph += 3;
-          const double2 v = S[(int64_t)ckc[m] * msz + (int64_t)j0 * n * n + e];
+          const C v = S[(int64_t)ckc[m] * msz + (int64_t)j0 * n * n + e];
           acc = cfma(w3[ph], v, acc);
         }
-        const double cf = levfac * dtab[nn];
+        const Real cf = (Real)(levfac * dtab[nn]);
         acc.x *= cf;
         acc.y *= cf;
       }
@@ -655,28 +717,28 @@ __global__ __launch_bounds__(256) void k_pw_in(KParams kp, Level L, const double
     __syncthreads();
     for (int e = threadIdx.x; e < n * p; e += 256) {
       const int j1 = e / p, c = e % p;
-      double2 acc = make_double2(0.0, 0.0);
+      C acc = zero;
       for (int j2 = 0; j2 < n; ++j2) acc = cfma_conj_a(f[j2 * p + c], slab[j1 * n + j2], acc);
       z[e] = acc;
     }
     __syncthreads();
     for (int e = threadIdx.x; e < p2; e += 256) {
       const int bb = e / p, c = e % p;
-      double2 acc = make_double2(0.0, 0.0);
+      C acc = zero;
       for (int j1 = 0; j1 < n; ++j1) acc = cfma_conj_a(f[j1 * p + bb], z[j1 * p + c], acc);
       x[e] = acc;
     }
     __syncthreads();
-    const double w = j0 == 0 ? 1.0 : 2.0;
-    const double2* fr = f + (J + j0) * p;
+    const Real w = j0 == 0 ? (Real)1 : (Real)2;
+    const C* fr = f + (J + j0) * p;
     for (int e = threadIdx.x; e < p3; e += 256) {
       const int a = e / p2, bc = e % p2;
-      const double2 fa = fr[a], xv = x[bc];
+      const C fa = fr[a], xv = x[bc];
       phi[e] = fma(w, fa.x * xv.x + fa.y * xv.y, phi[e]);   // Re(conj(fa) xv)
     }
     __syncthreads();
   }
-  double* out = Phi + (int64_t)k * p3;
+  Real* out = Phi + (int64_t)k * p3;
   for (int e = threadIdx.x; e < p3; e += 256) out[e] += phi[e];
 }
 
@@ -685,15 +747,16 @@ __global__ __launch_bounds__(256) void k_pw_in(KParams kp, Level L, const double
 // potential (one block per P, one thread per target).  The potential tensor is
 // read through the scalar cache (uniform addresses); the Lagrange rows of the
 // last axis live in registers, the others in LDS (transposed, conflict free).
-typedef const double __attribute__((address_space(4)))* const_dptr;
+template <class Real>
+using const_rptr = const Real __attribute__((address_space(4)))*;
 
-template <int D, int PMAX, int NT, bool GRAD>
+template <int D, int PMAX, int NT, bool GRAD, class Real>
 __global__ __launch_bounds__(NT) void k_eval_children(
     KParams kp, Level Lp, Level Lc, int lvl, const double* __restrict__ tx, int64_t ntrg,
     const double* __restrict__ nodes, const double* __restrict__ bw,
     double* __restrict__ pot, double* __restrict__ grad) {
   constexpr int NR = GRAD ? 2 : 1;
-  __shared__ double lrow[NR * (D - 1) * PMAX * NT];   // rows (and derivative rows) of axes < D-1
+  __shared__ Real lrow[NR * (D - 1) * PMAX * NT];   // rows (and derivative rows) of axes < D-1
   __shared__ int cb[8], cpre[9];
   const int p = kp.p;
   const int k = blockIdx.x;
@@ -717,7 +780,7 @@ __global__ __launch_bounds__(NT) void k_eval_children(
   const int total = cpre[1 << D];
   if (total == 0) return;
   const int pD = D == 3 ? p * p * p : p * p;
-  const_dptr Phi = (const_dptr)(Lp.proxy_phi + (int64_t)k * pD);
+  const_rptr<Real> Phi = (const_rptr<Real>)((const Real*)Lp.proxy_phi + (int64_t)k * pD);
   const double hP = kp.rc / (double)(1 << lvl);
   double cen[D];
   for (int a = 0; a < D; ++a) cen[a] = kp.origin[a] + (Lp.coord[P * D + a] + 0.5) * hP;
@@ -732,10 +795,16 @@ __global__ __launch_bounds__(NT) void k_eval_children(
       while (o + 1 < (1 << D) && cpre[o + 1] <= j) ++o;
       t = cb[o] + (j - cpre[o]);
     }
-    double rl[PMAX], dl[PMAX];
+    double rld[PMAX], dld[PMAX];
+    Real rl[PMAX], dl[PMAX];
     for (int a = 0; a < D; ++a) {
       const double xi = valid ? (tx[a * ntrg + t] - cen[a]) * sc : 0.0;
-      lagrange_rows_reg<PMAX, GRAD>(p, nodes, bw, xi, rl, dl);
+      lagrange_rows_reg<PMAX, GRAD>(p, nodes, bw, xi, rld, dld);
+#pragma unroll
+      for (int m = 0; m < PMAX; ++m) {
+        rl[m] = (Real)rld[m];
+        dl[m] = GRAD ? (Real)dld[m] : (Real)0;
+      }
       if (a < D - 1) {
 #pragma unroll
         for (int m = 0; m < PMAX; ++m) {
@@ -745,31 +814,31 @@ __global__ __launch_bounds__(NT) void k_eval_children(
       }
     }
     // rl / dl now hold the last axis
-    double acc = 0.0, g0 = 0.0, g1 = 0.0, g2 = 0.0;
+    Real acc = 0, g0 = 0, g1 = 0, g2 = 0;
     if (D == 3) {
       for (int i0 = 0; i0 < p; ++i0) {
-        double a1 = 0.0, a1g1 = 0.0, a1g2 = 0.0;
+        Real a1 = 0, a1g1 = 0, a1g2 = 0;
         for (int i1 = 0; i1 < p; ++i1) {
-          const_dptr ph = Phi + (i0 * p + i1) * p;
+          const_rptr<Real> ph = Phi + (i0 * p + i1) * p;
           // PMAX consecutive values (entries past p meet zero rows; the
           // buffer carries PMAX zeros of padding at its end)
-          double v[PMAX];
+          Real v[PMAX];
 #pragma unroll
           for (int m = 0; m < PMAX; ++m) v[m] = ph[m];
-          double a2 = 0.0, a2d = 0.0;
+          Real a2 = 0, a2d = 0;
 #pragma unroll
           for (int m = 0; m < PMAX; ++m) {
             a2 = fma(v[m], rl[m], a2);
             if (GRAD) a2d = fma(v[m], dl[m], a2d);
           }
-          const double r1 = lrow[(PMAX + i1) * NT + tid];
+          const Real r1 = lrow[(PMAX + i1) * NT + tid];
           a1 = fma(r1, a2, a1);
           if (GRAD) {
             a1g1 = fma(lrow[(((D - 1) + 1) * PMAX + i1) * NT + tid], a2, a1g1);
             a1g2 = fma(r1, a2d, a1g2);
           }
         }
-        const double r0 = lrow[i0 * NT + tid];
+        const Real r0 = lrow[i0 * NT + tid];
         acc = fma(r0, a1, acc);
         if (GRAD) {
           g0 = fma(lrow[((D - 1) * PMAX + i0) * NT + tid], a1, g0);
@@ -779,17 +848,17 @@ __global__ __launch_bounds__(NT) void k_eval_children(
       }
     } else {
       for (int i0 = 0; i0 < p; ++i0) {
-        const_dptr ph = Phi + i0 * p;
-        double v[PMAX];
+        const_rptr<Real> ph = Phi + i0 * p;
+        Real v[PMAX];
 #pragma unroll
         for (int m = 0; m < PMAX; ++m) v[m] = ph[m];
-        double a1 = 0.0, a1d = 0.0;
+        Real a1 = 0, a1d = 0;
 #pragma unroll
         for (int m = 0; m < PMAX; ++m) {
           a1 = fma(v[m], rl[m], a1);
           if (GRAD) a1d = fma(v[m], dl[m], a1d);
         }
-        const double r0 = lrow[i0 * NT + tid];
+        const Real r0 = lrow[i0 * NT + tid];
         acc = fma(r0, a1, acc);
         if (GRAD) {
           g0 = fma(lrow[((D - 1) * PMAX + i0) * NT + tid], a1, g0);
@@ -798,54 +867,66 @@ __global__ __launch_bounds__(NT) void k_eval_children(
       }
     }
     if (valid) {
-      pot[t] += acc;
+      pot[t] += (double)acc;
       if (GRAD) {
-        grad[(int64_t)t * D + 0] += g0 * sc;
-        grad[(int64_t)t * D + 1] += g1 * sc;
-        if (D == 3) grad[(int64_t)t * D + 2] += g2 * sc;
+        grad[(int64_t)t * D + 0] += (double)g0 * sc;
+        grad[(int64_t)t * D + 1] += (double)g1 * sc;
+        if (D == 3) grad[(int64_t)t * D + 2] += (double)g2 * sc;
       }
     }
   }
 }
 
-template <int D>
-static void launch_direct(const KParams& kp, Eval& E, pdmk_plan* P, hipStream_t s,
-                          bool want_grad) {
-  const int nc = std::max(D == 3 ? kp.nE : kp.nF2, D == 3 ? kp.nEd : kp.nF2d);
+template <int D, int NE, class Real>
+static void launch_direct_t(const KParams& kp, Eval& E, pdmk_plan* P, hipStream_t s,
+                            bool want_grad) {
   const double* c = D == 3 ? P->d_E : P->d_F2;
   const double* cd = D == 3 ? P->d_Ed : P->d_F2d;
-#define PDMK_DIR(NE)                                                                           \
-  hipLaunchKernelGGL((k_direct<D, NE>), dim3(E.nleaf_t), dim3(64), 0, s, kp, E.nleaf_t, E.d_lev, \
-                     E.lf_level, E.lf_box, E.lf_list_beg, E.list, E.sx, E.sq, E.n_img, E.tx,     \
-                     E.n_trg, E.tperm, E.q, E.self_targets ? 1 : 0, c, cd, E.pot_sorted,         \
-                     E.grad_sorted, want_grad ? 1 : 0)
-  if (nc <= 12) PDMK_DIR(12);
-  else if (nc <= 16) PDMK_DIR(16);
-  else if (nc <= 20) PDMK_DIR(20);
-  else if (nc <= 24) PDMK_DIR(24);
-  else PDMK_DIR(32);
-#undef PDMK_DIR
+  hipLaunchKernelGGL((k_direct<D, NE, Real>), dim3(E.nleaf_t), dim3(64), 0, s, kp, E.nleaf_t,
+                     E.d_lev, E.lf_level, E.lf_box, E.lf_list_beg, E.list, E.sx, E.sq, E.n_img,
+                     E.tx, E.n_trg, E.tperm, E.q, E.self_targets ? 1 : 0, c, cd, E.pot_sorted,
+                     E.grad_sorted, want_grad ? 1 : 0);
+}
+
+template <int D, class Real>
+static void launch_direct_r(const KParams& kp, Eval& E, pdmk_plan* P, hipStream_t s,
+                            bool want_grad) {
+  const int nc = std::max(D == 3 ? kp.nE : kp.nF2, D == 3 ? kp.nEd : kp.nF2d);
+  if (nc <= 12) launch_direct_t<D, 12, Real>(kp, E, P, s, want_grad);
+  else if (nc <= 16) launch_direct_t<D, 16, Real>(kp, E, P, s, want_grad);
+  else if (nc <= 20) launch_direct_t<D, 20, Real>(kp, E, P, s, want_grad);
+  else if (nc <= 24) launch_direct_t<D, 24, Real>(kp, E, P, s, want_grad);
+  else launch_direct_t<D, 32, Real>(kp, E, P, s, want_grad);
 }
 
 template <int D>
+static void launch_direct(const KParams& kp, Eval& E, pdmk_plan* P, hipStream_t s,
+                          bool want_grad) {
+  if (kp.precision == PDMK_PREC_MIXED) launch_direct_r<D, float>(kp, E, P, s, want_grad);
+  else launch_direct_r<D, double>(kp, E, P, s, want_grad);
+}
+
+template <int D, class Real>
 static void launch_transfer(const KParams& kp, const Level& Lp, const Level& Lc, int up,
-                            const double* src, double* dst, pdmk_plan* P, Eval& E,
+                            const void* src_, void* dst_, pdmk_plan* P, Eval& E,
                             hipStream_t s) {
+  const Real* src = static_cast<const Real*>(src_);
+  Real* dst = static_cast<Real*>(dst_);
   const int p = kp.p;
   const int pD = D == 3 ? p * p * p : p * p;
-  const size_t full = (size_t)(pD + 2 * p * 40) * sizeof(double);
+  const size_t full = (size_t)(pD + 2 * p * 40) * sizeof(Real);
   const bool lds = full <= 100 * 1024;
-  const size_t smem = lds ? full : (size_t)2 * p * 40 * sizeof(double);
+  const size_t smem = lds ? full : (size_t)2 * p * 40 * sizeof(Real);
   const int nown = (pD + 255) / 256;
   const int mode = up ? (nown <= 48 ? 0 : 1) : 2;
   const int nblocks = mode == 0 ? Lp.nnl : Lc.nnl;
-  double* scratch = lds ? nullptr : E.alloc<double>((size_t)nblocks * pD);
+  Real* scratch = lds ? nullptr : E.alloc<Real>((size_t)nblocks * pD);
 #define PDMK_TR(PM, L, NO, MO)                                                                  \
   do {                                                                                          \
-    PDMK_HIP(hipFuncSetAttribute((const void*)&k_transfer<D, PM, L, NO, MO>,                    \
+    PDMK_HIP(hipFuncSetAttribute((const void*)&k_transfer<D, PM, L, NO, MO, Real>,              \
                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem));       \
-    hipLaunchKernelGGL((k_transfer<D, PM, L, NO, MO>), dim3(nblocks), dim3(256), smem, s, kp,   \
-                       Lp, Lc, src, dst, P->d_Tm, scratch);                                     \
+    hipLaunchKernelGGL((k_transfer<D, PM, L, NO, MO, Real>), dim3(nblocks), dim3(256), smem, s, \
+                       kp, Lp, Lc, src, dst, P->d_Tm, scratch);                                 \
   } while (0)
   if (mode == 0) {
     if (nown <= 8) {
@@ -873,13 +954,14 @@ static void launch_transfer(const KParams& kp, const Level& Lp, const Level& Lc,
 #undef PDMK_TR
 }
 
-template <int D>
+template <int D, class Real>
 static void launch_anterp(const KParams& kp, const Level& L, const Level& C, int l, Eval& E,
                           pdmk_plan* P, hipStream_t s) {
   const int p = kp.p;
+  Real* Q = static_cast<Real*>(L.proxy_q);
 #define PDMK_AN(PM) \
-  hipLaunchKernelGGL((k_anterp<D, PM>), dim3(L.nnl), dim3(256), 0, s, kp, L, C, l, E.sx, E.sq, \
-                     E.n_img, P->d_nodes, P->d_bw, L.proxy_q)
+  hipLaunchKernelGGL((k_anterp<D, PM, Real>), dim3(L.nnl), dim3(256), 0, s, kp, L, C, l, E.sx, \
+                     E.sq, E.n_img, P->d_nodes, P->d_bw, Q)
   if (p <= 16) PDMK_AN(16);
   else if (p <= 24) PDMK_AN(24);
   else if (p <= 32) PDMK_AN(32);
@@ -887,13 +969,14 @@ static void launch_anterp(const KParams& kp, const Level& L, const Level& C, int
 #undef PDMK_AN
 }
 
-template <int D>
+template <int D, class Real>
 static void launch_eval_children(const KParams& kp, const Level& Lp, const Level& Lc, int l,
                                  Eval& E, pdmk_plan* P, hipStream_t s, bool want_grad) {
   const int p = kp.p;
 #define PDMK_EV(PM, NT, G)                                                                   \
-  hipLaunchKernelGGL((k_eval_children<D, PM, NT, G>), dim3(Lp.nnl), dim3(NT), 0, s, kp, Lp, \
-                     Lc, l, E.tx, E.n_trg, P->d_nodes, P->d_bw, E.pot_sorted, E.grad_sorted)
+  hipLaunchKernelGGL((k_eval_children<D, PM, NT, G, Real>), dim3(Lp.nnl), dim3(NT), 0, s, kp, \
+                     Lp, Lc, l, E.tx, E.n_trg, P->d_nodes, P->d_bw, E.pot_sorted,             \
+                     E.grad_sorted)
   if (want_grad) {
     if (p <= 16) PDMK_EV(16, 64, true);
     else if (p <= 24) PDMK_EV(24, 64, true);
@@ -908,8 +991,22 @@ static void launch_eval_children(const KParams& kp, const Level& Lp, const Level
 #undef PDMK_EV
 }
 
-template <int D>
+// LDS bytes of the fused plane-wave kernels for element type Real.
+static size_t lds_pw_out(int p, int J, size_t rs) {
+  const size_t n1 = 2 * J + 1;
+  return (size_t)p * p * p * rs + (2 * n1 * p + (size_t)p * p + n1 * p) * 2 * rs;
+}
+static size_t lds_pw_in(int p, int J, size_t rs) {
+  const size_t n1 = 2 * J + 1;
+  return (size_t)p * p * p * rs + (n1 * p + n1 * n1 + n1 * p + (size_t)p * p) * 2 * rs;
+}
+
+// Near-field pipeline with proxy and plane-wave data of type Real.  Real =
+// float is used only with the fused 3D plane-wave kernels; the generic
+// axis-by-axis path (2D, or tensors too large for LDS) is FP64.
+template <int D, class Real>
 static void near_impl(pdmk_plan* P, Eval& E, bool want_grad) {
+  using C = Cx<Real>;
   const KParams& kp = P->kp;
   hipStream_t s = E.s;
   const int p = kp.p, J = kp.J;
@@ -931,41 +1028,40 @@ static void near_impl(pdmk_plan* P, Eval& E, bool want_grad) {
   for (int l = 0; l < nlev; ++l) {
     Level& L = E.lev[l];
     if (L.nnl == 0) continue;
-    // 64 doubles of zero padding: the leaf evaluation reads whole register
+    // 64 entries of zero padding: the leaf evaluation reads whole register
     // rows past the last tensor entry
-    L.proxy_q = E.alloc<double>((size_t)L.nnl * pD + 64);
-    L.proxy_phi = E.alloc<double>((size_t)L.nnl * pD + 64);
-    PDMK_HIP(hipMemsetAsync(L.proxy_phi, 0, sizeof(double) * ((size_t)L.nnl * pD + 64), s));
+    L.proxy_q = E.alloc<Real>((size_t)L.nnl * pD + 64);
+    L.proxy_phi = E.alloc<Real>((size_t)L.nnl * pD + 64);
+    PDMK_HIP(hipMemsetAsync(L.proxy_phi, 0, sizeof(Real) * ((size_t)L.nnl * pD + 64), s));
   }
   if (maxnl > 0) {
     // upward pass
     for (int l = nlev - 2; l >= 0; --l) {
       Level& L = E.lev[l];
       if (L.nnl == 0) continue;
-      Level& C = E.lev[l + 1];
-      launch_anterp<D>(kp, L, C, l, E, P, s);
-      if (C.nnl > 0) launch_transfer<D>(kp, L, C, 1, C.proxy_q, L.proxy_q, P, E, s);
+      Level& Cl = E.lev[l + 1];
+      launch_anterp<D, Real>(kp, L, Cl, l, E, P, s);
+      if (Cl.nnl > 0) launch_transfer<D, Real>(kp, L, Cl, 1, Cl.proxy_q, L.proxy_q, P, E, s);
     }
     // plane waves, level by level
     const int64_t s1 = (int64_t)(J + 1) * p * (D == 3 ? p : 1);
     const int64_t s2 = D == 3 ? (int64_t)(J + 1) * n1 * p : 0;
     const int64_t s3 = D == 3 ? (int64_t)(J + 1) * n1 * n1 : (int64_t)(J + 1) * n1;
-    const bool fused_any = D == 3 &&
-        (size_t)p * p * p * 8 + (size_t)(n1 * p + n1 * n1 + n1 * p + p * p) * 16 <= 150 * 1024 &&
-        (size_t)p * p * p * 8 + (size_t)(2 * n1 * p + p * p + n1 * p) * 16 <= 150 * 1024;
-    double2* bS = E.alloc<double2>((size_t)maxnl * s3);
-    double2* bA = fused_any ? nullptr : E.alloc<double2>((size_t)maxnl * s1);
-    double2* bB = (D == 3 && !fused_any) ? E.alloc<double2>((size_t)maxnl * s2) : nullptr;
-    double2* bI = fused_any ? nullptr : E.alloc<double2>((size_t)maxnl * s3);
+    const size_t lds_out = lds_pw_out(p, J, sizeof(Real));
+    const size_t lds_in = lds_pw_in(p, J, sizeof(Real));
+    const bool fused = D == 3 && lds_out <= 150 * 1024 && lds_in <= 150 * 1024;
+    C* bS = E.alloc<C>((size_t)maxnl * s3);
+    double2* bA = fused ? nullptr : E.alloc<double2>((size_t)maxnl * s1);
+    double2* bB = (D == 3 && !fused) ? E.alloc<double2>((size_t)maxnl * s2) : nullptr;
+    double2* bI = fused ? nullptr : E.alloc<double2>((size_t)maxnl * s3);
     unsigned long long* npairs = E.alloc<unsigned long long>(1);
     PDMK_HIP(hipMemsetAsync(npairs, 0, sizeof(unsigned long long), s));
-    const size_t lds_out = (size_t)p * p * p * 8 + (size_t)(2 * n1 * p + p * p + n1 * p) * 16;
-    const size_t lds_in = (size_t)p * p * p * 8 + (size_t)(n1 * p + n1 * n1 + n1 * p + p * p) * 16;
-    const bool fused = D == 3 && lds_out <= 150 * 1024 && lds_in <= 150 * 1024;
+    const C* Ftab = reinterpret_cast<const C*>(sizeof(Real) == 4 ? (const void*)P->d_Ff
+                                                                 : (const void*)P->d_F);
     if (fused) {
-      PDMK_HIP(hipFuncSetAttribute((const void*)&k_pw_out,
+      PDMK_HIP(hipFuncSetAttribute((const void*)&k_pw_out<Real>,
                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_out));
-      PDMK_HIP(hipFuncSetAttribute((const void*)&k_pw_in,
+      PDMK_HIP(hipFuncSetAttribute((const void*)&k_pw_in<Real>,
                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_in));
     }
     for (int l = 0; l < nlev; ++l) {
@@ -976,12 +1072,14 @@ static void near_impl(pdmk_plan* P, Eval& E, bool want_grad) {
       const double levfac = D == 3 ? 1.0 / (3.0 * h) : 1.0;
       const int zz = D == 3 ? p : 1;
       if (fused) {
-        hipLaunchKernelGGL(k_pw_out, dim3(nn), dim3(256), lds_out, s, kp, L, L.proxy_q, P->d_F,
-                           bS);
-        hipLaunchKernelGGL(k_pw_in, dim3(nn), dim3(256), lds_in, s, kp, L, bS, P->d_F,
-                           P->d_dtab, levfac, L.proxy_phi, npairs);
+        hipLaunchKernelGGL(k_pw_out<Real>, dim3(nn), dim3(256), lds_out, s, kp, L,
+                           static_cast<const Real*>(L.proxy_q), Ftab, bS);
+        hipLaunchKernelGGL(k_pw_in<Real>, dim3(nn), dim3(256), lds_in, s, kp, L, bS, Ftab,
+                           P->d_dtab, levfac, static_cast<Real*>(L.proxy_phi), npairs);
         continue;
       }
+      if (sizeof(Real) != 8) throw Error{PDMK_ERR_UNSUPPORTED, "FP32 proxies need the fused path"};
+      double2* bSd = reinterpret_cast<double2*>(bS);
       // outgoing: proxy charges -> plane waves (Hermitian half on axis 0)
       hipLaunchKernelGGL((k_axis<false, 0>), dim3(nblk(nn * s1, 256)), dim3(256), 0, s, nn, p,
                          p, zz, 0, J + 1, (const void*)L.proxy_q, (void*)bA, P->d_F, J, p, 0, 0);
@@ -989,14 +1087,14 @@ static void near_impl(pdmk_plan* P, Eval& E, bool want_grad) {
         hipLaunchKernelGGL((k_axis<true, 0>), dim3(nblk(nn * s2, 256)), dim3(256), 0, s, nn,
                            J + 1, p, p, 1, n1, (const void*)bA, (void*)bB, P->d_F, 0, p, 0, 0);
         hipLaunchKernelGGL((k_axis<true, 0>), dim3(nblk(nn * s3, 256)), dim3(256), 0, s, nn,
-                           J + 1, n1, p, 2, n1, (const void*)bB, (void*)bS, P->d_F, 0, p, 0, 0);
+                           J + 1, n1, p, 2, n1, (const void*)bB, (void*)bSd, P->d_F, 0, p, 0, 0);
       } else {
         hipLaunchKernelGGL((k_axis<true, 0>), dim3(nblk(nn * s3, 256)), dim3(256), 0, s, nn,
-                           J + 1, p, 1, 1, n1, (const void*)bA, (void*)bS, P->d_F, 0, p, 0, 0);
+                           J + 1, p, 1, 1, n1, (const void*)bA, (void*)bSd, P->d_F, 0, p, 0, 0);
       }
       // translation between colleagues with the difference-kernel multiplier
-      hipLaunchKernelGGL(k_translate<D>, dim3(nblk(nn * s3, 256)), dim3(256), 0, s, L, J, bS, bI,
-                         P->d_dtab, levfac, npairs);
+      hipLaunchKernelGGL(k_translate<D>, dim3(nblk(nn * s3, 256)), dim3(256), 0, s, L, J, bSd,
+                         bI, P->d_dtab, levfac, npairs);
       // incoming: plane waves -> proxy potentials
       if (D == 3) {
         hipLaunchKernelGGL((k_axis<true, 0>), dim3(nblk(nn * s2, 256)), dim3(256), 0, s, nn,
@@ -1013,10 +1111,10 @@ static void near_impl(pdmk_plan* P, Eval& E, bool want_grad) {
     }
     // downward pass: parent proxy potential -> non-leaf child proxy potential
     for (int l = 1; l < nlev; ++l) {
-      Level& C = E.lev[l];
+      Level& Cl = E.lev[l];
       Level& L = E.lev[l - 1];
-      if (C.nnl == 0) continue;
-      launch_transfer<D>(kp, L, C, 0, L.proxy_phi, C.proxy_phi, P, E, s);
+      if (Cl.nnl == 0) continue;
+      launch_transfer<D, Real>(kp, L, Cl, 0, L.proxy_phi, Cl.proxy_phi, P, E, s);
     }
     PDMK_HIP(hipMemcpyAsync(E.d_lev, E.lev.data(), sizeof(Level) * E.lev.size(),
                             hipMemcpyHostToDevice, s));
@@ -1029,7 +1127,8 @@ static void near_impl(pdmk_plan* P, Eval& E, bool want_grad) {
   // leaf targets evaluate their parent's proxy potential
   if (maxnl > 0)
     for (int l = 0; l + 1 < nlev; ++l)
-      if (E.lev[l].nnl > 0) launch_eval_children<D>(kp, E.lev[l], E.lev[l + 1], l, E, P, s, want_grad);
+      if (E.lev[l].nnl > 0)
+        launch_eval_children<D, Real>(kp, E.lev[l], E.lev[l + 1], l, E, P, s, want_grad);
   PDMK_HIP(hipEventRecord(e3, s));
   PDMK_HIP(hipEventSynchronize(e3));
   float t01, t12, t23;
@@ -1048,8 +1147,16 @@ static void near_impl(pdmk_plan* P, Eval& E, bool want_grad) {
 void stage_near(pdmk_plan* P, Eval& E, bool want_grad) {
   E.pot_sorted = E.alloc<double>(E.n_trg);
   E.grad_sorted = want_grad ? E.alloc<double>(E.n_trg * P->kp.dim) : nullptr;
-  if (P->kp.dim == 3) near_impl<3>(P, E, want_grad);
-  else near_impl<2>(P, E, want_grad);
+  const KParams& kp = P->kp;
+  const bool f32 = kp.precision == PDMK_PREC_MIXED && kp.dim == 3 &&
+                   lds_pw_out(kp.p, kp.J, 4) <= 150 * 1024 &&
+                   lds_pw_in(kp.p, kp.J, 4) <= 150 * 1024;
+  if (kp.dim == 3) {
+    if (f32) near_impl<3, float>(P, E, want_grad);
+    else near_impl<3, double>(P, E, want_grad);
+  } else {
+    near_impl<2, double>(P, E, want_grad);
+  }
 }
 
 }  // namespace pdmk

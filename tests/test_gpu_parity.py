@@ -31,12 +31,12 @@ def pdmk():
     return m
 
 
-def _eval(pdmk, torch_dev, L, src, q, eps, trg=None, grad=False, **over):
+def _eval(pdmk, torch_dev, L, src, q, eps, trg=None, grad=False, precision="fp64", **over):
     torch, dev = torch_dev
     S = torch.tensor(src, device=dev)
     Q = torch.tensor(q, device=dev)
     T = torch.tensor(trg, device=dev) if trg is not None else None
-    out = pdmk.pdmk_eval(L, S, Q, trg=T, eps=eps, grad=grad, **over)
+    out = pdmk.pdmk_eval(L, S, Q, trg=T, eps=eps, grad=grad, precision=precision, **over)
     if grad:
         return out[0].cpu().numpy(), out[1].cpu().numpy()
     return out.cpu().numpy()
@@ -210,3 +210,47 @@ def test_plan_reuse_and_stats(pdmk, torch_dev):
     assert np.abs(a - b).max() <= 1e-13 * np.abs(a).max()
     st = plan.stats()
     assert st["n_src"] == 20000 and st["n_images"] >= 20000 and st["n_levels"] >= 1
+
+
+# ------------------------------------------------------------- mixed precision
+# FP32 residual sums, proxies and plane waves (box-local offsets), FP64 box
+# assignment, far-field scaling and accumulation; the error against the FP64
+# oracle must still be within eps.
+
+@pytest.mark.parametrize("eps", [1e-3, 1e-6])
+def test_mixed_c2_clustered(pdmk, torch_dev, eps):
+    L, src, q = workloads.clustered3d(6000, seed=2)
+    ref = ewald.ewald(L, src, q)
+    pot = _eval(pdmk, torch_dev, L, src, q, eps, precision="mixed", kappa=3.0, n_s=60)
+    assert ewald.rel_l2(pot, ref) <= eps
+
+
+@pytest.mark.parametrize("eps", [1e-3, 1e-6])
+def test_mixed_c3_shell_sampled(pdmk, torch_dev, eps):
+    L, src, q = workloads.shell3d(60000, seed=3)
+    idx = np.random.default_rng(1).choice(len(q), 96, replace=False)
+    ref = ewald.ewald_sampled(L, src, q, idx)
+    pot = _eval(pdmk, torch_dev, L, src, q, eps, precision="mixed")
+    assert ewald.rel_l2(pot[idx], ref) <= eps
+
+
+def test_mixed_c3_full_size_golden(pdmk, torch_dev):
+    path = os.path.join(HERE, "golden", "shell3d_n1e7_seed3.txt")
+    data = np.loadtxt(path)
+    idx = data[:, 0].astype(np.int64)
+    L, src, q = workloads.shell3d(10_000_000, seed=3)
+    pot = _eval(pdmk, torch_dev, L, src, q, 1e-6, precision="mixed")
+    assert ewald.rel_l2(pot[idx], data[:, 1]) <= 1e-6
+
+
+def test_mixed_2d_and_gradient(pdmk, torch_dev):
+    L, src, q = workloads.oblique2d(2000, seed=1)
+    ref = ewald.ewald(L, src, q)
+    pot = _eval(pdmk, torch_dev, L, src, q, 1e-6, precision="mixed", n_s=20)
+    assert ewald.rel_l2(pot, ref) <= 1e-6
+    L, src, q = workloads.clustered3d(3000, seed=12)
+    ref, gref = ewald.ewald(L, src, q, grad=True)
+    pot, g = _eval(pdmk, torch_dev, L, src, q, 1e-6, precision="mixed", grad=True, kappa=2.0,
+                   n_s=60)
+    assert ewald.rel_l2(pot, ref) <= 1e-6
+    assert ewald.rel_l2(g, gref) <= 1e-5
