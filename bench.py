@@ -7,46 +7,150 @@ in fractional coordinates), +-1 neutral charges, targets = sources,
 eps = 1e-6.  A step is one full call (orientation, images, tree, lists, near
 field, far field, assembly) with inputs resident in HBM.
 
+Both arithmetic modes are timed: the mixed-precision evaluation gives
+`value`; the FP64 evaluation is reported beside it under "fp64".  Each mode
+reports its relative l2 error on stored oracle values at 64 sampled sources.
+
 Prints one JSON line.  --gpus above 1 is rejected: this build runs on one GPU.
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
+import statistics
+import subprocess
 import sys
 import time
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# Per-pair floating-point work of the residual sum (3D, FP64), counted from the
-# kernel's arithmetic on every visited pair: 3 sub + 3 FMA for r^2, compare.
-# Pairs inside the support add sqrt, divide and a Clenshaw series of nE terms;
-# those are counted separately from the kernel's own in-support statistics.
-FLOP_PER_VISITED_PAIR = 9.0
+# Published MI355X peaks used for the roofline of the residual-sum kernel
+# (vector ALU, not matrix cores: the kernel is an n-body sum with a
+# compactly supported polynomial kernel, not a contraction).
+PEAK_TFLOPS = {"fp64": 78.6, "mixed": 157.3}
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_direct_traffic_shell3d_n1e7.json")
+NEAR_SRC = os.path.join(ROOT, "paper_2606_28608_amd", "csrc", "near.hip")
+
+
+def flop_per_pair(series_len: int):
+    """Arithmetic of the residual kernel, counted from its operations.
+
+    Every visited pair: 3 subtractions, 1 multiply and 2 FMAs for r^2 (8 flop).
+    A pair inside the support r < h adds s = r^2/h^2 (2), the Chebyshev
+    argument (2), a Clenshaw step per coefficient (FMA + subtraction, 3 each),
+    the final Clenshaw step (4), rsqrt (1), E/h (1), 1/r - E/h (1) and the
+    charge FMA (2): 3 * series_len + 10 flop.
+    """
+    return 8.0, 3.0 * series_len + 10.0
 
 
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--n", type=float, default=1e7)
     ap.add_argument("--eps", type=float, default=1e-6)
-    ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
+    ap.add_argument("--precision", default="both", choices=["both", "fp64", "mixed"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-check", action="store_true")
-    ap.add_argument("--cpu-sample", type=int, default=16)
+    ap.add_argument("--cpu-sample", type=int, default=0,
+                    help="oracle targets for the CPU baseline (0: one per oracle thread)")
+    ap.add_argument("--cpu-alpha", type=float, default=1.3,
+                    help="Ewald splitting parameter of the CPU baseline run")
+    ap.add_argument("--child", action="store_true", help=argparse.SUPPRESS)
+    ap.add_argument("--copy-calib", action="store_true",
+                    help="only run a plain 1 GiB device copy (calibrates HBM byte counters)")
     return ap.parse_args()
 
 
-def main():
-    args = parse()
-    if args.gpus != 1:
-        print("bench.py: this build runs on exactly one GPU; --gpus %d is not supported"
-              % args.gpus, file=sys.stderr)
-        sys.exit(2)
+def kernel_source_hash():
+    with open(NEAR_SRC, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def load_traffic(mode):
+    """HBM bytes per launch of the residual kernel from the committed counter
+    runs, or None when the kernel source has changed since they were taken."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if t.get("near_hip_sha256_16") != kernel_source_hash():
+        return None
+    m = t.get("modes", {}).get(mode)
+    return None if m is None else m.get("bytes_per_launch")
+
+
+def run_mode(pdmk, L, S, Q, n, eps, precision, steps, warmup, gold):
+    import numpy as np
+    import torch
+    plan = pdmk.Plan(L, eps=eps, precision=precision)
+    g = plan.geometry()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    pot = plan.eval(S, Q)
+    torch.cuda.synchronize()
+    cold_ms = 1e3 * (time.perf_counter() - t0)
+    for _ in range(max(0, warmup - 1)):
+        pot = plan.eval(S, Q)
+    torch.cuda.synchronize()
+    stage, per = [], []
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        t1 = time.perf_counter()
+        pot = plan.eval(S, Q)          # blocks until the results are written
+        per.append(1e3 * (time.perf_counter() - t1))
+        stage.append(plan.stats())
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    err = None
+    if gold is not None:
+        idx, ref = gold
+        got = pot.cpu().numpy()[idx]
+        err = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
+    st = stage[-1]
+    avg = {k: sum(s[k] for s in stage) / len(stage) for k in stage[0] if k.startswith("t_")}
+    return {"plan": g, "ms_per_step": 1e3 * dt / steps, "median_ms": statistics.median(per),
+            "step_ms": [round(x, 2) for x in per],
+            "cold_first_call_ms": cold_ms, "value": n / (dt / steps), "e_rel_sampled": err,
+            "stats": st, "stages_ms": {k: round(v, 3) for k, v in avg.items()}}
+
+
+def roofline(r, mode):
+    st = r["stats"]
+    t_launch = r["stages_ms"]["t_direct_ms"] * 1e-3
+    fv, fs = flop_per_pair(st["series_len"])
+    flop = st["n_direct_pairs"] * fv + st["n_support_pairs"] * fs
+    achieved = flop / t_launch / 1e12 if t_launch > 0 else 0.0
+    peak = PEAK_TFLOPS[mode]
+    traffic = load_traffic(mode)
+    return {"bound": "alu", "kernel": "k_direct", "achieved": achieved, "peak": peak,
+            "unit": "TFLOP/s", "frac": achieved / peak, "traffic": traffic,
+            "launch_ms": r["stages_ms"]["t_direct_ms"], "flop_per_launch": flop,
+            "pairs_visited": st["n_direct_pairs"], "pairs_in_support": st["n_support_pairs"],
+            "flop_per_visited_pair": fv, "flop_per_support_pair": fs,
+            "arith": "fp32" if mode == "mixed" else "fp64"}
+
+
+def copy_calib():
+    import torch
+    nbytes = 1 << 30
+    a = torch.empty(nbytes // 8, dtype=torch.float64, device="cuda:0").fill_(1.0)
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_read": nbytes, "copy_bytes_written": nbytes, "launches": 3}))
+
+
+def child(args):
+    """Time one arithmetic mode on the GPU and print its results as JSON."""
     import numpy as np
     import torch
     from paper_2606_28608_amd import pdmk, workloads as W
@@ -56,80 +160,103 @@ def main():
     dev = torch.device("cuda:0")
     S = torch.tensor(src, dtype=torch.float64, device=dev)
     Q = torch.tensor(q, dtype=torch.float64, device=dev)
-    plan = pdmk.Plan(L, eps=args.eps, precision=args.precision)
-    g = plan.geometry()
+    gold = None
+    if not args.no_check and n == 10_000_000:
+        path = os.path.join(ROOT, "tests", "golden", "shell3d_n1e7_seed3.txt")
+        if os.path.exists(path):
+            data = np.loadtxt(path)
+            gold = (data[:, 0].astype(np.int64), data[:, 1])
+    r = run_mode(pdmk, L, S, Q, n, args.eps, args.precision, args.steps, args.warmup, gold)
+    g = r.pop("plan")
+    r["plan"] = {"kappa": g.kappa, "n_s": g.n_s, "porder": g.porder, "npw": g.npw,
+                 "nufft_w": g.nufft_w, "fourier_grid": list(g.fgrid)}
+    r["roofline"] = roofline(r, args.precision)
+    print(json.dumps(r))
 
-    for _ in range(args.warmup):
-        pot = plan.eval(S, Q)
-    torch.cuda.synchronize()
-    stage = []
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        pot = plan.eval(S, Q)
-        stage.append(plan.stats())
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    ms = 1e3 * dt / args.steps
-    value = n / (dt / args.steps)
 
-    st = stage[-1]
-    avg = {k: sum(s[k] for s in stage) / len(stage) for k in stage[0] if k.startswith("t_")}
+def run_child(args, mode):
+    cmd = [sys.executable, os.path.abspath(__file__), "--child", "--precision", mode,
+           "--steps", str(args.steps), "--warmup", str(args.warmup), "--n", str(args.n),
+           "--eps", str(args.eps)]
+    if args.no_check:
+        cmd.append("--no-check")
+    p = subprocess.run(cmd, stdout=subprocess.PIPE, text=True)
+    if p.returncode != 0:
+        print("bench.py: %s run failed with status %d" % (mode, p.returncode), file=sys.stderr)
+        sys.exit(p.returncode if p.returncode > 0 else 1)
+    return json.loads(p.stdout.strip().splitlines()[-1])
 
-    # dominant kernel: the residual sums (one launch per call); its duration is
-    # the library's HIP-event time around that launch on the call's stream
-    t_dir = avg["t_direct_ms"] * 1e-3
-    pairs = st["n_direct_pairs"]
-    # peak of FP64 vector arithmetic (256 CUs x 4 SIMD x 16 lanes x 2 flop x 2.4 GHz)
-    peak = 78.6
-    achieved = pairs * FLOP_PER_VISITED_PAIR / t_dir / 1e12 if t_dir > 0 else 0.0
-    roofline = {"bound": "alu", "kernel": "k_direct", "achieved": achieved, "peak": peak,
-                "unit": "TFLOP/s", "frac": achieved / peak, "traffic": None,
-                "launch_ms": avg["t_direct_ms"], "pairs_per_launch": pairs,
-                "flop_per_pair": FLOP_PER_VISITED_PAIR}
 
-    err = None
-    if not args.no_check:
-        gold = os.path.join(ROOT, "tests", "golden", "shell3d_n1e7_seed3.txt")
-        if os.path.exists(gold) and n == 10_000_000:
-            data = np.loadtxt(gold)
-            idx = data[:, 0].astype(np.int64)
-            ref = data[:, 1]
-            got = pot.cpu().numpy()[idx]
-            err = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py: this build runs on exactly one GPU; --gpus %d is not supported"
+              % args.gpus, file=sys.stderr)
+        sys.exit(2)
+    if args.copy_calib:
+        copy_calib()
+        return
+    if args.child:
+        child(args)
+        return
+    # Each arithmetic mode runs in a child process of its own, one after the
+    # other, so that the two measurements share no device state.  This
+    # process never touches the GPU.
+    modes = ["mixed", "fp64"] if args.precision == "both" else [args.precision]
+    res = {m: run_child(args, m) for m in modes}
+    head = modes[0]
+    r = res[head]
+    n = int(args.n)
 
     cpu = None
     if not args.no_cpu_baseline:
+        import numpy as np
         from oracle import ewald as E
-        rng = np.random.default_rng(7)
-        ns = args.cpu_sample
-        idx = rng.choice(n, ns, replace=False)
+        from paper_2606_28608_amd import workloads as W
+        L, src, q = W.shell3d(n, seed=3)
+        ns = args.cpu_sample if args.cpu_sample > 0 else E.threads()
+        idx = np.random.default_rng(7).choice(n, ns, replace=False)
         t1 = time.perf_counter()
-        E.ewald_sampled(L, src, q, idx)
+        E.ewald_sampled(L, src, q, idx, alpha=args.cpu_alpha)
         tc = time.perf_counter() - t1
-        cpu = {"value": ns / tc, "unit": "particles/s", "cores": os.cpu_count(),
+        cpu = {"value": ns / tc, "unit": "particles/s", "cores": E.threads(),
                "kind": "oracle",
-               "sample": "Ewald potential at %d sampled targets of the same N=%d system "
-                         "(structure factor over all sources, real-space sum over all "
-                         "sources); %.1f s" % (ns, n, tc)}
+               "sample": "Ewald potential at %d sampled sources of the same N=%d shell "
+                         "system, splitting alpha=%g (structure factor over all N sources, "
+                         "real-space sum over all N sources and their images); %.1f s"
+                         % (ns, n, args.cpu_alpha, tc)}
 
+    def summary(x):
+        return {k: x[k] for k in ("value", "ms_per_step", "median_ms", "step_ms",
+                                  "cold_first_call_ms", "e_rel_sampled", "stages_ms",
+                                  "roofline")}
+
+    pl = r["plan"]
     out = {
         "metric": "particles/sec, 3D triclinic N=1e7 at eps=1e-6: mixed-precision vs FP64 on 1 GPU",
-        "value": value, "unit": "particles/s", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": "f64" if args.precision == "fp64" else "mixed",
+        "value": r["value"], "unit": "particles/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": r["ms_per_step"], "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None,
+        "dtype": "mixed" if head == "mixed" else "f64",
         "data": "synthetic",
         "config": {"workload": "shell3d: triclinic a1=(1,0,0) a2=(0.5,4,0) a3=(0.3,0.7,17), "
-                               "N=%d thin shell r=0.3 w=1e-3, +-1 charges, eps=%g" % (n, args.eps),
-                   "precision": args.precision, "kappa": g.kappa, "n_s": g.n_s,
-                   "porder": g.porder, "npw": g.npw, "nufft_w": g.nufft_w,
-                   "fourier_grid": list(g.fgrid)},
-        "e_rel_sampled": err,
-        "stages_ms": {k: round(v, 3) for k, v in avg.items()},
-        "counts": {k: st[k] for k in ("n_images", "n_levels", "n_boxes", "n_leaves",
-                                      "n_nonleaf", "n_direct_pairs", "n_pw_pairs")},
-        "roofline": roofline,
+                               "N=%d thin shell r=0.3 w=1e-3, +-1 charges, eps=%g, "
+                               "targets = sources" % (n, args.eps),
+                   "precision": head, "kappa": pl["kappa"], "n_s": pl["n_s"],
+                   "porder": pl["porder"], "npw": pl["npw"], "nufft_w": pl["nufft_w"],
+                   "fourier_grid": pl["fourier_grid"]},
+        "median_ms": r["median_ms"], "step_ms": r["step_ms"],
+        "cold_first_call_ms": r["cold_first_call_ms"],
+        "e_rel_sampled": r["e_rel_sampled"],
+        "stages_ms": r["stages_ms"],
+        "counts": {k: r["stats"][k] for k in ("n_images", "n_levels", "n_boxes", "n_leaves",
+                                             "n_nonleaf", "n_direct_pairs", "n_support_pairs",
+                                             "n_pw_pairs")},
+        "roofline": r["roofline"],
         "cpu_baseline": cpu,
     }
+    for m in modes[1:]:
+        out[m] = summary(res[m])
     print(json.dumps(out))
 
 

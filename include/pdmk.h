@@ -108,7 +108,12 @@ int pdmk_eval(const pdmk_opts* opts, const double* L, int64_t n_src,
 /*
  * Plans keep the host tables for one (opts, L) pair and the device
  * workspace between calls (the tree is rebuilt every call, as in the
- * paper).  A plan is bound to the device that was current at creation.
+ * paper).  The workspace is one device buffer that grows to the largest call
+ * seen; a call that needs more than it holds allocates the difference for
+ * itself, and the plan then grows the buffer, so repeated calls of one size
+ * allocate nothing after the first.  It is freed by pdmk_plan_destroy.  A
+ * plan is bound to the device that was current at creation and serves one
+ * call at a time (calls on one plan from several threads must not overlap).
  */
 typedef struct pdmk_plan pdmk_plan;
 int pdmk_plan_create(const pdmk_opts* opts, const double* L, pdmk_plan** out);
@@ -149,6 +154,10 @@ typedef struct {
   int64_t n_pw_pairs;               /* plane-wave box pairs */
   double t_build_ms, t_near_ms, t_far_ms, t_total_ms;
   double t_direct_ms, t_pw_ms, t_proxy_ms;
+  int64_t n_support_pairs;          /* visited pairs inside the residual support (r < h) */
+  int series_len;                   /* terms of the residual's Chebyshev series */
+  double t_call_ms;                 /* host wall time of the whole call */
+  int64_t workspace_bytes;          /* device workspace the call used */
 } pdmk_stats;
 int pdmk_plan_stats(const pdmk_plan* plan, pdmk_stats* out);
 

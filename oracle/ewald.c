@@ -482,3 +482,12 @@ int oracle_ball_sum(int d, const double* L, long n_src, const double* src,
   }
   return 0;
 }
+
+/* Number of OpenMP threads the sums above run on. */
+int oracle_threads(void) {
+#ifdef _OPENMP
+  return omp_get_max_threads();
+#else
+  return 1;
+#endif
+}

@@ -66,6 +66,8 @@ def _load():
         lib.oracle_ball_sum.restype = ctypes.c_int
         lib.oracle_expint_e1.argtypes = [ctypes.c_double]
         lib.oracle_expint_e1.restype = ctypes.c_double
+        lib.oracle_threads.argtypes = []
+        lib.oracle_threads.restype = ctypes.c_int
         _lib = lib
     return _lib
 
@@ -173,6 +175,11 @@ def ball_sum(L, src, q, trg, R, self_idx=None):
     _load().oracle_ball_sum(d, _dp(L), src.shape[0], _dp(src), _dp(q), trg.shape[0],
                             _dp(trg), _lp(self_idx), float(R), _dp(pot))
     return pot
+
+
+def threads() -> int:
+    """OpenMP threads the oracle's sums use."""
+    return int(_load().oracle_threads())
 
 
 def rel_l2(approx, ref) -> float:

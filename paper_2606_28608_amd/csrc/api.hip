@@ -1,6 +1,7 @@
 // C interface (include/pdmk.h): plans, evaluation pipeline of Algorithm 1,
 // assembly with the self-interaction correction (Section 3.8), status codes.
 #include <cmath>
+#include <chrono>
 #include <cstring>
 #include <string>
 
@@ -114,6 +115,33 @@ static void free_plan_tables(pdmk_plan* P) {
                   P->d_F, P->d_Ff, P->d_dtab, P->d_farscale, P->d_shiftvec};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
+  if (P->arena) {
+    // every evaluation synchronises its stream before returning, so the
+    // arena is no longer in use
+    (void)hipFree(P->arena);
+    P->arena = nullptr;
+    P->arena_size = 0;
+  }
+}
+
+// After a call: free this call's overflow blocks and grow the arena to the
+// call's total, so that the next call of this size takes no allocation.
+static void finish_workspace(pdmk_plan* P, Workspace& ws) {
+  const bool grow = !ws.overflow.empty();
+  ws.release_overflow();
+  if (grow) {
+    if (P->arena) PDMK_HIP(hipFree(P->arena));
+    P->arena = nullptr;
+    P->arena_size = 0;
+    const size_t want = ws.used + ws.used / 8;
+    void* p = nullptr;
+    if (hipMalloc(&p, want) == hipSuccess) {
+      P->arena = static_cast<char*>(p);
+      P->arena_size = want;
+    } else {
+      (void)hipGetLastError();   // the next call allocates per request again
+    }
+  }
 }
 
 // ---------------------------------------------------------------- kernels
@@ -404,8 +432,13 @@ int pdmk_plan_eval(pdmk_plan* P, int64_t n_src, const double* src, const double*
   if ((n_src > 0 && (!src || !q)) || (n_trg > 0 && !pot) || (want_grad && n_trg > 0 && !grad))
     return fail(PDMK_ERR_INVALID_ARG, "null array");
   hipStream_t s = (hipStream_t)stream;
+  const auto wall0 = std::chrono::steady_clock::now();
+  Workspace ws;
+  ws.base = P->arena;
+  ws.size = P->arena_size;
   Eval E;
   E.s = s;
+  E.ws = &ws;
   E.n_src = n_src;
   E.n_trg = n_trg;
   E.self_targets = self_t;
@@ -467,16 +500,21 @@ int pdmk_plan_eval(pdmk_plan* P, int64_t n_src, const double* src, const double*
     E.st.n_src = n_src;
     E.st.n_trg = n_trg;
     E.st.n_images = E.n_img;
+    E.st.series_len = d == 3 ? P->kp.nE : P->kp.nF2;
     E.st.t_build_ms = t1;
     E.st.t_near_ms = t2;
     E.st.t_far_ms = t3;
     E.st.t_total_ms = t4;
     P->last = E.st;
-    dfree_all(E.allocs, s);
     PDMK_HIP(hipStreamSynchronize(s));
+    finish_workspace(P, ws);
+    P->last.workspace_bytes = (int64_t)ws.used;
+    P->last.t_call_ms =
+        std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - wall0)
+            .count();
   } catch (const Error& e) {
-    dfree_all(E.allocs, s);
     (void)hipStreamSynchronize(s);
+    ws.release_overflow();
     return fail(e.code, e.msg);
   }
   return PDMK_OK;

@@ -25,15 +25,42 @@ struct Error {
                           std::string(#call) + ": " + hipGetErrorString(e_)};   \
   } while (0)
 
-// Stream-ordered device allocation from the default memory pool.
-template <class T>
-T* dalloc(size_t n, hipStream_t s) {
-  void* p = nullptr;
-  if (n == 0) n = 1;
-  PDMK_HIP(hipMallocAsync(&p, n * sizeof(T), s));
-  return static_cast<T*>(p);
-}
-void dfree_all(std::vector<void*>& v, hipStream_t s);
+// Workspace of one evaluation: a bump allocator over the plan's arena (one
+// device buffer kept between calls).  Requests beyond the arena get their own
+// hipMalloc for this call; the plan then grows the arena to the call's total
+// so that later calls of the same size allocate nothing.
+struct Workspace {
+  char* base = nullptr;      // plan arena
+  size_t size = 0;           // arena bytes
+  size_t used = 0;           // bytes handed out this call (arena + overflow)
+  std::vector<void*> overflow;
+  void* take(size_t bytes) {
+    bytes = (bytes + 255) & ~(size_t)255;
+    if (bytes == 0) bytes = 256;
+    void* p = nullptr;
+    if (used + bytes <= size) {
+      p = base + used;
+    } else {
+      hipError_t e = hipMalloc(&p, bytes);
+      if (e != hipSuccess)
+        throw ::pdmk::Error{e == hipErrorOutOfMemory ? PDMK_ERR_OUT_OF_MEMORY : PDMK_ERR_HIP,
+                            std::string("hipMalloc: ") + hipGetErrorString(e)};
+      overflow.push_back(p);
+    }
+    used += bytes;
+    return p;
+  }
+  // Call after the stream has drained.
+  void release_overflow() {
+    for (void* p : overflow) (void)hipFree(p);
+    overflow.clear();
+  }
+};
+
+// Sources per work item of the leaf residual sums: a target leaf's source
+// list is cut into segments of this length, so that the cost of one block is
+// bounded by (targets of a leaf) x kDirectSeg pairs.
+constexpr int kDirectSeg = 2048;
 
 // ------------------------------------------------------- device constants
 // Everything a kernel needs about the method, passed by value.
@@ -74,12 +101,10 @@ struct Level {
 // Per-evaluation state.
 struct Eval {
   hipStream_t s = nullptr;
-  std::vector<void*> allocs;
+  Workspace* ws = nullptr;
   template <class T>
   T* alloc(size_t n) {
-    T* p = dalloc<T>(n, s);
-    allocs.push_back(p);
-    return p;
+    return static_cast<T*>(ws->take(n * sizeof(T)));
   }
   int64_t n_src = 0, n_trg = 0, n_img = 0;
   bool self_targets = true;
@@ -108,6 +133,9 @@ struct Eval {
   int* lf_list_beg = nullptr;
   int4* list = nullptr;     // {sbeg, send, level, 0}
   int64_t nlist = 0;
+  int* lf_nsrc = nullptr;   // sources in each target leaf's list
+  int2* items = nullptr;    // residual-sum work items (leaf, segment)
+  int nitems = 0;
   double* pot_sorted = nullptr;   // near field per sorted target
   double* grad_sorted = nullptr;
   double* far_pot = nullptr;      // far field per original target
@@ -125,6 +153,8 @@ struct pdmk_plan {
   const pdmk::SplitTables* T = nullptr;
   const pdmk::Pswf* P = nullptr;
   int device = 0;
+  char* arena = nullptr;        // device workspace kept between calls
+  size_t arena_size = 0;
   pdmk::KParams kp{};
   // device tables
   double* d_E = nullptr;
@@ -157,6 +187,6 @@ void plan_upload_tables(pdmk_plan* P);
 void far_build_scale(pdmk_plan* P);
 
 // scans (rocprim)
-void exclusive_scan_int(const int* in, int* out, int n, hipStream_t s, std::vector<void*>& allocs);
+void exclusive_scan_int(const int* in, int* out, int n, Eval& E);
 int read_int(const int* dptr, hipStream_t s);
 }  // namespace pdmk

@@ -112,10 +112,13 @@ template <class Real> struct Vec4Of;
 template <> struct Vec4Of<double> { using T = double4; };
 template <> struct Vec4Of<float> { using T = float4; };
 
-template <int D, int NE, class Real>
+// q_s R(|x - y_s|) (and its gradient) for one pair, with R_h of eq:pswf_split:
+// 3D 1/r - E(r^2/h^2)/h, 2D -log(r/h) + F2(r^2/h^2) (both without the 1/(4 pi),
+// 1/(2 pi) factors), zero outside the support r < h and for the pair r = 0.
+template <int D, int NE, bool GRAD, class Real>
 __device__ inline void residual_pair(const Real* x, const typename Vec4Of<Real>::T& sv, Real h2,
-                                     Real ih, const Real* ec, const Real* edc, bool want_grad,
-                                     Real& acc, Real* g) {
+                                     Real ih, const Real* ec, const Real* edc, Real& acc,
+                                     Real* g, int& nin) {
   Real dx[3];
   dx[0] = x[0] - sv.x;
   dx[1] = x[1] - sv.y;
@@ -123,7 +126,9 @@ __device__ inline void residual_pair(const Real* x, const typename Vec4Of<Real>:
   Real r2 = dx[0] * dx[0];
   r2 = fma(dx[1], dx[1], r2);
   if (D == 3) r2 = fma(dx[2], dx[2], r2);
-  if (r2 < h2 && r2 > (Real)0) {
+  const bool in = r2 < h2 && r2 > (Real)0;
+  nin += in ? 1 : 0;
+  if (in) {
     const Real s = r2 * ih * ih;
     const Real qs = sv.w;
     // Clenshaw recurrence for sum_k c_k T_k(2s - 1)
@@ -134,7 +139,7 @@ __device__ inline void residual_pair(const Real* x, const typename Vec4Of<Real>:
       const Real b0 = fma(t2, b1, ec[m] - b2);
       b2 = b1;
       b1 = b0;
-      if (want_grad) {
+      if (GRAD) {
         const Real e0 = fma(t2, d1, edc[m] - d2);
         d2 = d1;
         d1 = e0;
@@ -144,14 +149,14 @@ __device__ inline void residual_pair(const Real* x, const typename Vec4Of<Real>:
     if (D == 3) {
       const Real ir = rsqrt_r(r2);
       acc = fma(qs, ir - F * ih, acc);
-      if (want_grad) {
+      if (GRAD) {
         const Real Fd = fma((Real)0.5 * t2, d1, edc[0] - d2);
         const Real f = qs * (-ir * ir * ir - (Real)2 * Fd * ih * ih * ih);
         for (int a = 0; a < D; ++a) g[a] = fma(f, dx[a], g[a]);
       }
     } else {
       acc = fma(qs, (Real)-0.5 * log_r(s) + F, acc);
-      if (want_grad) {
+      if (GRAD) {
         const Real Fd = fma((Real)0.5 * t2, d1, edc[0] - d2);
         const Real f = qs * (-(Real)1 / r2 + (Real)2 * Fd * ih * ih);
         for (int a = 0; a < D; ++a) g[a] = fma(f, dx[a], g[a]);
@@ -160,30 +165,139 @@ __device__ inline void residual_pair(const Real* x, const typename Vec4Of<Real>:
   }
 }
 
-// Real = double: FP64 throughout.  Real = float: FP32 pair arithmetic on
-// offsets from the target leaf's centre (each formed in FP64, then rounded),
-// FP32 sums over one tile of 64 sources, FP64 across tiles.  Each LDS slot
-// holds (x, y, z, q) of one source and the support of its residual level.
-template <int D, int NE, class Real>
+// Cursor over the concatenated source list of one target leaf: each lane owns
+// one slot of the current 64-slot tile (entry ee, offset oo inside it).
+// Only positions before `end` (a segment boundary) are valid.
+struct ListCursor {
+  int ee, le, oo, rem;
+  int4 en;
+  __device__ void init(const int4* __restrict__ list, int lb, int le_, int slot, int end) {
+    ee = lb;
+    le = le_;
+    oo = slot;
+    rem = end - slot;
+    en = ee < le ? list[ee] : make_int4(0, 0, 0, 0);
+    walk(list);
+  }
+  __device__ void walk(const int4* __restrict__ list) {
+    while (ee < le && oo >= en.y - en.x) {
+      oo -= en.y - en.x;
+      ++ee;
+      if (ee < le) en = list[ee];
+    }
+  }
+  __device__ void advance(const int4* __restrict__ list) {
+    oo += 64;
+    rem -= 64;
+    walk(list);
+  }
+  __device__ bool valid() const { return ee < le && rem > 0; }
+};
+
+template <class Real>
+struct SourceSlot {
+  typename Vec4Of<Real>::T v;
+  Real h2, ih;
+  // Source offset from the target leaf centre (formed in FP64), charge and
+  // the support of its residual level; slots past the list end never
+  // interact (h^2 = 0).
+  __device__ void fetch(const ListCursor& c, const KParams& kp, const double* __restrict__ sx,
+                        const double* __restrict__ sq, int64_t nimg, const double* cT, int D) {
+    if (c.valid()) {
+      const int sidx = c.en.x + c.oo;
+      v.x = (Real)(sx[sidx] - cT[0]);
+      v.y = (Real)(sx[nimg + sidx] - cT[1]);
+      v.z = D == 3 ? (Real)(sx[2 * nimg + sidx] - cT[2]) : (Real)0;
+      v.w = (Real)sq[sidx];
+      const double hh = kp.rc / (double)(1 << c.en.z);
+      h2 = (Real)(hh * hh);
+      ih = (Real)(1.0 / hh);
+    } else {
+      v.x = v.y = v.z = (Real)1e30;
+      v.w = 0;
+      h2 = 0;
+      ih = 1;
+    }
+  }
+};
+
+// One pass of a leaf's residual sums: 64 / S targets starting at t0, S lanes
+// per target, over the whole source list in tiles of 64 staged in LDS.  The
+// next tile's sources are fetched into registers while the current one is
+// summed.
+template <int D, int NE, int S, bool GRAD, class Real>
+__device__ void direct_pass(const KParams& kp, const int4* __restrict__ list, int lb, int le,
+                            int pos0, int pos1, const double* __restrict__ sx,
+                            const double* __restrict__ sq,
+                            int64_t nimg, const double* cT, const Real* x, const Real* ec,
+                            const Real* edc, typename Vec4Of<Real>::T* shv, Real* shh2,
+                            Real* shih, double& acc, double* g, int& nin) {
+  const int lane = threadIdx.x;
+  const int slice = lane % S;
+  ListCursor cur;
+  cur.init(list, lb, le, pos0 + lane, pos1);
+  SourceSlot<Real> nxt;
+  nxt.fetch(cur, kp, sx, sq, nimg, cT, D);
+  // the tile exists while the first lane's slot is in the list
+  while (__shfl(cur.valid() ? 1 : 0, 0)) {
+    __syncthreads();
+    shv[lane] = nxt.v;
+    shh2[lane] = nxt.h2;
+    shih[lane] = nxt.ih;
+    __syncthreads();
+    cur.advance(list);
+    nxt.fetch(cur, kp, sx, sq, nimg, cT, D);
+    Real ta = 0, tb = 0, ga[3] = {0, 0, 0}, gb[3] = {0, 0, 0};
+#pragma unroll 2
+    for (int k = slice; k < 64; k += 2 * S) {
+      residual_pair<D, NE, GRAD, Real>(x, shv[k], shh2[k], shih[k], ec, edc, ta, ga, nin);
+      residual_pair<D, NE, GRAD, Real>(x, shv[k + S], shh2[k + S], shih[k + S], ec, edc, tb,
+                                       gb, nin);
+    }
+    acc += (double)ta + (double)tb;
+    if (GRAD)
+      for (int a = 0; a < D; ++a) g[a] += (double)ga[a] + (double)gb[a];
+  }
+#pragma unroll
+  for (int m = 1; m < S; m <<= 1) {
+    acc += __shfl_xor(acc, m);
+    if (GRAD)
+      for (int a = 0; a < D; ++a) g[a] += __shfl_xor(g[a], m);
+  }
+}
+
+// Leaf residual sums (the R part of the near field; interaction rule in
+// k_leaf_lists).  One 64-lane block per work item = (target leaf, segment of
+// kDirectSeg sources of its list); leaves in decreasing order of work.  The
+// segments of a leaf add into the zeroed outputs with FP64 atomics; the first
+// one also removes the self term.  Real = double: FP64 throughout.  Real =
+// float: FP32 pair arithmetic on offsets from the target leaf's centre (each
+// formed in FP64, then rounded), FP32 sums over one tile of 64 sources, FP64
+// across tiles.
+template <int D, int NE, bool GRAD, class Real>
 __global__ __launch_bounds__(64) void k_direct(
-    KParams kp, int nleaf, const Level* __restrict__ lev, const int* __restrict__ lf_level,
+    KParams kp, int nitems, const int2* __restrict__ items, const int* __restrict__ lf_nsrc,
+    const Level* __restrict__ lev, const int* __restrict__ lf_level,
     const int* __restrict__ lf_box, const int* __restrict__ lbeg, const int4* __restrict__ list,
     const double* __restrict__ sx, const double* __restrict__ sq, int64_t nimg,
     const double* __restrict__ tx, int64_t ntrg, const int* __restrict__ tperm,
     const double* __restrict__ qorig, int self_targets, const double* __restrict__ Ec,
     const double* __restrict__ Edc, double* __restrict__ pot, double* __restrict__ grad,
-    int want_grad) {
+    unsigned long long* __restrict__ n_support) {
   using V4 = typename Vec4Of<Real>::T;
   __shared__ V4 shv[64];
   __shared__ Real shh2[64], shih[64];
-  const int i = blockIdx.x;
-  if (i >= nleaf) return;
-  // series coefficients (zero-padded to NE) held in registers
+  if ((int)blockIdx.x >= nitems) return;
+  const int2 item = items[blockIdx.x];
+  const int i = item.x;
+  const int pos0 = item.y * kDirectSeg;
+  const int pos1 = min(lf_nsrc[i], pos0 + kDirectSeg);
+  // series coefficients (zero-padded to NE)
   Real ec[NE], edc[NE];
 #pragma unroll
   for (int k = 0; k < NE; ++k) {
     ec[k] = (Real)Ec[k];
-    edc[k] = (Real)Edc[k];
+    edc[k] = GRAD ? (Real)Edc[k] : (Real)0;
   }
   const int lane = threadIdx.x;
   const int lvl = lf_level[i], b = lf_box[i];
@@ -191,92 +305,59 @@ __global__ __launch_bounds__(64) void k_direct(
   const int tb = T.tbeg[b], te = T.tend[b];
   const int lb = lbeg[i], le = lbeg[i + 1];
   const double hT = kp.rc / (double)(1 << lvl);
-  double cT[D];
+  double cT[3] = {0, 0, 0};
   for (int a = 0; a < D; ++a) cT[a] = kp.origin[a] + (T.coord[b * D + a] + 0.5) * hT;
+  int nin = 0;
   for (int t0 = tb; t0 < te;) {
     // lanes per target for this pass, from the targets still to do
     const int rem = te - t0;
     const int S = rem > 32 ? 1 : (rem > 16 ? 2 : (rem > 8 ? 4 : 8));
-    const int tpb = 64 / S;
-    const int slice = lane % S, tslot = lane / S;
-    const int t = t0 + tslot;
+    const int t = t0 + lane / S;
     const bool valid = t < te;
     Real x[3] = {0, 0, 0};
     for (int a = 0; a < D; ++a) x[a] = valid ? (Real)(tx[a * ntrg + t] - cT[a]) : (Real)0;
-    double acc = 0.0, g[D];
-    for (int a = 0; a < D; ++a) g[a] = 0.0;
-    int e = lb, off = 0;
-    while (e < le) {
-      // this lane's slot of the tile: position off + lane along the list
-      int ee = e, oo = off + lane;
-      while (ee < le) {
-        const int len = list[ee].y - list[ee].x;
-        if (oo < len) break;
-        oo -= len;
-        ++ee;
-      }
-      __syncthreads();
-      if (ee < le) {
-        const int4 en = list[ee];
-        const int sidx = en.x + oo;
-        V4 v;
-        v.x = (Real)(sx[sidx] - cT[0]);
-        v.y = (Real)(sx[nimg + sidx] - cT[1]);
-        v.z = D == 3 ? (Real)(sx[2 * nimg + sidx] - cT[2]) : (Real)0;
-        v.w = (Real)sq[sidx];
-        shv[lane] = v;
-        const double hh = kp.rc / (double)(1 << en.z);
-        shh2[lane] = (Real)(hh * hh);
-        shih[lane] = (Real)(1.0 / hh);
-      } else {
-        V4 v;
-        v.x = v.y = v.z = (Real)1e30;
-        v.w = 0;
-        shv[lane] = v;
-        shh2[lane] = 0;
-        shih[lane] = 1;
-      }
-      __syncthreads();
-      // advance the (uniform) cursor by 64 slots
-      oo = off + 64;
-      while (e < le) {
-        const int len = list[e].y - list[e].x;
-        if (oo < len) break;
-        oo -= len;
-        ++e;
-      }
-      off = oo;
-      Real ta = 0, tbb = 0, tg[3] = {0, 0, 0}, tg2[3] = {0, 0, 0};
-      // two independent pair chains per iteration
-      for (int k = slice; k < 64; k += 2 * S) {
-        residual_pair<D, NE, Real>(x, shv[k], shh2[k], shih[k], ec, edc, want_grad, ta, tg);
-        const int k2 = k + S;
-        if (k2 < 64)
-          residual_pair<D, NE, Real>(x, shv[k2], shh2[k2], shih[k2], ec, edc, want_grad, tbb,
-                                     tg2);
-      }
-      acc += (double)ta + (double)tbb;
-      if (want_grad)
-        for (int a = 0; a < D; ++a) g[a] += (double)tg[a] + (double)tg2[a];
+    double acc = 0.0, g[3] = {0, 0, 0};
+    // lanes of targets past the end still take part in staging but do no pairs
+    int nin_p = 0;
+    switch (S) {
+      case 1:
+        direct_pass<D, NE, 1, GRAD, Real>(kp, list, lb, le, pos0, pos1, sx, sq, nimg, cT, x,
+                                          ec, edc, shv,
+                                          shh2, shih, acc, g, nin_p);
+        break;
+      case 2:
+        direct_pass<D, NE, 2, GRAD, Real>(kp, list, lb, le, pos0, pos1, sx, sq, nimg, cT, x,
+                                          ec, edc, shv,
+                                          shh2, shih, acc, g, nin_p);
+        break;
+      case 4:
+        direct_pass<D, NE, 4, GRAD, Real>(kp, list, lb, le, pos0, pos1, sx, sq, nimg, cT, x,
+                                          ec, edc, shv,
+                                          shh2, shih, acc, g, nin_p);
+        break;
+      default:
+        direct_pass<D, NE, 8, GRAD, Real>(kp, list, lb, le, pos0, pos1, sx, sq, nimg, cT, x,
+                                          ec, edc, shv,
+                                          shh2, shih, acc, g, nin_p);
+        break;
     }
-    for (int m = 1; m < S; m <<= 1) {
-      acc += __shfl_xor(acc, m);
-      if (want_grad)
-        for (int a = 0; a < D; ++a) g[a] += __shfl_xor(g[a], m);
-    }
-    if (valid && slice == 0) {
+    if (valid) nin += nin_p;
+    if (valid && lane % S == 0) {
       const double cst = D == 3 ? kInv4Pi : kInv2Pi;
       double v = acc * cst;
-      if (self_targets) {
+      if (self_targets && item.y == 0) {
         const double w0 = D == 3 ? kp.w0unit / hT : kp.w0unit - log(hT) * kInv2Pi;
         v -= qorig[tperm[t]] * w0;
       }
-      pot[t] = v;
-      if (want_grad)
-        for (int a = 0; a < D; ++a) grad[(int64_t)t * D + a] = g[a] * cst;
+      atomicAdd(&pot[t], v);
+      if (GRAD)
+        for (int a = 0; a < D; ++a) atomicAdd(&grad[(int64_t)t * D + a], g[a] * cst);
     }
-    t0 += tpb;
+    t0 += 64 / S;
   }
+  // pairs inside the support (statistics): one atomic per block
+  for (int m = 1; m < 64; m <<= 1) nin += __shfl_xor(nin, m);
+  if (lane == 0 && n_support) atomicAdd(n_support, (unsigned long long)nin);
 }
 
 // ------------------------------------------------------ source -> proxy charge
@@ -879,31 +960,38 @@ __global__ __launch_bounds__(NT) void k_eval_children(
 
 template <int D, int NE, class Real>
 static void launch_direct_t(const KParams& kp, Eval& E, pdmk_plan* P, hipStream_t s,
-                            bool want_grad) {
+                            bool want_grad, unsigned long long* nsup) {
   const double* c = D == 3 ? P->d_E : P->d_F2;
   const double* cd = D == 3 ? P->d_Ed : P->d_F2d;
-  hipLaunchKernelGGL((k_direct<D, NE, Real>), dim3(E.nleaf_t), dim3(64), 0, s, kp, E.nleaf_t,
-                     E.d_lev, E.lf_level, E.lf_box, E.lf_list_beg, E.list, E.sx, E.sq, E.n_img,
-                     E.tx, E.n_trg, E.tperm, E.q, E.self_targets ? 1 : 0, c, cd, E.pot_sorted,
-                     E.grad_sorted, want_grad ? 1 : 0);
+  if (want_grad)
+    hipLaunchKernelGGL((k_direct<D, NE, true, Real>), dim3(E.nitems), dim3(64), 0, s, kp,
+                       E.nitems, E.items, E.lf_nsrc, E.d_lev, E.lf_level, E.lf_box, E.lf_list_beg, E.list, E.sx,
+                       E.sq, E.n_img, E.tx, E.n_trg, E.tperm, E.q, E.self_targets ? 1 : 0, c, cd,
+                       E.pot_sorted, E.grad_sorted, nsup);
+  else
+    hipLaunchKernelGGL((k_direct<D, NE, false, Real>), dim3(E.nitems), dim3(64), 0, s, kp,
+                       E.nitems, E.items, E.lf_nsrc, E.d_lev, E.lf_level, E.lf_box, E.lf_list_beg, E.list, E.sx,
+                       E.sq, E.n_img, E.tx, E.n_trg, E.tperm, E.q, E.self_targets ? 1 : 0, c, cd,
+                       E.pot_sorted, E.grad_sorted, nsup);
 }
 
 template <int D, class Real>
 static void launch_direct_r(const KParams& kp, Eval& E, pdmk_plan* P, hipStream_t s,
-                            bool want_grad) {
-  const int nc = std::max(D == 3 ? kp.nE : kp.nF2, D == 3 ? kp.nEd : kp.nF2d);
-  if (nc <= 12) launch_direct_t<D, 12, Real>(kp, E, P, s, want_grad);
-  else if (nc <= 16) launch_direct_t<D, 16, Real>(kp, E, P, s, want_grad);
-  else if (nc <= 20) launch_direct_t<D, 20, Real>(kp, E, P, s, want_grad);
-  else if (nc <= 24) launch_direct_t<D, 24, Real>(kp, E, P, s, want_grad);
-  else launch_direct_t<D, 32, Real>(kp, E, P, s, want_grad);
+                            bool want_grad, unsigned long long* nsup) {
+  const int nc = want_grad ? std::max(D == 3 ? kp.nE : kp.nF2, D == 3 ? kp.nEd : kp.nF2d)
+                           : (D == 3 ? kp.nE : kp.nF2);
+  if (nc <= 12) launch_direct_t<D, 12, Real>(kp, E, P, s, want_grad, nsup);
+  else if (nc <= 16) launch_direct_t<D, 16, Real>(kp, E, P, s, want_grad, nsup);
+  else if (nc <= 20) launch_direct_t<D, 20, Real>(kp, E, P, s, want_grad, nsup);
+  else if (nc <= 24) launch_direct_t<D, 24, Real>(kp, E, P, s, want_grad, nsup);
+  else launch_direct_t<D, 32, Real>(kp, E, P, s, want_grad, nsup);
 }
 
 template <int D>
 static void launch_direct(const KParams& kp, Eval& E, pdmk_plan* P, hipStream_t s,
-                          bool want_grad) {
-  if (kp.precision == PDMK_PREC_MIXED) launch_direct_r<D, float>(kp, E, P, s, want_grad);
-  else launch_direct_r<D, double>(kp, E, P, s, want_grad);
+                          bool want_grad, unsigned long long* nsup) {
+  if (kp.precision == PDMK_PREC_MIXED) launch_direct_r<D, float>(kp, E, P, s, want_grad, nsup);
+  else launch_direct_r<D, double>(kp, E, P, s, want_grad, nsup);
 }
 
 template <int D, class Real>
@@ -1018,9 +1106,14 @@ static void near_impl(pdmk_plan* P, Eval& E, bool want_grad) {
   PDMK_HIP(hipEventCreate(&e1));
   PDMK_HIP(hipEventCreate(&e2));
   PDMK_HIP(hipEventCreate(&e3));
+  unsigned long long* nsup = E.alloc<unsigned long long>(1);
+  PDMK_HIP(hipMemsetAsync(nsup, 0, sizeof(unsigned long long), s));
+  PDMK_HIP(hipMemsetAsync(E.pot_sorted, 0, sizeof(double) * E.n_trg, s));
+  if (want_grad)
+    PDMK_HIP(hipMemsetAsync(E.grad_sorted, 0, sizeof(double) * E.n_trg * D, s));
   PDMK_HIP(hipEventRecord(e0, s));
-  // residual sums (write pot_sorted)
-  if (E.nleaf_t > 0) launch_direct<D>(kp, E, P, s, want_grad);
+  // residual sums (add into the zeroed pot_sorted)
+  if (E.nitems > 0) launch_direct<D>(kp, E, P, s, want_grad, nsup);
   PDMK_HIP(hipEventRecord(e1, s));
   // proxies
   int maxnl = 0;
@@ -1122,6 +1215,12 @@ static void near_impl(pdmk_plan* P, Eval& E, bool want_grad) {
     PDMK_HIP(hipMemcpyAsync(&np, npairs, sizeof(np), hipMemcpyDeviceToHost, s));
     PDMK_HIP(hipStreamSynchronize(s));
     E.st.n_pw_pairs = (int64_t)np;
+  }
+  {
+    unsigned long long ns = 0;
+    PDMK_HIP(hipMemcpyAsync(&ns, nsup, sizeof(ns), hipMemcpyDeviceToHost, s));
+    PDMK_HIP(hipStreamSynchronize(s));
+    E.st.n_support_pairs = (int64_t)ns;
   }
   PDMK_HIP(hipEventRecord(e2, s));
   // leaf targets evaluate their parent's proxy potential

@@ -15,21 +15,14 @@
 
 namespace pdmk {
 
-void dfree_all(std::vector<void*>& v, hipStream_t s) {
-  for (void* p : v) (void)hipFreeAsync(p, s);
-  v.clear();
-}
-
-void exclusive_scan_int(const int* in, int* out, int n, hipStream_t s,
-                        std::vector<void*>& allocs) {
+void exclusive_scan_int(const int* in, int* out, int n, Eval& E) {
   if (n <= 0) return;
   size_t tb = 0;
   PDMK_HIP(rocprim::exclusive_scan(nullptr, tb, in, out, 0, (size_t)n,
-                                   rocprim::plus<int>(), s));
-  void* tmp = dalloc<char>(tb, s);
-  allocs.push_back(tmp);
+                                   rocprim::plus<int>(), E.s));
+  void* tmp = E.alloc<char>(tb);
   PDMK_HIP(rocprim::exclusive_scan(tmp, tb, in, out, 0, (size_t)n,
-                                   rocprim::plus<int>(), s));
+                                   rocprim::plus<int>(), E.s));
 }
 
 int read_int(const int* dptr, hipStream_t s) {
@@ -230,7 +223,7 @@ void stage_images(pdmk_plan* P, Eval& E, const double* q) {
   if (n > 0)
     hipLaunchKernelGGL(k_img_count, dim3(nblk(n, 256)), dim3(256), 0, E.s, kp, n, E.xs,
                        P->d_shiftvec, P->nshift, cnt);
-  exclusive_scan_int(cnt, off, (int)(n + 1), E.s, E.allocs);
+  exclusive_scan_int(cnt, off, (int)(n + 1), E);
   E.n_img = read_int(off + n, E.s);
   double* xi = E.alloc<double>(E.n_img * kp.dim);
   double* qi = E.alloc<double>(E.n_img);
@@ -416,7 +409,7 @@ void stage_tree(pdmk_plan* P, Eval& E) {
     int* off = E.alloc<int>(Lp.n + 1);
     hipLaunchKernelGGL(k_split_flags, dim3(nblk(Lp.n + 1, 256)), dim3(256), 0, E.s, Lp, l,
                        P->mp.n_s, maxlev, flag);
-    exclusive_scan_int(flag, off, Lp.n + 1, E.s, E.allocs);
+    exclusive_scan_int(flag, off, Lp.n + 1, E);
     int nsplit = read_int(off + Lp.n, E.s);
     Lp.nnl = nsplit;
     Lp.nl_box = E.alloc<int>(nsplit);
@@ -467,7 +460,8 @@ __global__ void k_collect_leaves(Level L, int lvl, int* __restrict__ counter,
 __global__ void k_leaf_lists(int d, int nleaf, const Level* __restrict__ lev,
                              const int* __restrict__ lf_level, const int* __restrict__ lf_box,
                              int* __restrict__ cnt, const int* __restrict__ beg,
-                             int4* __restrict__ list, unsigned long long* __restrict__ pairs) {
+                             int4* __restrict__ list, unsigned long long* __restrict__ pairs,
+                             unsigned* __restrict__ work_key, int* __restrict__ nsrc) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= nleaf) return;
   const int ncoll = d == 3 ? 27 : 9;
@@ -500,9 +494,46 @@ __global__ void k_leaf_lists(int d, int nleaf, const Level* __restrict__ lev,
     a = A.parent[a];
   }
   if (cnt) {
+    const long long nt = T.tend[b] - T.tbeg[b];
     cnt[i] = k;
-    atomicAdd(pairs, (unsigned long long)(np * (long long)(T.tend[b] - T.tbeg[b])));
+    nsrc[i] = (int)np;
+    atomicAdd(pairs, (unsigned long long)(np * nt));
+    // residual-sum cost of the leaf (targets are processed at least 8 at a
+    // time); the key sorts the heaviest leaves first
+    const long long w = (((nt + 7) / 8) * 8 * np) >> 6;
+    work_key[i] = 0xffffffffu - (unsigned)(w < 0xfffffffell ? w : 0xfffffffell);
   }
+}
+
+__global__ void k_iota(int n, int* __restrict__ out) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = i;
+}
+
+__global__ void k_permute_leaves(int n, const int* __restrict__ perm, const int* __restrict__ a,
+                                 const int* __restrict__ b, const int* __restrict__ c,
+                                 const int* __restrict__ e, int* __restrict__ a2,
+                                 int* __restrict__ b2, int* __restrict__ c2, int* __restrict__ e2) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int j = perm[i];
+  a2[i] = a[j];
+  b2[i] = b[j];
+  c2[i] = c[j];
+  e2[i] = e[j];
+}
+
+// Work items of the residual sums: leaf i's concatenated source list is cut
+// into segments of kDirectSeg sources; item = (leaf, segment).
+__global__ void k_seg_count(int n, const int* __restrict__ nsrc, int* __restrict__ segs) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) segs[i] = (nsrc[i] + kDirectSeg - 1) / kDirectSeg;
+}
+
+__global__ void k_seg_fill(int n, const int* __restrict__ beg, int2* __restrict__ items) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  for (int k = beg[i]; k < beg[i + 1]; ++k) items[k] = make_int2(i, k - beg[i]);
 }
 
 void stage_lists(pdmk_plan* P, Eval& E) {
@@ -523,16 +554,50 @@ void stage_lists(pdmk_plan* P, Eval& E) {
   unsigned long long* pairs = E.alloc<unsigned long long>(1);
   PDMK_HIP(hipMemsetAsync(pairs, 0, sizeof(unsigned long long), E.s));
   PDMK_HIP(hipMemsetAsync(cnt + n, 0, sizeof(int), E.s));
-  if (n > 0)
+  if (n > 0) {
+    unsigned* key = E.alloc<unsigned>(n);
+    unsigned* key2 = E.alloc<unsigned>(n);
+    int* idx = E.alloc<int>(n);
+    int* perm = E.alloc<int>(n);
+    int* nsrc = E.alloc<int>(n);
     hipLaunchKernelGGL(k_leaf_lists, dim3(nblk(n, 128)), dim3(128), 0, E.s, d, n, E.d_lev,
-                       E.lf_level, E.lf_box, cnt, (const int*)nullptr, (int4*)nullptr, pairs);
-  exclusive_scan_int(cnt, E.lf_list_beg, n + 1, E.s, E.allocs);
+                       E.lf_level, E.lf_box, cnt, (const int*)nullptr, (int4*)nullptr, pairs,
+                       key, nsrc);
+    // launch order of the residual sums: heaviest leaf first, so that the
+    // long blocks do not form the tail of the grid
+    hipLaunchKernelGGL(k_iota, dim3(nblk(n, 256)), dim3(256), 0, E.s, n, idx);
+    size_t tb = 0;
+    PDMK_HIP(rocprim::radix_sort_pairs(nullptr, tb, key, key2, idx, perm, (size_t)n, 0u, 32u,
+                                       E.s));
+    void* tmp = E.alloc<char>(tb);
+    PDMK_HIP(rocprim::radix_sort_pairs(tmp, tb, key, key2, idx, perm, (size_t)n, 0u, 32u, E.s));
+    int* lv2 = E.alloc<int>(n);
+    int* bx2 = E.alloc<int>(n);
+    int* cn2 = E.alloc<int>(n + 1);
+    E.lf_nsrc = E.alloc<int>(n);
+    PDMK_HIP(hipMemsetAsync(cn2 + n, 0, sizeof(int), E.s));
+    hipLaunchKernelGGL(k_permute_leaves, dim3(nblk(n, 256)), dim3(256), 0, E.s, n, perm,
+                       E.lf_level, E.lf_box, cnt, nsrc, lv2, bx2, cn2, E.lf_nsrc);
+    E.lf_level = lv2;
+    E.lf_box = bx2;
+    cnt = cn2;
+    // segments of the source lists (each leaf has at least its own sources)
+    int* segs = E.alloc<int>(n + 1);
+    int* sbeg = E.alloc<int>(n + 1);
+    PDMK_HIP(hipMemsetAsync(segs + n, 0, sizeof(int), E.s));
+    hipLaunchKernelGGL(k_seg_count, dim3(nblk(n, 256)), dim3(256), 0, E.s, n, E.lf_nsrc, segs);
+    exclusive_scan_int(segs, sbeg, n + 1, E);
+    E.nitems = read_int(sbeg + n, E.s);
+    E.items = E.alloc<int2>(E.nitems);
+    hipLaunchKernelGGL(k_seg_fill, dim3(nblk(n, 256)), dim3(256), 0, E.s, n, sbeg, E.items);
+  }
+  exclusive_scan_int(cnt, E.lf_list_beg, n + 1, E);
   E.nlist = read_int(E.lf_list_beg + n, E.s);
   E.list = E.alloc<int4>(E.nlist);
   if (n > 0)
     hipLaunchKernelGGL(k_leaf_lists, dim3(nblk(n, 128)), dim3(128), 0, E.s, d, n, E.d_lev,
                        E.lf_level, E.lf_box, (int*)nullptr, E.lf_list_beg, E.list,
-                       (unsigned long long*)nullptr);
+                       (unsigned long long*)nullptr, (unsigned*)nullptr, (int*)nullptr);
   unsigned long long np = 0;
   PDMK_HIP(hipMemcpyAsync(&np, pairs, sizeof(np), hipMemcpyDeviceToHost, E.s));
   PDMK_HIP(hipStreamSynchronize(E.s));

@@ -63,7 +63,9 @@ class Stats(ctypes.Structure):
                 ("n_pw_pairs", ctypes.c_int64), ("t_build_ms", ctypes.c_double),
                 ("t_near_ms", ctypes.c_double), ("t_far_ms", ctypes.c_double),
                 ("t_total_ms", ctypes.c_double), ("t_direct_ms", ctypes.c_double),
-                ("t_pw_ms", ctypes.c_double), ("t_proxy_ms", ctypes.c_double)]
+                ("t_pw_ms", ctypes.c_double), ("t_proxy_ms", ctypes.c_double),
+                ("n_support_pairs", ctypes.c_int64), ("series_len", ctypes.c_int),
+                ("t_call_ms", ctypes.c_double), ("workspace_bytes", ctypes.c_int64)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
