@@ -59,8 +59,10 @@ struct Workspace {
 
 // Sources per work item of the leaf residual sums: a target leaf's source
 // list is cut into segments of this length, so that the cost of one block is
-// bounded by (targets of a leaf) x kDirectSeg pairs.
+// bounded by kDirectTgt x kDirectSeg pairs.
 constexpr int kDirectSeg = 2048;
+// Targets per work item of the leaf residual sums (one 64-lane pass).
+constexpr int kDirectTgt = 64;
 
 // ------------------------------------------------------- device constants
 // Everything a kernel needs about the method, passed by value.

@@ -267,8 +267,9 @@ __device__ void direct_pass(const KParams& kp, const int4* __restrict__ list, in
 }
 
 // Leaf residual sums (the R part of the near field; interaction rule in
-// k_leaf_lists).  One 64-lane block per work item = (target leaf, segment of
-// kDirectSeg sources of its list); leaves in decreasing order of work.  The
+// k_leaf_lists).  One 64-lane block per work item = (target leaf, chunk of
+// kDirectTgt targets, segment of kDirectSeg sources of its list), in
+// decreasing order of cost.  The
 // segments of a leaf add into the zeroed outputs with FP64 atomics; the first
 // one also removes the self term.  Real = double: FP64 throughout.  Real =
 // float: FP32 pair arithmetic on offsets from the target leaf's centre (each
@@ -290,8 +291,11 @@ __global__ __launch_bounds__(64) void k_direct(
   if ((int)blockIdx.x >= nitems) return;
   const int2 item = items[blockIdx.x];
   const int i = item.x;
-  const int pos0 = item.y * kDirectSeg;
-  const int pos1 = min(lf_nsrc[i], pos0 + kDirectSeg);
+  const int nsrc = lf_nsrc[i];
+  const int nseg = (nsrc + kDirectSeg - 1) / kDirectSeg;
+  const int seg = item.y % nseg, tchunk = item.y / nseg;
+  const int pos0 = seg * kDirectSeg;
+  const int pos1 = min(nsrc, pos0 + kDirectSeg);
   // series coefficients (zero-padded to NE)
   Real ec[NE], edc[NE];
 #pragma unroll
@@ -302,7 +306,8 @@ __global__ __launch_bounds__(64) void k_direct(
   const int lane = threadIdx.x;
   const int lvl = lf_level[i], b = lf_box[i];
   const Level& T = lev[lvl];
-  const int tb = T.tbeg[b], te = T.tend[b];
+  const int tb = T.tbeg[b] + tchunk * kDirectTgt;
+  const int te = min(T.tend[b], tb + kDirectTgt);
   const int lb = lbeg[i], le = lbeg[i + 1];
   const double hT = kp.rc / (double)(1 << lvl);
   double cT[3] = {0, 0, 0};
@@ -345,7 +350,7 @@ __global__ __launch_bounds__(64) void k_direct(
     if (valid && lane % S == 0) {
       const double cst = D == 3 ? kInv4Pi : kInv2Pi;
       double v = acc * cst;
-      if (self_targets && item.y == 0) {
+      if (self_targets && seg == 0) {
         const double w0 = D == 3 ? kp.w0unit / hT : kp.w0unit - log(hT) * kInv2Pi;
         v -= qorig[tperm[t]] * w0;
       }
@@ -969,7 +974,8 @@ static void launch_direct_t(const KParams& kp, Eval& E, pdmk_plan* P, hipStream_
                        E.sq, E.n_img, E.tx, E.n_trg, E.tperm, E.q, E.self_targets ? 1 : 0, c, cd,
                        E.pot_sorted, E.grad_sorted, nsup);
   else
-    hipLaunchKernelGGL((k_direct<D, NE, false, Real>), dim3(E.nitems), dim3(64), 0, s, kp,
+    hipLaunchKernelGGL((k_direct<D, NE, false, Real>), dim3(E.nitems), dim3(64), 0, s,
+                       kp,
                        E.nitems, E.items, E.lf_nsrc, E.d_lev, E.lf_level, E.lf_box, E.lf_list_beg, E.list, E.sx,
                        E.sq, E.n_img, E.tx, E.n_trg, E.tperm, E.q, E.self_targets ? 1 : 0, c, cd,
                        E.pot_sorted, E.grad_sorted, nsup);

@@ -439,16 +439,20 @@ void stage_tree(pdmk_plan* P, Eval& E) {
 }
 
 // ------------------------------------------------------------------- lists
-// Target leaves: boxes without children that hold targets.
-__global__ void k_collect_leaves(Level L, int lvl, int* __restrict__ counter,
-                                 int* __restrict__ lf_level, int* __restrict__ lf_box) {
+// Target leaves: boxes without children that hold targets, collected in tree
+// order (level by level, boxes in key order) by flag + scan.
+__global__ void k_leaf_flag(Level L, int* __restrict__ flag) {
   int b = blockIdx.x * blockDim.x + threadIdx.x;
-  if (b >= L.n) return;
-  if (L.child0[b] < 0 && L.tend[b] > L.tbeg[b]) {
-    int k = atomicAdd(counter, 1);
-    lf_level[k] = lvl;
-    lf_box[k] = b;
-  }
+  if (b < L.n) flag[b] = (L.child0[b] < 0 && L.tend[b] > L.tbeg[b]) ? 1 : 0;
+}
+
+__global__ void k_leaf_scatter(Level L, int lvl, const int* __restrict__ flag,
+                               const int* __restrict__ pos, int* __restrict__ lf_level,
+                               int* __restrict__ lf_box) {
+  int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= L.n || !flag[b]) return;
+  lf_level[pos[b]] = lvl;
+  lf_box[pos[b]] = b;
 }
 
 // Residual interaction list of a target leaf T at level i (plane waves are
@@ -461,7 +465,7 @@ __global__ void k_leaf_lists(int d, int nleaf, const Level* __restrict__ lev,
                              const int* __restrict__ lf_level, const int* __restrict__ lf_box,
                              int* __restrict__ cnt, const int* __restrict__ beg,
                              int4* __restrict__ list, unsigned long long* __restrict__ pairs,
-                             unsigned* __restrict__ work_key, int* __restrict__ nsrc) {
+                             int* __restrict__ nsrc) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= nleaf) return;
   const int ncoll = d == 3 ? 27 : 9;
@@ -498,56 +502,73 @@ __global__ void k_leaf_lists(int d, int nleaf, const Level* __restrict__ lev,
     cnt[i] = k;
     nsrc[i] = (int)np;
     atomicAdd(pairs, (unsigned long long)(np * nt));
-    // residual-sum cost of the leaf (targets are processed at least 8 at a
-    // time); the key sorts the heaviest leaves first
-    const long long w = (((nt + 7) / 8) * 8 * np) >> 6;
-    work_key[i] = 0xffffffffu - (unsigned)(w < 0xfffffffell ? w : 0xfffffffell);
   }
 }
 
-__global__ void k_iota(int n, int* __restrict__ out) {
-  int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) out[i] = i;
-}
-
-__global__ void k_permute_leaves(int n, const int* __restrict__ perm, const int* __restrict__ a,
-                                 const int* __restrict__ b, const int* __restrict__ c,
-                                 const int* __restrict__ e, int* __restrict__ a2,
-                                 int* __restrict__ b2, int* __restrict__ c2, int* __restrict__ e2) {
+// Work items of the residual sums: leaf i's targets are cut into chunks of
+// kDirectTgt and its concatenated source list into segments of kDirectSeg
+// sources; item = (leaf, chunk * nseg + segment).
+__global__ void k_seg_count(int n, const Level* __restrict__ lev, const int* __restrict__ lf_level,
+                            const int* __restrict__ lf_box, const int* __restrict__ nsrc,
+                            int* __restrict__ segs) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  const int j = perm[i];
-  a2[i] = a[j];
-  b2[i] = b[j];
-  c2[i] = c[j];
-  e2[i] = e[j];
+  const Level& T = lev[lf_level[i]];
+  const int b = lf_box[i];
+  const int nt = T.tend[b] - T.tbeg[b];
+  segs[i] = ((nsrc[i] + kDirectSeg - 1) / kDirectSeg) * ((nt + kDirectTgt - 1) / kDirectTgt);
 }
 
-// Work items of the residual sums: leaf i's concatenated source list is cut
-// into segments of kDirectSeg sources; item = (leaf, segment).
-__global__ void k_seg_count(int n, const int* __restrict__ nsrc, int* __restrict__ segs) {
-  int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) segs[i] = (nsrc[i] + kDirectSeg - 1) / kDirectSeg;
-}
-
-__global__ void k_seg_fill(int n, const int* __restrict__ beg, int2* __restrict__ items) {
+// Also writes a sort key per item: larger cost (targets of the chunk, at
+// least 8, times sources of the segment) sorts first.
+__global__ void k_seg_fill(int n, const Level* __restrict__ lev, const int* __restrict__ lf_level,
+                           const int* __restrict__ lf_box, const int* __restrict__ nsrc,
+                           const int* __restrict__ beg, int2* __restrict__ items,
+                           unsigned* __restrict__ key) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  for (int k = beg[i]; k < beg[i + 1]; ++k) items[k] = make_int2(i, k - beg[i]);
+  const Level& T = lev[lf_level[i]];
+  const int b = lf_box[i];
+  const int nt = T.tend[b] - T.tbeg[b];
+  const int ns = nsrc[i];
+  const int nseg = (ns + kDirectSeg - 1) / kDirectSeg;
+  for (int k = beg[i]; k < beg[i + 1]; ++k) {
+    const int r = k - beg[i];
+    const int seg = r % nseg, tc = r / nseg;
+    const int ct = min(kDirectTgt, nt - tc * kDirectTgt);
+    const int cs = min(kDirectSeg, ns - seg * kDirectSeg);
+    items[k] = make_int2(i, r);
+    key[k] = 0xffffffffu - (unsigned)(max(ct, 8) * cs);
+  }
 }
 
 void stage_lists(pdmk_plan* P, Eval& E) {
   const int d = P->kp.dim;
   int total = 0;
   for (auto& L : E.lev) total += L.n;
-  int* counter = E.alloc<int>(1);
-  PDMK_HIP(hipMemsetAsync(counter, 0, sizeof(int), E.s));
   E.lf_level = E.alloc<int>(total);
   E.lf_box = E.alloc<int>(total);
-  for (size_t l = 0; l < E.lev.size(); ++l)
-    hipLaunchKernelGGL(k_collect_leaves, dim3(nblk(E.lev[l].n, 256)), dim3(256), 0, E.s,
-                       E.lev[l], (int)l, counter, E.lf_level, E.lf_box);
-  E.nleaf_t = read_int(counter, E.s);
+  {
+    int* flag = E.alloc<int>(total + 1);
+    int* pos = E.alloc<int>(total + 1);
+    PDMK_HIP(hipMemsetAsync(flag + total, 0, sizeof(int), E.s));
+    int off = 0;
+    for (size_t l = 0; l < E.lev.size(); ++l) {
+      if (E.lev[l].n > 0)
+        hipLaunchKernelGGL(k_leaf_flag, dim3(nblk(E.lev[l].n, 256)), dim3(256), 0, E.s,
+                           E.lev[l], flag + off);
+      off += E.lev[l].n;
+    }
+    exclusive_scan_int(flag, pos, total + 1, E);
+    off = 0;
+    for (size_t l = 0; l < E.lev.size(); ++l) {
+      if (E.lev[l].n > 0)
+        hipLaunchKernelGGL(k_leaf_scatter, dim3(nblk(E.lev[l].n, 256)), dim3(256), 0, E.s,
+                           E.lev[l], (int)l, flag + off, pos + off, E.lf_level, E.lf_box);
+      off += E.lev[l].n;
+    }
+    E.nleaf_t = read_int(pos + total, E.s);
+  }
   int n = E.nleaf_t;
   int* cnt = E.alloc<int>(n + 1);
   E.lf_list_beg = E.alloc<int>(n + 1);
@@ -555,41 +576,32 @@ void stage_lists(pdmk_plan* P, Eval& E) {
   PDMK_HIP(hipMemsetAsync(pairs, 0, sizeof(unsigned long long), E.s));
   PDMK_HIP(hipMemsetAsync(cnt + n, 0, sizeof(int), E.s));
   if (n > 0) {
-    unsigned* key = E.alloc<unsigned>(n);
-    unsigned* key2 = E.alloc<unsigned>(n);
-    int* idx = E.alloc<int>(n);
-    int* perm = E.alloc<int>(n);
-    int* nsrc = E.alloc<int>(n);
+    E.lf_nsrc = E.alloc<int>(n);
     hipLaunchKernelGGL(k_leaf_lists, dim3(nblk(n, 128)), dim3(128), 0, E.s, d, n, E.d_lev,
                        E.lf_level, E.lf_box, cnt, (const int*)nullptr, (int4*)nullptr, pairs,
-                       key, nsrc);
-    // launch order of the residual sums: heaviest leaf first, so that the
-    // long blocks do not form the tail of the grid
-    hipLaunchKernelGGL(k_iota, dim3(nblk(n, 256)), dim3(256), 0, E.s, n, idx);
-    size_t tb = 0;
-    PDMK_HIP(rocprim::radix_sort_pairs(nullptr, tb, key, key2, idx, perm, (size_t)n, 0u, 32u,
-                                       E.s));
-    void* tmp = E.alloc<char>(tb);
-    PDMK_HIP(rocprim::radix_sort_pairs(tmp, tb, key, key2, idx, perm, (size_t)n, 0u, 32u, E.s));
-    int* lv2 = E.alloc<int>(n);
-    int* bx2 = E.alloc<int>(n);
-    int* cn2 = E.alloc<int>(n + 1);
-    E.lf_nsrc = E.alloc<int>(n);
-    PDMK_HIP(hipMemsetAsync(cn2 + n, 0, sizeof(int), E.s));
-    hipLaunchKernelGGL(k_permute_leaves, dim3(nblk(n, 256)), dim3(256), 0, E.s, n, perm,
-                       E.lf_level, E.lf_box, cnt, nsrc, lv2, bx2, cn2, E.lf_nsrc);
-    E.lf_level = lv2;
-    E.lf_box = bx2;
-    cnt = cn2;
-    // segments of the source lists (each leaf has at least its own sources)
+                       E.lf_nsrc);
+    // work items of the residual sums: segments of each leaf's source list
     int* segs = E.alloc<int>(n + 1);
     int* sbeg = E.alloc<int>(n + 1);
     PDMK_HIP(hipMemsetAsync(segs + n, 0, sizeof(int), E.s));
-    hipLaunchKernelGGL(k_seg_count, dim3(nblk(n, 256)), dim3(256), 0, E.s, n, E.lf_nsrc, segs);
+    hipLaunchKernelGGL(k_seg_count, dim3(nblk(n, 256)), dim3(256), 0, E.s, n, E.d_lev, E.lf_level,
+                       E.lf_box, E.lf_nsrc, segs);
     exclusive_scan_int(segs, sbeg, n + 1, E);
     E.nitems = read_int(sbeg + n, E.s);
+    int2* items = E.alloc<int2>(E.nitems);
+    unsigned* key = E.alloc<unsigned>(E.nitems);
+    hipLaunchKernelGGL(k_seg_fill, dim3(nblk(n, 256)), dim3(256), 0, E.s, n, E.d_lev,
+                       E.lf_level, E.lf_box, E.lf_nsrc, sbeg, items, key);
+    // launch order: most expensive items first, so that no long block forms
+    // the tail of the grid
     E.items = E.alloc<int2>(E.nitems);
-    hipLaunchKernelGGL(k_seg_fill, dim3(nblk(n, 256)), dim3(256), 0, E.s, n, sbeg, E.items);
+    unsigned* key2 = E.alloc<unsigned>(E.nitems);
+    size_t tb = 0;
+    PDMK_HIP(rocprim::radix_sort_pairs(nullptr, tb, key, key2, items, E.items,
+                                       (size_t)E.nitems, 0u, 32u, E.s));
+    void* tmp = E.alloc<char>(tb);
+    PDMK_HIP(rocprim::radix_sort_pairs(tmp, tb, key, key2, items, E.items, (size_t)E.nitems, 0u,
+                                       32u, E.s));
   }
   exclusive_scan_int(cnt, E.lf_list_beg, n + 1, E);
   E.nlist = read_int(E.lf_list_beg + n, E.s);
@@ -597,7 +609,7 @@ void stage_lists(pdmk_plan* P, Eval& E) {
   if (n > 0)
     hipLaunchKernelGGL(k_leaf_lists, dim3(nblk(n, 128)), dim3(128), 0, E.s, d, n, E.d_lev,
                        E.lf_level, E.lf_box, (int*)nullptr, E.lf_list_beg, E.list,
-                       (unsigned long long*)nullptr, (unsigned*)nullptr, (int*)nullptr);
+                       (unsigned long long*)nullptr, (int*)nullptr);
   unsigned long long np = 0;
   PDMK_HIP(hipMemcpyAsync(&np, pairs, sizeof(np), hipMemcpyDeviceToHost, E.s));
   PDMK_HIP(hipStreamSynchronize(E.s));
