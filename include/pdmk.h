@@ -99,7 +99,8 @@ int pdmk_default_opts(int dim, double eps, pdmk_opts* out);
  * One evaluation (Algorithm 1).  Targets are the sources when trg == NULL
  * (then n_trg is ignored and the self pair of every source is excluded);
  * otherwise targets are n_trg separate points and no self pair is removed.
- * grad may be NULL; it is written only when PDMK_WANT_GRAD is set.
+ * grad may be NULL; when it is not NULL, grad Phi at the targets is written
+ * (PDMK_WANT_GRAD in the options requires it to be non-NULL).
  */
 int pdmk_eval(const pdmk_opts* opts, const double* L, int64_t n_src,
               const double* src, const double* q, int64_t n_trg,
@@ -121,6 +122,28 @@ int pdmk_plan_eval(pdmk_plan* plan, int64_t n_src, const double* src,
                    const double* q, int64_t n_trg, const double* trg,
                    double* pot, double* grad, void* stream);
 void pdmk_plan_destroy(pdmk_plan* plan);
+
+/*
+ * Adjoint of an evaluation, for a loss l(Phi) with g = dl/dPhi at the n_trg
+ * targets.  The Laplace kernel is symmetric, so the adjoint is one more
+ * evaluation with the roles of sources and targets swapped: with
+ * Psi(y) = sum_i g_i K(y - x_i) (the potential of the charges g at the targets,
+ * uniform background for sum g != 0, the same convention the evaluation uses
+ * for non-neutral charges; the method's split G - W_0 + W_0 is unchanged),
+ *     dq_j   = Psi(y_j)
+ *     dsrc_j = q_j grad Psi(y_j)   (+ g_j grad Phi(y_j) when targets are the sources)
+ *     dtrg_i = g_i grad Phi(x_i)   (separate targets only)
+ * Arguments: src, q, trg as in the evaluation (trg == NULL: targets are the
+ * sources); g: n_trg doubles; grad_phi: the gradient the forward evaluation
+ * returned (n_trg x d, row-major), required for dsrc with targets = sources and
+ * for dtrg; dq (n_src), dsrc (n_src x d), dtrg (n_trg x d): outputs, each may be
+ * NULL.  Device pointers; the plan keeps a device buffer of n_src (d + 1)
+ * doubles for Psi between calls.  Blocks until the outputs are written.
+ */
+int pdmk_plan_adjoint(pdmk_plan* plan, int64_t n_src, const double* src, const double* q,
+                      int64_t n_trg, const double* trg, const double* g,
+                      const double* grad_phi, double* dq, double* dsrc, double* dtrg,
+                      void* stream);
 
 /* Geometry and parameters a plan derived from (opts, L); host only. */
 typedef struct {

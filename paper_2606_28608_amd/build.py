@@ -17,7 +17,7 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libpdmk.so")
 
-SOURCES = ["planner.cpp", "tree.hip", "near.hip", "far.hip", "api.hip"]
+SOURCES = ["planner.cpp", "tree.hip", "near.hip", "pwmfma.hip", "far.hip", "api.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = os.environ.get("PDMK_ARCH", "gfx950")

@@ -2,6 +2,7 @@
 // assembly with the self-interaction correction (Section 3.8), status codes.
 #include <cmath>
 #include <chrono>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 
@@ -112,7 +113,8 @@ void plan_upload_tables(pdmk_plan* P) {
 
 static void free_plan_tables(pdmk_plan* P) {
   void* ptrs[] = {P->d_E, P->d_Ed, P->d_F2, P->d_F2d, P->d_nodes, P->d_bw, P->d_Tm,
-                  P->d_F, P->d_Ff, P->d_dtab, P->d_farscale, P->d_shiftvec};
+                  P->d_F, P->d_Ff, P->d_dtab, P->d_farscale, P->d_shiftvec, P->d_pwt_f,
+                  P->d_pwt_d, P->adj_buf};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   if (P->arena) {
@@ -193,15 +195,28 @@ __global__ void k_assemble(int64_t n, int d, const int* __restrict__ tperm,
   }
 }
 
-namespace pdmk {
-void stage_assemble(pdmk_plan* P, Eval& E, const double* q, double* pot, double* grad) {
-  (void)q;
-  (void)P;
-  (void)E;
-  (void)pot;
-  (void)grad;
+// Adjoint combination (targets = sources when gphi_self is set):
+//   dq_j = Psi(y_j),  dsrc_j = q_j grad Psi(y_j) [+ g_j grad Phi(y_j)],
+//   dtrg_i = g_i grad Phi(x_i)
+__global__ void k_adjoint_combine(int64_t ns, int64_t nt, int d, const double* __restrict__ q,
+                                  const double* __restrict__ g,
+                                  const double* __restrict__ gphi, int self_t,
+                                  const double* __restrict__ psi,
+                                  const double* __restrict__ gpsi, double* __restrict__ dq,
+                                  double* __restrict__ dsrc, double* __restrict__ dtrg) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < ns) {
+    if (dq) dq[i] = psi[i];
+    if (dsrc)
+      for (int a = 0; a < d; ++a) {
+        double v = q[i] * gpsi[i * d + a];
+        if (self_t) v = fma(g[i], gphi[i * d + a], v);
+        dsrc[i * d + a] = v;
+      }
+  }
+  if (dtrg && i < nt)
+    for (int a = 0; a < d; ++a) dtrg[i * d + a] = g[i] * gphi[i * d + a];
 }
-}  // namespace pdmk
 
 // ------------------------------------------------------------------- C ABI
 extern "C" {
@@ -342,6 +357,12 @@ int pdmk_plan_create(const pdmk_opts* opts, const double* L, pdmk_plan** out) {
     }
     kp.w0unit = P->T->w0_unit(d);
     plan_upload_tables(P);
+    if (d == 3) pw_mfma_upload(P);
+    {
+      // diagnostic switch: PDMK_NO_MFMA=1 selects the vector-ALU plane-wave kernels
+      const char* env = std::getenv("PDMK_NO_MFMA");
+      P->pw_mfma = !(env && env[0] == '1');
+    }
     far_build_scale(P);
   } catch (const Error& e) {
     free_plan_tables(P);
@@ -419,17 +440,22 @@ int pdmk_plan_stats(const pdmk_plan* P, pdmk_stats* out) {
   return PDMK_OK;
 }
 
-int pdmk_plan_eval(pdmk_plan* P, int64_t n_src, const double* src, const double* q,
-                   int64_t n_trg, const double* trg, double* pot, double* grad, void* stream) {
+}  // extern "C"
+
+// One evaluation; `flags` replaces the plan's flags (PDMK_ALLOW_NONNEUTRAL is
+// honoured, gradients are computed iff grad is not null).
+static int eval_impl(pdmk_plan* P, int64_t n_src, const double* src, const double* q,
+                     int64_t n_trg, const double* trg, double* pot, double* grad, void* stream,
+                     unsigned flags) {
   if (!P) return fail(PDMK_ERR_INVALID_ARG, "null plan");
   const int d = P->g.dim;
   const bool self_t = (trg == nullptr);
   if (self_t) n_trg = n_src;
-  const bool want_grad = (P->o.flags & PDMK_WANT_GRAD) != 0;
+  const bool want_grad = grad != nullptr;
   if (n_src < 0 || n_trg < 0) return fail(PDMK_ERR_INVALID_ARG, "negative count");
   if (n_src > (int64_t)1 << 30 || n_trg > (int64_t)1 << 30)
     return fail(PDMK_ERR_INVALID_ARG, "more than 2^30 points");
-  if ((n_src > 0 && (!src || !q)) || (n_trg > 0 && !pot) || (want_grad && n_trg > 0 && !grad))
+  if ((n_src > 0 && (!src || !q)) || (n_trg > 0 && !pot))
     return fail(PDMK_ERR_INVALID_ARG, "null array");
   hipStream_t s = (hipStream_t)stream;
   const auto wall0 = std::chrono::steady_clock::now();
@@ -470,7 +496,7 @@ int pdmk_plan_eval(pdmk_plan* P, int64_t n_src, const double* src, const double*
     PDMK_HIP(hipMemcpyAsync(&hbad, bad, sizeof(int), hipMemcpyDeviceToHost, s));
     PDMK_HIP(hipStreamSynchronize(s));
     if (hbad) throw Error{PDMK_ERR_NONFINITE, "non-finite charge"};
-    if (std::fabs(hq[0]) > 1e-8 * hq[1] && !(P->o.flags & PDMK_ALLOW_NONNEUTRAL))
+    if (std::fabs(hq[0]) > 1e-8 * hq[1] && !(flags & PDMK_ALLOW_NONNEUTRAL))
       throw Error{PDMK_ERR_NOT_NEUTRAL, "sum of charges is not zero"};
     stage_prepare(P, E, src, trg);
     stage_images(P, E, q);
@@ -515,6 +541,67 @@ int pdmk_plan_eval(pdmk_plan* P, int64_t n_src, const double* src, const double*
   } catch (const Error& e) {
     (void)hipStreamSynchronize(s);
     ws.release_overflow();
+    return fail(e.code, e.msg);
+  }
+  return PDMK_OK;
+}
+
+extern "C" {
+
+int pdmk_plan_eval(pdmk_plan* P, int64_t n_src, const double* src, const double* q,
+                   int64_t n_trg, const double* trg, double* pot, double* grad, void* stream) {
+  if (!P) return fail(PDMK_ERR_INVALID_ARG, "null plan");
+  if ((P->o.flags & PDMK_WANT_GRAD) && !grad && (trg ? n_trg : n_src) > 0)
+    return fail(PDMK_ERR_INVALID_ARG, "PDMK_WANT_GRAD set but grad is null");
+  return eval_impl(P, n_src, src, q, n_trg, trg, pot, grad, stream, P->o.flags);
+}
+
+int pdmk_plan_adjoint(pdmk_plan* P, int64_t n_src, const double* src, const double* q,
+                      int64_t n_trg, const double* trg, const double* g, const double* grad_phi,
+                      double* dq, double* dsrc, double* dtrg, void* stream) {
+  if (!P) return fail(PDMK_ERR_INVALID_ARG, "null plan");
+  const int d = P->g.dim;
+  const bool self_t = trg == nullptr;
+  if (self_t) n_trg = n_src;
+  if (n_src < 0 || n_trg < 0) return fail(PDMK_ERR_INVALID_ARG, "negative count");
+  if (n_src > 0 && !src) return fail(PDMK_ERR_INVALID_ARG, "null src");
+  if (n_trg > 0 && !g) return fail(PDMK_ERR_INVALID_ARG, "null g");
+  if (dsrc && n_src > 0 && !q) return fail(PDMK_ERR_INVALID_ARG, "dsrc needs q");
+  if (((dsrc && self_t) || (dtrg && !self_t)) && n_trg > 0 && !grad_phi)
+    return fail(PDMK_ERR_INVALID_ARG, "grad_phi is needed for the position adjoint");
+  if (dtrg && self_t) return fail(PDMK_ERR_INVALID_ARG, "dtrg needs separate targets");
+  hipStream_t s = (hipStream_t)stream;
+  try {
+    int cur = -1;
+    PDMK_HIP(hipGetDevice(&cur));
+    if (cur != P->device) throw Error{PDMK_ERR_INVALID_ARG, "plan bound to another device"};
+    // Psi and grad Psi at the sources: the potential of the charges g placed
+    // at the targets (the kernel is symmetric), uniform background allowed
+    const size_t need = (size_t)n_src * (d + 1);
+    if (need > P->adj_size) {
+      if (P->adj_buf) PDMK_HIP(hipFree(P->adj_buf));
+      P->adj_buf = nullptr;
+      P->adj_size = 0;
+      PDMK_HIP(hipMalloc((void**)&P->adj_buf, need * sizeof(double)));
+      P->adj_size = need;
+    }
+    double* psi = P->adj_buf;
+    double* gpsi = P->adj_buf + n_src;
+    if (n_src > 0) {
+      const int st = self_t ? eval_impl(P, n_src, src, g, 0, nullptr, psi, dsrc ? gpsi : nullptr,
+                                        stream, PDMK_ALLOW_NONNEUTRAL)
+                            : eval_impl(P, n_trg, trg, g, n_src, src, psi,
+                                        dsrc ? gpsi : nullptr, stream, PDMK_ALLOW_NONNEUTRAL);
+      if (st != PDMK_OK) return st;
+    }
+    const int64_t nmax = std::max(n_src, n_trg);
+    if (nmax > 0)
+      hipLaunchKernelGGL(k_adjoint_combine, dim3(nblk(nmax, 256)), dim3(256), 0, s, n_src,
+                         n_trg, d, q, g, grad_phi, self_t ? 1 : 0, psi, gpsi, dq, dsrc, dtrg);
+    PDMK_HIP(hipGetLastError());
+    PDMK_HIP(hipStreamSynchronize(s));
+  } catch (const Error& e) {
+    (void)hipStreamSynchronize(s);
     return fail(e.code, e.msg);
   }
   return PDMK_OK;

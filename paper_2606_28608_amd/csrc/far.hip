@@ -121,11 +121,8 @@ __device__ inline float es_win(float z, float beta) {
   return t >= 0.0f ? __expf(beta * (sqrtf(t) - 1.0f)) : 0.0f;
 }
 
-// Tiled spreading: a block takes 256 consecutive sources in tree order; their
-// windows cover a small box of grid cells, accumulated in an LDS subgrid with
-// LDS atomics and then added to the grid with one global atomic per touched
-// cell.  A block whose box exceeds the LDS subgrid (sources straddling the
-// periodic boundary) falls back to global atomics.
+// LDS subgrid (doubles) of the spreading and interpolation blocks: the
+// windows of 256 consecutive points in tree order cover a small box of cells.
 constexpr int kSubCap = 8192;
 
 template <int D>
@@ -140,86 +137,112 @@ __device__ inline void grid_coords(const KParams& kp, const double* __restrict__
   }
 }
 
-template <int D, class Real>
-__global__ __launch_bounds__(256) void k_spread_tiled(KParams kp, int64_t n,
-                                                      const double* __restrict__ x,
-                                                      const double* __restrict__ q, int M0,
-                                                      int M1, int M2, int w, double beta,
-                                                      double* __restrict__ grid) {
-  __shared__ double sub[kSubCap];
-  __shared__ int lo[3], hi[3];
-  const int Ms[3] = {M0, M1, M2};
-  const double hw = 0.5 * w;
-  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  const bool valid = i < n;
+// Bounding box of the block's 256 points in grid cells (window start i0 per
+// axis); returns the subgrid extent and whether it fits in LDS.
+template <int D, int W>
+__device__ inline bool block_box(const KParams& kp, int64_t n, const double* __restrict__ x,
+                                 int64_t i, bool valid, const int* Ms, double* g, int* i0,
+                                 int* lo_s, int* hi_s, int* lo, int* ext, int& vol) {
+  constexpr double hw = 0.5 * W;
   if (threadIdx.x < 3) {
-    lo[threadIdx.x] = INT_MAX;
-    hi[threadIdx.x] = INT_MIN;
+    lo_s[threadIdx.x] = INT_MAX;
+    hi_s[threadIdx.x] = INT_MIN;
   }
   __syncthreads();
-  double g[D];
-  int i0[D];
+  for (int a = 0; a < D; ++a) {
+    g[a] = 0;
+    i0[a] = 0;
+  }
   if (valid) {
     grid_coords<D>(kp, x, n, i, Ms, g);
     for (int a = 0; a < D; ++a) {
       i0[a] = (int)ceil(g[a] - hw);
-      atomicMin(&lo[a], i0[a]);
-      atomicMax(&hi[a], i0[a]);
+      atomicMin(&lo_s[a], i0[a]);
+      atomicMax(&hi_s[a], i0[a]);
     }
   }
   __syncthreads();
-  int ext[3] = {1, 1, 1};
-  long long vol = 1;
-  for (int a = 0; a < D; ++a) {
-    ext[a] = hi[a] - lo[a] + w;
-    vol *= ext[a];
+  long long v = 1;
+  for (int a = 0; a < 3; ++a) {
+    lo[a] = a < D ? lo_s[a] : 0;
+    ext[a] = a < D ? hi_s[a] - lo_s[a] + W : 1;
+    if (a < D) v *= ext[a];
   }
-  const bool tiled = vol <= kSubCap;
+  vol = v <= kSubCap ? (int)v : kSubCap + 1;
+  return v <= kSubCap;
+}
+
+__device__ inline int wrap_index(int i, int M) {
+  int r = i % M;
+  return r < 0 ? r + M : r;
+}
+
+// Spreading (step one of Section 3.6): the block takes 256 consecutive
+// sources in tree order and accumulates their windows in an LDS subgrid; each
+// wave spreads its 64 sources one at a time, the lanes covering the W^D
+// stencil entries (distinct addresses, so the LDS atomics do not collide).
+// The subgrid is then added to the grid with one global atomic per touched
+// cell.  A block whose box exceeds the LDS subgrid (sources straddling the
+// periodic boundary) spreads straight into the grid with global atomics.
+template <int D, int W, class Real>
+__global__ __launch_bounds__(256) void k_spread_coop(KParams kp, int64_t n,
+                                                     const double* __restrict__ x,
+                                                     const double* __restrict__ q, int M0,
+                                                     int M1, int M2, double beta,
+                                                     double* __restrict__ grid) {
+  __shared__ double sub[kSubCap];
+  __shared__ int lo_s[3], hi_s[3];
+  constexpr int NE = D == 3 ? W * W * W : W * W;
+  constexpr Real hw = (Real)(0.5 * W);
+  const int Ms[3] = {M0, M1, M2};
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const bool valid = i < n;
+  double g[D];
+  int i0[D], lo[3], ext[3], vol;
+  const bool tiled = block_box<D, W>(kp, n, x, i, valid, Ms, g, i0, lo_s, hi_s, lo, ext, vol);
   if (tiled) {
     for (int c = threadIdx.x; c < vol; c += 256) sub[c] = 0.0;
     __syncthreads();
   }
-  if (valid) {
-    const double qi = q[i];
-    double wt[D][16];
-    for (int a = 0; a < D; ++a)
-      for (int k = 0; k < w; ++k)
-        wt[a][k] = (double)es_win((Real)((i0[a] + k - g[a]) / hw), (Real)beta);
-    if (tiled) {
-      const int o0 = i0[0] - lo[0], o1 = i0[1] - lo[1], o2 = D == 3 ? i0[2] - lo[2] : 0;
-      if (D == 3) {
-        for (int k2 = 0; k2 < w; ++k2)
-          for (int k1 = 0; k1 < w; ++k1) {
-            const double w12 = qi * wt[1][k1] * wt[D - 1][k2];
-            double* row = sub + ((o2 + k2) * ext[1] + (o1 + k1)) * ext[0] + o0;
-            for (int k0 = 0; k0 < w; ++k0) atomicAdd(row + k0, w12 * wt[0][k0]);
-          }
-      } else {
-        for (int k1 = 0; k1 < w; ++k1) {
-          const double w1 = qi * wt[1][k1];
-          double* row = sub + (o1 + k1) * ext[0] + o0;
-          for (int k0 = 0; k0 < w; ++k0) atomicAdd(row + k0, w1 * wt[0][k0]);
-        }
-      }
-    } else {
-      int ix[D][16];
-      for (int a = 0; a < D; ++a)
-        for (int k = 0; k < w; ++k) {
-          int id = (i0[a] + k) % Ms[a];
-          ix[a][k] = id < 0 ? id + Ms[a] : id;
-        }
-      if (D == 3) {
-        for (int k2 = 0; k2 < w; ++k2)
-          for (int k1 = 0; k1 < w; ++k1) {
-            const double w12 = qi * wt[1][k1] * wt[D - 1][k2];
-            const int64_t row = (int64_t)M0 * (ix[1][k1] + (int64_t)M1 * ix[D - 1][k2]);
-            for (int k0 = 0; k0 < w; ++k0) atomicAdd(grid + row + ix[0][k0], w12 * wt[0][k0]);
-          }
-      } else {
-        for (int k1 = 0; k1 < w; ++k1) {
-          const double w1 = qi * wt[1][k1];
-          const int64_t row = (int64_t)M0 * ix[1][k1];
-          for (int k0 = 0; k0 < w; ++k0) atomicAdd(grid + row + ix[0][k0], w1 * wt[0][k0]);
+  const double qi = valid ? q[i] : 0.0;
+  const int lane = threadIdx.x & 63;
+  // lane l < D W holds the window value of axis l / W, offset l % W
+  const int wa = lane / W, wk = lane - wa * W;
+  for (int j = 0; j < 64; ++j) {
+    const double qj = __shfl(qi, j);
+    if (qj == 0.0) continue;   // also skips lanes past the end (uniform across the wave)
+    double gj[D];
+    int ij[D];
+    for (int a = 0; a < D; ++a) {
+      gj[a] = __shfl(g[a], j);
+      ij[a] = __shfl(i0[a], j);
+    }
+    Real wv = 0;
+    if (wa < D) {
+      const double ga = wa == 0 ? gj[0] : (wa == 1 ? gj[1] : gj[D - 1]);
+      const int ia = wa == 0 ? ij[0] : (wa == 1 ? ij[1] : ij[D - 1]);
+      wv = es_win((Real)((ia + wk - ga) / (double)hw), (Real)beta);
+      if (wa == 0) wv *= (Real)qj;
+    }
+#pragma unroll
+    for (int e0 = 0; e0 < NE; e0 += 64) {
+      const int e = e0 + lane;
+      const int k0 = e % W, k1 = (e / W) % W, k2 = D == 3 ? e / (W * W) : 0;
+      Real v = __shfl(wv, k0) * __shfl(wv, W + k1);
+      if (D == 3) v *= __shfl(wv, 2 * W + k2);
+      if (e < NE) {
+        if (tiled) {
+          const int o = ((ij[D - 1] - lo[D - 1] + (D == 3 ? k2 : k1)) *
+                             (D == 3 ? ext[1] : 1) +
+                         (D == 3 ? ij[1] - lo[1] + k1 : 0)) *
+                            ext[0] +
+                        ij[0] - lo[0] + k0;
+          atomicAdd(sub + o, (double)v);
+        } else {
+          int64_t gi = wrap_index(ij[0] + k0, M0) +
+                       (int64_t)M0 * wrap_index(ij[1] + k1, M1);
+          if (D == 3) gi += (int64_t)M0 * M1 * wrap_index(ij[D - 1] + k2, M2);
+          atomicAdd(grid + gi, (double)v);
         }
       }
     }
@@ -229,133 +252,155 @@ __global__ __launch_bounds__(256) void k_spread_tiled(KParams kp, int64_t n,
     for (int c = threadIdx.x; c < vol; c += 256) {
       const double v = sub[c];
       if (v == 0.0) continue;
-      int cc[3] = {c % ext[0], (c / ext[0]) % ext[1], c / (ext[0] * ext[1])};
-      int64_t gi = 0, mul = 1;
-      for (int a = 0; a < D; ++a) {
-        int id = (lo[a] + cc[a]) % Ms[a];
-        if (id < 0) id += Ms[a];
-        gi += id * mul;
-        mul *= Ms[a];
-      }
+      const int c0 = c % ext[0], c1 = (c / ext[0]) % ext[1], c2 = c / (ext[0] * ext[1]);
+      int64_t gi = wrap_index(lo[0] + c0, M0) + (int64_t)M0 * wrap_index(lo[1] + c1, M1);
+      if (D == 3) gi += (int64_t)M0 * M1 * wrap_index(lo[2] + c2, M2);
       atomicAdd(grid + gi, v);
     }
   }
 }
 
-// Tiled interpolation at targets in tree order: the block's subgrid is read
-// into LDS once; results are added to the near-field arrays (tree order).
-template <int D, class Real>
-__global__ __launch_bounds__(256) void k_interp_tiled(KParams kp, int64_t n,
-                                                      const double* __restrict__ x, int M0,
-                                                      int M1, int M2, int w, double beta,
-                                                      const double2* __restrict__ grid,
-                                                      double* __restrict__ pot,
-                                                      double* __restrict__ grad, int want_grad) {
+// Interpolation (step five of Section 3.6) at targets in tree order, one
+// target per lane; the block's subgrid is read into LDS once.  Results are
+// added to the near-field arrays (tree order), gradients rotated by L^{-T}.
+template <int D, int W, bool GRAD, class Real>
+__global__ __launch_bounds__(256) void k_interp_t(KParams kp, int64_t n,
+                                                  const double* __restrict__ x, int M0, int M1,
+                                                  int M2, double beta,
+                                                  const double2* __restrict__ grid,
+                                                  double* __restrict__ pot,
+                                                  double* __restrict__ grad) {
   __shared__ double sub[kSubCap];
-  __shared__ int lo[3], hi[3];
+  __shared__ int lo_s[3], hi_s[3];
+  constexpr double hw = 0.5 * W;
   const int Ms[3] = {M0, M1, M2};
-  const double hw = 0.5 * w;
   const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
   const bool valid = i < n;
-  if (threadIdx.x < 3) {
-    lo[threadIdx.x] = INT_MAX;
-    hi[threadIdx.x] = INT_MIN;
-  }
-  __syncthreads();
   double g[D];
-  int i0[D];
-  if (valid) {
-    grid_coords<D>(kp, x, n, i, Ms, g);
-    for (int a = 0; a < D; ++a) {
-      i0[a] = (int)ceil(g[a] - hw);
-      atomicMin(&lo[a], i0[a]);
-      atomicMax(&hi[a], i0[a]);
-    }
-  }
-  __syncthreads();
-  int ext[3] = {1, 1, 1};
-  long long vol = 1;
-  for (int a = 0; a < D; ++a) {
-    ext[a] = hi[a] - lo[a] + w;
-    vol *= ext[a];
-  }
-  const bool tiled = vol <= kSubCap;
+  int i0[D], lo[3], ext[3], vol;
+  const bool tiled = block_box<D, W>(kp, n, x, i, valid, Ms, g, i0, lo_s, hi_s, lo, ext, vol);
   if (tiled) {
     for (int c = threadIdx.x; c < vol; c += 256) {
-      int cc[3] = {c % ext[0], (c / ext[0]) % ext[1], c / (ext[0] * ext[1])};
-      int64_t gi = 0, mul = 1;
-      for (int a = 0; a < D; ++a) {
-        int id = (lo[a] + cc[a]) % Ms[a];
-        if (id < 0) id += Ms[a];
-        gi += id * mul;
-        mul *= Ms[a];
-      }
+      const int c0 = c % ext[0], c1 = (c / ext[0]) % ext[1], c2 = c / (ext[0] * ext[1]);
+      int64_t gi = wrap_index(lo[0] + c0, M0) + (int64_t)M0 * wrap_index(lo[1] + c1, M1);
+      if (D == 3) gi += (int64_t)M0 * M1 * wrap_index(lo[2] + c2, M2);
       sub[c] = grid[gi].x;
     }
     __syncthreads();
   }
   if (!valid) return;
-  double wt[D][16], dw[D][16];
-  int ix[D][16];
-  for (int a = 0; a < D; ++a)
-    for (int k = 0; k < w; ++k) {
-      const Real z = (Real)((i0[a] + k - g[a]) / hw);
-      const Real v = es_win(z, (Real)beta);
-      wt[a][k] = (double)v;
+  // window values (and derivatives) of axes 0 and 1 in registers; axis 2 is
+  // evaluated inside its loop
+  auto win = [&](int a, int k, double& v, double& dv) {
+    const Real z = (Real)((i0[a] + k - g[a]) / hw);
+    const Real e = es_win(z, (Real)beta);
+    v = (double)e;
+    dv = 0.0;
+    if (GRAD) {
       const Real t = (Real)1 - z * z;
-      dw[a][k] = (t > (Real)0) ? (double)(v * (Real)beta * (-z / sqrt(t))) * (-Ms[a] / hw) : 0.0;
+      dv = (t > (Real)0) ? (double)(e * (Real)beta * (-z / sqrt(t))) * (-Ms[a] / hw) : 0.0;
+    }
+  };
+  double wt0[W], dw0[W], wt1[W], dw1[W];
+#pragma unroll
+  for (int k = 0; k < W; ++k) {
+    win(0, k, wt0[k], dw0[k]);
+    win(1, k, wt1[k], dw1[k]);
+  }
+  double acc = 0.0, gu[3] = {0, 0, 0};
+  constexpr int K2 = D == 3 ? W : 1;
+  const int b0 = i0[0] - lo[0], b1 = i0[1] - lo[1], b2 = D == 3 ? i0[D - 1] - lo[D - 1] : 0;
+  for (int k2 = 0; k2 < K2; ++k2) {
+    double w2 = 1.0, d2 = 0.0;
+    if (D == 3) win(D - 1, k2, w2, d2);
+    double p2 = 0.0, g20 = 0.0, g21 = 0.0;   // this k2 plane: value, d/du0, d/du1
+#pragma unroll
+    for (int k1 = 0; k1 < W; ++k1) {
+      double a0 = 0.0, ad0 = 0.0;
       if (tiled) {
-        ix[a][k] = i0[a] + k - lo[a];
+        const double* row = sub + ((b2 + k2) * ext[1] + (b1 + k1)) * ext[0] + b0;
+#pragma unroll
+        for (int k0 = 0; k0 < W; ++k0) {
+          const double v = row[k0];
+          a0 = fma(v, wt0[k0], a0);
+          if (GRAD) ad0 = fma(v, dw0[k0], ad0);
+        }
       } else {
-        int id = (i0[a] + k) % Ms[a];
-        ix[a][k] = id < 0 ? id + Ms[a] : id;
+        int64_t row = (int64_t)M0 * wrap_index(i0[1] + k1, M1);
+        if (D == 3) row += (int64_t)M0 * M1 * wrap_index(i0[D - 1] + k2, M2);
+#pragma unroll
+        for (int k0 = 0; k0 < W; ++k0) {
+          const double v = grid[row + wrap_index(i0[0] + k0, M0)].x;
+          a0 = fma(v, wt0[k0], a0);
+          if (GRAD) ad0 = fma(v, dw0[k0], ad0);
+        }
+      }
+      p2 = fma(a0, wt1[k1], p2);
+      if (GRAD) {
+        g20 = fma(ad0, wt1[k1], g20);
+        g21 = fma(a0, dw1[k1], g21);
       }
     }
-  const int s0 = tiled ? ext[0] : M0;
-  const int s1 = tiled ? ext[1] : M1;
-  double acc = 0.0, gu[3] = {0, 0, 0};
-  if (D == 3) {
-    for (int k2 = 0; k2 < w; ++k2)
-      for (int k1 = 0; k1 < w; ++k1) {
-        const int64_t row = (int64_t)s0 * (ix[1][k1] + (int64_t)s1 * ix[D - 1][k2]);
-        double a0 = 0.0, ad0 = 0.0;
-        for (int k0 = 0; k0 < w; ++k0) {
-          const double v = tiled ? sub[row + ix[0][k0]] : grid[row + ix[0][k0]].x;
-          a0 = fma(v, wt[0][k0], a0);
-          if (want_grad) ad0 = fma(v, dw[0][k0], ad0);
-        }
-        const double w12 = wt[1][k1] * wt[D - 1][k2];
-        acc = fma(a0, w12, acc);
-        if (want_grad) {
-          gu[0] = fma(ad0, w12, gu[0]);
-          gu[1] = fma(a0, dw[1][k1] * wt[D - 1][k2], gu[1]);
-          gu[2] = fma(a0, wt[1][k1] * dw[D - 1][k2], gu[2]);
-        }
-      }
-  } else {
-    for (int k1 = 0; k1 < w; ++k1) {
-      const int64_t row = (int64_t)s0 * ix[1][k1];
-      double a0 = 0.0, ad0 = 0.0;
-      for (int k0 = 0; k0 < w; ++k0) {
-        const double v = tiled ? sub[row + ix[0][k0]] : grid[row + ix[0][k0]].x;
-        a0 = fma(v, wt[0][k0], a0);
-        if (want_grad) ad0 = fma(v, dw[0][k0], ad0);
-      }
-      acc = fma(a0, wt[1][k1], acc);
-      if (want_grad) {
-        gu[0] = fma(ad0, wt[1][k1], gu[0]);
-        gu[1] = fma(a0, dw[1][k1], gu[1]);
-      }
+    acc = fma(p2, w2, acc);
+    if (GRAD) {
+      gu[0] = fma(g20, w2, gu[0]);
+      gu[1] = fma(g21, w2, gu[1]);
+      if (D == 3) gu[2] = fma(p2, d2, gu[2]);
     }
   }
   pot[i] += acc;
-  if (want_grad)
+  if (GRAD)
     for (int b = 0; b < D; ++b) {
       double s = 0.0;
       for (int a = 0; a <= b; ++a) s += kp.Li[a + D * b] * gu[a];
       grad[i * D + b] += s;
     }
 }
+
+template <int D, int W, class Real>
+static void launch_spread_interp(pdmk_plan* P, Eval& E, const int* M, double beta, double* grid,
+                                 double2* cg, bool want_grad, bool spread) {
+  if (spread) {
+    if (E.n_src > 0)
+      hipLaunchKernelGGL((k_spread_coop<D, W, Real>), dim3(nblk(E.n_src, 256)), dim3(256), 0,
+                         E.s, P->kp, E.n_src, E.ox, E.oq, M[0], M[1], M[2], beta, grid);
+  } else if (E.n_trg > 0) {
+    if (want_grad)
+      hipLaunchKernelGGL((k_interp_t<D, W, true, Real>), dim3(nblk(E.n_trg, 256)), dim3(256), 0,
+                         E.s, P->kp, E.n_trg, E.tx, M[0], M[1], M[2], beta, cg, E.pot_sorted,
+                         E.grad_sorted);
+    else
+      hipLaunchKernelGGL((k_interp_t<D, W, false, Real>), dim3(nblk(E.n_trg, 256)), dim3(256),
+                         0, E.s, P->kp, E.n_trg, E.tx, M[0], M[1], M[2], beta, cg, E.pot_sorted,
+                         E.grad_sorted);
+  }
+}
+
+template <int D, class Real>
+static void spread_interp_w(pdmk_plan* P, Eval& E, const int* M, int w, double beta,
+                            double* grid, double2* cg, bool want_grad, bool spread) {
+  switch (w) {
+#define PDMK_W(WW) \
+  case WW: launch_spread_interp<D, WW, Real>(P, E, M, beta, grid, cg, want_grad, spread); break;
+    PDMK_W(4) PDMK_W(5) PDMK_W(6) PDMK_W(7) PDMK_W(8) PDMK_W(9) PDMK_W(10) PDMK_W(11)
+    PDMK_W(12) PDMK_W(13) PDMK_W(14) PDMK_W(15) PDMK_W(16)
+#undef PDMK_W
+    default: throw Error{PDMK_ERR_UNSUPPORTED, "window width outside 4..16"};
+  }
+}
+
+static void spread_interp(pdmk_plan* P, Eval& E, const int* M, int w, double beta,
+                          double* grid, double2* cg, bool want_grad, bool spread) {
+  const bool f32 = P->kp.precision == PDMK_PREC_MIXED;
+  if (P->kp.dim == 3) {
+    if (f32) spread_interp_w<3, float>(P, E, M, w, beta, grid, cg, want_grad, spread);
+    else spread_interp_w<3, double>(P, E, M, w, beta, grid, cg, want_grad, spread);
+  } else {
+    if (f32) spread_interp_w<2, float>(P, E, M, w, beta, grid, cg, want_grad, spread);
+    else spread_interp_w<2, double>(P, E, M, w, beta, grid, cg, want_grad, spread);
+  }
+}
+
 
 __global__ void k_to_complex(int64_t n, const double* __restrict__ g, double2* __restrict__ c) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -451,28 +496,12 @@ void stage_far(pdmk_plan* P, Eval& E, const double* q, bool want_grad) {
   double* grid = E.alloc<double>(n);
   double2* cg = E.alloc<double2>(n);
   PDMK_HIP(hipMemsetAsync(grid, 0, n * sizeof(double), E.s));
-  const bool f32 = P->kp.precision == PDMK_PREC_MIXED;
-#define PDMK_SP(DD, R)                                                                        \
-  hipLaunchKernelGGL((k_spread_tiled<DD, R>), dim3(nblk(E.n_src, 256)), dim3(256), 0, E.s, \
-                     P->kp, E.n_src, E.ox, E.oq, M[0], M[1], M[2], w, beta, grid)
-#define PDMK_IN(DD, R)                                                                        \
-  hipLaunchKernelGGL((k_interp_tiled<DD, R>), dim3(nblk(E.n_trg, 256)), dim3(256), 0, E.s, \
-                     P->kp, E.n_trg, E.tx, M[0], M[1], M[2], w, beta, cg, E.pot_sorted,     \
-                     E.grad_sorted, want_grad ? 1 : 0)
-  if (E.n_src > 0) {
-    if (d == 3) { if (f32) PDMK_SP(3, float); else PDMK_SP(3, double); }
-    else { if (f32) PDMK_SP(2, float); else PDMK_SP(2, double); }
-  }
+  spread_interp(P, E, M, w, beta, grid, cg, want_grad, true);
   hipLaunchKernelGGL(k_to_complex, dim3(nblk(n, 256)), dim3(256), 0, E.s, n, grid, cg);
   fft3(cg, M, d, -1, E.s);
   hipLaunchKernelGGL(k_scale, dim3(nblk(n, 256)), dim3(256), 0, E.s, n, cg, P->d_farscale);
   fft3(cg, M, d, +1, E.s);
-  if (E.n_trg > 0) {
-    if (d == 3) { if (f32) PDMK_IN(3, float); else PDMK_IN(3, double); }
-    else { if (f32) PDMK_IN(2, float); else PDMK_IN(2, double); }
-  }
-#undef PDMK_SP
-#undef PDMK_IN
+  spread_interp(P, E, M, w, beta, grid, cg, want_grad, false);
 }
 
 }  // namespace pdmk

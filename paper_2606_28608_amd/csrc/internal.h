@@ -157,6 +157,13 @@ struct pdmk_plan {
   int device = 0;
   char* arena = nullptr;        // device workspace kept between calls
   size_t arena_size = 0;
+  // real matrices of the plane-wave contractions for the matrix-core path
+  float* d_pwt_f = nullptr;
+  double* d_pwt_d = nullptr;
+  size_t pwt_off[6] = {0, 0, 0, 0, 0, 0};
+  bool pw_mfma = true;          // use the matrix-core plane-wave kernels when they fit
+  double* adj_buf = nullptr;    // Psi and grad Psi of the adjoint (n_src (d + 1))
+  size_t adj_size = 0;
   pdmk::KParams kp{};
   // device tables
   double* d_E = nullptr;
@@ -177,6 +184,20 @@ struct pdmk_plan {
 };
 
 namespace pdmk {
+// Matrix-core plane-wave transforms (pwmfma.hip).
+constexpr int kPwMaxTiles = 16;   // accumulator tiles of a box's proxy potential per wave
+struct PwMfmaShape {
+  bool ok;
+  int g_out, g_in;              // slabs j0 per group
+  size_t lds_out, lds_in;       // dynamic LDS bytes
+  int sX, sZ, sI, sY, sW;       // LDS row strides
+};
+PwMfmaShape pw_mfma_shape(int p, int J, size_t real_size);
+void pw_mfma_upload(pdmk_plan* P);
+template <class Real>
+void pw_mfma_level(const pdmk_plan* P, const Level& L, int nn, const void* proxy_q, void* S,
+                   void* proxy_phi, double levfac, unsigned long long* npairs, hipStream_t s);
+
 // stages (implemented in tree.hip / near.hip / far.hip)
 void stage_prepare(pdmk_plan* P, Eval& E, const double* src, const double* trg);
 void stage_images(pdmk_plan* P, Eval& E, const double* q);

@@ -1149,6 +1149,7 @@ static void near_impl(pdmk_plan* P, Eval& E, bool want_grad) {
     const size_t lds_out = lds_pw_out(p, J, sizeof(Real));
     const size_t lds_in = lds_pw_in(p, J, sizeof(Real));
     const bool fused = D == 3 && lds_out <= 150 * 1024 && lds_in <= 150 * 1024;
+    const bool mfma = D == 3 && P->pw_mfma && pw_mfma_shape(p, J, sizeof(Real)).ok;
     C* bS = E.alloc<C>((size_t)maxnl * s3);
     double2* bA = fused ? nullptr : E.alloc<double2>((size_t)maxnl * s1);
     double2* bB = (D == 3 && !fused) ? E.alloc<double2>((size_t)maxnl * s2) : nullptr;
@@ -1170,6 +1171,10 @@ static void near_impl(pdmk_plan* P, Eval& E, bool want_grad) {
       const double h = kp.rc / (double)(1 << l);
       const double levfac = D == 3 ? 1.0 / (3.0 * h) : 1.0;
       const int zz = D == 3 ? p : 1;
+      if (mfma) {
+        pw_mfma_level<Real>(P, L, nn, L.proxy_q, bS, L.proxy_phi, levfac, npairs, s);
+        continue;
+      }
       if (fused) {
         hipLaunchKernelGGL(k_pw_out<Real>, dim3(nn), dim3(256), lds_out, s, kp, L,
                            static_cast<const Real*>(L.proxy_q), Ftab, bS);

@@ -97,6 +97,8 @@ def lib():
         L.pdmk_plan_create.argtypes = [ctypes.POINTER(Opts), _dp, ctypes.POINTER(_vp)]
         L.pdmk_plan_eval.argtypes = [_vp, ctypes.c_int64, _vp, _vp, ctypes.c_int64, _vp, _vp, _vp,
                                      _vp]
+        L.pdmk_plan_adjoint.argtypes = [_vp, ctypes.c_int64, _vp, _vp, ctypes.c_int64, _vp, _vp,
+                                        _vp, _vp, _vp, _vp, _vp]
         L.pdmk_plan_destroy.argtypes = [_vp]
         L.pdmk_plan_destroy.restype = None
         L.pdmk_plan_geometry.argtypes = [_vp, ctypes.POINTER(Geometry)]
@@ -202,8 +204,12 @@ class Plan:
             _lib.pdmk_plan_destroy(h)
             self._h = None
 
-    def eval(self, src, q, trg=None, out=None):
+    def eval(self, src, q, trg=None, out=None, want_grad=None):
+        """Potential at the targets (the sources when trg is None); with
+        gradients when the plan was made with grad=True or want_grad is set
+        (then returns (pot, grad))."""
         import torch
+        wg = self.want_grad if want_grad is None else bool(want_grad)
         src = _dev(src, torch)
         q = _dev(q, torch)
         n = src.shape[0]
@@ -216,14 +222,40 @@ class Plan:
             m = n
         pot = torch.empty(m, dtype=torch.float64, device=src.device) if out is None else out
         grad = torch.empty((m, self.dim), dtype=torch.float64, device=src.device) \
-            if self.want_grad else None
+            if wg else None
         _check(lib().pdmk_plan_eval(self._h, n, ctypes.c_void_p(src.data_ptr()),
                                     ctypes.c_void_p(q.data_ptr()), m,
                                     ctypes.c_void_p(trg.data_ptr()) if trg is not None else None,
                                     ctypes.c_void_p(pot.data_ptr()),
                                     ctypes.c_void_p(grad.data_ptr()) if grad is not None else None,
                                     _stream(torch)))
-        return (pot, grad) if self.want_grad else pot
+        return (pot, grad) if wg else pot
+
+    def adjoint(self, src, q, g, trg=None, grad_phi=None, want_dq=True, want_dsrc=True,
+                want_dtrg=False):
+        """pdmk_plan_adjoint: returns (dq, dsrc, dtrg) for dl/dPhi = g (entries
+        not asked for are None).  grad_phi is the forward gradient."""
+        import torch
+        src = _dev(src, torch)
+        q = _dev(q, torch)
+        g = _dev(g, torch)
+        n = src.shape[0]
+        if trg is not None:
+            trg = _dev(trg, torch)
+        m = trg.shape[0] if trg is not None else n
+        if g.shape != (m,):
+            raise ValueError("g must have one entry per target")
+        if grad_phi is not None:
+            grad_phi = _dev(grad_phi, torch)
+        dev = src.device
+        dq = torch.empty(n, dtype=torch.float64, device=dev) if want_dq else None
+        ds = torch.empty((n, self.dim), dtype=torch.float64, device=dev) if want_dsrc else None
+        dt = torch.empty((m, self.dim), dtype=torch.float64, device=dev) \
+            if (want_dtrg and trg is not None) else None
+        vp = lambda t: ctypes.c_void_p(t.data_ptr()) if t is not None else None  # noqa: E731
+        _check(lib().pdmk_plan_adjoint(self._h, n, vp(src), vp(q), m, vp(trg), vp(g),
+                                       vp(grad_phi), vp(dq), vp(ds), vp(dt), _stream(torch)))
+        return dq, ds, dt
 
     def geometry(self):
         g = Geometry()
@@ -259,3 +291,51 @@ def pdmk_eval(L, src, q, trg=None, eps=1e-6, precision="fp64", grad=False,
                            ctypes.c_void_p(g.data_ptr()) if g is not None else None,
                            _stream(torch)))
     return (pot, g) if grad else pot
+
+
+def _autograd_fn():
+    import torch
+
+    class _PeriodicPotentialFn(torch.autograd.Function):
+        @staticmethod
+        def forward(ctx, src, q, trg, plan):
+            need_pos = src.requires_grad or (trg is not None and trg.requires_grad)
+            if need_pos:
+                pot, gphi = plan.eval(src.detach(), q.detach(),
+                                      trg.detach() if trg is not None else None, want_grad=True)
+            else:
+                pot, gphi = plan.eval(src.detach(), q.detach(),
+                                      trg.detach() if trg is not None else None,
+                                      want_grad=False), None
+            ctx.plan = plan
+            ctx.has_trg = trg is not None
+            ctx.save_for_backward(src.detach(), q.detach(),
+                                  trg.detach() if trg is not None else None, gphi)
+            return pot
+
+        @staticmethod
+        def backward(ctx, gout):
+            src, q, trg, gphi = ctx.saved_tensors
+            want_dq = ctx.needs_input_grad[1]
+            want_ds = ctx.needs_input_grad[0]
+            want_dt = ctx.has_trg and ctx.needs_input_grad[2]
+            dq, ds, dt = ctx.plan.adjoint(src, q, gout.contiguous(), trg=trg, grad_phi=gphi,
+                                          want_dq=want_dq, want_dsrc=want_ds,
+                                          want_dtrg=want_dt)
+            return ds, dq, dt, None
+
+    return _PeriodicPotentialFn
+
+
+_FN = None
+
+
+def periodic_potential(plan, src, q, trg=None):
+    """Differentiable potential (torch.autograd): Phi at the targets (the
+    sources when trg is None) for the plan's lattice and accuracy.  Gradients
+    flow to src, q and trg through pdmk_plan_adjoint; the forward computes
+    grad Phi only when a position requires grad."""
+    global _FN
+    if _FN is None:
+        _FN = _autograd_fn()
+    return _FN.apply(src, q, trg, plan)

@@ -5,9 +5,11 @@ value here comes from the GPU library.  Run from the repository root:
 
     python tests/golden/make_golden.py shell3d     # N = 1e7 thin shell, 64 targets
     python tests/golden/make_golden.py clustered3d # N = 1e6 clustered triclinic, 64 targets
+    python tests/golden/make_golden.py clustered3d_grad  # same, potential and gradient
 
 Each output file has one line per sampled target: the source index and the
-tin-foil potential there (targets = sources, self pair removed).
+tin-foil potential there (targets = sources, self pair removed); the _grad
+file adds the d components of grad Phi.
 """
 import os
 import sys
@@ -44,6 +46,16 @@ if __name__ == "__main__":
         write("shell3d_n1e7_seed3.txt", L, src, q,
               "workloads.shell3d(10_000_000, seed=3); oracle Ewald at 64 sampled sources "
               "(numpy default_rng(123).choice); columns: index potential")
+    elif which == "clustered3d_grad":
+        L, src, q = workloads.clustered3d(1_000_000, seed=2)
+        idx = sample(len(q))
+        pot, grad = ewald.ewald_sampled(L, src, q, idx, grad=True)
+        path = os.path.join(HERE, "clustered3d_n1e6_seed2_grad.txt")
+        np.savetxt(path, np.c_[idx, pot, grad], fmt=["%d"] + ["%.17e"] * 4,
+                   header="workloads.clustered3d(1_000_000, seed=2); oracle Ewald potential and "
+                          "gradient at 64 sampled sources (numpy default_rng(123).choice); "
+                          "columns: index potential gx gy gz")
+        print("wrote", path)
     elif which == "clustered3d":
         L, src, q = workloads.clustered3d(1_000_000, seed=2)
         write("clustered3d_n1e6_seed2.txt", L, src, q,
