@@ -73,7 +73,7 @@ enum { PDMK_PREC_FP64 = 0, PDMK_PREC_MIXED = 1 };
 
 /* Flags */
 enum {
-  PDMK_WANT_GRAD = 1,          /* also return grad Phi at the targets */
+  PDMK_WANT_GRAD = 1,          /* gradients wanted: accurate grad Phi (see pdmk_eval) */
   PDMK_ALLOW_NONNEUTRAL = 2    /* accept sum q != 0 (uniform background) */
 };
 
@@ -86,21 +86,25 @@ typedef struct {
   unsigned flags;   /* PDMK_WANT_GRAD | PDMK_ALLOW_NONNEUTRAL */
   int porder;       /* Chebyshev proxy points per axis; <= 0: chosen from eps */
   int npw;          /* plane-wave half count J per axis (modes -J..J); <= 0: from eps */
-  int nufft_w;      /* spreading-window width in grid cells; <= 0: from eps */
+  int nufft_w;      /* spreading-window width in grid cells; <= 0: from eps (two
+                       cells more when PDMK_WANT_GRAD is set) */
   double sigma;     /* Fourier grid per axis = sigma * M_i of eq:Mi rounded up to a
                        2,3,5-smooth even size; <= 0: 1 (no upsampling, as in the
                        paper) for eps >= 1e-7, 2 below */
 } pdmk_opts;
 
-/* Fill *out with the defaults for (dim, eps).  Host only; no device needed. */
+/* Fill *out with the defaults for (dim, eps); nufft_w is left 0 (chosen at
+ * plan creation from eps and the flags).  Host only; no device needed. */
 int pdmk_default_opts(int dim, double eps, pdmk_opts* out);
 
 /*
  * One evaluation (Algorithm 1).  Targets are the sources when trg == NULL
  * (then n_trg is ignored and the self pair of every source is excluded);
  * otherwise targets are n_trg separate points and no self pair is removed.
- * grad may be NULL; when it is not NULL, grad Phi at the targets is written
- * (PDMK_WANT_GRAD in the options requires it to be non-NULL).
+ * grad may be NULL; when it is not NULL, grad Phi at the targets is written.
+ * PDMK_WANT_GRAD in the options asks for gradients of full accuracy (it
+ * widens the far-field window at plan creation); pdmk_eval with that flag
+ * requires grad to be non-NULL.
  */
 int pdmk_eval(const pdmk_opts* opts, const double* L, int64_t n_src,
               const double* src, const double* q, int64_t n_trg,
@@ -145,6 +149,36 @@ int pdmk_plan_adjoint(pdmk_plan* plan, int64_t n_src, const double* src, const d
                       const double* grad_phi, double* dq, double* dsrc, double* dtrg,
                       void* stream);
 
+/*
+ * Batches of independent systems (many small cells in one call; the adaptive
+ * tuning remark of Section 5 leaves per-problem planning to future work, and
+ * a batch is where it pays).  All systems share the
+ * options; system s has its own lattice L + s*d*d (HOST, column-major) and the
+ * sources offsets[s] .. offsets[s+1]-1 of the concatenated arrays (offsets is a
+ * HOST array of n_sys + 1 nondecreasing entries; targets are the sources, the
+ * self pair excluded).  src (row-major N x d), q, pot (N) and grad (N x d, may
+ * be NULL; required with PDMK_WANT_GRAD) are DEVICE arrays.  Every system must
+ * be neutral unless PDMK_ALLOW_NONNEUTRAL is set.
+ *
+ * pdmk_batch_create builds one plan per system (host tables, geometry) and
+ * n_workers host workers (<= 0: 8), each with its own non-blocking HIP stream
+ * and device workspace; pdmk_batch_eval hands the systems to the workers, so
+ * the pipelines of different systems run concurrently on the device.  The call
+ * first synchronises `stream` (the inputs must be complete) and returns when
+ * every output is written.  On the first failing system the remaining ones are
+ * skipped and its status is returned.  pdmk_batch_stats reads the counters of
+ * system `sys`.  pdmk_eval_batched = create + eval + destroy.
+ */
+typedef struct pdmk_batch pdmk_batch;
+int pdmk_batch_create(const pdmk_opts* opts, int n_sys, const double* L, int n_workers,
+                      pdmk_batch** out);
+int pdmk_batch_eval(pdmk_batch* batch, const int64_t* offsets, const double* src,
+                    const double* q, double* pot, double* grad, void* stream);
+void pdmk_batch_destroy(pdmk_batch* batch);
+int pdmk_eval_batched(const pdmk_opts* opts, int n_sys, const double* L,
+                      const int64_t* offsets, const double* src, const double* q,
+                      double* pot, double* grad, void* stream);
+
 /* Geometry and parameters a plan derived from (opts, L); host only. */
 typedef struct {
   int dim;
@@ -183,6 +217,7 @@ typedef struct {
   int64_t workspace_bytes;          /* device workspace the call used */
 } pdmk_stats;
 int pdmk_plan_stats(const pdmk_plan* plan, pdmk_stats* out);
+int pdmk_batch_stats(const pdmk_batch* batch, int sys, pdmk_stats* out);
 
 /* Kernel-splitting scalars for (dim, eps); host only.  Pins the host
  * implementation of the PSWF calibration (Section 2.2) and of the split

@@ -1,6 +1,8 @@
 // C interface (include/pdmk.h): plans, evaluation pipeline of Algorithm 1,
 // assembly with the self-interaction correction (Section 3.8), status codes.
 #include <cmath>
+#include <atomic>
+#include <thread>
 #include <chrono>
 #include <cstdlib>
 #include <cstring>
@@ -128,22 +130,39 @@ static void free_plan_tables(pdmk_plan* P) {
 
 // After a call: free this call's overflow blocks and grow the arena to the
 // call's total, so that the next call of this size takes no allocation.
-static void finish_workspace(pdmk_plan* P, Workspace& ws) {
+static void finish_workspace(char*& arena, size_t& arena_size, Workspace& ws) {
   const bool grow = !ws.overflow.empty();
   ws.release_overflow();
   if (grow) {
-    if (P->arena) PDMK_HIP(hipFree(P->arena));
-    P->arena = nullptr;
-    P->arena_size = 0;
+    if (arena) PDMK_HIP(hipFree(arena));
+    arena = nullptr;
+    arena_size = 0;
     const size_t want = ws.used + ws.used / 8;
     void* p = nullptr;
     if (hipMalloc(&p, want) == hipSuccess) {
-      P->arena = static_cast<char*>(p);
-      P->arena_size = want;
+      arena = static_cast<char*>(p);
+      arena_size = want;
     } else {
       (void)hipGetLastError();   // the next call allocates per request again
     }
   }
+}
+
+// Method parameters for the options: defaults for (dim, eps), overridden by
+// every positive field.  With PDMK_WANT_GRAD the default window is two cells
+// wider: the gradient of the far field differentiates the window, which
+// loses about a factor 10-50 of accuracy at the default width.
+static MethodParams resolve_params(const pdmk_opts* o) {
+  MethodParams m = default_params(o->dim, o->eps);
+  if (o->flags & PDMK_WANT_GRAD) m.nufft_w = std::min(16, m.nufft_w + 2);
+  if (o->kappa > 0) m.kappa = o->kappa;
+  if (o->n_s > 0) m.n_s = o->n_s;
+  if (o->porder > 0) m.porder = o->porder;
+  if (o->npw > 0) m.npw = o->npw;
+  if (o->sigma > 0) m.sigma = o->sigma;
+  if (o->nufft_w > 0) m.nufft_w = o->nufft_w;
+  m.beta = window_beta(m.nufft_w, m.sigma);
+  return m;
 }
 
 // ---------------------------------------------------------------- kernels
@@ -252,7 +271,7 @@ int pdmk_default_opts(int dim, double eps, pdmk_opts* out) {
   out->n_s = m.n_s;
   out->porder = m.porder;
   out->npw = m.npw;
-  out->nufft_w = m.nufft_w;
+  out->nufft_w = 0;   // chosen at plan creation (it depends on PDMK_WANT_GRAD)
   out->sigma = m.sigma;
   return PDMK_OK;
 }
@@ -314,14 +333,7 @@ int pdmk_plan_create(const pdmk_opts* opts, const double* L, pdmk_plan** out) {
   try {
     P->o = *opts;
     const int d = opts->dim;
-    P->mp = default_params(d, opts->eps);
-    if (opts->kappa > 0) P->mp.kappa = opts->kappa;
-    if (opts->n_s > 0) P->mp.n_s = opts->n_s;
-    if (opts->porder > 0) P->mp.porder = opts->porder;
-    if (opts->npw > 0) P->mp.npw = opts->npw;
-    if (opts->sigma > 0) P->mp.sigma = opts->sigma;
-    if (opts->nufft_w > 0) P->mp.nufft_w = opts->nufft_w;
-    P->mp.beta = window_beta(P->mp.nufft_w, P->mp.sigma);
+    P->mp = resolve_params(opts);
     P->nufft_beta = P->mp.beta;
     P->P = &pswf_for_eps(opts->eps);
     P->T = &tables_for_eps(opts->eps);
@@ -362,6 +374,10 @@ int pdmk_plan_create(const pdmk_opts* opts, const double* L, pdmk_plan** out) {
       // diagnostic switch: PDMK_NO_MFMA=1 selects the vector-ALU plane-wave kernels
       const char* env = std::getenv("PDMK_NO_MFMA");
       P->pw_mfma = !(env && env[0] == '1');
+      // diagnostic switch: PDMK_MIXED_PARTS=<mask> limits which stages run in
+      // FP32 in mixed mode (1 residual sums, 2 proxies/plane waves, 4 window)
+      const char* mp = std::getenv("PDMK_MIXED_PARTS");
+      if (mp) P->mixed_parts = (unsigned)std::atoi(mp) & 7u;
     }
     far_build_scale(P);
   } catch (const Error& e) {
@@ -415,14 +431,7 @@ int pdmk_geometry_get(const pdmk_opts* opts, const double* L, pdmk_geometry* out
   if (st) return st;
   pdmk_plan tmp;
   tmp.o = *opts;
-  tmp.mp = default_params(opts->dim, opts->eps);
-  if (opts->kappa > 0) tmp.mp.kappa = opts->kappa;
-  if (opts->n_s > 0) tmp.mp.n_s = opts->n_s;
-  if (opts->porder > 0) tmp.mp.porder = opts->porder;
-  if (opts->npw > 0) tmp.mp.npw = opts->npw;
-  if (opts->sigma > 0) tmp.mp.sigma = opts->sigma;
-  if (opts->nufft_w > 0) tmp.mp.nufft_w = opts->nufft_w;
-  tmp.mp.beta = window_beta(tmp.mp.nufft_w, tmp.mp.sigma);
+  tmp.mp = resolve_params(opts);
   tmp.nufft_beta = tmp.mp.beta;
   tmp.P = &pswf_for_eps(opts->eps);
   tmp.T = &tables_for_eps(opts->eps);
@@ -446,7 +455,7 @@ int pdmk_plan_stats(const pdmk_plan* P, pdmk_stats* out) {
 // honoured, gradients are computed iff grad is not null).
 static int eval_impl(pdmk_plan* P, int64_t n_src, const double* src, const double* q,
                      int64_t n_trg, const double* trg, double* pot, double* grad, void* stream,
-                     unsigned flags) {
+                     unsigned flags, char*& arena, size_t& arena_size) {
   if (!P) return fail(PDMK_ERR_INVALID_ARG, "null plan");
   const int d = P->g.dim;
   const bool self_t = (trg == nullptr);
@@ -460,8 +469,8 @@ static int eval_impl(pdmk_plan* P, int64_t n_src, const double* src, const doubl
   hipStream_t s = (hipStream_t)stream;
   const auto wall0 = std::chrono::steady_clock::now();
   Workspace ws;
-  ws.base = P->arena;
-  ws.size = P->arena_size;
+  ws.base = arena;
+  ws.size = arena_size;
   Eval E;
   E.s = s;
   E.ws = &ws;
@@ -533,7 +542,7 @@ static int eval_impl(pdmk_plan* P, int64_t n_src, const double* src, const doubl
     E.st.t_total_ms = t4;
     P->last = E.st;
     PDMK_HIP(hipStreamSynchronize(s));
-    finish_workspace(P, ws);
+    finish_workspace(arena, arena_size, ws);
     P->last.workspace_bytes = (int64_t)ws.used;
     P->last.t_call_ms =
         std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - wall0)
@@ -551,9 +560,8 @@ extern "C" {
 int pdmk_plan_eval(pdmk_plan* P, int64_t n_src, const double* src, const double* q,
                    int64_t n_trg, const double* trg, double* pot, double* grad, void* stream) {
   if (!P) return fail(PDMK_ERR_INVALID_ARG, "null plan");
-  if ((P->o.flags & PDMK_WANT_GRAD) && !grad && (trg ? n_trg : n_src) > 0)
-    return fail(PDMK_ERR_INVALID_ARG, "PDMK_WANT_GRAD set but grad is null");
-  return eval_impl(P, n_src, src, q, n_trg, trg, pot, grad, stream, P->o.flags);
+  return eval_impl(P, n_src, src, q, n_trg, trg, pot, grad, stream, P->o.flags, P->arena,
+                   P->arena_size);
 }
 
 int pdmk_plan_adjoint(pdmk_plan* P, int64_t n_src, const double* src, const double* q,
@@ -589,9 +597,10 @@ int pdmk_plan_adjoint(pdmk_plan* P, int64_t n_src, const double* src, const doub
     double* gpsi = P->adj_buf + n_src;
     if (n_src > 0) {
       const int st = self_t ? eval_impl(P, n_src, src, g, 0, nullptr, psi, dsrc ? gpsi : nullptr,
-                                        stream, PDMK_ALLOW_NONNEUTRAL)
+                                        stream, PDMK_ALLOW_NONNEUTRAL, P->arena, P->arena_size)
                             : eval_impl(P, n_trg, trg, g, n_src, src, psi,
-                                        dsrc ? gpsi : nullptr, stream, PDMK_ALLOW_NONNEUTRAL);
+                                        dsrc ? gpsi : nullptr, stream, PDMK_ALLOW_NONNEUTRAL,
+                                        P->arena, P->arena_size);
       if (st != PDMK_OK) return st;
     }
     const int64_t nmax = std::max(n_src, n_trg);
@@ -610,11 +619,135 @@ int pdmk_plan_adjoint(pdmk_plan* P, int64_t n_src, const double* src, const doub
 int pdmk_eval(const pdmk_opts* opts, const double* L, int64_t n_src, const double* src,
               const double* q, int64_t n_trg, const double* trg, double* pot, double* grad,
               void* stream) {
+  if (opts && (opts->flags & PDMK_WANT_GRAD) && !grad && (trg ? n_trg : n_src) > 0)
+    return fail(PDMK_ERR_INVALID_ARG, "PDMK_WANT_GRAD set but grad is null");
   pdmk_plan* P = nullptr;
   int st = pdmk_plan_create(opts, L, &P);
   if (st) return st;
   st = pdmk_plan_eval(P, n_src, src, q, n_trg, trg, pot, grad, stream);
   pdmk_plan_destroy(P);
+  return st;
+}
+
+// ------------------------------------------------------------------ batches
+// Many independent systems: one plan per system, evaluated by a pool of host
+// workers, each with its own HIP stream and device workspace, so that the
+// small per-system pipelines of different systems overlap on the GPU.
+struct pdmk_batch {
+  pdmk_opts o{};
+  int device = 0;
+  std::vector<pdmk_plan*> plans;
+  std::vector<hipStream_t> streams;
+  std::vector<char*> arenas;
+  std::vector<size_t> arena_sizes;
+};
+
+int pdmk_batch_create(const pdmk_opts* opts, int n_sys, const double* L, int n_workers,
+                      pdmk_batch** out) {
+  if (!opts || !L || !out || n_sys < 0) return fail(PDMK_ERR_INVALID_ARG, "null argument");
+  const int d = opts->dim;
+  if (d != 2 && d != 3) return fail(PDMK_ERR_INVALID_ARG, "dim must be 2 or 3");
+  pdmk_batch* B = new pdmk_batch;
+  B->o = *opts;
+  try {
+    PDMK_HIP(hipGetDevice(&B->device));
+    for (int sy = 0; sy < n_sys; ++sy) {
+      pdmk_plan* P = nullptr;
+      const int st = pdmk_plan_create(opts, L + (size_t)sy * d * d, &P);
+      if (st) {
+        pdmk_batch_destroy(B);
+        return st;
+      }
+      B->plans.push_back(P);
+    }
+    const int nw = std::max(1, std::min(n_workers > 0 ? n_workers : 8, std::max(1, n_sys)));
+    for (int w = 0; w < nw; ++w) {
+      hipStream_t st = nullptr;
+      PDMK_HIP(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+      B->streams.push_back(st);
+      B->arenas.push_back(nullptr);
+      B->arena_sizes.push_back(0);
+    }
+  } catch (const Error& e) {
+    pdmk_batch_destroy(B);
+    return fail(e.code, e.msg);
+  }
+  *out = B;
+  return PDMK_OK;
+}
+
+int pdmk_batch_eval(pdmk_batch* B, const int64_t* offsets, const double* src, const double* q,
+                    double* pot, double* grad, void* stream) {
+  if (!B || !offsets) return fail(PDMK_ERR_INVALID_ARG, "null argument");
+  const int n_sys = (int)B->plans.size();
+  const int d = B->o.dim;
+  for (int sy = 0; sy < n_sys; ++sy)
+    if (offsets[sy + 1] < offsets[sy]) return fail(PDMK_ERR_INVALID_ARG, "offsets decrease");
+  if (offsets[n_sys] > offsets[0] && (!src || !q || !pot))
+    return fail(PDMK_ERR_INVALID_ARG, "null array");
+  if ((B->o.flags & PDMK_WANT_GRAD) && !grad) return fail(PDMK_ERR_INVALID_ARG, "null grad");
+  // the caller's stream is joined before and after (its earlier work, e.g.
+  // the inputs, is complete before any worker starts)
+  if (hipStreamSynchronize((hipStream_t)stream) != hipSuccess)
+    return fail(PDMK_ERR_HIP, "stream synchronise failed");
+  const int nw = (int)B->streams.size();
+  std::vector<int> status(nw, PDMK_OK);
+  std::vector<std::string> msg(nw);
+  std::atomic<int> next(0);
+  auto work = [&](int w) {
+    if (hipSetDevice(B->device) != hipSuccess) {
+      status[w] = PDMK_ERR_HIP;
+      msg[w] = "hipSetDevice failed";
+      return;
+    }
+    for (;;) {
+      const int sy = next.fetch_add(1);
+      if (sy >= n_sys) break;
+      const int64_t o = offsets[sy], n = offsets[sy + 1] - offsets[sy];
+      const int st = eval_impl(B->plans[sy], n, src + o * d, q + o, 0, nullptr, pot + o,
+                               grad ? grad + o * d : nullptr, B->streams[w], B->o.flags,
+                               B->arenas[w], B->arena_sizes[w]);
+      if (st != PDMK_OK) {
+        status[w] = st;
+        msg[w] = g_last_error;
+        next.store(n_sys);
+        break;
+      }
+    }
+  };
+  std::vector<std::thread> th;
+  for (int w = 1; w < nw; ++w) th.emplace_back(work, w);
+  work(0);
+  for (auto& t : th) t.join();
+  for (int w = 0; w < nw; ++w)
+    if (status[w] != PDMK_OK) return fail(status[w], msg[w]);
+  return PDMK_OK;
+}
+
+void pdmk_batch_destroy(pdmk_batch* B) {
+  if (!B) return;
+  for (pdmk_plan* P : B->plans) pdmk_plan_destroy(P);
+  for (hipStream_t s : B->streams) (void)hipStreamDestroy(s);
+  for (char* a : B->arenas)
+    if (a) (void)hipFree(a);
+  delete B;
+}
+
+int pdmk_batch_stats(const pdmk_batch* B, int sys, pdmk_stats* out) {
+  if (!B || !out || sys < 0 || sys >= (int)B->plans.size())
+    return fail(PDMK_ERR_INVALID_ARG, "bad system index");
+  *out = B->plans[sys]->last;
+  return PDMK_OK;
+}
+
+int pdmk_eval_batched(const pdmk_opts* opts, int n_sys, const double* L, const int64_t* offsets,
+                      const double* src, const double* q, double* pot, double* grad,
+                      void* stream) {
+  pdmk_batch* B = nullptr;
+  int st = pdmk_batch_create(opts, n_sys, L, 0, &B);
+  if (st) return st;
+  st = pdmk_batch_eval(B, offsets, src, q, pot, grad, stream);
+  pdmk_batch_destroy(B);
   return st;
 }
 

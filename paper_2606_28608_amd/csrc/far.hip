@@ -391,7 +391,7 @@ static void spread_interp_w(pdmk_plan* P, Eval& E, const int* M, int w, double b
 
 static void spread_interp(pdmk_plan* P, Eval& E, const int* M, int w, double beta,
                           double* grid, double2* cg, bool want_grad, bool spread) {
-  const bool f32 = P->kp.precision == PDMK_PREC_MIXED;
+  const bool f32 = P->kp.precision == PDMK_PREC_MIXED && (P->mixed_parts & 4);
   if (P->kp.dim == 3) {
     if (f32) spread_interp_w<3, float>(P, E, M, w, beta, grid, cg, want_grad, spread);
     else spread_interp_w<3, double>(P, E, M, w, beta, grid, cg, want_grad, spread);

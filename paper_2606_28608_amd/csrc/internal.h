@@ -162,6 +162,9 @@ struct pdmk_plan {
   double* d_pwt_d = nullptr;
   size_t pwt_off[6] = {0, 0, 0, 0, 0, 0};
   bool pw_mfma = true;          // use the matrix-core plane-wave kernels when they fit
+  // stages that run in FP32 in mixed mode: 1 residual sums, 2 proxies and
+  // plane waves, 4 far-field window weights (all by default)
+  unsigned mixed_parts = 7;
   double* adj_buf = nullptr;    // Psi and grad Psi of the adjoint (n_src (d + 1))
   size_t adj_size = 0;
   pdmk::KParams kp{};

@@ -108,29 +108,30 @@ __device__ inline float log_r(float x) { return __logf(x); }
 // Real = double: FP64 throughout.  Real = float: FP32 pair arithmetic on
 // offsets from the target leaf's centre (each formed in FP64, then rounded),
 // FP32 sums over one tile of 64 sources, FP64 across tiles.
-template <class Real> struct Vec4Of;
-template <> struct Vec4Of<double> { using T = double4; };
-template <> struct Vec4Of<float> { using T = float4; };
-
 // q_s R(|x - y_s|) (and its gradient) for one pair, with R_h of eq:pswf_split:
 // 3D 1/r - E(r^2/h^2)/h, 2D -log(r/h) + F2(r^2/h^2) (both without the 1/(4 pi),
 // 1/(2 pi) factors), zero outside the support r < h and for the pair r = 0.
+// Offsets and r^2 are formed in FP64 (an FP32 offset would lose u * h / r of r
+// for the close pairs of a coarse leaf); the series, rsqrt and the charge sum
+// run in Real.
 template <int D, int NE, bool GRAD, class Real>
-__device__ inline void residual_pair(const Real* x, const typename Vec4Of<Real>::T& sv, Real h2,
-                                     Real ih, const Real* ec, const Real* edc, Real& acc,
-                                     Real* g, int& nin) {
-  Real dx[3];
-  dx[0] = x[0] - sv.x;
-  dx[1] = x[1] - sv.y;
-  dx[2] = D == 3 ? x[2] - sv.z : (Real)0;
-  Real r2 = dx[0] * dx[0];
-  r2 = fma(dx[1], dx[1], r2);
-  if (D == 3) r2 = fma(dx[2], dx[2], r2);
-  const bool in = r2 < h2 && r2 > (Real)0;
+__device__ inline void residual_pair(const double* x, const double4& sv, double h2d, Real ih,
+                                     const Real* ec, const Real* edc, Real& acc, Real* g,
+                                     int& nin) {
+  double dd[3];
+  dd[0] = x[0] - sv.x;
+  dd[1] = x[1] - sv.y;
+  dd[2] = D == 3 ? x[2] - sv.z : 0.0;
+  double r2d = dd[0] * dd[0];
+  r2d = fma(dd[1], dd[1], r2d);
+  if (D == 3) r2d = fma(dd[2], dd[2], r2d);
+  const bool in = r2d < h2d && r2d > 0.0;
   nin += in ? 1 : 0;
   if (in) {
+    const Real r2 = (Real)r2d;
+    Real dx[3] = {(Real)dd[0], (Real)dd[1], (Real)dd[2]};
     const Real s = r2 * ih * ih;
-    const Real qs = sv.w;
+    const Real qs = (Real)sv.w;
     // Clenshaw recurrence for sum_k c_k T_k(2s - 1)
     const Real t2 = (Real)4 * s - (Real)2;
     Real b1 = 0, b2 = 0, d1 = 0, d2 = 0;
@@ -196,8 +197,9 @@ struct ListCursor {
 
 template <class Real>
 struct SourceSlot {
-  typename Vec4Of<Real>::T v;
-  Real h2, ih;
+  double4 v;
+  double h2;
+  Real ih;
   // Source offset from the target leaf centre (formed in FP64), charge and
   // the support of its residual level; slots past the list end never
   // interact (h^2 = 0).
@@ -205,15 +207,15 @@ struct SourceSlot {
                         const double* __restrict__ sq, int64_t nimg, const double* cT, int D) {
     if (c.valid()) {
       const int sidx = c.en.x + c.oo;
-      v.x = (Real)(sx[sidx] - cT[0]);
-      v.y = (Real)(sx[nimg + sidx] - cT[1]);
-      v.z = D == 3 ? (Real)(sx[2 * nimg + sidx] - cT[2]) : (Real)0;
-      v.w = (Real)sq[sidx];
+      v.x = sx[sidx] - cT[0];
+      v.y = sx[nimg + sidx] - cT[1];
+      v.z = D == 3 ? sx[2 * nimg + sidx] - cT[2] : 0.0;
+      v.w = sq[sidx];
       const double hh = kp.rc / (double)(1 << c.en.z);
-      h2 = (Real)(hh * hh);
+      h2 = hh * hh;
       ih = (Real)(1.0 / hh);
     } else {
-      v.x = v.y = v.z = (Real)1e30;
+      v.x = v.y = v.z = 1e30;
       v.w = 0;
       h2 = 0;
       ih = 1;
@@ -229,9 +231,9 @@ template <int D, int NE, int S, bool GRAD, class Real>
 __device__ void direct_pass(const KParams& kp, const int4* __restrict__ list, int lb, int le,
                             int pos0, int pos1, const double* __restrict__ sx,
                             const double* __restrict__ sq,
-                            int64_t nimg, const double* cT, const Real* x, const Real* ec,
-                            const Real* edc, typename Vec4Of<Real>::T* shv, Real* shh2,
-                            Real* shih, double& acc, double* g, int& nin) {
+                            int64_t nimg, const double* cT, const double* x, const Real* ec,
+                            const Real* edc, double4* shv, double* shh2, Real* shih,
+                            double& acc, double* g, int& nin) {
   const int lane = threadIdx.x;
   const int slice = lane % S;
   ListCursor cur;
@@ -269,12 +271,11 @@ __device__ void direct_pass(const KParams& kp, const int4* __restrict__ list, in
 // Leaf residual sums (the R part of the near field; interaction rule in
 // k_leaf_lists).  One 64-lane block per work item = (target leaf, chunk of
 // kDirectTgt targets, segment of kDirectSeg sources of its list), in
-// decreasing order of cost.  The
-// segments of a leaf add into the zeroed outputs with FP64 atomics; the first
-// one also removes the self term.  Real = double: FP64 throughout.  Real =
-// float: FP32 pair arithmetic on offsets from the target leaf's centre (each
-// formed in FP64, then rounded), FP32 sums over one tile of 64 sources, FP64
-// across tiles.
+// decreasing order of cost.  The segments of a leaf add into the zeroed
+// outputs with FP64 atomics; the first one also removes the self term.
+// Positions are offsets from the target leaf's centre in FP64; Real = double:
+// FP64 throughout; Real = float: the series, rsqrt and the sums over one tile
+// of 64 sources in FP32, FP64 across tiles.
 template <int D, int NE, bool GRAD, class Real>
 __global__ __launch_bounds__(64) void k_direct(
     KParams kp, int nitems, const int2* __restrict__ items, const int* __restrict__ lf_nsrc,
@@ -285,9 +286,9 @@ __global__ __launch_bounds__(64) void k_direct(
     const double* __restrict__ qorig, int self_targets, const double* __restrict__ Ec,
     const double* __restrict__ Edc, double* __restrict__ pot, double* __restrict__ grad,
     unsigned long long* __restrict__ n_support) {
-  using V4 = typename Vec4Of<Real>::T;
-  __shared__ V4 shv[64];
-  __shared__ Real shh2[64], shih[64];
+  __shared__ double4 shv[64];
+  __shared__ double shh2[64];
+  __shared__ Real shih[64];
   if ((int)blockIdx.x >= nitems) return;
   const int2 item = items[blockIdx.x];
   const int i = item.x;
@@ -319,8 +320,8 @@ __global__ __launch_bounds__(64) void k_direct(
     const int S = rem > 32 ? 1 : (rem > 16 ? 2 : (rem > 8 ? 4 : 8));
     const int t = t0 + lane / S;
     const bool valid = t < te;
-    Real x[3] = {0, 0, 0};
-    for (int a = 0; a < D; ++a) x[a] = valid ? (Real)(tx[a * ntrg + t] - cT[a]) : (Real)0;
+    double x[3] = {0, 0, 0};
+    for (int a = 0; a < D; ++a) x[a] = valid ? tx[a * ntrg + t] - cT[a] : 0.0;
     double acc = 0.0, g[3] = {0, 0, 0};
     // lanes of targets past the end still take part in staging but do no pairs
     int nin_p = 0;
@@ -996,7 +997,8 @@ static void launch_direct_r(const KParams& kp, Eval& E, pdmk_plan* P, hipStream_
 template <int D>
 static void launch_direct(const KParams& kp, Eval& E, pdmk_plan* P, hipStream_t s,
                           bool want_grad, unsigned long long* nsup) {
-  if (kp.precision == PDMK_PREC_MIXED) launch_direct_r<D, float>(kp, E, P, s, want_grad, nsup);
+  if (kp.precision == PDMK_PREC_MIXED && (P->mixed_parts & 1))
+    launch_direct_r<D, float>(kp, E, P, s, want_grad, nsup);
   else launch_direct_r<D, double>(kp, E, P, s, want_grad, nsup);
 }
 
@@ -1258,7 +1260,7 @@ void stage_near(pdmk_plan* P, Eval& E, bool want_grad) {
   E.pot_sorted = E.alloc<double>(E.n_trg);
   E.grad_sorted = want_grad ? E.alloc<double>(E.n_trg * P->kp.dim) : nullptr;
   const KParams& kp = P->kp;
-  const bool f32 = kp.precision == PDMK_PREC_MIXED && kp.dim == 3 &&
+  const bool f32 = kp.precision == PDMK_PREC_MIXED && (P->mixed_parts & 2) && kp.dim == 3 &&
                    lds_pw_out(kp.p, kp.J, 4) <= 150 * 1024 &&
                    lds_pw_in(kp.p, kp.J, 4) <= 150 * 1024;
   if (kp.dim == 3) {

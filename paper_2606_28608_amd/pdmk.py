@@ -99,6 +99,13 @@ def lib():
                                      _vp]
         L.pdmk_plan_adjoint.argtypes = [_vp, ctypes.c_int64, _vp, _vp, ctypes.c_int64, _vp, _vp,
                                         _vp, _vp, _vp, _vp, _vp]
+        L.pdmk_batch_create.argtypes = [ctypes.POINTER(Opts), ctypes.c_int, _dp, ctypes.c_int,
+                                        ctypes.POINTER(_vp)]
+        L.pdmk_batch_eval.argtypes = [_vp, ctypes.POINTER(ctypes.c_int64), _vp, _vp, _vp, _vp,
+                                      _vp]
+        L.pdmk_batch_destroy.argtypes = [_vp]
+        L.pdmk_batch_destroy.restype = None
+        L.pdmk_batch_stats.argtypes = [_vp, ctypes.c_int, ctypes.POINTER(Stats)]
         L.pdmk_plan_destroy.argtypes = [_vp]
         L.pdmk_plan_destroy.restype = None
         L.pdmk_plan_geometry.argtypes = [_vp, ctypes.POINTER(Geometry)]
@@ -291,6 +298,56 @@ def pdmk_eval(L, src, q, trg=None, eps=1e-6, precision="fp64", grad=False,
                            ctypes.c_void_p(g.data_ptr()) if g is not None else None,
                            _stream(torch)))
     return (pot, g) if grad else pot
+
+
+class Batch:
+    """A pdmk_batch: one plan per system (lattices Ls, shape (n_sys, d, d),
+    columns = lattice vectors), evaluated by concurrent workers."""
+
+    def __init__(self, Ls, eps=1e-6, precision="fp64", grad=False, allow_nonneutral=False,
+                 workers=0, **over):
+        Ls = np.asarray(Ls, dtype=np.float64)
+        self.n_sys, self.dim = Ls.shape[0], Ls.shape[1]
+        self.opts = default_opts(self.dim, eps, precision, grad, allow_nonneutral, **over)
+        self.want_grad = grad
+        Lf = np.ascontiguousarray(np.stack([_lattice(L, self.dim) for L in Ls]))
+        self._h = _vp()
+        _check(lib().pdmk_batch_create(ctypes.byref(self.opts), self.n_sys,
+                                       Lf.ctypes.data_as(_dp), int(workers),
+                                       ctypes.byref(self._h)))
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value and _lib is not None:
+            _lib.pdmk_batch_destroy(h)
+            self._h = None
+
+    def eval(self, offsets, src, q):
+        """offsets: host int array (n_sys + 1); src (N, d), q (N,) on the GPU."""
+        import torch
+        off = np.ascontiguousarray(offsets, dtype=np.int64)
+        if off.shape != (self.n_sys + 1,):
+            raise ValueError("offsets must have n_sys + 1 entries")
+        src = _dev(src, torch)
+        q = _dev(q, torch)
+        n = src.shape[0]
+        if off[-1] != n or q.shape != (n,):
+            raise ValueError("offsets do not match the arrays")
+        pot = torch.empty(n, dtype=torch.float64, device=src.device)
+        grad = torch.empty((n, self.dim), dtype=torch.float64, device=src.device) \
+            if self.want_grad else None
+        _check(lib().pdmk_batch_eval(self._h, off.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                                     ctypes.c_void_p(src.data_ptr()),
+                                     ctypes.c_void_p(q.data_ptr()),
+                                     ctypes.c_void_p(pot.data_ptr()),
+                                     ctypes.c_void_p(grad.data_ptr()) if grad is not None
+                                     else None, _stream(torch)))
+        return (pot, grad) if self.want_grad else pot
+
+    def stats(self, sys):
+        s = Stats()
+        _check(lib().pdmk_batch_stats(self._h, int(sys), ctypes.byref(s)))
+        return s.as_dict()
 
 
 def _autograd_fn():

@@ -52,7 +52,7 @@ def test_adjoint_targets_are_sources(pdmk, torch_dev, dim):
     g = np.random.default_rng(23).standard_normal(len(q))   # not neutral
     phi, gphi = ewald.ewald(L, src, q, grad=True)
     psi, gpsi = ewald.ewald(L, src, g, grad=True)
-    plan = pdmk.Plan(L, eps=eps, **over)
+    plan = pdmk.Plan(L, eps=eps, grad=True, **over)
     S, Q, G = _t(torch_dev, src), _t(torch_dev, q), _t(torch_dev, g)
     pot, grad = plan.eval(S, Q, want_grad=True)
     assert ewald.rel_l2(pot.cpu().numpy(), phi) <= eps
@@ -70,7 +70,7 @@ def test_adjoint_separate_targets(pdmk, torch_dev):
     phi, gphi = ewald.ewald(L, src, q, trg=trg, grad=True)
     # Psi at the sources: charges g at the targets
     psi, gpsi = ewald.ewald(L, trg, g, trg=src, grad=True)
-    plan = pdmk.Plan(L, eps=eps, kappa=2.0, n_s=60)
+    plan = pdmk.Plan(L, eps=eps, grad=True, kappa=2.0, n_s=60)
     S, Q, T, G = (_t(torch_dev, a) for a in (src, q, trg, g))
     pot, grad = plan.eval(S, Q, trg=T, want_grad=True)
     assert ewald.rel_l2(pot.cpu().numpy(), phi) <= eps
@@ -89,7 +89,7 @@ def test_autograd_function(pdmk, torch_dev):
     w = np.random.default_rng(28).standard_normal(len(q))
     phi, gphi = ewald.ewald(L, src, q, grad=True)
     psi, gpsi = ewald.ewald(L, src, w, grad=True)
-    plan = pdmk.Plan(L, eps=eps, kappa=2.0, n_s=60)
+    plan = pdmk.Plan(L, eps=eps, grad=True, kappa=2.0, n_s=60)
     S = _t(torch_dev, src).requires_grad_(True)
     Q = _t(torch_dev, q).requires_grad_(True)
     W = _t(torch_dev, w)
@@ -120,8 +120,8 @@ def test_forces_full_size_golden(pdmk, torch_dev):
     data = np.loadtxt(path)
     idx = data[:, 0].astype(np.int64)
     L, src, q = workloads.clustered3d(1_000_000, seed=2)
-    plan = pdmk.Plan(L, eps=1e-6, kappa=7.0)
-    pot, grad = plan.eval(_t(torch_dev, src), _t(torch_dev, q), want_grad=True)
+    plan = pdmk.Plan(L, eps=1e-6, grad=True, kappa=7.0)
+    pot, grad = plan.eval(_t(torch_dev, src), _t(torch_dev, q))
     assert ewald.rel_l2(pot.cpu().numpy()[idx], data[:, 1]) <= 1e-6
     assert ewald.rel_l2(grad.cpu().numpy()[idx], data[:, 2:5]) <= 1e-5
 
