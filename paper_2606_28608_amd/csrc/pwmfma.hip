@@ -49,78 +49,154 @@ template <> struct Mfma<double> {
   static __device__ int row(int l, int r) { return (l >> 4) + 4 * r; }
 };
 
-// C (M x N) = A (M x K) B (K x N) over 16x16 tiles dealt round-robin to the
-// block's waves.  A(m, k), B(k, n) read one element; out(m, n, v) stores one.
-template <class Real, class AF, class BF, class OF>
-__device__ inline void tile_gemm(int M, int N, int K, AF A, BF B, OF out) {
-  using MF = Mfma<Real>;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
-  const int tn = (N + 15) >> 4, nt = ((M + 15) >> 4) * tn, ks = (K + 3) >> 2;
-  const int li = lane & 15, lk = lane >> 4;
-  for (int t = wave; t < nt; t += nw) {
-    const int r0 = (t / tn) << 4, c0 = (t % tn) << 4;
-    const int ar = r0 + li, bc = c0 + li;
-    const bool arow = ar < M, bcol = bc < N;
-    typename MF::V acc = {0, 0, 0, 0};
-#pragma unroll 4
-    for (int s = 0; s < ks; ++s) {
-      const int k = (s << 2) + lk;
-      const bool kin = k < K;
-      const Real a = (arow && kin) ? A(ar, k) : (Real)0;
-      const Real b = (kin && bcol) ? B(k, bc) : (Real)0;
-      acc = MF::op(a, b, acc);
-    }
-    if (bcol)
-      for (int r = 0; r < 4; ++r) {
-        const int row = r0 + MF::row(lane, r);
-        if (row < M) out(row, bc, acc[r]);
-      }
-  }
-}
+// Compile-time shape of one (p, J) pair.
+template <int P, int J>
+struct PwShape {
+  static constexpr int N1 = 2 * J + 1;                 // modes per axis
+  static constexpr int KA = (P + 3) & ~3;              // stage A depth (a)
+  static constexpr int K2P = (2 * P + 3) & ~3;         // depth over (ri, axis point)
+  static constexpr int K2N = (2 * N1 + 3) & ~3;        // depth over (mode, ri)
+  static constexpr int T2N = (2 * N1 + 15) / 16;       // 16-tiles over 2 N1
+  static constexpr int T2P = (2 * P + 15) / 16;        // 16-tiles over 2 P
+  static constexpr int TP = (P + 15) / 16;             // 16-tiles over P
+  static constexpr int TPP = (P * P + 15) / 16;        // 16-tiles over P^2
+};
 
-// Outgoing plane waves of the non-leaf boxes of one level (one block per box).
-template <class Real>
-__global__ __launch_bounds__(256) void k_pw_out_mfma(KParams kp, const Real* __restrict__ Q,
+__host__ __device__ constexpr int align16(int n) { return (n + 15) & ~15; }
+
+// Outgoing plane waves of the non-leaf boxes of one level (one block of 4
+// waves per box).  The constant operands of stages B and C stay in registers
+// for a whole group; the data operands are read from LDS without bounds tests
+// (padding rows/columns of the LDS matrices are zero or only reach discarded
+// outputs).
+template <class Real, int P, int J>
+__global__ __launch_bounds__(256) void k_pw_out_mfma(const Real* __restrict__ Q,
                                                      const Real* __restrict__ TA,
                                                      const Real* __restrict__ TB,
                                                      const Real* __restrict__ TC,
                                                      Real* __restrict__ S, int G, int sX,
                                                      int sZ) {
+  using SH = PwShape<P, J>;
+  using MF = Mfma<Real>;
+  using V = typename MF::V;
+  constexpr int N1 = SH::N1, PP = P * P;
   extern __shared__ __align__(16) unsigned char smraw[];
-  const int p = kp.p, J = kp.J, n = 2 * J + 1, p2 = p * p;
-  Real* X = reinterpret_cast<Real*>(smraw);   // 2p rows x sX
-  Real* Z = X + 2 * p * sX;                   // G n rows x sZ
+  Real* X = reinterpret_cast<Real*>(smraw);   // K2P rows x sX: rows (ri, b), cols (jj, c)
+  Real* Z = X + SH::K2P * sX;                 // align16(G N1) rows x sZ: cols (ro, c)
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int li = lane & 15, lk = lane >> 4;
   const int k = blockIdx.x;
-  const Real* Qk = Q + (int64_t)k * p * p2;
-  Real* Sk = S + (int64_t)k * (J + 1) * n * n * 2;
+  // zero the padding rows of X and columns of Z once (never written later)
+  for (int e = threadIdx.x; e < (SH::K2P - 2 * P) * sX; e += 256) X[2 * P * sX + e] = 0;
+  for (int e = threadIdx.x; e < align16(G * N1) * (SH::K2P - 2 * P); e += 256) {
+    const int r = e / (SH::K2P - 2 * P), c = e - r * (SH::K2P - 2 * P);
+    Z[r * sZ + 2 * P + c] = 0;
+  }
+  const Real* Qk = Q + (int64_t)k * P * PP;
+  Real* Sk = S + (int64_t)k * (J + 1) * N1 * N1 * 2;
   for (int j0b = 0; j0b <= J; j0b += G) {
     const int g = min(G, J + 1 - j0b);
-    tile_gemm<Real>(
-        2 * g, p2, p,
-        [&](int m, int a) {
-          const int ri = m >= g, jj = m - ri * g;
-          return TA[(ri * (J + 1) + j0b + jj) * p + a];
-        },
-        [&](int a, int e) { return Qk[a * p2 + e]; },
-        [&](int m, int e, Real v) {
-          const int ri = m >= g, jj = m - ri * g;
-          const int b = e / p, c = e - b * p;
-          X[(ri * p + b) * sX + jj * p + c] = v;
-        });
+    // stage A (transposed): X^T[bc][(ri,jj)] = sum_a Q[a][bc] TA[(ri, j0b+jj)][a]
+    {
+      Real bf[SH::KA / 4];
+#pragma unroll
+      for (int s = 0; s < SH::KA / 4; ++s) {
+        const int a = 4 * s + lk;
+        const int ri = li >= g, jj = li - ri * g;
+        bf[s] = (a < P && li < 2 * g) ? TA[(ri * (J + 1) + j0b + jj) * P + a] : (Real)0;
+      }
+      for (int t = wave; t < SH::TPP; t += 4) {
+        const int bc = 16 * t + li;
+        V acc = {0, 0, 0, 0};
+#pragma unroll
+        for (int s = 0; s < SH::KA / 4; ++s) {
+          const int a = 4 * s + lk;
+          const Real av = (a < P && bc < PP) ? Qk[a * PP + bc] : (Real)0;
+          acc = MF::op(av, bf[s], acc);
+        }
+        // acc element r: row bc' = 16 t + row(lane, r), column (ri, jj) = li
+        const int ri = li >= g, jj = li - ri * g;
+        if (li < 2 * g)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int e = 16 * t + MF::row(lane, r);
+            if (e < PP) {
+              const int b = e / P, c = e - b * P;
+              X[(ri * P + b) * sX + jj * P + c] = acc[r];
+            }
+          }
+      }
+    }
     __syncthreads();
-    tile_gemm<Real>(
-        2 * n, g * p, 2 * p, [&](int m, int q) { return TB[m * 2 * p + q]; },
-        [&](int q, int e) { return X[q * sX + e]; },
-        [&](int m, int e, Real v) {
-          const int ro = m >= n, j1 = m - ro * n;
-          const int jj = e / p, c = e - jj * p;
-          Z[(jj * n + j1) * sZ + ro * p + c] = v;
-        });
+    // stage B: Z[(jj,j1)][(ro,c)] = sum_(ri,b) TB[(ro,j1)][(ri,b)] X[(ri,b)][(jj,c)]
+    {
+      Real af[SH::T2N][SH::K2P / 4];
+#pragma unroll
+      for (int m = 0; m < SH::T2N; ++m)
+#pragma unroll
+        for (int s = 0; s < SH::K2P / 4; ++s)
+          af[m][s] = TB[(16 * m + li) * SH::K2P + 4 * s + lk];
+      const int nt = (g * P + 15) >> 4;
+      for (int t = wave; t < nt; t += 4) {
+        const Real* xb = X + lk * sX + 16 * t + li;
+        V acc[SH::T2N];
+#pragma unroll
+        for (int m = 0; m < SH::T2N; ++m) acc[m] = V{0, 0, 0, 0};
+#pragma unroll
+        for (int s = 0; s < SH::K2P / 4; ++s) {
+          const Real bv = xb[4 * s * sX];
+#pragma unroll
+          for (int m = 0; m < SH::T2N; ++m) acc[m] = MF::op(af[m][s], bv, acc[m]);
+        }
+        const int e = 16 * t + li;   // column (jj, c)
+        if (e < g * P) {
+          const int jj = e / P, c = e - jj * P;
+#pragma unroll
+          for (int m = 0; m < SH::T2N; ++m)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+              const int row = 16 * m + MF::row(lane, r);   // (ro, j1)
+              if (row < 2 * N1) {
+                const int ro = row >= N1, j1 = row - ro * N1;
+                Z[(jj * N1 + j1) * sZ + ro * P + c] = acc[m][r];
+              }
+            }
+        }
+      }
+    }
     __syncthreads();
-    tile_gemm<Real>(
-        g * n, 2 * n, 2 * p, [&](int m, int q) { return Z[m * sZ + q]; },
-        [&](int q, int e) { return TC[q * 2 * n + e]; },
-        [&](int m, int e, Real v) { Sk[(int64_t)(j0b * n + m) * 2 * n + e] = v; });
+    // stage C: S[(j0,j1)][2 j2 + ro] = sum_(ri,c) Z[(jj,j1)][(ri,c)] TC[(ri,c)][2 j2 + ro]
+    {
+      Real bf[SH::T2N][SH::K2P / 4];
+#pragma unroll
+      for (int m = 0; m < SH::T2N; ++m)
+#pragma unroll
+        for (int s = 0; s < SH::K2P / 4; ++s)
+          bf[m][s] = TC[(4 * s + lk) * (16 * SH::T2N) + 16 * m + li];
+      const int mt = (g * N1 + 15) >> 4;
+      for (int t = wave; t < mt; t += 4) {
+        const Real* zr = Z + (16 * t + li) * sZ + lk;
+        V acc[SH::T2N];
+#pragma unroll
+        for (int m = 0; m < SH::T2N; ++m) acc[m] = V{0, 0, 0, 0};
+#pragma unroll
+        for (int s = 0; s < SH::K2P / 4; ++s) {
+          const Real av = zr[4 * s];
+#pragma unroll
+          for (int m = 0; m < SH::T2N; ++m) acc[m] = MF::op(av, bf[m][s], acc[m]);
+        }
+#pragma unroll
+        for (int m = 0; m < SH::T2N; ++m) {
+          const int col = 16 * m + li;
+          if (col < 2 * N1)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+              const int row = 16 * t + MF::row(lane, r);
+              if (row < g * N1) Sk[(int64_t)(j0b * N1 + row) * 2 * N1 + col] = acc[m][r];
+            }
+        }
+      }
+    }
     __syncthreads();
   }
 }
@@ -128,24 +204,28 @@ __global__ __launch_bounds__(256) void k_pw_out_mfma(KParams kp, const Real* __r
 // Incoming plane waves of the non-leaf boxes of one level that hold targets:
 // translation from the colleagues that have children, scaled by the
 // difference-kernel multiplier, then the three conjugate contractions into
-// the box's proxy potential.  MAXT = accumulator tiles of Phi per wave.
-template <class Real, int MAXT>
+// the box's proxy potential (accumulated in registers across the groups).
+template <class Real, int P, int J>
 __global__ __launch_bounds__(256) void k_pw_in_mfma(
     KParams kp, Level L, const Real* __restrict__ S, const Real* __restrict__ TA2,
     const Real* __restrict__ TB2, const Real* __restrict__ TC2, const double* __restrict__ dtab,
     double levfac, Real* __restrict__ Phi, unsigned long long* __restrict__ npairs, int G,
     int sI, int sY, int sW) {
+  using SH = PwShape<P, J>;
   using MF = Mfma<Real>;
+  using V = typename MF::V;
+  constexpr int N1 = SH::N1, PP = P * P;
+  constexpr int NACC = (SH::TPP + 3) / 4;   // Phi column tiles per wave
   extern __shared__ __align__(16) unsigned char smraw[];
   __shared__ int ckc[27], cph[27][3];
   __shared__ int ncol;
-  const int p = kp.p, J = kp.J, n = 2 * J + 1, p2 = p * p;
   const int k = blockIdx.x;
   const int b = L.nl_box[k];
   if (L.tend[b] <= L.tbeg[b]) return;   // no targets below this box
-  Real* I = reinterpret_cast<Real*>(smraw);   // G n rows x sI   (W aliases it)
-  Real* W = I;                                // 2G rows x sW
-  Real* Y = I + (size_t)G * n * sI;           // 2n rows x sY
+  Real* I = reinterpret_cast<Real*>(smraw);      // align16(G N1) rows x sI: cols 2 j2 + ri
+  Real* Y = I + align16(G * N1) * sI;            // K2N rows x sY: rows 2 j1 + ri, cols (jj, c)
+  Real* W = Y + SH::K2N * sY;                    // align(2G, 4) rows x sW: cols (b, c)
+  const int wrows = (2 * G + 3) & ~3;
   if (threadIdx.x == 0) {
     int m = 0;
     for (int sl = 0; sl < 27; ++sl) {
@@ -160,28 +240,36 @@ __global__ __launch_bounds__(256) void k_pw_in_mfma(
     ncol = m;
     if (npairs) atomicAdd(npairs, (unsigned long long)m);
   }
+  // zero the padding: I columns >= 2 N1, Y rows >= 2 N1, all of W
+  for (int e = threadIdx.x; e < align16(G * N1) * (SH::K2N - 2 * N1); e += 256) {
+    const int r = e / (SH::K2N - 2 * N1), c = e - r * (SH::K2N - 2 * N1);
+    I[r * sI + 2 * N1 + c] = 0;
+  }
+  for (int e = threadIdx.x; e < (SH::K2N - 2 * N1) * sY; e += 256) Y[2 * N1 * sY + e] = 0;
+  for (int e = threadIdx.x; e < wrows * sW; e += 256) W[e] = 0;
   __syncthreads();
   const int nc = ncol;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int li = lane & 15, lk = lane >> 4;
-  const int tn = (p2 + 15) >> 4, ntile = ((p + 15) >> 4) * tn;
-  typename MF::V acc[MAXT];
+  V acc[SH::TP][NACC];
 #pragma unroll
-  for (int i = 0; i < MAXT; ++i) acc[i] = typename MF::V{0, 0, 0, 0};
-  const int64_t msz = (int64_t)(J + 1) * n * n;   // complex entries per box
+  for (int m = 0; m < SH::TP; ++m)
+#pragma unroll
+    for (int i = 0; i < NACC; ++i) acc[m][i] = V{0, 0, 0, 0};
+  const int64_t msz = (int64_t)(J + 1) * N1 * N1;   // complex entries per box
   const Real w3r[3] = {(Real)1, (Real)-0.5, (Real)-0.5};
   const Real w3i[3] = {(Real)0, (Real)0.8660254037844386, (Real)-0.8660254037844386};
   for (int j0b = 0; j0b <= J; j0b += G) {
     const int g = min(G, J + 1 - j0b);
     // translation: I[(jj,j1)][2j2+ri] = c(|j|^2) sum_C omega^{j.delta} S_C[j0][j1][j2]
-    for (int e = threadIdx.x; e < g * n * n; e += blockDim.x) {
-      const int jj = e / (n * n), r = e - jj * n * n;
-      const int j1i = r / n, j2i = r - j1i * n;
+    for (int e = threadIdx.x; e < g * N1 * N1; e += blockDim.x) {
+      const int jj = e / (N1 * N1), r = e - jj * N1 * N1;
+      const int j1i = r / N1, j2i = r - j1i * N1;
       const int j0 = j0b + jj, j1 = j1i - J, j2 = j2i - J;
       const int nn = j0 * j0 + j1 * j1 + j2 * j2;
       Real ar = 0, ai = 0;
       if (nn <= J * J) {
-        const int64_t off = ((int64_t)j0 * n * n + r) * 2;
+        const int64_t off = ((int64_t)j0 * N1 * N1 + r) * 2;
         for (int m = 0; m < nc; ++m) {
           int ph = (j0 * cph[m][0] + j1 * cph[m][1] + j2 * cph[m][2]) % 3;
           if (ph < 0) ph += 3;
@@ -196,81 +284,153 @@ __global__ __launch_bounds__(256) void k_pw_in_mfma(
         ar *= cf;
         ai *= cf;
       }
-      Real* dst = I + (jj * n + j1i) * sI + 2 * j2i;
+      Real* dst = I + (jj * N1 + j1i) * sI + 2 * j2i;
       dst[0] = ar;
       dst[1] = ai;
     }
     __syncthreads();
-    tile_gemm<Real>(
-        g * n, 2 * p, 2 * n, [&](int m, int q) { return I[m * sI + q]; },
-        [&](int q, int e) { return TC2[q * 2 * p + e]; },
-        [&](int m, int e, Real v) {
-          const int jj = m / n, j1 = m - jj * n;
-          Y[(2 * j1 + (e & 1)) * sY + jj * p + (e >> 1)] = v;
-        });
-    __syncthreads();
-    tile_gemm<Real>(
-        2 * p, g * p, 2 * n, [&](int m, int q) { return TB2[m * 2 * n + q]; },
-        [&](int q, int e) { return Y[q * sY + e]; },
-        [&](int m, int e, Real v) {
-          const int jj = e / p, c = e - jj * p;
-          W[(2 * jj + (m & 1)) * sW + (m >> 1) * p + c] = v;
-        });
-    __syncthreads();
-    // Phi[a][(b,c)] += sum_q TA2[a][2 j0b + q] W[q][(b,c)], accumulators in registers
-    const int ks = (2 * g + 3) >> 2;
+    // stage C': Y[2 j1 + ro][(jj, c)] = sum_q I[(jj,j1)][q] TC2[q][2 c + ro]
+    {
+      Real bf[SH::T2P][SH::K2N / 4];
 #pragma unroll
-    for (int i = 0; i < MAXT; ++i) {
-      const int t = wave + 4 * i;
-      if (t < ntile) {
-        const int ar = ((t / tn) << 4) + li, bc = ((t % tn) << 4) + li;
-        for (int s = 0; s < ks; ++s) {
-          const int q = (s << 2) + lk;
-          const bool qin = q < 2 * g;
-          const Real a = (ar < p && qin) ? TA2[ar * 2 * (J + 1) + 2 * j0b + q] : (Real)0;
-          const Real bv = (qin && bc < p2) ? W[q * sW + bc] : (Real)0;
-          acc[i] = MF::op(a, bv, acc[i]);
+      for (int m = 0; m < SH::T2P; ++m)
+#pragma unroll
+        for (int s = 0; s < SH::K2N / 4; ++s)
+          bf[m][s] = TC2[(4 * s + lk) * (16 * SH::T2P) + 16 * m + li];
+      const int mt = (g * N1 + 15) >> 4;
+      for (int t = wave; t < mt; t += 4) {
+        const Real* ir = I + (16 * t + li) * sI + lk;
+        V a2[SH::T2P];
+#pragma unroll
+        for (int m = 0; m < SH::T2P; ++m) a2[m] = V{0, 0, 0, 0};
+#pragma unroll
+        for (int s = 0; s < SH::K2N / 4; ++s) {
+          const Real av = ir[4 * s];
+#pragma unroll
+          for (int m = 0; m < SH::T2P; ++m) a2[m] = MF::op(av, bf[m][s], a2[m]);
+        }
+#pragma unroll
+        for (int m = 0; m < SH::T2P; ++m) {
+          const int col = 16 * m + li;   // 2 c + ro
+          if (col < 2 * P)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+              const int row = 16 * t + MF::row(lane, r);   // (jj, j1)
+              if (row < g * N1) {
+                const int jj = row / N1, j1 = row - jj * N1;
+                Y[(2 * j1 + (col & 1)) * sY + jj * P + (col >> 1)] = a2[m][r];
+              }
+            }
+        }
+      }
+    }
+    __syncthreads();
+    // stage B': W[2 jj + ro][(b, c)] = sum_q TB2[2 b + ro][q] Y[q][(jj, c)]
+    {
+      Real af[SH::T2P][SH::K2N / 4];
+#pragma unroll
+      for (int m = 0; m < SH::T2P; ++m)
+#pragma unroll
+        for (int s = 0; s < SH::K2N / 4; ++s)
+          af[m][s] = TB2[(16 * m + li) * SH::K2N + 4 * s + lk];
+      const int nt = (g * P + 15) >> 4;
+      for (int t = wave; t < nt; t += 4) {
+        const Real* yb = Y + lk * sY + 16 * t + li;
+        V a2[SH::T2P];
+#pragma unroll
+        for (int m = 0; m < SH::T2P; ++m) a2[m] = V{0, 0, 0, 0};
+#pragma unroll
+        for (int s = 0; s < SH::K2N / 4; ++s) {
+          const Real bv = yb[4 * s * sY];
+#pragma unroll
+          for (int m = 0; m < SH::T2P; ++m) a2[m] = MF::op(af[m][s], bv, a2[m]);
+        }
+        const int e = 16 * t + li;   // (jj, c)
+        if (e < g * P) {
+          const int jj = e / P, c = e - jj * P;
+#pragma unroll
+          for (int m = 0; m < SH::T2P; ++m)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+              const int row = 16 * m + MF::row(lane, r);   // 2 b + ro
+              if (row < 2 * P) W[(2 * jj + (row & 1)) * sW + (row >> 1) * P + c] = a2[m][r];
+            }
+        }
+      }
+    }
+    __syncthreads();
+    // stage A': Phi[a][bc] += sum_q TA2[a][2 j0b + q] W[q][bc], q < 2g
+    {
+      Real af[SH::TP][4];
+#pragma unroll
+      for (int m = 0; m < SH::TP; ++m)
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+          const int a = 16 * m + li, q = 4 * s + lk;
+          af[m][s] = (a < P && q < 2 * g) ? TA2[a * 2 * (J + 1) + 2 * j0b + q] : (Real)0;
+        }
+      const int ks = (2 * g + 3) >> 2;
+#pragma unroll
+      for (int i = 0; i < NACC; ++i) {
+        const int t = wave + 4 * i;
+        if (t < SH::TPP) {
+          const Real* wb = W + lk * sW + 16 * t + li;
+#pragma unroll
+          for (int s = 0; s < 4; ++s)
+            if (s < ks) {
+              const Real bv = wb[4 * s * sW];
+#pragma unroll
+              for (int m = 0; m < SH::TP; ++m) acc[m][i] = MF::op(af[m][s], bv, acc[m][i]);
+            }
         }
       }
     }
     __syncthreads();
   }
-  Real* out = Phi + (int64_t)k * p * p2;
+  Real* out = Phi + (int64_t)k * P * PP;
 #pragma unroll
-  for (int i = 0; i < MAXT; ++i) {
+  for (int i = 0; i < NACC; ++i) {
     const int t = wave + 4 * i;
-    if (t < ntile) {
-      const int bc = ((t % tn) << 4) + li;
-      if (bc < p2)
+    const int bc = 16 * t + li;
+    if (t < SH::TPP && bc < PP)
+#pragma unroll
+      for (int m = 0; m < SH::TP; ++m)
+#pragma unroll
         for (int r = 0; r < 4; ++r) {
-          const int row = ((t / tn) << 4) + MF::row(lane, r);
-          if (row < p) out[row * p2 + bc] += acc[i][r];
+          const int a = 16 * m + MF::row(lane, r);
+          if (a < P) out[a * PP + bc] += acc[m][i][r];
         }
-    }
   }
 }
 
 // ------------------------------------------------------------------ host
+// (p, J) pairs with matrix-core kernels: the defaults at eps = 1e-3 and 1e-6.
+static bool pw_mfma_supported(int p, int J) {
+  return (p == 22 && J == 16) || (p == 13 && J == 9);
+}
+
+static int stride_a(int n) { return n | 1; }   // rows read across lanes: odd stride
 static int stride_b(int n, size_t rs) {
-  // row stride of a matrix read along rows (B operand): lanes 0-15 and 16-31
-  // then fall on disjoint halves of the 32 LDS banks
+  // rows read along a row (B operand): lanes 0-15 and 16-31 fall on disjoint
+  // halves of the LDS banks
   return rs == 4 ? ((n + 31) & ~31) + 16 : ((n + 15) & ~15) + 8;
 }
 
 PwMfmaShape pw_mfma_shape(int p, int J, size_t rs) {
   PwMfmaShape s{};
-  const int n = 2 * J + 1;
-  const int tiles = ((p + 15) / 16) * ((p * p + 15) / 16);
-  s.ok = tiles <= 4 * kPwMaxTiles;
+  s.ok = pw_mfma_supported(p, J);
   if (!s.ok) return s;
+  const int n = 2 * J + 1;
+  const int k2p = (2 * p + 3) & ~3, k2n = (2 * n + 3) & ~3;
   const size_t budget = 80 * 1024, hard = 150 * 1024;
   auto out_lds = [&](int g) {
-    return ((size_t)2 * p * stride_b(g * p, rs) + (size_t)g * n * (2 * p + 1)) * rs;
+    return ((size_t)k2p * stride_b(align16(g * p), rs) +
+            (size_t)align16(g * n) * stride_a(k2p)) * rs;
   };
   auto in_lds = [&](int g) {
-    const size_t iw = std::max((size_t)g * n * (2 * n + 1),
-                               (size_t)2 * g * stride_b(p * p, rs));
-    return (iw + (size_t)2 * n * stride_b(g * p, rs)) * rs;
+    return ((size_t)align16(g * n) * stride_a(k2n) +
+            (size_t)k2n * stride_b(align16(g * p), rs) +
+            (size_t)((2 * g + 3) & ~3) * stride_b(align16(p * p), rs)) * rs;
   };
   auto pick = [&](auto lds, int& G, size_t& bytes) {
     int gmax = 0;
@@ -287,45 +447,54 @@ PwMfmaShape pw_mfma_shape(int p, int J, size_t rs) {
   };
   s.ok = pick(out_lds, s.g_out, s.lds_out) && pick(in_lds, s.g_in, s.lds_in);
   if (!s.ok) return s;
-  s.sX = stride_b(s.g_out * p, rs);
-  s.sZ = 2 * p + 1;
-  s.sI = 2 * n + 1;
-  s.sY = stride_b(s.g_in * p, rs);
-  s.sW = stride_b(p * p, rs);
+  s.sX = stride_b(align16(s.g_out * p), rs);
+  s.sZ = stride_a(k2p);
+  s.sI = stride_a(k2n);
+  s.sY = stride_b(align16(s.g_in * p), rs);
+  s.sW = stride_b(align16(p * p), rs);
   return s;
 }
 
-// Real matrices of the complex contractions (layouts in the file header).
+// Real matrices of the complex contractions (layouts in the file header),
+// zero-padded to the tile grid the kernels read without bounds tests.
 template <class Real>
 static std::vector<Real> pw_mfma_tables_t(const std::vector<double>& nodes, int p, int J,
                                           size_t off[6]) {
   const int n = 2 * J + 1;
+  const int k2p = (2 * p + 3) & ~3, k2n = (2 * n + 3) & ~3;
+  const int r2n = 16 * ((2 * n + 15) / 16), r2p = 16 * ((2 * p + 15) / 16);
   auto Fr = [&](int j, int x) { return std::cos(-kPi * j * nodes[x] / 3.0); };
   auto Fi = [&](int j, int x) { return std::sin(-kPi * j * nodes[x] / 3.0); };
   std::vector<Real> t;
-  // TA: 2(J+1) x p
+  // TA: 2(J+1) x p, rows (ri, j0)
   off[0] = t.size();
   for (int ri = 0; ri < 2; ++ri)
     for (int j0 = 0; j0 <= J; ++j0)
       for (int a = 0; a < p; ++a) t.push_back((Real)(ri ? Fi(j0, a) : Fr(j0, a)));
-  // TB: 2n x 2p, [[Fr, -Fi], [Fi, Fr]]
+  // TB: r2n x k2p, rows (ro, j1), columns (ri, b): [[Fr, -Fi], [Fi, Fr]]
   off[1] = t.size();
-  for (int ro = 0; ro < 2; ++ro)
-    for (int j1 = 0; j1 < n; ++j1)
-      for (int ri = 0; ri < 2; ++ri)
-        for (int b = 0; b < p; ++b) {
-          const double fr = Fr(j1 - J, b), fi = Fi(j1 - J, b);
-          t.push_back((Real)(ro == ri ? fr : (ro ? fi : -fi)));
-        }
-  // TC: 2p x 2n, rows (ri, c), columns 2 j2 + ro
+  for (int row = 0; row < r2n; ++row)
+    for (int col = 0; col < k2p; ++col) {
+      double v = 0;
+      if (row < 2 * n && col < 2 * p) {
+        const int ro = row / n, j1 = row % n, ri = col / p, b = col % p;
+        const double fr = Fr(j1 - J, b), fi = Fi(j1 - J, b);
+        v = ro == ri ? fr : (ro ? fi : -fi);
+      }
+      t.push_back((Real)v);
+    }
+  // TC: k2p x r2n, rows (ri, c), columns 2 j2 + ro
   off[2] = t.size();
-  for (int ri = 0; ri < 2; ++ri)
-    for (int c = 0; c < p; ++c)
-      for (int j2 = 0; j2 < n; ++j2)
-        for (int ro = 0; ro < 2; ++ro) {
-          const double fr = Fr(j2 - J, c), fi = Fi(j2 - J, c);
-          t.push_back((Real)(ri == ro ? fr : (ri ? -fi : fi)));
-        }
+  for (int row = 0; row < k2p; ++row)
+    for (int col = 0; col < r2n; ++col) {
+      double v = 0;
+      if (row < 2 * p && col < 2 * n) {
+        const int ri = row / p, c = row % p, j2 = col / 2, ro = col % 2;
+        const double fr = Fr(j2 - J, c), fi = Fi(j2 - J, c);
+        v = ri == ro ? fr : (ri ? -fi : fi);
+      }
+      t.push_back((Real)v);
+    }
   // TA2: p x 2(J+1), columns 2 j0 + ri, weight 2 for j0 > 0
   off[3] = t.size();
   for (int a = 0; a < p; ++a)
@@ -334,29 +503,36 @@ static std::vector<Real> pw_mfma_tables_t(const std::vector<double>& nodes, int 
         const double w = j0 == 0 ? 1.0 : 2.0;
         t.push_back((Real)(w * (ri ? Fi(j0, a) : Fr(j0, a))));
       }
-  // TB2: 2p x 2n, rows 2 b + ro, columns 2 j1 + ri: conj(F) acting on Y
+  // TB2: r2p x k2n, rows 2 b + ro, columns 2 j1 + ri: conj(F) acting on Y
   off[4] = t.size();
-  for (int b = 0; b < p; ++b)
-    for (int ro = 0; ro < 2; ++ro)
-      for (int j1 = 0; j1 < n; ++j1)
-        for (int ri = 0; ri < 2; ++ri) {
-          const double fr = Fr(j1 - J, b), fi = Fi(j1 - J, b);
-          t.push_back((Real)(ro == ri ? fr : (ro ? -fi : fi)));
-        }
-  // TC2: 2n x 2p, rows 2 j2 + ri, columns 2 c + ro: I conj(F)^T
+  for (int row = 0; row < r2p; ++row)
+    for (int col = 0; col < k2n; ++col) {
+      double v = 0;
+      if (row < 2 * p && col < 2 * n) {
+        const int b = row / 2, ro = row % 2, j1 = col / 2, ri = col % 2;
+        const double fr = Fr(j1 - J, b), fi = Fi(j1 - J, b);
+        v = ro == ri ? fr : (ro ? -fi : fi);
+      }
+      t.push_back((Real)v);
+    }
+  // TC2: k2n x r2p, rows 2 j2 + ri, columns 2 c + ro: I conj(F)^T
   off[5] = t.size();
-  for (int j2 = 0; j2 < n; ++j2)
-    for (int ri = 0; ri < 2; ++ri)
-      for (int c = 0; c < p; ++c)
-        for (int ro = 0; ro < 2; ++ro) {
-          const double fr = Fr(j2 - J, c), fi = Fi(j2 - J, c);
-          t.push_back((Real)(ri == ro ? fr : (ri ? fi : -fi)));
-        }
+  for (int row = 0; row < k2n; ++row)
+    for (int col = 0; col < r2p; ++col) {
+      double v = 0;
+      if (row < 2 * n && col < 2 * p) {
+        const int j2 = row / 2, ri = row % 2, c = col / 2, ro = col % 2;
+        const double fr = Fr(j2 - J, c), fi = Fi(j2 - J, c);
+        v = ri == ro ? fr : (ri ? fi : -fi);
+      }
+      t.push_back((Real)v);
+    }
   return t;
 }
 
 void pw_mfma_upload(pdmk_plan* P) {
   const int p = P->mp.porder, J = P->mp.npw;
+  if (!pw_mfma_supported(p, J)) return;
   std::vector<double> nodes, bw;
   cheb_nodes(p, nodes, bw);
   {
@@ -382,24 +558,36 @@ const float* pw_tables<float>(const pdmk_plan* P) { return P->d_pwt_f; }
 template <>
 const double* pw_tables<double>(const pdmk_plan* P) { return P->d_pwt_d; }
 
+template <class Real, int PP, int JJ>
+static void pw_mfma_launch(const pdmk_plan* P, const PwMfmaShape& sh, const Level& L, int nn,
+                           const void* proxy_q, void* S, void* proxy_phi, double levfac,
+                           unsigned long long* npairs, hipStream_t s) {
+  const Real* T = pw_tables<Real>(P);
+  const size_t* o = P->pwt_off;
+  PDMK_HIP(hipFuncSetAttribute((const void*)&k_pw_out_mfma<Real, PP, JJ>,
+                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh.lds_out));
+  PDMK_HIP(hipFuncSetAttribute((const void*)&k_pw_in_mfma<Real, PP, JJ>,
+                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh.lds_in));
+  hipLaunchKernelGGL((k_pw_out_mfma<Real, PP, JJ>), dim3(nn), dim3(256), sh.lds_out, s,
+                     static_cast<const Real*>(proxy_q), T + o[0], T + o[1], T + o[2],
+                     static_cast<Real*>(S), sh.g_out, sh.sX, sh.sZ);
+  hipLaunchKernelGGL((k_pw_in_mfma<Real, PP, JJ>), dim3(nn), dim3(256), sh.lds_in, s, P->kp,
+                     L, static_cast<const Real*>(S), T + o[3], T + o[4], T + o[5], P->d_dtab,
+                     levfac, static_cast<Real*>(proxy_phi), npairs, sh.g_in, sh.sI, sh.sY,
+                     sh.sW);
+}
+
 template <class Real>
 void pw_mfma_level(const pdmk_plan* P, const Level& L, int nn, const void* proxy_q, void* S,
                    void* proxy_phi, double levfac, unsigned long long* npairs, hipStream_t s) {
   const KParams& kp = P->kp;
   const PwMfmaShape sh = pw_mfma_shape(kp.p, kp.J, sizeof(Real));
-  const Real* T = pw_tables<Real>(P);
-  const size_t* o = P->pwt_off;
-  PDMK_HIP(hipFuncSetAttribute((const void*)&k_pw_out_mfma<Real>,
-                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh.lds_out));
-  PDMK_HIP(hipFuncSetAttribute((const void*)&k_pw_in_mfma<Real, kPwMaxTiles>,
-                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh.lds_in));
-  hipLaunchKernelGGL(k_pw_out_mfma<Real>, dim3(nn), dim3(256), sh.lds_out, s, kp,
-                     static_cast<const Real*>(proxy_q), T + o[0], T + o[1], T + o[2],
-                     static_cast<Real*>(S), sh.g_out, sh.sX, sh.sZ);
-  hipLaunchKernelGGL((k_pw_in_mfma<Real, kPwMaxTiles>), dim3(nn), dim3(256), sh.lds_in, s, kp,
-                     L, static_cast<const Real*>(S), T + o[3], T + o[4], T + o[5], P->d_dtab,
-                     levfac, static_cast<Real*>(proxy_phi), npairs, sh.g_in, sh.sI, sh.sY,
-                     sh.sW);
+  if (kp.p == 22 && kp.J == 16)
+    pw_mfma_launch<Real, 22, 16>(P, sh, L, nn, proxy_q, S, proxy_phi, levfac, npairs, s);
+  else if (kp.p == 13 && kp.J == 9)
+    pw_mfma_launch<Real, 13, 9>(P, sh, L, nn, proxy_q, S, proxy_phi, levfac, npairs, s);
+  else
+    throw Error{PDMK_ERR_UNSUPPORTED, "no matrix-core plane-wave kernel for this (p, J)"};
 }
 
 template void pw_mfma_level<float>(const pdmk_plan*, const Level&, int, const void*, void*, void*,
