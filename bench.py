@@ -27,12 +27,13 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# Published MI355X peaks used for the roofline of the residual-sum kernel
-# (vector ALU, not matrix cores: the kernel is an n-body sum with a
-# compactly supported polynomial kernel, not a contraction).
+# Published MI355X peaks: vector ALU for the residual sums (an n-body sum with
+# a compactly supported polynomial kernel), matrix cores for the plane-wave
+# contractions; both are 157.3 TFLOP/s in FP32 and 78.6 TFLOP/s in FP64.
 PEAK_TFLOPS = {"fp64": 78.6, "mixed": 157.3}
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_direct_traffic_shell3d_n1e7.json")
-NEAR_SRC = os.path.join(ROOT, "paper_2606_28608_amd", "csrc", "near.hip")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_shell3d_n1e7_eps1e-6.json")
+KERNEL_SRCS = [os.path.join(ROOT, "paper_2606_28608_amd", "csrc", f)
+               for f in ("near.hip", "pwmfma.hip")]
 
 
 def flop_per_pair(series_len: int):
@@ -68,21 +69,24 @@ def parse():
 
 
 def kernel_source_hash():
-    with open(NEAR_SRC, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+    h = hashlib.sha256()
+    for src in KERNEL_SRCS:
+        with open(src, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
 
 
-def load_traffic(mode):
-    """HBM bytes per launch of the residual kernel from the committed counter
-    runs, or None when the kernel source has changed since they were taken."""
+def load_traffic(mode, kernel):
+    """HBM bytes per launch of `kernel` from the committed counter runs, or
+    None when the kernel sources have changed since they were taken."""
     try:
         with open(TRAFFIC_FILE) as f:
             t = json.load(f)
     except (OSError, ValueError):
         return None
-    if t.get("near_hip_sha256_16") != kernel_source_hash():
+    if t.get("sources_sha256_16") != kernel_source_hash():
         return None
-    m = t.get("modes", {}).get(mode)
+    m = t.get("kernels", {}).get(kernel, {}).get(mode)
     return None if m is None else m.get("bytes_per_launch")
 
 
@@ -121,20 +125,68 @@ def run_mode(pdmk, L, S, Q, n, eps, precision, steps, warmup, gold):
             "stats": st, "stages_ms": {k: round(v, 3) for k, v in avg.items()}}
 
 
-def roofline(r, mode):
-    st = r["stats"]
-    t_launch = r["stages_ms"]["t_direct_ms"] * 1e-3
+def _ball_modes(J):
+    """Modes of the Hermitian half ball |j| <= J (j0 >= 0)."""
+    n = 0
+    for j0 in range(J + 1):
+        for j1 in range(-J, J + 1):
+            for j2 in range(-J, J + 1):
+                n += j0 * j0 + j1 * j1 + j2 * j2 <= J * J
+    return n
+
+
+def pw_fma_per_box(P, J):
+    """Useful real multiply-adds of the three axis contractions of one box
+    (one direction), counted from the shapes: (J+1) slabs of N1 x N1 modes,
+    P^3 proxy points, complex arithmetic as real products."""
+    N1 = 2 * J + 1
+    return (2 * (J + 1) * P * P * P + 2 * N1 * 2 * P * (J + 1) * P
+            + (J + 1) * N1 * 2 * P * 2 * N1)
+
+
+def roofline_all(r, mode, plan):
+    """Achieved rate of the main kernels: algorithmic flops of one call /
+    summed HIP-event duration of the kernel's launches in that call."""
+    st, sm = r["stats"], r["stages_ms"]
+    out = {}
     fv, fs = flop_per_pair(st["series_len"])
     flop = st["n_direct_pairs"] * fv + st["n_support_pairs"] * fs
-    achieved = flop / t_launch / 1e12 if t_launch > 0 else 0.0
-    peak = PEAK_TFLOPS[mode]
-    traffic = load_traffic(mode)
-    return {"bound": "alu", "kernel": "k_direct", "achieved": achieved, "peak": peak,
-            "unit": "TFLOP/s", "frac": achieved / peak, "traffic": traffic,
-            "launch_ms": r["stages_ms"]["t_direct_ms"], "flop_per_launch": flop,
-            "pairs_visited": st["n_direct_pairs"], "pairs_in_support": st["n_support_pairs"],
-            "flop_per_visited_pair": fv, "flop_per_support_pair": fs,
-            "arith": "fp32" if mode == "mixed" else "fp64"}
+    t = sm["t_direct_ms"] * 1e-3
+    out["k_direct"] = {"bound": "alu", "achieved": flop / t / 1e12 if t > 0 else 0.0,
+                       "peak": PEAK_TFLOPS[mode], "unit": "TFLOP/s", "launch_ms": sm["t_direct_ms"],
+                       "launches": 1, "flop_per_launch": flop,
+                       "pairs_visited": st["n_direct_pairs"],
+                       "pairs_in_support": st["n_support_pairs"],
+                       "flop_per_visited_pair": fv, "flop_per_support_pair": fs}
+    P, J = plan["porder"], plan["npw"]
+    nb = _ball_modes(J)
+    tr = pw_fma_per_box(P, J)
+    flop_in = 2.0 * tr * st["n_pwin_boxes"] + 8.0 * nb * st["n_pw_pairs"]
+    flop_out = 2.0 * tr * st["n_pwout_boxes"]
+    nlev = st["n_levels"] - 1
+    for name, f, tms in (("k_pw_in", flop_in, sm.get("t_pwin_ms", 0.0)),
+                         ("k_pw_out", flop_out, sm.get("t_pwout_ms", 0.0))):
+        t = tms * 1e-3
+        out[name] = {"bound": "mfma", "achieved": f / t / 1e12 if t > 0 else 0.0,
+                     "peak": PEAK_TFLOPS[mode], "unit": "TFLOP/s", "launch_ms": tms / max(1, nlev),
+                     "launches": nlev, "flop_per_launch": f / max(1, nlev),
+                     "flop_per_box": 2.0 * tr}
+    for v in out.values():
+        v["frac"] = v["achieved"] / v["peak"]
+    return out
+
+
+def roofline(r, mode, plan):
+    """The bench's `roofline` object: the kernel with the largest time per call."""
+    allk = roofline_all(r, mode, plan)
+    dom = max(allk, key=lambda k: allk[k]["launch_ms"] * allk[k]["launches"])
+    d = dict(allk[dom])
+    d["kernel"] = dom
+    d["traffic"] = load_traffic(mode, dom)
+    d["arith"] = "fp32" if mode == "mixed" else "fp64"
+    d["kernels"] = {k: {kk: allk[k][kk] for kk in ("achieved", "frac", "launch_ms", "launches")}
+                    for k in allk}
+    return d
 
 
 def copy_calib():
@@ -170,7 +222,7 @@ def child(args):
     g = r.pop("plan")
     r["plan"] = {"kappa": g.kappa, "n_s": g.n_s, "porder": g.porder, "npw": g.npw,
                  "nufft_w": g.nufft_w, "fourier_grid": list(g.fgrid)}
-    r["roofline"] = roofline(r, args.precision)
+    r["roofline"] = roofline(r, args.precision, r["plan"])
     print(json.dumps(r))
 
 
@@ -251,7 +303,8 @@ def main():
         "stages_ms": r["stages_ms"],
         "counts": {k: r["stats"][k] for k in ("n_images", "n_levels", "n_boxes", "n_leaves",
                                              "n_nonleaf", "n_direct_pairs", "n_support_pairs",
-                                             "n_pw_pairs")},
+                                             "n_pw_pairs", "n_pwout_boxes", "n_pwin_boxes",
+                                             "workspace_bytes")},
         "roofline": r["roofline"],
         "cpu_baseline": cpu,
     }

@@ -215,6 +215,9 @@ typedef struct {
   int series_len;                   /* terms of the residual's Chebyshev series */
   double t_call_ms;                 /* host wall time of the whole call */
   int64_t workspace_bytes;          /* device workspace the call used */
+  int64_t n_pwout_boxes;            /* boxes given outgoing plane waves (all levels) */
+  int64_t n_pwin_boxes;             /* boxes given incoming plane waves (with targets) */
+  double t_pwout_ms, t_pwin_ms;     /* time of the outgoing / incoming plane-wave kernels */
 } pdmk_stats;
 int pdmk_plan_stats(const pdmk_plan* plan, pdmk_stats* out);
 int pdmk_batch_stats(const pdmk_batch* batch, int sys, pdmk_stats* out);

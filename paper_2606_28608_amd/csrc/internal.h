@@ -161,6 +161,8 @@ struct pdmk_plan {
   float* d_pwt_f = nullptr;
   double* d_pwt_d = nullptr;
   size_t pwt_off[6] = {0, 0, 0, 0, 0, 0};
+  int* d_ball = nullptr;        // modes of the half ball, then the slab starts
+  int nball = 0;
   bool pw_mfma = true;          // use the matrix-core plane-wave kernels when they fit
   // stages that run in FP32 in mixed mode: 1 residual sums, 2 proxies and
   // plane waves, 4 far-field window weights (all by default)
@@ -199,7 +201,8 @@ PwMfmaShape pw_mfma_shape(int p, int J, size_t real_size);
 void pw_mfma_upload(pdmk_plan* P);
 template <class Real>
 void pw_mfma_level(const pdmk_plan* P, const Level& L, int nn, const void* proxy_q, void* S,
-                   void* proxy_phi, double levfac, unsigned long long* npairs, hipStream_t s);
+                   void* proxy_phi, double levfac, unsigned long long* npairs, hipEvent_t mid,
+                   hipStream_t s);
 
 // stages (implemented in tree.hip / near.hip / far.hip)
 void stage_prepare(pdmk_plan* P, Eval& E, const double* src, const double* trg);

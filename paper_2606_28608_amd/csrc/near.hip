@@ -10,6 +10,8 @@
 // divided by the period volume.  Boxes represent their sources by proxy
 // charges on a p^d tensor Chebyshev grid, and their incoming field by proxy
 // potentials on the same grid.
+#include <array>
+
 #include "internal.h"
 
 namespace pdmk {
@@ -773,7 +775,10 @@ __global__ __launch_bounds__(256) void k_pw_in(KParams kp, Level L, const Cx<Rea
       ++m;
     }
     ncol = m;
-    if (npairs) atomicAdd(npairs, (unsigned long long)m);
+    if (npairs) {
+      atomicAdd(npairs, (unsigned long long)m);
+      atomicAdd(npairs + 1, 1ull);
+    }
   }
   for (int e = threadIdx.x; e < p3; e += 256) phi[e] = 0;
   for (int e = threadIdx.x; e < n * p; e += 256) f[e] = F[e];
@@ -1156,8 +1161,10 @@ static void near_impl(pdmk_plan* P, Eval& E, bool want_grad) {
     double2* bA = fused ? nullptr : E.alloc<double2>((size_t)maxnl * s1);
     double2* bB = (D == 3 && !fused) ? E.alloc<double2>((size_t)maxnl * s2) : nullptr;
     double2* bI = fused ? nullptr : E.alloc<double2>((size_t)maxnl * s3);
-    unsigned long long* npairs = E.alloc<unsigned long long>(1);
-    PDMK_HIP(hipMemsetAsync(npairs, 0, sizeof(unsigned long long), s));
+    // [0] colleague pairs translated, [1] boxes given incoming plane waves
+    unsigned long long* npairs = E.alloc<unsigned long long>(2);
+    PDMK_HIP(hipMemsetAsync(npairs, 0, 2 * sizeof(unsigned long long), s));
+    std::vector<std::array<hipEvent_t, 3>> pw_events;
     const C* Ftab = reinterpret_cast<const C*>(sizeof(Real) == 4 ? (const void*)P->d_Ff
                                                                  : (const void*)P->d_F);
     if (fused) {
@@ -1173,17 +1180,26 @@ static void near_impl(pdmk_plan* P, Eval& E, bool want_grad) {
       const double h = kp.rc / (double)(1 << l);
       const double levfac = D == 3 ? 1.0 / (3.0 * h) : 1.0;
       const int zz = D == 3 ? p : 1;
+      hipEvent_t pe[3];
+      for (auto& e : pe) PDMK_HIP(hipEventCreate(&e));
+      pw_events.push_back({pe[0], pe[1], pe[2]});
+      E.st.n_pwout_boxes += nn;
+      PDMK_HIP(hipEventRecord(pe[0], s));
       if (mfma) {
-        pw_mfma_level<Real>(P, L, nn, L.proxy_q, bS, L.proxy_phi, levfac, npairs, s);
+        pw_mfma_level<Real>(P, L, nn, L.proxy_q, bS, L.proxy_phi, levfac, npairs, pe[1], s);
+        PDMK_HIP(hipEventRecord(pe[2], s));
         continue;
       }
       if (fused) {
         hipLaunchKernelGGL(k_pw_out<Real>, dim3(nn), dim3(256), lds_out, s, kp, L,
                            static_cast<const Real*>(L.proxy_q), Ftab, bS);
+        PDMK_HIP(hipEventRecord(pe[1], s));
         hipLaunchKernelGGL(k_pw_in<Real>, dim3(nn), dim3(256), lds_in, s, kp, L, bS, Ftab,
                            P->d_dtab, levfac, static_cast<Real*>(L.proxy_phi), npairs);
+        PDMK_HIP(hipEventRecord(pe[2], s));
         continue;
       }
+      PDMK_HIP(hipEventRecord(pe[1], s));
       if (sizeof(Real) != 8) throw Error{PDMK_ERR_UNSUPPORTED, "FP32 proxies need the fused path"};
       double2* bSd = reinterpret_cast<double2*>(bS);
       // outgoing: proxy charges -> plane waves (Hermitian half on axis 0)
@@ -1214,6 +1230,7 @@ static void near_impl(pdmk_plan* P, Eval& E, bool want_grad) {
       hipLaunchKernelGGL((k_axis<true, 1>), dim3(nblk((int64_t)nn * pD, 256)), dim3(256), 0, s,
                          nn, J + 1, p, zz, 0, p, (const void*)bA, (void*)L.proxy_phi, P->d_F, J,
                          p, 1, 1);
+      PDMK_HIP(hipEventRecord(pe[2], s));
     }
     // downward pass: parent proxy potential -> non-leaf child proxy potential
     for (int l = 1; l < nlev; ++l) {
@@ -1224,10 +1241,19 @@ static void near_impl(pdmk_plan* P, Eval& E, bool want_grad) {
     }
     PDMK_HIP(hipMemcpyAsync(E.d_lev, E.lev.data(), sizeof(Level) * E.lev.size(),
                             hipMemcpyHostToDevice, s));
-    unsigned long long np = 0;
-    PDMK_HIP(hipMemcpyAsync(&np, npairs, sizeof(np), hipMemcpyDeviceToHost, s));
+    unsigned long long np[2] = {0, 0};
+    PDMK_HIP(hipMemcpyAsync(np, npairs, sizeof(np), hipMemcpyDeviceToHost, s));
     PDMK_HIP(hipStreamSynchronize(s));
-    E.st.n_pw_pairs = (int64_t)np;
+    E.st.n_pw_pairs = (int64_t)np[0];
+    E.st.n_pwin_boxes = (int64_t)np[1];
+    for (auto& pe : pw_events) {
+      float a = 0, b = 0;
+      PDMK_HIP(hipEventElapsedTime(&a, pe[0], pe[1]));
+      PDMK_HIP(hipEventElapsedTime(&b, pe[1], pe[2]));
+      E.st.t_pwout_ms += a;
+      E.st.t_pwin_ms += b;
+      for (auto& e : pe) (void)hipEventDestroy(e);
+    }
   }
   {
     unsigned long long ns = 0;

@@ -209,8 +209,9 @@ template <class Real, int P, int J>
 __global__ __launch_bounds__(256) void k_pw_in_mfma(
     KParams kp, Level L, const Real* __restrict__ S, const Real* __restrict__ TA2,
     const Real* __restrict__ TB2, const Real* __restrict__ TC2, const double* __restrict__ dtab,
-    double levfac, Real* __restrict__ Phi, unsigned long long* __restrict__ npairs, int G,
-    int sI, int sY, int sW) {
+    const int* __restrict__ ball, const int* __restrict__ ball_beg, double levfac,
+    Real* __restrict__ Phi, unsigned long long* __restrict__ npairs, int G, int sI, int sY,
+    int sW) {
   using SH = PwShape<P, J>;
   using MF = Mfma<Real>;
   using V = typename MF::V;
@@ -238,7 +239,10 @@ __global__ __launch_bounds__(256) void k_pw_in_mfma(
       ++m;
     }
     ncol = m;
-    if (npairs) atomicAdd(npairs, (unsigned long long)m);
+    if (npairs) {
+      atomicAdd(npairs, (unsigned long long)m);
+      atomicAdd(npairs + 1, 1ull);
+    }
   }
   // zero the padding: I columns >= 2 N1, Y rows >= 2 N1, all of W
   for (int e = threadIdx.x; e < align16(G * N1) * (SH::K2N - 2 * N1); e += 256) {
@@ -257,36 +261,50 @@ __global__ __launch_bounds__(256) void k_pw_in_mfma(
 #pragma unroll
     for (int i = 0; i < NACC; ++i) acc[m][i] = V{0, 0, 0, 0};
   const int64_t msz = (int64_t)(J + 1) * N1 * N1;   // complex entries per box
+  // colleague plane-wave bases and shift vectors delta mod 3
+  __shared__ const Real* cbase[27];
+  __shared__ int cdel[27];
+  if (threadIdx.x < nc) {
+    const int m = threadIdx.x;
+    cbase[m] = S + (int64_t)ckc[m] * msz * 2;
+    cdel[m] = ((cph[m][0] + 3) % 3) | (((cph[m][1] + 3) % 3) << 2) | (((cph[m][2] + 3) % 3) << 4);
+  }
   const Real w3r[3] = {(Real)1, (Real)-0.5, (Real)-0.5};
   const Real w3i[3] = {(Real)0, (Real)0.8660254037844386, (Real)-0.8660254037844386};
   for (int j0b = 0; j0b <= J; j0b += G) {
     const int g = min(G, J + 1 - j0b);
-    // translation: I[(jj,j1)][2j2+ri] = c(|j|^2) sum_C omega^{j.delta} S_C[j0][j1][j2]
-    for (int e = threadIdx.x; e < g * N1 * N1; e += blockDim.x) {
-      const int jj = e / (N1 * N1), r = e - jj * N1 * N1;
-      const int j1i = r / N1, j2i = r - j1i * N1;
-      const int j0 = j0b + jj, j1 = j1i - J, j2 = j2i - J;
+    // translation over the modes of the ball |j| <= J only (the rest of the
+    // slab group stays zero): I[(jj,j1)][2j2+ri] = c(|j|^2) sum_C omega^{j.delta} S_C[j]
+    for (int e = threadIdx.x; e < g * N1 * 2 * N1; e += blockDim.x) {
+      const int r = e / (2 * N1), c = e - r * (2 * N1);
+      I[r * sI + c] = 0;
+    }
+    __syncthreads();
+    const int eb = ball_beg[j0b], ee = ball_beg[j0b + g];
+    for (int e = eb + (int)threadIdx.x; e < ee; e += blockDim.x) {
+      const int code = ball[e];   // j0 | j1i << 8 | j2i << 16
+      const int j0 = code & 255, j1i = (code >> 8) & 255, j2i = code >> 16;
+      const int j1 = j1i - J, j2 = j2i - J;
       const int nn = j0 * j0 + j1 * j1 + j2 * j2;
+      const int p0 = j0 % 3, p1 = (j1 + 3 * J) % 3, p2 = (j2 + 3 * J) % 3;
+      const int64_t off = ((int64_t)j0 * N1 * N1 + j1i * N1 + j2i) * 2;
       Real ar = 0, ai = 0;
-      if (nn <= J * J) {
-        const int64_t off = ((int64_t)j0 * N1 * N1 + r) * 2;
-        for (int m = 0; m < nc; ++m) {
-          int ph = (j0 * cph[m][0] + j1 * cph[m][1] + j2 * cph[m][2]) % 3;
-          if (ph < 0) ph += 3;
-          const Real* v = S + (int64_t)ckc[m] * msz * 2 + off;
-          const Real vr = v[0], vi = v[1];
-          ar = fma(w3r[ph], vr, ar);
-          ar = fma(-w3i[ph], vi, ar);
-          ai = fma(w3r[ph], vi, ai);
-          ai = fma(w3i[ph], vr, ai);
-        }
-        const Real cf = (Real)(levfac * dtab[nn]);
-        ar *= cf;
-        ai *= cf;
+      for (int m = 0; m < nc; ++m) {
+        const int dl = cdel[m];
+        const int ph = (p0 * (dl & 3) + p1 * ((dl >> 2) & 3) + p2 * (dl >> 4)) % 3;
+        const Real* v = cbase[m] + off;
+        const Real vr = v[0], vi = v[1];
+        const Real cr = ph == 0 ? (Real)1 : (Real)-0.5;
+        const Real ci = ph == 0 ? (Real)0 : (ph == 1 ? w3i[1] : w3i[2]);
+        ar = fma(cr, vr, ar);
+        ar = fma(-ci, vi, ar);
+        ai = fma(cr, vi, ai);
+        ai = fma(ci, vr, ai);
       }
-      Real* dst = I + (jj * N1 + j1i) * sI + 2 * j2i;
-      dst[0] = ar;
-      dst[1] = ai;
+      const Real cf = (Real)(levfac * dtab[nn]);
+      Real* dst = I + ((j0 - j0b) * N1 + j1i) * sI + 2 * j2i;
+      dst[0] = ar * cf;
+      dst[1] = ai * cf;
     }
     __syncthreads();
     // stage C': Y[2 j1 + ro][(jj, c)] = sum_q I[(jj,j1)][q] TC2[q][2 c + ro]
@@ -533,6 +551,27 @@ static std::vector<Real> pw_mfma_tables_t(const std::vector<double>& nodes, int 
 void pw_mfma_upload(pdmk_plan* P) {
   const int p = P->mp.porder, J = P->mp.npw;
   if (!pw_mfma_supported(p, J)) return;
+  {
+    // modes of the Hermitian half ball |j| <= J, slab by slab (j0 | j1 << 8 | j2 << 16
+    // with j1, j2 shifted by J), followed by the J + 2 slab starts
+    const int n = 2 * J + 1;
+    std::vector<int> ball, beg;
+    for (int j0 = 0; j0 <= J; ++j0) {
+      beg.push_back((int)ball.size());
+      for (int a = 0; a < n; ++a)
+        for (int b = 0; b < n; ++b) {
+          const int j1 = a - J, j2 = b - J;
+          if (j0 * j0 + j1 * j1 + j2 * j2 <= J * J) ball.push_back(j0 | (a << 8) | (b << 16));
+        }
+    }
+    beg.push_back((int)ball.size());
+    P->nball = (int)ball.size();
+    ball.insert(ball.end(), beg.begin(), beg.end());
+    void* d = nullptr;
+    PDMK_HIP(hipMalloc(&d, ball.size() * sizeof(int)));
+    PDMK_HIP(hipMemcpy(d, ball.data(), ball.size() * sizeof(int), hipMemcpyHostToDevice));
+    P->d_ball = static_cast<int*>(d);
+  }
   std::vector<double> nodes, bw;
   cheb_nodes(p, nodes, bw);
   {
@@ -561,7 +600,7 @@ const double* pw_tables<double>(const pdmk_plan* P) { return P->d_pwt_d; }
 template <class Real, int PP, int JJ>
 static void pw_mfma_launch(const pdmk_plan* P, const PwMfmaShape& sh, const Level& L, int nn,
                            const void* proxy_q, void* S, void* proxy_phi, double levfac,
-                           unsigned long long* npairs, hipStream_t s) {
+                           unsigned long long* npairs, hipEvent_t mid, hipStream_t s) {
   const Real* T = pw_tables<Real>(P);
   const size_t* o = P->pwt_off;
   PDMK_HIP(hipFuncSetAttribute((const void*)&k_pw_out_mfma<Real, PP, JJ>,
@@ -571,28 +610,30 @@ static void pw_mfma_launch(const pdmk_plan* P, const PwMfmaShape& sh, const Leve
   hipLaunchKernelGGL((k_pw_out_mfma<Real, PP, JJ>), dim3(nn), dim3(256), sh.lds_out, s,
                      static_cast<const Real*>(proxy_q), T + o[0], T + o[1], T + o[2],
                      static_cast<Real*>(S), sh.g_out, sh.sX, sh.sZ);
+  if (mid) PDMK_HIP(hipEventRecord(mid, s));
   hipLaunchKernelGGL((k_pw_in_mfma<Real, PP, JJ>), dim3(nn), dim3(256), sh.lds_in, s, P->kp,
                      L, static_cast<const Real*>(S), T + o[3], T + o[4], T + o[5], P->d_dtab,
-                     levfac, static_cast<Real*>(proxy_phi), npairs, sh.g_in, sh.sI, sh.sY,
-                     sh.sW);
+                     P->d_ball, P->d_ball + P->nball, levfac, static_cast<Real*>(proxy_phi),
+                     npairs, sh.g_in, sh.sI, sh.sY, sh.sW);
 }
 
 template <class Real>
 void pw_mfma_level(const pdmk_plan* P, const Level& L, int nn, const void* proxy_q, void* S,
-                   void* proxy_phi, double levfac, unsigned long long* npairs, hipStream_t s) {
+                   void* proxy_phi, double levfac, unsigned long long* npairs, hipEvent_t mid,
+                   hipStream_t s) {
   const KParams& kp = P->kp;
   const PwMfmaShape sh = pw_mfma_shape(kp.p, kp.J, sizeof(Real));
   if (kp.p == 22 && kp.J == 16)
-    pw_mfma_launch<Real, 22, 16>(P, sh, L, nn, proxy_q, S, proxy_phi, levfac, npairs, s);
+    pw_mfma_launch<Real, 22, 16>(P, sh, L, nn, proxy_q, S, proxy_phi, levfac, npairs, mid, s);
   else if (kp.p == 13 && kp.J == 9)
-    pw_mfma_launch<Real, 13, 9>(P, sh, L, nn, proxy_q, S, proxy_phi, levfac, npairs, s);
+    pw_mfma_launch<Real, 13, 9>(P, sh, L, nn, proxy_q, S, proxy_phi, levfac, npairs, mid, s);
   else
     throw Error{PDMK_ERR_UNSUPPORTED, "no matrix-core plane-wave kernel for this (p, J)"};
 }
 
 template void pw_mfma_level<float>(const pdmk_plan*, const Level&, int, const void*, void*, void*,
-                                   double, unsigned long long*, hipStream_t);
+                                   double, unsigned long long*, hipEvent_t, hipStream_t);
 template void pw_mfma_level<double>(const pdmk_plan*, const Level&, int, const void*, void*,
-                                    void*, double, unsigned long long*, hipStream_t);
+                                    void*, double, unsigned long long*, hipEvent_t, hipStream_t);
 
 }  // namespace pdmk

@@ -65,7 +65,9 @@ class Stats(ctypes.Structure):
                 ("t_total_ms", ctypes.c_double), ("t_direct_ms", ctypes.c_double),
                 ("t_pw_ms", ctypes.c_double), ("t_proxy_ms", ctypes.c_double),
                 ("n_support_pairs", ctypes.c_int64), ("series_len", ctypes.c_int),
-                ("t_call_ms", ctypes.c_double), ("workspace_bytes", ctypes.c_int64)]
+                ("t_call_ms", ctypes.c_double), ("workspace_bytes", ctypes.c_int64),
+                ("n_pwout_boxes", ctypes.c_int64), ("n_pwin_boxes", ctypes.c_int64),
+                ("t_pwout_ms", ctypes.c_double), ("t_pwin_ms", ctypes.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
