@@ -204,6 +204,10 @@ void pw_mfma_level(const pdmk_plan* P, const Level& L, int nn, const void* proxy
                    void* proxy_phi, double levfac, unsigned long long* npairs, hipEvent_t mid,
                    hipStream_t s);
 
+template <class Real>
+bool eval_leaf_mfma(const pdmk_plan* P, const Level& Lp, const Level& Lc, int l,
+                    const double* tx, int64_t ntrg, double* pot, double* grad, hipStream_t s);
+
 // stages (implemented in tree.hip / near.hip / far.hip)
 void stage_prepare(pdmk_plan* P, Eval& E, const double* src, const double* trg);
 void stage_images(pdmk_plan* P, Eval& E, const double* q);

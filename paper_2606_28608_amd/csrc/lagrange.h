@@ -1,0 +1,66 @@
+// Lagrange interpolation at Chebyshev nodes for the proxy grids (device
+// helpers shared by the near-field translation units).
+#pragma once
+#include <hip/hip_runtime.h>
+
+namespace pdmk {
+
+// Lagrange basis at the p Chebyshev nodes (barycentric form), and optionally
+// its derivative.  x exactly at a node is moved by 1e-13.
+template <class T>
+__device__ inline void lagrange_rows(int p, const double* __restrict__ nodes,
+                                     const double* __restrict__ bw, double x,
+                                     T* row, T* drow) {
+  for (int j = 0; j < p; ++j)
+    if (x == nodes[j]) { x += 1e-13; break; }
+  double s = 0.0, s1 = 0.0;
+  for (int j = 0; j < p; ++j) {
+    double inv = 1.0 / (x - nodes[j]);
+    double t = bw[j] * inv;
+    s += t;
+    s1 += t * inv;
+  }
+  double is = 1.0 / s;
+  for (int j = 0; j < p; ++j) {
+    // l_j = (w_j/(x - x_j)) / S;  l_j' = l_j (-1/(x - x_j) + S1/S),  S1 = sum w_k/(x-x_k)^2
+    const double inv = 1.0 / (x - nodes[j]);
+    const double lj = bw[j] * inv * is;
+    row[j] = (T)lj;
+    if (drow) drow[j] = (T)(lj * (-inv + s1 * is));
+  }
+}
+
+// Same as lagrange_rows with compile-time capacity PMAX (entries >= p are 0),
+// so the rows stay in registers.
+template <int PMAX, bool DER>
+__device__ inline void lagrange_rows_reg(int p, const double* __restrict__ nodes,
+                                         const double* __restrict__ bw, double x,
+                                         double (&row)[PMAX], double (&drow)[PMAX]) {
+#pragma unroll
+  for (int m = 0; m < PMAX; ++m)
+    if (m < p && x == nodes[m]) x += 1e-13;
+  double s = 0.0, s1 = 0.0;
+  double inv[PMAX];
+#pragma unroll
+  for (int m = 0; m < PMAX; ++m) {
+    if (m < p) {
+      inv[m] = 1.0 / (x - nodes[m]);
+      const double t = bw[m] * inv[m];
+      row[m] = t;
+      s += t;
+      s1 += t * inv[m];
+    } else {
+      inv[m] = 0.0;
+      row[m] = 0.0;
+    }
+  }
+  const double is = 1.0 / s;
+#pragma unroll
+  for (int m = 0; m < PMAX; ++m) {
+    const double lj = row[m] * is;
+    if (DER) drow[m] = lj * (s1 * is - inv[m]);
+    row[m] = lj;
+  }
+}
+
+}  // namespace pdmk

@@ -25,6 +25,7 @@
 #include <vector>
 
 #include "internal.h"
+#include "lagrange.h"
 
 namespace pdmk {
 
@@ -420,6 +421,198 @@ __global__ __launch_bounds__(256) void k_pw_in_mfma(
         }
   }
 }
+
+// Leaf targets evaluate their parent's proxy potential (3D):
+//   phi(x) = sum_{i0,i1,i2} Phi[i0][i1][i2] l_i0(xi_0) l_i1(xi_1) l_i2(xi_2)
+// For 16 targets at a time the contraction over i2 is a product
+//   T[(i0,i1)][t] = sum_i2 Phi[(i0,i1)][i2] Lz[i2][t]
+// on MFMA tiles; the remaining weights l_i0 l_i1 are applied as each tile
+// leaves the accumulators.  One block of 4 waves per non-leaf parent; each
+// wave takes whole 16-target chunks, so the waves never wait on each other.
+template <class Real, int P, bool GRAD>
+__global__ __launch_bounds__(256) void k_eval_leaf_mfma(
+    KParams kp, Level Lp, Level Lc, int lvl, const double* __restrict__ tx, int64_t ntrg,
+    const double* __restrict__ nodes, const double* __restrict__ bw, double* __restrict__ pot,
+    double* __restrict__ grad) {
+  using MF = Mfma<Real>;
+  using V = typename MF::V;
+  constexpr int PP = P * P, KA = (P + 3) & ~3, SP = KA | 1, SL = P | 1;
+  constexpr int MT = (PP + 15) / 16;
+  constexpr int NR = GRAD ? 2 : 1;
+  extern __shared__ __align__(16) unsigned char smraw[];
+  Real* PhiA = reinterpret_cast<Real*>(smraw);        // 16 MT rows (i0,i1) x SP (i2)
+  Real* wrow = PhiA + 16 * MT * SP;                     // per wave: rows of 16 targets
+  __shared__ int cb[8], cpre[9];
+  const int k = blockIdx.x;
+  const int Pb = Lp.nl_box[k];
+  const int c0 = Lp.child0[Pb];
+  if (threadIdx.x == 0) {
+    int acc = 0;
+    for (int o = 0; o < 8; ++o) {
+      const int c = c0 + o;
+      cpre[o] = acc;
+      if (Lc.child0[c] < 0) {
+        cb[o] = Lc.tbeg[c];
+        acc += Lc.tend[c] - Lc.tbeg[c];
+      } else {
+        cb[o] = 0;
+      }
+    }
+    cpre[8] = acc;
+  }
+  __syncthreads();
+  const int total = cpre[8];
+  if (total == 0) return;
+  const Real* Phi = static_cast<const Real*>(Lp.proxy_phi) + (int64_t)k * P * PP;
+  for (int e = threadIdx.x; e < 16 * MT * SP; e += 256) {
+    const int m = e / SP, c = e - m * SP;
+    PhiA[e] = (m < PP && c < P) ? Phi[m * P + c] : (Real)0;
+  }
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  // wave-private rows: Lx, Ly [16][SL] (and derivatives), Lz as B operand [KA][16]
+  Real* Lx = wrow + wave * NR * (2 * 16 * SL + KA * 16);
+  Real* Ly = Lx + 16 * SL;
+  Real* Lz = Ly + 16 * SL;
+  Real* dLx = Lz + KA * 16;
+  Real* dLy = dLx + 16 * SL;
+  Real* dLz = dLy + 16 * SL;
+  const double hP = kp.rc / (double)(1 << lvl);
+  const double sc = 2.0 / hP;
+  for (int ch = wave; 16 * ch < total; ch += 4) {
+    // target of lane li in this chunk
+    const int j = 16 * ch + li;
+    const bool valid = j < total;
+    int t = 0;
+    if (valid) {
+      int o = 0;
+      while (o < 7 && cpre[o + 1] <= j) ++o;
+      t = cb[o] + (j - cpre[o]);
+    }
+    // rows: lane (li, axis lk < 3) computes l_i(xi) for its target
+    if (lk < 3) {
+      const int a = lk;
+      const double cen = kp.origin[a] + (Lp.coord[Pb * 3 + a] + 0.5) * hP;
+      const double xi = valid ? (tx[a * ntrg + t] - cen) * sc : 0.0;
+      double rl[P], dl[P];
+      lagrange_rows_reg<P, GRAD>(P, nodes, bw, xi, rl, dl);
+#pragma unroll
+      for (int i = 0; i < P; ++i) {
+        const Real v = valid ? (Real)rl[i] : (Real)0;
+        const Real dv = (GRAD && valid) ? (Real)dl[i] : (Real)0;
+        if (a == 0) {
+          Lx[li * SL + i] = v;
+          if (GRAD) dLx[li * SL + i] = dv;
+        } else if (a == 1) {
+          Ly[li * SL + i] = v;
+          if (GRAD) dLy[li * SL + i] = dv;
+        } else {
+          Lz[i * 16 + li] = v;
+          if (GRAD) dLz[i * 16 + li] = dv;
+        }
+      }
+      if (a == 2)
+        for (int i = P; i < KA; ++i) {
+          Lz[i * 16 + li] = 0;
+          if (GRAD) dLz[i * 16 + li] = 0;
+        }
+    }
+    __builtin_amdgcn_s_waitcnt(0);
+    __builtin_amdgcn_wave_barrier();
+    Real bz[KA / 4], bd[KA / 4];
+#pragma unroll
+    for (int s = 0; s < KA / 4; ++s) {
+      bz[s] = Lz[(4 * s + lk) * 16 + li];
+      bd[s] = GRAD ? dLz[(4 * s + lk) * 16 + li] : (Real)0;
+    }
+    Real acc = 0, g0 = 0, g1 = 0, g2 = 0;
+    for (int mt = 0; mt < MT; ++mt) {
+      const Real* ar = PhiA + (16 * mt + li) * SP + lk;
+      V c = {0, 0, 0, 0}, cd = {0, 0, 0, 0};
+#pragma unroll
+      for (int s = 0; s < KA / 4; ++s) {
+        const Real av = ar[4 * s];
+        c = MF::op(av, bz[s], c);
+        if (GRAD) cd = MF::op(av, bd[s], cd);
+      }
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int m = 16 * mt + MF::row(lane, r);
+        if (m < PP) {
+          const int i0 = m / P, i1 = m - i0 * P;
+          const Real x0 = Lx[li * SL + i0], y1 = Ly[li * SL + i1];
+          const Real w = x0 * y1;
+          acc = fma(c[r], w, acc);
+          if (GRAD) {
+            g0 = fma(c[r], dLx[li * SL + i0] * y1, g0);
+            g1 = fma(c[r], x0 * dLy[li * SL + i1], g1);
+            g2 = fma(cd[r], w, g2);
+          }
+        }
+      }
+    }
+    // lanes li, li + 16, li + 32, li + 48 hold parts of target li
+    for (int m = 16; m < 64; m <<= 1) {
+      acc += __shfl_xor(acc, m);
+      if (GRAD) {
+        g0 += __shfl_xor(g0, m);
+        g1 += __shfl_xor(g1, m);
+        g2 += __shfl_xor(g2, m);
+      }
+    }
+    if (valid && lk == 0) {
+      pot[t] += (double)acc;
+      if (GRAD) {
+        grad[(int64_t)t * 3 + 0] += (double)g0 * sc;
+        grad[(int64_t)t * 3 + 1] += (double)g1 * sc;
+        grad[(int64_t)t * 3 + 2] += (double)g2 * sc;
+      }
+    }
+    __builtin_amdgcn_wave_barrier();
+  }
+}
+
+template <class Real, int PP>
+static size_t eval_leaf_lds(bool grad) {
+  constexpr int KA = (PP + 3) & ~3, SP = KA | 1, SL = PP | 1, MT = (PP * PP + 15) / 16;
+  const int NR = grad ? 2 : 1;
+  return ((size_t)16 * MT * SP + (size_t)4 * NR * (2 * 16 * SL + KA * 16)) * sizeof(Real);
+}
+
+template <class Real, int PP>
+static bool eval_leaf_launch(const pdmk_plan* P, const Level& Lp, const Level& Lc, int l,
+                             const double* tx, int64_t ntrg, double* pot, double* grad,
+                             hipStream_t s) {
+  const size_t lds = eval_leaf_lds<Real, PP>(grad != nullptr);
+  if (lds > 150 * 1024) return false;
+  if (grad) {
+    PDMK_HIP(hipFuncSetAttribute((const void*)&k_eval_leaf_mfma<Real, PP, true>,
+                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    hipLaunchKernelGGL((k_eval_leaf_mfma<Real, PP, true>), dim3(Lp.nnl), dim3(256), lds, s,
+                       P->kp, Lp, Lc, l, tx, ntrg, P->d_nodes, P->d_bw, pot, grad);
+  } else {
+    PDMK_HIP(hipFuncSetAttribute((const void*)&k_eval_leaf_mfma<Real, PP, false>,
+                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    hipLaunchKernelGGL((k_eval_leaf_mfma<Real, PP, false>), dim3(Lp.nnl), dim3(256), lds, s,
+                       P->kp, Lp, Lc, l, tx, ntrg, P->d_nodes, P->d_bw, pot, grad);
+  }
+  return true;
+}
+
+template <class Real>
+bool eval_leaf_mfma(const pdmk_plan* P, const Level& Lp, const Level& Lc, int l,
+                    const double* tx, int64_t ntrg, double* pot, double* grad, hipStream_t s) {
+  if (P->kp.dim != 3 || !P->pw_mfma) return false;
+  if (P->kp.p == 22) return eval_leaf_launch<Real, 22>(P, Lp, Lc, l, tx, ntrg, pot, grad, s);
+  if (P->kp.p == 13) return eval_leaf_launch<Real, 13>(P, Lp, Lc, l, tx, ntrg, pot, grad, s);
+  return false;
+}
+
+template bool eval_leaf_mfma<float>(const pdmk_plan*, const Level&, const Level&, int,
+                                    const double*, int64_t, double*, double*, hipStream_t);
+template bool eval_leaf_mfma<double>(const pdmk_plan*, const Level&, const Level&, int,
+                                     const double*, int64_t, double*, double*, hipStream_t);
 
 // ------------------------------------------------------------------ host
 // (p, J) pairs with matrix-core kernels: the defaults at eps = 1e-3 and 1e-6.
