@@ -63,6 +63,11 @@ def parse():
     ap.add_argument("--cpu-alpha", type=float, default=1.3,
                     help="Ewald splitting parameter of the CPU baseline run")
     ap.add_argument("--child", action="store_true", help=argparse.SUPPRESS)
+    ap.add_argument("--child-batch", action="store_true", help=argparse.SUPPRESS)
+    ap.add_argument("--no-batch", action="store_true",
+                    help="skip the batched many-cell measurement")
+    ap.add_argument("--batch-systems", type=int, default=512)
+    ap.add_argument("--batch-steps", type=int, default=3)
     ap.add_argument("--copy-calib", action="store_true",
                     help="only run a plain 1 GiB device copy (calibrates HBM byte counters)")
     return ap.parse_args()
@@ -226,15 +231,50 @@ def child(args):
     print(json.dumps(r))
 
 
-def run_child(args, mode):
-    cmd = [sys.executable, os.path.abspath(__file__), "--child", "--precision", mode,
-           "--steps", str(args.steps), "--warmup", str(args.warmup), "--n", str(args.n),
-           "--eps", str(args.eps)]
+def child_batch(args):
+    """Batched evaluation of many small cells (random triclinic cells, log-uniform
+    sizes 500..5e4, even systems uniform, odd clustered; +-1 charges): one call
+    evaluates every system.  Prints the timing as JSON."""
+    import numpy as np
+    import torch
+    from paper_2606_28608_amd import pdmk, workloads as W
+    systems = W.batch_cells(n_sys=args.batch_systems, seed=5)
+    offs = np.cumsum([0] + [len(s[2]) for s in systems]).astype(np.int64)
+    src = torch.tensor(np.vstack([s[1] for s in systems]), device="cuda:0")
+    q = torch.tensor(np.concatenate([s[2] for s in systems]), device="cuda:0")
+    Ls = np.stack([s[0] for s in systems])
+    t0 = time.perf_counter()
+    B = pdmk.Batch(Ls, eps=args.eps, precision=args.precision, workers=8)
+    t_plan = time.perf_counter() - t0
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    B.eval(offs, src, q)
+    cold = time.perf_counter() - t0
+    for _ in range(max(0, args.warmup - 1)):
+        B.eval(offs, src, q)
+    per = []
+    for _ in range(args.steps):
+        t1 = time.perf_counter()
+        B.eval(offs, src, q)
+        per.append(time.perf_counter() - t1)
+    n = int(offs[-1])
+    ms = 1e3 * sum(per) / len(per)
+    print(json.dumps({"systems": len(systems), "particles": n, "ms_per_call": ms,
+                      "value": n / (ms * 1e-3), "cold_first_call_ms": 1e3 * cold,
+                      "plan_create_s": t_plan, "precision": args.precision}))
+
+
+def run_child(args, mode, batch=False):
+    cmd = [sys.executable, os.path.abspath(__file__), "--child-batch" if batch else "--child",
+           "--precision", mode, "--steps", str(args.batch_steps if batch else args.steps),
+           "--warmup", str(args.warmup), "--n", str(args.n), "--eps", str(args.eps),
+           "--batch-systems", str(args.batch_systems)]
     if args.no_check:
         cmd.append("--no-check")
     p = subprocess.run(cmd, stdout=subprocess.PIPE, text=True)
     if p.returncode != 0:
-        print("bench.py: %s run failed with status %d" % (mode, p.returncode), file=sys.stderr)
+        print("bench.py: %s%s run failed with status %d"
+              % (mode, " batch" if batch else "", p.returncode), file=sys.stderr)
         sys.exit(p.returncode if p.returncode > 0 else 1)
     return json.loads(p.stdout.strip().splitlines()[-1])
 
@@ -250,6 +290,9 @@ def main():
         return
     if args.child:
         child(args)
+        return
+    if args.child_batch:
+        child_batch(args)
         return
     # Each arithmetic mode runs in a child process of its own, one after the
     # other, so that the two measurements share no device state.  This
@@ -310,6 +353,14 @@ def main():
     }
     for m in modes[1:]:
         out[m] = summary(res[m])
+    if not args.no_batch:
+        out["batch"] = {"workload": "%d random triclinic cells (edges 1, U[1,8], U[1,8], angles "
+                                    "U[60,120] deg), N per cell log-uniform in [500, 5e4], even "
+                                    "cells uniform, odd clustered, +-1 charges, eps=%g"
+                                    % (args.batch_systems, args.eps),
+                        "unit": "particles/s"}
+        for m in modes:
+            out["batch"][m] = run_child(args, m, batch=True)
     print(json.dumps(out))
 
 
