@@ -1003,6 +1003,7 @@ static void launch_anterp(const KParams& kp, const Level& L, const Level& C, int
                           pdmk_plan* P, hipStream_t s) {
   const int p = kp.p;
   Real* Q = static_cast<Real*>(L.proxy_q);
+  if (D == 3 && anterp_mfma<Real>(P, L, C, l, E.sx, E.sq, E.n_img, Q, s)) return;
 #define PDMK_AN(PM) \
   hipLaunchKernelGGL((k_anterp<D, PM, Real>), dim3(L.nnl), dim3(256), 0, s, kp, L, C, l, E.sx, \
                      E.sq, E.n_img, P->d_nodes, P->d_bw, Q)

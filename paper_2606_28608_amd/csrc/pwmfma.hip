@@ -614,6 +614,141 @@ template bool eval_leaf_mfma<float>(const pdmk_plan*, const Level&, const Level&
 template bool eval_leaf_mfma<double>(const pdmk_plan*, const Level&, const Level&, int,
                                      const double*, int64_t, double*, double*, hipStream_t);
 
+// Proxy charges of a non-leaf box from the sources of its childless children
+// (3D): Q[i0][i1][i2] = sum_s q_s l_i0(xi_0) l_i1(xi_1) l_i2(xi_2), i.e. the
+// product (q l_i0 l_i1)[(i0,i1)][s] x l_i2[s][i2] over the sources, on MFMA
+// tiles with the sources in chunks of 32.  One block of 4 waves per box; each
+// wave owns the same M-tiles of Q for every chunk (accumulators in registers).
+template <class Real, int P>
+__global__ __launch_bounds__(256) void k_anterp_mfma(KParams kp, Level L, Level C, int lvl,
+                                                     const double* __restrict__ sx,
+                                                     const double* __restrict__ sq,
+                                                     int64_t nimg,
+                                                     const double* __restrict__ nodes,
+                                                     const double* __restrict__ bw,
+                                                     Real* __restrict__ Q) {
+  using MF = Mfma<Real>;
+  using V = typename MF::V;
+  constexpr int PP = P * P, SL = P | 1, CH = 32, NT = (P + 15) / 16, NW = 16 * NT;
+  constexpr int MT = (PP + 15) / 16, MW = (MT + 3) / 4;
+  __shared__ Real qLx[CH * SL], Ly[CH * SL], Lz[CH * NW];
+  __shared__ int cb[8], cpre[9];
+  const int k = blockIdx.x;
+  const int b = L.nl_box[k];
+  const int c0 = L.child0[b];
+  if (threadIdx.x == 0) {
+    int acc = 0;
+    for (int o = 0; o < 8; ++o) {
+      const int c = c0 + o;
+      cpre[o] = acc;
+      if (C.child0[c] < 0) {
+        cb[o] = C.sbeg[c];
+        acc += C.send[c] - C.sbeg[c];
+      } else {
+        cb[o] = 0;
+      }
+    }
+    cpre[8] = acc;
+  }
+  // B operand padding columns stay zero
+  for (int e = threadIdx.x; e < CH * NW; e += 256) Lz[e] = 0;
+  __syncthreads();
+  const int total = cpre[8];
+  const double h = kp.rc / (double)(1 << lvl);
+  const double sc = 2.0 / h;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  V acc[MW][NT];
+#pragma unroll
+  for (int i = 0; i < MW; ++i)
+#pragma unroll
+    for (int n = 0; n < NT; ++n) acc[i][n] = V{0, 0, 0, 0};
+  for (int s0 = 0; s0 < total; s0 += CH) {
+    // Lagrange rows of the chunk: thread (source, axis)
+    if (threadIdx.x < 3 * CH) {
+      const int si = threadIdx.x / 3, a = threadIdx.x - 3 * si;
+      const int j = s0 + si;
+      const bool valid = j < total;
+      int sidx = 0;
+      if (valid) {
+        int o = 0;
+        while (o < 7 && cpre[o + 1] <= j) ++o;
+        sidx = cb[o] + (j - cpre[o]);
+      }
+      const double cen = kp.origin[a] + (L.coord[b * 3 + a] + 0.5) * h;
+      const double xi = valid ? (sx[a * nimg + sidx] - cen) * sc : 0.0;
+      const double qs = (valid && a == 0) ? sq[sidx] : 1.0;
+      double rl[P], dl[P];
+      lagrange_rows_reg<P, false>(P, nodes, bw, xi, rl, dl);
+#pragma unroll
+      for (int i = 0; i < P; ++i) {
+        const Real v = valid ? (Real)(a == 0 ? qs * rl[i] : rl[i]) : (Real)0;
+        if (a == 0) qLx[si * SL + i] = v;
+        else if (a == 1) Ly[si * SL + i] = v;
+        else Lz[si * NW + i] = v;
+      }
+    }
+    __syncthreads();
+    Real bz[CH / 4][NT];
+#pragma unroll
+    for (int st = 0; st < CH / 4; ++st)
+#pragma unroll
+      for (int n = 0; n < NT; ++n) bz[st][n] = Lz[(4 * st + lk) * NW + 16 * n + li];
+#pragma unroll
+    for (int i = 0; i < MW; ++i) {
+      const int mt = wave + 4 * i;
+      if (mt < MT) {
+        const int m = 16 * mt + li;
+        const int i0 = min(m / P, P - 1), i1 = m - (m / P) * P;
+#pragma unroll
+        for (int st = 0; st < CH / 4; ++st) {
+          const int si = 4 * st + lk;
+          const Real av = qLx[si * SL + i0] * Ly[si * SL + i1];
+#pragma unroll
+          for (int n = 0; n < NT; ++n) acc[i][n] = MF::op(av, bz[st][n], acc[i][n]);
+        }
+      }
+    }
+    __syncthreads();
+  }
+  Real* out = Q + (int64_t)k * P * PP;
+#pragma unroll
+  for (int i = 0; i < MW; ++i) {
+    const int mt = wave + 4 * i;
+    if (mt < MT)
+#pragma unroll
+      for (int n = 0; n < NT; ++n) {
+        const int i2 = 16 * n + li;
+        if (i2 < P)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int m = 16 * mt + MF::row(lane, r);
+            if (m < PP) out[m * P + i2] = acc[i][n][r];
+          }
+      }
+  }
+}
+
+template <class Real>
+bool anterp_mfma(const pdmk_plan* P, const Level& L, const Level& C, int l, const double* sx,
+                 const double* sq, int64_t nimg, void* Q, hipStream_t s) {
+  if (P->kp.dim != 3 || !P->pw_mfma) return false;
+  if (P->kp.p == 22)
+    hipLaunchKernelGGL((k_anterp_mfma<Real, 22>), dim3(L.nnl), dim3(256), 0, s, P->kp, L, C, l,
+                       sx, sq, nimg, P->d_nodes, P->d_bw, static_cast<Real*>(Q));
+  else if (P->kp.p == 13)
+    hipLaunchKernelGGL((k_anterp_mfma<Real, 13>), dim3(L.nnl), dim3(256), 0, s, P->kp, L, C, l,
+                       sx, sq, nimg, P->d_nodes, P->d_bw, static_cast<Real*>(Q));
+  else
+    return false;
+  return true;
+}
+
+template bool anterp_mfma<float>(const pdmk_plan*, const Level&, const Level&, int,
+                                 const double*, const double*, int64_t, void*, hipStream_t);
+template bool anterp_mfma<double>(const pdmk_plan*, const Level&, const Level&, int,
+                                  const double*, const double*, int64_t, void*, hipStream_t);
+
 // ------------------------------------------------------------------ host
 // (p, J) pairs with matrix-core kernels: the defaults at eps = 1e-3 and 1e-6.
 static bool pw_mfma_supported(int p, int J) {
