@@ -212,6 +212,10 @@ template <class Real>
 bool anterp_mfma(const pdmk_plan* P, const Level& L, const Level& C, int l, const double* sx,
                  const double* sq, int64_t nimg, void* Q, hipStream_t s);
 
+template <class Real>
+bool transfer_mfma(const pdmk_plan* P, const Level& Lp, const Level& Lc, bool up,
+                   const void* src, void* dst, hipStream_t s);
+
 // stages (implemented in tree.hip / near.hip / far.hip)
 void stage_prepare(pdmk_plan* P, Eval& E, const double* src, const double* trg);
 void stage_images(pdmk_plan* P, Eval& E, const double* q);

@@ -954,6 +954,7 @@ template <int D, class Real>
 static void launch_transfer(const KParams& kp, const Level& Lp, const Level& Lc, int up,
                             const void* src_, void* dst_, pdmk_plan* P, Eval& E,
                             hipStream_t s) {
+  if (D == 3 && Lc.nnl > 0 && transfer_mfma<Real>(P, Lp, Lc, up != 0, src_, dst_, s)) return;
   const Real* src = static_cast<const Real*>(src_);
   Real* dst = static_cast<Real*>(dst_);
   const int p = kp.p;

@@ -749,6 +749,141 @@ template bool anterp_mfma<float>(const pdmk_plan*, const Level&, const Level&, i
 template bool anterp_mfma<double>(const pdmk_plan*, const Level&, const Level&, int,
                                   const double*, const double*, int64_t, void*, hipStream_t);
 
+// Proxy transfer between a non-leaf child (level l+1) and its parent (level
+// l): a 1D Lagrange matrix applied along each axis (up: child charges into
+// the parent's, summed over siblings with atomics; down: parent potentials
+// into the child's).  Each axis is one product C[o][(j,k)] = sum_i M[i][o]
+// X[i][(j,k)] that contracts the slowest axis, stored with o as the fastest
+// axis, so three products return to the original layout.  The first product
+// reads the input from memory, the other two from one LDS buffer; each
+// product's tiles stay in registers until every wave has read the buffer.
+template <class Real, int P, bool UP>
+__global__ __launch_bounds__(256) void k_transfer_mfma(Level Lp, Level Lc,
+                                                       const Real* __restrict__ src,
+                                                       Real* __restrict__ dst,
+                                                       const double* __restrict__ Tm, int SB) {
+  using MF = Mfma<Real>;
+  using V = typename MF::V;
+  constexpr int PP = P * P, KA = (P + 3) & ~3, NTILE = (PP + 15) / 16, MTL = (P + 15) / 16;
+  constexpr int NW = (NTILE + 3) / 4;
+  extern __shared__ __align__(16) unsigned char smraw[];
+  Real* buf = reinterpret_cast<Real*>(smraw);   // KA rows x SB
+  const int kc = blockIdx.x;
+  const int c = Lc.nl_box[kc];
+  const int pb = Lc.parent[c];
+  const int kpar = Lp.nlid[pb];
+  const int oct = c - Lp.child0[pb];
+  const Real* in = src + (int64_t)(UP ? kc : kpar) * P * PP;
+  Real* out = dst + (int64_t)(UP ? kpar : kc) * P * PP;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  for (int e = threadIdx.x; e < (KA - P) * SB; e += 256) buf[P * SB + e] = 0;
+  V acc[NW][MTL];
+  for (int st = 0; st < 3; ++st) {
+    // A fragments: A[o][i] = M[i][o]; up: M[i][o] = Tm[sel][o][i], down: Tm[sel][i][o]
+    const int sel = (oct >> st) & 1;
+    Real af[MTL][KA / 4];
+#pragma unroll
+    for (int m = 0; m < MTL; ++m)
+#pragma unroll
+      for (int q = 0; q < KA / 4; ++q) {
+        const int o = 16 * m + li, i = 4 * q + lk;
+        af[m][q] = (o < P && i < P)
+                       ? (Real)(UP ? Tm[sel * PP + o * P + i] : Tm[sel * PP + i * P + o])
+                       : (Real)0;
+      }
+#pragma unroll
+    for (int w = 0; w < NW; ++w) {
+      const int t = wave + 4 * w;
+#pragma unroll
+      for (int m = 0; m < MTL; ++m) acc[w][m] = V{0, 0, 0, 0};
+      if (t < NTILE) {
+        const int n = 16 * t + li;
+#pragma unroll
+        for (int q = 0; q < KA / 4; ++q) {
+          const int i = 4 * q + lk;
+          Real bv;
+          if (st == 0) bv = (i < P && n < PP) ? in[i * PP + n] : (Real)0;
+          else bv = buf[i * SB + n];
+#pragma unroll
+          for (int m = 0; m < MTL; ++m) acc[w][m] = MF::op(af[m][q], bv, acc[w][m]);
+        }
+      }
+    }
+    if (st < 2) {
+      __syncthreads();   // every wave has read the buffer
+#pragma unroll
+      for (int w = 0; w < NW; ++w) {
+        const int t = wave + 4 * w;
+        const int n = 16 * t + li;   // (j, k)
+        if (t < NTILE && n < PP) {
+          const int j = n / P, kk = n - j * P;
+#pragma unroll
+          for (int m = 0; m < MTL; ++m)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+              const int o = 16 * m + MF::row(lane, r);
+              if (o < P) buf[j * SB + kk * P + o] = acc[w][m][r];
+            }
+        }
+      }
+      __syncthreads();
+    }
+  }
+#pragma unroll
+  for (int w = 0; w < NW; ++w) {
+    const int t = wave + 4 * w;
+    const int n = 16 * t + li;
+    if (t < NTILE && n < PP)
+#pragma unroll
+      for (int m = 0; m < MTL; ++m)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int o = 16 * m + MF::row(lane, r);
+          if (o < P) {
+            if (UP) atomicAdd(out + n * P + o, acc[w][m][r]);
+            else out[n * P + o] += acc[w][m][r];
+          }
+        }
+  }
+}
+
+template <class Real, int PPP>
+static void transfer_launch(const pdmk_plan* P, const Level& Lp, const Level& Lc, bool up,
+                            const void* src, void* dst, hipStream_t s) {
+  constexpr int KA = (PPP + 3) & ~3, PP = PPP * PPP;
+  const int SB = sizeof(Real) == 4 ? ((PP + 31) & ~31) + 16 : ((PP + 15) & ~15) + 8;
+  const size_t lds = (size_t)KA * SB * sizeof(Real);
+  if (up) {
+    PDMK_HIP(hipFuncSetAttribute((const void*)&k_transfer_mfma<Real, PPP, true>,
+                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    hipLaunchKernelGGL((k_transfer_mfma<Real, PPP, true>), dim3(Lc.nnl), dim3(256), lds, s, Lp,
+                       Lc, static_cast<const Real*>(src), static_cast<Real*>(dst), P->d_Tm, SB);
+  } else {
+    PDMK_HIP(hipFuncSetAttribute((const void*)&k_transfer_mfma<Real, PPP, false>,
+                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    hipLaunchKernelGGL((k_transfer_mfma<Real, PPP, false>), dim3(Lc.nnl), dim3(256), lds, s, Lp,
+                       Lc, static_cast<const Real*>(src), static_cast<Real*>(dst), P->d_Tm, SB);
+  }
+}
+
+// Used for FP64 tensors; in FP32 the vector-ALU line transforms of the whole
+// sibling group (one block per parent, no atomics) measured faster.
+template <class Real>
+bool transfer_mfma(const pdmk_plan* P, const Level& Lp, const Level& Lc, bool up,
+                   const void* src, void* dst, hipStream_t s) {
+  if (P->kp.dim != 3 || !P->pw_mfma || sizeof(Real) != 8) return false;
+  if (P->kp.p == 22) transfer_launch<Real, 22>(P, Lp, Lc, up, src, dst, s);
+  else if (P->kp.p == 13) transfer_launch<Real, 13>(P, Lp, Lc, up, src, dst, s);
+  else return false;
+  return true;
+}
+
+template bool transfer_mfma<float>(const pdmk_plan*, const Level&, const Level&, bool,
+                                   const void*, void*, hipStream_t);
+template bool transfer_mfma<double>(const pdmk_plan*, const Level&, const Level&, bool,
+                                    const void*, void*, hipStream_t);
+
 // ------------------------------------------------------------------ host
 // (p, J) pairs with matrix-core kernels: the defaults at eps = 1e-3 and 1e-6.
 static bool pw_mfma_supported(int p, int J) {
