@@ -81,42 +81,95 @@ __device__ inline bool in_extended(const KParams& kp, const double* y) {
   return true;
 }
 
+// Images y = x + L n of one point inside the extended domain (Section 3.4).
+// L is upper triangular after orientation, so the admissible n_d follows from
+// the last coordinate alone, then n_{d-1} given n_d, and so on: each axis is
+// scanned over the range its bounds allow (one extra candidate on each side;
+// the per-axis tests only prune), and every candidate that survives is
+// decided by in_extended on the full image.  The shift vector is summed in
+// the same order as the host shift table.
+template <class F>
+__device__ inline void for_each_image(const KParams& kp, const double* x, F f) {
+  const int d = kp.dim;
+  const double* L = kp.L;
+  double lo[3], hi[3];
+  for (int a = 0; a < d; ++a) {
+    lo[a] = kp.origin[a];
+    hi[a] = kp.origin[a] + kp.next[a] * kp.rc;
+  }
+  const double tol = 1e-9 * kp.rc;
+  auto range = [&](double base, double lo_, double hi_, double Lii, int& nlo, int& nhi) {
+    nlo = (int)floor((lo_ - base) / Lii) - 1;
+    nhi = (int)ceil((hi_ - base) / Lii) + 1;
+  };
+  auto ok = [&](double v, int a) { return v >= lo[a] - tol && v < hi[a] + tol; };
+  if (d == 3) {
+    int a3, b3;
+    range(x[2], lo[2], hi[2], L[8], a3, b3);
+    for (int n3 = a3; n3 <= b3; ++n3) {
+      if (!ok(x[2] + L[8] * n3, 2)) continue;
+      int a2, b2;
+      range(x[1] + L[7] * n3, lo[1], hi[1], L[4], a2, b2);
+      for (int n2 = a2; n2 <= b2; ++n2) {
+        if (!ok(x[1] + (L[4] * n2 + L[7] * n3), 1)) continue;
+        int a1, b1;
+        range(x[0] + (L[3] * n2 + L[6] * n3), lo[0], hi[0], L[0], a1, b1);
+        for (int n1 = a1; n1 <= b1; ++n1) {
+          double y[3];
+          y[0] = x[0] + __dadd_rn(__dadd_rn(__dmul_rn(L[0], n1), __dmul_rn(L[3], n2)),
+                                  __dmul_rn(L[6], n3));
+          y[1] = x[1] + __dadd_rn(__dadd_rn(__dmul_rn(L[1], n1), __dmul_rn(L[4], n2)),
+                                  __dmul_rn(L[7], n3));
+          y[2] = x[2] + __dadd_rn(__dadd_rn(__dmul_rn(L[2], n1), __dmul_rn(L[5], n2)),
+                                  __dmul_rn(L[8], n3));
+          if (in_extended(kp, y)) f(y);
+        }
+      }
+    }
+  } else {
+    int a2, b2;
+    range(x[1], lo[1], hi[1], L[3], a2, b2);
+    for (int n2 = a2; n2 <= b2; ++n2) {
+      if (!ok(x[1] + L[3] * n2, 1)) continue;
+      int a1, b1;
+      range(x[0] + L[2] * n2, lo[0], hi[0], L[0], a1, b1);
+      for (int n1 = a1; n1 <= b1; ++n1) {
+        double y[3] = {0, 0, 0};
+        y[0] = x[0] + __dadd_rn(__dmul_rn(L[0], n1), __dmul_rn(L[2], n2));
+        y[1] = x[1] + __dadd_rn(__dmul_rn(L[1], n1), __dmul_rn(L[3], n2));
+        if (in_extended(kp, y)) f(y);
+      }
+    }
+  }
+}
+
 __global__ void k_img_count(KParams kp, int64_t n, const double* __restrict__ xs,
-                            const double* __restrict__ sv, int nsh, int* __restrict__ cnt) {
+                            int* __restrict__ cnt) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const int d = kp.dim;
   double x[3] = {0, 0, 0};
   for (int a = 0; a < d; ++a) x[a] = xs[a * n + i];
   int c = 0;
-  for (int s = 0; s < nsh; ++s) {
-    double y[3];
-    for (int a = 0; a < d; ++a) y[a] = x[a] + sv[s * d + a];
-    c += in_extended(kp, y) ? 1 : 0;
-  }
+  for_each_image(kp, x, [&](const double*) { ++c; });
   cnt[i] = c;
 }
 
 __global__ void k_img_emit(KParams kp, int64_t n, const double* __restrict__ xs,
-                           const double* __restrict__ q, const double* __restrict__ sv,
-                           int nsh, const int* __restrict__ off, int64_t nimg,
-                           double* __restrict__ xi, double* __restrict__ qi) {
+                           const double* __restrict__ q, const int* __restrict__ off,
+                           int64_t nimg, double* __restrict__ xi, double* __restrict__ qi) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const int d = kp.dim;
   double x[3] = {0, 0, 0};
   for (int a = 0; a < d; ++a) x[a] = xs[a * n + i];
-  double qq = q[i];
+  const double qq = q[i];
   int64_t o = off[i];
-  for (int s = 0; s < nsh; ++s) {
-    double y[3];
-    for (int a = 0; a < d; ++a) y[a] = x[a] + sv[s * d + a];
-    if (in_extended(kp, y)) {
-      for (int a = 0; a < d; ++a) xi[a * nimg + o] = y[a];
-      qi[o] = qq;
-      ++o;
-    }
-  }
+  for_each_image(kp, x, [&](const double* y) {
+    for (int a = 0; a < d; ++a) xi[a * nimg + o] = y[a];
+    qi[o] = qq;
+    ++o;
+  });
 }
 
 // -------------------------------------------------------------------- keys
@@ -221,15 +274,14 @@ void stage_images(pdmk_plan* P, Eval& E, const double* q) {
   int* off = E.alloc<int>(n + 1);
   PDMK_HIP(hipMemsetAsync(cnt + n, 0, sizeof(int), E.s));
   if (n > 0)
-    hipLaunchKernelGGL(k_img_count, dim3(nblk(n, 256)), dim3(256), 0, E.s, kp, n, E.xs,
-                       P->d_shiftvec, P->nshift, cnt);
+    hipLaunchKernelGGL(k_img_count, dim3(nblk(n, 256)), dim3(256), 0, E.s, kp, n, E.xs, cnt);
   exclusive_scan_int(cnt, off, (int)(n + 1), E);
   E.n_img = read_int(off + n, E.s);
   double* xi = E.alloc<double>(E.n_img * kp.dim);
   double* qi = E.alloc<double>(E.n_img);
   if (n > 0)
-    hipLaunchKernelGGL(k_img_emit, dim3(nblk(n, 256)), dim3(256), 0, E.s, kp, n, E.xs, q,
-                       P->d_shiftvec, P->nshift, off, E.n_img, xi, qi);
+    hipLaunchKernelGGL(k_img_emit, dim3(nblk(n, 256)), dim3(256), 0, E.s, kp, n, E.xs, q, off,
+                       E.n_img, xi, qi);
   int* perm = nullptr;
   sort_points(P, E, E.n_img, xi, qi, E.skey, E.sx, E.sq, perm);
   double* dummyq = nullptr;
