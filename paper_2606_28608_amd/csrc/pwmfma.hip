@@ -186,14 +186,18 @@ __global__ __launch_bounds__(256) void k_pw_out_mfma(const Real* __restrict__ Q,
 #pragma unroll
           for (int m = 0; m < SH::T2N; ++m) acc[m] = MF::op(av, bf[m][s], acc[m]);
         }
+        // only the modes of the ball |j| <= J are ever read by the translation
 #pragma unroll
         for (int m = 0; m < SH::T2N; ++m) {
           const int col = 16 * m + li;
+          const int j2 = (col >> 1) - J;
           if (col < 2 * N1)
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
               const int row = 16 * t + MF::row(lane, r);
-              if (row < g * N1) Sk[(int64_t)(j0b * N1 + row) * 2 * N1 + col] = acc[m][r];
+              const int jj = row / N1, j1 = row - jj * N1 - J, j0 = j0b + jj;
+              if (row < g * N1 && j0 * j0 + j1 * j1 + j2 * j2 <= J * J)
+                Sk[(int64_t)(j0b * N1 + row) * 2 * N1 + col] = acc[m][r];
             }
         }
       }
