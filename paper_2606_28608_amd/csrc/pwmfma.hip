@@ -65,13 +65,26 @@ struct PwShape {
 
 __host__ __device__ constexpr int align16(int n) { return (n + 15) & ~15; }
 
+// Workgroups of a launch are handed to the eight XCDs round-robin.  This maps
+// the i-th workgroup an XCD receives to the i-th item of that XCD's
+// contiguous share of [0, n), so neighbouring boxes (consecutive in key
+// order) run on the same XCD and share its L2.
+__device__ inline int xcd_contiguous(int b, int n) {
+  const int x = b & 7, q = n >> 3, r = n & 7;
+  return x * q + min(x, r) + (b >> 3);
+}
+
+template <class Real> struct Cplx;
+template <> struct Cplx<float> { using T = float2; };
+template <> struct Cplx<double> { using T = double2; };
+
 // Outgoing plane waves of the non-leaf boxes of one level (one block of 4
 // waves per box).  The constant operands of stages B and C stay in registers
 // for a whole group; the data operands are read from LDS without bounds tests
 // (padding rows/columns of the LDS matrices are zero or only reach discarded
 // outputs).
 template <class Real, int P, int J>
-__global__ __launch_bounds__(256) void k_pw_out_mfma(const Real* __restrict__ Q,
+__global__ __launch_bounds__(256, sizeof(Real) == 4 ? 2 : 1) void k_pw_out_mfma(const Real* __restrict__ Q,
                                                      const Real* __restrict__ TA,
                                                      const Real* __restrict__ TB,
                                                      const Real* __restrict__ TC,
@@ -106,15 +119,26 @@ __global__ __launch_bounds__(256) void k_pw_out_mfma(const Real* __restrict__ Q,
         const int ri = li >= g, jj = li - ri * g;
         bf[s] = (a < P && li < 2 * g) ? TA[(ri * (J + 1) + j0b + jj) * P + a] : (Real)0;
       }
-      for (int t = wave; t < SH::TPP; t += 4) {
-        const int bc = 16 * t + li;
-        V acc = {0, 0, 0, 0};
+      // the proxy charges of every tile of this wave are loaded first (one
+      // memory round trip per group instead of one per tile)
+      constexpr int NT = (SH::TPP + 3) / 4;
+      Real qv[NT][SH::KA / 4];
+#pragma unroll
+      for (int i = 0; i < NT; ++i) {
+        const int bc = 16 * (wave + 4 * i) + li;
 #pragma unroll
         for (int s = 0; s < SH::KA / 4; ++s) {
           const int a = 4 * s + lk;
-          const Real av = (a < P && bc < PP) ? Qk[a * PP + bc] : (Real)0;
-          acc = MF::op(av, bf[s], acc);
+          qv[i][s] = (a < P && bc < PP) ? Qk[a * PP + bc] : (Real)0;
         }
+      }
+#pragma unroll
+      for (int i = 0; i < NT; ++i) {
+        const int t = wave + 4 * i;
+        if (t >= SH::TPP) break;
+        V acc = {0, 0, 0, 0};
+#pragma unroll
+        for (int s = 0; s < SH::KA / 4; ++s) acc = MF::op(qv[i][s], bf[s], acc);
         // acc element r: row bc' = 16 t + row(lane, r), column (ri, jj) = li
         const int ri = li >= g, jj = li - ri * g;
         if (li < 2 * g)
@@ -211,7 +235,7 @@ __global__ __launch_bounds__(256) void k_pw_out_mfma(const Real* __restrict__ Q,
 // difference-kernel multiplier, then the three conjugate contractions into
 // the box's proxy potential (accumulated in registers across the groups).
 template <class Real, int P, int J>
-__global__ __launch_bounds__(256) void k_pw_in_mfma(
+__global__ __launch_bounds__(256, sizeof(Real) == 4 ? 2 : 1) void k_pw_in_mfma(
     KParams kp, Level L, const Real* __restrict__ S, const Real* __restrict__ TA2,
     const Real* __restrict__ TB2, const Real* __restrict__ TC2, const double* __restrict__ dtab,
     const int* __restrict__ ball, const int* __restrict__ ball_beg, double levfac,
@@ -225,22 +249,28 @@ __global__ __launch_bounds__(256) void k_pw_in_mfma(
   extern __shared__ __align__(16) unsigned char smraw[];
   __shared__ int ckc[27], cph[27][3];
   __shared__ int ncol;
-  const int k = blockIdx.x;
+  // colleague plane-wave bases; per class (j mod 3 on each axis) the 2-bit
+  // phase indices of all colleagues, packed
+  __shared__ const typename Cplx<Real>::T* cbase[27];
+  __shared__ unsigned long long phc[27];
+  const int k = xcd_contiguous(blockIdx.x, gridDim.x);
   const int b = L.nl_box[k];
   if (L.tend[b] <= L.tbeg[b]) return;   // no targets below this box
   Real* I = reinterpret_cast<Real*>(smraw);      // align16(G N1) rows x sI: cols 2 j2 + ri
   Real* Y = I + align16(G * N1) * sI;            // K2N rows x sY: rows 2 j1 + ri, cols (jj, c)
   Real* W = Y + SH::K2N * sY;                    // align(2G, 4) rows x sW: cols (b, c)
   const int wrows = (2 * G + 3) & ~3;
+  const int64_t msz = (int64_t)(J + 1) * N1 * N1;   // complex entries per box
   if (threadIdx.x == 0) {
     int m = 0;
     for (int sl = 0; sl < 27; ++sl) {
       const int c = L.coll[b * 27 + sl];
       if (c < 0 || L.nlid[c] < 0) continue;
       ckc[m] = L.nlid[c];
-      cph[m][0] = -(sl % 3 - 1);
-      cph[m][1] = -((sl / 3) % 3 - 1);
-      cph[m][2] = -(sl / 9 - 1);
+      // shift delta = c_T - c_S in units of h, taken mod 3
+      cph[m][0] = (3 - (sl % 3 - 1)) % 3;
+      cph[m][1] = (3 - ((sl / 3) % 3 - 1)) % 3;
+      cph[m][2] = (3 - (sl / 9 - 1)) % 3;
       ++m;
     }
     ncol = m;
@@ -258,6 +288,17 @@ __global__ __launch_bounds__(256) void k_pw_in_mfma(
   for (int e = threadIdx.x; e < wrows * sW; e += 256) W[e] = 0;
   __syncthreads();
   const int nc = ncol;
+  if (threadIdx.x < nc)
+    cbase[threadIdx.x] =
+        reinterpret_cast<const typename Cplx<Real>::T*>(S) + (int64_t)ckc[threadIdx.x] * msz;
+  if (threadIdx.x < 27) {
+    const int t = threadIdx.x, p0 = t % 3, p1 = (t / 3) % 3, p2 = t / 9;
+    unsigned long long code = 0;
+    for (int m = 0; m < nc; ++m)
+      code |= (unsigned long long)((p0 * cph[m][0] + p1 * cph[m][1] + p2 * cph[m][2]) % 3)
+              << (2 * m);
+    phc[t] = code;
+  }
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int li = lane & 15, lk = lane >> 4;
   V acc[SH::TP][NACC];
@@ -265,17 +306,7 @@ __global__ __launch_bounds__(256) void k_pw_in_mfma(
   for (int m = 0; m < SH::TP; ++m)
 #pragma unroll
     for (int i = 0; i < NACC; ++i) acc[m][i] = V{0, 0, 0, 0};
-  const int64_t msz = (int64_t)(J + 1) * N1 * N1;   // complex entries per box
-  // colleague plane-wave bases and shift vectors delta mod 3
-  __shared__ const Real* cbase[27];
-  __shared__ int cdel[27];
-  if (threadIdx.x < nc) {
-    const int m = threadIdx.x;
-    cbase[m] = S + (int64_t)ckc[m] * msz * 2;
-    cdel[m] = ((cph[m][0] + 3) % 3) | (((cph[m][1] + 3) % 3) << 2) | (((cph[m][2] + 3) % 3) << 4);
-  }
-  const Real w3r[3] = {(Real)1, (Real)-0.5, (Real)-0.5};
-  const Real w3i[3] = {(Real)0, (Real)0.8660254037844386, (Real)-0.8660254037844386};
+  const Real s3 = (Real)0.8660254037844386;   // sin(2 pi / 3)
   for (int j0b = 0; j0b <= J; j0b += G) {
     const int g = min(G, J + 1 - j0b);
     // translation over the modes of the ball |j| <= J only (the rest of the
@@ -291,20 +322,30 @@ __global__ __launch_bounds__(256) void k_pw_in_mfma(
       const int j0 = code & 255, j1i = (code >> 8) & 255, j2i = code >> 16;
       const int j1 = j1i - J, j2 = j2i - J;
       const int nn = j0 * j0 + j1 * j1 + j2 * j2;
-      const int p0 = j0 % 3, p1 = (j1 + 3 * J) % 3, p2 = (j2 + 3 * J) % 3;
-      const int64_t off = ((int64_t)j0 * N1 * N1 + j1i * N1 + j2i) * 2;
+      const int pc = j0 % 3 + 3 * ((j1 + 3 * J) % 3) + 9 * ((j2 + 3 * J) % 3);
+      const int off = (j0 * N1 + j1i) * N1 + j2i;
+      // colleagues nine at a time: all nine loads in flight, then their sum
+      const unsigned long long ph = phc[pc];
       Real ar = 0, ai = 0;
-      for (int m = 0; m < nc; ++m) {
-        const int dl = cdel[m];
-        const int ph = (p0 * (dl & 3) + p1 * ((dl >> 2) & 3) + p2 * (dl >> 4)) % 3;
-        const Real* v = cbase[m] + off;
-        const Real vr = v[0], vi = v[1];
-        const Real cr = ph == 0 ? (Real)1 : (Real)-0.5;
-        const Real ci = ph == 0 ? (Real)0 : (ph == 1 ? w3i[1] : w3i[2]);
-        ar = fma(cr, vr, ar);
-        ar = fma(-ci, vi, ar);
-        ai = fma(cr, vi, ai);
-        ai = fma(ci, vr, ai);
+#pragma unroll 1
+      for (int m0 = 0; m0 < nc; m0 += 9) {
+        typename Cplx<Real>::T v[9];
+#pragma unroll
+        for (int u = 0; u < 9; ++u) {
+          v[u].x = 0;
+          v[u].y = 0;
+          if (m0 + u < nc) v[u] = cbase[m0 + u][off];
+        }
+#pragma unroll
+        for (int u = 0; u < 9; ++u) {
+          const int q = (int)(ph >> (2 * (m0 + u))) & 3;
+          const Real cr = q == 0 ? (Real)1 : (Real)-0.5;
+          const Real ci = q == 0 ? (Real)0 : (q == 1 ? s3 : -s3);
+          ar = fma(cr, v[u].x, ar);
+          ar = fma(-ci, v[u].y, ar);
+          ai = fma(cr, v[u].y, ai);
+          ai = fma(ci, v[u].x, ai);
+        }
       }
       const Real cf = (Real)(levfac * dtab[nn]);
       Real* dst = I + ((j0 - j0b) * N1 + j1i) * sI + 2 * j2i;
