@@ -30,6 +30,16 @@ __device__ inline void lagrange_rows(int p, const double* __restrict__ nodes,
   }
 }
 
+// 1/d from the hardware reciprocal estimate refined by two Newton steps
+// (r <- r + r (1 - d r)); each step squares the relative error, so the result
+// is within a few units in the last place of the correctly rounded quotient.
+__device__ inline double recip_nr(double d) {
+  double r = __builtin_amdgcn_rcp(d);
+  r = fma(r, fma(-d, r, 1.0), r);
+  r = fma(r, fma(-d, r, 1.0), r);
+  return r;
+}
+
 // Same as lagrange_rows with compile-time capacity PMAX (entries >= p are 0),
 // so the rows stay in registers.
 template <int PMAX, bool DER>
@@ -44,7 +54,7 @@ __device__ inline void lagrange_rows_reg(int p, const double* __restrict__ nodes
 #pragma unroll
   for (int m = 0; m < PMAX; ++m) {
     if (m < p) {
-      inv[m] = 1.0 / (x - nodes[m]);
+      inv[m] = recip_nr(x - nodes[m]);
       const double t = bw[m] * inv[m];
       row[m] = t;
       s += t;

@@ -74,6 +74,25 @@ __device__ inline int xcd_contiguous(int b, int n) {
   return x * q + min(x, r) + (b >> 3);
 }
 
+// Fills dst[0, n) from load(e) with `B` loads in flight per thread (all
+// loads of a batch are issued before its LDS stores).
+template <int B, class Real, class Load>
+__device__ inline void lds_fill(Real* dst, int n, Load load) {
+  for (int e0 = threadIdx.x; e0 < n; e0 += B * 256) {
+    Real v[B];
+#pragma unroll
+    for (int u = 0; u < B; ++u) {
+      const int e = e0 + u * 256;
+      v[u] = e < n ? load(e) : (Real)0;
+    }
+#pragma unroll
+    for (int u = 0; u < B; ++u) {
+      const int e = e0 + u * 256;
+      if (e < n) dst[e] = v[u];
+    }
+  }
+}
+
 template <class Real> struct Cplx;
 template <> struct Cplx<float> { using T = float2; };
 template <> struct Cplx<double> { using T = double2; };
@@ -509,10 +528,10 @@ __global__ __launch_bounds__(256) void k_eval_leaf_mfma(
   const int total = cpre[8];
   if (total == 0) return;
   const Real* Phi = static_cast<const Real*>(Lp.proxy_phi) + (int64_t)k * P * PP;
-  for (int e = threadIdx.x; e < 16 * MT * SP; e += 256) {
+  lds_fill<8>(PhiA, 16 * MT * SP, [&](int e) {
     const int m = e / SP, c = e - m * SP;
-    PhiA[e] = (m < PP && c < P) ? Phi[m * P + c] : (Real)0;
-  }
+    return (m < PP && c < P) ? Phi[m * P + c] : (Real)0;
+  });
   __syncthreads();
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int li = lane & 15, lk = lane >> 4;
@@ -837,59 +856,97 @@ __global__ __launch_bounds__(256) void k_transfer_mfma(Level Lp, Level Lc,
                        ? (Real)(UP ? Tm[sel * PP + o * P + i] : Tm[sel * PP + i * P + o])
                        : (Real)0;
       }
+    if (st == 0) {
+      // every input value of this wave's tiles is loaded before the products
+      Real bq[NW][KA / 4];
 #pragma unroll
-    for (int w = 0; w < NW; ++w) {
-      const int t = wave + 4 * w;
-#pragma unroll
-      for (int m = 0; m < MTL; ++m) acc[w][m] = V{0, 0, 0, 0};
-      if (t < NTILE) {
-        const int n = 16 * t + li;
+      for (int w = 0; w < NW; ++w) {
+        const int n = 16 * (wave + 4 * w) + li;
 #pragma unroll
         for (int q = 0; q < KA / 4; ++q) {
           const int i = 4 * q + lk;
-          Real bv;
-          if (st == 0) bv = (i < P && n < PP) ? in[i * PP + n] : (Real)0;
-          else bv = buf[i * SB + n];
-#pragma unroll
-          for (int m = 0; m < MTL; ++m) acc[w][m] = MF::op(af[m][q], bv, acc[w][m]);
+          bq[w][q] = (i < P && n < PP) ? in[i * PP + n] : (Real)0;
         }
       }
-    }
-    if (st < 2) {
-      __syncthreads();   // every wave has read the buffer
+#pragma unroll
+      for (int w = 0; w < NW; ++w) {
+#pragma unroll
+        for (int m = 0; m < MTL; ++m) acc[w][m] = V{0, 0, 0, 0};
+        if (wave + 4 * w < NTILE)
+#pragma unroll
+          for (int q = 0; q < KA / 4; ++q)
+#pragma unroll
+            for (int m = 0; m < MTL; ++m) acc[w][m] = MF::op(af[m][q], bq[w][q], acc[w][m]);
+      }
+    } else {
 #pragma unroll
       for (int w = 0; w < NW; ++w) {
         const int t = wave + 4 * w;
-        const int n = 16 * t + li;   // (j, k)
-        if (t < NTILE && n < PP) {
-          const int j = n / P, kk = n - j * P;
 #pragma unroll
-          for (int m = 0; m < MTL; ++m)
+        for (int m = 0; m < MTL; ++m) acc[w][m] = V{0, 0, 0, 0};
+        if (t < NTILE) {
+          const int n = 16 * t + li;
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-              const int o = 16 * m + MF::row(lane, r);
-              if (o < P) buf[j * SB + kk * P + o] = acc[w][m][r];
-            }
-        }
-      }
-      __syncthreads();
-    }
-  }
+          for (int q = 0; q < KA / 4; ++q) {
+            const Real bv = buf[(4 * q + lk) * SB + n];
 #pragma unroll
-  for (int w = 0; w < NW; ++w) {
-    const int t = wave + 4 * w;
-    const int n = 16 * t + li;
-    if (t < NTILE && n < PP)
-#pragma unroll
-      for (int m = 0; m < MTL; ++m)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int o = 16 * m + MF::row(lane, r);
-          if (o < P) {
-            if (UP) atomicAdd(out + n * P + o, acc[w][m][r]);
-            else out[n * P + o] += acc[w][m][r];
+            for (int m = 0; m < MTL; ++m) acc[w][m] = MF::op(af[m][q], bv, acc[w][m]);
           }
         }
+      }
+    }
+    __syncthreads();   // every wave has read the buffer
+#pragma unroll
+    for (int w = 0; w < NW; ++w) {
+      const int t = wave + 4 * w;
+      const int n = 16 * t + li;   // (j, k)
+      if (t < NTILE && n < PP) {
+        const int j = n / P, kk = n - j * P;
+#pragma unroll
+        for (int m = 0; m < MTL; ++m)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int o = 16 * m + MF::row(lane, r);
+            if (o < P) buf[j * SB + kk * P + o] = acc[w][m][r];
+          }
+      }
+    }
+    __syncthreads();
+  }
+  // after the third product buf holds the tensor in its natural order (row j
+  // of P^2 entries at stride SB): coalesced update of the output, eight
+  // entries per thread in flight
+  constexpr int NE = P * PP;
+  for (int e0 = threadIdx.x; e0 < NE; e0 += 8 * 256) {
+    Real v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int e = e0 + u * 256;
+      v[u] = 0;
+      if (e < NE) {
+        const int j = e / PP;
+        v[u] = buf[j * SB + (e - j * PP)];
+      }
+    }
+    if (UP) {
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int e = e0 + u * 256;
+        if (e < NE) atomicAdd(out + e, v[u]);
+      }
+    } else {
+      Real o[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int e = e0 + u * 256;
+        o[u] = e < NE ? out[e] : (Real)0;
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int e = e0 + u * 256;
+        if (e < NE) out[e] = o[u] + v[u];
+      }
+    }
   }
 }
 
@@ -912,12 +969,12 @@ static void transfer_launch(const pdmk_plan* P, const Level& Lp, const Level& Lc
   }
 }
 
-// Used for FP64 tensors; in FP32 the vector-ALU line transforms of the whole
-// sibling group (one block per parent, no atomics) measured faster.
+// 3D proxy transfers on the matrix cores for the (p, J) pairs that have
+// matrix-core plane-wave kernels (FP32 and FP64 tensors).
 template <class Real>
 bool transfer_mfma(const pdmk_plan* P, const Level& Lp, const Level& Lc, bool up,
                    const void* src, void* dst, hipStream_t s) {
-  if (P->kp.dim != 3 || !P->pw_mfma || sizeof(Real) != 8) return false;
+  if (P->kp.dim != 3 || !P->pw_mfma) return false;
   if (P->kp.p == 22) transfer_launch<Real, 22>(P, Lp, Lc, up, src, dst, s);
   else if (P->kp.p == 13) transfer_launch<Real, 13>(P, Lp, Lc, up, src, dst, s);
   else return false;
