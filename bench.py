@@ -31,6 +31,7 @@ sys.path.insert(0, ROOT)
 # a compactly supported polynomial kernel), matrix cores for the plane-wave
 # contractions; both are 157.3 TFLOP/s in FP32 and 78.6 TFLOP/s in FP64.
 PEAK_TFLOPS = {"fp64": 78.6, "mixed": 157.3}
+PEAK_HBM_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_shell3d_n1e7_eps1e-6.json")
 KERNEL_SRCS = [os.path.join(ROOT, "paper_2606_28608_amd", "csrc", f)
                for f in ("near.hip", "pwmfma.hip")]
@@ -166,7 +167,7 @@ def roofline_all(r, mode, plan):
     P, J = plan["porder"], plan["npw"]
     nb = _ball_modes(J)
     tr = pw_fma_per_box(P, J)
-    flop_in = 2.0 * tr * st["n_pwin_boxes"] + 8.0 * nb * st["n_pw_pairs"]
+    flop_in = 2.0 * tr * st["n_pwin_boxes"]
     flop_out = 2.0 * tr * st["n_pwout_boxes"]
     nlev = st["n_levels"] - 1
     for name, f, tms in (("k_pw_in", flop_in, sm.get("t_pwin_ms", 0.0)),
@@ -176,6 +177,19 @@ def roofline_all(r, mode, plan):
                      "peak": PEAK_TFLOPS[mode], "unit": "TFLOP/s", "launch_ms": tms / max(1, nlev),
                      "launches": nlev, "flop_per_launch": f / max(1, nlev),
                      "flop_per_box": 2.0 * tr}
+    # colleague translation: compulsory bytes = every outgoing expansion of
+    # the level read once + every incoming expansion written once (half-ball
+    # modes, complex FP32 or FP64)
+    cb = 8 if mode == "mixed" else 16
+    tms = sm.get("t_pwtr_ms", 0.0)
+    if tms > 0:
+        by = float(nb * cb * (st["n_pwout_boxes"] + st["n_pwin_boxes"]))
+        t = tms * 1e-3
+        out["k_pw_trans"] = {"bound": "hbm", "achieved": by / t / 1e9, "peak": PEAK_HBM_GBS,
+                             "unit": "GB/s", "launch_ms": tms / max(1, nlev), "launches": nlev,
+                             "bytes_per_launch": by / max(1, nlev),
+                             "bytes_per_box": nb * cb,
+                             "flop_per_launch": 8.0 * nb * st["n_pw_pairs"] / max(1, nlev)}
     for v in out.values():
         v["frac"] = v["achieved"] / v["peak"]
     return out

@@ -218,6 +218,8 @@ typedef struct {
   int64_t n_pwout_boxes;            /* boxes given outgoing plane waves (all levels) */
   int64_t n_pwin_boxes;             /* boxes given incoming plane waves (with targets) */
   double t_pwout_ms, t_pwin_ms;     /* time of the outgoing / incoming plane-wave kernels */
+  double t_pwtr_ms;                 /* time of the colleague translation kernel (matrix-core
+                                       path; 0 where the incoming kernel translates itself) */
 } pdmk_stats;
 int pdmk_plan_stats(const pdmk_plan* plan, pdmk_stats* out);
 int pdmk_batch_stats(const pdmk_batch* batch, int sys, pdmk_stats* out);

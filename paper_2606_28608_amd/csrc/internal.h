@@ -162,6 +162,7 @@ struct pdmk_plan {
   double* d_pwt_d = nullptr;
   size_t pwt_off[6] = {0, 0, 0, 0, 0, 0};
   int* d_ball = nullptr;        // modes of the half ball, then the slab starts
+  int2* d_brow = nullptr;       // per mode row (j0, j1 + J): {index of j2 = -J, half width}
   int nball = 0;
   bool pw_mfma = true;          // use the matrix-core plane-wave kernels when they fit
   // stages that run in FP32 in mixed mode: 1 residual sums, 2 proxies and
@@ -199,10 +200,13 @@ struct PwMfmaShape {
 };
 PwMfmaShape pw_mfma_shape(int p, int J, size_t real_size);
 void pw_mfma_upload(pdmk_plan* P);
+// One level: outgoing expansions into S (compact half-ball order), the
+// colleague translation into Iw, incoming expansions into proxy_phi; ev_out /
+// ev_tr (optional) are recorded after the first two kernels.
 template <class Real>
 void pw_mfma_level(const pdmk_plan* P, const Level& L, int nn, const void* proxy_q, void* S,
-                   void* proxy_phi, double levfac, unsigned long long* npairs, hipEvent_t mid,
-                   hipStream_t s);
+                   void* Iw, void* proxy_phi, double levfac, unsigned long long* npairs,
+                   hipEvent_t ev_out, hipEvent_t ev_tr, hipStream_t s);
 
 template <class Real>
 bool eval_leaf_mfma(const pdmk_plan* P, const Level& Lp, const Level& Lc, int l,

@@ -1102,14 +1102,17 @@ static void near_impl(pdmk_plan* P, Eval& E, bool want_grad) {
     const size_t lds_in = lds_pw_in(p, J, sizeof(Real));
     const bool fused = D == 3 && lds_out <= 150 * 1024 && lds_in <= 150 * 1024;
     const bool mfma = D == 3 && P->pw_mfma && pw_mfma_shape(p, J, sizeof(Real)).ok;
-    C* bS = E.alloc<C>((size_t)maxnl * s3);
+    // matrix-core path: outgoing and translated incoming expansions in compact
+    // half-ball order; vector-ALU path: outgoing expansions on the full grid
+    C* bS = E.alloc<C>((size_t)maxnl * (mfma ? P->nball : s3));
+    C* bIw = mfma ? E.alloc<C>((size_t)maxnl * P->nball) : nullptr;
     double2* bA = fused ? nullptr : E.alloc<double2>((size_t)maxnl * s1);
     double2* bB = (D == 3 && !fused) ? E.alloc<double2>((size_t)maxnl * s2) : nullptr;
     double2* bI = fused ? nullptr : E.alloc<double2>((size_t)maxnl * s3);
     // [0] colleague pairs translated, [1] boxes given incoming plane waves
     unsigned long long* npairs = E.alloc<unsigned long long>(2);
     PDMK_HIP(hipMemsetAsync(npairs, 0, 2 * sizeof(unsigned long long), s));
-    std::vector<std::array<hipEvent_t, 3>> pw_events;
+    std::vector<std::array<hipEvent_t, 4>> pw_events;
     const C* Ftab = reinterpret_cast<const C*>(sizeof(Real) == 4 ? (const void*)P->d_Ff
                                                                  : (const void*)P->d_F);
     if (fused) {
@@ -1125,13 +1128,15 @@ static void near_impl(pdmk_plan* P, Eval& E, bool want_grad) {
       const double h = kp.rc / (double)(1 << l);
       const double levfac = D == 3 ? 1.0 / (3.0 * h) : 1.0;
       const int zz = D == 3 ? p : 1;
-      hipEvent_t pe[3];
+      // pe[0] | outgoing | pe[1] | translation (matrix-core path) | pe[3] | incoming | pe[2]
+      hipEvent_t pe[4];
       for (auto& e : pe) PDMK_HIP(hipEventCreate(&e));
-      pw_events.push_back({pe[0], pe[1], pe[2]});
+      pw_events.push_back({pe[0], pe[1], pe[2], pe[3]});
       E.st.n_pwout_boxes += nn;
       PDMK_HIP(hipEventRecord(pe[0], s));
       if (mfma) {
-        pw_mfma_level<Real>(P, L, nn, L.proxy_q, bS, L.proxy_phi, levfac, npairs, pe[1], s);
+        pw_mfma_level<Real>(P, L, nn, L.proxy_q, bS, bIw, L.proxy_phi, levfac, npairs, pe[1],
+                            pe[3], s);
         PDMK_HIP(hipEventRecord(pe[2], s));
         continue;
       }
@@ -1192,10 +1197,16 @@ static void near_impl(pdmk_plan* P, Eval& E, bool want_grad) {
     E.st.n_pw_pairs = (int64_t)np[0];
     E.st.n_pwin_boxes = (int64_t)np[1];
     for (auto& pe : pw_events) {
-      float a = 0, b = 0;
+      float a = 0, b = 0, c = 0;
       PDMK_HIP(hipEventElapsedTime(&a, pe[0], pe[1]));
-      PDMK_HIP(hipEventElapsedTime(&b, pe[1], pe[2]));
+      if (mfma) {
+        PDMK_HIP(hipEventElapsedTime(&c, pe[1], pe[3]));
+        PDMK_HIP(hipEventElapsedTime(&b, pe[3], pe[2]));
+      } else {
+        PDMK_HIP(hipEventElapsedTime(&b, pe[1], pe[2]));
+      }
       E.st.t_pwout_ms += a;
+      E.st.t_pwtr_ms += c;
       E.st.t_pwin_ms += b;
       for (auto& e : pe) (void)hipEventDestroy(e);
     }

@@ -103,12 +103,10 @@ template <> struct Cplx<double> { using T = double2; };
 // (padding rows/columns of the LDS matrices are zero or only reach discarded
 // outputs).
 template <class Real, int P, int J>
-__global__ __launch_bounds__(256, sizeof(Real) == 4 ? 2 : 1) void k_pw_out_mfma(const Real* __restrict__ Q,
-                                                     const Real* __restrict__ TA,
-                                                     const Real* __restrict__ TB,
-                                                     const Real* __restrict__ TC,
-                                                     Real* __restrict__ S, int G, int sX,
-                                                     int sZ) {
+__global__ __launch_bounds__(256, sizeof(Real) == 4 ? 2 : 1) void k_pw_out_mfma(
+    const Real* __restrict__ Q, const Real* __restrict__ TA, const Real* __restrict__ TB,
+    const Real* __restrict__ TC, const int2* __restrict__ brow, int nball,
+    Real* __restrict__ S, int G, int sX, int sZ) {
   using SH = PwShape<P, J>;
   using MF = Mfma<Real>;
   using V = typename MF::V;
@@ -126,7 +124,11 @@ __global__ __launch_bounds__(256, sizeof(Real) == 4 ? 2 : 1) void k_pw_out_mfma(
     Z[r * sZ + 2 * P + c] = 0;
   }
   const Real* Qk = Q + (int64_t)k * P * PP;
-  Real* Sk = S + (int64_t)k * (J + 1) * N1 * N1 * 2;
+  Real* Sk = S + (int64_t)k * nball * 2;   // compact half-ball order, re/im interleaved
+  // per row (j0, j1 + J) of the mode grid: {compact index of j2 = -J, half
+  // width w}; the row's ball modes are |j2| <= w (w < 0: none)
+  __shared__ int2 rows[(J + 1) * N1];
+  for (int e = threadIdx.x; e < (J + 1) * N1; e += 256) rows[e] = brow[e];
   for (int j0b = 0; j0b <= J; j0b += G) {
     const int g = min(G, J + 1 - j0b);
     // stage A (transposed): X^T[bc][(ri,jj)] = sum_a Q[a][bc] TA[(ri, j0b+jj)][a]
@@ -229,18 +231,19 @@ __global__ __launch_bounds__(256, sizeof(Real) == 4 ? 2 : 1) void k_pw_out_mfma(
 #pragma unroll
           for (int m = 0; m < SH::T2N; ++m) acc[m] = MF::op(av, bf[m][s], acc[m]);
         }
-        // only the modes of the ball |j| <= J are ever read by the translation
+        // only the modes of the ball |j| <= J are kept
 #pragma unroll
         for (int m = 0; m < SH::T2N; ++m) {
           const int col = 16 * m + li;
-          const int j2 = (col >> 1) - J;
           if (col < 2 * N1)
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-              const int row = 16 * t + MF::row(lane, r);
-              const int jj = row / N1, j1 = row - jj * N1 - J, j0 = j0b + jj;
-              if (row < g * N1 && j0 * j0 + j1 * j1 + j2 * j2 <= J * J)
-                Sk[(int64_t)(j0b * N1 + row) * 2 * N1 + col] = acc[m][r];
+              const int row = 16 * t + MF::row(lane, r);   // (jj, j1)
+              if (row < g * N1) {
+                const int2 rw = rows[j0b * N1 + row];
+                const int j2 = (col >> 1) - J;
+                if (j2 <= rw.y && -j2 <= rw.y) Sk[2 * (rw.x + (col >> 1)) + (col & 1)] = acc[m][r];
+              }
             }
         }
       }
@@ -249,55 +252,134 @@ __global__ __launch_bounds__(256, sizeof(Real) == 4 ? 2 : 1) void k_pw_out_mfma(
   }
 }
 
-// Incoming plane waves of the non-leaf boxes of one level that hold targets:
-// translation from the colleagues that have children, scaled by the
-// difference-kernel multiplier, then the three conjugate contractions into
-// the box's proxy potential (accumulated in registers across the groups).
+// Colleague translation of one level (Section 3.5): for each non-leaf box T
+// with targets and each mode j of the half ball,
+//   I_T[j] = levfac Dhat(|j|^2) sum_C omega^{j.delta} S_C[j],   omega = exp(2 pi i / 3),
+// over the colleagues C of T that have children, delta = (c_T - c_S) / h.
+// One block per (chunk of kTransChunk modes, box); blocks are numbered
+// chunk-major and handed to the XCDs in contiguous ranges, so the boxes that
+// run together on an XCD read the same mode chunk of overlapping colleague
+// sets and find it in that XCD's L2.  Expansions are in compact half-ball
+// order, so lanes read consecutive modes of each colleague.
+constexpr int kTransChunk = 1024;
+template <class Real>
+__global__ __launch_bounds__(256) void k_pw_trans(Level L, const typename Cplx<Real>::T* __restrict__ S,
+                                                  const double* __restrict__ dtab,
+                                                  const int* __restrict__ ball, int nball, int J,
+                                                  double levfac,
+                                                  typename Cplx<Real>::T* __restrict__ Iw,
+                                                  unsigned long long* __restrict__ npairs) {
+  using C2 = typename Cplx<Real>::T;
+  __shared__ const C2* cbase[27];
+  __shared__ int cdl[27];
+  __shared__ unsigned long long phc[27];
+  __shared__ int ncol;
+  const int nn = L.nnl;
+  const int idx = xcd_contiguous(blockIdx.x, gridDim.x);
+  const int ch = idx / nn, k = idx - ch * nn;
+  const int b = L.nl_box[k];
+  if (L.tend[b] <= L.tbeg[b]) return;   // no targets below this box
+  if (threadIdx.x < 64) {
+    // slot sl of the 3x3x3 neighbourhood: a colleague with children?
+    const int sl = threadIdx.x;
+    int kc = -1;
+    if (sl < 27) {
+      const int c = L.coll[b * 27 + sl];
+      if (c >= 0) kc = L.nlid[c];
+    }
+    const unsigned long long mask = __ballot(kc >= 0);
+    if (kc >= 0) {
+      const int pos = __popcll(mask & ((1ull << sl) - 1));
+      cbase[pos] = S + (int64_t)kc * nball;
+      // delta = c_T - c_S in units of h, each component taken mod 3
+      cdl[pos] = ((3 - (sl % 3 - 1)) % 3) | (((3 - ((sl / 3) % 3 - 1)) % 3) << 2) |
+                 (((3 - (sl / 9 - 1)) % 3) << 4);
+    }
+    if (sl == 0) {
+      const int m = __popcll(mask);
+      ncol = m;
+      if (npairs && ch == 0) {
+        atomicAdd(npairs, (unsigned long long)m);
+        atomicAdd(npairs + 1, 1ull);
+      }
+    }
+  }
+  __syncthreads();
+  const int nc = ncol;
+  if (threadIdx.x < 27) {
+    // per class (j mod 3 on each axis): the 2-bit phase index of every colleague
+    const int t = threadIdx.x, p0 = t % 3, p1 = (t / 3) % 3, p2 = t / 9;
+    unsigned long long code = 0;
+    for (int m = 0; m < nc; ++m) {
+      const int dl = cdl[m];
+      code |= (unsigned long long)((p0 * (dl & 3) + p1 * ((dl >> 2) & 3) + p2 * (dl >> 4)) % 3)
+              << (2 * m);
+    }
+    phc[t] = code;
+  }
+  __syncthreads();
+  const Real s3 = (Real)0.8660254037844386;   // sin(2 pi / 3)
+  const int ee = min(nball, (ch + 1) * kTransChunk);
+  C2* out = Iw + (int64_t)k * nball;
+  for (int e = ch * kTransChunk + (int)threadIdx.x; e < ee; e += 256) {
+    const int code = ball[e];   // j0 | j1i << 8 | j2i << 16
+    const int j0 = code & 255, j1 = ((code >> 8) & 255) - J, j2 = (code >> 16) - J;
+    const int pc = j0 % 3 + 3 * ((j1 + 3 * J) % 3) + 9 * ((j2 + 3 * J) % 3);
+    const unsigned long long ph = phc[pc];
+    Real ar = 0, ai = 0;
+    // colleagues nine at a time: all nine loads in flight, then their sum
+#pragma unroll 1
+    for (int m0 = 0; m0 < nc; m0 += 9) {
+      C2 v[9];
+#pragma unroll
+      for (int u = 0; u < 9; ++u) {
+        v[u].x = 0;
+        v[u].y = 0;
+        if (m0 + u < nc) v[u] = cbase[m0 + u][e];
+      }
+#pragma unroll
+      for (int u = 0; u < 9; ++u) {
+        const int q = (int)(ph >> (2 * (m0 + u))) & 3;
+        const Real cr = q == 0 ? (Real)1 : (Real)-0.5;
+        const Real ci = q == 0 ? (Real)0 : (q == 1 ? s3 : -s3);
+        ar = fma(cr, v[u].x, ar);
+        ar = fma(-ci, v[u].y, ar);
+        ai = fma(cr, v[u].y, ai);
+        ai = fma(ci, v[u].x, ai);
+      }
+    }
+    const Real cf = (Real)(levfac * dtab[j0 * j0 + j1 * j1 + j2 * j2]);
+    C2 r;
+    r.x = ar * cf;
+    r.y = ai * cf;
+    out[e] = r;
+  }
+}
+
+// Incoming plane waves of the non-leaf boxes of one level that hold targets
+// (already translated and scaled, in compact half-ball order) become the
+// box's proxy potential by the three conjugate contractions (accumulated in
+// registers across the slab groups).
 template <class Real, int P, int J>
 __global__ __launch_bounds__(256, sizeof(Real) == 4 ? 2 : 1) void k_pw_in_mfma(
-    KParams kp, Level L, const Real* __restrict__ S, const Real* __restrict__ TA2,
-    const Real* __restrict__ TB2, const Real* __restrict__ TC2, const double* __restrict__ dtab,
-    const int* __restrict__ ball, const int* __restrict__ ball_beg, double levfac,
-    Real* __restrict__ Phi, unsigned long long* __restrict__ npairs, int G, int sI, int sY,
+    Level L, const typename Cplx<Real>::T* __restrict__ Iw, const Real* __restrict__ TA2,
+    const Real* __restrict__ TB2, const Real* __restrict__ TC2, const int* __restrict__ ball,
+    const int* __restrict__ ball_beg, int nball, Real* __restrict__ Phi, int G, int sI, int sY,
     int sW) {
   using SH = PwShape<P, J>;
   using MF = Mfma<Real>;
   using V = typename MF::V;
+  using C2 = typename Cplx<Real>::T;
   constexpr int N1 = SH::N1, PP = P * P;
   constexpr int NACC = (SH::TPP + 3) / 4;   // Phi column tiles per wave
   extern __shared__ __align__(16) unsigned char smraw[];
-  __shared__ int ckc[27], cph[27][3];
-  __shared__ int ncol;
-  // colleague plane-wave bases; per class (j mod 3 on each axis) the 2-bit
-  // phase indices of all colleagues, packed
-  __shared__ const typename Cplx<Real>::T* cbase[27];
-  __shared__ unsigned long long phc[27];
-  const int k = xcd_contiguous(blockIdx.x, gridDim.x);
+  const int k = blockIdx.x;
   const int b = L.nl_box[k];
   if (L.tend[b] <= L.tbeg[b]) return;   // no targets below this box
   Real* I = reinterpret_cast<Real*>(smraw);      // align16(G N1) rows x sI: cols 2 j2 + ri
   Real* Y = I + align16(G * N1) * sI;            // K2N rows x sY: rows 2 j1 + ri, cols (jj, c)
   Real* W = Y + SH::K2N * sY;                    // align(2G, 4) rows x sW: cols (b, c)
   const int wrows = (2 * G + 3) & ~3;
-  const int64_t msz = (int64_t)(J + 1) * N1 * N1;   // complex entries per box
-  if (threadIdx.x == 0) {
-    int m = 0;
-    for (int sl = 0; sl < 27; ++sl) {
-      const int c = L.coll[b * 27 + sl];
-      if (c < 0 || L.nlid[c] < 0) continue;
-      ckc[m] = L.nlid[c];
-      // shift delta = c_T - c_S in units of h, taken mod 3
-      cph[m][0] = (3 - (sl % 3 - 1)) % 3;
-      cph[m][1] = (3 - ((sl / 3) % 3 - 1)) % 3;
-      cph[m][2] = (3 - (sl / 9 - 1)) % 3;
-      ++m;
-    }
-    ncol = m;
-    if (npairs) {
-      atomicAdd(npairs, (unsigned long long)m);
-      atomicAdd(npairs + 1, 1ull);
-    }
-  }
   // zero the padding: I columns >= 2 N1, Y rows >= 2 N1, all of W
   for (int e = threadIdx.x; e < align16(G * N1) * (SH::K2N - 2 * N1); e += 256) {
     const int r = e / (SH::K2N - 2 * N1), c = e - r * (SH::K2N - 2 * N1);
@@ -305,19 +387,6 @@ __global__ __launch_bounds__(256, sizeof(Real) == 4 ? 2 : 1) void k_pw_in_mfma(
   }
   for (int e = threadIdx.x; e < (SH::K2N - 2 * N1) * sY; e += 256) Y[2 * N1 * sY + e] = 0;
   for (int e = threadIdx.x; e < wrows * sW; e += 256) W[e] = 0;
-  __syncthreads();
-  const int nc = ncol;
-  if (threadIdx.x < nc)
-    cbase[threadIdx.x] =
-        reinterpret_cast<const typename Cplx<Real>::T*>(S) + (int64_t)ckc[threadIdx.x] * msz;
-  if (threadIdx.x < 27) {
-    const int t = threadIdx.x, p0 = t % 3, p1 = (t / 3) % 3, p2 = t / 9;
-    unsigned long long code = 0;
-    for (int m = 0; m < nc; ++m)
-      code |= (unsigned long long)((p0 * cph[m][0] + p1 * cph[m][1] + p2 * cph[m][2]) % 3)
-              << (2 * m);
-    phc[t] = code;
-  }
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int li = lane & 15, lk = lane >> 4;
   V acc[SH::TP][NACC];
@@ -325,51 +394,34 @@ __global__ __launch_bounds__(256, sizeof(Real) == 4 ? 2 : 1) void k_pw_in_mfma(
   for (int m = 0; m < SH::TP; ++m)
 #pragma unroll
     for (int i = 0; i < NACC; ++i) acc[m][i] = V{0, 0, 0, 0};
-  const Real s3 = (Real)0.8660254037844386;   // sin(2 pi / 3)
+  const C2* Ik = Iw + (int64_t)k * nball;
   for (int j0b = 0; j0b <= J; j0b += G) {
     const int g = min(G, J + 1 - j0b);
-    // translation over the modes of the ball |j| <= J only (the rest of the
-    // slab group stays zero): I[(jj,j1)][2j2+ri] = c(|j|^2) sum_C omega^{j.delta} S_C[j]
+    // the group's half-ball modes into the zeroed slab matrix
+    // I[(jj,j1)][2j2+ri] (modes outside the ball stay zero)
     for (int e = threadIdx.x; e < g * N1 * 2 * N1; e += blockDim.x) {
       const int r = e / (2 * N1), c = e - r * (2 * N1);
       I[r * sI + c] = 0;
     }
     __syncthreads();
     const int eb = ball_beg[j0b], ee = ball_beg[j0b + g];
-    for (int e = eb + (int)threadIdx.x; e < ee; e += blockDim.x) {
-      const int code = ball[e];   // j0 | j1i << 8 | j2i << 16
-      const int j0 = code & 255, j1i = (code >> 8) & 255, j2i = code >> 16;
-      const int j1 = j1i - J, j2 = j2i - J;
-      const int nn = j0 * j0 + j1 * j1 + j2 * j2;
-      const int pc = j0 % 3 + 3 * ((j1 + 3 * J) % 3) + 9 * ((j2 + 3 * J) % 3);
-      const int off = (j0 * N1 + j1i) * N1 + j2i;
-      // colleagues nine at a time: all nine loads in flight, then their sum
-      const unsigned long long ph = phc[pc];
-      Real ar = 0, ai = 0;
-#pragma unroll 1
-      for (int m0 = 0; m0 < nc; m0 += 9) {
-        typename Cplx<Real>::T v[9];
+    for (int e0 = eb + (int)threadIdx.x; e0 < ee; e0 += 4 * 256) {
+      C2 v[4];
+      int cd[4];
 #pragma unroll
-        for (int u = 0; u < 9; ++u) {
-          v[u].x = 0;
-          v[u].y = 0;
-          if (m0 + u < nc) v[u] = cbase[m0 + u][off];
-        }
-#pragma unroll
-        for (int u = 0; u < 9; ++u) {
-          const int q = (int)(ph >> (2 * (m0 + u))) & 3;
-          const Real cr = q == 0 ? (Real)1 : (Real)-0.5;
-          const Real ci = q == 0 ? (Real)0 : (q == 1 ? s3 : -s3);
-          ar = fma(cr, v[u].x, ar);
-          ar = fma(-ci, v[u].y, ar);
-          ai = fma(cr, v[u].y, ai);
-          ai = fma(ci, v[u].x, ai);
-        }
+      for (int u = 0; u < 4; ++u) {
+        const int e = e0 + u * 256;
+        cd[u] = e < ee ? ball[e] : 0;
+        if (e < ee) v[u] = Ik[e];
       }
-      const Real cf = (Real)(levfac * dtab[nn]);
-      Real* dst = I + ((j0 - j0b) * N1 + j1i) * sI + 2 * j2i;
-      dst[0] = ar * cf;
-      dst[1] = ai * cf;
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+        if (e0 + u * 256 < ee) {
+          const int j0 = cd[u] & 255, j1i = (cd[u] >> 8) & 255, j2i = cd[u] >> 16;
+          Real* dst = I + ((j0 - j0b) * N1 + j1i) * sI + 2 * j2i;
+          dst[0] = v[u].x;
+          dst[1] = v[u].y;
+        }
     }
     __syncthreads();
     // stage C': Y[2 j1 + ro][(jj, c)] = sum_q I[(jj,j1)][q] TC2[q][2 c + ro]
@@ -1131,11 +1183,27 @@ void pw_mfma_upload(pdmk_plan* P) {
     }
     beg.push_back((int)ball.size());
     P->nball = (int)ball.size();
+    // per row (j0, j1 + J): {compact index of the row's mode j2 = -J (may lie
+    // outside the row), half width w of the row's ball modes, -1 if none}
+    std::vector<int> brow((size_t)(J + 1) * n * 2, 0);
+    for (size_t r = 0; r < (size_t)(J + 1) * n; ++r) brow[2 * r + 1] = -1;
+    for (int e = 0; e < P->nball; ++e) {
+      const int c = ball[e];
+      const int j0 = c & 255, a = (c >> 8) & 255, b = c >> 16;
+      const size_t r = (size_t)j0 * n + a;
+      if (brow[2 * r + 1] < 0) {
+        brow[2 * r] = e - b;
+        brow[2 * r + 1] = J - b;
+      }
+    }
     ball.insert(ball.end(), beg.begin(), beg.end());
     void* d = nullptr;
     PDMK_HIP(hipMalloc(&d, ball.size() * sizeof(int)));
     PDMK_HIP(hipMemcpy(d, ball.data(), ball.size() * sizeof(int), hipMemcpyHostToDevice));
     P->d_ball = static_cast<int*>(d);
+    PDMK_HIP(hipMalloc(&d, brow.size() * sizeof(int)));
+    PDMK_HIP(hipMemcpy(d, brow.data(), brow.size() * sizeof(int), hipMemcpyHostToDevice));
+    P->d_brow = static_cast<int2*>(d);
   }
   std::vector<double> nodes, bw;
   cheb_nodes(p, nodes, bw);
@@ -1164,8 +1232,10 @@ const double* pw_tables<double>(const pdmk_plan* P) { return P->d_pwt_d; }
 
 template <class Real, int PP, int JJ>
 static void pw_mfma_launch(const pdmk_plan* P, const PwMfmaShape& sh, const Level& L, int nn,
-                           const void* proxy_q, void* S, void* proxy_phi, double levfac,
-                           unsigned long long* npairs, hipEvent_t mid, hipStream_t s) {
+                           const void* proxy_q, void* S, void* Iw, void* proxy_phi,
+                           double levfac, unsigned long long* npairs, hipEvent_t ev_out,
+                           hipEvent_t ev_tr, hipStream_t s) {
+  using C2 = typename Cplx<Real>::T;
   const Real* T = pw_tables<Real>(P);
   const size_t* o = P->pwt_off;
   PDMK_HIP(hipFuncSetAttribute((const void*)&k_pw_out_mfma<Real, PP, JJ>,
@@ -1173,32 +1243,41 @@ static void pw_mfma_launch(const pdmk_plan* P, const PwMfmaShape& sh, const Leve
   PDMK_HIP(hipFuncSetAttribute((const void*)&k_pw_in_mfma<Real, PP, JJ>,
                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh.lds_in));
   hipLaunchKernelGGL((k_pw_out_mfma<Real, PP, JJ>), dim3(nn), dim3(256), sh.lds_out, s,
-                     static_cast<const Real*>(proxy_q), T + o[0], T + o[1], T + o[2],
-                     static_cast<Real*>(S), sh.g_out, sh.sX, sh.sZ);
-  if (mid) PDMK_HIP(hipEventRecord(mid, s));
-  hipLaunchKernelGGL((k_pw_in_mfma<Real, PP, JJ>), dim3(nn), dim3(256), sh.lds_in, s, P->kp,
-                     L, static_cast<const Real*>(S), T + o[3], T + o[4], T + o[5], P->d_dtab,
-                     P->d_ball, P->d_ball + P->nball, levfac, static_cast<Real*>(proxy_phi),
-                     npairs, sh.g_in, sh.sI, sh.sY, sh.sW);
+                     static_cast<const Real*>(proxy_q), T + o[0], T + o[1], T + o[2], P->d_brow,
+                     P->nball, static_cast<Real*>(S), sh.g_out, sh.sX, sh.sZ);
+  if (ev_out) PDMK_HIP(hipEventRecord(ev_out, s));
+  const int nchunk = (P->nball + kTransChunk - 1) / kTransChunk;
+  hipLaunchKernelGGL(k_pw_trans<Real>, dim3(nchunk * nn), dim3(256), 0, s, L,
+                     static_cast<const C2*>(S), P->d_dtab, P->d_ball, P->nball, JJ, levfac,
+                     static_cast<C2*>(Iw), npairs);
+  if (ev_tr) PDMK_HIP(hipEventRecord(ev_tr, s));
+  hipLaunchKernelGGL((k_pw_in_mfma<Real, PP, JJ>), dim3(nn), dim3(256), sh.lds_in, s, L,
+                     static_cast<const C2*>(Iw), T + o[3], T + o[4], T + o[5], P->d_ball,
+                     P->d_ball + P->nball, P->nball, static_cast<Real*>(proxy_phi), sh.g_in,
+                     sh.sI, sh.sY, sh.sW);
 }
 
 template <class Real>
 void pw_mfma_level(const pdmk_plan* P, const Level& L, int nn, const void* proxy_q, void* S,
-                   void* proxy_phi, double levfac, unsigned long long* npairs, hipEvent_t mid,
-                   hipStream_t s) {
+                   void* Iw, void* proxy_phi, double levfac, unsigned long long* npairs,
+                   hipEvent_t ev_out, hipEvent_t ev_tr, hipStream_t s) {
   const KParams& kp = P->kp;
   const PwMfmaShape sh = pw_mfma_shape(kp.p, kp.J, sizeof(Real));
   if (kp.p == 22 && kp.J == 16)
-    pw_mfma_launch<Real, 22, 16>(P, sh, L, nn, proxy_q, S, proxy_phi, levfac, npairs, mid, s);
+    pw_mfma_launch<Real, 22, 16>(P, sh, L, nn, proxy_q, S, Iw, proxy_phi, levfac, npairs,
+                                 ev_out, ev_tr, s);
   else if (kp.p == 13 && kp.J == 9)
-    pw_mfma_launch<Real, 13, 9>(P, sh, L, nn, proxy_q, S, proxy_phi, levfac, npairs, mid, s);
+    pw_mfma_launch<Real, 13, 9>(P, sh, L, nn, proxy_q, S, Iw, proxy_phi, levfac, npairs,
+                                ev_out, ev_tr, s);
   else
     throw Error{PDMK_ERR_UNSUPPORTED, "no matrix-core plane-wave kernel for this (p, J)"};
 }
 
-template void pw_mfma_level<float>(const pdmk_plan*, const Level&, int, const void*, void*, void*,
-                                   double, unsigned long long*, hipEvent_t, hipStream_t);
+template void pw_mfma_level<float>(const pdmk_plan*, const Level&, int, const void*, void*,
+                                   void*, void*, double, unsigned long long*, hipEvent_t,
+                                   hipEvent_t, hipStream_t);
 template void pw_mfma_level<double>(const pdmk_plan*, const Level&, int, const void*, void*,
-                                    void*, double, unsigned long long*, hipEvent_t, hipStream_t);
+                                    void*, void*, double, unsigned long long*, hipEvent_t,
+                                    hipEvent_t, hipStream_t);
 
 }  // namespace pdmk

@@ -67,7 +67,8 @@ class Stats(ctypes.Structure):
                 ("n_support_pairs", ctypes.c_int64), ("series_len", ctypes.c_int),
                 ("t_call_ms", ctypes.c_double), ("workspace_bytes", ctypes.c_int64),
                 ("n_pwout_boxes", ctypes.c_int64), ("n_pwin_boxes", ctypes.c_int64),
-                ("t_pwout_ms", ctypes.c_double), ("t_pwin_ms", ctypes.c_double)]
+                ("t_pwout_ms", ctypes.c_double), ("t_pwin_ms", ctypes.c_double),
+                ("t_pwtr_ms", ctypes.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
