@@ -116,7 +116,7 @@ void plan_upload_tables(pdmk_plan* P) {
 static void free_plan_tables(pdmk_plan* P) {
   void* ptrs[] = {P->d_E, P->d_Ed, P->d_F2, P->d_F2d, P->d_nodes, P->d_bw, P->d_Tm,
                   P->d_F, P->d_Ff, P->d_dtab, P->d_farscale, P->d_shiftvec, P->d_pwt_f,
-                  P->d_pwt_d, P->adj_buf, P->d_ball, P->d_brow};
+                  P->d_pwt_d, P->adj_buf, P->d_ball, P->d_brow, P->d_fftw};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   if (P->arena) {

@@ -8,7 +8,9 @@
 // What_0(k) = psi~(k r_c / c) / k^2 (eq:W0hat), computed once per plan in FP64.
 // The FFT is a hand-written mixed-radix (2, 3, 4, 5) Stockham transform; each
 // workgroup transforms one grid line held in LDS.
+#include <algorithm>
 #include <climits>
+#include <cmath>
 
 #include "internal.h"
 
@@ -36,45 +38,113 @@ __device__ inline double2 cmul(double2 a, double2 b) {
   return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
 }
 
-// y[k] = sum_r v[r] exp(sign 2 pi i r k / R), R <= 5
+// y[k] = sum_r v[r] exp(sign 2 pi i r k / R) for R in {2, 3, 4, 5}, with the
+// roots of unity as constants.
 __device__ inline void small_dft(double2* v, int R, int sign) {
-  double2 y[5];
-  for (int k = 0; k < R; ++k) {
-    double sr = 0, si = 0;
-    for (int r = 0; r < R; ++r) {
-      double c, s;
-      sincospi(2.0 * (double)((r * k) % R) / (double)R, &s, &c);
-      s *= sign;
-      sr += v[r].x * c - v[r].y * s;
-      si += v[r].x * s + v[r].y * c;
+  const double sg = (double)sign;
+  if (R == 2) {
+    const double2 a = v[0], b = v[1];
+    v[0] = make_double2(a.x + b.x, a.y + b.y);
+    v[1] = make_double2(a.x - b.x, a.y - b.y);
+  } else if (R == 4) {
+    const double2 s0 = make_double2(v[0].x + v[2].x, v[0].y + v[2].y);
+    const double2 d0 = make_double2(v[0].x - v[2].x, v[0].y - v[2].y);
+    const double2 s1 = make_double2(v[1].x + v[3].x, v[1].y + v[3].y);
+    const double2 d1 = make_double2(v[1].x - v[3].x, v[1].y - v[3].y);
+    // sign i d1 = (-sign d1.y, sign d1.x)
+    v[0] = make_double2(s0.x + s1.x, s0.y + s1.y);
+    v[2] = make_double2(s0.x - s1.x, s0.y - s1.y);
+    v[1] = make_double2(d0.x - sg * d1.y, d0.y + sg * d1.x);
+    v[3] = make_double2(d0.x + sg * d1.y, d0.y - sg * d1.x);
+  } else if (R == 3) {
+    const double h = 0.8660254037844386;   // sin(2 pi / 3)
+    const double2 a = v[0];
+    const double2 t = make_double2(v[1].x + v[2].x, v[1].y + v[2].y);
+    const double2 u = make_double2(v[1].x - v[2].x, v[1].y - v[2].y);
+    const double2 m = make_double2(a.x - 0.5 * t.x, a.y - 0.5 * t.y);
+    // sign i h u = (-sign h u.y, sign h u.x)
+    v[0] = make_double2(a.x + t.x, a.y + t.y);
+    v[1] = make_double2(m.x - sg * h * u.y, m.y + sg * h * u.x);
+    v[2] = make_double2(m.x + sg * h * u.y, m.y - sg * h * u.x);
+  } else {
+    // cos and sin of 2 pi m / 5
+    const double C[5] = {1.0, 0.30901699437494745, -0.8090169943749475, -0.8090169943749475,
+                         0.30901699437494745};
+    const double S[5] = {0.0, 0.9510565162951535, 0.5877852522924731, -0.5877852522924731,
+                         -0.9510565162951535};
+    double2 y[5];
+#pragma unroll
+    for (int k = 0; k < 5; ++k) {
+      double sr = 0, si = 0;
+#pragma unroll
+      for (int r = 0; r < 5; ++r) {
+        const int m = (r * k) % 5;
+        const double c = C[m], sn = sg * S[m];
+        sr += v[r].x * c - v[r].y * sn;
+        si += v[r].x * sn + v[r].y * c;
+      }
+      y[k] = make_double2(sr, si);
     }
-    y[k] = make_double2(sr, si);
+#pragma unroll
+    for (int k = 0; k < 5; ++k) v[k] = y[k];
   }
-  for (int k = 0; k < R; ++k) v[k] = y[k];
 }
 
-// One workgroup per grid line of length M along one axis.
-__global__ void k_fft_lines(double2* __restrict__ data, int M, int64_t stride, int nl0,
-                            int64_t so0, int64_t so1, int sign, Radices rad) {
+// Stockham FFT of `lpb` grid lines of length M along one axis per workgroup,
+// in LDS.  tw[k] = exp(-2 pi i k / M) (FP64, from the host); sign = +1 uses
+// its conjugate.  Lines along a strided axis are loaded line-fastest (the
+// lines of a workgroup are adjacent in memory), lines along the contiguous
+// axis element-fastest.
+__global__ __launch_bounds__(256) void k_fft_lines(double2* __restrict__ data, int M,
+                                                   int64_t stride, int nl0, int64_t so0,
+                                                   int64_t so1, int nlines, int lpb, int sign,
+                                                   Radices rad,
+                                                   const double2* __restrict__ tw) {
   extern __shared__ double2 sh[];
   double2* b0 = sh;
-  double2* b1 = sh + M;
-  const int line = blockIdx.x;
-  const int64_t base = (int64_t)(line % nl0) * so0 + (int64_t)(line / nl0) * so1;
-  for (int i = threadIdx.x; i < M; i += blockDim.x) b0[i] = data[base + i * stride];
+  double2* b1 = sh + lpb * M;
+  const int l0 = blockIdx.x * lpb;
+  const int nl = min(lpb, nlines - l0);
+  const int tot = nl * M;
+  auto addr = [&](int l, int i) {
+    const int line = l0 + l;
+    return (int64_t)(line % nl0) * so0 + (int64_t)(line / nl0) * so1 + (int64_t)i * stride;
+  };
+  // eight loads in flight per thread
+  for (int e0 = threadIdx.x; e0 < tot; e0 += 8 * 256) {
+    double2 v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int e = e0 + u * 256;
+      if (e < tot) {
+        const int l = stride == 1 ? e / M : e % nl, i = stride == 1 ? e % M : e / nl;
+        v[u] = data[addr(l, i)];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int e = e0 + u * 256;
+      if (e < tot) {
+        const int l = stride == 1 ? e / M : e % nl, i = stride == 1 ? e % M : e / nl;
+        b0[l * M + i] = v[u];
+      }
+    }
+  }
   __syncthreads();
   int Ns = 1;
   for (int pass = 0; pass < rad.n; ++pass) {
     const int R = rad.r[pass];
     const int nb = M / R;
-    for (int j = threadIdx.x; j < nb; j += blockDim.x) {
+    const int step = M / (Ns * R);   // twiddle index stride: exp(2 pi i jm / (Ns R))
+    for (int jj = threadIdx.x; jj < nl * nb; jj += blockDim.x) {
+      const int l = jj / nb, j = jj - l * nb;
+      const double2* in = b0 + l * M;
       double2 v[5];
-      for (int r = 0; r < R; ++r) v[r] = b0[j + r * nb];
+      for (int r = 0; r < R; ++r) v[r] = in[j + r * nb];
       const int jm = j % Ns;
-      if (Ns > 1) {
-        double s, c;
-        sincospi(2.0 * (double)jm / (double)(Ns * R), &s, &c);
-        const double2 w1 = make_double2(c, sign * s);
+      if (Ns > 1 && jm > 0) {
+        double2 w1 = tw[jm * step];
+        if (sign > 0) w1.y = -w1.y;
         double2 w = w1;
         for (int r = 1; r < R; ++r) {
           v[r] = cmul(v[r], w);
@@ -82,8 +152,8 @@ __global__ void k_fft_lines(double2* __restrict__ data, int M, int64_t stride, i
         }
       }
       small_dft(v, R, sign);
-      const int idx = (j / Ns) * Ns * R + jm;
-      for (int r = 0; r < R; ++r) b1[idx + r * Ns] = v[r];
+      double2* out = b1 + l * M + (j / Ns) * Ns * R + jm;
+      for (int r = 0; r < R; ++r) out[r * Ns] = v[r];
     }
     __syncthreads();
     double2* t = b0;
@@ -91,10 +161,14 @@ __global__ void k_fft_lines(double2* __restrict__ data, int M, int64_t stride, i
     b1 = t;
     Ns *= R;
   }
-  for (int i = threadIdx.x; i < M; i += blockDim.x) data[base + i * stride] = b0[i];
+  for (int e0 = threadIdx.x; e0 < tot; e0 += 256) {
+    const int l = stride == 1 ? e0 / M : e0 % nl, i = stride == 1 ? e0 % M : e0 / nl;
+    data[addr(l, i)] = b0[l * M + i];
+  }
 }
 
-static void fft3(double2* g, const int* M, int dim, int sign, hipStream_t s) {
+static void fft3(double2* g, const int* M, int dim, int sign, const double2* tw,
+                 const int64_t* tw_off, hipStream_t s) {
   const int64_t M0 = M[0], M1 = M[1], M2 = dim == 3 ? M[2] : 1;
   for (int ax = 0; ax < dim; ++ax) {
     int Ma = M[ax];
@@ -106,9 +180,14 @@ static void fft3(double2* g, const int* M, int dim, int sign, hipStream_t s) {
     if (ax == 0) { stride = 1; nl0 = (int)M1; so0 = M0; so1 = M0 * M1; nlines = (int)(M1 * M2); }
     else if (ax == 1) { stride = M0; nl0 = (int)M0; so0 = 1; so1 = M0 * M1; nlines = (int)(M0 * M2); }
     else { stride = M0 * M1; nl0 = (int)M0; so0 = 1; so1 = M0; nlines = (int)(M0 * M1); }
-    size_t smem = 2 * (size_t)Ma * sizeof(double2);
-    hipLaunchKernelGGL(k_fft_lines, dim3(nlines), dim3(256), smem, s, g, Ma, stride, nl0, so0,
-                       so1, sign, R);
+    // several short lines per workgroup (at most 2048 points, 64 KB of LDS)
+    const int lpb = std::max(1, std::min(2048 / Ma, 64));
+    const int nblocks = (nlines + lpb - 1) / lpb;
+    size_t smem = 2 * (size_t)lpb * Ma * sizeof(double2);
+    PDMK_HIP(hipFuncSetAttribute((const void*)&k_fft_lines,
+                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem));
+    hipLaunchKernelGGL(k_fft_lines, dim3(nblocks), dim3(256), smem, s, g, Ma, stride, nl0, so0,
+                       so1, nlines, lpb, sign, R, tw + tw_off[ax]);
   }
 }
 
@@ -478,6 +557,19 @@ void far_build_scale(pdmk_plan* P) {
   double* d2 = up(wf[2]);
   double* dgx = up(ps.qx);
   double* dgw = up(gwpsi);
+  {
+    // FFT twiddles exp(-2 pi i k / M_a), k < M_a, one table per axis
+    std::vector<double2> tw;
+    for (int a = 0; a < 3; ++a) {
+      P->fftw_off[a] = (int64_t)tw.size();
+      for (int k = 0; k < M[a]; ++k) {
+        const double t = -2.0 * M_PI * (double)k / (double)M[a];
+        tw.push_back(make_double2(std::cos(t), std::sin(t)));
+      }
+    }
+    PDMK_HIP(hipMalloc(&P->d_fftw, tw.size() * sizeof(double2)));
+    PDMK_HIP(hipMemcpy(P->d_fftw, tw.data(), tw.size() * sizeof(double2), hipMemcpyHostToDevice));
+  }
   PDMK_HIP(hipMalloc(&P->d_farscale, n * sizeof(double)));
   hipLaunchKernelGGL(k_farscale, dim3(nblk(n, 256)), dim3(256), 0, 0, P->kp, M[0], M[1], M[2],
                      g.fgrid_paper[0], g.fgrid_paper[1], d == 3 ? g.fgrid_paper[2] : 1, d0,
@@ -498,9 +590,9 @@ void stage_far(pdmk_plan* P, Eval& E, const double* q, bool want_grad) {
   PDMK_HIP(hipMemsetAsync(grid, 0, n * sizeof(double), E.s));
   spread_interp(P, E, M, w, beta, grid, cg, want_grad, true);
   hipLaunchKernelGGL(k_to_complex, dim3(nblk(n, 256)), dim3(256), 0, E.s, n, grid, cg);
-  fft3(cg, M, d, -1, E.s);
+  fft3(cg, M, d, -1, P->d_fftw, P->fftw_off, E.s);
   hipLaunchKernelGGL(k_scale, dim3(nblk(n, 256)), dim3(256), 0, E.s, n, cg, P->d_farscale);
-  fft3(cg, M, d, +1, E.s);
+  fft3(cg, M, d, +1, P->d_fftw, P->fftw_off, E.s);
   spread_interp(P, E, M, w, beta, grid, cg, want_grad, false);
 }
 

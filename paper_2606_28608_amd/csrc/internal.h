@@ -183,6 +183,8 @@ struct pdmk_plan {
   float2* d_Ff = nullptr;      // FP32 copy
   double* d_dtab = nullptr;    // |j|^2 table
   double* d_farscale = nullptr;// M0*M1*M2
+  double2* d_fftw = nullptr;   // FFT twiddles exp(-2 pi i k / M_a) per axis
+  int64_t fftw_off[3] = {0, 0, 0};
   double* d_shiftvec = nullptr;  // nshift * dim lattice translations L n
   int nshift = 0;
   double nufft_beta = 0;
