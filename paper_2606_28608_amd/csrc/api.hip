@@ -119,6 +119,8 @@ static void free_plan_tables(pdmk_plan* P) {
                   P->d_pwt_d, P->adj_buf, P->d_ball, P->d_brow, P->d_fftw};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
+  if (P->h_cnt) (void)hipHostFree(P->h_cnt);
+  P->h_cnt = nullptr;
   if (P->arena) {
     // every evaluation synchronises its stream before returning, so the
     // arena is no longer in use
@@ -380,6 +382,7 @@ int pdmk_plan_create(const pdmk_opts* opts, const double* L, pdmk_plan** out) {
       if (mp) P->mixed_parts = (unsigned)std::atoi(mp) & 7u;
     }
     far_build_scale(P);
+    PDMK_HIP(hipHostMalloc((void**)&P->h_cnt, 4 * sizeof(unsigned long long)));
   } catch (const Error& e) {
     free_plan_tables(P);
     delete P;
@@ -526,6 +529,7 @@ static int eval_impl(pdmk_plan* P, int64_t n_src, const double* src, const doubl
                        want_grad ? grad : nullptr);
     PDMK_HIP(hipEventRecord(ev[4], s));
     PDMK_HIP(hipEventSynchronize(ev[4]));
+    near_finish(P, E);
     float t1, t2, t3, t4;
     PDMK_HIP(hipEventElapsedTime(&t1, ev[0], ev[1]));
     PDMK_HIP(hipEventElapsedTime(&t2, ev[1], ev[2]));

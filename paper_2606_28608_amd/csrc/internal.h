@@ -4,6 +4,7 @@
 
 #include <cstdint>
 #include <string>
+#include <array>
 #include <vector>
 
 #include "../../include/pdmk.h"
@@ -143,7 +144,18 @@ struct Eval {
   double* far_pot = nullptr;      // far field per original target
   double* far_grad = nullptr;
   pdmk_stats st{};
+  // near-field timing and counters, read once the call's stream has finished
+  // (no host wait inside the pipeline): events e0..e3 around residual sums,
+  // plane waves, leaf evaluation; per level {start, outgoing done, incoming
+  // done, translation done}; device counters copied into the plan's pinned
+  // host buffer
+  bool near_pending = false;
+  bool pw_split = false;
+  hipEvent_t near_ev[4] = {nullptr, nullptr, nullptr, nullptr};
+  std::vector<std::array<hipEvent_t, 4>> pw_ev;
 };
+// Fills the near-field entries of E.st (call after the stream has finished).
+void near_finish(const pdmk_plan* P, Eval& E);
 
 }  // namespace pdmk
 
@@ -169,6 +181,7 @@ struct pdmk_plan {
   // plane waves, 4 far-field window weights (all by default)
   unsigned mixed_parts = 7;
   double* adj_buf = nullptr;    // Psi and grad Psi of the adjoint (n_src (d + 1))
+  unsigned long long* h_cnt = nullptr;   // pinned host: plane-wave pairs, boxes, support pairs
   size_t adj_size = 0;
   pdmk::KParams kp{};
   // device tables

@@ -1059,13 +1059,14 @@ static void near_impl(pdmk_plan* P, Eval& E, bool want_grad) {
   const int pD = D == 3 ? p * p * p : p * p;
   const int n1 = 2 * J + 1;
   const int nlev = (int)E.lev.size();
-  hipEvent_t e0, e1, e2, e3;
-  PDMK_HIP(hipEventCreate(&e0));
-  PDMK_HIP(hipEventCreate(&e1));
-  PDMK_HIP(hipEventCreate(&e2));
-  PDMK_HIP(hipEventCreate(&e3));
-  unsigned long long* nsup = E.alloc<unsigned long long>(1);
-  PDMK_HIP(hipMemsetAsync(nsup, 0, sizeof(unsigned long long), s));
+  for (auto& e : E.near_ev) PDMK_HIP(hipEventCreate(&e));
+  E.near_pending = true;
+  hipEvent_t e0 = E.near_ev[0], e1 = E.near_ev[1], e2 = E.near_ev[2], e3 = E.near_ev[3];
+  // [0] colleague pairs translated, [1] boxes given incoming plane waves,
+  // [2] residual pairs inside the support
+  unsigned long long* cnt = E.alloc<unsigned long long>(3);
+  PDMK_HIP(hipMemsetAsync(cnt, 0, 3 * sizeof(unsigned long long), s));
+  unsigned long long* nsup = cnt + 2;
   PDMK_HIP(hipMemsetAsync(E.pot_sorted, 0, sizeof(double) * E.n_trg, s));
   if (want_grad)
     PDMK_HIP(hipMemsetAsync(E.grad_sorted, 0, sizeof(double) * E.n_trg * D, s));
@@ -1109,10 +1110,8 @@ static void near_impl(pdmk_plan* P, Eval& E, bool want_grad) {
     double2* bA = fused ? nullptr : E.alloc<double2>((size_t)maxnl * s1);
     double2* bB = (D == 3 && !fused) ? E.alloc<double2>((size_t)maxnl * s2) : nullptr;
     double2* bI = fused ? nullptr : E.alloc<double2>((size_t)maxnl * s3);
-    // [0] colleague pairs translated, [1] boxes given incoming plane waves
-    unsigned long long* npairs = E.alloc<unsigned long long>(2);
-    PDMK_HIP(hipMemsetAsync(npairs, 0, 2 * sizeof(unsigned long long), s));
-    std::vector<std::array<hipEvent_t, 4>> pw_events;
+    unsigned long long* npairs = cnt;
+    E.pw_split = mfma;
     const C* Ftab = reinterpret_cast<const C*>(sizeof(Real) == 4 ? (const void*)P->d_Ff
                                                                  : (const void*)P->d_F);
     if (fused) {
@@ -1131,7 +1130,7 @@ static void near_impl(pdmk_plan* P, Eval& E, bool want_grad) {
       // pe[0] | outgoing | pe[1] | translation (matrix-core path) | pe[3] | incoming | pe[2]
       hipEvent_t pe[4];
       for (auto& e : pe) PDMK_HIP(hipEventCreate(&e));
-      pw_events.push_back({pe[0], pe[1], pe[2], pe[3]});
+      E.pw_ev.push_back({pe[0], pe[1], pe[2], pe[3]});
       E.st.n_pwout_boxes += nn;
       PDMK_HIP(hipEventRecord(pe[0], s));
       if (mfma) {
@@ -1191,31 +1190,6 @@ static void near_impl(pdmk_plan* P, Eval& E, bool want_grad) {
     }
     PDMK_HIP(hipMemcpyAsync(E.d_lev, E.lev.data(), sizeof(Level) * E.lev.size(),
                             hipMemcpyHostToDevice, s));
-    unsigned long long np[2] = {0, 0};
-    PDMK_HIP(hipMemcpyAsync(np, npairs, sizeof(np), hipMemcpyDeviceToHost, s));
-    PDMK_HIP(hipStreamSynchronize(s));
-    E.st.n_pw_pairs = (int64_t)np[0];
-    E.st.n_pwin_boxes = (int64_t)np[1];
-    for (auto& pe : pw_events) {
-      float a = 0, b = 0, c = 0;
-      PDMK_HIP(hipEventElapsedTime(&a, pe[0], pe[1]));
-      if (mfma) {
-        PDMK_HIP(hipEventElapsedTime(&c, pe[1], pe[3]));
-        PDMK_HIP(hipEventElapsedTime(&b, pe[3], pe[2]));
-      } else {
-        PDMK_HIP(hipEventElapsedTime(&b, pe[1], pe[2]));
-      }
-      E.st.t_pwout_ms += a;
-      E.st.t_pwtr_ms += c;
-      E.st.t_pwin_ms += b;
-      for (auto& e : pe) (void)hipEventDestroy(e);
-    }
-  }
-  {
-    unsigned long long ns = 0;
-    PDMK_HIP(hipMemcpyAsync(&ns, nsup, sizeof(ns), hipMemcpyDeviceToHost, s));
-    PDMK_HIP(hipStreamSynchronize(s));
-    E.st.n_support_pairs = (int64_t)ns;
   }
   PDMK_HIP(hipEventRecord(e2, s));
   // leaf targets evaluate their parent's proxy potential
@@ -1227,18 +1201,39 @@ static void near_impl(pdmk_plan* P, Eval& E, bool want_grad) {
                                              s)))
           launch_eval_children<D, Real>(kp, E.lev[l], E.lev[l + 1], l, E, P, s, want_grad);
   PDMK_HIP(hipEventRecord(e3, s));
-  PDMK_HIP(hipEventSynchronize(e3));
+  PDMK_HIP(hipMemcpyAsync(P->h_cnt, cnt, 3 * sizeof(unsigned long long), hipMemcpyDeviceToHost,
+                          s));
+}
+
+void near_finish(const pdmk_plan* P, Eval& E) {
+  if (!E.near_pending) return;
+  E.near_pending = false;
+  E.st.n_pw_pairs = (int64_t)P->h_cnt[0];
+  E.st.n_pwin_boxes = (int64_t)P->h_cnt[1];
+  E.st.n_support_pairs = (int64_t)P->h_cnt[2];
+  for (auto& pe : E.pw_ev) {
+    float a = 0, b = 0, c = 0;
+    PDMK_HIP(hipEventElapsedTime(&a, pe[0], pe[1]));
+    if (E.pw_split) {
+      PDMK_HIP(hipEventElapsedTime(&c, pe[1], pe[3]));
+      PDMK_HIP(hipEventElapsedTime(&b, pe[3], pe[2]));
+    } else {
+      PDMK_HIP(hipEventElapsedTime(&b, pe[1], pe[2]));
+    }
+    E.st.t_pwout_ms += a;
+    E.st.t_pwtr_ms += c;
+    E.st.t_pwin_ms += b;
+    for (auto& e : pe) (void)hipEventDestroy(e);
+  }
+  E.pw_ev.clear();
   float t01, t12, t23;
-  PDMK_HIP(hipEventElapsedTime(&t01, e0, e1));
-  PDMK_HIP(hipEventElapsedTime(&t12, e1, e2));
-  PDMK_HIP(hipEventElapsedTime(&t23, e2, e3));
+  PDMK_HIP(hipEventElapsedTime(&t01, E.near_ev[0], E.near_ev[1]));
+  PDMK_HIP(hipEventElapsedTime(&t12, E.near_ev[1], E.near_ev[2]));
+  PDMK_HIP(hipEventElapsedTime(&t23, E.near_ev[2], E.near_ev[3]));
   E.st.t_direct_ms = t01;
   E.st.t_pw_ms = t12;
   E.st.t_proxy_ms = t23;
-  (void)hipEventDestroy(e0);
-  (void)hipEventDestroy(e1);
-  (void)hipEventDestroy(e2);
-  (void)hipEventDestroy(e3);
+  for (auto& e : E.near_ev) (void)hipEventDestroy(e);
 }
 
 void stage_near(pdmk_plan* P, Eval& E, bool want_grad) {

@@ -401,32 +401,33 @@ __global__ void k_make_children(KParams kp, Level P, Level C, int lvl,
   C.nlid[c] = -1;
 }
 
+// Colleagues of the boxes of a child level, one thread per (box, slot): the
+// neighbour at offset dl lies in the child octant ((g + dl) & 1) of the
+// parent's colleague at offset ((g + dl) >> 1) - (g >> 1) (children are made
+// in octant order, coordinates are 2 * parent + bit).
 __global__ void k_colleagues(Level P, Level C, int d) {
-  int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= C.n) return;
-  int ncoll = d == 3 ? 27 : 9;
-  int g[3] = {0, 0, 0};
-  for (int a = 0; a < d; ++a) g[a] = C.coord[c * d + a];
-  int out[27];
-  for (int sl = 0; sl < ncoll; ++sl) out[sl] = -1;
-  int b = C.parent[c];
-  for (int sl = 0; sl < ncoll; ++sl) {
-    int pb = P.coll[b * ncoll + sl];
-    if (pb < 0) continue;
-    int c0 = P.child0[pb];
-    if (c0 < 0) continue;
-    for (int o = 0; o < (1 << d); ++o) {
-      int cc = c0 + o;
-      int dl[3] = {0, 0, 0};
-      bool ok = true;
-      for (int a = 0; a < d; ++a) {
-        dl[a] = C.coord[cc * d + a] - g[a];
-        ok = ok && dl[a] >= -1 && dl[a] <= 1;
-      }
-      if (ok) out[coll_slot(dl, d)] = cc;
-    }
+  const int ncoll = d == 3 ? 27 : 9;
+  const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (gid >= (int64_t)C.n * ncoll) return;
+  const int c = (int)(gid / ncoll), sl = (int)(gid - (int64_t)c * ncoll);
+  const int b = C.parent[c];
+  int ps = 0, m = 1, oct = 0, t = sl;
+  for (int a = 0; a < d; ++a) {
+    const int dl = t % 3 - 1;
+    t /= 3;
+    const int g = C.coord[c * d + a];
+    const int n = g + dl;
+    ps += ((n >> 1) - (g >> 1) + 1) * m;
+    m *= 3;
+    oct |= (n & 1) << a;
   }
-  for (int sl = 0; sl < ncoll; ++sl) C.coll[c * ncoll + sl] = out[sl];
+  int cc = -1;
+  const int pb = P.coll[b * ncoll + ps];
+  if (pb >= 0) {
+    const int c0 = P.child0[pb];
+    if (c0 >= 0) cc = c0 + oct;
+  }
+  C.coll[c * ncoll + sl] = cc;
 }
 
 static void alloc_level(Eval& E, Level& L, int n, int d) {
@@ -473,7 +474,8 @@ void stage_tree(pdmk_plan* P, Eval& E) {
     Level Pcopy = E.lev[l];
     hipLaunchKernelGGL(k_make_children, dim3(nblk(C.n, 128)), dim3(128), 0, E.s, kp, Pcopy, C, l,
                        E.skey, E.tkey);
-    hipLaunchKernelGGL(k_colleagues, dim3(nblk(C.n, 128)), dim3(128), 0, E.s, Pcopy, C, d);
+    hipLaunchKernelGGL(k_colleagues, dim3(nblk((int64_t)C.n * (d == 3 ? 27 : 9), 256)),
+                       dim3(256), 0, E.s, Pcopy, C, d);
     E.lev.push_back(C);
   }
   E.d_lev = E.alloc<Level>(E.lev.size());
