@@ -41,12 +41,11 @@ def flop_per_pair(series_len: int):
     """Arithmetic of the residual kernel, counted from its operations.
 
     Every visited pair: 3 subtractions, 1 multiply and 2 FMAs for r^2 (8 flop).
-    A pair inside the support r < h adds s = r^2/h^2 (2), the Chebyshev
-    argument (2), a Clenshaw step per coefficient (FMA + subtraction, 3 each),
-    the final Clenshaw step (4), rsqrt (1), E/h (1), 1/r - E/h (1) and the
-    charge FMA (2): 3 * series_len + 10 flop.
+    A pair inside the support r < h adds the series argument u = r^2 (2/h^2) - 1
+    (one FMA, 2), Horner's rule over the series (series_len - 1 FMAs), rsqrt
+    (1), 1/r - E/h as one FMA (2) and the charge FMA (2): 2 * series_len + 5.
     """
-    return 8.0, 3.0 * series_len + 10.0
+    return 8.0, 2.0 * series_len + 5.0
 
 
 def parse():

@@ -212,7 +212,7 @@ typedef struct {
   double t_build_ms, t_near_ms, t_far_ms, t_total_ms;
   double t_direct_ms, t_pw_ms, t_proxy_ms;
   int64_t n_support_pairs;          /* visited pairs inside the residual support (r < h) */
-  int series_len;                   /* terms of the residual's Chebyshev series */
+  int series_len;                   /* terms of the residual series the residual sums used */
   double t_call_ms;                 /* host wall time of the whole call */
   int64_t workspace_bytes;          /* device workspace the call used */
   int64_t n_pwout_boxes;            /* boxes given outgoing plane waves (all levels) */

@@ -62,16 +62,50 @@ void plan_upload_tables(pdmk_plan* P) {
   const int d = P->g.dim;
   const int p = P->mp.porder, J = P->mp.npw;
   ChebSeries Ed = cheb_derivative(P->T->E), F2d = cheb_derivative(P->T->F2);
-  // device copies zero-padded to 32 terms (kernels unroll to a fixed length)
-  auto pad = [](std::vector<double> v) {
-    if (v.size() > 32) throw Error{PDMK_ERR_UNSUPPORTED, "kernel series longer than 32 terms"};
-    v.resize(32, 0.0);
-    return v;
+  // The kernels evaluate each series sum_k c_k T_k(u) by Horner's rule in the
+  // monomial basis of u = 2 s - 1 (half the operations of Clenshaw's
+  // recurrence).  For these series sum_j |a_j| stays within a factor 5 of
+  // max |E| on [-1, 1] (a factor 1.0-1.2 except for the 2D derivative at
+  // eps = 1e-3), so the monomial form costs no accuracy.  FP32 evaluation
+  // uses the series cut where |c_k| drops below 1e-8 max |c| (below FP32
+  // resolution).  Zero-padded to 32 + 32 entries.
+  auto mono = [](std::vector<double> c, bool fp32) {
+    if (fp32) {
+      double mx = 0;
+      for (double v : c) mx = std::max(mx, std::fabs(v));
+      while (c.size() > 1 && std::fabs(c.back()) < 1e-8 * mx) c.pop_back();
+    }
+    const size_t n = c.size();
+    std::vector<double> a(n, 0.0), tm(n, 0.0), tk(n, 0.0), tp(n, 0.0);
+    if (n > 0) tm[0] = 1.0;            // T_0
+    if (n > 1) tk[1] = 1.0;            // T_1
+    for (size_t k = 0; k < n; ++k) {
+      const std::vector<double>& T = k == 0 ? tm : tk;
+      for (size_t j = 0; j < n; ++j) a[j] += c[k] * T[j];
+      if (k >= 1) {
+        // T_{k+1} = 2 u T_k - T_{k-1}
+        for (size_t j = 0; j < n; ++j) tp[j] = (j ? 2.0 * tk[j - 1] : 0.0) - tm[j];
+        tm = tk;
+        tk = tp;
+      }
+    }
+    return a;
   };
-  P->d_E = upload(pad(P->T->E.a));
-  P->d_Ed = upload(pad(Ed.a));
-  P->d_F2 = upload(pad(P->T->F2.a));
-  P->d_F2d = upload(pad(F2d.a));
+  auto both = [&](const std::vector<double>& c, int& n64, int& n32) {
+    std::vector<double> a = mono(c, false), b = mono(c, true);
+    if (a.size() > 32) throw Error{PDMK_ERR_UNSUPPORTED, "kernel series longer than 32 terms"};
+    n64 = (int)a.size();
+    n32 = (int)b.size();
+    a.resize(32, 0.0);
+    b.resize(32, 0.0);
+    a.insert(a.end(), b.begin(), b.end());
+    return a;
+  };
+  KParams& kq = P->kp;
+  P->d_E = upload(both(P->T->E.a, kq.nE, kq.nE32));
+  P->d_Ed = upload(both(Ed.a, kq.nEd, kq.nEd32));
+  P->d_F2 = upload(both(P->T->F2.a, kq.nF2, kq.nF232));
+  P->d_F2d = upload(both(F2d.a, kq.nF2d, kq.nF2d32));
   std::vector<double> nodes, bw;
   cheb_nodes(p, nodes, bw);
   P->d_nodes = upload(nodes);
@@ -105,11 +139,6 @@ void plan_upload_tables(pdmk_plan* P) {
     }
   P->nshift = (int)(P->g.shifts.size() / d);
   P->d_shiftvec = upload(sv);
-  KParams& kp = P->kp;
-  kp.nE = (int)P->T->E.a.size();
-  kp.nEd = (int)Ed.a.size();
-  kp.nF2 = (int)P->T->F2.a.size();
-  kp.nF2d = (int)F2d.a.size();
 }
 }  // namespace pdmk
 
@@ -539,7 +568,11 @@ static int eval_impl(pdmk_plan* P, int64_t n_src, const double* src, const doubl
     E.st.n_src = n_src;
     E.st.n_trg = n_trg;
     E.st.n_images = E.n_img;
-    E.st.series_len = d == 3 ? P->kp.nE : P->kp.nF2;
+    {
+      // length of the series the residual kernel evaluated
+      const bool f32 = P->kp.precision == PDMK_PREC_MIXED && (P->mixed_parts & 1);
+      E.st.series_len = d == 3 ? (f32 ? P->kp.nE32 : P->kp.nE) : (f32 ? P->kp.nF232 : P->kp.nF2);
+    }
     E.st.t_build_ms = t1;
     E.st.t_near_ms = t2;
     E.st.t_far_ms = t3;

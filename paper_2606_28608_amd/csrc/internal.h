@@ -71,8 +71,10 @@ struct KParams {
   int dim;
   int p;            // proxy points per axis
   int J;            // plane-wave half count
-  int nE, nF2;      // Chebyshev series lengths
+  int nE, nF2;      // series lengths (FP64 evaluation)
   int nEd, nF2d;
+  int nE32, nF232;  // series lengths for FP32 evaluation (cut at FP32 resolution)
+  int nEd32, nF2d32;
   int B;            // Morton bits per axis
   int next[3];      // extended root grid dims
   double rc;
@@ -185,9 +187,11 @@ struct pdmk_plan {
   size_t adj_size = 0;
   pdmk::KParams kp{};
   // device tables
+  // residual series as monomials in u = 2 s - 1 (s = r^2 / h^2): entries
+  // [0, 32) for FP64 evaluation, [32, 64) cut for FP32 evaluation
   double* d_E = nullptr;
-  double* d_Ed = nullptr;       // dE/ds series
-  double* d_F2d = nullptr;      // dF2/ds series
+  double* d_Ed = nullptr;       // dE/ds
+  double* d_F2d = nullptr;      // dF2/ds
   double* d_F2 = nullptr;
   double* d_nodes = nullptr;   // p
   double* d_bw = nullptr;      // p

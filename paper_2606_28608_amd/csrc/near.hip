@@ -21,16 +21,6 @@ static inline int nblk(int64_t n, int b) { return (int)((n + b - 1) / b); }
 constexpr double kInv4Pi = 0.07957747154594767;
 constexpr double kInv2Pi = 0.15915494309189535;
 
-__device__ inline double clenshaw(const double* __restrict__ a, int n, double s) {
-  double t = 2.0 * s - 1.0, b1 = 0.0, b2 = 0.0;
-  for (int k = n - 1; k >= 1; --k) {
-    double b0 = fma(2.0 * t, b1, a[k] - b2);
-    b2 = b1;
-    b1 = b0;
-  }
-  return fma(t, b1, a[0] - b2);
-}
-
 // ------------------------------------------------------------- residual sums
 // One 64-lane block per target leaf.  The block walks the concatenated source
 // ranges of the leaf's list in tiles of 64 staged in LDS (each slot carries
@@ -50,19 +40,23 @@ __device__ inline float rsqrt_r(float x) { return __builtin_amdgcn_rsqf(x); }
 __device__ inline double log_r(double x) { return log(x); }
 __device__ inline float log_r(float x) { return __logf(x); }
 
-// Real = double: FP64 throughout.  Real = float: FP32 pair arithmetic on
-// offsets from the target leaf's centre (each formed in FP64, then rounded),
-// FP32 sums over one tile of 64 sources, FP64 across tiles.
+// Real = double: FP64 throughout.  Real = float: the series, rsqrt and the
+// sums over one tile of 64 sources in FP32, FP64 across tiles.
 // q_s R(|x - y_s|) (and its gradient) for one pair, with R_h of eq:pswf_split:
 // 3D 1/r - E(r^2/h^2)/h, 2D -log(r/h) + F2(r^2/h^2) (both without the 1/(4 pi),
 // 1/(2 pi) factors), zero outside the support r < h and for the pair r = 0.
 // Offsets and r^2 are formed in FP64 (an FP32 offset would lose u * h / r of r
-// for the close pairs of a coarse leaf); the series, rsqrt and the charge sum
-// run in Real.
+// for the close pairs of a coarse leaf).  The series are monomials in
+// u = 2 s - 1 = r^2 (2 / h^2) - 1, evaluated by Horner's rule.  A source slot
+// carries (q, 1/h, 2/h^2) in Real.
+template <class Real> struct SlotQ;
+template <> struct SlotQ<float> { using T = float4; };
+template <> struct SlotQ<double> { using T = double4; };
+
 template <int D, int NE, bool GRAD, class Real>
-__device__ inline void residual_pair(const double* x, const double4& sv, double h2d, Real ih,
-                                     const Real* ec, const Real* edc, Real& acc, Real* g,
-                                     int& nin) {
+__device__ inline void residual_pair(const double* x, const double4& sv, double h2d,
+                                     const typename SlotQ<Real>::T& sq, const Real* ec,
+                                     const Real* edc, Real& acc, Real* g, int& nin) {
   double dd[3];
   dd[0] = x[0] - sv.x;
   dd[1] = x[1] - sv.y;
@@ -74,37 +68,31 @@ __device__ inline void residual_pair(const double* x, const double4& sv, double 
   nin += in ? 1 : 0;
   if (in) {
     const Real r2 = (Real)r2d;
-    Real dx[3] = {(Real)dd[0], (Real)dd[1], (Real)dd[2]};
-    const Real s = r2 * ih * ih;
-    const Real qs = (Real)sv.w;
-    // Clenshaw recurrence for sum_k c_k T_k(2s - 1)
-    const Real t2 = (Real)4 * s - (Real)2;
-    Real b1 = 0, b2 = 0, d1 = 0, d2 = 0;
+    const Real qs = sq.x, ih = sq.y, ihh = sq.z;
+    const Real u = fma(r2, ihh, (Real)-1);
+    Real F = ec[NE - 1];
 #pragma unroll
-    for (int m = NE - 1; m >= 1; --m) {
-      const Real b0 = fma(t2, b1, ec[m] - b2);
-      b2 = b1;
-      b1 = b0;
-      if (GRAD) {
-        const Real e0 = fma(t2, d1, edc[m] - d2);
-        d2 = d1;
-        d1 = e0;
-      }
+    for (int m = NE - 2; m >= 0; --m) F = fma(F, u, ec[m]);
+    Real Fd = 0;
+    if (GRAD) {
+      Fd = edc[NE - 1];
+#pragma unroll
+      for (int m = NE - 2; m >= 0; --m) Fd = fma(Fd, u, edc[m]);
     }
-    const Real F = fma((Real)0.5 * t2, b1, ec[0] - b2);
     if (D == 3) {
       const Real ir = rsqrt_r(r2);
-      acc = fma(qs, ir - F * ih, acc);
+      acc = fma(qs, fma(-F, ih, ir), acc);
       if (GRAD) {
-        const Real Fd = fma((Real)0.5 * t2, d1, edc[0] - d2);
-        const Real f = qs * (-ir * ir * ir - (Real)2 * Fd * ih * ih * ih);
+        const Real dx[3] = {(Real)dd[0], (Real)dd[1], (Real)dd[2]};
+        const Real f = qs * (-ir * ir * ir - ihh * Fd * ih);
         for (int a = 0; a < D; ++a) g[a] = fma(f, dx[a], g[a]);
       }
     } else {
-      acc = fma(qs, (Real)-0.5 * log_r(s) + F, acc);
+      const Real sgr = (Real)0.5 * r2 * ihh;   // s = r^2 / h^2
+      acc = fma(qs, (Real)-0.5 * log_r(sgr) + F, acc);
       if (GRAD) {
-        const Real Fd = fma((Real)0.5 * t2, d1, edc[0] - d2);
-        const Real f = qs * (-(Real)1 / r2 + (Real)2 * Fd * ih * ih);
+        const Real dx[3] = {(Real)dd[0], (Real)dd[1], (Real)0};
+        const Real f = qs * (-(Real)1 / r2 + ihh * Fd);
         for (int a = 0; a < D; ++a) g[a] = fma(f, dx[a], g[a]);
       }
     }
@@ -144,10 +132,10 @@ template <class Real>
 struct SourceSlot {
   double4 v;
   double h2;
-  Real ih;
-  // Source offset from the target leaf centre (formed in FP64), charge and
-  // the support of its residual level; slots past the list end never
-  // interact (h^2 = 0).
+  typename SlotQ<Real>::T w;   // (q, 1/h, 2/h^2, 0)
+  // Source offset from the target leaf centre (formed in FP64), the support
+  // h^2 of its residual level, and (q, 1/h, 2/h^2); slots past the list end
+  // never interact (h^2 = 0).
   __device__ void fetch(const ListCursor& c, const KParams& kp, const double* __restrict__ sx,
                         const double* __restrict__ sq, int64_t nimg, const double* cT, int D) {
     if (c.valid()) {
@@ -155,15 +143,22 @@ struct SourceSlot {
       v.x = sx[sidx] - cT[0];
       v.y = sx[nimg + sidx] - cT[1];
       v.z = D == 3 ? sx[2 * nimg + sidx] - cT[2] : 0.0;
-      v.w = sq[sidx];
+      v.w = 0.0;
       const double hh = kp.rc / (double)(1 << c.en.z);
+      const double ih = 1.0 / hh;
       h2 = hh * hh;
-      ih = (Real)(1.0 / hh);
+      w.x = (Real)sq[sidx];
+      w.y = (Real)ih;
+      w.z = (Real)(2.0 * ih * ih);
+      w.w = 0;
     } else {
       v.x = v.y = v.z = 1e30;
       v.w = 0;
       h2 = 0;
-      ih = 1;
+      w.x = 0;
+      w.y = 1;
+      w.z = 2;
+      w.w = 0;
     }
   }
 };
@@ -177,8 +172,8 @@ __device__ void direct_pass(const KParams& kp, const int4* __restrict__ list, in
                             int pos0, int pos1, const double* __restrict__ sx,
                             const double* __restrict__ sq,
                             int64_t nimg, const double* cT, const double* x, const Real* ec,
-                            const Real* edc, double4* shv, double* shh2, Real* shih,
-                            double& acc, double* g, int& nin) {
+                            const Real* edc, double4* shv, double* shh2,
+                            typename SlotQ<Real>::T* shw, double& acc, double* g, int& nin) {
   const int lane = threadIdx.x;
   const int slice = lane % S;
   ListCursor cur;
@@ -190,15 +185,15 @@ __device__ void direct_pass(const KParams& kp, const int4* __restrict__ list, in
     __syncthreads();
     shv[lane] = nxt.v;
     shh2[lane] = nxt.h2;
-    shih[lane] = nxt.ih;
+    shw[lane] = nxt.w;
     __syncthreads();
     cur.advance(list);
     nxt.fetch(cur, kp, sx, sq, nimg, cT, D);
     Real ta = 0, tb = 0, ga[3] = {0, 0, 0}, gb[3] = {0, 0, 0};
 #pragma unroll 2
     for (int k = slice; k < 64; k += 2 * S) {
-      residual_pair<D, NE, GRAD, Real>(x, shv[k], shh2[k], shih[k], ec, edc, ta, ga, nin);
-      residual_pair<D, NE, GRAD, Real>(x, shv[k + S], shh2[k + S], shih[k + S], ec, edc, tb,
+      residual_pair<D, NE, GRAD, Real>(x, shv[k], shh2[k], shw[k], ec, edc, ta, ga, nin);
+      residual_pair<D, NE, GRAD, Real>(x, shv[k + S], shh2[k + S], shw[k + S], ec, edc, tb,
                                        gb, nin);
     }
     acc += (double)ta + (double)tb;
@@ -233,7 +228,7 @@ __global__ __launch_bounds__(64) void k_direct(
     unsigned long long* __restrict__ n_support) {
   __shared__ double4 shv[64];
   __shared__ double shh2[64];
-  __shared__ Real shih[64];
+  __shared__ typename SlotQ<Real>::T shw[64];
   if ((int)blockIdx.x >= nitems) return;
   const int2 item = items[blockIdx.x];
   const int i = item.x;
@@ -242,7 +237,7 @@ __global__ __launch_bounds__(64) void k_direct(
   const int seg = item.y % nseg, tchunk = item.y / nseg;
   const int pos0 = seg * kDirectSeg;
   const int pos1 = min(nsrc, pos0 + kDirectSeg);
-  // series coefficients (zero-padded to NE)
+  // series coefficients (monomials in u, zero-padded to NE)
   Real ec[NE], edc[NE];
 #pragma unroll
   for (int k = 0; k < NE; ++k) {
@@ -274,22 +269,22 @@ __global__ __launch_bounds__(64) void k_direct(
       case 1:
         direct_pass<D, NE, 1, GRAD, Real>(kp, list, lb, le, pos0, pos1, sx, sq, nimg, cT, x,
                                           ec, edc, shv,
-                                          shh2, shih, acc, g, nin_p);
+                                          shh2, shw, acc, g, nin_p);
         break;
       case 2:
         direct_pass<D, NE, 2, GRAD, Real>(kp, list, lb, le, pos0, pos1, sx, sq, nimg, cT, x,
                                           ec, edc, shv,
-                                          shh2, shih, acc, g, nin_p);
+                                          shh2, shw, acc, g, nin_p);
         break;
       case 4:
         direct_pass<D, NE, 4, GRAD, Real>(kp, list, lb, le, pos0, pos1, sx, sq, nimg, cT, x,
                                           ec, edc, shv,
-                                          shh2, shih, acc, g, nin_p);
+                                          shh2, shw, acc, g, nin_p);
         break;
       default:
         direct_pass<D, NE, 8, GRAD, Real>(kp, list, lb, le, pos0, pos1, sx, sq, nimg, cT, x,
                                           ec, edc, shv,
-                                          shh2, shih, acc, g, nin_p);
+                                          shh2, shw, acc, g, nin_p);
         break;
     }
     if (valid) nin += nin_p;
@@ -915,8 +910,9 @@ __global__ __launch_bounds__(NT) void k_eval_children(
 template <int D, int NE, class Real>
 static void launch_direct_t(const KParams& kp, Eval& E, pdmk_plan* P, hipStream_t s,
                             bool want_grad, unsigned long long* nsup) {
-  const double* c = D == 3 ? P->d_E : P->d_F2;
-  const double* cd = D == 3 ? P->d_Ed : P->d_F2d;
+  const int off = sizeof(Real) == 4 ? 32 : 0;   // FP32 evaluation: the cut series
+  const double* c = (D == 3 ? P->d_E : P->d_F2) + off;
+  const double* cd = (D == 3 ? P->d_Ed : P->d_F2d) + off;
   if (want_grad)
     hipLaunchKernelGGL((k_direct<D, NE, true, Real>), dim3(E.nitems), dim3(64), 0, s, kp,
                        E.nitems, E.items, E.lf_nsrc, E.d_lev, E.lf_level, E.lf_box, E.lf_list_beg, E.list, E.sx,
@@ -933,9 +929,15 @@ static void launch_direct_t(const KParams& kp, Eval& E, pdmk_plan* P, hipStream_
 template <int D, class Real>
 static void launch_direct_r(const KParams& kp, Eval& E, pdmk_plan* P, hipStream_t s,
                             bool want_grad, unsigned long long* nsup) {
-  const int nc = want_grad ? std::max(D == 3 ? kp.nE : kp.nF2, D == 3 ? kp.nEd : kp.nF2d)
-                           : (D == 3 ? kp.nE : kp.nF2);
-  if (nc <= 12) launch_direct_t<D, 12, Real>(kp, E, P, s, want_grad, nsup);
+  const bool f32 = sizeof(Real) == 4;
+  const int nv = D == 3 ? (f32 ? kp.nE32 : kp.nE) : (f32 ? kp.nF232 : kp.nF2);
+  const int nd = D == 3 ? (f32 ? kp.nEd32 : kp.nEd) : (f32 ? kp.nF2d32 : kp.nF2d);
+  const int nc = want_grad ? std::max(nv, nd) : nv;
+  // Horner pays one FMA per padding term: lengths close to the series'
+  if (nc <= 8) launch_direct_t<D, 8, Real>(kp, E, P, s, want_grad, nsup);
+  else if (nc <= 10) launch_direct_t<D, 10, Real>(kp, E, P, s, want_grad, nsup);
+  else if (nc <= 12) launch_direct_t<D, 12, Real>(kp, E, P, s, want_grad, nsup);
+  else if (nc <= 14) launch_direct_t<D, 14, Real>(kp, E, P, s, want_grad, nsup);
   else if (nc <= 16) launch_direct_t<D, 16, Real>(kp, E, P, s, want_grad, nsup);
   else if (nc <= 20) launch_direct_t<D, 20, Real>(kp, E, P, s, want_grad, nsup);
   else if (nc <= 24) launch_direct_t<D, 24, Real>(kp, E, P, s, want_grad, nsup);
