@@ -553,10 +553,10 @@ __global__ __launch_bounds__(256) void k_eval_leaf_mfma(
   using MF = Mfma<Real>;
   using V = typename MF::V;
   constexpr int PP = P * P, KA = (P + 3) & ~3, SP = KA | 1, SL = P | 1;
-  constexpr int MT = (PP + 15) / 16;
+  constexpr int MT = ((PP + 15) / 16 + 1) & ~1;   // row tiles, even (two per step)
   constexpr int NR = GRAD ? 2 : 1;
   extern __shared__ __align__(16) unsigned char smraw[];
-  Real* PhiA = reinterpret_cast<Real*>(smraw);        // 16 MT rows (i0,i1) x SP (i2)
+  Real* PhiA = reinterpret_cast<Real*>(smraw);        // 16 MT rows (i0,i1) x SP (i2), zero past PP
   Real* wrow = PhiA + 16 * MT * SP;                     // per wave: rows of 16 targets
   __shared__ int cb[8], cpre[9];
   const int k = blockIdx.x;
@@ -643,30 +643,37 @@ __global__ __launch_bounds__(256) void k_eval_leaf_mfma(
       bd[s] = GRAD ? dLz[(4 * s + lk) * 16 + li] : (Real)0;
     }
     Real acc = 0, g0 = 0, g1 = 0, g2 = 0;
-    for (int mt = 0; mt < MT; ++mt) {
+    // two row tiles per step: independent accumulator chains overlap on the
+    // matrix pipe; rows past PP are zero in PhiA, so their (clamped) weights
+    // never contribute and no lane branches
+    for (int mt = 0; mt < MT; mt += 2) {
       const Real* ar = PhiA + (16 * mt + li) * SP + lk;
-      V c = {0, 0, 0, 0}, cd = {0, 0, 0, 0};
+      V c[2] = {{0, 0, 0, 0}, {0, 0, 0, 0}}, cd[2] = {{0, 0, 0, 0}, {0, 0, 0, 0}};
 #pragma unroll
       for (int s = 0; s < KA / 4; ++s) {
-        const Real av = ar[4 * s];
-        c = MF::op(av, bz[s], c);
-        if (GRAD) cd = MF::op(av, bd[s], cd);
+        const Real a0 = ar[4 * s], a1 = ar[16 * SP + 4 * s];
+        c[0] = MF::op(a0, bz[s], c[0]);
+        c[1] = MF::op(a1, bz[s], c[1]);
+        if (GRAD) {
+          cd[0] = MF::op(a0, bd[s], cd[0]);
+          cd[1] = MF::op(a1, bd[s], cd[1]);
+        }
       }
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int m = 16 * mt + MF::row(lane, r);
-        if (m < PP) {
+      for (int h = 0; h < 2; ++h)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int m = min(16 * (mt + h) + MF::row(lane, r), PP - 1);
           const int i0 = m / P, i1 = m - i0 * P;
           const Real x0 = Lx[li * SL + i0], y1 = Ly[li * SL + i1];
           const Real w = x0 * y1;
-          acc = fma(c[r], w, acc);
+          acc = fma(c[h][r], w, acc);
           if (GRAD) {
-            g0 = fma(c[r], dLx[li * SL + i0] * y1, g0);
-            g1 = fma(c[r], x0 * dLy[li * SL + i1], g1);
-            g2 = fma(cd[r], w, g2);
+            g0 = fma(c[h][r], dLx[li * SL + i0] * y1, g0);
+            g1 = fma(c[h][r], x0 * dLy[li * SL + i1], g1);
+            g2 = fma(cd[h][r], w, g2);
           }
         }
-      }
     }
     // lanes li, li + 16, li + 32, li + 48 hold parts of target li
     for (int m = 16; m < 64; m <<= 1) {
@@ -691,7 +698,8 @@ __global__ __launch_bounds__(256) void k_eval_leaf_mfma(
 
 template <class Real, int PP>
 static size_t eval_leaf_lds(bool grad) {
-  constexpr int KA = (PP + 3) & ~3, SP = KA | 1, SL = PP | 1, MT = (PP * PP + 15) / 16;
+  constexpr int KA = (PP + 3) & ~3, SP = KA | 1, SL = PP | 1,
+                MT = ((PP * PP + 15) / 16 + 1) & ~1;
   const int NR = grad ? 2 : 1;
   return ((size_t)16 * MT * SP + (size_t)4 * NR * (2 * 16 * SL + KA * 16)) * sizeof(Real);
 }
@@ -810,19 +818,19 @@ __global__ __launch_bounds__(256) void k_anterp_mfma(KParams kp, Level L, Level 
     for (int st = 0; st < CH / 4; ++st)
 #pragma unroll
       for (int n = 0; n < NT; ++n) bz[st][n] = Lz[(4 * st + lk) * NW + 16 * n + li];
+    // every tile slot of the wave is computed (a slot past the last tile
+    // yields rows m >= P^2, whose clamped indices stay inside the rows and
+    // whose results are never stored), so the tiles' chains interleave
 #pragma unroll
     for (int i = 0; i < MW; ++i) {
-      const int mt = wave + 4 * i;
-      if (mt < MT) {
-        const int m = 16 * mt + li;
-        const int i0 = min(m / P, P - 1), i1 = m - (m / P) * P;
+      const int m = min(16 * (wave + 4 * i) + li, PP - 1);
+      const int i0 = m / P, i1 = m - i0 * P;
 #pragma unroll
-        for (int st = 0; st < CH / 4; ++st) {
-          const int si = 4 * st + lk;
-          const Real av = qLx[si * SL + i0] * Ly[si * SL + i1];
+      for (int st = 0; st < CH / 4; ++st) {
+        const int si = 4 * st + lk;
+        const Real av = qLx[si * SL + i0] * Ly[si * SL + i1];
 #pragma unroll
-          for (int n = 0; n < NT; ++n) acc[i][n] = MF::op(av, bz[st][n], acc[i][n]);
-        }
+        for (int n = 0; n < NT; ++n) acc[i][n] = MF::op(av, bz[st][n], acc[i][n]);
       }
     }
     __syncthreads();
