@@ -65,8 +65,9 @@ __device__ inline void residual_pair(const double* x, const double4& sv, double 
   r2d = fma(dd[1], dd[1], r2d);
   if (D == 3) r2d = fma(dd[2], dd[2], r2d);
   const bool in = r2d < h2d && r2d > 0.0;
-  nin += in ? 1 : 0;
   if (in) {
+    // pairs inside the support: a wave-uniform count of the active lanes
+    nin += __popcll(__ballot(1));
     const Real r2 = (Real)r2d;
     const Real qs = sq.x, ih = sq.y, ihh = sq.z;
     const Real u = fma(r2, ihh, (Real)-1);
@@ -190,11 +191,21 @@ __device__ void direct_pass(const KParams& kp, const int4* __restrict__ list, in
     cur.advance(list);
     nxt.fetch(cur, kp, sx, sq, nimg, cT, D);
     Real ta = 0, tb = 0, ga[3] = {0, 0, 0}, gb[3] = {0, 0, 0};
+    if constexpr (S == 1) {
+      // one lane per target: the whole tile unrolled (LDS reads at immediate offsets)
+#pragma unroll
+      for (int k = 0; k < 64; k += 2) {
+        residual_pair<D, NE, GRAD, Real>(x, shv[k], shh2[k], shw[k], ec, edc, ta, ga, nin);
+        residual_pair<D, NE, GRAD, Real>(x, shv[k + 1], shh2[k + 1], shw[k + 1], ec, edc, tb,
+                                         gb, nin);
+      }
+    } else {
 #pragma unroll 2
-    for (int k = slice; k < 64; k += 2 * S) {
-      residual_pair<D, NE, GRAD, Real>(x, shv[k], shh2[k], shw[k], ec, edc, ta, ga, nin);
-      residual_pair<D, NE, GRAD, Real>(x, shv[k + S], shh2[k + S], shw[k + S], ec, edc, tb,
-                                       gb, nin);
+      for (int k = slice; k < 64; k += 2 * S) {
+        residual_pair<D, NE, GRAD, Real>(x, shv[k], shh2[k], shw[k], ec, edc, ta, ga, nin);
+        residual_pair<D, NE, GRAD, Real>(x, shv[k + S], shh2[k + S], shw[k + S], ec, edc, tb,
+                                         gb, nin);
+      }
     }
     acc += (double)ta + (double)tb;
     if (GRAD)
@@ -261,9 +272,10 @@ __global__ __launch_bounds__(64) void k_direct(
     const int t = t0 + lane / S;
     const bool valid = t < te;
     double x[3] = {0, 0, 0};
-    for (int a = 0; a < D; ++a) x[a] = valid ? tx[a * ntrg + t] - cT[a] : 0.0;
+    // lanes of targets past the end sit far away: they stage sources but no
+    // pair of theirs is inside the support
+    for (int a = 0; a < D; ++a) x[a] = valid ? tx[a * ntrg + t] - cT[a] : 1e30;
     double acc = 0.0, g[3] = {0, 0, 0};
-    // lanes of targets past the end still take part in staging but do no pairs
     int nin_p = 0;
     switch (S) {
       case 1:
@@ -287,7 +299,7 @@ __global__ __launch_bounds__(64) void k_direct(
                                           shh2, shw, acc, g, nin_p);
         break;
     }
-    if (valid) nin += nin_p;
+    nin += nin_p;   // wave-uniform (lanes of targets past the end never interact)
     if (valid && lane % S == 0) {
       const double cst = D == 3 ? kInv4Pi : kInv2Pi;
       double v = acc * cst;
@@ -302,7 +314,6 @@ __global__ __launch_bounds__(64) void k_direct(
     t0 += 64 / S;
   }
   // pairs inside the support (statistics): one atomic per block
-  for (int m = 1; m < 64; m <<= 1) nin += __shfl_xor(nin, m);
   if (lane == 0 && n_support) atomicAdd(n_support, (unsigned long long)nin);
 }
 
