@@ -256,6 +256,17 @@ __device__ inline int wrap_index(int i, int M) {
   return r < 0 ? r + M : r;
 }
 
+// Lane j's value, read by every lane (wave-uniform).
+__device__ inline double rdlane(double v, int j) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), j);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), j);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+__device__ inline float rdlane(float v, int j) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), j));
+}
+
 // Spreading (step one of Section 3.6): the block takes 256 consecutive
 // sources in tree order and accumulates their windows in an LDS subgrid; each
 // wave spreads its 64 sources one at a time, the lanes covering the W^D
@@ -288,13 +299,14 @@ __global__ __launch_bounds__(256) void k_spread_coop(KParams kp, int64_t n,
   // lane l < D W holds the window value of axis l / W, offset l % W
   const int wa = lane / W, wk = lane - wa * W;
   for (int j = 0; j < 64; ++j) {
-    const double qj = __shfl(qi, j);
+    // point j of this wave, broadcast from its lane (uniform values)
+    const double qj = rdlane(qi, j);
     if (qj == 0.0) continue;   // also skips lanes past the end (uniform across the wave)
     double gj[D];
     int ij[D];
     for (int a = 0; a < D; ++a) {
-      gj[a] = __shfl(g[a], j);
-      ij[a] = __shfl(i0[a], j);
+      gj[a] = rdlane(g[a], j);
+      ij[a] = __builtin_amdgcn_readlane(i0[a], j);
     }
     Real wv = 0;
     if (wa < D) {
@@ -303,25 +315,49 @@ __global__ __launch_bounds__(256) void k_spread_coop(KParams kp, int64_t n,
       wv = es_win((Real)((ia + wk - ga) / (double)hw), (Real)beta);
       if (wa == 0) wv *= (Real)qj;
     }
+    if (D == 3) {
+      // lane = stencil column (k0, k1); the column's W values differ only
+      // in the uniform last-axis weight
 #pragma unroll
-    for (int e0 = 0; e0 < NE; e0 += 64) {
-      const int e = e0 + lane;
-      const int k0 = e % W, k1 = (e / W) % W, k2 = D == 3 ? e / (W * W) : 0;
-      Real v = __shfl(wv, k0) * __shfl(wv, W + k1);
-      if (D == 3) v *= __shfl(wv, 2 * W + k2);
-      if (e < NE) {
-        if (tiled) {
-          const int o = ((ij[D - 1] - lo[D - 1] + (D == 3 ? k2 : k1)) *
-                             (D == 3 ? ext[1] : 1) +
-                         (D == 3 ? ij[1] - lo[1] + k1 : 0)) *
-                            ext[0] +
-                        ij[0] - lo[0] + k0;
-          atomicAdd(sub + o, (double)v);
-        } else {
-          int64_t gi = wrap_index(ij[0] + k0, M0) +
-                       (int64_t)M0 * wrap_index(ij[1] + k1, M1);
-          if (D == 3) gi += (int64_t)M0 * M1 * wrap_index(ij[D - 1] + k2, M2);
-          atomicAdd(grid + gi, (double)v);
+      for (int p0 = 0; p0 < W * W; p0 += 64) {
+        const int pr = p0 + lane;
+        const int k0 = pr % W, k1 = pr / W;
+        const Real v01 = __shfl(wv, k0) * __shfl(wv, W + (k1 < W ? k1 : 0));
+        if (pr < W * W) {
+          if (tiled) {
+            const int ob = ((ij[D - 1] - lo[D - 1]) * ext[1] + ij[1] - lo[1] + k1) * ext[0] +
+                           ij[0] - lo[0] + k0;
+            const int st = ext[0] * ext[1];
+#pragma unroll
+            for (int k2 = 0; k2 < W; ++k2) {
+              const Real v2 = rdlane(wv, 2 * W + k2);
+              atomicAdd(sub + ob + k2 * st, (double)(v01 * v2));
+            }
+          } else {
+            const int64_t gb = wrap_index(ij[0] + k0, M0) + (int64_t)M0 * wrap_index(ij[1] + k1, M1);
+#pragma unroll
+            for (int k2 = 0; k2 < W; ++k2) {
+              const Real v2 = rdlane(wv, 2 * W + k2);
+              atomicAdd(grid + gb + (int64_t)M0 * M1 * wrap_index(ij[D - 1] + k2, M2),
+                        (double)(v01 * v2));
+            }
+          }
+        }
+      }
+    } else {
+#pragma unroll
+      for (int e0 = 0; e0 < NE; e0 += 64) {
+        const int e = e0 + lane;
+        const int k0 = e % W, k1 = (e / W) % W;
+        const Real v = __shfl(wv, k0) * __shfl(wv, W + k1);
+        if (e < NE) {
+          if (tiled) {
+            const int o = (ij[D - 1] - lo[D - 1] + k1) * ext[0] + ij[0] - lo[0] + k0;
+            atomicAdd(sub + o, (double)v);
+          } else {
+            const int64_t gi = wrap_index(ij[0] + k0, M0) + (int64_t)M0 * wrap_index(ij[1] + k1, M1);
+            atomicAdd(grid + gi, (double)v);
+          }
         }
       }
     }
