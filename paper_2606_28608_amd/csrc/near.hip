@@ -66,8 +66,7 @@ __device__ inline void residual_pair(const double* x, const double4& sv, double 
   if (D == 3) r2d = fma(dd[2], dd[2], r2d);
   const bool in = r2d < h2d && r2d > 0.0;
   if (in) {
-    // pairs inside the support: a wave-uniform count of the active lanes
-    nin += __popcll(__ballot(1));
+    ++nin;   // pairs inside the support (one masked add where the series runs)
     const Real r2 = (Real)r2d;
     const Real qs = sq.x, ih = sq.y, ihh = sq.z;
     const Real u = fma(r2, ihh, (Real)-1);
@@ -299,7 +298,7 @@ __global__ __launch_bounds__(64) void k_direct(
                                           shh2, shw, acc, g, nin_p);
         break;
     }
-    nin += nin_p;   // wave-uniform (lanes of targets past the end never interact)
+    nin += nin_p;   // lanes of targets past the end never interact
     if (valid && lane % S == 0) {
       const double cst = D == 3 ? kInv4Pi : kInv2Pi;
       double v = acc * cst;
@@ -314,6 +313,7 @@ __global__ __launch_bounds__(64) void k_direct(
     t0 += 64 / S;
   }
   // pairs inside the support (statistics): one atomic per block
+  for (int m = 1; m < 64; m <<= 1) nin += __shfl_xor(nin, m);
   if (lane == 0 && n_support) atomicAdd(n_support, (unsigned long long)nin);
 }
 
