@@ -144,20 +144,28 @@ __device__ inline void for_each_image(const KParams& kp, const double* x, F f) {
 }
 
 __global__ void k_img_count(KParams kp, int64_t n, const double* __restrict__ xs,
-                            int* __restrict__ cnt) {
+                            int* __restrict__ cnt, int* __restrict__ missing) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const int d = kp.dim;
   double x[3] = {0, 0, 0};
   for (int a = 0; a < d; ++a) x[a] = xs[a * n + i];
   int c = 0;
-  for_each_image(kp, x, [&](const double*) { ++c; });
+  bool orig = false;
+  for_each_image(kp, x, [&](const double* y) {
+    ++c;
+    orig = orig || (y[0] == x[0] && y[1] == x[1] && y[2] == x[2]);
+  });
   cnt[i] = c;
+  if (!orig) atomicAdd(missing, 1);   // the unshifted copy was not emitted
 }
 
+// Images of source i at off[i]...; isrc[o] = i for the unshifted copy, -1
+// for the shifted ones.
 __global__ void k_img_emit(KParams kp, int64_t n, const double* __restrict__ xs,
                            const double* __restrict__ q, const int* __restrict__ off,
-                           int64_t nimg, double* __restrict__ xi, double* __restrict__ qi) {
+                           int64_t nimg, double* __restrict__ xi, double* __restrict__ qi,
+                           int* __restrict__ isrc) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const int d = kp.dim;
@@ -168,8 +176,32 @@ __global__ void k_img_emit(KParams kp, int64_t n, const double* __restrict__ xs,
   for_each_image(kp, x, [&](const double* y) {
     for (int a = 0; a < d; ++a) xi[a * nimg + o] = y[a];
     qi[o] = qq;
+    isrc[o] = (y[0] == x[0] && y[1] == x[1] && y[2] == x[2]) ? (int)i : -1;
     ++o;
   });
+}
+
+// Targets that are the sources: the sorted targets are the unshifted copies
+// in the sorted images (equal coordinates give equal keys, and the stable
+// radix sort keeps both in source-index order among equal keys).
+__global__ void k_orig_flag(int64_t nimg, const int* __restrict__ perm,
+                            const int* __restrict__ isrc, int* __restrict__ flag) {
+  int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p < nimg) flag[p] = isrc[perm[p]] >= 0 ? 1 : 0;
+}
+__global__ void k_orig_pick(int64_t nimg, int64_t n, int d, const int* __restrict__ perm,
+                            const int* __restrict__ isrc, const int* __restrict__ pos,
+                            const uint64_t* __restrict__ skey, const double* __restrict__ sx,
+                            uint64_t* __restrict__ tkey, double* __restrict__ tx,
+                            int* __restrict__ tperm) {
+  int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= nimg) return;
+  const int src = isrc[perm[p]];
+  if (src < 0) return;
+  const int t = pos[p];
+  tperm[t] = src;
+  tkey[t] = skey[p];
+  for (int a = 0; a < d; ++a) tx[a * n + t] = sx[a * nimg + p];
 }
 
 // -------------------------------------------------------------------- keys
@@ -270,22 +302,44 @@ void stage_prepare(pdmk_plan* P, Eval& E, const double* src, const double* trg) 
 void stage_images(pdmk_plan* P, Eval& E, const double* q) {
   const KParams& kp = P->kp;
   int64_t n = E.n_src;
-  int* cnt = E.alloc<int>(n + 1);
+  int* cnt = E.alloc<int>(n + 2);   // [n + 1]: sources whose unshifted copy is missing
   int* off = E.alloc<int>(n + 1);
-  PDMK_HIP(hipMemsetAsync(cnt + n, 0, sizeof(int), E.s));
+  PDMK_HIP(hipMemsetAsync(cnt + n, 0, 2 * sizeof(int), E.s));
   if (n > 0)
-    hipLaunchKernelGGL(k_img_count, dim3(nblk(n, 256)), dim3(256), 0, E.s, kp, n, E.xs, cnt);
+    hipLaunchKernelGGL(k_img_count, dim3(nblk(n, 256)), dim3(256), 0, E.s, kp, n, E.xs, cnt,
+                       cnt + n + 1);
   exclusive_scan_int(cnt, off, (int)(n + 1), E);
-  E.n_img = read_int(off + n, E.s);
+  int hv[2] = {0, 0};
+  PDMK_HIP(hipMemcpyAsync(&hv[0], off + n, sizeof(int), hipMemcpyDeviceToHost, E.s));
+  PDMK_HIP(hipMemcpyAsync(&hv[1], cnt + n + 1, sizeof(int), hipMemcpyDeviceToHost, E.s));
+  PDMK_HIP(hipStreamSynchronize(E.s));
+  E.n_img = hv[0];
+  const bool from_images = E.self_targets && hv[1] == 0;
   double* xi = E.alloc<double>(E.n_img * kp.dim);
   double* qi = E.alloc<double>(E.n_img);
+  int* isrc = E.alloc<int>(E.n_img);
   if (n > 0)
     hipLaunchKernelGGL(k_img_emit, dim3(nblk(n, 256)), dim3(256), 0, E.s, kp, n, E.xs, q, off,
-                       E.n_img, xi, qi);
+                       E.n_img, xi, qi, isrc);
   int* perm = nullptr;
   sort_points(P, E, E.n_img, xi, qi, E.skey, E.sx, E.sq, perm);
-  double* dummyq = nullptr;
-  sort_points(P, E, E.n_trg, E.xt, nullptr, E.tkey, E.tx, dummyq, E.tperm);
+  if (from_images) {
+    E.tkey = E.alloc<uint64_t>(E.n_trg);
+    E.tx = E.alloc<double>(E.n_trg * kp.dim);
+    E.tperm = E.alloc<int>(E.n_trg);
+    int* flag = E.alloc<int>(E.n_img + 1);
+    int* pos = E.alloc<int>(E.n_img + 1);
+    if (E.n_img > 0) {
+      hipLaunchKernelGGL(k_orig_flag, dim3(nblk(E.n_img, 256)), dim3(256), 0, E.s, E.n_img,
+                         perm, isrc, flag);
+      exclusive_scan_int(flag, pos, (int)E.n_img, E);
+      hipLaunchKernelGGL(k_orig_pick, dim3(nblk(E.n_img, 256)), dim3(256), 0, E.s, E.n_img,
+                         E.n_trg, kp.dim, perm, isrc, pos, E.skey, E.sx, E.tkey, E.tx, E.tperm);
+    }
+  } else {
+    double* dummyq = nullptr;
+    sort_points(P, E, E.n_trg, E.xt, nullptr, E.tkey, E.tx, dummyq, E.tperm);
+  }
   // original sources in tree order (spatially coherent spreading)
   if (E.self_targets) {
     E.ox = E.tx;
