@@ -226,12 +226,20 @@ __global__ void k_charge_stats(int64_t n, const double* __restrict__ q, double* 
   }
 }
 
+// Final assembly: un-permute, add the uniform-background constant
+// -(sum q) cnn, rotate gradients back.  Writes nothing when the input was
+// rejected (non-finite values, or charges not neutral without
+// allow_nonneutral), so the caller's outputs stay untouched on error.
 __global__ void k_assemble(int64_t n, int d, const int* __restrict__ tperm,
                            const double* __restrict__ ps, const double* __restrict__ gs,
-                           double shift, KParams kp, double* __restrict__ pot,
-                           double* __restrict__ grad) {
+                           const double* __restrict__ qs, const int* __restrict__ flags,
+                           double cnn, int allow_nonneutral, KParams kp,
+                           double* __restrict__ pot, double* __restrict__ grad) {
   int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= n) return;
+  if (flags[0] || flags[1]) return;
+  if (!allow_nonneutral && fabs(qs[0]) > 1e-8 * qs[1]) return;
+  const double shift = -qs[0] * cnn;
   const int o = tperm[t];
   pot[o] = ps[t] + shift;
   if (grad) {
@@ -411,7 +419,7 @@ int pdmk_plan_create(const pdmk_opts* opts, const double* L, pdmk_plan** out) {
       if (mp) P->mixed_parts = (unsigned)std::atoi(mp) & 7u;
     }
     far_build_scale(P);
-    PDMK_HIP(hipHostMalloc((void**)&P->h_cnt, 4 * sizeof(unsigned long long)));
+    PDMK_HIP(hipHostMalloc((void**)&P->h_cnt, 8 * sizeof(unsigned long long)));
   } catch (const Error& e) {
     free_plan_tables(P);
     delete P;
@@ -524,21 +532,16 @@ static int eval_impl(pdmk_plan* P, int64_t n_src, const double* src, const doubl
     hipEvent_t ev[5];
     for (auto& e : ev) PDMK_HIP(hipEventCreate(&e));
     PDMK_HIP(hipEventRecord(ev[0], s));
-    // charge checks
+    // input checks (charge sums, non-finite charges and positions) stay on
+    // the device and are read after the call's final synchronisation; the
+    // pipeline runs on sanitised data in between and the assembly writes
+    // nothing for a rejected input
     double* qs = E.alloc<double>(2);
-    int* bad = E.alloc<int>(1);
+    E.d_flags = E.alloc<int>(2);
     PDMK_HIP(hipMemsetAsync(qs, 0, 2 * sizeof(double), s));
-    PDMK_HIP(hipMemsetAsync(bad, 0, sizeof(int), s));
+    PDMK_HIP(hipMemsetAsync(E.d_flags, 0, 2 * sizeof(int), s));
     hipLaunchKernelGGL(k_charge_stats, dim3(std::min(1024, nblk(n_src, 256))), dim3(256), 0, s,
-                       n_src, q, qs, bad);
-    double hq[2];
-    int hbad = 0;
-    PDMK_HIP(hipMemcpyAsync(hq, qs, sizeof(hq), hipMemcpyDeviceToHost, s));
-    PDMK_HIP(hipMemcpyAsync(&hbad, bad, sizeof(int), hipMemcpyDeviceToHost, s));
-    PDMK_HIP(hipStreamSynchronize(s));
-    if (hbad) throw Error{PDMK_ERR_NONFINITE, "non-finite charge"};
-    if (std::fabs(hq[0]) > 1e-8 * hq[1] && !(flags & PDMK_ALLOW_NONNEUTRAL))
-      throw Error{PDMK_ERR_NOT_NEUTRAL, "sum of charges is not zero"};
+                       n_src, q, qs, E.d_flags);
     stage_prepare(P, E, src, trg);
     stage_images(P, E, q);
     stage_tree(P, E);
@@ -552,10 +555,12 @@ static int eval_impl(pdmk_plan* P, int64_t n_src, const double* src, const doubl
     // tin-foil potential plus (sum q) * Rhat_0(0) / V
     const double cc = P->P->c;
     const double cnn = -P->P->psit_dd0 * P->g.rc * P->g.rc / (2.0 * cc * cc * P->g.volume);
-    const double shift = -hq[0] * cnn;
     hipLaunchKernelGGL(k_assemble, dim3(nblk(n_trg, 256)), dim3(256), 0, s, n_trg, d, E.tperm,
-                       E.pot_sorted, E.grad_sorted, shift, P->kp, pot,
+                       E.pot_sorted, E.grad_sorted, qs, E.d_flags, cnn,
+                       (flags & PDMK_ALLOW_NONNEUTRAL) ? 1 : 0, P->kp, pot,
                        want_grad ? grad : nullptr);
+    PDMK_HIP(hipMemcpyAsync(P->h_cnt + 4, qs, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
+    PDMK_HIP(hipMemcpyAsync(P->h_cnt + 6, E.d_flags, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
     PDMK_HIP(hipEventRecord(ev[4], s));
     PDMK_HIP(hipEventSynchronize(ev[4]));
     near_finish(P, E);
@@ -565,6 +570,16 @@ static int eval_impl(pdmk_plan* P, int64_t n_src, const double* src, const doubl
     PDMK_HIP(hipEventElapsedTime(&t3, ev[2], ev[3]));
     PDMK_HIP(hipEventElapsedTime(&t4, ev[0], ev[4]));
     for (auto& e : ev) (void)hipEventDestroy(e);
+    {
+      double hq[2];
+      int hf[2];
+      std::memcpy(hq, P->h_cnt + 4, sizeof(hq));
+      std::memcpy(hf, P->h_cnt + 6, sizeof(hf));
+      if (hf[0]) throw Error{PDMK_ERR_NONFINITE, "non-finite charge"};
+      if (hf[1]) throw Error{PDMK_ERR_NONFINITE, "non-finite position"};
+      if (std::fabs(hq[0]) > 1e-8 * hq[1] && !(flags & PDMK_ALLOW_NONNEUTRAL))
+        throw Error{PDMK_ERR_NOT_NEUTRAL, "sum of charges is not zero"};
+    }
     E.st.n_src = n_src;
     E.st.n_trg = n_trg;
     E.st.n_images = E.n_img;

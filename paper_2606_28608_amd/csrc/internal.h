@@ -151,6 +151,7 @@ struct Eval {
   // plane waves, leaf evaluation; per level {start, outgoing done, incoming
   // done, translation done}; device counters copied into the plan's pinned
   // host buffer
+  int* d_flags = nullptr;   // device {non-finite charge, non-finite position}
   bool near_pending = false;
   bool pw_split = false;
   hipEvent_t near_ev[4] = {nullptr, nullptr, nullptr, nullptr};
@@ -183,7 +184,9 @@ struct pdmk_plan {
   // plane waves, 4 far-field window weights (all by default)
   unsigned mixed_parts = 7;
   double* adj_buf = nullptr;    // Psi and grad Psi of the adjoint (n_src (d + 1))
-  unsigned long long* h_cnt = nullptr;   // pinned host: plane-wave pairs, boxes, support pairs
+  // pinned host: [0..2] plane-wave pairs, boxes, support pairs; [4..5] sum q,
+  // sum |q| (FP64 bits); [6] the two input flags of Eval::d_flags
+  unsigned long long* h_cnt = nullptr;
   size_t adj_size = 0;
   pdmk::KParams kp{};
   // device tables

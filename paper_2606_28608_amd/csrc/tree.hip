@@ -277,10 +277,12 @@ static void sort_points(pdmk_plan* P, Eval& E, int64_t n, const double* x_in,
                        q_in, x_sorted, q_sorted);
 }
 
+// Orientation and wrap.  Non-finite coordinates are replaced by 0 and flagged
+// in E.d_flags[1] (read by the caller once the call's stream has finished),
+// so every later index stays valid.
 void stage_prepare(pdmk_plan* P, Eval& E, const double* src, const double* trg) {
   const KParams& kp = P->kp;
-  int* bad = E.alloc<int>(1);
-  PDMK_HIP(hipMemsetAsync(bad, 0, sizeof(int), E.s));
+  int* bad = E.d_flags + 1;
   E.xs = E.alloc<double>(E.n_src * kp.dim);
   E.us = E.alloc<double>(E.n_src * kp.dim);
   if (E.n_src > 0)
@@ -296,7 +298,6 @@ void stage_prepare(pdmk_plan* P, Eval& E, const double* src, const double* trg) 
       hipLaunchKernelGGL(k_prepare, dim3(nblk(E.n_trg, 256)), dim3(256), 0, E.s, kp, E.n_trg,
                          trg, E.xt, E.ut, bad);
   }
-  if (read_int(bad, E.s)) throw Error{PDMK_ERR_NONFINITE, "non-finite position"};
 }
 
 void stage_images(pdmk_plan* P, Eval& E, const double* q) {

@@ -254,3 +254,20 @@ def test_mixed_2d_and_gradient(pdmk, torch_dev):
                    n_s=60)
     assert ewald.rel_l2(pot, ref) <= 1e-6
     assert ewald.rel_l2(g, gref) <= 1e-5
+
+
+def test_rejected_input_leaves_outputs_untouched(pdmk, torch_dev):
+    """Input checks are read after the call's stream has finished; a rejected
+    call (non-neutral charges, non-finite charge) must not write the outputs."""
+    torch, dev = torch_dev
+    L, src, q = workloads.clustered3d(800, seed=12)
+    plan = pdmk.Plan(L, eps=1e-6)
+    S = torch.tensor(src, dtype=torch.float64, device=dev)
+    for bad_q in (q + 0.05, np.where(np.arange(len(q)) == 3, np.inf, q)):
+        out = torch.full((len(q),), 7.0, dtype=torch.float64, device=dev)
+        with pytest.raises(pdmk.PdmkError):
+            plan.eval(S, torch.tensor(bad_q, dtype=torch.float64, device=dev), out=out)
+        assert bool((out == 7.0).all())
+    # the plan still evaluates a valid input afterwards
+    pot = plan.eval(S, torch.tensor(q, dtype=torch.float64, device=dev)).cpu().numpy()
+    assert ewald.rel_l2(pot, ewald.ewald(L, src, q)) <= 1e-6
