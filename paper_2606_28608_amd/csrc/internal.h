@@ -131,7 +131,7 @@ struct Eval {
   std::vector<Level> lev;
   Level* d_lev = nullptr;   // device copy of lev (for list building)
   // target leaves
-  int nleaf_t = 0;
+  int nleaf_t = 0;          // list slots: every box of every level
   int* lf_box = nullptr;    // (level << 26 | box) packed as two arrays
   int* lf_level = nullptr;
   int* lf_boxid = nullptr;
@@ -184,7 +184,8 @@ struct pdmk_plan {
   // plane waves, 4 far-field window weights (all by default)
   unsigned mixed_parts = 7;
   double* adj_buf = nullptr;    // Psi and grad Psi of the adjoint (n_src (d + 1))
-  // pinned host: [0..2] plane-wave pairs, boxes, support pairs; [4..5] sum q,
+  // pinned host: [0..2] plane-wave pairs, boxes, support pairs; [3] visited
+  // residual pairs; [4..5] sum q,
   // sum |q| (FP64 bits); [6] the two input flags of Eval::d_flags
   unsigned long long* h_cnt = nullptr;
   size_t adj_size = 0;

@@ -1224,6 +1224,7 @@ void near_finish(const pdmk_plan* P, Eval& E) {
   E.st.n_pw_pairs = (int64_t)P->h_cnt[0];
   E.st.n_pwin_boxes = (int64_t)P->h_cnt[1];
   E.st.n_support_pairs = (int64_t)P->h_cnt[2];
+  E.st.n_direct_pairs = (int64_t)P->h_cnt[3];   // copied by the list stage
   for (auto& pe : E.pw_ev) {
     float a = 0, b = 0, c = 0;
     PDMK_HIP(hipEventElapsedTime(&a, pe[0], pe[1]));

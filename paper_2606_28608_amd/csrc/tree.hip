@@ -548,28 +548,13 @@ void stage_tree(pdmk_plan* P, Eval& E) {
 }
 
 // ------------------------------------------------------------------- lists
-// Target leaves: boxes without children that hold targets, collected in tree
-// order (level by level, boxes in key order) by flag + scan.
-__global__ void k_leaf_flag(Level L, int* __restrict__ flag) {
-  int b = blockIdx.x * blockDim.x + threadIdx.x;
-  if (b < L.n) flag[b] = (L.child0[b] < 0 && L.tend[b] > L.tbeg[b]) ? 1 : 0;
-}
-
-__global__ void k_leaf_scatter(Level L, int lvl, const int* __restrict__ flag,
-                               const int* __restrict__ pos, int* __restrict__ lf_level,
-                               int* __restrict__ lf_box) {
-  int b = blockIdx.x * blockDim.x + threadIdx.x;
-  if (b >= L.n || !flag[b]) return;
-  lf_level[pos[b]] = lvl;
-  lf_box[pos[b]] = b;
-}
-
 // Residual interaction list of a target leaf T at level i (plane waves are
 // exchanged only between colleagues that both have children):
 //   (a) every colleague C of T: all sources of C, residual R_i;
 //   (b) for every ancestor A of T at level j < i: every colleague D of A
 //       without children: all sources of D, residual R_j.
-// Mode 0 counts entries (and direct pairs), mode 1 writes them.
+// Mode 0 counts entries (and direct pairs), mode 1 writes them.  Slots of
+// boxes that are not target leaves get no entries.
 __global__ void k_leaf_lists(int d, int nleaf, const Level* __restrict__ lev,
                              const int* __restrict__ lf_level, const int* __restrict__ lf_box,
                              int* __restrict__ cnt, const int* __restrict__ beg,
@@ -580,6 +565,14 @@ __global__ void k_leaf_lists(int d, int nleaf, const Level* __restrict__ lev,
   const int ncoll = d == 3 ? 27 : 9;
   int lvl = lf_level[i], b = lf_box[i];
   const Level& T = lev[lvl];
+  if (T.child0[b] >= 0 || T.tend[b] <= T.tbeg[b]) {
+    // not a target leaf: no list, no residual work
+    if (cnt) {
+      cnt[i] = 0;
+      nsrc[i] = 0;
+    }
+    return;
+  }
   int k = 0;
   long long np = 0;
   int o = beg ? beg[i] : 0;
@@ -651,52 +644,65 @@ __global__ void k_seg_fill(int n, const Level* __restrict__ lev, const int* __re
   }
 }
 
+// Every box of every level (level by level, boxes in key order) is a list
+// slot; boxes that are not target leaves get empty lists and no work items,
+// so the slots need no compaction (and no host read of the leaf count).
+__global__ void k_box_slots(Level L, int lvl, int* __restrict__ lf_level,
+                            int* __restrict__ lf_box) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= L.n) return;
+  lf_level[b] = lvl;
+  lf_box[b] = b;
+}
+
 void stage_lists(pdmk_plan* P, Eval& E) {
   const int d = P->kp.dim;
   int total = 0;
   for (auto& L : E.lev) total += L.n;
-  E.lf_level = E.alloc<int>(total);
-  E.lf_box = E.alloc<int>(total);
+  const int n = total;
+  E.nleaf_t = n;
+  E.lf_level = E.alloc<int>(n);
+  E.lf_box = E.alloc<int>(n);
   {
-    int* flag = E.alloc<int>(total + 1);
-    int* pos = E.alloc<int>(total + 1);
-    PDMK_HIP(hipMemsetAsync(flag + total, 0, sizeof(int), E.s));
     int off = 0;
     for (size_t l = 0; l < E.lev.size(); ++l) {
       if (E.lev[l].n > 0)
-        hipLaunchKernelGGL(k_leaf_flag, dim3(nblk(E.lev[l].n, 256)), dim3(256), 0, E.s,
-                           E.lev[l], flag + off);
+        hipLaunchKernelGGL(k_box_slots, dim3(nblk(E.lev[l].n, 256)), dim3(256), 0, E.s,
+                           E.lev[l], (int)l, E.lf_level + off, E.lf_box + off);
       off += E.lev[l].n;
     }
-    exclusive_scan_int(flag, pos, total + 1, E);
-    off = 0;
-    for (size_t l = 0; l < E.lev.size(); ++l) {
-      if (E.lev[l].n > 0)
-        hipLaunchKernelGGL(k_leaf_scatter, dim3(nblk(E.lev[l].n, 256)), dim3(256), 0, E.s,
-                           E.lev[l], (int)l, flag + off, pos + off, E.lf_level, E.lf_box);
-      off += E.lev[l].n;
-    }
-    E.nleaf_t = read_int(pos + total, E.s);
   }
-  int n = E.nleaf_t;
   int* cnt = E.alloc<int>(n + 1);
   E.lf_list_beg = E.alloc<int>(n + 1);
   unsigned long long* pairs = E.alloc<unsigned long long>(1);
   PDMK_HIP(hipMemsetAsync(pairs, 0, sizeof(unsigned long long), E.s));
   PDMK_HIP(hipMemsetAsync(cnt + n, 0, sizeof(int), E.s));
+  E.lf_nsrc = E.alloc<int>(n > 0 ? n : 1);
+  int* segs = E.alloc<int>(n + 1);
+  int* sbeg = E.alloc<int>(n + 1);
+  PDMK_HIP(hipMemsetAsync(segs + n, 0, sizeof(int), E.s));
   if (n > 0) {
-    E.lf_nsrc = E.alloc<int>(n);
     hipLaunchKernelGGL(k_leaf_lists, dim3(nblk(n, 128)), dim3(128), 0, E.s, d, n, E.d_lev,
                        E.lf_level, E.lf_box, cnt, (const int*)nullptr, (int4*)nullptr, pairs,
                        E.lf_nsrc);
     // work items of the residual sums: segments of each leaf's source list
-    int* segs = E.alloc<int>(n + 1);
-    int* sbeg = E.alloc<int>(n + 1);
-    PDMK_HIP(hipMemsetAsync(segs + n, 0, sizeof(int), E.s));
     hipLaunchKernelGGL(k_seg_count, dim3(nblk(n, 256)), dim3(256), 0, E.s, n, E.d_lev, E.lf_level,
                        E.lf_box, E.lf_nsrc, segs);
-    exclusive_scan_int(segs, sbeg, n + 1, E);
-    E.nitems = read_int(sbeg + n, E.s);
+  }
+  // visited pairs (statistics): read with the call's other counters at its end
+  PDMK_HIP(hipMemcpyAsync(P->h_cnt + 3, pairs, sizeof(unsigned long long),
+                          hipMemcpyDeviceToHost, E.s));
+  exclusive_scan_int(segs, sbeg, n + 1, E);
+  exclusive_scan_int(cnt, E.lf_list_beg, n + 1, E);
+  {
+    int hv[2] = {0, 0};
+    PDMK_HIP(hipMemcpyAsync(&hv[0], sbeg + n, sizeof(int), hipMemcpyDeviceToHost, E.s));
+    PDMK_HIP(hipMemcpyAsync(&hv[1], E.lf_list_beg + n, sizeof(int), hipMemcpyDeviceToHost, E.s));
+    PDMK_HIP(hipStreamSynchronize(E.s));
+    E.nitems = hv[0];
+    E.nlist = hv[1];
+  }
+  if (E.nitems > 0) {
     int2* items = E.alloc<int2>(E.nitems);
     unsigned* key = E.alloc<unsigned>(E.nitems);
     hipLaunchKernelGGL(k_seg_fill, dim3(nblk(n, 256)), dim3(256), 0, E.s, n, E.d_lev,
@@ -712,17 +718,11 @@ void stage_lists(pdmk_plan* P, Eval& E) {
     PDMK_HIP(rocprim::radix_sort_pairs(tmp, tb, key, key2, items, E.items, (size_t)E.nitems, 0u,
                                        32u, E.s));
   }
-  exclusive_scan_int(cnt, E.lf_list_beg, n + 1, E);
-  E.nlist = read_int(E.lf_list_beg + n, E.s);
-  E.list = E.alloc<int4>(E.nlist);
-  if (n > 0)
+  E.list = E.alloc<int4>(E.nlist > 0 ? E.nlist : 1);
+  if (n > 0 && E.nlist > 0)
     hipLaunchKernelGGL(k_leaf_lists, dim3(nblk(n, 128)), dim3(128), 0, E.s, d, n, E.d_lev,
                        E.lf_level, E.lf_box, (int*)nullptr, E.lf_list_beg, E.list,
                        (unsigned long long*)nullptr, (int*)nullptr);
-  unsigned long long np = 0;
-  PDMK_HIP(hipMemcpyAsync(&np, pairs, sizeof(np), hipMemcpyDeviceToHost, E.s));
-  PDMK_HIP(hipStreamSynchronize(E.s));
-  E.st.n_direct_pairs = (int64_t)np;
 }
 
 }  // namespace pdmk
