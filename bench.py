@@ -58,6 +58,8 @@ def parse():
     ap.add_argument("--precision", default="both", choices=["both", "fp64", "mixed"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-check", action="store_true")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="use the default (kappa, n_s) instead of planning them on the input")
     ap.add_argument("--cpu-sample", type=int, default=0,
                     help="oracle targets for the CPU baseline (0: one per oracle thread)")
     ap.add_argument("--cpu-alpha", type=float, default=1.3,
@@ -95,10 +97,10 @@ def load_traffic(mode, kernel):
     return None if m is None else m.get("bytes_per_launch")
 
 
-def run_mode(pdmk, L, S, Q, n, eps, precision, steps, warmup, gold):
+def run_mode(pdmk, L, S, Q, n, eps, precision, steps, warmup, gold, over=None):
     import numpy as np
     import torch
-    plan = pdmk.Plan(L, eps=eps, precision=precision)
+    plan = pdmk.Plan(L, eps=eps, precision=precision, **(over or {}))
     g = plan.geometry()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -236,7 +238,16 @@ def child(args):
         if os.path.exists(path):
             data = np.loadtxt(path)
             gold = (data[:, 0].astype(np.int64), data[:, 1])
-    r = run_mode(pdmk, L, S, Q, n, args.eps, args.precision, args.steps, args.warmup, gold)
+    over, tuning = {}, None
+    if not args.no_tune:
+        # runtime planning of (kappa, n_s) on this input, before the timed region
+        t0 = time.perf_counter()
+        k, ns, table = pdmk.tune(L, S, Q, eps=args.eps, precision=args.precision, trials=1)
+        over = {"kappa": k, "n_s": ns}
+        tuning = {"seconds": round(time.perf_counter() - t0, 2),
+                  "ms_per_candidate": {"kappa=%g,n_s=%d" % c: round(t, 2) for c, t in table.items()}}
+    r = run_mode(pdmk, L, S, Q, n, args.eps, args.precision, args.steps, args.warmup, gold, over)
+    r["tuning"] = tuning
     g = r.pop("plan")
     r["plan"] = {"kappa": g.kappa, "n_s": g.n_s, "porder": g.porder, "npw": g.npw,
                  "nufft_w": g.nufft_w, "fourier_grid": list(g.fgrid)}
@@ -284,6 +295,8 @@ def run_child(args, mode, batch=False):
            "--batch-systems", str(args.batch_systems)]
     if args.no_check:
         cmd.append("--no-check")
+    if args.no_tune:
+        cmd.append("--no-tune")
     p = subprocess.run(cmd, stdout=subprocess.PIPE, text=True)
     if p.returncode != 0:
         print("bench.py: %s%s run failed with status %d"
@@ -335,9 +348,11 @@ def main():
                          % (ns, n, args.cpu_alpha, tc)}
 
     def summary(x):
-        return {k: x[k] for k in ("value", "ms_per_step", "median_ms", "step_ms",
-                                  "cold_first_call_ms", "e_rel_sampled", "stages_ms",
-                                  "roofline")}
+        d = {k: x[k] for k in ("value", "ms_per_step", "median_ms", "step_ms",
+                               "cold_first_call_ms", "e_rel_sampled", "stages_ms",
+                               "roofline", "tuning")}
+        d["kappa"], d["n_s"] = x["plan"]["kappa"], x["plan"]["n_s"]
+        return d
 
     pl = r["plan"]
     out = {
@@ -352,7 +367,10 @@ def main():
                                "targets = sources" % (n, args.eps),
                    "precision": head, "kappa": pl["kappa"], "n_s": pl["n_s"],
                    "porder": pl["porder"], "npw": pl["npw"], "nufft_w": pl["nufft_w"],
-                   "fourier_grid": pl["fourier_grid"]},
+                   "fourier_grid": pl["fourier_grid"],
+                   "kappa_n_s_from": "runtime planner (pdmk_plan_tune) on this input, "
+                                     "before the timed steps" if r.get("tuning") else "defaults"},
+        "tuning": r.get("tuning"),
         "median_ms": r["median_ms"], "step_ms": r["step_ms"],
         "cold_first_call_ms": r["cold_first_call_ms"],
         "e_rel_sampled": r["e_rel_sampled"],

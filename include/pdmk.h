@@ -179,6 +179,30 @@ int pdmk_eval_batched(const pdmk_opts* opts, int n_sys, const double* L,
                       const int64_t* offsets, const double* src, const double* q,
                       double* pot, double* grad, void* stream);
 
+/*
+ * Runtime planning of the method's two free parameters, the root-cube side
+ * r_c = L_min / kappa and the leaf capacity n_s (Section 5; the paper leaves
+ * planning them at run time for later).  Each candidate (kappa[i], n_s[i])
+ * (<= 0: the value in opts) is planned and timed on the caller's input: one
+ * warm-up evaluation and `trials` timed ones (>= 1), results discarded.  The
+ * fastest pair is written to *best_kappa, *best_n_s.  The result of the
+ * method does not depend on (kappa, n_s) beyond the tolerance eps (the split
+ * of Section 3 is exact for any tree), so every candidate is a valid choice.
+ * opts, L: as for pdmk_plan_create (HOST).  kappa, n_s: n_cand candidates
+ * (HOST).  src, q, trg, n_src, n_trg: as for pdmk_plan_eval (DEVICE).  pot:
+ * DEVICE scratch of n_trg doubles (overwritten).  times_ms: HOST, n_cand
+ * doubles or NULL; receives each candidate's mean time per evaluation in
+ * milliseconds, -1 where the candidate could not be planned (for instance
+ * kappa out of range).  Blocks.  Errors: PDMK_ERR_INVALID_ARG for null
+ * arguments or n_cand < 1; the status of the first candidate when none
+ * could be planned; evaluation errors of a planned candidate are returned
+ * at once (they do not depend on the candidate).
+ */
+int pdmk_plan_tune(const pdmk_opts* opts, const double* L, int n_cand, const double* kappa,
+                   const int* n_s, int trials, int64_t n_src, const double* src,
+                   const double* q, int64_t n_trg, const double* trg, double* pot,
+                   void* stream, double* times_ms, double* best_kappa, int* best_n_s);
+
 /* Geometry and parameters a plan derived from (opts, L); host only. */
 typedef struct {
   int dim;

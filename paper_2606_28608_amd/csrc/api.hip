@@ -792,6 +792,52 @@ int pdmk_batch_stats(const pdmk_batch* B, int sys, pdmk_stats* out) {
   return PDMK_OK;
 }
 
+int pdmk_plan_tune(const pdmk_opts* opts, const double* L, int n_cand, const double* kappa,
+                   const int* n_s, int trials, int64_t n_src, const double* src,
+                   const double* q, int64_t n_trg, const double* trg, double* pot,
+                   void* stream, double* times_ms, double* best_kappa, int* best_n_s) {
+  if (!opts || !L || !kappa || !n_s || !best_kappa || !best_n_s || n_cand < 1 || trials < 1)
+    return fail(PDMK_ERR_INVALID_ARG, "null argument, n_cand < 1 or trials < 1");
+  double best = -1.0;
+  int first_err = PDMK_OK;
+  std::string first_msg;
+  for (int c = 0; c < n_cand; ++c) {
+    if (times_ms) times_ms[c] = -1.0;
+    pdmk_opts o = *opts;
+    if (kappa[c] > 0) o.kappa = kappa[c];
+    if (n_s[c] > 0) o.n_s = n_s[c];
+    pdmk_plan* P = nullptr;
+    int st = pdmk_plan_create(&o, L, &P);
+    if (st != PDMK_OK) {
+      if (first_err == PDMK_OK) {
+        first_err = st;
+        first_msg = g_last_error;
+      }
+      continue;
+    }
+    // warm-up (grows the plan's workspace), then the timed evaluations
+    st = pdmk_plan_eval(P, n_src, src, q, n_trg, trg, pot, nullptr, stream);
+    double ms = 0.0;
+    for (int t = 0; st == PDMK_OK && t < trials; ++t) {
+      const auto t0 = std::chrono::steady_clock::now();
+      st = pdmk_plan_eval(P, n_src, src, q, n_trg, trg, pot, nullptr, stream);
+      ms += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0)
+                .count();
+    }
+    pdmk_plan_destroy(P);
+    if (st != PDMK_OK) return st;   // an input error: the same for every candidate
+    ms /= trials;
+    if (times_ms) times_ms[c] = ms;
+    if (best < 0 || ms < best) {
+      best = ms;
+      *best_kappa = o.kappa;
+      *best_n_s = o.n_s;
+    }
+  }
+  if (best < 0) return fail(first_err, first_msg);
+  return PDMK_OK;
+}
+
 int pdmk_eval_batched(const pdmk_opts* opts, int n_sys, const double* L, const int64_t* offsets,
                       const double* src, const double* q, double* pot, double* grad,
                       void* stream) {

@@ -109,6 +109,10 @@ def lib():
         L.pdmk_batch_destroy.argtypes = [_vp]
         L.pdmk_batch_destroy.restype = None
         L.pdmk_batch_stats.argtypes = [_vp, ctypes.c_int, ctypes.POINTER(Stats)]
+        L.pdmk_plan_tune.argtypes = [ctypes.POINTER(Opts), _dp, ctypes.c_int, _dp,
+                                     ctypes.POINTER(ctypes.c_int), ctypes.c_int, ctypes.c_int64,
+                                     _vp, _vp, ctypes.c_int64, _vp, _vp, _vp, _dp, _dp,
+                                     ctypes.POINTER(ctypes.c_int)]
         L.pdmk_plan_destroy.argtypes = [_vp]
         L.pdmk_plan_destroy.restype = None
         L.pdmk_plan_geometry.argtypes = [_vp, ctypes.POINTER(Geometry)]
@@ -148,6 +152,44 @@ def _lattice(L, dim):
     if L.shape != (dim, dim):
         raise ValueError("L must be %dx%d with lattice vectors as columns" % (dim, dim))
     return np.asfortranarray(L).ravel(order="F").copy()
+
+
+def tune(L, src, q, eps=1e-6, precision="fp64", candidates=None, trials=2, trg=None,
+         dim=None, **over):
+    """Runtime planning (pdmk_plan_tune): times each (kappa, n_s) candidate on
+    this input and returns (kappa, n_s, {(kappa, n_s): ms}).  Default
+    candidates: kappa in {3, 4, 6} with the default leaf capacity times
+    {1, 1.5, 2}."""
+    import torch
+    L = np.asarray(L, dtype=np.float64)
+    dim = dim or L.shape[0]
+    o = default_opts(dim, eps, precision, **over)
+    if candidates is None:
+        base = o.n_s
+        candidates = [(k, int(round(base * f))) for k in (3.0, 4.0, 6.0) for f in (1.0, 1.5, 2.0)]
+    kap = np.array([float(c[0]) for c in candidates], dtype=np.float64)
+    nss = (ctypes.c_int * len(candidates))(*[int(c[1]) for c in candidates])
+    src = _dev(src, torch)
+    q = _dev(q, torch)
+    n = src.shape[0]
+    if trg is not None:
+        trg = _dev(trg, torch)
+        m = trg.shape[0]
+    else:
+        m = n
+    pot = torch.empty(m, dtype=torch.float64, device=src.device)
+    times = np.zeros(len(candidates), dtype=np.float64)
+    bk = ctypes.c_double(0.0)
+    bn = ctypes.c_int(0)
+    Lf = _lattice(L, dim)
+    _check(lib().pdmk_plan_tune(ctypes.byref(o), Lf.ctypes.data_as(_dp), len(candidates),
+                                kap.ctypes.data_as(_dp), nss, int(trials), n,
+                                ctypes.c_void_p(src.data_ptr()), ctypes.c_void_p(q.data_ptr()),
+                                m, ctypes.c_void_p(trg.data_ptr()) if trg is not None else None,
+                                ctypes.c_void_p(pot.data_ptr()),
+                                _stream(torch), times.ctypes.data_as(_dp), ctypes.byref(bk), ctypes.byref(bn)))
+    table = {(float(c[0]), int(c[1])): float(t) for c, t in zip(candidates, times)}
+    return bk.value, bn.value, table
 
 
 def geometry(L, dim=None, eps=1e-6, **over):

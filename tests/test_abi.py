@@ -197,3 +197,21 @@ def test_geometry_2d(lib):
     assert g.kappa == 7.0
     assert list(g.fgrid_paper)[:2] == [2 * math.ceil(g.c * a / (2 * math.pi * g.rc))
                                        for a in (Lo[0, 0], math.hypot(Lo[0, 1], Lo[1, 1]))]
+
+
+def test_plan_tune_argument_errors(lib):
+    """pdmk_plan_tune rejects bad arguments before touching a device."""
+    import ctypes
+    from paper_2606_28608_amd import pdmk
+    o = pdmk.Opts()
+    assert lib.pdmk_default_opts(3, ctypes.c_double(1e-6), ctypes.byref(o)) == 0
+    L = np.eye(3).ravel(order="F").copy()
+    kap = np.array([3.0])
+    ns = (ctypes.c_int * 1)(200)
+    bk, bn = ctypes.c_double(0), ctypes.c_int(0)
+    dp = ctypes.POINTER(ctypes.c_double)
+    for n_cand, trials in ((0, 1), (1, 0)):
+        st = lib.pdmk_plan_tune(ctypes.byref(o), L.ctypes.data_as(dp), n_cand,
+                                kap.ctypes.data_as(dp), ns, trials, 10, None, None, 10, None,
+                                None, None, None, ctypes.byref(bk), ctypes.byref(bn))
+        assert st == -1

@@ -271,3 +271,20 @@ def test_rejected_input_leaves_outputs_untouched(pdmk, torch_dev):
     # the plan still evaluates a valid input afterwards
     pot = plan.eval(S, torch.tensor(q, dtype=torch.float64, device=dev)).cpu().numpy()
     assert ewald.rel_l2(pot, ewald.ewald(L, src, q)) <= 1e-6
+
+
+def test_runtime_planner(pdmk, torch_dev):
+    """pdmk_plan_tune returns one of the candidates, and the plan made with it
+    meets the tolerance (the result does not depend on kappa, n_s)."""
+    torch, dev = torch_dev
+    L, src, q = workloads.clustered3d(4000, seed=13)
+    cands = [(2.0, 60), (3.0, 100), (4.0, 60)]
+    S = torch.tensor(src, dtype=torch.float64, device=dev)
+    Q = torch.tensor(q, dtype=torch.float64, device=dev)
+    k, ns, table = pdmk.tune(L, S, Q, eps=1e-6, precision="mixed", candidates=cands, trials=1)
+    assert (k, ns) in [(float(a), b) for a, b in cands]
+    assert all(t > 0 for t in table.values())
+    assert table[(k, ns)] == min(table.values())
+    plan = pdmk.Plan(L, eps=1e-6, precision="mixed", kappa=k, n_s=ns)
+    pot = plan.eval(S, Q).cpu().numpy()
+    assert ewald.rel_l2(pot, ewald.ewald(L, src, q)) <= 1e-6
