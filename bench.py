@@ -60,6 +60,10 @@ def parse():
     ap.add_argument("--no-check", action="store_true")
     ap.add_argument("--no-tune", action="store_true",
                     help="use the default (kappa, n_s) instead of planning them on the input")
+    ap.add_argument("--kappa", type=float, default=0.0,
+                    help="fixed kappa for the timed runs (with --n-s; skips the planner)")
+    ap.add_argument("--n-s", type=int, default=0, dest="n_s",
+                    help="fixed leaf capacity for the timed runs (with --kappa)")
     ap.add_argument("--cpu-sample", type=int, default=0,
                     help="oracle targets for the CPU baseline (0: one per oracle thread)")
     ap.add_argument("--cpu-alpha", type=float, default=1.3,
@@ -83,15 +87,19 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def load_traffic(mode, kernel):
+def load_traffic(mode, kernel, kappa, n_s):
     """HBM bytes per launch of `kernel` from the committed counter runs, or
-    None when the kernel sources have changed since they were taken."""
+    None when the kernel sources have changed since they were taken or the
+    runs used other (kappa, n_s)."""
     try:
         with open(TRAFFIC_FILE) as f:
             t = json.load(f)
     except (OSError, ValueError):
         return None
     if t.get("sources_sha256_16") != kernel_source_hash():
+        return None
+    pr = t.get("params", {}).get(mode)
+    if not pr or abs(pr["kappa"] - kappa) > 1e-12 or pr["n_s"] != n_s:
         return None
     m = t.get("kernels", {}).get(kernel, {}).get(mode)
     return None if m is None else m.get("bytes_per_launch")
@@ -202,7 +210,7 @@ def roofline(r, mode, plan):
     dom = max(allk, key=lambda k: allk[k]["launch_ms"] * allk[k]["launches"])
     d = dict(allk[dom])
     d["kernel"] = dom
-    d["traffic"] = load_traffic(mode, dom)
+    d["traffic"] = load_traffic(mode, dom, plan["kappa"], plan["n_s"])
     d["arith"] = "fp32" if mode == "mixed" else "fp64"
     d["kernels"] = {k: {kk: allk[k][kk] for kk in ("achieved", "frac", "launch_ms", "launches")}
                     for k in allk}
@@ -239,7 +247,9 @@ def child(args):
             data = np.loadtxt(path)
             gold = (data[:, 0].astype(np.int64), data[:, 1])
     over, tuning = {}, None
-    if not args.no_tune:
+    if args.kappa > 0 and args.n_s > 0:
+        over = {"kappa": args.kappa, "n_s": args.n_s}
+    elif not args.no_tune:
         # runtime planning of (kappa, n_s) on this input, before the timed region
         t0 = time.perf_counter()
         k, ns, table = pdmk.tune(L, S, Q, eps=args.eps, precision=args.precision, trials=1)
@@ -297,6 +307,8 @@ def run_child(args, mode, batch=False):
         cmd.append("--no-check")
     if args.no_tune:
         cmd.append("--no-tune")
+    if args.kappa > 0 and args.n_s > 0:
+        cmd += ["--kappa", str(args.kappa), "--n-s", str(args.n_s)]
     p = subprocess.run(cmd, stdout=subprocess.PIPE, text=True)
     if p.returncode != 0:
         print("bench.py: %s%s run failed with status %d"
