@@ -145,7 +145,7 @@ void plan_upload_tables(pdmk_plan* P) {
 static void free_plan_tables(pdmk_plan* P) {
   void* ptrs[] = {P->d_E, P->d_Ed, P->d_F2, P->d_F2d, P->d_nodes, P->d_bw, P->d_Tm,
                   P->d_F, P->d_Ff, P->d_dtab, P->d_farscale, P->d_shiftvec, P->d_pwt_f,
-                  P->d_pwt_d, P->adj_buf, P->d_ball, P->d_brow, P->d_fftw};
+                  P->d_pwt_d, P->adj_buf, P->d_ball, P->d_brow, P->d_fftw, P->d_pwt_b};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   if (P->h_cnt) (void)hipHostFree(P->h_cnt);
@@ -414,9 +414,10 @@ int pdmk_plan_create(const pdmk_opts* opts, const double* L, pdmk_plan** out) {
       const char* env = std::getenv("PDMK_NO_MFMA");
       P->pw_mfma = !(env && env[0] == '1');
       // diagnostic switch: PDMK_MIXED_PARTS=<mask> limits which stages run in
-      // FP32 in mixed mode (1 residual sums, 2 proxies/plane waves, 4 window)
+      // FP32 in mixed mode (1 residual sums, 2 proxies/plane waves, 4 window,
+      // 8 BF16 plane-wave products at eps >= 1e-3)
       const char* mp = std::getenv("PDMK_MIXED_PARTS");
-      if (mp) P->mixed_parts = (unsigned)std::atoi(mp) & 7u;
+      if (mp) P->mixed_parts = (unsigned)std::atoi(mp) & 15u;
     }
     far_build_scale(P);
     PDMK_HIP(hipHostMalloc((void**)&P->h_cnt, 8 * sizeof(unsigned long long)));

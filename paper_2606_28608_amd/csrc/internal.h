@@ -175,14 +175,17 @@ struct pdmk_plan {
   // real matrices of the plane-wave contractions for the matrix-core path
   float* d_pwt_f = nullptr;
   double* d_pwt_d = nullptr;
+  float* d_pwt_b = nullptr;     // FP32 values, depths padded for the BF16 products
   size_t pwt_off[6] = {0, 0, 0, 0, 0, 0};
+  size_t pwt_off_b[6] = {0, 0, 0, 0, 0, 0};
   int* d_ball = nullptr;        // modes of the half ball, then the slab starts
   int2* d_brow = nullptr;       // per mode row (j0, j1 + J): {index of j2 = -J, half width}
   int nball = 0;
   bool pw_mfma = true;          // use the matrix-core plane-wave kernels when they fit
   // stages that run in FP32 in mixed mode: 1 residual sums, 2 proxies and
-  // plane waves, 4 far-field window weights (all by default)
-  unsigned mixed_parts = 7;
+  // plane waves, 4 far-field window weights; 8: BF16 plane-wave products at
+  // eps >= 1e-3 (all by default)
+  unsigned mixed_parts = 15;
   double* adj_buf = nullptr;    // Psi and grad Psi of the adjoint (n_src (d + 1))
   // pinned host: [0..2] plane-wave pairs, boxes, support pairs; [3] visited
   // residual pairs; [4..5] sum q,
@@ -221,7 +224,8 @@ struct PwMfmaShape {
   size_t lds_out, lds_in;       // dynamic LDS bytes
   int sX, sZ, sI, sY, sW;       // LDS row strides
 };
-PwMfmaShape pw_mfma_shape(int p, int J, size_t real_size);
+// kb: k-steps of 4 per product (1: FP32 / FP64 16x16x4; 4: BF16 16x16x16)
+PwMfmaShape pw_mfma_shape(int p, int J, size_t real_size, int kb = 1);
 void pw_mfma_upload(pdmk_plan* P);
 // One level: outgoing expansions into S (compact half-ball order), the
 // colleague translation into Iw, incoming expansions into proxy_phi; ev_out /

@@ -50,13 +50,61 @@ template <> struct Mfma<double> {
   static __device__ int row(int l, int r) { return (l >> 4) + 4 * r; }
 };
 
-// Compile-time shape of one (p, J) pair.
-template <int P, int J>
+// One matrix-core step over KB k-steps of 4.  KB = 1: the 16x16x4 product
+// of Mfma<Real>.  KB = 4 (FP32 data): BF16 products with FP32 accumulation.
+// Every operand is split as x = hi + lo with hi = bf16(x), lo = bf16(x - hi)
+// (rounded to nearest even), and a b ~ hi_a hi_b + hi_a lo_b + lo_a hi_b,
+// which keeps about 16 significant bits (a single BF16 product keeps 8, too
+// few at eps = 1e-3 where the plane waves carry most of the potential).
+// Each is one 16x16x16 product in which lane l supplies its four k-step
+// values (A and B take the same permutation of the contraction index, so the
+// sum is unchanged).
+typedef short s4v __attribute__((ext_vector_type(4)));
+__device__ inline unsigned bf16_bits(float x) {
+  unsigned u = __float_as_uint(x);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return u & 0xffff0000u;   // the BF16 value as FP32 bits
+}
+template <class Real, int KB> struct KStep;
+template <class Real> struct KStep<Real, 1> {
+  using F = Real;
+  using V = typename Mfma<Real>::V;
+  static __device__ F pack(const Real* v) { return v[0]; }
+  static __device__ V op(F a, F b, V c) { return Mfma<Real>::op(a, b, c); }
+};
+struct Bf16x2 {
+  s4v hi, lo;
+};
+template <> struct KStep<float, 4> {
+  using F = Bf16x2;
+  using V = f4v;
+  static __device__ F pack(const float* v) {
+    F r;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const unsigned h = bf16_bits(v[j]);
+      const unsigned l = bf16_bits(v[j] - __uint_as_float(h));
+      r.hi[j] = (short)(h >> 16);
+      r.lo[j] = (short)(l >> 16);
+    }
+    return r;
+  }
+  static __device__ V op(const F& a, const F& b, V c) {
+    c = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a.lo, b.hi, c, 0, 0, 0);
+    c = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a.hi, b.lo, c, 0, 0, 0);
+    return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a.hi, b.hi, c, 0, 0, 0);
+  }
+};
+
+// Compile-time shape of one (p, J) pair; contraction depths are padded to
+// multiples of 4 KB (KB k-steps of 4 per matrix-core instruction).
+template <int P, int J, int KB = 1>
 struct PwShape {
+  static constexpr int KQ = 4 * KB;
   static constexpr int N1 = 2 * J + 1;                 // modes per axis
-  static constexpr int KA = (P + 3) & ~3;              // stage A depth (a)
-  static constexpr int K2P = (2 * P + 3) & ~3;         // depth over (ri, axis point)
-  static constexpr int K2N = (2 * N1 + 3) & ~3;        // depth over (mode, ri)
+  static constexpr int KA = (P + KQ - 1) / KQ * KQ;    // stage A depth (a)
+  static constexpr int K2P = (2 * P + KQ - 1) / KQ * KQ;    // depth over (ri, axis point)
+  static constexpr int K2N = (2 * N1 + KQ - 1) / KQ * KQ;   // depth over (mode, ri)
   static constexpr int T2N = (2 * N1 + 15) / 16;       // 16-tiles over 2 N1
   static constexpr int T2P = (2 * P + 15) / 16;        // 16-tiles over 2 P
   static constexpr int TP = (P + 15) / 16;             // 16-tiles over P
@@ -102,14 +150,16 @@ template <> struct Cplx<double> { using T = double2; };
 // for a whole group; the data operands are read from LDS without bounds tests
 // (padding rows/columns of the LDS matrices are zero or only reach discarded
 // outputs).
-template <class Real, int P, int J>
+template <class Real, int P, int J, int KB>
 __global__ __launch_bounds__(256, sizeof(Real) == 4 ? 2 : 1) void k_pw_out_mfma(
     const Real* __restrict__ Q, const Real* __restrict__ TA, const Real* __restrict__ TB,
     const Real* __restrict__ TC, const int2* __restrict__ brow, int nball,
     Real* __restrict__ S, int G, int sX, int sZ) {
-  using SH = PwShape<P, J>;
+  using SH = PwShape<P, J, KB>;
   using MF = Mfma<Real>;
   using V = typename MF::V;
+  using KS = KStep<Real, KB>;
+  using F = typename KS::F;
   constexpr int N1 = SH::N1, PP = P * P;
   extern __shared__ __align__(16) unsigned char smraw[];
   Real* X = reinterpret_cast<Real*>(smraw);   // K2P rows x sX: rows (ri, b), cols (jj, c)
@@ -133,13 +183,16 @@ __global__ __launch_bounds__(256, sizeof(Real) == 4 ? 2 : 1) void k_pw_out_mfma(
     const int g = min(G, J + 1 - j0b);
     // stage A (transposed): X^T[bc][(ri,jj)] = sum_a Q[a][bc] TA[(ri, j0b+jj)][a]
     {
-      Real bf[SH::KA / 4];
+      Real bfr[SH::KA / 4];
 #pragma unroll
       for (int s = 0; s < SH::KA / 4; ++s) {
         const int a = 4 * s + lk;
         const int ri = li >= g, jj = li - ri * g;
-        bf[s] = (a < P && li < 2 * g) ? TA[(ri * (J + 1) + j0b + jj) * P + a] : (Real)0;
+        bfr[s] = (a < P && li < 2 * g) ? TA[(ri * (J + 1) + j0b + jj) * P + a] : (Real)0;
       }
+      F bf[SH::KA / 4 / KB];
+#pragma unroll
+      for (int s = 0; s < SH::KA / 4 / KB; ++s) bf[s] = KS::pack(bfr + KB * s);
       // the proxy charges of every tile of this wave are loaded first (one
       // memory round trip per group instead of one per tile)
       constexpr int NT = (SH::TPP + 3) / 4;
@@ -159,7 +212,7 @@ __global__ __launch_bounds__(256, sizeof(Real) == 4 ? 2 : 1) void k_pw_out_mfma(
         if (t >= SH::TPP) break;
         V acc = {0, 0, 0, 0};
 #pragma unroll
-        for (int s = 0; s < SH::KA / 4; ++s) acc = MF::op(qv[i][s], bf[s], acc);
+        for (int s = 0; s < SH::KA / 4 / KB; ++s) acc = KS::op(KS::pack(qv[i] + KB * s), bf[s], acc);
         // acc element r: row bc' = 16 t + row(lane, r), column (ri, jj) = li
         const int ri = li >= g, jj = li - ri * g;
         if (li < 2 * g)
@@ -176,12 +229,16 @@ __global__ __launch_bounds__(256, sizeof(Real) == 4 ? 2 : 1) void k_pw_out_mfma(
     __syncthreads();
     // stage B: Z[(jj,j1)][(ro,c)] = sum_(ri,b) TB[(ro,j1)][(ri,b)] X[(ri,b)][(jj,c)]
     {
-      Real af[SH::T2N][SH::K2P / 4];
+      F af[SH::T2N][SH::K2P / 4 / KB];
 #pragma unroll
       for (int m = 0; m < SH::T2N; ++m)
 #pragma unroll
-        for (int s = 0; s < SH::K2P / 4; ++s)
-          af[m][s] = TB[(16 * m + li) * SH::K2P + 4 * s + lk];
+        for (int s = 0; s < SH::K2P / 4 / KB; ++s) {
+          Real v[KB];
+#pragma unroll
+          for (int u = 0; u < KB; ++u) v[u] = TB[(16 * m + li) * SH::K2P + 4 * (KB * s + u) + lk];
+          af[m][s] = KS::pack(v);
+        }
       const int nt = (g * P + 15) >> 4;
       for (int t = wave; t < nt; t += 4) {
         const Real* xb = X + lk * sX + 16 * t + li;
@@ -189,10 +246,13 @@ __global__ __launch_bounds__(256, sizeof(Real) == 4 ? 2 : 1) void k_pw_out_mfma(
 #pragma unroll
         for (int m = 0; m < SH::T2N; ++m) acc[m] = V{0, 0, 0, 0};
 #pragma unroll
-        for (int s = 0; s < SH::K2P / 4; ++s) {
-          const Real bv = xb[4 * s * sX];
+        for (int s = 0; s < SH::K2P / 4 / KB; ++s) {
+          Real v[KB];
 #pragma unroll
-          for (int m = 0; m < SH::T2N; ++m) acc[m] = MF::op(af[m][s], bv, acc[m]);
+          for (int u = 0; u < KB; ++u) v[u] = xb[4 * (KB * s + u) * sX];
+          const F bv = KS::pack(v);
+#pragma unroll
+          for (int m = 0; m < SH::T2N; ++m) acc[m] = KS::op(af[m][s], bv, acc[m]);
         }
         const int e = 16 * t + li;   // column (jj, c)
         if (e < g * P) {
@@ -213,12 +273,16 @@ __global__ __launch_bounds__(256, sizeof(Real) == 4 ? 2 : 1) void k_pw_out_mfma(
     __syncthreads();
     // stage C: S[(j0,j1)][2 j2 + ro] = sum_(ri,c) Z[(jj,j1)][(ri,c)] TC[(ri,c)][2 j2 + ro]
     {
-      Real bf[SH::T2N][SH::K2P / 4];
+      F bf[SH::T2N][SH::K2P / 4 / KB];
 #pragma unroll
       for (int m = 0; m < SH::T2N; ++m)
 #pragma unroll
-        for (int s = 0; s < SH::K2P / 4; ++s)
-          bf[m][s] = TC[(4 * s + lk) * (16 * SH::T2N) + 16 * m + li];
+        for (int s = 0; s < SH::K2P / 4 / KB; ++s) {
+          Real v[KB];
+#pragma unroll
+          for (int u = 0; u < KB; ++u) v[u] = TC[(4 * (KB * s + u) + lk) * (16 * SH::T2N) + 16 * m + li];
+          bf[m][s] = KS::pack(v);
+        }
       const int mt = (g * N1 + 15) >> 4;
       for (int t = wave; t < mt; t += 4) {
         const Real* zr = Z + (16 * t + li) * sZ + lk;
@@ -226,10 +290,13 @@ __global__ __launch_bounds__(256, sizeof(Real) == 4 ? 2 : 1) void k_pw_out_mfma(
 #pragma unroll
         for (int m = 0; m < SH::T2N; ++m) acc[m] = V{0, 0, 0, 0};
 #pragma unroll
-        for (int s = 0; s < SH::K2P / 4; ++s) {
-          const Real av = zr[4 * s];
+        for (int s = 0; s < SH::K2P / 4 / KB; ++s) {
+          Real v[KB];
 #pragma unroll
-          for (int m = 0; m < SH::T2N; ++m) acc[m] = MF::op(av, bf[m][s], acc[m]);
+          for (int u = 0; u < KB; ++u) v[u] = zr[4 * (KB * s + u)];
+          const F av = KS::pack(v);
+#pragma unroll
+          for (int m = 0; m < SH::T2N; ++m) acc[m] = KS::op(av, bf[m][s], acc[m]);
         }
         // only the modes of the ball |j| <= J are kept
 #pragma unroll
@@ -360,15 +427,17 @@ __global__ __launch_bounds__(256) void k_pw_trans(Level L, const typename Cplx<R
 // (already translated and scaled, in compact half-ball order) become the
 // box's proxy potential by the three conjugate contractions (accumulated in
 // registers across the slab groups).
-template <class Real, int P, int J>
+template <class Real, int P, int J, int KB>
 __global__ __launch_bounds__(256, sizeof(Real) == 4 ? 2 : 1) void k_pw_in_mfma(
     Level L, const typename Cplx<Real>::T* __restrict__ Iw, const Real* __restrict__ TA2,
     const Real* __restrict__ TB2, const Real* __restrict__ TC2, const int* __restrict__ ball,
     const int* __restrict__ ball_beg, int nball, Real* __restrict__ Phi, int G, int sI, int sY,
     int sW) {
-  using SH = PwShape<P, J>;
+  using SH = PwShape<P, J, KB>;
   using MF = Mfma<Real>;
   using V = typename MF::V;
+  using KS = KStep<Real, KB>;
+  using F = typename KS::F;
   using C2 = typename Cplx<Real>::T;
   constexpr int N1 = SH::N1, PP = P * P;
   constexpr int NACC = (SH::TPP + 3) / 4;   // Phi column tiles per wave
@@ -378,8 +447,8 @@ __global__ __launch_bounds__(256, sizeof(Real) == 4 ? 2 : 1) void k_pw_in_mfma(
   if (L.tend[b] <= L.tbeg[b]) return;   // no targets below this box
   Real* I = reinterpret_cast<Real*>(smraw);      // align16(G N1) rows x sI: cols 2 j2 + ri
   Real* Y = I + align16(G * N1) * sI;            // K2N rows x sY: rows 2 j1 + ri, cols (jj, c)
-  Real* W = Y + SH::K2N * sY;                    // align(2G, 4) rows x sW: cols (b, c)
-  const int wrows = (2 * G + 3) & ~3;
+  Real* W = Y + SH::K2N * sY;                    // align(2G, 4 KB) rows x sW: cols (b, c)
+  const int wrows = (2 * G + 4 * KB - 1) / (4 * KB) * (4 * KB);
   // zero the padding: I columns >= 2 N1, Y rows >= 2 N1, all of W
   for (int e = threadIdx.x; e < align16(G * N1) * (SH::K2N - 2 * N1); e += 256) {
     const int r = e / (SH::K2N - 2 * N1), c = e - r * (SH::K2N - 2 * N1);
@@ -426,12 +495,16 @@ __global__ __launch_bounds__(256, sizeof(Real) == 4 ? 2 : 1) void k_pw_in_mfma(
     __syncthreads();
     // stage C': Y[2 j1 + ro][(jj, c)] = sum_q I[(jj,j1)][q] TC2[q][2 c + ro]
     {
-      Real bf[SH::T2P][SH::K2N / 4];
+      F bf[SH::T2P][SH::K2N / 4 / KB];
 #pragma unroll
       for (int m = 0; m < SH::T2P; ++m)
 #pragma unroll
-        for (int s = 0; s < SH::K2N / 4; ++s)
-          bf[m][s] = TC2[(4 * s + lk) * (16 * SH::T2P) + 16 * m + li];
+        for (int s = 0; s < SH::K2N / 4 / KB; ++s) {
+          Real v[KB];
+#pragma unroll
+          for (int u = 0; u < KB; ++u) v[u] = TC2[(4 * (KB * s + u) + lk) * (16 * SH::T2P) + 16 * m + li];
+          bf[m][s] = KS::pack(v);
+        }
       const int mt = (g * N1 + 15) >> 4;
       for (int t = wave; t < mt; t += 4) {
         const Real* ir = I + (16 * t + li) * sI + lk;
@@ -439,10 +512,13 @@ __global__ __launch_bounds__(256, sizeof(Real) == 4 ? 2 : 1) void k_pw_in_mfma(
 #pragma unroll
         for (int m = 0; m < SH::T2P; ++m) a2[m] = V{0, 0, 0, 0};
 #pragma unroll
-        for (int s = 0; s < SH::K2N / 4; ++s) {
-          const Real av = ir[4 * s];
+        for (int s = 0; s < SH::K2N / 4 / KB; ++s) {
+          Real v[KB];
 #pragma unroll
-          for (int m = 0; m < SH::T2P; ++m) a2[m] = MF::op(av, bf[m][s], a2[m]);
+          for (int u = 0; u < KB; ++u) v[u] = ir[4 * (KB * s + u)];
+          const F av = KS::pack(v);
+#pragma unroll
+          for (int m = 0; m < SH::T2P; ++m) a2[m] = KS::op(av, bf[m][s], a2[m]);
         }
 #pragma unroll
         for (int m = 0; m < SH::T2P; ++m) {
@@ -462,12 +538,16 @@ __global__ __launch_bounds__(256, sizeof(Real) == 4 ? 2 : 1) void k_pw_in_mfma(
     __syncthreads();
     // stage B': W[2 jj + ro][(b, c)] = sum_q TB2[2 b + ro][q] Y[q][(jj, c)]
     {
-      Real af[SH::T2P][SH::K2N / 4];
+      F af[SH::T2P][SH::K2N / 4 / KB];
 #pragma unroll
       for (int m = 0; m < SH::T2P; ++m)
 #pragma unroll
-        for (int s = 0; s < SH::K2N / 4; ++s)
-          af[m][s] = TB2[(16 * m + li) * SH::K2N + 4 * s + lk];
+        for (int s = 0; s < SH::K2N / 4 / KB; ++s) {
+          Real v[KB];
+#pragma unroll
+          for (int u = 0; u < KB; ++u) v[u] = TB2[(16 * m + li) * SH::K2N + 4 * (KB * s + u) + lk];
+          af[m][s] = KS::pack(v);
+        }
       const int nt = (g * P + 15) >> 4;
       for (int t = wave; t < nt; t += 4) {
         const Real* yb = Y + lk * sY + 16 * t + li;
@@ -475,10 +555,13 @@ __global__ __launch_bounds__(256, sizeof(Real) == 4 ? 2 : 1) void k_pw_in_mfma(
 #pragma unroll
         for (int m = 0; m < SH::T2P; ++m) a2[m] = V{0, 0, 0, 0};
 #pragma unroll
-        for (int s = 0; s < SH::K2N / 4; ++s) {
-          const Real bv = yb[4 * s * sY];
+        for (int s = 0; s < SH::K2N / 4 / KB; ++s) {
+          Real v[KB];
 #pragma unroll
-          for (int m = 0; m < SH::T2P; ++m) a2[m] = MF::op(af[m][s], bv, a2[m]);
+          for (int u = 0; u < KB; ++u) v[u] = yb[4 * (KB * s + u) * sY];
+          const F bv = KS::pack(v);
+#pragma unroll
+          for (int m = 0; m < SH::T2P; ++m) a2[m] = KS::op(af[m][s], bv, a2[m]);
         }
         const int e = 16 * t + li;   // (jj, c)
         if (e < g * P) {
@@ -496,26 +579,35 @@ __global__ __launch_bounds__(256, sizeof(Real) == 4 ? 2 : 1) void k_pw_in_mfma(
     __syncthreads();
     // stage A': Phi[a][bc] += sum_q TA2[a][2 j0b + q] W[q][bc], q < 2g
     {
-      Real af[SH::TP][4];
+      Real afr[SH::TP][4];
 #pragma unroll
       for (int m = 0; m < SH::TP; ++m)
 #pragma unroll
         for (int s = 0; s < 4; ++s) {
           const int a = 16 * m + li, q = 4 * s + lk;
-          af[m][s] = (a < P && q < 2 * g) ? TA2[a * 2 * (J + 1) + 2 * j0b + q] : (Real)0;
+          afr[m][s] = (a < P && q < 2 * g) ? TA2[a * 2 * (J + 1) + 2 * j0b + q] : (Real)0;
         }
-      const int ks = (2 * g + 3) >> 2;
+      F af[SH::TP][4 / KB];
+#pragma unroll
+      for (int m = 0; m < SH::TP; ++m)
+#pragma unroll
+        for (int s = 0; s < 4 / KB; ++s) af[m][s] = KS::pack(afr[m] + KB * s);
+      // k-steps that reach a row q < 2g (W rows past 2g are zero)
+      const int ks = ((2 * g + 3) >> 2) + KB - 1;
 #pragma unroll
       for (int i = 0; i < NACC; ++i) {
         const int t = wave + 4 * i;
         if (t < SH::TPP) {
           const Real* wb = W + lk * sW + 16 * t + li;
 #pragma unroll
-          for (int s = 0; s < 4; ++s)
-            if (s < ks) {
-              const Real bv = wb[4 * s * sW];
+          for (int s = 0; s < 4 / KB; ++s)
+            if (KB * s < ks - KB + 1) {
+              Real v[KB];
 #pragma unroll
-              for (int m = 0; m < SH::TP; ++m) acc[m][i] = MF::op(af[m][s], bv, acc[m][i]);
+              for (int u = 0; u < KB; ++u) v[u] = wb[4 * (KB * s + u) * sW];
+              const F bv = KS::pack(v);
+#pragma unroll
+              for (int m = 0; m < SH::TP; ++m) acc[m][i] = KS::op(af[m][s], bv, acc[m][i]);
             }
         }
       }
@@ -1059,12 +1151,12 @@ static int stride_b(int n, size_t rs) {
   return rs == 4 ? ((n + 31) & ~31) + 16 : ((n + 15) & ~15) + 8;
 }
 
-PwMfmaShape pw_mfma_shape(int p, int J, size_t rs) {
+PwMfmaShape pw_mfma_shape(int p, int J, size_t rs, int kb) {
   PwMfmaShape s{};
   s.ok = pw_mfma_supported(p, J);
   if (!s.ok) return s;
-  const int n = 2 * J + 1;
-  const int k2p = (2 * p + 3) & ~3, k2n = (2 * n + 3) & ~3;
+  const int n = 2 * J + 1, kq = 4 * kb;
+  const int k2p = (2 * p + kq - 1) / kq * kq, k2n = (2 * n + kq - 1) / kq * kq;
   const size_t budget = 80 * 1024, hard = 150 * 1024;
   auto out_lds = [&](int g) {
     return ((size_t)k2p * stride_b(align16(g * p), rs) +
@@ -1073,7 +1165,7 @@ PwMfmaShape pw_mfma_shape(int p, int J, size_t rs) {
   auto in_lds = [&](int g) {
     return ((size_t)align16(g * n) * stride_a(k2n) +
             (size_t)k2n * stride_b(align16(g * p), rs) +
-            (size_t)((2 * g + 3) & ~3) * stride_b(align16(p * p), rs)) * rs;
+            (size_t)((2 * g + kq - 1) / kq * kq) * stride_b(align16(p * p), rs)) * rs;
   };
   auto pick = [&](auto lds, int& G, size_t& bytes) {
     int gmax = 0;
@@ -1102,9 +1194,9 @@ PwMfmaShape pw_mfma_shape(int p, int J, size_t rs) {
 // zero-padded to the tile grid the kernels read without bounds tests.
 template <class Real>
 static std::vector<Real> pw_mfma_tables_t(const std::vector<double>& nodes, int p, int J,
-                                          size_t off[6]) {
-  const int n = 2 * J + 1;
-  const int k2p = (2 * p + 3) & ~3, k2n = (2 * n + 3) & ~3;
+                                          size_t off[6], int kb) {
+  const int n = 2 * J + 1, kq = 4 * kb;
+  const int k2p = (2 * p + kq - 1) / kq * kq, k2n = (2 * n + kq - 1) / kq * kq;
   const int r2n = 16 * ((2 * n + 15) / 16), r2p = 16 * ((2 * p + 15) / 16);
   auto Fr = [&](int j, int x) { return std::cos(-kPi * j * nodes[x] / 3.0); };
   auto Fi = [&](int j, int x) { return std::sin(-kPi * j * nodes[x] / 3.0); };
@@ -1216,14 +1308,22 @@ void pw_mfma_upload(pdmk_plan* P) {
   std::vector<double> nodes, bw;
   cheb_nodes(p, nodes, bw);
   {
-    auto t = pw_mfma_tables_t<float>(nodes, p, J, P->pwt_off);
+    auto t = pw_mfma_tables_t<float>(nodes, p, J, P->pwt_off, 1);
     void* d = nullptr;
     PDMK_HIP(hipMalloc(&d, t.size() * sizeof(float)));
     PDMK_HIP(hipMemcpy(d, t.data(), t.size() * sizeof(float), hipMemcpyHostToDevice));
     P->d_pwt_f = static_cast<float*>(d);
   }
   {
-    auto t = pw_mfma_tables_t<double>(nodes, p, J, P->pwt_off);
+    // the same matrices padded for the BF16 products (depths multiple of 16)
+    auto t = pw_mfma_tables_t<float>(nodes, p, J, P->pwt_off_b, 4);
+    void* d = nullptr;
+    PDMK_HIP(hipMalloc(&d, t.size() * sizeof(float)));
+    PDMK_HIP(hipMemcpy(d, t.data(), t.size() * sizeof(float), hipMemcpyHostToDevice));
+    P->d_pwt_b = static_cast<float*>(d);
+  }
+  {
+    auto t = pw_mfma_tables_t<double>(nodes, p, J, P->pwt_off, 1);
     void* d = nullptr;
     PDMK_HIP(hipMalloc(&d, t.size() * sizeof(double)));
     PDMK_HIP(hipMemcpy(d, t.data(), t.size() * sizeof(double), hipMemcpyHostToDevice));
@@ -1231,26 +1331,27 @@ void pw_mfma_upload(pdmk_plan* P) {
   }
 }
 
-template <class Real>
-static const Real* pw_tables(const pdmk_plan* P);
-template <>
-const float* pw_tables<float>(const pdmk_plan* P) { return P->d_pwt_f; }
-template <>
-const double* pw_tables<double>(const pdmk_plan* P) { return P->d_pwt_d; }
-
-template <class Real, int PP, int JJ>
-static void pw_mfma_launch(const pdmk_plan* P, const PwMfmaShape& sh, const Level& L, int nn,
-                           const void* proxy_q, void* S, void* Iw, void* proxy_phi,
-                           double levfac, unsigned long long* npairs, hipEvent_t ev_out,
-                           hipEvent_t ev_tr, hipStream_t s) {
+template <class Real, int PP, int JJ, int KB>
+static void pw_mfma_launch(const pdmk_plan* P, const Level& L, int nn, const void* proxy_q,
+                           void* S, void* Iw, void* proxy_phi, double levfac,
+                           unsigned long long* npairs, hipEvent_t ev_out, hipEvent_t ev_tr,
+                           hipStream_t s) {
   using C2 = typename Cplx<Real>::T;
-  const Real* T = pw_tables<Real>(P);
-  const size_t* o = P->pwt_off;
-  PDMK_HIP(hipFuncSetAttribute((const void*)&k_pw_out_mfma<Real, PP, JJ>,
+  const PwMfmaShape sh = pw_mfma_shape(PP, JJ, sizeof(Real), KB);
+  const Real* T;
+  const size_t* o;
+  if constexpr (sizeof(Real) == 8) {
+    T = P->d_pwt_d;
+    o = P->pwt_off;
+  } else {
+    T = KB == 4 ? P->d_pwt_b : P->d_pwt_f;
+    o = KB == 4 ? P->pwt_off_b : P->pwt_off;
+  }
+  PDMK_HIP(hipFuncSetAttribute((const void*)&k_pw_out_mfma<Real, PP, JJ, KB>,
                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh.lds_out));
-  PDMK_HIP(hipFuncSetAttribute((const void*)&k_pw_in_mfma<Real, PP, JJ>,
+  PDMK_HIP(hipFuncSetAttribute((const void*)&k_pw_in_mfma<Real, PP, JJ, KB>,
                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh.lds_in));
-  hipLaunchKernelGGL((k_pw_out_mfma<Real, PP, JJ>), dim3(nn), dim3(256), sh.lds_out, s,
+  hipLaunchKernelGGL((k_pw_out_mfma<Real, PP, JJ, KB>), dim3(nn), dim3(256), sh.lds_out, s,
                      static_cast<const Real*>(proxy_q), T + o[0], T + o[1], T + o[2], P->d_brow,
                      P->nball, static_cast<Real*>(S), sh.g_out, sh.sX, sh.sZ);
   if (ev_out) PDMK_HIP(hipEventRecord(ev_out, s));
@@ -1259,10 +1360,16 @@ static void pw_mfma_launch(const pdmk_plan* P, const PwMfmaShape& sh, const Leve
                      static_cast<const C2*>(S), P->d_dtab, P->d_ball, P->nball, JJ, levfac,
                      static_cast<C2*>(Iw), npairs);
   if (ev_tr) PDMK_HIP(hipEventRecord(ev_tr, s));
-  hipLaunchKernelGGL((k_pw_in_mfma<Real, PP, JJ>), dim3(nn), dim3(256), sh.lds_in, s, L,
+  hipLaunchKernelGGL((k_pw_in_mfma<Real, PP, JJ, KB>), dim3(nn), dim3(256), sh.lds_in, s, L,
                      static_cast<const C2*>(Iw), T + o[3], T + o[4], T + o[5], P->d_ball,
                      P->d_ball + P->nball, P->nball, static_cast<Real*>(proxy_phi), sh.g_in,
                      sh.sI, sh.sY, sh.sW);
+}
+
+// BF16 products with FP32 accumulation for FP32 data at eps >= 1e-3
+// (PDMK_MIXED_PARTS bit 8 clears it for diagnostics).
+static bool pw_use_bf16(const pdmk_plan* P, size_t rs) {
+  return rs == 4 && P->o.eps >= 1e-3 && (P->mixed_parts & 8);
 }
 
 template <class Real>
@@ -1270,15 +1377,16 @@ void pw_mfma_level(const pdmk_plan* P, const Level& L, int nn, const void* proxy
                    void* Iw, void* proxy_phi, double levfac, unsigned long long* npairs,
                    hipEvent_t ev_out, hipEvent_t ev_tr, hipStream_t s) {
   const KParams& kp = P->kp;
-  const PwMfmaShape sh = pw_mfma_shape(kp.p, kp.J, sizeof(Real));
-  if (kp.p == 22 && kp.J == 16)
-    pw_mfma_launch<Real, 22, 16>(P, sh, L, nn, proxy_q, S, Iw, proxy_phi, levfac, npairs,
-                                 ev_out, ev_tr, s);
-  else if (kp.p == 13 && kp.J == 9)
-    pw_mfma_launch<Real, 13, 9>(P, sh, L, nn, proxy_q, S, Iw, proxy_phi, levfac, npairs,
-                                ev_out, ev_tr, s);
-  else
+  const bool bf = pw_use_bf16(P, sizeof(Real));
+  if (kp.p == 22 && kp.J == 16) {
+    if (bf) pw_mfma_launch<Real, 22, 16, sizeof(Real) == 4 ? 4 : 1>(P, L, nn, proxy_q, S, Iw, proxy_phi, levfac, npairs, ev_out, ev_tr, s);
+    else pw_mfma_launch<Real, 22, 16, 1>(P, L, nn, proxy_q, S, Iw, proxy_phi, levfac, npairs, ev_out, ev_tr, s);
+  } else if (kp.p == 13 && kp.J == 9) {
+    if (bf) pw_mfma_launch<Real, 13, 9, sizeof(Real) == 4 ? 4 : 1>(P, L, nn, proxy_q, S, Iw, proxy_phi, levfac, npairs, ev_out, ev_tr, s);
+    else pw_mfma_launch<Real, 13, 9, 1>(P, L, nn, proxy_q, S, Iw, proxy_phi, levfac, npairs, ev_out, ev_tr, s);
+  } else {
     throw Error{PDMK_ERR_UNSUPPORTED, "no matrix-core plane-wave kernel for this (p, J)"};
+  }
 }
 
 template void pw_mfma_level<float>(const pdmk_plan*, const Level&, int, const void*, void*,

@@ -288,3 +288,25 @@ def test_runtime_planner(pdmk, torch_dev):
     plan = pdmk.Plan(L, eps=1e-6, precision="mixed", kappa=k, n_s=ns)
     pot = plan.eval(S, Q).cpu().numpy()
     assert ewald.rel_l2(pot, ewald.ewald(L, src, q)) <= 1e-6
+
+
+def test_bf16_plane_waves_at_eps_1e3(pdmk, torch_dev, monkeypatch):
+    """At eps >= 1e-3 mixed plans form the plane-wave products from BF16
+    hi/lo splits with FP32 accumulation.  Both that path and the FP32 one
+    (diagnostic mask without bit 8) meet the tolerance, and they agree far
+    below it."""
+    torch, dev = torch_dev
+    L, src, q = workloads.clustered3d(6000, seed=2)
+    ref = ewald.ewald(L, src, q)
+    S = torch.tensor(src, dtype=torch.float64, device=dev)
+    Q = torch.tensor(q, dtype=torch.float64, device=dev)
+    pots = {}
+    for mask in (None, "7"):
+        if mask is None:
+            monkeypatch.delenv("PDMK_MIXED_PARTS", raising=False)
+        else:
+            monkeypatch.setenv("PDMK_MIXED_PARTS", mask)
+        plan = pdmk.Plan(L, eps=1e-3, precision="mixed", kappa=3.0, n_s=60)
+        pots[mask] = plan.eval(S, Q).cpu().numpy()
+        assert ewald.rel_l2(pots[mask], ref) <= 1e-3
+    assert ewald.rel_l2(pots[None], pots["7"]) <= 1e-4
