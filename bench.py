@@ -98,11 +98,12 @@ def load_traffic(mode, kernel, kappa, n_s):
         return None
     if t.get("sources_sha256_16") != kernel_source_hash():
         return None
-    pr = t.get("params", {}).get(mode)
-    if not pr or abs(pr["kappa"] - kappa) > 1e-12 or pr["n_s"] != n_s:
-        return None
-    m = t.get("kernels", {}).get(kernel, {}).get(mode)
-    return None if m is None else m.get("bytes_per_launch")
+    for run in t.get("runs", []):
+        if (run["precision"] == mode and abs(run["kappa"] - kappa) < 1e-12
+                and run["n_s"] == n_s):
+            m = run["kernels"].get(kernel)
+            return None if m is None else m.get("bytes_per_launch")
+    return None
 
 
 def run_mode(pdmk, L, S, Q, n, eps, precision, steps, warmup, gold, over=None):
