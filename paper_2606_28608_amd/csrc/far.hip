@@ -202,7 +202,7 @@ __device__ inline float es_win(float z, float beta) {
 
 // LDS subgrid (doubles) of the spreading and interpolation blocks: the
 // windows of 256 consecutive points in tree order cover a small box of cells.
-constexpr int kSubCap = 8192;
+constexpr int kSubCap = 4096;
 
 template <int D>
 __device__ inline void grid_coords(const KParams& kp, const double* __restrict__ x, int64_t n,
@@ -395,11 +395,23 @@ __global__ __launch_bounds__(256) void k_interp_t(KParams kp, int64_t n,
   int i0[D], lo[3], ext[3], vol;
   const bool tiled = block_box<D, W>(kp, n, x, i, valid, Ms, g, i0, lo_s, hi_s, lo, ext, vol);
   if (tiled) {
-    for (int c = threadIdx.x; c < vol; c += 256) {
-      const int c0 = c % ext[0], c1 = (c / ext[0]) % ext[1], c2 = c / (ext[0] * ext[1]);
-      int64_t gi = wrap_index(lo[0] + c0, M0) + (int64_t)M0 * wrap_index(lo[1] + c1, M1);
-      if (D == 3) gi += (int64_t)M0 * M1 * wrap_index(lo[2] + c2, M2);
-      sub[c] = grid[gi].x;
+    // the block's subgrid into LDS, eight loads in flight per thread
+    for (int c0 = threadIdx.x; c0 < vol; c0 += 8 * 256) {
+      double v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int c = c0 + u * 256;
+        v[u] = 0.0;
+        if (c < vol) {
+          const int a0 = c % ext[0], a1 = (c / ext[0]) % ext[1], a2 = c / (ext[0] * ext[1]);
+          int64_t gi = wrap_index(lo[0] + a0, M0) + (int64_t)M0 * wrap_index(lo[1] + a1, M1);
+          if (D == 3) gi += (int64_t)M0 * M1 * wrap_index(lo[2] + a2, M2);
+          v[u] = grid[gi].x;
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+        if (c0 + u * 256 < vol) sub[c0 + u * 256] = v[u];
     }
     __syncthreads();
   }
