@@ -54,7 +54,7 @@ template <> struct SlotQ<float> { using T = float4; };
 template <> struct SlotQ<double> { using T = double4; };
 
 template <int D, int NE, bool GRAD, class Real>
-__device__ inline void residual_pair(const double* x, const double4& sv, double h2d,
+__device__ inline void residual_pair(const double* x, const double4& sv,
                                      const typename SlotQ<Real>::T& sq, const Real* ec,
                                      const Real* edc, Real& acc, Real* g, int& nin) {
   double dd[3];
@@ -64,9 +64,18 @@ __device__ inline void residual_pair(const double* x, const double4& sv, double 
   double r2d = dd[0] * dd[0];
   r2d = fma(dd[1], dd[1], r2d);
   if (D == 3) r2d = fma(dd[2], dd[2], r2d);
-  const bool in = r2d < h2d && r2d > 0.0;
+  const bool in = r2d < sv.w && r2d > 0.0;   // sv.w = h^2 of the source's level
+  // pairs inside the support, counted for the whole wave on the scalar unit
+  // (every lane of the wave executes this line)
+  {
+    // (a ballot of each comparison maps onto its lane mask directly)
+    const int c = __builtin_amdgcn_readfirstlane((int)__popcll(
+        __builtin_amdgcn_ballot_w64(r2d < sv.w) & __builtin_amdgcn_ballot_w64(r2d > 0.0)));
+    int u = __builtin_amdgcn_readfirstlane(nin);
+    asm volatile("s_add_i32 %0, %0, %1" : "+s"(u) : "s"(c) : "scc");
+    nin = u;
+  }
   if (in) {
-    ++nin;   // pairs inside the support (one masked add where the series runs)
     const Real r2 = (Real)r2d;
     const Real qs = sq.x, ih = sq.y, ihh = sq.z;
     const Real u = fma(r2, ihh, (Real)-1);
@@ -130,12 +139,11 @@ struct ListCursor {
 
 template <class Real>
 struct SourceSlot {
-  double4 v;
-  double h2;
+  double4 v;                   // (offset, h^2)
   typename SlotQ<Real>::T w;   // (q, 1/h, 2/h^2, 0)
-  // Source offset from the target leaf centre (formed in FP64), the support
-  // h^2 of its residual level, and (q, 1/h, 2/h^2); slots past the list end
-  // never interact (h^2 = 0).
+  // Source offset from the target leaf centre (formed in FP64) with the support
+  // h^2 of its residual level in v.w, and (q, 1/h, 2/h^2); slots past the list
+  // end never interact (h^2 = 0).
   __device__ void fetch(const ListCursor& c, const KParams& kp, const double* __restrict__ sx,
                         const double* __restrict__ sq, int64_t nimg, const double* cT, int D) {
     if (c.valid()) {
@@ -143,10 +151,9 @@ struct SourceSlot {
       v.x = sx[sidx] - cT[0];
       v.y = sx[nimg + sidx] - cT[1];
       v.z = D == 3 ? sx[2 * nimg + sidx] - cT[2] : 0.0;
-      v.w = 0.0;
       const double hh = kp.rc / (double)(1 << c.en.z);
       const double ih = 1.0 / hh;
-      h2 = hh * hh;
+      v.w = hh * hh;
       w.x = (Real)sq[sidx];
       w.y = (Real)ih;
       w.z = (Real)(2.0 * ih * ih);
@@ -154,7 +161,6 @@ struct SourceSlot {
     } else {
       v.x = v.y = v.z = 1e30;
       v.w = 0;
-      h2 = 0;
       w.x = 0;
       w.y = 1;
       w.z = 2;
@@ -172,7 +178,7 @@ __device__ void direct_pass(const KParams& kp, const int4* __restrict__ list, in
                             int pos0, int pos1, const double* __restrict__ sx,
                             const double* __restrict__ sq,
                             int64_t nimg, const double* cT, const double* x, const Real* ec,
-                            const Real* edc, double4* shv, double* shh2,
+                            const Real* edc, double4* shv,
                             typename SlotQ<Real>::T* shw, double& acc, double* g, int& nin) {
   const int lane = threadIdx.x;
   const int slice = lane % S;
@@ -180,11 +186,11 @@ __device__ void direct_pass(const KParams& kp, const int4* __restrict__ list, in
   cur.init(list, lb, le, pos0 + lane, pos1);
   SourceSlot<Real> nxt;
   nxt.fetch(cur, kp, sx, sq, nimg, cT, D);
-  // the tile exists while the first lane's slot is in the list
-  while (__shfl(cur.valid() ? 1 : 0, 0)) {
+  // the tile exists while the first lane's slot is in the list (all lanes of
+  // the wave are active here, so the first active lane is lane 0)
+  while (__builtin_amdgcn_readfirstlane(cur.valid() ? 1 : 0)) {
     __syncthreads();
     shv[lane] = nxt.v;
-    shh2[lane] = nxt.h2;
     shw[lane] = nxt.w;
     __syncthreads();
     cur.advance(list);
@@ -194,15 +200,17 @@ __device__ void direct_pass(const KParams& kp, const int4* __restrict__ list, in
       // one lane per target: the whole tile unrolled (LDS reads at immediate offsets)
 #pragma unroll
       for (int k = 0; k < 64; k += 2) {
-        residual_pair<D, NE, GRAD, Real>(x, shv[k], shh2[k], shw[k], ec, edc, ta, ga, nin);
-        residual_pair<D, NE, GRAD, Real>(x, shv[k + 1], shh2[k + 1], shw[k + 1], ec, edc, tb,
+        residual_pair<D, NE, GRAD, Real>(x, shv[k], shw[k], ec, edc, ta, ga, nin);
+        residual_pair<D, NE, GRAD, Real>(x, shv[k + 1], shw[k + 1], ec, edc, tb,
                                          gb, nin);
       }
     } else {
+      // trip count independent of the lane (64 is a multiple of 2 S)
 #pragma unroll 2
-      for (int k = slice; k < 64; k += 2 * S) {
-        residual_pair<D, NE, GRAD, Real>(x, shv[k], shh2[k], shw[k], ec, edc, ta, ga, nin);
-        residual_pair<D, NE, GRAD, Real>(x, shv[k + S], shh2[k + S], shw[k + S], ec, edc, tb,
+      for (int kk = 0; kk < 64; kk += 2 * S) {
+        const int k = kk + slice;
+        residual_pair<D, NE, GRAD, Real>(x, shv[k], shw[k], ec, edc, ta, ga, nin);
+        residual_pair<D, NE, GRAD, Real>(x, shv[k + S], shw[k + S], ec, edc, tb,
                                          gb, nin);
       }
     }
@@ -237,7 +245,6 @@ __global__ __launch_bounds__(64) void k_direct(
     const double* __restrict__ Edc, double* __restrict__ pot, double* __restrict__ grad,
     unsigned long long* __restrict__ n_support) {
   __shared__ double4 shv[64];
-  __shared__ double shh2[64];
   __shared__ typename SlotQ<Real>::T shw[64];
   if ((int)blockIdx.x >= nitems) return;
   const int2 item = items[blockIdx.x];
@@ -279,26 +286,22 @@ __global__ __launch_bounds__(64) void k_direct(
     switch (S) {
       case 1:
         direct_pass<D, NE, 1, GRAD, Real>(kp, list, lb, le, pos0, pos1, sx, sq, nimg, cT, x,
-                                          ec, edc, shv,
-                                          shh2, shw, acc, g, nin_p);
+                                          ec, edc, shv, shw, acc, g, nin_p);
         break;
       case 2:
         direct_pass<D, NE, 2, GRAD, Real>(kp, list, lb, le, pos0, pos1, sx, sq, nimg, cT, x,
-                                          ec, edc, shv,
-                                          shh2, shw, acc, g, nin_p);
+                                          ec, edc, shv, shw, acc, g, nin_p);
         break;
       case 4:
         direct_pass<D, NE, 4, GRAD, Real>(kp, list, lb, le, pos0, pos1, sx, sq, nimg, cT, x,
-                                          ec, edc, shv,
-                                          shh2, shw, acc, g, nin_p);
+                                          ec, edc, shv, shw, acc, g, nin_p);
         break;
       default:
         direct_pass<D, NE, 8, GRAD, Real>(kp, list, lb, le, pos0, pos1, sx, sq, nimg, cT, x,
-                                          ec, edc, shv,
-                                          shh2, shw, acc, g, nin_p);
+                                          ec, edc, shv, shw, acc, g, nin_p);
         break;
     }
-    nin += nin_p;   // lanes of targets past the end never interact
+    nin += nin_p;   // the same wave-wide count on every lane
     if (valid && lane % S == 0) {
       const double cst = D == 3 ? kInv4Pi : kInv2Pi;
       double v = acc * cst;
@@ -313,7 +316,6 @@ __global__ __launch_bounds__(64) void k_direct(
     t0 += 64 / S;
   }
   // pairs inside the support (statistics): one atomic per block
-  for (int m = 1; m < 64; m <<= 1) nin += __shfl_xor(nin, m);
   if (lane == 0 && n_support) atomicAdd(n_support, (unsigned long long)nin);
 }
 

@@ -635,8 +635,31 @@ __global__ __launch_bounds__(256, sizeof(Real) == 4 ? 2 : 1) void k_pw_in_mfma(
 // For 16 targets at a time the contraction over i2 is a product
 //   T[(i0,i1)][t] = sum_i2 Phi[(i0,i1)][i2] Lz[i2][t]
 // on MFMA tiles; the remaining weights l_i0 l_i1 are applied as each tile
-// leaves the accumulators.  One block of 4 waves per non-leaf parent; each
-// wave takes whole 16-target chunks, so the waves never wait on each other.
+// leaves the accumulators.  The rows (i0, i1) are ordered so that the weights
+// need no index arithmetic: an "A" tile holds one i0 with i1 = 0..15, a "B"
+// tile (P > 16) the pair i0 = 2j, 2j + 1 with i1 = 16..23.  A lane's
+// accumulator rows then keep the same i1 in every tile (those l_i1 stay in
+// registers) and each tile needs one l_i0 per row block.  Rows with i0 or
+// i1 >= P are zero.  One block of 4 waves per non-leaf parent; each wave
+// takes whole 16-target chunks, so the waves never wait on each other.
+template <int P> struct LeafRows {
+  static_assert(P > 8 && P <= 24, "row layout covers 8 < P <= 24");
+  static constexpr int P1 = (P + 7) & ~7;                            // i1 padded: 16 or 24
+  static constexpr int NA = (P + 1) & ~1;                            // A tiles, even
+  static constexpr int NB = P1 > 16 ? ((P + 1) / 2 + 1) & ~1 : 0;    // B tiles, even
+  static constexpr int MT = NA + NB;
+  // (i0, i1) of row rho of tile tl; both stay below P1
+  __device__ static void map(int tl, int rho, int& i0, int& i1) {
+    if (tl < NA) {
+      i0 = tl;
+      i1 = rho;
+    } else {
+      i0 = 2 * (tl - NA) + (rho >> 3);
+      i1 = 16 + (rho & 7);
+    }
+  }
+};
+
 template <class Real, int P, bool GRAD>
 __global__ __launch_bounds__(256) void k_eval_leaf_mfma(
     KParams kp, Level Lp, Level Lc, int lvl, const double* __restrict__ tx, int64_t ntrg,
@@ -644,11 +667,12 @@ __global__ __launch_bounds__(256) void k_eval_leaf_mfma(
     double* __restrict__ grad) {
   using MF = Mfma<Real>;
   using V = typename MF::V;
-  constexpr int PP = P * P, KA = (P + 3) & ~3, SP = KA | 1, SL = P | 1;
-  constexpr int MT = ((PP + 15) / 16 + 1) & ~1;   // row tiles, even (two per step)
+  using LR = LeafRows<P>;
+  constexpr int KA = (P + 3) & ~3, SP = KA | 1, P1 = LR::P1, SL = P1 | 1;
+  constexpr int MT = LR::MT, NA = LR::NA;
   constexpr int NR = GRAD ? 2 : 1;
   extern __shared__ __align__(16) unsigned char smraw[];
-  Real* PhiA = reinterpret_cast<Real*>(smraw);        // 16 MT rows (i0,i1) x SP (i2), zero past PP
+  Real* PhiA = reinterpret_cast<Real*>(smraw);        // 16 MT rows x SP (i2)
   Real* wrow = PhiA + 16 * MT * SP;                     // per wave: rows of 16 targets
   __shared__ int cb[8], cpre[9];
   const int k = blockIdx.x;
@@ -671,15 +695,18 @@ __global__ __launch_bounds__(256) void k_eval_leaf_mfma(
   __syncthreads();
   const int total = cpre[8];
   if (total == 0) return;
-  const Real* Phi = static_cast<const Real*>(Lp.proxy_phi) + (int64_t)k * P * PP;
+  const Real* Phi = static_cast<const Real*>(Lp.proxy_phi) + (int64_t)k * P * P * P;
   lds_fill<8>(PhiA, 16 * MT * SP, [&](int e) {
-    const int m = e / SP, c = e - m * SP;
-    return (m < PP && c < P) ? Phi[m * P + c] : (Real)0;
+    const int R = e / SP, c = e - R * SP;
+    int i0, i1;
+    LR::map(R >> 4, R & 15, i0, i1);
+    return (i0 < P && i1 < P && c < P) ? Phi[(i0 * P + i1) * P + c] : (Real)0;
   });
   __syncthreads();
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int li = lane & 15, lk = lane >> 4;
-  // wave-private rows: Lx, Ly [16][SL] (and derivatives), Lz as B operand [KA][16]
+  // wave-private rows: Lx, Ly [16][SL] (zero past P), Lz as B operand [KA][16],
+  // and their derivatives
   Real* Lx = wrow + wave * NR * (2 * 16 * SL + KA * 16);
   Real* Ly = Lx + 16 * SL;
   Real* Lz = Ly + 16 * SL;
@@ -720,7 +747,12 @@ __global__ __launch_bounds__(256) void k_eval_leaf_mfma(
           if (GRAD) dLz[i * 16 + li] = dv;
         }
       }
-      if (a == 2)
+      if (a < 2)
+        for (int i = P; i < P1; ++i) {
+          (a == 0 ? Lx : Ly)[li * SL + i] = 0;
+          if (GRAD) (a == 0 ? dLx : dLy)[li * SL + i] = 0;
+        }
+      else
         for (int i = P; i < KA; ++i) {
           Lz[i * 16 + li] = 0;
           if (GRAD) dLz[i * 16 + li] = 0;
@@ -734,13 +766,25 @@ __global__ __launch_bounds__(256) void k_eval_leaf_mfma(
       bz[s] = Lz[(4 * s + lk) * 16 + li];
       bd[s] = GRAD ? dLz[(4 * s + lk) * 16 + li] : (Real)0;
     }
+    // l_i1 (and derivatives) of the lane's accumulator rows: A tiles, B tiles
+    Real ya[4], yb[4], dya[4], dyb[4];
+    int bo[4];   // i0 offset of the row within a B tile's pair
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int rho = MF::row(lane, r);
+      ya[r] = Ly[li * SL + rho];
+      yb[r] = P1 > 16 ? Ly[li * SL + 16 + (rho & 7)] : (Real)0;
+      dya[r] = GRAD ? dLy[li * SL + rho] : (Real)0;
+      dyb[r] = (GRAD && P1 > 16) ? dLy[li * SL + 16 + (rho & 7)] : (Real)0;
+      bo[r] = rho >> 3;
+    }
     Real acc = 0, g0 = 0, g1 = 0, g2 = 0;
     // two row tiles per step: independent accumulator chains overlap on the
-    // matrix pipe; rows past PP are zero in PhiA, so their (clamped) weights
-    // never contribute and no lane branches
-    for (int mt = 0; mt < MT; mt += 2) {
+    // matrix pipe (both tiles of a step are of the same kind: NA is even)
+    auto tiles = [&](int mt, V (&c)[2], V (&cd)[2]) {
       const Real* ar = PhiA + (16 * mt + li) * SP + lk;
-      V c[2] = {{0, 0, 0, 0}, {0, 0, 0, 0}}, cd[2] = {{0, 0, 0, 0}, {0, 0, 0, 0}};
+#pragma unroll
+      for (int h = 0; h < 2; ++h) c[h] = cd[h] = V{0, 0, 0, 0};
 #pragma unroll
       for (int s = 0; s < KA / 4; ++s) {
         const Real a0 = ar[4 * s], a1 = ar[16 * SP + 4 * s];
@@ -751,21 +795,47 @@ __global__ __launch_bounds__(256) void k_eval_leaf_mfma(
           cd[1] = MF::op(a1, bd[s], cd[1]);
         }
       }
+    };
+    for (int mt = 0; mt < NA; mt += 2) {
+      V c[2], cd[2];
+      tiles(mt, c, cd);
 #pragma unroll
-      for (int h = 0; h < 2; ++h)
+      for (int h = 0; h < 2; ++h) {
+        const Real x0 = Lx[li * SL + mt + h];
+        Real sy = 0, sdy = 0, sdz = 0;
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-          const int m = min(16 * (mt + h) + MF::row(lane, r), PP - 1);
-          const int i0 = m / P, i1 = m - i0 * P;
-          const Real x0 = Lx[li * SL + i0], y1 = Ly[li * SL + i1];
-          const Real w = x0 * y1;
-          acc = fma(c[h][r], w, acc);
+          sy = fma(c[h][r], ya[r], sy);
           if (GRAD) {
-            g0 = fma(c[h][r], dLx[li * SL + i0] * y1, g0);
-            g1 = fma(c[h][r], x0 * dLy[li * SL + i1], g1);
-            g2 = fma(cd[h][r], w, g2);
+            sdy = fma(c[h][r], dya[r], sdy);
+            sdz = fma(cd[h][r], ya[r], sdz);
           }
         }
+        acc = fma(x0, sy, acc);
+        if (GRAD) {
+          g0 = fma(dLx[li * SL + mt + h], sy, g0);
+          g1 = fma(x0, sdy, g1);
+          g2 = fma(x0, sdz, g2);
+        }
+      }
+    }
+    for (int mt = NA; mt < MT; mt += 2) {
+      V c[2], cd[2];
+      tiles(mt, c, cd);
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int i0 = 2 * (mt + h - NA);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const Real x0 = Lx[li * SL + i0 + bo[r]];
+          acc = fma(c[h][r], x0 * yb[r], acc);
+          if (GRAD) {
+            g0 = fma(c[h][r], dLx[li * SL + i0 + bo[r]] * yb[r], g0);
+            g1 = fma(c[h][r], x0 * dyb[r], g1);
+            g2 = fma(cd[h][r], x0 * yb[r], g2);
+          }
+        }
+      }
     }
     // lanes li, li + 16, li + 32, li + 48 hold parts of target li
     for (int m = 16; m < 64; m <<= 1) {
@@ -790,8 +860,8 @@ __global__ __launch_bounds__(256) void k_eval_leaf_mfma(
 
 template <class Real, int PP>
 static size_t eval_leaf_lds(bool grad) {
-  constexpr int KA = (PP + 3) & ~3, SP = KA | 1, SL = PP | 1,
-                MT = ((PP * PP + 15) / 16 + 1) & ~1;
+  constexpr int KA = (PP + 3) & ~3, SP = KA | 1, SL = LeafRows<PP>::P1 | 1,
+                MT = LeafRows<PP>::MT;
   const int NR = grad ? 2 : 1;
   return ((size_t)16 * MT * SP + (size_t)4 * NR * (2 * 16 * SL + KA * 16)) * sizeof(Real);
 }
