@@ -796,44 +796,55 @@ __global__ __launch_bounds__(256) void k_eval_leaf_mfma(
         }
       }
     };
-    for (int mt = 0; mt < NA; mt += 2) {
-      V c[2], cd[2];
-      tiles(mt, c, cd);
+    // software pipeline: the next pair's products are issued before this
+    // pair's weights are applied
+    V c[2], cd[2];
+    tiles(0, c, cd);
 #pragma unroll
-      for (int h = 0; h < 2; ++h) {
-        const Real x0 = Lx[li * SL + mt + h];
-        Real sy = 0, sdy = 0, sdz = 0;
+    for (int mt = 0; mt < MT; mt += 2) {
+      V cn[2], cdn[2];
+      if (mt + 2 < MT) tiles(mt + 2, cn, cdn);
+      if (mt < NA) {
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          sy = fma(c[h][r], ya[r], sy);
+        for (int h = 0; h < 2; ++h) {
+          const Real x0 = Lx[li * SL + mt + h];
+          Real sy = 0, sdy = 0, sdz = 0;
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            sy = fma(c[h][r], ya[r], sy);
+            if (GRAD) {
+              sdy = fma(c[h][r], dya[r], sdy);
+              sdz = fma(cd[h][r], ya[r], sdz);
+            }
+          }
+          acc = fma(x0, sy, acc);
           if (GRAD) {
-            sdy = fma(c[h][r], dya[r], sdy);
-            sdz = fma(cd[h][r], ya[r], sdz);
+            g0 = fma(dLx[li * SL + mt + h], sy, g0);
+            g1 = fma(x0, sdy, g1);
+            g2 = fma(x0, sdz, g2);
           }
         }
-        acc = fma(x0, sy, acc);
-        if (GRAD) {
-          g0 = fma(dLx[li * SL + mt + h], sy, g0);
-          g1 = fma(x0, sdy, g1);
-          g2 = fma(x0, sdz, g2);
+      } else {
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          const int i0 = 2 * (mt + h - NA);
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const Real x0 = Lx[li * SL + i0 + bo[r]];
+            acc = fma(c[h][r], x0 * yb[r], acc);
+            if (GRAD) {
+              g0 = fma(c[h][r], dLx[li * SL + i0 + bo[r]] * yb[r], g0);
+              g1 = fma(c[h][r], x0 * dyb[r], g1);
+              g2 = fma(cd[h][r], x0 * yb[r], g2);
+            }
+          }
         }
       }
-    }
-    for (int mt = NA; mt < MT; mt += 2) {
-      V c[2], cd[2];
-      tiles(mt, c, cd);
+      if (mt + 2 < MT) {
 #pragma unroll
-      for (int h = 0; h < 2; ++h) {
-        const int i0 = 2 * (mt + h - NA);
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const Real x0 = Lx[li * SL + i0 + bo[r]];
-          acc = fma(c[h][r], x0 * yb[r], acc);
-          if (GRAD) {
-            g0 = fma(c[h][r], dLx[li * SL + i0 + bo[r]] * yb[r], g0);
-            g1 = fma(c[h][r], x0 * dyb[r], g1);
-            g2 = fma(cd[h][r], x0 * yb[r], g2);
-          }
+        for (int h = 0; h < 2; ++h) {
+          c[h] = cn[h];
+          cd[h] = cdn[h];
         }
       }
     }
@@ -903,10 +914,11 @@ template bool eval_leaf_mfma<double>(const pdmk_plan*, const Level&, const Level
 // Proxy charges of a non-leaf box from the sources of its childless children
 // (3D): Q[i0][i1][i2] = sum_s q_s l_i0(xi_0) l_i1(xi_1) l_i2(xi_2), i.e. the
 // product (q l_i0 l_i1)[(i0,i1)][s] x l_i2[s][i2] over the sources, on MFMA
-// tiles with the sources in chunks of 32.  One block of 4 waves per box; each
+// tiles with the sources in chunks of 64 in FP32 (3 x 64 threads form a
+// chunk's Lagrange rows), 32 in FP64.  One block of 4 waves per box; each
 // wave owns the same M-tiles of Q for every chunk (accumulators in registers).
 template <class Real, int P>
-__global__ __launch_bounds__(256) void k_anterp_mfma(KParams kp, Level L, Level C, int lvl,
+__global__ __launch_bounds__(256, sizeof(Real) == 4 ? 3 : 1) void k_anterp_mfma(KParams kp, Level L, Level C, int lvl,
                                                      const double* __restrict__ sx,
                                                      const double* __restrict__ sq,
                                                      int64_t nimg,
@@ -915,7 +927,7 @@ __global__ __launch_bounds__(256) void k_anterp_mfma(KParams kp, Level L, Level 
                                                      Real* __restrict__ Q) {
   using MF = Mfma<Real>;
   using V = typename MF::V;
-  constexpr int PP = P * P, SL = P | 1, CH = 32, NT = (P + 15) / 16, NW = 16 * NT;
+  constexpr int PP = P * P, SL = P | 1, CH = sizeof(Real) == 4 ? 64 : 32, NT = (P + 15) / 16, NW = 16 * NT;
   constexpr int MT = (PP + 15) / 16, MW = (MT + 3) / 4;
   __shared__ Real qLx[CH * SL], Ly[CH * SL], Lz[CH * NW];
   __shared__ int cb[8], cpre[9];
@@ -945,10 +957,15 @@ __global__ __launch_bounds__(256) void k_anterp_mfma(KParams kp, Level L, Level 
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int li = lane & 15, lk = lane >> 4;
   V acc[MW][NT];
+  int ri0[MW], ri1[MW];   // (i0, i1) of the lane's A-operand row in each tile slot
 #pragma unroll
-  for (int i = 0; i < MW; ++i)
+  for (int i = 0; i < MW; ++i) {
+    const int m = min(16 * (wave + 4 * i) + li, PP - 1);
+    ri0[i] = m / P;
+    ri1[i] = m - ri0[i] * P;
 #pragma unroll
     for (int n = 0; n < NT; ++n) acc[i][n] = V{0, 0, 0, 0};
+  }
   for (int s0 = 0; s0 < total; s0 += CH) {
     // Lagrange rows of the chunk: thread (source, axis)
     if (threadIdx.x < 3 * CH) {
@@ -975,24 +992,42 @@ __global__ __launch_bounds__(256) void k_anterp_mfma(KParams kp, Level L, Level 
       }
     }
     __syncthreads();
-    Real bz[CH / 4][NT];
-#pragma unroll
-    for (int st = 0; st < CH / 4; ++st)
-#pragma unroll
-      for (int n = 0; n < NT; ++n) bz[st][n] = Lz[(4 * st + lk) * NW + 16 * n + li];
-    // every tile slot of the wave is computed (a slot past the last tile
+    // Every tile slot of the wave is computed (a slot past the last tile
     // yields rows m >= P^2, whose clamped indices stay inside the rows and
-    // whose results are never stored), so the tiles' chains interleave
-#pragma unroll
-    for (int i = 0; i < MW; ++i) {
-      const int m = min(16 * (wave + 4 * i) + li, PP - 1);
-      const int i0 = m / P, i1 = m - i0 * P;
-#pragma unroll
+    // whose results are never stored).
+    if constexpr (sizeof(Real) == 4) {
+      // k-step outer, tile slots inner: consecutive products go to different
+      // accumulators
+#pragma unroll 4
       for (int st = 0; st < CH / 4; ++st) {
         const int si = 4 * st + lk;
-        const Real av = qLx[si * SL + i0] * Ly[si * SL + i1];
+        Real bz[NT];
 #pragma unroll
-        for (int n = 0; n < NT; ++n) acc[i][n] = MF::op(av, bz[st][n], acc[i][n]);
+        for (int n = 0; n < NT; ++n) bz[n] = Lz[si * NW + 16 * n + li];
+#pragma unroll
+        for (int i = 0; i < MW; ++i) {
+          const Real av = qLx[si * SL + ri0[i]] * Ly[si * SL + ri1[i]];
+#pragma unroll
+          for (int n = 0; n < NT; ++n) acc[i][n] = MF::op(av, bz[n], acc[i][n]);
+        }
+      }
+    } else {
+      // FP64 (one wave per SIMD): the chunk's B operand in registers, tile
+      // slots outer (measured faster at this occupancy)
+      Real bz[CH / 4][NT];
+#pragma unroll
+      for (int st = 0; st < CH / 4; ++st)
+#pragma unroll
+        for (int n = 0; n < NT; ++n) bz[st][n] = Lz[(4 * st + lk) * NW + 16 * n + li];
+#pragma unroll
+      for (int i = 0; i < MW; ++i) {
+#pragma unroll
+        for (int st = 0; st < CH / 4; ++st) {
+          const int si = 4 * st + lk;
+          const Real av = qLx[si * SL + ri0[i]] * Ly[si * SL + ri1[i]];
+#pragma unroll
+          for (int n = 0; n < NT; ++n) acc[i][n] = MF::op(av, bz[st][n], acc[i][n]);
+        }
       }
     }
     __syncthreads();
