@@ -390,6 +390,7 @@ int pdmk_plan_create(const pdmk_opts* opts, const double* L, pdmk_plan** out) {
     kp.p = P->mp.porder;
     kp.J = P->mp.npw;
     kp.rc = P->g.rc;
+    kp.irc = 1.0 / P->g.rc;
     kp.precision = opts->precision;
     int64_t nroot = 1;
     for (int a = 0; a < 3; ++a) {

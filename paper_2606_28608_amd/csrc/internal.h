@@ -78,6 +78,7 @@ struct KParams {
   int B;            // Morton bits per axis
   int next[3];      // extended root grid dims
   double rc;
+  double irc;   // 1 / rc
   double origin[3];
   double L[9], Li[9], Q[9];
   double w0unit;    // W_h(0) for h = 1

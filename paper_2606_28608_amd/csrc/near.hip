@@ -151,8 +151,9 @@ struct SourceSlot {
       v.x = sx[sidx] - cT[0];
       v.y = sx[nimg + sidx] - cT[1];
       v.z = D == 3 ? sx[2 * nimg + sidx] - cT[2] : 0.0;
-      const double hh = kp.rc / (double)(1 << c.en.z);
-      const double ih = 1.0 / hh;
+      // h = r_c 2^-z and 1/h = (1/r_c) 2^z (power-of-two scalings: exact)
+      const double hh = ldexp(kp.rc, -c.en.z);
+      const double ih = ldexp(kp.irc, c.en.z);
       v.w = hh * hh;
       w.x = (Real)sq[sidx];
       w.y = (Real)ih;
@@ -1203,8 +1204,6 @@ static void near_impl(pdmk_plan* P, Eval& E, bool want_grad) {
       if (Cl.nnl == 0) continue;
       launch_transfer<D, Real>(kp, L, Cl, 0, L.proxy_phi, Cl.proxy_phi, P, E, s);
     }
-    PDMK_HIP(hipMemcpyAsync(E.d_lev, E.lev.data(), sizeof(Level) * E.lev.size(),
-                            hipMemcpyHostToDevice, s));
   }
   PDMK_HIP(hipEventRecord(e2, s));
   // leaf targets evaluate their parent's proxy potential
