@@ -218,7 +218,7 @@ __device__ inline void grid_coords(const KParams& kp, const double* __restrict__
 
 // Bounding box of the block's 256 points in grid cells (window start i0 per
 // axis); returns the subgrid extent and whether it fits in LDS.
-template <int D, int W>
+template <int D, int W, bool PAD = false>
 __device__ inline bool block_box(const KParams& kp, int64_t n, const double* __restrict__ x,
                                  int64_t i, bool valid, const int* Ms, double* g, int* i0,
                                  int* lo_s, int* hi_s, int* lo, int* ext, int& vol) {
@@ -245,6 +245,10 @@ __device__ inline bool block_box(const KParams& kp, int64_t n, const double* __r
   for (int a = 0; a < 3; ++a) {
     lo[a] = a < D ? lo_s[a] : 0;
     ext[a] = a < D ? hi_s[a] - lo_s[a] + W : 1;
+    // PAD: row stride = 8 (mod 16) doubles, so that the 8 rows of a wave's
+    // 8 x 8 stencil columns fall on alternating halves of the LDS banks
+    // (padding cells are never written)
+    if (PAD && a == 0) ext[0] += (24 - ext[0] % 16) % 16;
     if (a < D) v *= ext[a];
   }
   vol = v <= kSubCap ? (int)v : kSubCap + 1;
@@ -289,7 +293,8 @@ __global__ __launch_bounds__(256) void k_spread_coop(KParams kp, int64_t n,
   const bool valid = i < n;
   double g[D];
   int i0[D], lo[3], ext[3], vol;
-  const bool tiled = block_box<D, W>(kp, n, x, i, valid, Ms, g, i0, lo_s, hi_s, lo, ext, vol);
+  const bool tiled =
+      block_box<D, W, W == 8>(kp, n, x, i, valid, Ms, g, i0, lo_s, hi_s, lo, ext, vol);
   if (tiled) {
     for (int c = threadIdx.x; c < vol; c += 256) sub[c] = 0.0;
     __syncthreads();
