@@ -36,7 +36,9 @@
  *     keeps no caller pointer after a call returns.
  *   - Calls are ordered on the HIP stream passed in (NULL = default stream)
  *     and block until the results are written (the call synchronises its
- *     stream before returning).
+ *     stream before returning).  Inside a call, part of the work runs on a
+ *     second, plan-owned stream (default priority) forked from and joined
+ *     back to the caller's stream by events.
  *   - Errors: every function returns a pdmk_status.  On an error detected on
  *     the host the output arrays are not written.  pdmk_last_error() returns a
  *     thread-local message for the last failure.
@@ -234,6 +236,10 @@ typedef struct {
   int64_t n_direct_pairs;           /* target-source pairs visited by the residual sums */
   int64_t n_pw_pairs;               /* plane-wave box pairs */
   double t_build_ms, t_near_ms, t_far_ms, t_total_ms;
+                                    /* t_far_ms: the far field's grid steps (run on the
+                                       plan's second stream beside the build and near
+                                       field, so they overlap those times) plus the
+                                       interpolation */
   double t_direct_ms, t_pw_ms, t_proxy_ms;
   int64_t n_support_pairs;          /* visited pairs inside the residual support (r < h) */
   int series_len;                   /* terms of the residual series the residual sums used */

@@ -150,6 +150,11 @@ static void free_plan_tables(pdmk_plan* P) {
     if (p) (void)hipFree(p);
   if (P->h_cnt) (void)hipHostFree(P->h_cnt);
   P->h_cnt = nullptr;
+  if (P->s_aux) {
+    (void)hipStreamSynchronize(P->s_aux);
+    (void)hipStreamDestroy(P->s_aux);
+    P->s_aux = nullptr;
+  }
   if (P->arena) {
     // every evaluation synchronises its stream before returning, so the
     // arena is no longer in use
@@ -422,6 +427,7 @@ int pdmk_plan_create(const pdmk_opts* opts, const double* L, pdmk_plan** out) {
     }
     far_build_scale(P);
     PDMK_HIP(hipHostMalloc((void**)&P->h_cnt, 8 * sizeof(unsigned long long)));
+    PDMK_HIP(hipStreamCreateWithFlags(&P->s_aux, hipStreamNonBlocking));
   } catch (const Error& e) {
     free_plan_tables(P);
     delete P;
@@ -531,8 +537,9 @@ static int eval_impl(pdmk_plan* P, int64_t n_src, const double* src, const doubl
       PDMK_HIP(hipStreamSynchronize(s));
       return PDMK_OK;
     }
-    hipEvent_t ev[5];
+    hipEvent_t ev[5], fev[3];
     for (auto& e : ev) PDMK_HIP(hipEventCreate(&e));
+    for (auto& e : fev) PDMK_HIP(hipEventCreate(&e));
     PDMK_HIP(hipEventRecord(ev[0], s));
     // input checks (charge sums, non-finite charges and positions) stay on
     // the device and are read after the call's final synchronisation; the
@@ -546,12 +553,23 @@ static int eval_impl(pdmk_plan* P, int64_t n_src, const double* src, const doubl
                        n_src, q, qs, E.d_flags);
     stage_prepare(P, E, src, trg);
     stage_images(P, E, q);
+    // the far field's grid steps need only the sorted sources: they run on
+    // the plan's second stream beside the tree, lists and near field, and are
+    // joined before the interpolation (which adds into pot_sorted)
+    PDMK_HIP(hipEventRecord(fev[0], s));
+    PDMK_HIP(hipStreamWaitEvent(P->s_aux, fev[0], 0));
+    PDMK_HIP(hipEventRecord(fev[1], P->s_aux));
+    E.s = P->s_aux;
+    stage_far_grid(P, E);
+    E.s = s;
+    PDMK_HIP(hipEventRecord(fev[2], P->s_aux));
     stage_tree(P, E);
     stage_lists(P, E);
     PDMK_HIP(hipEventRecord(ev[1], s));
     stage_near(P, E, want_grad);
     PDMK_HIP(hipEventRecord(ev[2], s));
-    stage_far(P, E, q, want_grad);
+    PDMK_HIP(hipStreamWaitEvent(s, fev[2], 0));
+    stage_far_interp(P, E, want_grad);
     PDMK_HIP(hipEventRecord(ev[3], s));
     // uniform-background constant: the method with m = 0 dropped returns the
     // tin-foil potential plus (sum q) * Rhat_0(0) / V
@@ -566,12 +584,15 @@ static int eval_impl(pdmk_plan* P, int64_t n_src, const double* src, const doubl
     PDMK_HIP(hipEventRecord(ev[4], s));
     PDMK_HIP(hipEventSynchronize(ev[4]));
     near_finish(P, E);
-    float t1, t2, t3, t4;
+    float t1, t2, t3, t4, tg;
     PDMK_HIP(hipEventElapsedTime(&t1, ev[0], ev[1]));
     PDMK_HIP(hipEventElapsedTime(&t2, ev[1], ev[2]));
     PDMK_HIP(hipEventElapsedTime(&t3, ev[2], ev[3]));
     PDMK_HIP(hipEventElapsedTime(&t4, ev[0], ev[4]));
+    PDMK_HIP(hipEventElapsedTime(&tg, fev[1], fev[2]));
     for (auto& e : ev) (void)hipEventDestroy(e);
+    for (auto& e : fev) (void)hipEventDestroy(e);
+    t3 += tg;   // far field: grid steps (overlapped with the build and near field) + interpolation
     {
       double hq[2];
       int hf[2];
@@ -603,6 +624,7 @@ static int eval_impl(pdmk_plan* P, int64_t n_src, const double* src, const doubl
             .count();
   } catch (const Error& e) {
     (void)hipStreamSynchronize(s);
+    (void)hipStreamSynchronize(P->s_aux);   // far-field steps forked before the error
     ws.release_overflow();
     return fail(e.code, e.msg);
   }

@@ -631,7 +631,7 @@ void far_build_scale(pdmk_plan* P) {
   for (void* p : tmp) (void)hipFree(p);
 }
 
-void stage_far(pdmk_plan* P, Eval& E, const double* q, bool want_grad) {
+void stage_far_grid(pdmk_plan* P, Eval& E) {
   const Geometry& g = P->g;
   const int d = g.dim;
   int M[3] = {g.fgrid[0], g.fgrid[1], d == 3 ? g.fgrid[2] : 1};
@@ -640,13 +640,20 @@ void stage_far(pdmk_plan* P, Eval& E, const double* q, bool want_grad) {
   const double beta = P->nufft_beta;
   double* grid = E.alloc<double>(n);
   double2* cg = E.alloc<double2>(n);
+  E.far_grid = grid;
+  E.far_cg = cg;
   PDMK_HIP(hipMemsetAsync(grid, 0, n * sizeof(double), E.s));
-  spread_interp(P, E, M, w, beta, grid, cg, want_grad, true);
+  spread_interp(P, E, M, w, beta, grid, cg, false, true);
   hipLaunchKernelGGL(k_to_complex, dim3(nblk(n, 256)), dim3(256), 0, E.s, n, grid, cg);
   fft3(cg, M, d, -1, P->d_fftw, P->fftw_off, E.s);
   hipLaunchKernelGGL(k_scale, dim3(nblk(n, 256)), dim3(256), 0, E.s, n, cg, P->d_farscale);
   fft3(cg, M, d, +1, P->d_fftw, P->fftw_off, E.s);
-  spread_interp(P, E, M, w, beta, grid, cg, want_grad, false);
+}
+
+void stage_far_interp(pdmk_plan* P, Eval& E, bool want_grad) {
+  const Geometry& g = P->g;
+  int M[3] = {g.fgrid[0], g.fgrid[1], g.dim == 3 ? g.fgrid[2] : 1};
+  spread_interp(P, E, M, P->mp.nufft_w, P->nufft_beta, E.far_grid, E.far_cg, want_grad, false);
 }
 
 }  // namespace pdmk

@@ -154,6 +154,8 @@ struct Eval {
   // host buffer
   int* d_flags = nullptr;   // device {non-finite charge, non-finite position}
   bool near_pending = false;
+  double* far_grid = nullptr;   // spreading grid (real)
+  double2* far_cg = nullptr;    // its transform, scaled and transformed back
   bool pw_split = false;
   hipEvent_t near_ev[4] = {nullptr, nullptr, nullptr, nullptr};
   std::vector<std::array<hipEvent_t, 4>> pw_ev;
@@ -192,6 +194,9 @@ struct pdmk_plan {
   // residual pairs; [4..5] sum q,
   // sum |q| (FP64 bits); [6] the two input flags of Eval::d_flags
   unsigned long long* h_cnt = nullptr;
+  // second stream (default priority): the far field's grid steps run on it
+  // beside the tree, list and near-field stages of the same evaluation
+  hipStream_t s_aux = nullptr;
   size_t adj_size = 0;
   pdmk::KParams kp{};
   // device tables
@@ -254,7 +259,10 @@ void stage_images(pdmk_plan* P, Eval& E, const double* q);
 void stage_tree(pdmk_plan* P, Eval& E);
 void stage_lists(pdmk_plan* P, Eval& E);
 void stage_near(pdmk_plan* P, Eval& E, bool want_grad);
-void stage_far(pdmk_plan* P, Eval& E, const double* q, bool want_grad);
+// far field, steps one to four (spreading, transforms, scaling) on E.s, and
+// step five (interpolation, adds into pot_sorted) on E.s
+void stage_far_grid(pdmk_plan* P, Eval& E);
+void stage_far_interp(pdmk_plan* P, Eval& E, bool want_grad);
 void stage_assemble(pdmk_plan* P, Eval& E, const double* q, double* pot, double* grad);
 void plan_upload_tables(pdmk_plan* P);
 void far_build_scale(pdmk_plan* P);
