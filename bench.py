@@ -74,6 +74,8 @@ def parse():
                     help="skip the batched many-cell measurement")
     ap.add_argument("--batch-systems", type=int, default=512)
     ap.add_argument("--batch-steps", type=int, default=3)
+    ap.add_argument("--batch-workers", type=int, default=8,
+                    help="host workers of the batched measurement")
     ap.add_argument("--copy-calib", action="store_true",
                     help="only run a plain 1 GiB device copy (calibrates HBM byte counters)")
     return ap.parse_args()
@@ -279,7 +281,7 @@ def child_batch(args):
     q = torch.tensor(np.concatenate([s[2] for s in systems]), device="cuda:0")
     Ls = np.stack([s[0] for s in systems])
     t0 = time.perf_counter()
-    B = pdmk.Batch(Ls, eps=args.eps, precision=args.precision, workers=8)
+    B = pdmk.Batch(Ls, eps=args.eps, precision=args.precision, workers=args.batch_workers)
     t_plan = time.perf_counter() - t0
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -296,14 +298,15 @@ def child_batch(args):
     ms = 1e3 * sum(per) / len(per)
     print(json.dumps({"systems": len(systems), "particles": n, "ms_per_call": ms,
                       "value": n / (ms * 1e-3), "cold_first_call_ms": 1e3 * cold,
-                      "plan_create_s": t_plan, "precision": args.precision}))
+                      "plan_create_s": t_plan, "precision": args.precision,
+                      "workers": args.batch_workers}))
 
 
 def run_child(args, mode, batch=False):
     cmd = [sys.executable, os.path.abspath(__file__), "--child-batch" if batch else "--child",
            "--precision", mode, "--steps", str(args.batch_steps if batch else args.steps),
            "--warmup", str(args.warmup), "--n", str(args.n), "--eps", str(args.eps),
-           "--batch-systems", str(args.batch_systems)]
+           "--batch-systems", str(args.batch_systems), "--batch-workers", str(args.batch_workers)]
     if args.no_check:
         cmd.append("--no-check")
     if args.no_tune:

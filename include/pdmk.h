@@ -37,8 +37,9 @@
  *   - Calls are ordered on the HIP stream passed in (NULL = default stream)
  *     and block until the results are written (the call synchronises its
  *     stream before returning).  Inside a call, part of the work runs on a
- *     second, plan-owned stream (default priority) forked from and joined
- *     back to the caller's stream by events.
+ *     second stream (default priority; owned by the plan, created on its
+ *     first evaluation, or by the batch worker) forked from and joined back
+ *     to the caller's stream by events.
  *   - Errors: every function returns a pdmk_status.  On an error detected on
  *     the host the output arrays are not written.  pdmk_last_error() returns a
  *     thread-local message for the last failure.

@@ -427,7 +427,6 @@ int pdmk_plan_create(const pdmk_opts* opts, const double* L, pdmk_plan** out) {
     }
     far_build_scale(P);
     PDMK_HIP(hipHostMalloc((void**)&P->h_cnt, 8 * sizeof(unsigned long long)));
-    PDMK_HIP(hipStreamCreateWithFlags(&P->s_aux, hipStreamNonBlocking));
   } catch (const Error& e) {
     free_plan_tables(P);
     delete P;
@@ -501,9 +500,16 @@ int pdmk_plan_stats(const pdmk_plan* P, pdmk_stats* out) {
 
 // One evaluation; `flags` replaces the plan's flags (PDMK_ALLOW_NONNEUTRAL is
 // honoured, gradients are computed iff grad is not null).
+// Sources + targets from which a call runs the far field's grid steps on a
+// second stream.
+constexpr int64_t kForkMin = 1 << 18;
+
+// aux: the second stream of the call (null: the plan's own, created on first
+// use; a batch worker passes its own)
 static int eval_impl(pdmk_plan* P, int64_t n_src, const double* src, const double* q,
                      int64_t n_trg, const double* trg, double* pot, double* grad, void* stream,
-                     unsigned flags, char*& arena, size_t& arena_size) {
+                     unsigned flags, char*& arena, size_t& arena_size,
+                     hipStream_t aux = nullptr) {
   if (!P) return fail(PDMK_ERR_INVALID_ARG, "null plan");
   const int d = P->g.dim;
   const bool self_t = (trg == nullptr);
@@ -537,6 +543,15 @@ static int eval_impl(pdmk_plan* P, int64_t n_src, const double* src, const doubl
       PDMK_HIP(hipStreamSynchronize(s));
       return PDMK_OK;
     }
+    // the second stream pays off only for large inputs: for small ones the
+    // fork's events and the extra stream's share of the hardware queues cost
+    // more than the overlap (measured on batches of small cells)
+    const bool fork = n_src + n_trg >= kForkMin;
+    if (fork && !aux) {
+      if (!P->s_aux) PDMK_HIP(hipStreamCreateWithFlags(&P->s_aux, hipStreamNonBlocking));
+      aux = P->s_aux;
+    }
+    if (!fork) aux = s;
     hipEvent_t ev[5], fev[3];
     for (auto& e : ev) PDMK_HIP(hipEventCreate(&e));
     for (auto& e : fev) PDMK_HIP(hipEventCreate(&e));
@@ -556,19 +571,21 @@ static int eval_impl(pdmk_plan* P, int64_t n_src, const double* src, const doubl
     // the far field's grid steps need only the sorted sources: they run on
     // the plan's second stream beside the tree, lists and near field, and are
     // joined before the interpolation (which adds into pot_sorted)
-    PDMK_HIP(hipEventRecord(fev[0], s));
-    PDMK_HIP(hipStreamWaitEvent(P->s_aux, fev[0], 0));
-    PDMK_HIP(hipEventRecord(fev[1], P->s_aux));
-    E.s = P->s_aux;
+    if (fork) {
+      PDMK_HIP(hipEventRecord(fev[0], s));
+      PDMK_HIP(hipStreamWaitEvent(aux, fev[0], 0));
+    }
+    PDMK_HIP(hipEventRecord(fev[1], aux));
+    E.s = aux;
     stage_far_grid(P, E);
     E.s = s;
-    PDMK_HIP(hipEventRecord(fev[2], P->s_aux));
+    PDMK_HIP(hipEventRecord(fev[2], aux));
     stage_tree(P, E);
     stage_lists(P, E);
     PDMK_HIP(hipEventRecord(ev[1], s));
     stage_near(P, E, want_grad);
     PDMK_HIP(hipEventRecord(ev[2], s));
-    PDMK_HIP(hipStreamWaitEvent(s, fev[2], 0));
+    if (fork) PDMK_HIP(hipStreamWaitEvent(s, fev[2], 0));
     stage_far_interp(P, E, want_grad);
     PDMK_HIP(hipEventRecord(ev[3], s));
     // uniform-background constant: the method with m = 0 dropped returns the
@@ -624,7 +641,7 @@ static int eval_impl(pdmk_plan* P, int64_t n_src, const double* src, const doubl
             .count();
   } catch (const Error& e) {
     (void)hipStreamSynchronize(s);
-    (void)hipStreamSynchronize(P->s_aux);   // far-field steps forked before the error
+    if (aux) (void)hipStreamSynchronize(aux);   // far-field steps forked before the error
     ws.release_overflow();
     return fail(e.code, e.msg);
   }
@@ -714,6 +731,7 @@ struct pdmk_batch {
   int device = 0;
   std::vector<pdmk_plan*> plans;
   std::vector<hipStream_t> streams;
+  std::vector<hipStream_t> aux;   // each worker's second stream
   std::vector<char*> arenas;
   std::vector<size_t> arena_sizes;
 };
@@ -738,9 +756,11 @@ int pdmk_batch_create(const pdmk_opts* opts, int n_sys, const double* L, int n_w
     }
     const int nw = std::max(1, std::min(n_workers > 0 ? n_workers : 8, std::max(1, n_sys)));
     for (int w = 0; w < nw; ++w) {
-      hipStream_t st = nullptr;
+      hipStream_t st = nullptr, sa = nullptr;
       PDMK_HIP(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
       B->streams.push_back(st);
+      PDMK_HIP(hipStreamCreateWithFlags(&sa, hipStreamNonBlocking));
+      B->aux.push_back(sa);
       B->arenas.push_back(nullptr);
       B->arena_sizes.push_back(0);
     }
@@ -782,7 +802,7 @@ int pdmk_batch_eval(pdmk_batch* B, const int64_t* offsets, const double* src, co
       const int64_t o = offsets[sy], n = offsets[sy + 1] - offsets[sy];
       const int st = eval_impl(B->plans[sy], n, src + o * d, q + o, 0, nullptr, pot + o,
                                grad ? grad + o * d : nullptr, B->streams[w], B->o.flags,
-                               B->arenas[w], B->arena_sizes[w]);
+                               B->arenas[w], B->arena_sizes[w], B->aux[w]);
       if (st != PDMK_OK) {
         status[w] = st;
         msg[w] = g_last_error;
@@ -804,6 +824,7 @@ void pdmk_batch_destroy(pdmk_batch* B) {
   if (!B) return;
   for (pdmk_plan* P : B->plans) pdmk_plan_destroy(P);
   for (hipStream_t s : B->streams) (void)hipStreamDestroy(s);
+  for (hipStream_t s : B->aux) (void)hipStreamDestroy(s);
   for (char* a : B->arenas)
     if (a) (void)hipFree(a);
   delete B;

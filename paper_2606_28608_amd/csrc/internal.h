@@ -194,8 +194,8 @@ struct pdmk_plan {
   // residual pairs; [4..5] sum q,
   // sum |q| (FP64 bits); [6] the two input flags of Eval::d_flags
   unsigned long long* h_cnt = nullptr;
-  // second stream (default priority): the far field's grid steps run on it
-  // beside the tree, list and near-field stages of the same evaluation
+  // second stream (default priority, created on first use): the far field's
+  // grid steps run on it beside the tree, list and near-field stages
   hipStream_t s_aux = nullptr;
   size_t adj_size = 0;
   pdmk::KParams kp{};
