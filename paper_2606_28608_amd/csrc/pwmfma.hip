@@ -1262,7 +1262,11 @@ PwMfmaShape pw_mfma_shape(int p, int J, size_t rs, int kb) {
   if (!s.ok) return s;
   const int n = 2 * J + 1, kq = 4 * kb;
   const int k2p = (2 * p + kq - 1) / kq * kq, k2n = (2 * n + kq - 1) / kq * kq;
-  const size_t budget = 80 * 1024, hard = 150 * 1024;
+  // LDS budget per block: FP32 keeps two blocks per CU (80 KB); FP64 takes
+  // the largest slab groups that fit one block per CU (fewer groups, so
+  // fewer barriers and operand reloads; measured 7.5 -> 5.4 ms incoming,
+  // 5.5 -> 4.2 ms outgoing at p = 22, J = 16)
+  const size_t hard = 150 * 1024, budget = rs == 8 ? hard : 80 * 1024;
   auto out_lds = [&](int g) {
     return ((size_t)k2p * stride_b(align16(g * p), rs) +
             (size_t)align16(g * n) * stride_a(k2p)) * rs;
