@@ -61,7 +61,7 @@ struct Workspace {
 // Sources per work item of the leaf residual sums: a target leaf's source
 // list is cut into segments of this length, so that the cost of one block is
 // bounded by kDirectTgt x kDirectSeg pairs.
-constexpr int kDirectSeg = 2048;
+constexpr int kDirectSeg = 4096;
 // Targets per work item of the leaf residual sums (one 64-lane pass).
 constexpr int kDirectTgt = 64;
 
