@@ -28,14 +28,20 @@ constexpr double kInv2Pi = 0.15915494309189535;
 // tiles half empty.  Leaves with few targets split each tile over S lanes per
 // target (S = 1, 2, 4, 8) and reduce across those lanes at the end.  The pair
 // kernel is evaluated without branches and masked outside its support.
+// 1/sqrt(x) in FP64: the hardware estimate (measured on gfx950: relative
+// error below 2^-24) refined by NR Newton steps y <- y (3/2 - x y^2 / 2); one
+// step leaves a relative error below 1e-14, two reach full precision.
+template <int NR>
 __device__ inline double rsqrt_f64(double x) {
   double y = __builtin_amdgcn_rsq(x);
   double hx = 0.5 * x;
-  y = y * fma(-hx * y, y, 1.5);
-  y = y * fma(-hx * y, y, 1.5);
+#pragma unroll
+  for (int k = 0; k < NR; ++k) y = y * fma(-hx * y, y, 1.5);
   return y;
 }
-__device__ inline double rsqrt_r(double x) { return rsqrt_f64(x); }
+template <int NR>
+__device__ inline double rsqrt_r(double x) { return rsqrt_f64<NR>(x); }
+template <int NR>
 __device__ inline float rsqrt_r(float x) { return __builtin_amdgcn_rsqf(x); }
 __device__ inline double log_r(double x) { return log(x); }
 __device__ inline float log_r(float x) { return __logf(x); }
@@ -53,7 +59,7 @@ template <class Real> struct SlotQ;
 template <> struct SlotQ<float> { using T = float4; };
 template <> struct SlotQ<double> { using T = double4; };
 
-template <int D, int NE, bool GRAD, class Real>
+template <int D, int NE, bool GRAD, class Real, int NR>
 __device__ inline void residual_pair(const double* x, const double4& sv,
                                      const typename SlotQ<Real>::T& sq, const Real* ec,
                                      const Real* edc, Real& acc, Real* g, int& nin) {
@@ -89,7 +95,7 @@ __device__ inline void residual_pair(const double* x, const double4& sv,
       for (int m = NE - 2; m >= 0; --m) Fd = fma(Fd, u, edc[m]);
     }
     if (D == 3) {
-      const Real ir = rsqrt_r(r2);
+      const Real ir = rsqrt_r<NR>(r2);
       acc = fma(qs, fma(-F, ih, ir), acc);
       if (GRAD) {
         const Real dx[3] = {(Real)dd[0], (Real)dd[1], (Real)dd[2]};
@@ -174,7 +180,7 @@ struct SourceSlot {
 // per target, over the whole source list in tiles of 64 staged in LDS.  The
 // next tile's sources are fetched into registers while the current one is
 // summed.
-template <int D, int NE, int S, bool GRAD, class Real>
+template <int D, int NE, int S, bool GRAD, class Real, int NR>
 __device__ void direct_pass(const KParams& kp, const int4* __restrict__ list, int lb, int le,
                             int pos0, int pos1, const double* __restrict__ sx,
                             const double* __restrict__ sq,
@@ -201,8 +207,8 @@ __device__ void direct_pass(const KParams& kp, const int4* __restrict__ list, in
       // one lane per target: the whole tile unrolled (LDS reads at immediate offsets)
 #pragma unroll
       for (int k = 0; k < 64; k += 2) {
-        residual_pair<D, NE, GRAD, Real>(x, shv[k], shw[k], ec, edc, ta, ga, nin);
-        residual_pair<D, NE, GRAD, Real>(x, shv[k + 1], shw[k + 1], ec, edc, tb,
+        residual_pair<D, NE, GRAD, Real, NR>(x, shv[k], shw[k], ec, edc, ta, ga, nin);
+        residual_pair<D, NE, GRAD, Real, NR>(x, shv[k + 1], shw[k + 1], ec, edc, tb,
                                          gb, nin);
       }
     } else {
@@ -210,8 +216,8 @@ __device__ void direct_pass(const KParams& kp, const int4* __restrict__ list, in
 #pragma unroll 2
       for (int kk = 0; kk < 64; kk += 2 * S) {
         const int k = kk + slice;
-        residual_pair<D, NE, GRAD, Real>(x, shv[k], shw[k], ec, edc, ta, ga, nin);
-        residual_pair<D, NE, GRAD, Real>(x, shv[k + S], shw[k + S], ec, edc, tb,
+        residual_pair<D, NE, GRAD, Real, NR>(x, shv[k], shw[k], ec, edc, ta, ga, nin);
+        residual_pair<D, NE, GRAD, Real, NR>(x, shv[k + S], shw[k + S], ec, edc, tb,
                                          gb, nin);
       }
     }
@@ -235,7 +241,7 @@ __device__ void direct_pass(const KParams& kp, const int4* __restrict__ list, in
 // Positions are offsets from the target leaf's centre in FP64; Real = double:
 // FP64 throughout; Real = float: the series, rsqrt and the sums over one tile
 // of 64 sources in FP32, FP64 across tiles.
-template <int D, int NE, bool GRAD, class Real>
+template <int D, int NE, bool GRAD, class Real, int NR>
 __global__ __launch_bounds__(64) void k_direct(
     KParams kp, int nitems, const int2* __restrict__ items, const int* __restrict__ lf_nsrc,
     const Level* __restrict__ lev, const int* __restrict__ lf_level,
@@ -286,19 +292,19 @@ __global__ __launch_bounds__(64) void k_direct(
     int nin_p = 0;
     switch (S) {
       case 1:
-        direct_pass<D, NE, 1, GRAD, Real>(kp, list, lb, le, pos0, pos1, sx, sq, nimg, cT, x,
+        direct_pass<D, NE, 1, GRAD, Real, NR>(kp, list, lb, le, pos0, pos1, sx, sq, nimg, cT, x,
                                           ec, edc, shv, shw, acc, g, nin_p);
         break;
       case 2:
-        direct_pass<D, NE, 2, GRAD, Real>(kp, list, lb, le, pos0, pos1, sx, sq, nimg, cT, x,
+        direct_pass<D, NE, 2, GRAD, Real, NR>(kp, list, lb, le, pos0, pos1, sx, sq, nimg, cT, x,
                                           ec, edc, shv, shw, acc, g, nin_p);
         break;
       case 4:
-        direct_pass<D, NE, 4, GRAD, Real>(kp, list, lb, le, pos0, pos1, sx, sq, nimg, cT, x,
+        direct_pass<D, NE, 4, GRAD, Real, NR>(kp, list, lb, le, pos0, pos1, sx, sq, nimg, cT, x,
                                           ec, edc, shv, shw, acc, g, nin_p);
         break;
       default:
-        direct_pass<D, NE, 8, GRAD, Real>(kp, list, lb, le, pos0, pos1, sx, sq, nimg, cT, x,
+        direct_pass<D, NE, 8, GRAD, Real, NR>(kp, list, lb, le, pos0, pos1, sx, sq, nimg, cT, x,
                                           ec, edc, shv, shw, acc, g, nin_p);
         break;
     }
@@ -927,17 +933,23 @@ static void launch_direct_t(const KParams& kp, Eval& E, pdmk_plan* P, hipStream_
   const int off = sizeof(Real) == 4 ? 32 : 0;   // FP32 evaluation: the cut series
   const double* c = (D == 3 ? P->d_E : P->d_F2) + off;
   const double* cd = (D == 3 ? P->d_Ed : P->d_F2d) + off;
-  if (want_grad)
-    hipLaunchKernelGGL((k_direct<D, NE, true, Real>), dim3(E.nitems), dim3(64), 0, s, kp,
-                       E.nitems, E.items, E.lf_nsrc, E.d_lev, E.lf_level, E.lf_box, E.lf_list_beg, E.list, E.sx,
-                       E.sq, E.n_img, E.tx, E.n_trg, E.tperm, E.q, E.self_targets ? 1 : 0, c, cd,
-                       E.pot_sorted, E.grad_sorted, nsup);
-  else
-    hipLaunchKernelGGL((k_direct<D, NE, false, Real>), dim3(E.nitems), dim3(64), 0, s,
-                       kp,
-                       E.nitems, E.items, E.lf_nsrc, E.d_lev, E.lf_level, E.lf_box, E.lf_list_beg, E.list, E.sx,
-                       E.sq, E.n_img, E.tx, E.n_trg, E.tperm, E.q, E.self_targets ? 1 : 0, c, cd,
-                       E.pot_sorted, E.grad_sorted, nsup);
+  auto go = [&](auto kern) {
+    hipLaunchKernelGGL(kern, dim3(E.nitems), dim3(64), 0, s, kp, E.nitems, E.items, E.lf_nsrc,
+                       E.d_lev, E.lf_level, E.lf_box, E.lf_list_beg, E.list, E.sx, E.sq, E.n_img,
+                       E.tx, E.n_trg, E.tperm, E.q, E.self_targets ? 1 : 0, c, cd, E.pot_sorted,
+                       E.grad_sorted, nsup);
+  };
+  // FP64 3D: one Newton step of the reciprocal square root where eps >= 1e-10
+  // (its error, below 1e-14, is then far under the tolerance), two below
+  if constexpr (D == 3 && sizeof(Real) == 8) {
+    if (P->o.eps >= 1e-10) {
+      if (want_grad) go(k_direct<D, NE, true, Real, 1>);
+      else go(k_direct<D, NE, false, Real, 1>);
+      return;
+    }
+  }
+  if (want_grad) go(k_direct<D, NE, true, Real, 2>);
+  else go(k_direct<D, NE, false, Real, 2>);
 }
 
 template <int D, class Real>
