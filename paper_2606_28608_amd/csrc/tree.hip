@@ -184,23 +184,31 @@ __global__ void k_img_emit(KParams kp, int64_t n, const double* __restrict__ xs,
 // Targets that are the sources: the sorted targets are the unshifted copies
 // in the sorted images (equal coordinates give equal keys, and the stable
 // radix sort keeps both in source-index order among equal keys).
+// osrc[p]: source index of sorted image p if it is an unshifted copy, else -1
+// (read in sorted order by the pick below).
 __global__ void k_orig_flag(int64_t nimg, const int* __restrict__ perm,
-                            const int* __restrict__ isrc, int* __restrict__ flag) {
-  int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (p < nimg) flag[p] = isrc[perm[p]] >= 0 ? 1 : 0;
-}
-__global__ void k_orig_pick(int64_t nimg, int64_t n, int d, const int* __restrict__ perm,
-                            const int* __restrict__ isrc, const int* __restrict__ pos,
-                            const uint64_t* __restrict__ skey, const double* __restrict__ sx,
-                            uint64_t* __restrict__ tkey, double* __restrict__ tx,
-                            int* __restrict__ tperm) {
+                            const int* __restrict__ isrc, int* __restrict__ flag,
+                            int* __restrict__ osrc) {
   int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= nimg) return;
-  const int src = isrc[perm[p]];
+  const int s = isrc[perm[p]];
+  osrc[p] = s;
+  flag[p] = s >= 0 ? 1 : 0;
+}
+// Also the charges of the sorted originals (oq) from the sorted image charges.
+__global__ void k_orig_pick(int64_t nimg, int64_t n, int d, const int* __restrict__ osrc,
+                            const int* __restrict__ pos, const uint64_t* __restrict__ skey,
+                            const double* __restrict__ sx, const double* __restrict__ sq,
+                            uint64_t* __restrict__ tkey, double* __restrict__ tx,
+                            int* __restrict__ tperm, double* __restrict__ oq) {
+  int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= nimg) return;
+  const int src = osrc[p];
   if (src < 0) return;
   const int t = pos[p];
   tperm[t] = src;
   tkey[t] = skey[p];
+  oq[t] = sq[p];
   for (int a = 0; a < d; ++a) tx[a * n + t] = sx[a * nimg + p];
 }
 
@@ -328,15 +336,20 @@ void stage_images(pdmk_plan* P, Eval& E, const double* q) {
     E.tkey = E.alloc<uint64_t>(E.n_trg);
     E.tx = E.alloc<double>(E.n_trg * kp.dim);
     E.tperm = E.alloc<int>(E.n_trg);
+    E.ox = E.tx;
+    E.oq = E.alloc<double>(n);
     int* flag = E.alloc<int>(E.n_img + 1);
     int* pos = E.alloc<int>(E.n_img + 1);
+    int* osrc = E.alloc<int>(E.n_img + 1);
     if (E.n_img > 0) {
       hipLaunchKernelGGL(k_orig_flag, dim3(nblk(E.n_img, 256)), dim3(256), 0, E.s, E.n_img,
-                         perm, isrc, flag);
+                         perm, isrc, flag, osrc);
       exclusive_scan_int(flag, pos, (int)E.n_img, E);
       hipLaunchKernelGGL(k_orig_pick, dim3(nblk(E.n_img, 256)), dim3(256), 0, E.s, E.n_img,
-                         E.n_trg, kp.dim, perm, isrc, pos, E.skey, E.sx, E.tkey, E.tx, E.tperm);
+                         E.n_trg, kp.dim, osrc, pos, E.skey, E.sx, E.sq, E.tkey, E.tx, E.tperm,
+                         E.oq);
     }
+    return;   // original sources in tree order: the picked copies
   } else {
     double* dummyq = nullptr;
     sort_points(P, E, E.n_trg, E.xt, nullptr, E.tkey, E.tx, dummyq, E.tperm);
