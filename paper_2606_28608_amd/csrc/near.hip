@@ -1105,6 +1105,9 @@ static void near_impl(pdmk_plan* P, Eval& E, bool want_grad) {
   // proxies
   int maxnl = 0;
   for (int l = 0; l < nlev; ++l) maxnl = std::max(maxnl, E.lev[l].nnl);
+  // matrix-core plane waves: the incoming kernel writes every proxy potential
+  // (zeros for boxes without targets), so only the other paths clear them
+  const bool mfma = D == 3 && P->pw_mfma && pw_mfma_shape(p, J, sizeof(Real)).ok;
   for (int l = 0; l < nlev; ++l) {
     Level& L = E.lev[l];
     if (L.nnl == 0) continue;
@@ -1112,7 +1115,11 @@ static void near_impl(pdmk_plan* P, Eval& E, bool want_grad) {
     // rows past the last tensor entry
     L.proxy_q = E.alloc<Real>((size_t)L.nnl * pD + 64);
     L.proxy_phi = E.alloc<Real>((size_t)L.nnl * pD + 64);
-    PDMK_HIP(hipMemsetAsync(L.proxy_phi, 0, sizeof(Real) * ((size_t)L.nnl * pD + 64), s));
+    if (mfma)
+      PDMK_HIP(hipMemsetAsync(static_cast<Real*>(L.proxy_phi) + (size_t)L.nnl * pD, 0,
+                              sizeof(Real) * 64, s));
+    else
+      PDMK_HIP(hipMemsetAsync(L.proxy_phi, 0, sizeof(Real) * ((size_t)L.nnl * pD + 64), s));
   }
   if (maxnl > 0) {
     // upward pass
@@ -1130,7 +1137,6 @@ static void near_impl(pdmk_plan* P, Eval& E, bool want_grad) {
     const size_t lds_out = lds_pw_out(p, J, sizeof(Real));
     const size_t lds_in = lds_pw_in(p, J, sizeof(Real));
     const bool fused = D == 3 && lds_out <= 150 * 1024 && lds_in <= 150 * 1024;
-    const bool mfma = D == 3 && P->pw_mfma && pw_mfma_shape(p, J, sizeof(Real)).ok;
     // matrix-core path: outgoing and translated incoming expansions in compact
     // half-ball order; vector-ALU path: outgoing expansions on the full grid
     C* bS = E.alloc<C>((size_t)maxnl * (mfma ? P->nball : s3));

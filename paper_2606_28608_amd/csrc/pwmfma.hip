@@ -444,7 +444,13 @@ __global__ __launch_bounds__(256, sizeof(Real) == 4 ? 2 : 1) void k_pw_in_mfma(
   extern __shared__ __align__(16) unsigned char smraw[];
   const int k = blockIdx.x;
   const int b = L.nl_box[k];
-  if (L.tend[b] <= L.tbeg[b]) return;   // no targets below this box
+  if (L.tend[b] <= L.tbeg[b]) {
+    // no targets below this box: its proxy potential is zero, written here so
+    // that the output needs no clearing beforehand
+    Real* out = Phi + (int64_t)k * P * PP;
+    for (int e = threadIdx.x; e < P * PP; e += 256) out[e] = 0;
+    return;
+  }
   Real* I = reinterpret_cast<Real*>(smraw);      // align16(G N1) rows x sI: cols 2 j2 + ri
   Real* Y = I + align16(G * N1) * sI;            // K2N rows x sY: rows 2 j1 + ri, cols (jj, c)
   Real* W = Y + SH::K2N * sY;                    // align(2G, 4 KB) rows x sW: cols (b, c)
@@ -625,7 +631,7 @@ __global__ __launch_bounds__(256, sizeof(Real) == 4 ? 2 : 1) void k_pw_in_mfma(
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
           const int a = 16 * m + MF::row(lane, r);
-          if (a < P) out[a * PP + bc] += acc[m][i][r];
+          if (a < P) out[a * PP + bc] = acc[m][i][r];
         }
   }
 }
