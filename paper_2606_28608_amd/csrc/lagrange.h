@@ -30,19 +30,21 @@ __device__ inline void lagrange_rows(int p, const double* __restrict__ nodes,
   }
 }
 
-// 1/d from the hardware reciprocal estimate refined by two Newton steps
-// (r <- r + r (1 - d r)); each step squares the relative error, so the result
-// is within a few units in the last place of the correctly rounded quotient.
+// 1/d from the hardware reciprocal estimate refined by NR Newton steps
+// (r <- r + r (1 - d r)); each step squares the relative error: two leave the
+// result within a few units in the last place of the correctly rounded
+// quotient, one is ample for rows that are rounded to FP32.
+template <int NR = 2>
 __device__ inline double recip_nr(double d) {
   double r = __builtin_amdgcn_rcp(d);
-  r = fma(r, fma(-d, r, 1.0), r);
-  r = fma(r, fma(-d, r, 1.0), r);
+#pragma unroll
+  for (int k = 0; k < NR; ++k) r = fma(r, fma(-d, r, 1.0), r);
   return r;
 }
 
 // Same as lagrange_rows with compile-time capacity PMAX (entries >= p are 0),
-// so the rows stay in registers.
-template <int PMAX, bool DER>
+// so the rows stay in registers; NR Newton steps per reciprocal.
+template <int PMAX, bool DER, int NR = 2>
 __device__ inline void lagrange_rows_reg(int p, const double* __restrict__ nodes,
                                          const double* __restrict__ bw, double x,
                                          double (&row)[PMAX], double (&drow)[PMAX]) {
@@ -54,7 +56,7 @@ __device__ inline void lagrange_rows_reg(int p, const double* __restrict__ nodes
 #pragma unroll
   for (int m = 0; m < PMAX; ++m) {
     if (m < p) {
-      inv[m] = recip_nr(x - nodes[m]);
+      inv[m] = recip_nr<NR>(x - nodes[m]);
       const double t = bw[m] * inv[m];
       row[m] = t;
       s += t;

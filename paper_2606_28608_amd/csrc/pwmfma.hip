@@ -737,7 +737,7 @@ __global__ __launch_bounds__(256) void k_eval_leaf_mfma(
       const double cen = kp.origin[a] + (Lp.coord[Pb * 3 + a] + 0.5) * hP;
       const double xi = valid ? (tx[a * ntrg + t] - cen) * sc : 0.0;
       double rl[P], dl[P];
-      lagrange_rows_reg<P, GRAD>(P, nodes, bw, xi, rl, dl);
+      lagrange_rows_reg<P, GRAD, sizeof(Real) == 4 ? 1 : 2>(P, nodes, bw, xi, rl, dl);
 #pragma unroll
       for (int i = 0; i < P; ++i) {
         const Real v = valid ? (Real)rl[i] : (Real)0;
@@ -988,7 +988,7 @@ __global__ __launch_bounds__(256, sizeof(Real) == 4 ? 3 : 1) void k_anterp_mfma(
       const double xi = valid ? (sx[a * nimg + sidx] - cen) * sc : 0.0;
       const double qs = (valid && a == 0) ? sq[sidx] : 1.0;
       double rl[P], dl[P];
-      lagrange_rows_reg<P, false>(P, nodes, bw, xi, rl, dl);
+      lagrange_rows_reg<P, false, sizeof(Real) == 4 ? 1 : 2>(P, nodes, bw, xi, rl, dl);
 #pragma unroll
       for (int i = 0; i < P; ++i) {
         const Real v = valid ? (Real)(a == 0 ? qs * rl[i] : rl[i]) : (Real)0;
