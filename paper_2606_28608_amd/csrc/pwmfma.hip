@@ -920,9 +920,9 @@ template bool eval_leaf_mfma<double>(const pdmk_plan*, const Level&, const Level
 // Proxy charges of a non-leaf box from the sources of its childless children
 // (3D): Q[i0][i1][i2] = sum_s q_s l_i0(xi_0) l_i1(xi_1) l_i2(xi_2), i.e. the
 // product (q l_i0 l_i1)[(i0,i1)][s] x l_i2[s][i2] over the sources, on MFMA
-// tiles with the sources in chunks of 64 in FP32 (3 x 64 threads form a
-// chunk's Lagrange rows), 32 in FP64.  One block of 4 waves per box; each
-// wave owns the same M-tiles of Q for every chunk (accumulators in registers).
+// tiles with the sources in chunks of 64 (3 x 64 threads form a chunk's
+// Lagrange rows).  One block of 4 waves per box; each wave owns the same
+// M-tiles of Q for every chunk (accumulators in registers).
 template <class Real, int P>
 __global__ __launch_bounds__(256, sizeof(Real) == 4 ? 3 : 1) void k_anterp_mfma(KParams kp, Level L, Level C, int lvl,
                                                      const double* __restrict__ sx,
@@ -933,7 +933,7 @@ __global__ __launch_bounds__(256, sizeof(Real) == 4 ? 3 : 1) void k_anterp_mfma(
                                                      Real* __restrict__ Q) {
   using MF = Mfma<Real>;
   using V = typename MF::V;
-  constexpr int PP = P * P, SL = P | 1, CH = sizeof(Real) == 4 ? 64 : 32, NT = (P + 15) / 16, NW = 16 * NT;
+  constexpr int PP = P * P, SL = P | 1, CH = 64, NT = (P + 15) / 16, NW = 16 * NT;
   constexpr int MT = (PP + 15) / 16, MW = (MT + 3) / 4;
   __shared__ Real qLx[CH * SL], Ly[CH * SL], Lz[CH * NW];
   __shared__ int cb[8], cpre[9];
