@@ -144,8 +144,6 @@ struct Eval {
   int nitems = 0;
   double* pot_sorted = nullptr;   // near field per sorted target
   double* grad_sorted = nullptr;
-  double* far_pot = nullptr;      // far field per original target
-  double* far_grad = nullptr;
   pdmk_stats st{};
   // near-field timing and counters, read once the call's stream has finished
   // (no host wait inside the pipeline): events e0..e3 around residual sums,
