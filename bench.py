@@ -74,6 +74,8 @@ def parse():
                     help="skip the batched many-cell measurement")
     ap.add_argument("--batch-systems", type=int, default=512)
     ap.add_argument("--batch-steps", type=int, default=3)
+    ap.add_argument("--no-batch-tune", action="store_true",
+                    help="skip the batch autotuner (per-size-class kappa, n_s)")
     ap.add_argument("--batch-workers", type=int, default=8,
                     help="host workers of the batched measurement")
     ap.add_argument("--copy-calib", action="store_true",
@@ -296,10 +298,27 @@ def child_batch(args):
         per.append(time.perf_counter() - t1)
     n = int(offs[-1])
     ms = 1e3 * sum(per) / len(per)
-    print(json.dumps({"systems": len(systems), "particles": n, "ms_per_call": ms,
-                      "value": n / (ms * 1e-3), "cold_first_call_ms": 1e3 * cold,
-                      "plan_create_s": t_plan, "precision": args.precision,
-                      "workers": args.batch_workers}))
+    res = {"systems": len(systems), "particles": n, "ms_per_call": ms,
+           "value": n / (ms * 1e-3), "cold_first_call_ms": 1e3 * cold,
+           "plan_create_s": t_plan, "precision": args.precision,
+           "workers": args.batch_workers}
+    if not args.no_batch_tune:
+        # batch autotuner: (kappa, n_s) per size class, then the same timing
+        t0 = time.perf_counter()
+        k, ns = B.tune(offs, src, q, trials=3)
+        res["tune_s"] = time.perf_counter() - t0
+        B.eval(offs, src, q)
+        per = []
+        for _ in range(args.steps):
+            t1 = time.perf_counter()
+            B.eval(offs, src, q)
+            per.append(time.perf_counter() - t1)
+        ms_t = 1e3 * sum(per) / len(per)
+        res.update({"untuned_ms_per_call": ms, "ms_per_call": ms_t, "value": n / (ms_t * 1e-3),
+                    "tuned_plans": {"%g,%d" % (r[0], r[1]): int(c) for r, c in
+                                    zip(*np.unique(np.stack([k, ns.astype(np.float64)], 1),
+                                                   axis=0, return_counts=True))}})
+    print(json.dumps(res))
 
 
 def run_child(args, mode, batch=False):
@@ -307,6 +326,8 @@ def run_child(args, mode, batch=False):
            "--precision", mode, "--steps", str(args.batch_steps if batch else args.steps),
            "--warmup", str(args.warmup), "--n", str(args.n), "--eps", str(args.eps),
            "--batch-systems", str(args.batch_systems), "--batch-workers", str(args.batch_workers)]
+    if args.no_batch_tune:
+        cmd.append("--no-batch-tune")
     if args.no_check:
         cmd.append("--no-check")
     if args.no_tune:

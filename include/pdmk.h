@@ -183,6 +183,33 @@ int pdmk_eval_batched(const pdmk_opts* opts, int n_sys, const double* L,
                       double* pot, double* grad, void* stream);
 
 /*
+ * Batch autotuner (the run-time choice of (kappa, n_s) that Section 5 leaves
+ * for later, per size class of a batch).  The systems of `batch` with n > 0
+ * sources are grouped by floor(log2 n);
+ * for each class and candidate (kappa[i], n_s[i]) (<= 0: the batch's value),
+ * up to n_workers systems spread evenly over the class's sizes are planned
+ * and evaluated concurrently, one per worker stream as in pdmk_batch_eval:
+ * one warm-up round and `trials` (>= 1) timed rounds, outputs discarded.
+ * Every system of the class is then re-planned with the candidate of the
+ * shortest rounds.  Any
+ * (kappa, n_s) is a valid plan (the split of Section 3 is exact for any
+ * tree), so tuning changes speed, not the tolerance.  offsets, src, q: as for
+ * pdmk_batch_eval (offsets HOST, src and q DEVICE); the call synchronises
+ * `stream` first.  kappa_out, n_s_out: HOST arrays of n_sys entries or NULL;
+ * they receive each system's plan parameters after tuning (systems with no
+ * sources keep their plan).  Blocks; allocates device buffers for the
+ * sampled systems' outputs for the duration of the call.  Errors:
+ * PDMK_ERR_INVALID_ARG for null arguments, n_cand < 1, trials < 1 or
+ * decreasing offsets; the first planning error of a class none of whose
+ * candidates could be planned; evaluation errors (for instance a
+ * non-neutral system) at once.  After an error the batch stays usable:
+ * classes tuned before it keep their new plans, the others their old ones.
+ */
+int pdmk_batch_tune(pdmk_batch* batch, const int64_t* offsets, const double* src,
+                    const double* q, int n_cand, const double* kappa, const int* n_s,
+                    int trials, void* stream, double* kappa_out, int* n_s_out);
+
+/*
  * Runtime planning of the method's two free parameters, the root-cube side
  * r_c = L_min / kappa and the leaf capacity n_s (Section 5; the paper leaves
  * planning them at run time for later).  Each candidate (kappa[i], n_s[i])

@@ -1,7 +1,9 @@
 // C interface (include/pdmk.h): plans, evaluation pipeline of Algorithm 1,
 // assembly with the self-interaction correction (Section 3.8), status codes.
 #include <cmath>
+#include <algorithm>
 #include <atomic>
+#include <map>
 #include <thread>
 #include <chrono>
 #include <cstdlib>
@@ -730,6 +732,7 @@ struct pdmk_batch {
   pdmk_opts o{};
   int device = 0;
   std::vector<pdmk_plan*> plans;
+  std::vector<double> L;          // lattices, d x d per system (column-major)
   std::vector<hipStream_t> streams;
   std::vector<hipStream_t> aux;   // each worker's second stream
   std::vector<char*> arenas;
@@ -743,6 +746,7 @@ int pdmk_batch_create(const pdmk_opts* opts, int n_sys, const double* L, int n_w
   if (d != 2 && d != 3) return fail(PDMK_ERR_INVALID_ARG, "dim must be 2 or 3");
   pdmk_batch* B = new pdmk_batch;
   B->o = *opts;
+  B->L.assign(L, L + (size_t)n_sys * d * d);
   try {
     PDMK_HIP(hipGetDevice(&B->device));
     for (int sy = 0; sy < n_sys; ++sy) {
@@ -880,6 +884,155 @@ int pdmk_plan_tune(const pdmk_opts* opts, const double* L, int n_cand, const dou
     }
   }
   if (best < 0) return fail(first_err, first_msg);
+  return PDMK_OK;
+}
+
+// Batch autotuner: systems are grouped by size class floor(log2 n).  For
+// each class and candidate (kappa, n_s), up to one system per worker, spread
+// evenly over the class's sizes, is planned and evaluated concurrently by the
+// batch's workers, one system per worker stream, as the batch itself runs;
+// the candidate with the shortest round is kept and every system of the class
+// is re-planned with it.  Small cells are bound by launch and host-read
+// latency shared among the workers, which a lone evaluation does not show.
+int pdmk_batch_tune(pdmk_batch* B, const int64_t* offsets, const double* src, const double* q,
+                    int n_cand, const double* kappa, const int* n_s, int trials, void* stream,
+                    double* kappa_out, int* n_s_out) {
+  if (!B || !offsets || !kappa || !n_s || n_cand < 1 || trials < 1)
+    return fail(PDMK_ERR_INVALID_ARG, "null argument, n_cand < 1 or trials < 1");
+  const int n_sys = (int)B->plans.size();
+  const int d = B->o.dim;
+  for (int sy = 0; sy < n_sys; ++sy)
+    if (offsets[sy + 1] < offsets[sy]) return fail(PDMK_ERR_INVALID_ARG, "offsets decrease");
+  if (offsets[n_sys] > offsets[0] && (!src || !q))
+    return fail(PDMK_ERR_INVALID_ARG, "null array");
+  if (hipSetDevice(B->device) != hipSuccess) return fail(PDMK_ERR_HIP, "hipSetDevice failed");
+  if (hipStreamSynchronize((hipStream_t)stream) != hipSuccess)
+    return fail(PDMK_ERR_HIP, "stream synchronise failed");
+  const int nw = (int)B->streams.size();
+  std::map<int, std::vector<int>> cls;
+  for (int sy = 0; sy < n_sys; ++sy) {
+    const int64_t n = offsets[sy + 1] - offsets[sy];
+    if (n <= 0) continue;
+    int c = 0;
+    while ((2ll << c) <= n) ++c;
+    cls[c].push_back(sy);
+  }
+  const bool want_grad = (B->o.flags & PDMK_WANT_GRAD) != 0;
+  int status = PDMK_OK;
+  std::string msg;
+  std::vector<double*> buf(nw, nullptr);   // each worker's outputs (discarded)
+  std::vector<size_t> buf_n(nw, 0);
+  for (auto& kv : cls) {
+    std::vector<int>& mem = kv.second;
+    std::sort(mem.begin(), mem.end(), [&](int a, int b) {
+      return offsets[a + 1] - offsets[a] < offsets[b + 1] - offsets[b];
+    });
+    const int ns = std::min<int>(nw, (int)mem.size());
+    std::vector<int> sample(ns);
+    for (int i = 0; i < ns; ++i) sample[i] = mem[(size_t)(2 * i + 1) * mem.size() / (2 * ns)];
+    for (int i = 0; i < ns && status == PDMK_OK; ++i) {
+      const size_t need = (size_t)(offsets[sample[i] + 1] - offsets[sample[i]]) *
+                          (want_grad ? d + 1 : 1);
+      if (need > buf_n[i]) {
+        if (buf[i]) (void)hipFree(buf[i]);
+        buf[i] = nullptr;
+        buf_n[i] = 0;
+        if (hipMalloc((void**)&buf[i], sizeof(double) * need) != hipSuccess) {
+          status = PDMK_ERR_OUT_OF_MEMORY;
+          msg = "tuning buffer";
+        } else {
+          buf_n[i] = need;
+        }
+      }
+    }
+    if (status != PDMK_OK) break;
+    double best = -1.0, bk = 0.0;
+    int bn = 0, first_err = PDMK_OK;
+    std::string first_msg;
+    for (int c = 0; c < n_cand && status == PDMK_OK; ++c) {
+      pdmk_opts o = B->o;
+      if (kappa[c] > 0) o.kappa = kappa[c];
+      if (n_s[c] > 0) o.n_s = n_s[c];
+      std::vector<pdmk_plan*> P(ns, nullptr);
+      int st = PDMK_OK;
+      for (int i = 0; i < ns && st == PDMK_OK; ++i)
+        st = pdmk_plan_create(&o, B->L.data() + (size_t)sample[i] * d * d, &P[i]);
+      if (st != PDMK_OK) {
+        if (first_err == PDMK_OK) {
+          first_err = st;
+          first_msg = g_last_error;
+        }
+        for (pdmk_plan* p : P) pdmk_plan_destroy(p);
+        continue;
+      }
+      std::vector<int> wst(ns, PDMK_OK);
+      std::vector<std::string> wmsg(ns);
+      auto one = [&](int i) {
+        if (hipSetDevice(B->device) != hipSuccess) {
+          wst[i] = PDMK_ERR_HIP;
+          wmsg[i] = "hipSetDevice failed";
+          return;
+        }
+        const int sy = sample[i];
+        const int64_t o0 = offsets[sy], n = offsets[sy + 1] - offsets[sy];
+        int r = eval_impl(P[i], n, src + o0 * d, q + o0, 0, nullptr, buf[i],
+                          want_grad ? buf[i] + n : nullptr, B->streams[i], B->o.flags,
+                          B->arenas[i], B->arena_sizes[i], B->aux[i]);
+        if (r == PDMK_OK && hipStreamSynchronize(B->streams[i]) != hipSuccess)
+          r = fail(PDMK_ERR_HIP, "stream synchronise failed");
+        wst[i] = r;
+        if (r != PDMK_OK) wmsg[i] = g_last_error;
+      };
+      double ms = 0.0;
+      for (int t = 0; t <= trials && st == PDMK_OK; ++t) {   // t = 0: warm-up
+        const auto t0 = std::chrono::steady_clock::now();
+        std::vector<std::thread> th;
+        for (int i = 1; i < ns; ++i) th.emplace_back(one, i);
+        one(0);
+        for (auto& x : th) x.join();
+        if (t > 0)
+          ms += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0)
+                    .count();
+        for (int i = 0; i < ns && st == PDMK_OK; ++i)
+          if (wst[i] != PDMK_OK) {
+            st = wst[i];
+            msg = wmsg[i];
+          }
+      }
+      if (st == PDMK_OK && (best < 0 || ms < best)) {
+        best = ms;
+        bk = P[0]->mp.kappa;
+        bn = P[0]->mp.n_s;
+      }
+      for (pdmk_plan* p : P) pdmk_plan_destroy(p);
+      if (st != PDMK_OK) status = st;   // an input error: the same for every candidate
+    }
+    if (status != PDMK_OK) break;
+    if (best < 0) {
+      status = first_err;
+      msg = first_msg;
+      break;
+    }
+    for (int sy : mem) {
+      pdmk_plan*& cur = B->plans[sy];
+      if (cur->mp.kappa == bk && cur->mp.n_s == bn) continue;
+      pdmk_opts o = B->o;
+      o.kappa = bk;
+      o.n_s = bn;
+      pdmk_plan* P = nullptr;
+      if (pdmk_plan_create(&o, B->L.data() + (size_t)sy * d * d, &P) != PDMK_OK)
+        continue;   // this cell keeps its current (valid) plan
+      pdmk_plan_destroy(cur);
+      cur = P;
+    }
+  }
+  for (double* b : buf)
+    if (b) (void)hipFree(b);
+  for (int sy = 0; sy < n_sys; ++sy) {
+    if (kappa_out) kappa_out[sy] = B->plans[sy]->mp.kappa;
+    if (n_s_out) n_s_out[sy] = B->plans[sy]->mp.n_s;
+  }
+  if (status != PDMK_OK) return fail(status, msg);
   return PDMK_OK;
 }
 

@@ -109,6 +109,9 @@ def lib():
         L.pdmk_batch_destroy.argtypes = [_vp]
         L.pdmk_batch_destroy.restype = None
         L.pdmk_batch_stats.argtypes = [_vp, ctypes.c_int, ctypes.POINTER(Stats)]
+        L.pdmk_batch_tune.argtypes = [_vp, ctypes.POINTER(ctypes.c_int64), _vp, _vp, ctypes.c_int,
+                                      _dp, ctypes.POINTER(ctypes.c_int), ctypes.c_int, _vp, _dp,
+                                      ctypes.POINTER(ctypes.c_int)]
         L.pdmk_plan_tune.argtypes = [ctypes.POINTER(Opts), _dp, ctypes.c_int, _dp,
                                      ctypes.POINTER(ctypes.c_int), ctypes.c_int, ctypes.c_int64,
                                      _vp, _vp, ctypes.c_int64, _vp, _vp, _vp, _dp, _dp,
@@ -393,6 +396,36 @@ class Batch:
         s = Stats()
         _check(lib().pdmk_batch_stats(self._h, int(sys), ctypes.byref(s)))
         return s.as_dict()
+
+    def tune(self, offsets, src, q, candidates=None, trials=2):
+        """Batch autotuner (pdmk_batch_tune): per size class floor(log2 n), times
+        each (kappa, n_s) candidate on a sample of the class evaluated
+        concurrently by the batch's workers and re-plans the class with the
+        fastest.  Default candidates: kappa in {1, 2, 3} with
+        the default leaf capacity times {1, 2, 4}.  Returns host arrays of each
+        system's (kappa, n_s) after tuning."""
+        import torch
+        off = np.ascontiguousarray(offsets, dtype=np.int64)
+        if off.shape != (self.n_sys + 1,):
+            raise ValueError("offsets must have n_sys + 1 entries")
+        src = _dev(src, torch)
+        q = _dev(q, torch)
+        if off[-1] != src.shape[0] or q.shape != (src.shape[0],):
+            raise ValueError("offsets do not match the arrays")
+        if candidates is None:
+            base = self.opts.n_s
+            candidates = [(k, base * f) for k in (1.0, 2.0, 3.0) for f in (1, 2, 4)]
+        kap = np.array([float(c[0]) for c in candidates], dtype=np.float64)
+        nss = (ctypes.c_int * len(candidates))(*[int(c[1]) for c in candidates])
+        k_out = np.zeros(self.n_sys, dtype=np.float64)
+        n_out = np.zeros(self.n_sys, dtype=np.int32)
+        _check(lib().pdmk_batch_tune(self._h, off.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                                     ctypes.c_void_p(src.data_ptr()),
+                                     ctypes.c_void_p(q.data_ptr()), len(candidates),
+                                     kap.ctypes.data_as(_dp), nss, int(trials), _stream(torch),
+                                     k_out.ctypes.data_as(_dp),
+                                     n_out.ctypes.data_as(ctypes.POINTER(ctypes.c_int))))
+        return k_out, n_out
 
 
 def _autograd_fn():

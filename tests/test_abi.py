@@ -215,3 +215,19 @@ def test_plan_tune_argument_errors(lib):
                                 kap.ctypes.data_as(dp), ns, trials, 10, None, None, 10, None,
                                 None, None, None, ctypes.byref(bk), ctypes.byref(bn))
         assert st == -1
+
+
+def test_batch_tune_argument_errors(lib):
+    """pdmk_batch_tune rejects a null batch, no candidates or no trials before
+    touching a device."""
+    import ctypes
+    off = np.array([0, 10], dtype=np.int64)
+    kap = np.array([3.0])
+    ns = (ctypes.c_int * 1)(200)
+    dp = ctypes.POINTER(ctypes.c_double)
+    ip = ctypes.POINTER(ctypes.c_int64)
+    for n_cand, trials in ((1, 1), (0, 1), (1, 0)):
+        st = lib.pdmk_batch_tune(None, off.ctypes.data_as(ip), None, None, n_cand,
+                                 kap.ctypes.data_as(dp), ns, trials, None, None, None)
+        assert st == -1
+    assert b"null argument" in lib.pdmk_last_error()

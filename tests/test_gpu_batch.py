@@ -88,3 +88,43 @@ def test_batch_errors_and_empty(pdmk, torch_dev, systems):
     assert pot.shape == (n,)
     with pytest.raises(ValueError):
         B.eval(offs[:-1], torch.tensor(src, device=dev), torch.tensor(q, device=dev))
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_batch_tune_matches_oracle(pdmk, torch_dev, systems, precision):
+    """The batch autotuner re-plans each size class with its fastest (kappa,
+    n_s) among the candidates; every tuned system still meets eps against the
+    oracle, and the reported parameters are among the candidates."""
+    torch, dev = torch_dev
+    sy, refs = systems
+    Ls, offs, src, q = _pack(sy)
+    B = pdmk.Batch(Ls, eps=1e-6, precision=precision, workers=3)
+    s_d, q_d = torch.tensor(src, device=dev), torch.tensor(q, device=dev)
+    cands = [(1.0, 60), (2.0, 30), (3.0, 400)]
+    k, n = B.tune(offs, s_d, q_d, candidates=cands, trials=1)
+    assert set(zip(k.tolist(), n.tolist())) <= set(cands)
+    pot = B.eval(offs, s_d, q_d).cpu().numpy()
+    for s, ref in enumerate(refs):
+        got = pot[offs[s]:offs[s + 1]]
+        assert ewald.rel_l2(got, ref) <= 1e-6, (s, k[s], n[s], ewald.rel_l2(got, ref))
+
+
+def test_batch_tune_gradients_and_empty_system(pdmk, torch_dev, systems):
+    """Tuning a gradient batch that holds a system without sources: the empty
+    system keeps its plan, the others' gradients still match the oracle's."""
+    torch, dev = torch_dev
+    sy, _ = systems
+    sy = [sy[0], (sy[1][0], sy[1][1][:0], sy[1][2][:0]), sy[2]]
+    Ls, offs, src, q = _pack(sy)
+    B = pdmk.Batch(Ls, eps=1e-6, grad=True, workers=2)
+    s_d, q_d = torch.tensor(src, device=dev), torch.tensor(q, device=dev)
+    k, n = B.tune(offs, s_d, q_d, candidates=[(2.0, 30), (1.0, 200)], trials=1)
+    base = pdmk.default_opts(3, 1e-6)
+    assert (k[1], n[1]) == (base.kappa, base.n_s)
+    pot, g = B.eval(offs, s_d, q_d)
+    pot, g = pot.cpu().numpy(), g.cpu().numpy()
+    for s in (0, 2):
+        L, x, qq = sy[s]
+        ref_p, ref_g = ewald.ewald(L, x, qq, grad=True)
+        assert ewald.rel_l2(pot[offs[s]:offs[s + 1]], ref_p) <= 1e-6
+        assert ewald.rel_l2(g[offs[s]:offs[s + 1]], ref_g) <= 1e-5, s
