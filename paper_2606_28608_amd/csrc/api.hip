@@ -793,6 +793,12 @@ int pdmk_batch_eval(pdmk_batch* B, const int64_t* offsets, const double* src, co
   const int nw = (int)B->streams.size();
   std::vector<int> status(nw, PDMK_OK);
   std::vector<std::string> msg(nw);
+  // largest cells first, so that no worker starts a large cell near the end
+  std::vector<int> order(n_sys);
+  for (int sy = 0; sy < n_sys; ++sy) order[sy] = sy;
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+    return offsets[a + 1] - offsets[a] > offsets[b + 1] - offsets[b];
+  });
   std::atomic<int> next(0);
   auto work = [&](int w) {
     if (hipSetDevice(B->device) != hipSuccess) {
@@ -801,8 +807,9 @@ int pdmk_batch_eval(pdmk_batch* B, const int64_t* offsets, const double* src, co
       return;
     }
     for (;;) {
-      const int sy = next.fetch_add(1);
-      if (sy >= n_sys) break;
+      const int k = next.fetch_add(1);
+      if (k >= n_sys) break;
+      const int sy = order[k];
       const int64_t o = offsets[sy], n = offsets[sy + 1] - offsets[sy];
       const int st = eval_impl(B->plans[sy], n, src + o * d, q + o, 0, nullptr, pot + o,
                                grad ? grad + o * d : nullptr, B->streams[w], B->o.flags,
