@@ -401,8 +401,8 @@ class Batch:
         """Batch autotuner (pdmk_batch_tune): per size class floor(log2 n), times
         each (kappa, n_s) candidate on a sample of the class evaluated
         concurrently by the batch's workers and re-plans the class with the
-        fastest.  Default candidates: kappa in {1, 2, 3} with
-        the default leaf capacity times {1, 2, 4}.  Returns host arrays of each
+        fastest.  Default candidates: kappa in {2, 3} with the default leaf
+        capacity times 2^0 .. 2^9 (small cells run fastest on shallow trees).  Returns host arrays of each
         system's (kappa, n_s) after tuning."""
         import torch
         off = np.ascontiguousarray(offsets, dtype=np.int64)
@@ -414,7 +414,7 @@ class Batch:
             raise ValueError("offsets do not match the arrays")
         if candidates is None:
             base = self.opts.n_s
-            candidates = [(k, base * f) for k in (1.0, 2.0, 3.0) for f in (1, 2, 4)]
+            candidates = [(k, base * f) for k in (2.0, 3.0) for f in (1, 2, 4, 8, 16, 32, 64, 128, 256, 512)]
         kap = np.array([float(c[0]) for c in candidates], dtype=np.float64)
         nss = (ctypes.c_int * len(candidates))(*[int(c[1]) for c in candidates])
         k_out = np.zeros(self.n_sys, dtype=np.float64)
