@@ -128,3 +128,37 @@ def test_batch_tune_gradients_and_empty_system(pdmk, torch_dev, systems):
         ref_p, ref_g = ewald.ewald(L, x, qq, grad=True)
         assert ewald.rel_l2(pot[offs[s]:offs[s + 1]], ref_p) <= 1e-6
         assert ewald.rel_l2(g[offs[s]:offs[s + 1]], ref_g) <= 1e-5, s
+
+
+def test_batch_tune_default_candidates(pdmk, torch_dev, systems):
+    """The default candidate set of the autotuner (leaf capacities up to 512
+    times the default, whole root cubes as leaves) still meets eps against
+    the oracle on every system, in both precisions."""
+    torch, dev = torch_dev
+    sy, refs = systems
+    Ls, offs, src, q = _pack(sy)
+    s_d, q_d = torch.tensor(src, device=dev), torch.tensor(q, device=dev)
+    for precision in ("fp64", "mixed"):
+        B = pdmk.Batch(Ls, eps=1e-6, precision=precision, workers=4)
+        k, n = B.tune(offs, s_d, q_d, trials=1)
+        pot = B.eval(offs, s_d, q_d).cpu().numpy()
+        for s, ref in enumerate(refs):
+            err = ewald.rel_l2(pot[offs[s]:offs[s + 1]], ref)
+            assert err <= 1e-6, (precision, s, k[s], n[s], err)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_large_single_leaves_sampled(pdmk, torch_dev, precision):
+    """A clustered cell of 40000 sources in a batch planned with a leaf
+    capacity above N (the shallow trees the autotuner picks for small cells:
+    leaves of tens of thousands of sources, many target groups and source
+    segments per leaf) against the oracle at 48 sampled sources."""
+    torch, dev = torch_dev
+    L, src, q = workloads.batch_cells(n_sys=2, seed=7, n_min=40_000, n_max=40_000)[1]
+    offs = np.array([0, len(q)], dtype=np.int64)
+    B = pdmk.Batch(L[None], eps=1e-6, precision=precision, workers=1, kappa=3.0, n_s=102400)
+    pot = B.eval(offs, torch.tensor(src, device=dev), torch.tensor(q, device=dev)).cpu().numpy()
+    st = B.stats(0)
+    assert st["n_levels"] == 1 and st["n_leaves"] >= 1
+    idx = np.random.default_rng(3).choice(len(q), 48, replace=False)
+    assert ewald.rel_l2(pot[idx], ewald.ewald_sampled(L, src, q, idx)) <= 1e-6
