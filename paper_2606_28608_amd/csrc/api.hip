@@ -9,6 +9,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <string>
+#include <system_error>
 
 #include "internal.h"
 
@@ -823,7 +824,11 @@ int pdmk_batch_eval(pdmk_batch* B, const int64_t* offsets, const double* src, co
     }
   };
   std::vector<std::thread> th;
-  for (int w = 1; w < nw; ++w) th.emplace_back(work, w);
+  try {
+    for (int w = 1; w < nw; ++w) th.emplace_back(work, w);
+  } catch (const std::system_error&) {
+    // fewer threads than workers: the threads that exist take every system
+  }
   work(0);
   for (auto& t : th) t.join();
   for (int w = 0; w < nw; ++w)
@@ -994,8 +999,14 @@ int pdmk_batch_tune(pdmk_batch* B, const int64_t* offsets, const double* src, co
       for (int t = 0; t <= trials && st == PDMK_OK; ++t) {   // t = 0: warm-up
         const auto t0 = std::chrono::steady_clock::now();
         std::vector<std::thread> th;
-        for (int i = 1; i < ns; ++i) th.emplace_back(one, i);
+        int started = 1;
+        try {
+          for (int i = 1; i < ns; ++i, ++started) th.emplace_back(one, i);
+        } catch (const std::system_error&) {
+          // samples without a thread run on this one after its own
+        }
         one(0);
+        for (int i = started; i < ns; ++i) one(i);
         for (auto& x : th) x.join();
         if (t > 0)
           ms += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0)
