@@ -36,7 +36,11 @@
  *     keeps no caller pointer after a call returns.
  *   - Calls are ordered on the HIP stream passed in (NULL = default stream)
  *     and block until the results are written (the call synchronises its
- *     stream before returning).  Inside a call, part of the work runs on a
+ *     stream before returning), except pdmk_plan_execute, which only
+ *     enqueues (its status comes from pdmk_plan_status).  The tree build
+ *     needs the sizes of each refinement level on the host before it can
+ *     launch the next one, so every call that builds a tree waits on the
+ *     device; pdmk_plan_execute builds none.  Inside a call, part of the work runs on a
  *     second stream (default priority; owned by the plan, created on its
  *     first evaluation, or by the batch worker) forked from and joined back
  *     to the caller's stream by events.
@@ -68,16 +72,37 @@ typedef enum {
 
 /* Arithmetic of the evaluation.
  *   PDMK_PREC_FP64 : every stage in double precision.
- *   PDMK_PREC_MIXED: near-field residual sums, proxy and plane-wave transforms
- *                    in FP32 (box-local coordinates); FP64 kept for wrapping,
- *                    box assignment, the far-field diagonal scaling and the
- *                    final accumulation. */
+ *   PDMK_PREC_MIXED: FP64 kept for wrapping, box assignment, residual-pair
+ *                    offsets and r^2, the far-field diagonal scaling and the
+ *                    final accumulation; FP32 for the stages in fp32_stages:
+ *                    3D: residual-series sums, proxy charges / potentials and
+ *                    plane-wave transforms (on FP32 matrix cores; BF16 hi/lo
+ *                    products with FP32 accumulation at eps >= 1e-3), far-field
+ *                    window weights.  2D: residual-series sums and window
+ *                    weights only (2D proxies and plane waves stay FP64).
+ *                    FP32 cannot reach eps below 1e-6: for eps < 1e-6 a mixed
+ *                    plan computes every stage in FP64 (the same arithmetic as
+ *                    PDMK_PREC_FP64), so the result still meets eps. */
 enum { PDMK_PREC_FP64 = 0, PDMK_PREC_MIXED = 1 };
+
+/* Stages a mixed plan may compute in FP32 (pdmk_opts.fp32_stages). */
+enum {
+  PDMK_FP32_RESIDUAL = 1,      /* leaf residual-series sums */
+  PDMK_FP32_PROXY = 2,         /* proxy tensors and plane-wave transforms (3D) */
+  PDMK_FP32_WINDOW = 4,        /* far-field spreading / interpolation weights */
+  PDMK_BF16_PLANE_WAVES = 8    /* BF16 hi/lo plane-wave products at eps >= 1e-3 (3D) */
+};
 
 /* Flags */
 enum {
   PDMK_WANT_GRAD = 1,          /* gradients wanted: accurate grad Phi (see pdmk_eval) */
-  PDMK_ALLOW_NONNEUTRAL = 2    /* accept sum q != 0 (uniform background) */
+  PDMK_ALLOW_NONNEUTRAL = 2,   /* accept sum q != 0 (uniform background) */
+  PDMK_DETERMINISTIC = 4,      /* fixed-order reductions: repeated calls on the same
+                                  input return bitwise-equal results (see below) */
+  PDMK_VECTOR_PLANE_WAVES = 8  /* use the vector-ALU plane-wave, anterpolation,
+                                  transfer and leaf-evaluation kernels instead of the
+                                  matrix-core ones (same arithmetic type; for
+                                  comparing the two implementations) */
 };
 
 typedef struct {
@@ -86,7 +111,8 @@ typedef struct {
   int precision;    /* PDMK_PREC_FP64 or PDMK_PREC_MIXED */
   double kappa;     /* root cube side r_c = L_min / kappa (Section 5); <= 0: default */
   int n_s;          /* leaf capacity (Section 5, Table tab:tuning); <= 0: default */
-  unsigned flags;   /* PDMK_WANT_GRAD | PDMK_ALLOW_NONNEUTRAL */
+  unsigned flags;   /* PDMK_WANT_GRAD | PDMK_ALLOW_NONNEUTRAL | PDMK_DETERMINISTIC |
+                       PDMK_VECTOR_PLANE_WAVES */
   int porder;       /* Chebyshev proxy points per axis; <= 0: chosen from eps */
   int npw;          /* plane-wave half count J per axis (modes -J..J); <= 0: from eps */
   int nufft_w;      /* spreading-window width in grid cells; <= 0: from eps (two
@@ -94,7 +120,26 @@ typedef struct {
   double sigma;     /* Fourier grid per axis = sigma * M_i of eq:Mi rounded up to a
                        2,3,5-smooth even size; <= 0: 1 (no upsampling, as in the
                        paper) for eps >= 1e-7, 2 below */
+  unsigned fp32_stages; /* PDMK_PREC_MIXED only: PDMK_FP32_* / PDMK_BF16_* bits of the
+                       stages computed in reduced precision; 0: all of them (the
+                       default).  Ignored (every stage FP64) when eps < 1e-6. */
 } pdmk_opts;
+
+/*
+ * PDMK_DETERMINISTIC.  Without it, the leaf residual sums (segments of one
+ * target's list), the far-field spreading, the child -> parent proxy-charge
+ * transfers and the charge sum accumulate with floating-point atomics, so
+ * repeated calls agree to rounding only.  With it every such reduction has a
+ * fixed order or is exact: residual segments write partial sums that one
+ * thread per target adds in segment order; spreading accumulates each
+ * block's subgrid in program order (one wave per block) and adds the
+ * subgrids into the grid in two-word 64-bit fixed point (integer atomics,
+ * order-independent; resolution 2^-101 of sum |q|); child -> parent
+ * transfers run one octant per launch.  Repeated calls with the same inputs,
+ * options and device then return bitwise-equal potentials and gradients,
+ * also through pdmk_batch_eval with any number of workers.  It costs time
+ * and is off by default.
+ */
 
 /* Fill *out with the defaults for (dim, eps); nufft_w is left 0 (chosen at
  * plan creation from eps and the flags).  Host only; no device needed. */
@@ -129,6 +174,53 @@ int pdmk_plan_eval(pdmk_plan* plan, int64_t n_src, const double* src,
                    const double* q, int64_t n_trg, const double* trg,
                    double* pot, double* grad, void* stream);
 void pdmk_plan_destroy(pdmk_plan* plan);
+
+/*
+ * Kept trees: evaluate many charge vectors (and small displacements) on one
+ * tree.  Algorithm 1 rebuilds the tree for every evaluation (the
+ * preprocessing and tree steps depend only on the positions); when the
+ * positions do not change -- new charges, the adjoint charges of a backward
+ * pass, a finite-difference stencil -- those steps can be done once.
+ *
+ * pdmk_plan_bind: one full evaluation (arguments and results as
+ * pdmk_plan_eval; blocks) that also keeps, in device memory owned by the
+ * plan, everything that depends on the positions alone: wrapped and sorted
+ * sources, images and targets, the tree, colleague and residual lists.  A
+ * previous binding is released first.  It also allocates the workspace an
+ * execute needs, so that executes allocate nothing.
+ *
+ * pdmk_plan_execute: the near field, far field and assembly of Algorithm 1
+ * for charges q (n_src, DEVICE) on the kept tree, into pot (n_trg) and, when
+ * grad is not NULL, grad (n_trg x d).  It only enqueues work on `stream` and
+ * returns: no host synchronisation, no allocation, no memset nodes, so a
+ * caller may capture it into a HIP graph and replay it (the graph then reads
+ * q and writes pot / grad at the addresses given at capture).  src / trg
+ * (DEVICE, caller layout, may be NULL = the bound positions) are moved
+ * positions of the bound points: the kept tree, lists, images and wrap are
+ * used with each point displaced by (new - bound) position ("frozen tree").
+ * The result is accurate to eps while every displacement stays well below
+ * the smallest leaf side (the near-field lists and proxy grids of the bound
+ * boxes remain valid: the residual kernel is continuous at the edge of its
+ * support and vanishes there to within eps); it is a smooth function of the
+ * positions, as finite-difference checks need.  trg must be NULL when the
+ * bound targets are the sources.  Errors of the inputs (non-finite values,
+ * charges not neutral without PDMK_ALLOW_NONNEUTRAL) are found on the
+ * device: the assembly then leaves pot / grad unwritten and the error is
+ * kept until the next pdmk_plan_status.  Calls on one plan are ordered by
+ * their streams; an execute must not overlap another call on the same plan.
+ *
+ * pdmk_plan_status: waits for the plan's last execute and returns the first
+ * error any execute since the previous status call found on the device
+ * (PDMK_ERR_NONFINITE, PDMK_ERR_NOT_NEUTRAL), else PDMK_OK; clears it.
+ *
+ * pdmk_plan_unbind releases the kept tree (pdmk_plan_destroy does too).
+ */
+int pdmk_plan_bind(pdmk_plan* plan, int64_t n_src, const double* src, const double* q,
+                   int64_t n_trg, const double* trg, double* pot, double* grad, void* stream);
+int pdmk_plan_execute(pdmk_plan* plan, const double* src, const double* trg, const double* q,
+                      double* pot, double* grad, void* stream);
+int pdmk_plan_status(pdmk_plan* plan);
+void pdmk_plan_unbind(pdmk_plan* plan);
 
 /*
  * Adjoint of an evaluation, for a loss l(Phi) with g = dl/dPhi at the n_trg

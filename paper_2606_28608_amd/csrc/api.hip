@@ -4,6 +4,8 @@
 #include <algorithm>
 #include <atomic>
 #include <map>
+#include <mutex>
+#include <set>
 #include <thread>
 #include <chrono>
 #include <cstdlib>
@@ -61,6 +63,46 @@ static T* upload(const std::vector<T>& v) {
 }
 
 namespace pdmk {
+__global__ void k_fill_zero(uint64_t* __restrict__ w, int64_t nw, unsigned char* __restrict__ tail,
+                            int ntail) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < nw) w[i] = 0ull;
+  if (i < ntail) tail[i] = 0;
+}
+
+__global__ void k_fill_zero_bytes(unsigned char* __restrict__ b, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) b[i] = 0;
+}
+
+void fill_zero(void* p, size_t bytes, hipStream_t s) {
+  if (bytes == 0) return;
+  if (reinterpret_cast<uintptr_t>(p) % 8 != 0) {
+    hipLaunchKernelGGL(k_fill_zero_bytes, dim3(nblk((int64_t)bytes, 256)), dim3(256), 0, s,
+                       static_cast<unsigned char*>(p), (int64_t)bytes);
+    return;
+  }
+  // whole 8-byte words, then the last bytes % 8
+  const int64_t nw = (int64_t)(bytes / 8);
+  const int ntail = (int)(bytes % 8);
+  const int64_t n = std::max<int64_t>(nw, ntail);
+  hipLaunchKernelGGL(k_fill_zero, dim3(nblk(n, 256)), dim3(256), 0, s,
+                     static_cast<uint64_t*>(p), nw, static_cast<unsigned char*>(p) + 8 * nw,
+                     ntail);
+}
+
+void ensure_lds(const void* kernel, size_t bytes) {
+  static std::mutex mu;
+  static std::map<std::pair<int, const void*>, size_t> limit;
+  int dev = 0;
+  PDMK_HIP(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lock(mu);
+  size_t& cur = limit[{dev, kernel}];
+  if (bytes <= cur) return;
+  PDMK_HIP(hipFuncSetAttribute(kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
+  cur = bytes;
+}
+
 void plan_upload_tables(pdmk_plan* P) {
   const int d = P->g.dim;
   const int p = P->mp.porder, J = P->mp.npw;
@@ -145,12 +187,17 @@ void plan_upload_tables(pdmk_plan* P) {
 }
 }  // namespace pdmk
 
+static void unbind(pdmk_plan* P);
+
 static void free_plan_tables(pdmk_plan* P) {
   void* ptrs[] = {P->d_E, P->d_Ed, P->d_F2, P->d_F2d, P->d_nodes, P->d_bw, P->d_Tm,
                   P->d_F, P->d_Ff, P->d_dtab, P->d_farscale, P->d_shiftvec, P->d_pwt_f,
                   P->d_pwt_d, P->adj_buf, P->d_ball, P->d_brow, P->d_fftw, P->d_pwt_b};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
+  for (hipEvent_t e : P->ev_pool) (void)hipEventDestroy(e);
+  P->ev_pool.clear();
+  P->ev_next = 0;
   if (P->h_cnt) (void)hipHostFree(P->h_cnt);
   P->h_cnt = nullptr;
   if (P->s_aux) {
@@ -205,7 +252,8 @@ static MethodParams resolve_params(const pdmk_opts* o) {
 }
 
 // ---------------------------------------------------------------- kernels
-__global__ void k_charge_stats(int64_t n, const double* __restrict__ q, double* __restrict__ out,
+// Charge sum and sum of magnitudes: per-block partials (part[2 b], part[2 b + 1]).
+__global__ void k_charge_stats(int64_t n, const double* __restrict__ q, double* __restrict__ part,
                                int* __restrict__ bad) {
   __shared__ double s1[256], s2[256];
   double a = 0.0, b = 0.0;
@@ -229,8 +277,35 @@ __global__ void k_charge_stats(int64_t n, const double* __restrict__ q, double* 
     __syncthreads();
   }
   if (threadIdx.x == 0) {
-    atomicAdd(out, s1[0]);
-    atomicAdd(out + 1, s2[0]);
+    part[2 * blockIdx.x] = s1[0];
+    part[2 * blockIdx.x + 1] = s2[0];
+  }
+}
+
+// Sum of the per-block partials of k_charge_stats in a fixed order (one
+// block), so the charge sum -- and the uniform-background constant it
+// scales -- does not depend on the order blocks finish in.
+__global__ void k_charge_stats_final(int nblocks, const double* __restrict__ part,
+                                     double* __restrict__ out) {
+  __shared__ double s1[256], s2[256];
+  double a = 0.0, b = 0.0;
+  for (int k = threadIdx.x; k < nblocks; k += 256) {
+    a += part[2 * k];
+    b += part[2 * k + 1];
+  }
+  s1[threadIdx.x] = a;
+  s2[threadIdx.x] = b;
+  __syncthreads();
+  for (int st = 128; st > 0; st >>= 1) {
+    if (threadIdx.x < st) {
+      s1[threadIdx.x] += s1[threadIdx.x + st];
+      s2[threadIdx.x] += s2[threadIdx.x + st];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    out[0] = s1[0];
+    out[1] = s2[0];
   }
 }
 
@@ -363,6 +438,10 @@ static int validate_opts(const pdmk_opts* o) {
     return fail(PDMK_ERR_INVALID_ARG, "unknown precision");
   if (o->porder > 40 || o->npw > 64 || o->nufft_w > 16 || o->sigma > 4.0)
     return fail(PDMK_ERR_INVALID_ARG, "porder <= 40, npw <= 64, nufft_w <= 16, sigma <= 4");
+  if (o->flags & ~(unsigned)(PDMK_WANT_GRAD | PDMK_ALLOW_NONNEUTRAL | PDMK_DETERMINISTIC |
+                             PDMK_VECTOR_PLANE_WAVES))
+    return fail(PDMK_ERR_INVALID_ARG, "unknown flag");
+  if (o->fp32_stages & ~15u) return fail(PDMK_ERR_INVALID_ARG, "unknown fp32_stages bit");
   return PDMK_OK;
 }
 
@@ -418,16 +497,13 @@ int pdmk_plan_create(const pdmk_opts* opts, const double* L, pdmk_plan** out) {
     kp.w0unit = P->T->w0_unit(d);
     plan_upload_tables(P);
     if (d == 3) pw_mfma_upload(P);
-    {
-      // diagnostic switch: PDMK_NO_MFMA=1 selects the vector-ALU plane-wave kernels
-      const char* env = std::getenv("PDMK_NO_MFMA");
-      P->pw_mfma = !(env && env[0] == '1');
-      // diagnostic switch: PDMK_MIXED_PARTS=<mask> limits which stages run in
-      // FP32 in mixed mode (1 residual sums, 2 proxies/plane waves, 4 window,
-      // 8 BF16 plane-wave products at eps >= 1e-3)
-      const char* mp = std::getenv("PDMK_MIXED_PARTS");
-      if (mp) P->mixed_parts = (unsigned)std::atoi(mp) & 15u;
-    }
+    P->pw_mfma = !(opts->flags & PDMK_VECTOR_PLANE_WAVES);
+    // stages in FP32 (mixed plans): the caller's mask, all by default; none
+    // below eps = 1e-6, where FP32 rounding (about 6e-8 per operation, and the
+    // FP32 residual series cut at 1e-8 of its largest coefficient) cannot
+    // reach the tolerance
+    P->mixed_parts = opts->fp32_stages ? (opts->fp32_stages & 15u) : 15u;
+    if (opts->precision != PDMK_PREC_MIXED || opts->eps < kMixedEpsFloor) P->mixed_parts = 0;
     far_build_scale(P);
     PDMK_HIP(hipHostMalloc((void**)&P->h_cnt, 8 * sizeof(unsigned long long)));
   } catch (const Error& e) {
@@ -441,6 +517,7 @@ int pdmk_plan_create(const pdmk_opts* opts, const double* L, pdmk_plan** out) {
 
 void pdmk_plan_destroy(pdmk_plan* P) {
   if (!P) return;
+  unbind(P);
   free_plan_tables(P);
   delete P;
 }
@@ -507,12 +584,53 @@ int pdmk_plan_stats(const pdmk_plan* P, pdmk_stats* out) {
 // second stream.
 constexpr int64_t kForkMin = 1 << 18;
 
+// Tree kept by pdmk_plan_bind: the evaluation state after the list stage
+// (sorted sources and targets, levels, lists, work items) in its own device
+// memory, the map from sorted images to sources, the bound positions, and the
+// execute workspace.
+struct pdmk::BoundState {
+  Eval E;                        // state after the lists (host copy of the level table)
+  Workspace tree_ws;             // device memory of E (arena + overflow), owned
+  char* tree_arena = nullptr;
+  char* xarena = nullptr;        // execute workspace (sized at bind)
+  size_t xarena_size = 0;
+  std::vector<void*> pending;    // execute overflow blocks, freed at the next status
+  size_t pending_need = 0;       // bytes the largest overflowing execute needed
+  double* src0 = nullptr;        // bound positions (caller layout, n x d)
+  double* trg0 = nullptr;
+  double* sx0 = nullptr;         // bound sorted images, targets, originals (SoA)
+  double* tx0 = nullptr;
+  double* ox0 = nullptr;
+  double* dsrc = nullptr;        // displacements (SoA) of a moved execute
+  double* dtrg = nullptr;
+  int* status_dev = nullptr;     // sticky device status bits of the executes
+  bool moved = false;            // sorted arrays hold displaced positions
+  hipStream_t last = nullptr;    // stream of the last execute
+  unsigned flags = 0;
+  ~BoundState() {
+    tree_ws.release_overflow();
+    for (void* p : pending) (void)hipFree(p);
+    void* ptrs[] = {tree_arena, xarena, src0, trg0, sx0, tx0, ox0, dsrc, dtrg, status_dev};
+    for (void* p : ptrs)
+      if (p) (void)hipFree(p);
+  }
+};
+
+static void unbind(pdmk_plan* P) {
+  if (!P->bound) return;
+  if (P->bound->last) (void)hipStreamSynchronize(P->bound->last);
+  if (P->s_aux) (void)hipStreamSynchronize(P->s_aux);
+  delete P->bound;
+  P->bound = nullptr;
+}
+
 // aux: the second stream of the call (null: the plan's own, created on first
-// use; a batch worker passes its own)
+// use; a batch worker passes its own).  keep: bind mode -- the call keeps its
+// tree in a new BoundState (the workspace arena passes to it).
 static int eval_impl(pdmk_plan* P, int64_t n_src, const double* src, const double* q,
                      int64_t n_trg, const double* trg, double* pot, double* grad, void* stream,
                      unsigned flags, char*& arena, size_t& arena_size,
-                     hipStream_t aux = nullptr) {
+                     hipStream_t aux = nullptr, BoundState** keep = nullptr) {
   if (!P) return fail(PDMK_ERR_INVALID_ARG, "null plan");
   const int d = P->g.dim;
   const bool self_t = (trg == nullptr);
@@ -523,6 +641,8 @@ static int eval_impl(pdmk_plan* P, int64_t n_src, const double* src, const doubl
     return fail(PDMK_ERR_INVALID_ARG, "more than 2^30 points");
   if ((n_src > 0 && (!src || !q)) || (n_trg > 0 && !pot))
     return fail(PDMK_ERR_INVALID_ARG, "null array");
+  if (keep && (n_src == 0 || n_trg == 0))
+    return fail(PDMK_ERR_INVALID_ARG, "binding needs sources and targets");
   hipStream_t s = (hipStream_t)stream;
   const auto wall0 = std::chrono::steady_clock::now();
   Workspace ws;
@@ -535,6 +655,8 @@ static int eval_impl(pdmk_plan* P, int64_t n_src, const double* src, const doubl
   E.n_trg = n_trg;
   E.self_targets = self_t;
   E.q = q;
+  E.keep_map = keep != nullptr;
+  E.det = (flags & PDMK_DETERMINISTIC) != 0;
   try {
     int cur = -1;
     PDMK_HIP(hipGetDevice(&cur));
@@ -555,9 +677,11 @@ static int eval_impl(pdmk_plan* P, int64_t n_src, const double* src, const doubl
       aux = P->s_aux;
     }
     if (!fork) aux = s;
+    P->ev_next = 0;
+    E.plan = P;
     hipEvent_t ev[5], fev[3];
-    for (auto& e : ev) PDMK_HIP(hipEventCreate(&e));
-    for (auto& e : fev) PDMK_HIP(hipEventCreate(&e));
+    for (auto& e : ev) e = E.event();
+    for (auto& e : fev) e = E.event();
     PDMK_HIP(hipEventRecord(ev[0], s));
     // input checks (charge sums, non-finite charges and positions) stay on
     // the device and are read after the call's final synchronisation; the
@@ -565,26 +689,41 @@ static int eval_impl(pdmk_plan* P, int64_t n_src, const double* src, const doubl
     // nothing for a rejected input
     double* qs = E.alloc<double>(2);
     E.d_flags = E.alloc<int>(2);
-    PDMK_HIP(hipMemsetAsync(qs, 0, 2 * sizeof(double), s));
-    PDMK_HIP(hipMemsetAsync(E.d_flags, 0, 2 * sizeof(int), s));
-    hipLaunchKernelGGL(k_charge_stats, dim3(std::min(1024, nblk(n_src, 256))), dim3(256), 0, s,
-                       n_src, q, qs, E.d_flags);
+    fill_zero(E.d_flags, 2 * sizeof(int), s);
+    {
+      const int nb = std::min(1024, nblk(n_src, 256));
+      double* part = E.alloc<double>(2 * nb);
+      hipLaunchKernelGGL(k_charge_stats, dim3(nb), dim3(256), 0, s, n_src, q, part, E.d_flags);
+      hipLaunchKernelGGL(k_charge_stats_final, dim3(1), dim3(256), 0, s, nb, part, qs);
+    }
+    E.qsum = qs;
     stage_prepare(P, E, src, trg);
     stage_images(P, E, q);
     // the far field's grid steps need only the sorted sources: they run on
     // the plan's second stream beside the tree, lists and near field, and are
-    // joined before the interpolation (which adds into pot_sorted)
-    if (fork) {
-      PDMK_HIP(hipEventRecord(fev[0], s));
-      PDMK_HIP(hipStreamWaitEvent(aux, fev[0], 0));
-    }
-    PDMK_HIP(hipEventRecord(fev[1], aux));
-    E.s = aux;
-    stage_far_grid(P, E);
-    E.s = s;
-    PDMK_HIP(hipEventRecord(fev[2], aux));
+    // joined before the interpolation (which adds into pot_sorted).  A bind
+    // builds the tree first, so that everything allocated after the lists is
+    // the state an execute rebuilds.
+    auto far_fork = [&]() {
+      if (fork) {
+        PDMK_HIP(hipEventRecord(fev[0], s));
+        PDMK_HIP(hipStreamWaitEvent(aux, fev[0], 0));
+      }
+      PDMK_HIP(hipEventRecord(fev[1], aux));
+      E.s = aux;
+      stage_far_grid(P, E);
+      E.s = s;
+      PDMK_HIP(hipEventRecord(fev[2], aux));
+    };
+    if (!keep) far_fork();
     stage_tree(P, E);
     stage_lists(P, E);
+    const size_t mark = ws.used;
+    Eval kept;
+    if (keep) {
+      kept = E;   // the state an execute starts from
+      far_fork();
+    }
     PDMK_HIP(hipEventRecord(ev[1], s));
     stage_near(P, E, want_grad);
     PDMK_HIP(hipEventRecord(ev[2], s));
@@ -610,8 +749,6 @@ static int eval_impl(pdmk_plan* P, int64_t n_src, const double* src, const doubl
     PDMK_HIP(hipEventElapsedTime(&t3, ev[2], ev[3]));
     PDMK_HIP(hipEventElapsedTime(&t4, ev[0], ev[4]));
     PDMK_HIP(hipEventElapsedTime(&tg, fev[1], fev[2]));
-    for (auto& e : ev) (void)hipEventDestroy(e);
-    for (auto& e : fev) (void)hipEventDestroy(e);
     t3 += tg;   // far field: grid steps (overlapped with the build and near field) + interpolation
     {
       double hq[2];
@@ -637,8 +774,27 @@ static int eval_impl(pdmk_plan* P, int64_t n_src, const double* src, const doubl
     E.st.t_total_ms = t4;
     P->last = E.st;
     PDMK_HIP(hipStreamSynchronize(s));
-    finish_workspace(arena, arena_size, ws);
-    P->last.workspace_bytes = (int64_t)ws.used;
+    if (keep) {
+      // the workspace (arena and overflow blocks) now holds the kept tree
+      BoundState* B = new BoundState();
+      *keep = B;
+      B->E = kept;
+      B->tree_ws.overflow.swap(ws.overflow);
+      B->tree_arena = arena;
+      arena = nullptr;
+      arena_size = 0;
+      B->flags = flags;
+      // an execute allocates what this call allocated after the lists, plus
+      // its charge sums and (whether or not this call had them) gradients
+      size_t need = ws.used - mark + 2 * 1024 * sizeof(double) + 8 * 256 +
+                    (want_grad ? 0 : (size_t)n_trg * d * sizeof(double) + 256);
+      PDMK_HIP(hipMalloc((void**)&B->xarena, need));
+      B->xarena_size = need;
+      P->last.workspace_bytes = (int64_t)(ws.used + need);
+    } else {
+      finish_workspace(arena, arena_size, ws);
+      P->last.workspace_bytes = (int64_t)ws.used;
+    }
     P->last.t_call_ms =
         std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - wall0)
             .count();
@@ -651,6 +807,169 @@ static int eval_impl(pdmk_plan* P, int64_t n_src, const double* src, const doubl
   return PDMK_OK;
 }
 
+// ------------------------------------------------------ kept-tree execute
+// d[a * n + i] = Q^T (x[i] - x0[i]) (oriented displacement); flags a
+// non-finite position
+__global__ void k_displacement(KParams kp, int64_t n, const double* __restrict__ x,
+                               const double* __restrict__ x0, double* __restrict__ dsp,
+                               int* __restrict__ bad) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int d = kp.dim;
+  double v[3] = {0, 0, 0};
+  bool ok = true;
+  for (int a = 0; a < d; ++a) {
+    v[a] = x[i * d + a] - x0[i * d + a];
+    ok = ok && isfinite(v[a]);
+  }
+  if (!ok) {
+    atomicOr(bad, 1);
+    for (int a = 0; a < d; ++a) v[a] = 0.0;
+  }
+  for (int a = 0; a < d; ++a) {
+    double s = 0;
+    for (int b = 0; b < d; ++b) s += kp.Q[b + d * a] * v[b];
+    dsp[a * n + i] = s;
+  }
+}
+
+// out[a * m + k] = base[a * m + k] + dsp[a * n + map[k]] (dsp == null: base)
+__global__ void k_displace(int64_t m, int d, const int* __restrict__ map,
+                           const double* __restrict__ base, const double* __restrict__ dsp,
+                           int64_t n, double* __restrict__ out) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= m) return;
+  const int j = dsp ? map[k] : 0;
+  for (int a = 0; a < d; ++a)
+    out[a * m + k] = base[a * m + k] + (dsp ? dsp[a * n + j] : 0.0);
+}
+
+// out[k] = q[map[k]]
+__global__ void k_gather_q(int64_t m, const int* __restrict__ map, const double* __restrict__ q,
+                           double* __restrict__ out) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < m) out[k] = q[map[k]];
+}
+
+// status bits of one execute, kept until pdmk_plan_status reads them:
+// 1 non-finite charge, 2 non-finite position, 4 charges not neutral
+__global__ void k_status_accum(const int* __restrict__ flags, const double* __restrict__ qs,
+                               int allow_nonneutral, int* __restrict__ status) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  int v = status[0];
+  if (flags[0]) v |= 1;
+  if (flags[1]) v |= 2;
+  if (!allow_nonneutral && fabs(qs[0]) > 1e-8 * qs[1]) v |= 4;
+  status[0] = v;
+}
+
+static int execute_impl(pdmk_plan* P, const double* src, const double* trg, const double* q,
+                        double* pot, double* grad, hipStream_t s) {
+  BoundState& B = *P->bound;
+  const int d = P->g.dim;
+  Eval E = B.E;
+  Workspace xws;
+  xws.base = B.xarena;
+  xws.size = B.xarena_size;
+  E.ws = &xws;
+  E.s = s;
+  E.plan = P;
+  E.timing = false;
+  E.q = q;
+  E.st = pdmk_stats{};
+  E.det = (B.flags & PDMK_DETERMINISTIC) != 0;
+  const bool want_grad = grad != nullptr;
+  const int64_t n = E.n_src, m = E.n_trg;
+  const bool fork = n + m >= kForkMin;
+  hipStream_t aux = fork ? P->s_aux : s;
+  try {
+    if (fork && !aux) throw Error{PDMK_ERR_INVALID_ARG, "plan has no second stream"};
+    P->ev_next = 0;
+    double* qs = E.alloc<double>(2);
+    E.d_flags = E.alloc<int>(2);
+    fill_zero(E.d_flags, 2 * sizeof(int), s);
+    {
+      const int nb = std::min(1024, nblk(n, 256));
+      double* part = E.alloc<double>(2 * nb);
+      hipLaunchKernelGGL(k_charge_stats, dim3(nb), dim3(256), 0, s, n, q, part, E.d_flags);
+      hipLaunchKernelGGL(k_charge_stats_final, dim3(1), dim3(256), 0, s, nb, part, qs);
+    }
+    E.qsum = qs;
+    // positions: the bound ones, or displaced from them on the kept tree
+    const bool move = src != nullptr || (trg != nullptr && !E.self_targets);
+    if (move || B.moved) {
+      const double* ds = nullptr;
+      const double* dt = nullptr;
+      if (src) {
+        hipLaunchKernelGGL(k_displacement, dim3(nblk(n, 256)), dim3(256), 0, s, P->kp, n, src,
+                           B.src0, B.dsrc, E.d_flags + 1);
+        ds = B.dsrc;
+      }
+      if (E.self_targets) dt = ds;
+      else if (trg) {
+        hipLaunchKernelGGL(k_displacement, dim3(nblk(m, 256)), dim3(256), 0, s, P->kp, m, trg,
+                           B.trg0, B.dtrg, E.d_flags + 1);
+        dt = B.dtrg;
+      }
+      hipLaunchKernelGGL(k_displace, dim3(nblk(E.n_img, 256)), dim3(256), 0, s, E.n_img, d,
+                         E.img_src, B.sx0, ds, n, E.sx);
+      hipLaunchKernelGGL(k_displace, dim3(nblk(m, 256)), dim3(256), 0, s, m, d, E.tperm, B.tx0,
+                         dt, m, E.tx);
+      if (!E.self_targets)
+        hipLaunchKernelGGL(k_displace, dim3(nblk(n, 256)), dim3(256), 0, s, n, d, E.operm,
+                           B.ox0, ds, n, E.ox);
+      B.moved = move;
+    }
+    // charges of the sorted images and of the originals in tree order
+    hipLaunchKernelGGL(k_gather_q, dim3(nblk(E.n_img, 256)), dim3(256), 0, s, E.n_img,
+                       E.img_src, q, E.sq);
+    hipLaunchKernelGGL(k_gather_q, dim3(nblk(n, 256)), dim3(256), 0, s, n,
+                       E.self_targets ? E.tperm : E.operm, q, E.oq);
+    hipEvent_t f0 = nullptr, f1 = nullptr;
+    if (fork) {
+      f0 = E.event();
+      f1 = E.event();
+      PDMK_HIP(hipEventRecord(f0, s));
+      PDMK_HIP(hipStreamWaitEvent(aux, f0, 0));
+    }
+    E.s = aux;
+    stage_far_grid(P, E);
+    E.s = s;
+    if (fork) PDMK_HIP(hipEventRecord(f1, aux));
+    stage_near(P, E, want_grad);
+    if (fork) PDMK_HIP(hipStreamWaitEvent(s, f1, 0));
+    stage_far_interp(P, E, want_grad);
+    const double cc = P->P->c;
+    const double cnn = -P->P->psit_dd0 * P->g.rc * P->g.rc / (2.0 * cc * cc * P->g.volume);
+    const int allow = (B.flags & PDMK_ALLOW_NONNEUTRAL) ? 1 : 0;
+    hipLaunchKernelGGL(k_assemble, dim3(nblk(m, 256)), dim3(256), 0, s, m, d, E.tperm,
+                       E.pot_sorted, E.grad_sorted, qs, E.d_flags, cnn, allow, P->kp, pot,
+                       want_grad ? grad : nullptr);
+    hipLaunchKernelGGL(k_status_accum, dim3(1), dim3(64), 0, s, E.d_flags, qs, allow,
+                       B.status_dev);
+    PDMK_HIP(hipGetLastError());
+    B.last = s;
+    if (!xws.overflow.empty()) {
+      // more than the bind measured (should not happen): keep the blocks
+      // until the stream has finished, then grow the workspace
+      for (void* p : xws.overflow) B.pending.push_back(p);
+      xws.overflow.clear();
+      B.pending_need = std::max(B.pending_need, xws.used);
+    }
+  } catch (const Error& e) {
+    (void)hipStreamSynchronize(s);
+    if (aux) (void)hipStreamSynchronize(aux);
+    xws.release_overflow();
+    return fail(e.code, e.msg);
+  }
+  return PDMK_OK;
+}
+
+__global__ void k_copy_soa(int64_t n, const double* __restrict__ in, double* __restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = in[i];
+}
+
 extern "C" {
 
 int pdmk_plan_eval(pdmk_plan* P, int64_t n_src, const double* src, const double* q,
@@ -658,6 +977,99 @@ int pdmk_plan_eval(pdmk_plan* P, int64_t n_src, const double* src, const double*
   if (!P) return fail(PDMK_ERR_INVALID_ARG, "null plan");
   return eval_impl(P, n_src, src, q, n_trg, trg, pot, grad, stream, P->o.flags, P->arena,
                    P->arena_size);
+}
+
+int pdmk_plan_bind(pdmk_plan* P, int64_t n_src, const double* src, const double* q,
+                   int64_t n_trg, const double* trg, double* pot, double* grad, void* stream) {
+  if (!P) return fail(PDMK_ERR_INVALID_ARG, "null plan");
+  unbind(P);
+  const int d = P->g.dim;
+  BoundState* B = nullptr;
+  int st = eval_impl(P, n_src, src, q, n_trg, trg, pot, grad, stream, P->o.flags, P->arena,
+                     P->arena_size, nullptr, &B);
+  if (st != PDMK_OK) return st;
+  P->bound = B;
+  try {
+    Eval& E = B->E;
+    const int64_t n = E.n_src, m = E.n_trg;
+    hipStream_t s = (hipStream_t)stream;
+    // bound positions: the caller's arrays and the sorted arrays they made
+    PDMK_HIP(hipMalloc((void**)&B->src0, (size_t)n * d * sizeof(double)));
+    PDMK_HIP(hipMemcpyAsync(B->src0, src, (size_t)n * d * sizeof(double),
+                            hipMemcpyDeviceToDevice, s));
+    PDMK_HIP(hipMalloc((void**)&B->dsrc, (size_t)n * d * sizeof(double)));
+    PDMK_HIP(hipMalloc((void**)&B->sx0, (size_t)E.n_img * d * sizeof(double)));
+    hipLaunchKernelGGL(k_copy_soa, dim3(nblk(E.n_img * d, 256)), dim3(256), 0, s, E.n_img * d,
+                       E.sx, B->sx0);
+    PDMK_HIP(hipMalloc((void**)&B->tx0, (size_t)m * d * sizeof(double)));
+    hipLaunchKernelGGL(k_copy_soa, dim3(nblk(m * d, 256)), dim3(256), 0, s, m * d, E.tx, B->tx0);
+    if (!E.self_targets) {
+      PDMK_HIP(hipMalloc((void**)&B->trg0, (size_t)m * d * sizeof(double)));
+      PDMK_HIP(hipMemcpyAsync(B->trg0, trg, (size_t)m * d * sizeof(double),
+                              hipMemcpyDeviceToDevice, s));
+      PDMK_HIP(hipMalloc((void**)&B->dtrg, (size_t)m * d * sizeof(double)));
+      PDMK_HIP(hipMalloc((void**)&B->ox0, (size_t)n * d * sizeof(double)));
+      hipLaunchKernelGGL(k_copy_soa, dim3(nblk(n * d, 256)), dim3(256), 0, s, n * d, E.ox,
+                         B->ox0);
+    }
+    PDMK_HIP(hipMalloc((void**)&B->status_dev, sizeof(int)));
+    PDMK_HIP(hipMemsetAsync(B->status_dev, 0, sizeof(int), s));
+    if (n + m >= kForkMin && !P->s_aux)
+      PDMK_HIP(hipStreamCreateWithFlags(&P->s_aux, hipStreamNonBlocking));
+    PDMK_HIP(hipStreamSynchronize(s));
+  } catch (const Error& e) {
+    unbind(P);
+    return fail(e.code, e.msg);
+  }
+  return PDMK_OK;
+}
+
+int pdmk_plan_execute(pdmk_plan* P, const double* src, const double* trg, const double* q,
+                      double* pot, double* grad, void* stream) {
+  if (!P) return fail(PDMK_ERR_INVALID_ARG, "null plan");
+  if (!P->bound) return fail(PDMK_ERR_INVALID_ARG, "no bound tree (call pdmk_plan_bind)");
+  if (!q || !pot) return fail(PDMK_ERR_INVALID_ARG, "null array");
+  if (trg && P->bound->E.self_targets)
+    return fail(PDMK_ERR_INVALID_ARG, "the bound targets are the sources");
+  if ((P->o.flags & PDMK_WANT_GRAD) && !grad)
+    return fail(PDMK_ERR_INVALID_ARG, "PDMK_WANT_GRAD set but grad is null");
+  int cur = -1;
+  if (hipGetDevice(&cur) != hipSuccess || cur != P->device)
+    return fail(PDMK_ERR_INVALID_ARG, "plan bound to another device");
+  return execute_impl(P, src, trg, q, pot, grad, (hipStream_t)stream);
+}
+
+int pdmk_plan_status(pdmk_plan* P) {
+  if (!P) return fail(PDMK_ERR_INVALID_ARG, "null plan");
+  BoundState* B = P->bound;
+  if (!B) return fail(PDMK_ERR_INVALID_ARG, "no bound tree");
+  int v = 0;
+  try {
+    if (B->last) PDMK_HIP(hipStreamSynchronize(B->last));
+    if (P->s_aux) PDMK_HIP(hipStreamSynchronize(P->s_aux));
+    PDMK_HIP(hipMemcpy(&v, B->status_dev, sizeof(int), hipMemcpyDeviceToHost));
+    PDMK_HIP(hipMemset(B->status_dev, 0, sizeof(int)));
+    if (!B->pending.empty()) {
+      for (void* p : B->pending) (void)hipFree(p);
+      B->pending.clear();
+      const size_t want = B->pending_need + B->pending_need / 8;
+      (void)hipFree(B->xarena);
+      B->xarena = nullptr;
+      B->xarena_size = 0;
+      PDMK_HIP(hipMalloc((void**)&B->xarena, want));
+      B->xarena_size = want;
+    }
+  } catch (const Error& e) {
+    return fail(e.code, e.msg);
+  }
+  if (v & 1) return fail(PDMK_ERR_NONFINITE, "non-finite charge");
+  if (v & 2) return fail(PDMK_ERR_NONFINITE, "non-finite position");
+  if (v & 4) return fail(PDMK_ERR_NOT_NEUTRAL, "sum of charges is not zero");
+  return PDMK_OK;
+}
+
+void pdmk_plan_unbind(pdmk_plan* P) {
+  if (P) unbind(P);
 }
 
 int pdmk_plan_adjoint(pdmk_plan* P, int64_t n_src, const double* src, const double* q,

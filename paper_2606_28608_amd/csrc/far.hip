@@ -184,8 +184,7 @@ static void fft3(double2* g, const int* M, int dim, int sign, const double2* tw,
     const int lpb = std::max(1, std::min(2048 / Ma, 64));
     const int nblocks = (nlines + lpb - 1) / lpb;
     size_t smem = 2 * (size_t)lpb * Ma * sizeof(double2);
-    PDMK_HIP(hipFuncSetAttribute((const void*)&k_fft_lines,
-                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem));
+    ensure_lds((const void*)&k_fft_lines, smem);
     hipLaunchKernelGGL(k_fft_lines, dim3(nblocks), dim3(256), smem, s, g, Ma, stride, nl0, so0,
                        so1, nlines, lpb, sign, R, tw + tw_off[ax]);
   }
@@ -642,7 +641,7 @@ void stage_far_grid(pdmk_plan* P, Eval& E) {
   double2* cg = E.alloc<double2>(n);
   E.far_grid = grid;
   E.far_cg = cg;
-  PDMK_HIP(hipMemsetAsync(grid, 0, n * sizeof(double), E.s));
+  fill_zero(grid, n * sizeof(double), E.s);
   spread_interp(P, E, M, w, beta, grid, cg, false, true);
   hipLaunchKernelGGL(k_to_complex, dim3(nblk(n, 256)), dim3(256), 0, E.s, n, grid, cg);
   fft3(cg, M, d, -1, P->d_fftw, P->fftw_off, E.s);

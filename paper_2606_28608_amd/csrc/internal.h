@@ -10,7 +10,10 @@
 #include "../../include/pdmk.h"
 #include "planner.h"
 
+struct pdmk_plan;
+
 namespace pdmk {
+struct BoundState;
 
 // ---------------------------------------------------------------- errors
 struct Error {
@@ -57,6 +60,22 @@ struct Workspace {
     overflow.clear();
   }
 };
+
+// Smallest eps at which a mixed plan computes stages in FP32.
+constexpr double kMixedEpsFloor = 1e-6;
+
+// Zeroes `bytes` bytes at p with a fill kernel on stream s (used instead of
+// hipMemsetAsync on every path a caller may capture into a HIP graph).
+void fill_zero(void* p, size_t bytes, hipStream_t s);
+
+// Raises a kernel's dynamic-LDS limit (per device) to at least `bytes`.  The
+// limit only grows, under a process-wide lock, so a thread evaluating one
+// plan never lowers the limit another thread's launch relies on.
+void ensure_lds(const void* kernel, size_t bytes);
+
+// Largest number of sources plus images (sorted indices, tree ranges and
+// list entries are int32).
+constexpr int64_t kMaxImages = ((int64_t)1 << 31) - 4096;
 
 // Sources per work item of the leaf residual sums: a target leaf's source
 // list is cut into segments of this length, so that the cost of one block is
@@ -108,6 +127,8 @@ struct Level {
 struct Eval {
   hipStream_t s = nullptr;
   Workspace* ws = nullptr;
+  pdmk_plan* plan = nullptr;   // events come from its pool
+  hipEvent_t event();
   template <class T>
   T* alloc(size_t n) {
     return static_cast<T*>(ws->take(n * sizeof(T)));
@@ -129,6 +150,13 @@ struct Eval {
   int* tperm = nullptr;   // sorted target -> original target index
   double* ox = nullptr;   // original sources in tree order (dim * n_src), for the far field
   double* oq = nullptr;
+  // kept-tree evaluation (pdmk_plan_bind / pdmk_plan_execute)
+  bool keep_map = false;    // stage_images also writes img_src (and operm)
+  int* img_src = nullptr;   // sorted image -> source index
+  int* operm = nullptr;     // separate targets: ox / oq entry -> source index (else null:
+                            // ox is tx and oq follows tperm)
+  bool timing = true;       // record per-stage events (off inside pdmk_plan_execute)
+  bool det = false;         // PDMK_DETERMINISTIC
   std::vector<Level> lev;
   Level* d_lev = nullptr;   // device copy of lev (for list building)
   // target leaves
@@ -151,6 +179,7 @@ struct Eval {
   // done, translation done}; device counters copied into the plan's pinned
   // host buffer
   int* d_flags = nullptr;   // device {non-finite charge, non-finite position}
+  double* qsum = nullptr;   // device {sum q, sum |q|}
   bool near_pending = false;
   double* far_grid = nullptr;   // spreading grid (real)
   double2* far_cg = nullptr;    // its transform, scaled and transformed back
@@ -187,6 +216,10 @@ struct pdmk_plan {
   // plane waves, 4 far-field window weights; 8: BF16 plane-wave products at
   // eps >= 1e-3 (all by default)
   unsigned mixed_parts = 15;
+  // HIP events reused by every call on this plan (created on first use;
+  // a plan serves one call at a time)
+  std::vector<hipEvent_t> ev_pool;
+  size_t ev_next = 0;
   double* adj_buf = nullptr;    // Psi and grad Psi of the adjoint (n_src (d + 1))
   // pinned host: [0..2] plane-wave pairs, boxes, support pairs; [3] visited
   // residual pairs; [4..5] sum q,
@@ -217,9 +250,20 @@ struct pdmk_plan {
   int nshift = 0;
   double nufft_beta = 0;
   pdmk_stats last{};
+  pdmk::BoundState* bound = nullptr;   // tree kept by pdmk_plan_bind
 };
 
 namespace pdmk {
+inline hipEvent_t Eval::event() {
+  pdmk_plan* P = plan;
+  if (P->ev_next < P->ev_pool.size()) return P->ev_pool[P->ev_next++];
+  hipEvent_t e = nullptr;
+  PDMK_HIP(hipEventCreate(&e));
+  P->ev_pool.push_back(e);
+  ++P->ev_next;
+  return e;
+}
+
 // Matrix-core plane-wave transforms (pwmfma.hip).
 constexpr int kPwMaxTiles = 16;   // accumulator tiles of a box's proxy potential per wave
 struct PwMfmaShape {

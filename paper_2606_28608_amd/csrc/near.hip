@@ -996,8 +996,7 @@ static void launch_transfer(const KParams& kp, const Level& Lp, const Level& Lc,
   Real* scratch = lds ? nullptr : E.alloc<Real>((size_t)nblocks * pD);
 #define PDMK_TR(PM, L, NO, MO)                                                                  \
   do {                                                                                          \
-    PDMK_HIP(hipFuncSetAttribute((const void*)&k_transfer<D, PM, L, NO, MO, Real>,              \
-                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem));       \
+    ensure_lds((const void*)&k_transfer<D, PM, L, NO, MO, Real>, smem);       \
     hipLaunchKernelGGL((k_transfer<D, PM, L, NO, MO, Real>), dim3(nblocks), dim3(256), smem, s, \
                        kp, Lp, Lc, src, dst, P->d_Tm, scratch);                                 \
   } while (0)
@@ -1087,21 +1086,23 @@ static void near_impl(pdmk_plan* P, Eval& E, bool want_grad) {
   const int pD = D == 3 ? p * p * p : p * p;
   const int n1 = 2 * J + 1;
   const int nlev = (int)E.lev.size();
-  for (auto& e : E.near_ev) PDMK_HIP(hipEventCreate(&e));
-  E.near_pending = true;
+  const bool tm = E.timing;   // per-stage events (not inside a kept-tree execute)
+  if (tm)
+    for (auto& e : E.near_ev) e = E.event();
+  E.near_pending = tm;
   hipEvent_t e0 = E.near_ev[0], e1 = E.near_ev[1], e2 = E.near_ev[2], e3 = E.near_ev[3];
   // [0] colleague pairs translated, [1] boxes given incoming plane waves,
   // [2] residual pairs inside the support
   unsigned long long* cnt = E.alloc<unsigned long long>(3);
-  PDMK_HIP(hipMemsetAsync(cnt, 0, 3 * sizeof(unsigned long long), s));
+  fill_zero(cnt, 3 * sizeof(unsigned long long), s);
   unsigned long long* nsup = cnt + 2;
-  PDMK_HIP(hipMemsetAsync(E.pot_sorted, 0, sizeof(double) * E.n_trg, s));
+  fill_zero(E.pot_sorted, sizeof(double) * E.n_trg, s);
   if (want_grad)
-    PDMK_HIP(hipMemsetAsync(E.grad_sorted, 0, sizeof(double) * E.n_trg * D, s));
-  PDMK_HIP(hipEventRecord(e0, s));
+    fill_zero(E.grad_sorted, sizeof(double) * E.n_trg * D, s);
+  if (tm) PDMK_HIP(hipEventRecord(e0, s));
   // residual sums (add into the zeroed pot_sorted)
   if (E.nitems > 0) launch_direct<D>(kp, E, P, s, want_grad, nsup);
-  PDMK_HIP(hipEventRecord(e1, s));
+  if (tm) PDMK_HIP(hipEventRecord(e1, s));
   // proxies
   int maxnl = 0;
   for (int l = 0; l < nlev; ++l) maxnl = std::max(maxnl, E.lev[l].nnl);
@@ -1116,10 +1117,9 @@ static void near_impl(pdmk_plan* P, Eval& E, bool want_grad) {
     L.proxy_q = E.alloc<Real>((size_t)L.nnl * pD + 64);
     L.proxy_phi = E.alloc<Real>((size_t)L.nnl * pD + 64);
     if (mfma)
-      PDMK_HIP(hipMemsetAsync(static_cast<Real*>(L.proxy_phi) + (size_t)L.nnl * pD, 0,
-                              sizeof(Real) * 64, s));
+      fill_zero(static_cast<Real*>(L.proxy_phi) + (size_t)L.nnl * pD, sizeof(Real) * 64, s);
     else
-      PDMK_HIP(hipMemsetAsync(L.proxy_phi, 0, sizeof(Real) * ((size_t)L.nnl * pD + 64), s));
+      fill_zero(L.proxy_phi, sizeof(Real) * ((size_t)L.nnl * pD + 64), s);
   }
   if (maxnl > 0) {
     // upward pass
@@ -1149,10 +1149,8 @@ static void near_impl(pdmk_plan* P, Eval& E, bool want_grad) {
     const C* Ftab = reinterpret_cast<const C*>(sizeof(Real) == 4 ? (const void*)P->d_Ff
                                                                  : (const void*)P->d_F);
     if (fused) {
-      PDMK_HIP(hipFuncSetAttribute((const void*)&k_pw_out<Real>,
-                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_out));
-      PDMK_HIP(hipFuncSetAttribute((const void*)&k_pw_in<Real>,
-                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_in));
+      ensure_lds((const void*)&k_pw_out<Real>, lds_out);
+      ensure_lds((const void*)&k_pw_in<Real>, lds_in);
     }
     for (int l = 0; l < nlev; ++l) {
       Level& L = E.lev[l];
@@ -1162,27 +1160,29 @@ static void near_impl(pdmk_plan* P, Eval& E, bool want_grad) {
       const double levfac = D == 3 ? 1.0 / (3.0 * h) : 1.0;
       const int zz = D == 3 ? p : 1;
       // pe[0] | outgoing | pe[1] | translation (matrix-core path) | pe[3] | incoming | pe[2]
-      hipEvent_t pe[4];
-      for (auto& e : pe) PDMK_HIP(hipEventCreate(&e));
-      E.pw_ev.push_back({pe[0], pe[1], pe[2], pe[3]});
+      hipEvent_t pe[4] = {nullptr, nullptr, nullptr, nullptr};
+      if (tm) {
+        for (auto& e : pe) e = E.event();
+        E.pw_ev.push_back({pe[0], pe[1], pe[2], pe[3]});
+      }
       E.st.n_pwout_boxes += nn;
-      PDMK_HIP(hipEventRecord(pe[0], s));
+      if (tm) PDMK_HIP(hipEventRecord(pe[0], s));
       if (mfma) {
         pw_mfma_level<Real>(P, L, nn, L.proxy_q, bS, bIw, L.proxy_phi, levfac, npairs, pe[1],
                             pe[3], s);
-        PDMK_HIP(hipEventRecord(pe[2], s));
+        if (tm) PDMK_HIP(hipEventRecord(pe[2], s));
         continue;
       }
       if (fused) {
         hipLaunchKernelGGL(k_pw_out<Real>, dim3(nn), dim3(256), lds_out, s, kp, L,
                            static_cast<const Real*>(L.proxy_q), Ftab, bS);
-        PDMK_HIP(hipEventRecord(pe[1], s));
+        if (tm) PDMK_HIP(hipEventRecord(pe[1], s));
         hipLaunchKernelGGL(k_pw_in<Real>, dim3(nn), dim3(256), lds_in, s, kp, L, bS, Ftab,
                            P->d_dtab, levfac, static_cast<Real*>(L.proxy_phi), npairs);
-        PDMK_HIP(hipEventRecord(pe[2], s));
+        if (tm) PDMK_HIP(hipEventRecord(pe[2], s));
         continue;
       }
-      PDMK_HIP(hipEventRecord(pe[1], s));
+      if (tm) PDMK_HIP(hipEventRecord(pe[1], s));
       if (sizeof(Real) != 8) throw Error{PDMK_ERR_UNSUPPORTED, "FP32 proxies need the fused path"};
       double2* bSd = reinterpret_cast<double2*>(bS);
       // outgoing: proxy charges -> plane waves (Hermitian half on axis 0)
@@ -1213,7 +1213,7 @@ static void near_impl(pdmk_plan* P, Eval& E, bool want_grad) {
       hipLaunchKernelGGL((k_axis<true, 1>), dim3(nblk((int64_t)nn * pD, 256)), dim3(256), 0, s,
                          nn, J + 1, p, zz, 0, p, (const void*)bA, (void*)L.proxy_phi, P->d_F, J,
                          p, 1, 1);
-      PDMK_HIP(hipEventRecord(pe[2], s));
+      if (tm) PDMK_HIP(hipEventRecord(pe[2], s));
     }
     // downward pass: parent proxy potential -> non-leaf child proxy potential
     for (int l = 1; l < nlev; ++l) {
@@ -1223,7 +1223,7 @@ static void near_impl(pdmk_plan* P, Eval& E, bool want_grad) {
       launch_transfer<D, Real>(kp, L, Cl, 0, L.proxy_phi, Cl.proxy_phi, P, E, s);
     }
   }
-  PDMK_HIP(hipEventRecord(e2, s));
+  if (tm) PDMK_HIP(hipEventRecord(e2, s));
   // leaf targets evaluate their parent's proxy potential
   if (maxnl > 0)
     for (int l = 0; l + 1 < nlev; ++l)
@@ -1232,9 +1232,11 @@ static void near_impl(pdmk_plan* P, Eval& E, bool want_grad) {
                                              E.pot_sorted, want_grad ? E.grad_sorted : nullptr,
                                              s)))
           launch_eval_children<D, Real>(kp, E.lev[l], E.lev[l + 1], l, E, P, s, want_grad);
-  PDMK_HIP(hipEventRecord(e3, s));
-  PDMK_HIP(hipMemcpyAsync(P->h_cnt, cnt, 3 * sizeof(unsigned long long), hipMemcpyDeviceToHost,
-                          s));
+  if (tm) {
+    PDMK_HIP(hipEventRecord(e3, s));
+    PDMK_HIP(hipMemcpyAsync(P->h_cnt, cnt, 3 * sizeof(unsigned long long),
+                            hipMemcpyDeviceToHost, s));
+  }
 }
 
 void near_finish(const pdmk_plan* P, Eval& E) {
@@ -1256,7 +1258,6 @@ void near_finish(const pdmk_plan* P, Eval& E) {
     E.st.t_pwout_ms += a;
     E.st.t_pwtr_ms += c;
     E.st.t_pwin_ms += b;
-    for (auto& e : pe) (void)hipEventDestroy(e);
   }
   E.pw_ev.clear();
   float t01, t12, t23;
@@ -1266,7 +1267,6 @@ void near_finish(const pdmk_plan* P, Eval& E) {
   E.st.t_direct_ms = t01;
   E.st.t_pw_ms = t12;
   E.st.t_proxy_ms = t23;
-  for (auto& e : E.near_ev) (void)hipEventDestroy(e);
 }
 
 void stage_near(pdmk_plan* P, Eval& E, bool want_grad) {

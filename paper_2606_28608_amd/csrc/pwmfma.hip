@@ -890,13 +890,11 @@ static bool eval_leaf_launch(const pdmk_plan* P, const Level& Lp, const Level& L
   const size_t lds = eval_leaf_lds<Real, PP>(grad != nullptr);
   if (lds > 150 * 1024) return false;
   if (grad) {
-    PDMK_HIP(hipFuncSetAttribute((const void*)&k_eval_leaf_mfma<Real, PP, true>,
-                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    ensure_lds((const void*)&k_eval_leaf_mfma<Real, PP, true>, lds);
     hipLaunchKernelGGL((k_eval_leaf_mfma<Real, PP, true>), dim3(Lp.nnl), dim3(256), lds, s,
                        P->kp, Lp, Lc, l, tx, ntrg, P->d_nodes, P->d_bw, pot, grad);
   } else {
-    PDMK_HIP(hipFuncSetAttribute((const void*)&k_eval_leaf_mfma<Real, PP, false>,
-                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    ensure_lds((const void*)&k_eval_leaf_mfma<Real, PP, false>, lds);
     hipLaunchKernelGGL((k_eval_leaf_mfma<Real, PP, false>), dim3(Lp.nnl), dim3(256), lds, s,
                        P->kp, Lp, Lc, l, tx, ntrg, P->d_nodes, P->d_bw, pot, grad);
   }
@@ -1220,13 +1218,11 @@ static void transfer_launch(const pdmk_plan* P, const Level& Lp, const Level& Lc
   const int SB = sizeof(Real) == 4 ? ((PP + 31) & ~31) + 16 : ((PP + 15) & ~15) + 8;
   const size_t lds = (size_t)KA * SB * sizeof(Real);
   if (up) {
-    PDMK_HIP(hipFuncSetAttribute((const void*)&k_transfer_mfma<Real, PPP, true>,
-                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    ensure_lds((const void*)&k_transfer_mfma<Real, PPP, true>, lds);
     hipLaunchKernelGGL((k_transfer_mfma<Real, PPP, true>), dim3(Lc.nnl), dim3(256), lds, s, Lp,
                        Lc, static_cast<const Real*>(src), static_cast<Real*>(dst), P->d_Tm, SB);
   } else {
-    PDMK_HIP(hipFuncSetAttribute((const void*)&k_transfer_mfma<Real, PPP, false>,
-                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    ensure_lds((const void*)&k_transfer_mfma<Real, PPP, false>, lds);
     hipLaunchKernelGGL((k_transfer_mfma<Real, PPP, false>), dim3(Lc.nnl), dim3(256), lds, s, Lp,
                        Lc, static_cast<const Real*>(src), static_cast<Real*>(dst), P->d_Tm, SB);
   }
@@ -1462,10 +1458,8 @@ static void pw_mfma_launch(const pdmk_plan* P, const Level& L, int nn, const voi
     T = KB == 4 ? P->d_pwt_b : P->d_pwt_f;
     o = KB == 4 ? P->pwt_off_b : P->pwt_off;
   }
-  PDMK_HIP(hipFuncSetAttribute((const void*)&k_pw_out_mfma<Real, PP, JJ, KB>,
-                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh.lds_out));
-  PDMK_HIP(hipFuncSetAttribute((const void*)&k_pw_in_mfma<Real, PP, JJ, KB>,
-                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh.lds_in));
+  ensure_lds((const void*)&k_pw_out_mfma<Real, PP, JJ, KB>, sh.lds_out);
+  ensure_lds((const void*)&k_pw_in_mfma<Real, PP, JJ, KB>, sh.lds_in);
   hipLaunchKernelGGL((k_pw_out_mfma<Real, PP, JJ, KB>), dim3(nn), dim3(256), sh.lds_out, s,
                      static_cast<const Real*>(proxy_q), T + o[0], T + o[1], T + o[2], P->d_brow,
                      P->nball, static_cast<Real*>(S), sh.g_out, sh.sX, sh.sZ);

@@ -143,29 +143,43 @@ __device__ inline void for_each_image(const KParams& kp, const double* x, F f) {
   }
 }
 
-__global__ void k_img_count(KParams kp, int64_t n, const double* __restrict__ xs,
-                            int* __restrict__ cnt, int* __restrict__ missing) {
+// Images per source; also their total in 64 bits (total64), so that a count
+// past the int32 range of the offsets and tree indices is detected before the
+// offsets are used.
+__global__ __launch_bounds__(256) void k_img_count(KParams kp, int64_t n,
+                                                   const double* __restrict__ xs,
+                                                   int* __restrict__ cnt, int* __restrict__ missing,
+                                                   unsigned long long* __restrict__ total64) {
+  __shared__ unsigned long long part[256];
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const int d = kp.dim;
-  double x[3] = {0, 0, 0};
-  for (int a = 0; a < d; ++a) x[a] = xs[a * n + i];
   int c = 0;
-  bool orig = false;
-  for_each_image(kp, x, [&](const double* y) {
-    ++c;
-    orig = orig || (y[0] == x[0] && y[1] == x[1] && y[2] == x[2]);
-  });
-  cnt[i] = c;
-  if (!orig) atomicAdd(missing, 1);   // the unshifted copy was not emitted
+  if (i < n) {
+    const int d = kp.dim;
+    double x[3] = {0, 0, 0};
+    for (int a = 0; a < d; ++a) x[a] = xs[a * n + i];
+    bool orig = false;
+    for_each_image(kp, x, [&](const double* y) {
+      ++c;
+      orig = orig || (y[0] == x[0] && y[1] == x[1] && y[2] == x[2]);
+    });
+    cnt[i] = c;
+    if (!orig) atomicAdd(missing, 1);   // the unshifted copy was not emitted
+  }
+  part[threadIdx.x] = (unsigned long long)c;
+  __syncthreads();
+  for (int st = 128; st > 0; st >>= 1) {
+    if ((int)threadIdx.x < st) part[threadIdx.x] += part[threadIdx.x + st];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) atomicAdd(total64, part[0]);
 }
 
 // Images of source i at off[i]...; isrc[o] = i for the unshifted copy, -1
-// for the shifted ones.
+// for the shifted ones; iall[o] = i for every image (when iall is given).
 __global__ void k_img_emit(KParams kp, int64_t n, const double* __restrict__ xs,
                            const double* __restrict__ q, const int* __restrict__ off,
                            int64_t nimg, double* __restrict__ xi, double* __restrict__ qi,
-                           int* __restrict__ isrc) {
+                           int* __restrict__ isrc, int* __restrict__ iall) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const int d = kp.dim;
@@ -177,6 +191,7 @@ __global__ void k_img_emit(KParams kp, int64_t n, const double* __restrict__ xs,
     for (int a = 0; a < d; ++a) xi[a * nimg + o] = y[a];
     qi[o] = qq;
     isrc[o] = (y[0] == x[0] && y[1] == x[1] && y[2] == x[2]) ? (int)i : -1;
+    if (iall) iall[o] = (int)i;
     ++o;
   });
 }
@@ -242,6 +257,13 @@ __global__ void k_keys(KParams kp, int64_t n, const double* __restrict__ x,
   uint64_t root = (uint64_t)r[0] + (uint64_t)kp.next[0] * ((uint64_t)r[1] + (uint64_t)kp.next[1] * (uint64_t)r[2]);
   key[i] = (root << (d * kp.B)) | morton_interleave(c, d, kp.B);
   idx[i] = (int)i;
+}
+
+// out[i] = in[perm[i]] (int)
+__global__ void k_gather_int(int64_t n, const int* __restrict__ perm, const int* __restrict__ in,
+                             int* __restrict__ out) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = in[perm[i]];
 }
 
 __global__ void k_gather(int64_t n, int d, const int* __restrict__ perm,
@@ -313,25 +335,43 @@ void stage_images(pdmk_plan* P, Eval& E, const double* q) {
   int64_t n = E.n_src;
   int* cnt = E.alloc<int>(n + 2);   // [n + 1]: sources whose unshifted copy is missing
   int* off = E.alloc<int>(n + 1);
+  unsigned long long* total64 = E.alloc<unsigned long long>(1);
   PDMK_HIP(hipMemsetAsync(cnt + n, 0, 2 * sizeof(int), E.s));
+  PDMK_HIP(hipMemsetAsync(total64, 0, sizeof(unsigned long long), E.s));
   if (n > 0)
     hipLaunchKernelGGL(k_img_count, dim3(nblk(n, 256)), dim3(256), 0, E.s, kp, n, E.xs, cnt,
-                       cnt + n + 1);
+                       cnt + n + 1, total64);
   exclusive_scan_int(cnt, off, (int)(n + 1), E);
   int hv[2] = {0, 0};
+  unsigned long long tot = 0;
   PDMK_HIP(hipMemcpyAsync(&hv[0], off + n, sizeof(int), hipMemcpyDeviceToHost, E.s));
   PDMK_HIP(hipMemcpyAsync(&hv[1], cnt + n + 1, sizeof(int), hipMemcpyDeviceToHost, E.s));
+  PDMK_HIP(hipMemcpyAsync(&tot, total64, sizeof(tot), hipMemcpyDeviceToHost, E.s));
   PDMK_HIP(hipStreamSynchronize(E.s));
+  if (tot > (unsigned long long)kMaxImages)
+    throw Error{PDMK_ERR_UNSUPPORTED,
+                "sources plus images exceed " + std::to_string(kMaxImages) +
+                    " (int32 tree indices): " + std::to_string(tot) +
+                    "; use fewer sources or a larger kappa"};
   E.n_img = hv[0];
   const bool from_images = E.self_targets && hv[1] == 0;
   double* xi = E.alloc<double>(E.n_img * kp.dim);
   double* qi = E.alloc<double>(E.n_img);
   int* isrc = E.alloc<int>(E.n_img);
+  int* iall = E.keep_map ? E.alloc<int>(E.n_img) : nullptr;
   if (n > 0)
     hipLaunchKernelGGL(k_img_emit, dim3(nblk(n, 256)), dim3(256), 0, E.s, kp, n, E.xs, q, off,
-                       E.n_img, xi, qi, isrc);
+                       E.n_img, xi, qi, isrc, iall);
   int* perm = nullptr;
   sort_points(P, E, E.n_img, xi, qi, E.skey, E.sx, E.sq, perm);
+  if (E.keep_map) {
+    // source index of every sorted image, for re-gathering charges and
+    // displacements on the kept tree
+    E.img_src = E.alloc<int>(E.n_img);
+    if (E.n_img > 0)
+      hipLaunchKernelGGL(k_gather_int, dim3(nblk(E.n_img, 256)), dim3(256), 0, E.s, E.n_img,
+                         perm, iall, E.img_src);
+  }
   if (from_images) {
     E.tkey = E.alloc<uint64_t>(E.n_trg);
     E.tx = E.alloc<double>(E.n_trg * kp.dim);
@@ -365,6 +405,7 @@ void stage_images(pdmk_plan* P, Eval& E, const double* q) {
     uint64_t* okey = nullptr;
     int* operm = nullptr;
     sort_points(P, E, n, E.xs, q, okey, E.ox, E.oq, operm);
+    E.operm = operm;
   }
 }
 

@@ -23,6 +23,12 @@ PDMK_PREC_FP64 = 0
 PDMK_PREC_MIXED = 1
 PDMK_WANT_GRAD = 1
 PDMK_ALLOW_NONNEUTRAL = 2
+PDMK_DETERMINISTIC = 4
+PDMK_VECTOR_PLANE_WAVES = 8
+PDMK_FP32_RESIDUAL = 1
+PDMK_FP32_PROXY = 2
+PDMK_FP32_WINDOW = 4
+PDMK_BF16_PLANE_WAVES = 8
 
 STATUS = {0: "PDMK_OK", -1: "PDMK_ERR_INVALID_ARG", -2: "PDMK_ERR_SINGULAR_LATTICE",
           -3: "PDMK_ERR_NOT_NEUTRAL", -4: "PDMK_ERR_EPS_RANGE", -5: "PDMK_ERR_NONFINITE",
@@ -40,7 +46,7 @@ class Opts(ctypes.Structure):
     _fields_ = [("dim", ctypes.c_int), ("eps", ctypes.c_double), ("precision", ctypes.c_int),
                 ("kappa", ctypes.c_double), ("n_s", ctypes.c_int), ("flags", ctypes.c_uint),
                 ("porder", ctypes.c_int), ("npw", ctypes.c_int), ("nufft_w", ctypes.c_int),
-                ("sigma", ctypes.c_double)]
+                ("sigma", ctypes.c_double), ("fp32_stages", ctypes.c_uint)]
 
 
 class Geometry(ctypes.Structure):
@@ -116,6 +122,12 @@ def lib():
                                      ctypes.POINTER(ctypes.c_int), ctypes.c_int, ctypes.c_int64,
                                      _vp, _vp, ctypes.c_int64, _vp, _vp, _vp, _dp, _dp,
                                      ctypes.POINTER(ctypes.c_int)]
+        L.pdmk_plan_bind.argtypes = [_vp, ctypes.c_int64, _vp, _vp, ctypes.c_int64, _vp, _vp, _vp,
+                                     _vp]
+        L.pdmk_plan_execute.argtypes = [_vp, _vp, _vp, _vp, _vp, _vp, _vp]
+        L.pdmk_plan_status.argtypes = [_vp]
+        L.pdmk_plan_unbind.argtypes = [_vp]
+        L.pdmk_plan_unbind.restype = None
         L.pdmk_plan_destroy.argtypes = [_vp]
         L.pdmk_plan_destroy.restype = None
         L.pdmk_plan_geometry.argtypes = [_vp, ctypes.POINTER(Geometry)]
@@ -139,11 +151,20 @@ def _check(code):
         raise PdmkError(code, lib().pdmk_last_error().decode())
 
 
-def default_opts(dim, eps, precision="fp64", grad=False, allow_nonneutral=False, **over):
+def default_opts(dim, eps, precision="fp64", grad=False, allow_nonneutral=False,
+                 deterministic=False, vector_plane_waves=False, **over):
+    """pdmk_opts for (dim, eps) with the defaults of pdmk_default_opts; keyword
+    arguments set flags (grad, allow_nonneutral, deterministic,
+    vector_plane_waves) or override fields (kappa, n_s, porder, npw, nufft_w,
+    sigma, fp32_stages)."""
     o = Opts()
     _check(lib().pdmk_default_opts(int(dim), float(eps), ctypes.byref(o)))
+    if precision not in ("fp64", "mixed"):
+        raise ValueError("precision must be 'fp64' or 'mixed'")
     o.precision = PDMK_PREC_MIXED if precision == "mixed" else PDMK_PREC_FP64
-    o.flags = (PDMK_WANT_GRAD if grad else 0) | (PDMK_ALLOW_NONNEUTRAL if allow_nonneutral else 0)
+    o.flags = ((PDMK_WANT_GRAD if grad else 0) | (PDMK_ALLOW_NONNEUTRAL if allow_nonneutral else 0)
+               | (PDMK_DETERMINISTIC if deterministic else 0)
+               | (PDMK_VECTOR_PLANE_WAVES if vector_plane_waves else 0))
     for k, v in over.items():
         if v is not None:
             setattr(o, k, v)
@@ -247,6 +268,7 @@ class Plan:
         L = np.asarray(L, dtype=np.float64)
         self.dim = dim or L.shape[0]
         self.opts = default_opts(self.dim, eps, precision, grad, allow_nonneutral, **over)
+        self.eps = float(eps)
         self.want_grad = grad
         self._h = _vp()
         Lf = _lattice(L, self.dim)
@@ -285,6 +307,64 @@ class Plan:
                                     ctypes.c_void_p(grad.data_ptr()) if grad is not None else None,
                                     _stream(torch)))
         return (pot, grad) if wg else pot
+
+    def bind(self, src, q, trg=None, want_grad=None):
+        """pdmk_plan_bind: a full evaluation that keeps the tree for execute().
+        Returns what eval() returns."""
+        import torch
+        wg = self.want_grad if want_grad is None else bool(want_grad)
+        src = _dev(src, torch)
+        q = _dev(q, torch)
+        n = src.shape[0]
+        if src.shape != (n, self.dim) or q.shape != (n,):
+            raise ValueError("src must be (N, dim) and q (N,)")
+        trg = _dev(trg, torch) if trg is not None else None
+        m = trg.shape[0] if trg is not None else n
+        pot = torch.empty(m, dtype=torch.float64, device=src.device)
+        grad = torch.empty((m, self.dim), dtype=torch.float64, device=src.device) if wg else None
+        vp = lambda t: ctypes.c_void_p(t.data_ptr()) if t is not None else None  # noqa: E731
+        _check(lib().pdmk_plan_bind(self._h, n, vp(src), vp(q), m, vp(trg), vp(pot), vp(grad),
+                                    _stream(torch)))
+        self._bound = (n, m)
+        return (pot, grad) if wg else pot
+
+    def execute(self, q, src=None, trg=None, out=None, grad_out=None, want_grad=None):
+        """pdmk_plan_execute on the kept tree: charges q, optionally moved
+        positions src / trg (frozen tree).  Enqueues only; status() waits and
+        reports device-detected input errors."""
+        import torch
+        if getattr(self, "_bound", None) is None:
+            raise ValueError("bind() first")
+        n, m = self._bound
+        wg = self.want_grad if want_grad is None else bool(want_grad)
+        q = _dev(q, torch)
+        if q.shape != (n,):
+            raise ValueError("q must have the bound source count")
+        if src is not None:
+            src = _dev(src, torch)
+            if src.shape != (n, self.dim):
+                raise ValueError("src must have the bound shape")
+        if trg is not None:
+            trg = _dev(trg, torch)
+            if trg.shape != (m, self.dim):
+                raise ValueError("trg must have the bound shape")
+        pot = torch.empty(m, dtype=torch.float64, device=q.device) if out is None else out
+        grad = None
+        if wg:
+            grad = torch.empty((m, self.dim), dtype=torch.float64, device=q.device) \
+                if grad_out is None else grad_out
+        vp = lambda t: ctypes.c_void_p(t.data_ptr()) if t is not None else None  # noqa: E731
+        _check(lib().pdmk_plan_execute(self._h, vp(src), vp(trg), vp(q), vp(pot), vp(grad),
+                                       _stream(torch)))
+        return (pot, grad) if wg else pot
+
+    def status(self):
+        """pdmk_plan_status: waits for the last execute; raises its error."""
+        _check(lib().pdmk_plan_status(self._h))
+
+    def unbind(self):
+        lib().pdmk_plan_unbind(self._h)
+        self._bound = None
 
     def adjoint(self, src, q, g, trg=None, grad_phi=None, want_dq=True, want_dsrc=True,
                 want_dtrg=False):
@@ -469,8 +549,17 @@ def periodic_potential(plan, src, q, trg=None):
     """Differentiable potential (torch.autograd): Phi at the targets (the
     sources when trg is None) for the plan's lattice and accuracy.  Gradients
     flow to src, q and trg through pdmk_plan_adjoint; the forward computes
-    grad Phi only when a position requires grad."""
+    grad Phi only when a position requires grad.
+
+    Position gradients need a plan made with grad=True (PDMK_WANT_GRAD): that
+    flag widens the far-field window so that grad Phi meets the plan's
+    accuracy; a plan without it raises ValueError when a position requires
+    grad.  Charge gradients work with any plan."""
     global _FN
     if _FN is None:
         _FN = _autograd_fn()
+    need_pos = src.requires_grad or (trg is not None and trg.requires_grad)
+    if need_pos and not plan.want_grad:
+        raise ValueError("position gradients need a plan made with grad=True "
+                         "(PDMK_WANT_GRAD widens the far-field window for accurate gradients)")
     return _FN.apply(src, q, trg, plan)

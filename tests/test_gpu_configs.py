@@ -1,0 +1,130 @@
+"""The full-size configurations in the launch configurations the benchmark
+times, against stored oracle values (tests/golden, written by
+make_golden.py from the Ewald oracle only).
+
+* C3 (N = 1e7 thin shell in the triclinic cell of edge ratio ~17): the
+  runtime planner's choice for this input (kappa = 6 with n_s = 300 mixed /
+  400 FP64, no image halo at kappa = 6) and the halo-populated default
+  (kappa = 3, n_s = 200, N'/N ~ 1.45), at eps = 1e-6 and eps = 1e-3, in both
+  arithmetic modes.
+* C4 (N = 1e6 clustered triclinic): forces and charge gradients through the
+  autograd function (the adjoint evaluation), against the oracle's
+  potential and gradient at 64 sampled sources.
+* Mixed precision below its FP32 floor (eps = 1e-9 on the C2 workload):
+  computed in FP64 and within eps.
+
+E_rel = ||x - x_ref|| / ||x_ref|| over the sampled entries.
+"""
+import os
+
+import numpy as np
+import pytest
+
+from oracle import ewald
+from paper_2606_28608_amd import workloads
+
+pytestmark = pytest.mark.gpu
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    return torch, torch.device("cuda:0")
+
+
+@pytest.fixture(scope="module")
+def pdmk():
+    from paper_2606_28608_amd import pdmk as m
+    m.lib()
+    return m
+
+
+def _gold(name):
+    data = np.loadtxt(os.path.join(HERE, "golden", name))
+    return data[:, 0].astype(np.int64), data[:, 1:]
+
+
+@pytest.fixture(scope="module")
+def shell(torch_dev):
+    torch, dev = torch_dev
+    L, src, q = workloads.shell3d(10_000_000, seed=3)
+    idx, ref = _gold("shell3d_n1e7_seed3.txt")
+    S = torch.tensor(src, dtype=torch.float64, device=dev)
+    Q = torch.tensor(q, dtype=torch.float64, device=dev)
+    return L, S, Q, idx, ref[:, 0]
+
+
+# (precision, eps, kappa, n_s): the planner's choice at eps = 1e-6 and the
+# default plan with its image halo, both precisions, both C3 tolerances
+C3_PLANS = [("mixed", 1e-6, 6.0, 300), ("fp64", 1e-6, 6.0, 400),
+            ("mixed", 1e-6, 3.0, 200), ("fp64", 1e-6, 3.0, 200),
+            ("mixed", 1e-3, 6.0, 300), ("fp64", 1e-3, 6.0, 300),
+            ("mixed", 1e-3, 3.0, 80), ("fp64", 1e-3, 3.0, 80)]
+
+
+@pytest.mark.parametrize("precision,eps,kappa,n_s", C3_PLANS)
+def test_c3_full_size_plans(pdmk, shell, precision, eps, kappa, n_s):
+    L, S, Q, idx, ref = shell
+    plan = pdmk.Plan(L, eps=eps, precision=precision, kappa=kappa, n_s=n_s)
+    pot = plan.eval(S, Q).cpu().numpy()
+    err = ewald.rel_l2(pot[idx], ref)
+    print("C3 %s eps=%g kappa=%g n_s=%d E_rel=%.3e" % (precision, eps, kappa, n_s, err))
+    assert err <= eps
+    st = plan.stats()
+    if kappa == 3.0:
+        assert st["n_images"] > 1.3 * st["n_src"]   # the halo is populated
+
+
+def test_c4_autograd_forces_full_size(pdmk, torch_dev):
+    """Energy U = 1/2 sum q Phi through periodic_potential: dU/dy_j = q_j
+    grad Phi(y_j) (minus the force) and dU/dq_j = Phi(y_j), both from the
+    adjoint evaluation, against the oracle at 64 sampled sources."""
+    torch, dev = torch_dev
+    idx, ref = _gold("clustered3d_n1e6_seed2_grad.txt")
+    L, src, q = workloads.clustered3d(1_000_000, seed=2)
+    plan = pdmk.Plan(L, eps=1e-6, grad=True, kappa=7.0)
+    S = torch.tensor(src, dtype=torch.float64, device=dev).requires_grad_(True)
+    Q = torch.tensor(q, dtype=torch.float64, device=dev).requires_grad_(True)
+    pot = pdmk.periodic_potential(plan, S, Q)
+    U = 0.5 * (Q * pot).sum()
+    U.backward()
+    dq = Q.grad.cpu().numpy()[idx]
+    ds = S.grad.cpu().numpy()[idx]
+    e_pot = ewald.rel_l2(pot.detach().cpu().numpy()[idx], ref[:, 0])
+    e_dq = ewald.rel_l2(dq, ref[:, 0])
+    e_f = ewald.rel_l2(ds, q[idx, None] * ref[:, 1:4])
+    print("C4 E_rel potential %.3e, dU/dq %.3e, forces %.3e" % (e_pot, e_dq, e_f))
+    assert e_pot <= 1e-6
+    assert e_dq <= 1e-6
+    assert e_f <= 1e-5
+
+
+@pytest.mark.parametrize("cell", ["triclinic", "cubic"])
+def test_mixed_below_fp32_floor(pdmk, torch_dev, cell):
+    """A mixed plan at eps = 1e-9 computes every stage in FP64 and meets eps."""
+    torch, dev = torch_dev
+    L, src, q = workloads.clustered3d(6000, seed=2, cell=cell)
+    ref = ewald.ewald(L, src, q)
+    S = torch.tensor(src, dtype=torch.float64, device=dev)
+    Q = torch.tensor(q, dtype=torch.float64, device=dev)
+    pm = pdmk.Plan(L, eps=1e-9, precision="mixed", kappa=3.0, n_s=60).eval(S, Q).cpu().numpy()
+    pd = pdmk.Plan(L, eps=1e-9, precision="fp64", kappa=3.0, n_s=60).eval(S, Q).cpu().numpy()
+    assert ewald.rel_l2(pm, ref) <= 1e-9
+    assert ewald.rel_l2(pm, pd) <= 1e-13
+
+
+def test_position_gradients_need_a_gradient_plan(pdmk, torch_dev):
+    torch, dev = torch_dev
+    L, src, q = workloads.clustered3d(500, seed=3)
+    plan = pdmk.Plan(L, eps=1e-6)
+    S = torch.tensor(src, dtype=torch.float64, device=dev).requires_grad_(True)
+    Q = torch.tensor(q, dtype=torch.float64, device=dev)
+    with pytest.raises(ValueError):
+        pdmk.periodic_potential(plan, S, Q)
+    # charge gradients need no gradient plan
+    Q2 = Q.clone().requires_grad_(True)
+    pdmk.periodic_potential(plan, S.detach(), Q2).sum().backward()
+    assert Q2.grad is not None

@@ -68,7 +68,8 @@ def test_c3_shell_sampled(pdmk, torch_dev, eps):
 
 
 def test_c3_full_size_golden(pdmk, torch_dev):
-    """N = 1e7 thin shell at the benchmark's launch configuration, against
+    """N = 1e7 thin shell with the default plan (kappa = 3, n_s = 200; the
+    benchmark's planned configurations are in test_gpu_configs.py), against
     oracle values stored by tests/golden/make_golden.py."""
     path = os.path.join(HERE, "golden", "shell3d_n1e7_seed3.txt")
     if not os.path.exists(path):
@@ -290,10 +291,10 @@ def test_runtime_planner(pdmk, torch_dev):
     assert ewald.rel_l2(pot, ewald.ewald(L, src, q)) <= 1e-6
 
 
-def test_bf16_plane_waves_at_eps_1e3(pdmk, torch_dev, monkeypatch):
+def test_bf16_plane_waves_at_eps_1e3(pdmk, torch_dev):
     """At eps >= 1e-3 mixed plans form the plane-wave products from BF16
     hi/lo splits with FP32 accumulation.  Both that path and the FP32 one
-    (diagnostic mask without bit 8) meet the tolerance, and they agree far
+    (fp32_stages without the BF16 bit) meet the tolerance, and they agree far
     below it."""
     torch, dev = torch_dev
     L, src, q = workloads.clustered3d(6000, seed=2)
@@ -301,12 +302,8 @@ def test_bf16_plane_waves_at_eps_1e3(pdmk, torch_dev, monkeypatch):
     S = torch.tensor(src, dtype=torch.float64, device=dev)
     Q = torch.tensor(q, dtype=torch.float64, device=dev)
     pots = {}
-    for mask in (None, "7"):
-        if mask is None:
-            monkeypatch.delenv("PDMK_MIXED_PARTS", raising=False)
-        else:
-            monkeypatch.setenv("PDMK_MIXED_PARTS", mask)
-        plan = pdmk.Plan(L, eps=1e-3, precision="mixed", kappa=3.0, n_s=60)
+    for mask in (0, 7):
+        plan = pdmk.Plan(L, eps=1e-3, precision="mixed", kappa=3.0, n_s=60, fp32_stages=mask)
         pots[mask] = plan.eval(S, Q).cpu().numpy()
         assert ewald.rel_l2(pots[mask], ref) <= 1e-3
-    assert ewald.rel_l2(pots[None], pots["7"]) <= 1e-4
+    assert ewald.rel_l2(pots[0], pots[7]) <= 1e-4
