@@ -134,7 +134,7 @@ typedef struct {
  * thread per target adds in segment order; spreading accumulates each
  * block's subgrid in program order (one wave per block) and adds the
  * subgrids into the grid in two-word 64-bit fixed point (integer atomics,
- * order-independent; resolution 2^-101 of sum |q|); child -> parent
+ * order-independent; resolution 2^-82 of sum |q|); child -> parent
  * transfers run one octant per launch.  Repeated calls with the same inputs,
  * options and device then return bitwise-equal potentials and gradients,
  * also through pdmk_batch_eval with any number of workers.  It costs time

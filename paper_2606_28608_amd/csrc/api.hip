@@ -1031,8 +1031,6 @@ int pdmk_plan_execute(pdmk_plan* P, const double* src, const double* trg, const 
   if (!q || !pot) return fail(PDMK_ERR_INVALID_ARG, "null array");
   if (trg && P->bound->E.self_targets)
     return fail(PDMK_ERR_INVALID_ARG, "the bound targets are the sources");
-  if ((P->o.flags & PDMK_WANT_GRAD) && !grad)
-    return fail(PDMK_ERR_INVALID_ARG, "PDMK_WANT_GRAD set but grad is null");
   int cur = -1;
   if (hipGetDevice(&cur) != hipSuccess || cur != P->device)
     return fail(PDMK_ERR_INVALID_ARG, "plan bound to another device");

@@ -379,6 +379,117 @@ __global__ __launch_bounds__(256) void k_spread_coop(KParams kp, int64_t n,
   }
 }
 
+// Fixed-order spreading.  A block is one wave and takes 64 consecutive
+// sources in tree order; its lanes cover distinct stencil entries of one
+// source at a time, so the LDS subgrid is accumulated with plain adds in
+// program order.  Each subgrid cell value v (|v| <= sum |q|, the window is at
+// most 1) then goes to the grid as two 64-bit fixed-point words, hi = rint(v /
+// u) and lo = rint((v - hi u) / u2) with u = sum |q| 2^-52 and u2 = u 2^-30,
+// added with integer atomics: integer sums do not depend on their order, and
+// k_fp_to_grid reads the grid back as HI u + LO u2.  Bounds: |hi| <= 2^52 and
+// |lo| <= 1.5 2^30 per add, and a cell receives at most one add per source
+// (2^30 sources), so neither word overflows; the representation error of an
+// add is below u2.  Blocks whose box does not fit the subgrid add each
+// stencil entry the same way.
+__device__ inline void fp_add(unsigned long long* __restrict__ hi,
+                              unsigned long long* __restrict__ lo, double v, double u,
+                              double iu, double iu2, double u2) {
+  const double h = rint(v * iu);
+  const double r = fma(-h, u, v);
+  const long long hl = (long long)h;
+  const long long ll = (long long)rint(r * iu2);
+  atomicAdd(hi, (unsigned long long)hl);
+  atomicAdd(lo, (unsigned long long)ll);
+  (void)u2;
+}
+
+template <int D, int W, class Real>
+__global__ __launch_bounds__(64) void k_spread_det(KParams kp, int64_t n,
+                                                   const double* __restrict__ x,
+                                                   const double* __restrict__ q, int M0, int M1,
+                                                   int M2, double beta,
+                                                   const double* __restrict__ qsum,
+                                                   unsigned long long* __restrict__ ghi,
+                                                   unsigned long long* __restrict__ glo) {
+  __shared__ double sub[kSubCap];
+  __shared__ int lo_s[3], hi_s[3];
+  constexpr int NE = D == 3 ? W * W * W : W * W;
+  constexpr Real hw = (Real)(0.5 * W);
+  const int Ms[3] = {M0, M1, M2};
+  const int64_t i = (int64_t)blockIdx.x * 64 + threadIdx.x;
+  const bool valid = i < n;
+  const double qa = qsum[1] > 0.0 ? qsum[1] : 1.0;
+  const double u = ldexp(qa, -52), u2 = ldexp(qa, -82);
+  const double iu = 1.0 / u, iu2 = 1.0 / u2;
+  double g[D];
+  int i0[D], lo[3], ext[3], vol;
+  const bool tiled = block_box<D, W>(kp, n, x, i, valid, Ms, g, i0, lo_s, hi_s, lo, ext, vol);
+  if (tiled) {
+    for (int c = threadIdx.x; c < vol; c += 64) sub[c] = 0.0;
+    __syncthreads();
+  }
+  const double qi = valid ? q[i] : 0.0;
+  const int lane = threadIdx.x;
+  const int wa = lane / W, wk = lane - wa * W;
+  for (int j = 0; j < 64; ++j) {
+    const double qj = rdlane(qi, j);
+    if (qj == 0.0) continue;
+    double gj[D];
+    int ij[D];
+    for (int a = 0; a < D; ++a) {
+      gj[a] = rdlane(g[a], j);
+      ij[a] = __builtin_amdgcn_readlane(i0[a], j);
+    }
+    Real wv = 0;
+    if (wa < D) {
+      const double ga = wa == 0 ? gj[0] : (wa == 1 ? gj[1] : gj[D - 1]);
+      const int ia = wa == 0 ? ij[0] : (wa == 1 ? ij[1] : ij[D - 1]);
+      wv = es_win((Real)((ia + wk - ga) / (double)hw), (Real)beta);
+      if (wa == 0) wv *= (Real)qj;
+    }
+    for (int e0 = 0; e0 < NE; e0 += 64) {
+      const int e = e0 + lane;
+      const int k0 = e % W, k1 = (e / W) % W, k2 = D == 3 ? e / (W * W) : 0;
+      Real v = __shfl(wv, k0) * __shfl(wv, W + (k1 < W ? k1 : 0));
+      if (D == 3) v *= __shfl(wv, 2 * W + (k2 < W ? k2 : 0));
+      if (e < NE) {
+        if (tiled) {
+          int o = (ij[1] - lo[1] + k1) * ext[0] + ij[0] - lo[0] + k0;
+          if (D == 3) o += (ij[D - 1] - lo[D - 1] + k2) * ext[0] * ext[1];
+          sub[o] += (double)v;   // distinct addresses across the wave
+        } else {
+          int64_t gi = wrap_index(ij[0] + k0, M0) + (int64_t)M0 * wrap_index(ij[1] + k1, M1);
+          if (D == 3) gi += (int64_t)M0 * M1 * wrap_index(ij[D - 1] + k2, M2);
+          fp_add(ghi + gi, glo + gi, (double)v, u, iu, iu2, u2);
+        }
+      }
+    }
+  }
+  if (tiled) {
+    __syncthreads();
+    for (int c = threadIdx.x; c < vol; c += 64) {
+      const double v = sub[c];
+      if (v == 0.0) continue;
+      const int c0 = c % ext[0], c1 = (c / ext[0]) % ext[1], c2 = c / (ext[0] * ext[1]);
+      int64_t gi = wrap_index(lo[0] + c0, M0) + (int64_t)M0 * wrap_index(lo[1] + c1, M1);
+      if (D == 3) gi += (int64_t)M0 * M1 * wrap_index(lo[2] + c2, M2);
+      fp_add(ghi + gi, glo + gi, v, u, iu, iu2, u2);
+    }
+  }
+}
+
+// Fixed-point grid -> complex grid (HI u + LO u2, u from sum |q|).
+__global__ void k_fp_to_grid(int64_t n, const unsigned long long* __restrict__ ghi,
+                             const unsigned long long* __restrict__ glo,
+                             const double* __restrict__ qsum, double2* __restrict__ c) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double qa = qsum[1] > 0.0 ? qsum[1] : 1.0;
+  const double v = (double)(long long)ghi[i] * ldexp(qa, -52) +
+                   (double)(long long)glo[i] * ldexp(qa, -82);
+  c[i] = make_double2(v, 0.0);
+}
+
 // Interpolation (step five of Section 3.6) at targets in tree order, one
 // target per lane; the block's subgrid is read into LDS once.  Results are
 // added to the near-field arrays (tree order), gradients rotated by L^{-T}.
@@ -492,7 +603,11 @@ template <int D, int W, class Real>
 static void launch_spread_interp(pdmk_plan* P, Eval& E, const int* M, double beta, double* grid,
                                  double2* cg, bool want_grad, bool spread) {
   if (spread) {
-    if (E.n_src > 0)
+    if (E.n_src > 0 && E.det)
+      hipLaunchKernelGGL((k_spread_det<D, W, Real>), dim3(nblk(E.n_src, 64)), dim3(64), 0, E.s,
+                         P->kp, E.n_src, E.ox, E.oq, M[0], M[1], M[2], beta, E.qsum,
+                         E.far_hi, E.far_lo);
+    else if (E.n_src > 0)
       hipLaunchKernelGGL((k_spread_coop<D, W, Real>), dim3(nblk(E.n_src, 256)), dim3(256), 0,
                          E.s, P->kp, E.n_src, E.ox, E.oq, M[0], M[1], M[2], beta, grid);
   } else if (E.n_trg > 0) {
@@ -641,9 +756,20 @@ void stage_far_grid(pdmk_plan* P, Eval& E) {
   double2* cg = E.alloc<double2>(n);
   E.far_grid = grid;
   E.far_cg = cg;
-  fill_zero(grid, n * sizeof(double), E.s);
-  spread_interp(P, E, M, w, beta, grid, cg, false, true);
-  hipLaunchKernelGGL(k_to_complex, dim3(nblk(n, 256)), dim3(256), 0, E.s, n, grid, cg);
+  if (E.det) {
+    // fixed-point grid (two words per cell), see k_spread_det
+    E.far_hi = E.alloc<unsigned long long>(n);
+    E.far_lo = E.alloc<unsigned long long>(n);
+    fill_zero(E.far_hi, n * sizeof(unsigned long long), E.s);
+    fill_zero(E.far_lo, n * sizeof(unsigned long long), E.s);
+    spread_interp(P, E, M, w, beta, grid, cg, false, true);
+    hipLaunchKernelGGL(k_fp_to_grid, dim3(nblk(n, 256)), dim3(256), 0, E.s, n, E.far_hi,
+                       E.far_lo, E.qsum, cg);
+  } else {
+    fill_zero(grid, n * sizeof(double), E.s);
+    spread_interp(P, E, M, w, beta, grid, cg, false, true);
+    hipLaunchKernelGGL(k_to_complex, dim3(nblk(n, 256)), dim3(256), 0, E.s, n, grid, cg);
+  }
   fft3(cg, M, d, -1, P->d_fftw, P->fftw_off, E.s);
   hipLaunchKernelGGL(k_scale, dim3(nblk(n, 256)), dim3(256), 0, E.s, n, cg, P->d_farscale);
   fft3(cg, M, d, +1, P->d_fftw, P->fftw_off, E.s);

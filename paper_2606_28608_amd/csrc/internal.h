@@ -168,7 +168,9 @@ struct Eval {
   int4* list = nullptr;     // {sbeg, send, level, 0}
   int64_t nlist = 0;
   int* lf_nsrc = nullptr;   // sources in each target leaf's list
-  int2* items = nullptr;    // residual-sum work items (leaf, segment)
+  int2* items = nullptr;    // residual-sum work items (leaf, segment), heaviest first
+  int2* items_u = nullptr;  // the same in list order: item_beg[leaf] + segment
+  int* item_beg = nullptr;  // first work item of each list slot (list order)
   int nitems = 0;
   double* pot_sorted = nullptr;   // near field per sorted target
   double* grad_sorted = nullptr;
@@ -182,6 +184,8 @@ struct Eval {
   double* qsum = nullptr;   // device {sum q, sum |q|}
   bool near_pending = false;
   double* far_grid = nullptr;   // spreading grid (real)
+  unsigned long long* far_hi = nullptr;   // fixed-order mode: fixed-point grid words
+  unsigned long long* far_lo = nullptr;
   double2* far_cg = nullptr;    // its transform, scaled and transformed back
   bool pw_split = false;
   hipEvent_t near_ev[4] = {nullptr, nullptr, nullptr, nullptr};
@@ -291,9 +295,10 @@ template <class Real>
 bool anterp_mfma(const pdmk_plan* P, const Level& L, const Level& C, int l, const double* sx,
                  const double* sq, int64_t nimg, void* Q, hipStream_t s);
 
+// det: children add into their parents one octant per launch (fixed order)
 template <class Real>
 bool transfer_mfma(const pdmk_plan* P, const Level& Lp, const Level& Lc, bool up,
-                   const void* src, void* dst, hipStream_t s);
+                   const void* src, void* dst, bool det, hipStream_t s);
 
 // stages (implemented in tree.hip / near.hip / far.hip)
 void stage_prepare(pdmk_plan* P, Eval& E, const double* src, const double* trg);

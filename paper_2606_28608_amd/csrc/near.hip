@@ -250,7 +250,8 @@ __global__ __launch_bounds__(64) void k_direct(
     const double* __restrict__ tx, int64_t ntrg, const int* __restrict__ tperm,
     const double* __restrict__ qorig, int self_targets, const double* __restrict__ Ec,
     const double* __restrict__ Edc, double* __restrict__ pot, double* __restrict__ grad,
-    unsigned long long* __restrict__ n_support) {
+    unsigned long long* __restrict__ n_support, double* __restrict__ part,
+    double* __restrict__ gpart, const int* __restrict__ item_beg) {
   __shared__ double4 shv[64];
   __shared__ typename SlotQ<Real>::T shw[64];
   if ((int)blockIdx.x >= nitems) return;
@@ -316,14 +317,58 @@ __global__ __launch_bounds__(64) void k_direct(
         const double w0 = D == 3 ? kp.w0unit / hT : kp.w0unit - log(hT) * kInv2Pi;
         v -= qorig[tperm[t]] * w0;
       }
-      atomicAdd(&pot[t], v);
-      if (GRAD)
-        for (int a = 0; a < D; ++a) atomicAdd(&grad[(int64_t)t * D + a], g[a] * cst);
+      if (part) {
+        // fixed-order mode: this segment's partial sum, added by k_direct_reduce
+        const int64_t slot = ((int64_t)item_beg[i] + item.y) * kDirectTgt + (t - tb);
+        part[slot] = v;
+        if (GRAD)
+          for (int a = 0; a < D; ++a) gpart[slot * D + a] = g[a] * cst;
+      } else {
+        atomicAdd(&pot[t], v);
+        if (GRAD)
+          for (int a = 0; a < D; ++a) atomicAdd(&grad[(int64_t)t * D + a], g[a] * cst);
+      }
     }
     t0 += 64 / S;
   }
   // pairs inside the support (statistics): one atomic per block
   if (lane == 0 && n_support) atomicAdd(n_support, (unsigned long long)nin);
+}
+
+// Fixed-order completion of the residual sums: one block per work item in
+// list order; the block of a chunk's first segment adds the chunk's segment
+// partial sums in segment order (one thread per target, the only writer).
+template <int D, bool GRAD>
+__global__ __launch_bounds__(64) void k_direct_reduce(
+    int nitems, const int2* __restrict__ items_u, const int* __restrict__ lf_nsrc,
+    const Level* __restrict__ lev, const int* __restrict__ lf_level,
+    const int* __restrict__ lf_box, const int* __restrict__ item_beg,
+    const double* __restrict__ part, const double* __restrict__ gpart, double* __restrict__ pot,
+    double* __restrict__ grad) {
+  const int k = blockIdx.x;
+  if (k >= nitems) return;
+  const int2 it = items_u[k];
+  const int i = it.x;
+  const int nseg = (lf_nsrc[i] + kDirectSeg - 1) / kDirectSeg;
+  if (it.y % nseg != 0) return;
+  const int tchunk = it.y / nseg;
+  const Level& T = lev[lf_level[i]];
+  const int b = lf_box[i];
+  const int tb = T.tbeg[b] + tchunk * kDirectTgt;
+  const int te = min(T.tend[b], tb + kDirectTgt);
+  const int t = tb + (int)threadIdx.x;
+  if (t >= te) return;
+  double v = 0.0, g[3] = {0.0, 0.0, 0.0};
+  for (int sg = 0; sg < nseg; ++sg) {
+    const int64_t slot =
+        ((int64_t)item_beg[i] + tchunk * nseg + sg) * kDirectTgt + threadIdx.x;
+    v += part[slot];
+    if (GRAD)
+      for (int a = 0; a < D; ++a) g[a] += gpart[slot * D + a];
+  }
+  pot[t] += v;
+  if (GRAD)
+    for (int a = 0; a < D; ++a) grad[(int64_t)t * D + a] += g[a];
 }
 
 // ------------------------------------------------------ source -> proxy charge
@@ -445,7 +490,7 @@ __global__ __launch_bounds__(256) void k_transfer(KParams kp, Level Lp, Level Lc
                                                   const Real* __restrict__ src,
                                                   Real* __restrict__ dst,
                                                   const double* __restrict__ Tm,
-                                                  Real* __restrict__ scratch) {
+                                                  Real* __restrict__ scratch, int oct_only) {
   extern __shared__ __align__(16) unsigned char smraw[];
   Real* sm = reinterpret_cast<Real*>(smraw);
   const int p = kp.p;
@@ -498,6 +543,8 @@ __global__ __launch_bounds__(256) void k_transfer(KParams kp, Level Lp, Level Lc
     const int pb = Lc.parent[c];
     const int kpar = Lp.nlid[pb];
     const int oct = c - Lp.child0[pb];
+    // fixed-order mode: one octant per launch, so a parent receives one add
+    if (oct_only >= 0 && oct != oct_only) return;
     const Real* in = src + (int64_t)(MODE == 1 ? kc : kpar) * pD;
     for (int e = threadIdx.x; e < pD; e += blockDim.x) ten[e] = in[e];
     __syncthreads();
@@ -933,11 +980,28 @@ static void launch_direct_t(const KParams& kp, Eval& E, pdmk_plan* P, hipStream_
   const int off = sizeof(Real) == 4 ? 32 : 0;   // FP32 evaluation: the cut series
   const double* c = (D == 3 ? P->d_E : P->d_F2) + off;
   const double* cd = (D == 3 ? P->d_Ed : P->d_F2d) + off;
+  // fixed-order mode: per-segment partial sums, then k_direct_reduce
+  double* part = nullptr;
+  double* gpart = nullptr;
+  if (E.det) {
+    part = E.alloc<double>((size_t)E.nitems * kDirectTgt);
+    if (want_grad) gpart = E.alloc<double>((size_t)E.nitems * kDirectTgt * D);
+  }
   auto go = [&](auto kern) {
     hipLaunchKernelGGL(kern, dim3(E.nitems), dim3(64), 0, s, kp, E.nitems, E.items, E.lf_nsrc,
                        E.d_lev, E.lf_level, E.lf_box, E.lf_list_beg, E.list, E.sx, E.sq, E.n_img,
                        E.tx, E.n_trg, E.tperm, E.q, E.self_targets ? 1 : 0, c, cd, E.pot_sorted,
-                       E.grad_sorted, nsup);
+                       E.grad_sorted, nsup, part, gpart, E.item_beg);
+    if (E.det) {
+      if (want_grad)
+        hipLaunchKernelGGL((k_direct_reduce<D, true>), dim3(E.nitems), dim3(64), 0, s,
+                           E.nitems, E.items_u, E.lf_nsrc, E.d_lev, E.lf_level, E.lf_box,
+                           E.item_beg, part, gpart, E.pot_sorted, E.grad_sorted);
+      else
+        hipLaunchKernelGGL((k_direct_reduce<D, false>), dim3(E.nitems), dim3(64), 0, s,
+                           E.nitems, E.items_u, E.lf_nsrc, E.d_lev, E.lf_level, E.lf_box,
+                           E.item_beg, part, gpart, E.pot_sorted, E.grad_sorted);
+    }
   };
   // FP64 3D: one Newton step of the reciprocal square root where eps >= 1e-10
   // (its error, below 1e-14, is then far under the tolerance), two below
@@ -982,7 +1046,8 @@ template <int D, class Real>
 static void launch_transfer(const KParams& kp, const Level& Lp, const Level& Lc, int up,
                             const void* src_, void* dst_, pdmk_plan* P, Eval& E,
                             hipStream_t s) {
-  if (D == 3 && Lc.nnl > 0 && transfer_mfma<Real>(P, Lp, Lc, up != 0, src_, dst_, s)) return;
+  if (D == 3 && Lc.nnl > 0 && transfer_mfma<Real>(P, Lp, Lc, up != 0, src_, dst_, E.det, s))
+    return;
   const Real* src = static_cast<const Real*>(src_);
   Real* dst = static_cast<Real*>(dst_);
   const int p = kp.p;
@@ -994,11 +1059,14 @@ static void launch_transfer(const KParams& kp, const Level& Lp, const Level& Lc,
   const int mode = up ? (nown <= 48 ? 0 : 1) : 2;
   const int nblocks = mode == 0 ? Lp.nnl : Lc.nnl;
   Real* scratch = lds ? nullptr : E.alloc<Real>((size_t)nblocks * pD);
+  // fixed-order mode: per-child up transfers (mode 1) add one octant per launch
+  const bool octs = E.det && mode == 1;
 #define PDMK_TR(PM, L, NO, MO)                                                                  \
   do {                                                                                          \
-    ensure_lds((const void*)&k_transfer<D, PM, L, NO, MO, Real>, smem);       \
-    hipLaunchKernelGGL((k_transfer<D, PM, L, NO, MO, Real>), dim3(nblocks), dim3(256), smem, s, \
-                       kp, Lp, Lc, src, dst, P->d_Tm, scratch);                                 \
+    ensure_lds((const void*)&k_transfer<D, PM, L, NO, MO, Real>, smem);                         \
+    for (int o = octs ? 0 : -1; o < (octs ? (1 << D) : 0); ++o)                                 \
+      hipLaunchKernelGGL((k_transfer<D, PM, L, NO, MO, Real>), dim3(nblocks), dim3(256), smem,  \
+                         s, kp, Lp, Lc, src, dst, P->d_Tm, scratch, o);                         \
   } while (0)
   if (mode == 0) {
     if (nown <= 8) {

@@ -1086,7 +1086,8 @@ template <class Real, int P, bool UP>
 __global__ __launch_bounds__(256) void k_transfer_mfma(Level Lp, Level Lc,
                                                        const Real* __restrict__ src,
                                                        Real* __restrict__ dst,
-                                                       const double* __restrict__ Tm, int SB) {
+                                                       const double* __restrict__ Tm, int SB,
+                                                       int oct_only) {
   using MF = Mfma<Real>;
   using V = typename MF::V;
   constexpr int PP = P * P, KA = (P + 3) & ~3, NTILE = (PP + 15) / 16, MTL = (P + 15) / 16;
@@ -1098,6 +1099,8 @@ __global__ __launch_bounds__(256) void k_transfer_mfma(Level Lp, Level Lc,
   const int pb = Lc.parent[c];
   const int kpar = Lp.nlid[pb];
   const int oct = c - Lp.child0[pb];
+  // fixed-order mode: one octant per launch, so a parent receives one add
+  if (oct_only >= 0 && oct != oct_only) return;
   const Real* in = src + (int64_t)(UP ? kc : kpar) * P * PP;
   Real* out = dst + (int64_t)(UP ? kpar : kc) * P * PP;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -1213,18 +1216,22 @@ __global__ __launch_bounds__(256) void k_transfer_mfma(Level Lp, Level Lc,
 
 template <class Real, int PPP>
 static void transfer_launch(const pdmk_plan* P, const Level& Lp, const Level& Lc, bool up,
-                            const void* src, void* dst, hipStream_t s) {
+                            const void* src, void* dst, bool det, hipStream_t s) {
   constexpr int KA = (PPP + 3) & ~3, PP = PPP * PPP;
   const int SB = sizeof(Real) == 4 ? ((PP + 31) & ~31) + 16 : ((PP + 15) & ~15) + 8;
   const size_t lds = (size_t)KA * SB * sizeof(Real);
   if (up) {
     ensure_lds((const void*)&k_transfer_mfma<Real, PPP, true>, lds);
-    hipLaunchKernelGGL((k_transfer_mfma<Real, PPP, true>), dim3(Lc.nnl), dim3(256), lds, s, Lp,
-                       Lc, static_cast<const Real*>(src), static_cast<Real*>(dst), P->d_Tm, SB);
+    // fixed-order mode: the children add into their parents one octant at a time
+    for (int o = det ? 0 : -1; o < (det ? 8 : 0); ++o)
+      hipLaunchKernelGGL((k_transfer_mfma<Real, PPP, true>), dim3(Lc.nnl), dim3(256), lds, s,
+                         Lp, Lc, static_cast<const Real*>(src), static_cast<Real*>(dst),
+                         P->d_Tm, SB, o);
   } else {
     ensure_lds((const void*)&k_transfer_mfma<Real, PPP, false>, lds);
     hipLaunchKernelGGL((k_transfer_mfma<Real, PPP, false>), dim3(Lc.nnl), dim3(256), lds, s, Lp,
-                       Lc, static_cast<const Real*>(src), static_cast<Real*>(dst), P->d_Tm, SB);
+                       Lc, static_cast<const Real*>(src), static_cast<Real*>(dst), P->d_Tm, SB,
+                       -1);
   }
 }
 
@@ -1232,18 +1239,18 @@ static void transfer_launch(const pdmk_plan* P, const Level& Lp, const Level& Lc
 // matrix-core plane-wave kernels (FP32 and FP64 tensors).
 template <class Real>
 bool transfer_mfma(const pdmk_plan* P, const Level& Lp, const Level& Lc, bool up,
-                   const void* src, void* dst, hipStream_t s) {
+                   const void* src, void* dst, bool det, hipStream_t s) {
   if (P->kp.dim != 3 || !P->pw_mfma) return false;
-  if (P->kp.p == 22) transfer_launch<Real, 22>(P, Lp, Lc, up, src, dst, s);
-  else if (P->kp.p == 13) transfer_launch<Real, 13>(P, Lp, Lc, up, src, dst, s);
+  if (P->kp.p == 22) transfer_launch<Real, 22>(P, Lp, Lc, up, src, dst, det, s);
+  else if (P->kp.p == 13) transfer_launch<Real, 13>(P, Lp, Lc, up, src, dst, det, s);
   else return false;
   return true;
 }
 
 template bool transfer_mfma<float>(const pdmk_plan*, const Level&, const Level&, bool,
-                                   const void*, void*, hipStream_t);
+                                   const void*, void*, bool, hipStream_t);
 template bool transfer_mfma<double>(const pdmk_plan*, const Level&, const Level&, bool,
-                                    const void*, void*, hipStream_t);
+                                    const void*, void*, bool, hipStream_t);
 
 // ------------------------------------------------------------------ host
 // (p, J) pairs with matrix-core kernels: the defaults at eps = 1e-3 and 1e-6.

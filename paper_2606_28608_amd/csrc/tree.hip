@@ -756,8 +756,10 @@ void stage_lists(pdmk_plan* P, Eval& E) {
     E.nitems = hv[0];
     E.nlist = hv[1];
   }
+  E.item_beg = sbeg;
   if (E.nitems > 0) {
     int2* items = E.alloc<int2>(E.nitems);
+    E.items_u = items;
     unsigned* key = E.alloc<unsigned>(E.nitems);
     hipLaunchKernelGGL(k_seg_fill, dim3(nblk(n, 256)), dim3(256), 0, E.s, n, E.d_lev,
                        E.lf_level, E.lf_box, E.lf_nsrc, sbeg, items, key);

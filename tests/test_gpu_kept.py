@@ -53,12 +53,15 @@ def test_execute_new_charges(pdmk, torch_dev, precision):
     plan.status()
     got = got.cpu().numpy()
     fresh = plan.eval(S, _t(torch_dev, q2)).cpu().numpy()
-    assert ewald.rel_l2(got, fresh) <= 1e-12
+    # same tree and arithmetic; atomics reorder sums (FP32 ones in the mixed
+    # proxy transfers), so equal to the rounding of the arithmetic type
+    tol = 1e-12 if precision == "fp64" else 1e-6
+    assert ewald.rel_l2(got, fresh) <= tol
     assert ewald.rel_l2(got, ewald.ewald(L, src, q2)) <= 1e-6
     # the bound charges again: the first result
     again = plan.execute(_t(torch_dev, q)).cpu().numpy()
     plan.status()
-    assert ewald.rel_l2(again, p1) <= 1e-12
+    assert ewald.rel_l2(again, p1) <= tol
 
 
 def test_execute_separate_targets_and_gradient(pdmk, torch_dev):
@@ -167,12 +170,13 @@ def test_c4_forces_against_finite_differences(pdmk, torch_dev):
     differences of U with h = 1e-5 on the frozen tree (pdmk_plan_execute with
     displaced positions), for 100 seeded particles x 3 axes.
 
-    The central difference carries a truncation error ~ (h / r)^2 of the
-    derivative of the closest pair terms (r down to ~5e-4 here), so the same
-    difference with h / 2 is combined by Richardson extrapolation, D =
-    (4 D(h/2) - D(h)) / 3 (error ~ (h / r)^4), and D is held to 1e-6 per
-    component relative to the largest component of the sample; the raw
-    h = 1e-5 differences are held to the truncation estimate."""
+    A central difference carries a truncation error ~ (h / r)^2 of the
+    derivative from the closest pair terms (r ~ 1e-4 in this cluster: about
+    1e-2 at h = 1e-5), which says nothing about the method.  The differences
+    at h, h/2 and h/4 are therefore combined by Romberg extrapolation
+    (error ~ (h / r)^6), held to 1e-6 per component relative to the largest
+    component of the sample; the raw h = 1e-5 differences are held to their
+    own truncation estimate."""
     torch, dev = torch_dev
     L, src, q = workloads.clustered3d(1_000_000, seed=2)
     plan = pdmk.Plan(L, eps=1e-6, grad=True, kappa=7.0)
@@ -195,20 +199,22 @@ def test_c4_forces_against_finite_differences(pdmk, torch_dev):
         return float((0.5 * Q * (up - dn)).sum().item()) / (2.0 * h)
 
     h = 1e-5
-    fd = np.zeros((len(idx), 3))
-    fd2 = np.zeros((len(idx), 3))
+    D = np.zeros((3, len(idx), 3))   # central differences at h, h/2, h/4
     for k, i in enumerate(idx):
         for a in range(3):
-            fd[k, a] = energy_diff(int(i), a, h)
-            fd2[k, a] = energy_diff(int(i), a, h / 2)
+            for lv in range(3):
+                D[lv, k, a] = energy_diff(int(i), a, h / 2 ** lv)
     plan.status()
     ref = dU[idx]
     scale = np.abs(ref).max()
-    rich = (4.0 * fd2 - fd) / 3.0
-    err_rich = np.abs(rich - ref).max() / scale
-    err_raw = np.abs(fd - ref).max() / scale
-    trunc = np.abs(fd - fd2).max() * 4.0 / 3.0 / scale
-    print("C4 FD: h=1e-5 max rel %.3e (truncation estimate %.3e), Richardson %.3e"
-          % (err_raw, trunc, err_rich))
-    assert err_rich <= 1e-6
+    r1 = (4.0 * D[1] - D[0]) / 3.0
+    r1b = (4.0 * D[2] - D[1]) / 3.0
+    romberg = (16.0 * r1b - r1) / 15.0
+    err_rom = np.abs(romberg - ref).max() / scale
+    err_raw = np.abs(D[0] - ref).max() / scale
+    trunc = np.abs(D[0] - D[1]).max() * 4.0 / 3.0 / scale
+    l2 = np.linalg.norm(romberg - ref) / np.linalg.norm(ref)
+    print("C4 FD: h=1e-5 max rel %.3e (truncation estimate %.3e); Romberg max rel %.3e, "
+          "l2 rel %.3e" % (err_raw, trunc, err_rom, l2))
+    assert err_rom <= 1e-6
     assert err_raw <= 2.0 * trunc + 1e-6
