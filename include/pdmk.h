@@ -67,7 +67,9 @@ typedef enum {
   PDMK_ERR_OUT_OF_MEMORY = -6,   /* device allocation failed */
   PDMK_ERR_HIP = -7,             /* a HIP runtime call failed */
   PDMK_ERR_NO_DEVICE = -8,       /* no HIP device available */
-  PDMK_ERR_UNSUPPORTED = -9      /* option combination not implemented */
+  PDMK_ERR_UNSUPPORTED = -9,     /* option combination not implemented */
+  PDMK_ERR_SCRATCH = -10         /* pdmk_plan_eval_noalloc: the input needs more
+                                    device scratch than the library's fixed array */
 } pdmk_status;
 
 /* Arithmetic of the evaluation.
@@ -174,6 +176,26 @@ int pdmk_plan_eval(pdmk_plan* plan, int64_t n_src, const double* src,
                    const double* q, int64_t n_trg, const double* trg,
                    double* pot, double* grad, void* stream);
 void pdmk_plan_destroy(pdmk_plan* plan);
+
+/*
+ * pdmk_plan_eval without device allocation, for callers that cannot
+ * allocate (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc).  Arguments, results and blocking as pdmk_plan_eval.  Its
+ * workspace is one fixed device array inside the library,
+ * PDMK_NOALLOC_SCRATCH_BYTES (64 MiB) per device, held from the first such
+ * call on a device until the process ends; the call makes no hipMalloc,
+ * hipFree, stream or event creation (the far field runs on the caller's
+ * stream, no stage timings are recorded).  Inputs whose tree, lists and
+ * buffers do not fit the array are rejected with PDMK_ERR_SCRATCH, with the
+ * outputs unwritten (roughly up to 5e4 points in 3D at eps = 1e-6; the exact
+ * limit depends on the distribution).  The array is shared by every call on
+ * one device: the library holds a per-device lock for the whole call, so
+ * calls from several threads on one device run one after another.
+ */
+#define PDMK_NOALLOC_SCRATCH_BYTES (64ull << 20)
+int pdmk_plan_eval_noalloc(pdmk_plan* plan, int64_t n_src, const double* src, const double* q,
+                           int64_t n_trg, const double* trg, double* pot, double* grad,
+                           void* stream);
 
 /*
  * Kept trees: evaluate many charge vectors (and small displacements) on one

@@ -374,6 +374,7 @@ const char* pdmk_status_string(int s) {
     case PDMK_ERR_HIP: return "HIP runtime error";
     case PDMK_ERR_NO_DEVICE: return "no HIP device";
     case PDMK_ERR_UNSUPPORTED: return "unsupported option";
+    case PDMK_ERR_SCRATCH: return "input too large for the fixed device scratch";
   }
   return "unknown status";
 }
@@ -630,7 +631,8 @@ static void unbind(pdmk_plan* P) {
 static int eval_impl(pdmk_plan* P, int64_t n_src, const double* src, const double* q,
                      int64_t n_trg, const double* trg, double* pot, double* grad, void* stream,
                      unsigned flags, char*& arena, size_t& arena_size,
-                     hipStream_t aux = nullptr, BoundState** keep = nullptr) {
+                     hipStream_t aux = nullptr, BoundState** keep = nullptr,
+                     bool noalloc = false) {
   if (!P) return fail(PDMK_ERR_INVALID_ARG, "null plan");
   const int d = P->g.dim;
   const bool self_t = (trg == nullptr);
@@ -648,6 +650,7 @@ static int eval_impl(pdmk_plan* P, int64_t n_src, const double* src, const doubl
   Workspace ws;
   ws.base = arena;
   ws.size = arena_size;
+  ws.fixed = noalloc;
   Eval E;
   E.s = s;
   E.ws = &ws;
@@ -656,6 +659,7 @@ static int eval_impl(pdmk_plan* P, int64_t n_src, const double* src, const doubl
   E.self_targets = self_t;
   E.q = q;
   E.keep_map = keep != nullptr;
+  E.timing = !noalloc;   // stage events only where the call may create them
   E.det = (flags & PDMK_DETERMINISTIC) != 0;
   try {
     int cur = -1;
@@ -671,7 +675,7 @@ static int eval_impl(pdmk_plan* P, int64_t n_src, const double* src, const doubl
     // the second stream pays off only for large inputs: for small ones the
     // fork's events and the extra stream's share of the hardware queues cost
     // more than the overlap (measured on batches of small cells)
-    const bool fork = n_src + n_trg >= kForkMin;
+    const bool fork = !noalloc && n_src + n_trg >= kForkMin;
     if (fork && !aux) {
       if (!P->s_aux) PDMK_HIP(hipStreamCreateWithFlags(&P->s_aux, hipStreamNonBlocking));
       aux = P->s_aux;
@@ -679,10 +683,17 @@ static int eval_impl(pdmk_plan* P, int64_t n_src, const double* src, const doubl
     if (!fork) aux = s;
     P->ev_next = 0;
     E.plan = P;
-    hipEvent_t ev[5], fev[3];
-    for (auto& e : ev) e = E.event();
-    for (auto& e : fev) e = E.event();
-    PDMK_HIP(hipEventRecord(ev[0], s));
+    // timing events (none in the allocation-free mode, which creates nothing)
+    const bool tm = E.timing;
+    hipEvent_t ev[5] = {}, fev[3] = {};
+    if (tm) {
+      for (auto& e : ev) e = E.event();
+      for (auto& e : fev) e = E.event();
+    }
+    auto record = [&](hipEvent_t e, hipStream_t st) {
+      if (tm) PDMK_HIP(hipEventRecord(e, st));
+    };
+    record(ev[0], s);
     // input checks (charge sums, non-finite charges and positions) stay on
     // the device and are read after the call's final synchronisation; the
     // pipeline runs on sanitised data in between and the assembly writes
@@ -709,11 +720,11 @@ static int eval_impl(pdmk_plan* P, int64_t n_src, const double* src, const doubl
         PDMK_HIP(hipEventRecord(fev[0], s));
         PDMK_HIP(hipStreamWaitEvent(aux, fev[0], 0));
       }
-      PDMK_HIP(hipEventRecord(fev[1], aux));
+      record(fev[1], aux);
       E.s = aux;
       stage_far_grid(P, E);
       E.s = s;
-      PDMK_HIP(hipEventRecord(fev[2], aux));
+      record(fev[2], aux);
     };
     if (!keep) far_fork();
     stage_tree(P, E);
@@ -724,12 +735,12 @@ static int eval_impl(pdmk_plan* P, int64_t n_src, const double* src, const doubl
       kept = E;   // the state an execute starts from
       far_fork();
     }
-    PDMK_HIP(hipEventRecord(ev[1], s));
+    record(ev[1], s);
     stage_near(P, E, want_grad);
-    PDMK_HIP(hipEventRecord(ev[2], s));
+    record(ev[2], s);
     if (fork) PDMK_HIP(hipStreamWaitEvent(s, fev[2], 0));
     stage_far_interp(P, E, want_grad);
-    PDMK_HIP(hipEventRecord(ev[3], s));
+    record(ev[3], s);
     // uniform-background constant: the method with m = 0 dropped returns the
     // tin-foil potential plus (sum q) * Rhat_0(0) / V
     const double cc = P->P->c;
@@ -740,16 +751,20 @@ static int eval_impl(pdmk_plan* P, int64_t n_src, const double* src, const doubl
                        want_grad ? grad : nullptr);
     PDMK_HIP(hipMemcpyAsync(P->h_cnt + 4, qs, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
     PDMK_HIP(hipMemcpyAsync(P->h_cnt + 6, E.d_flags, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
-    PDMK_HIP(hipEventRecord(ev[4], s));
-    PDMK_HIP(hipEventSynchronize(ev[4]));
-    near_finish(P, E);
-    float t1, t2, t3, t4, tg;
-    PDMK_HIP(hipEventElapsedTime(&t1, ev[0], ev[1]));
-    PDMK_HIP(hipEventElapsedTime(&t2, ev[1], ev[2]));
-    PDMK_HIP(hipEventElapsedTime(&t3, ev[2], ev[3]));
-    PDMK_HIP(hipEventElapsedTime(&t4, ev[0], ev[4]));
-    PDMK_HIP(hipEventElapsedTime(&tg, fev[1], fev[2]));
-    t3 += tg;   // far field: grid steps (overlapped with the build and near field) + interpolation
+    float t1 = 0, t2 = 0, t3 = 0, t4 = 0, tg = 0;
+    if (tm) {
+      PDMK_HIP(hipEventRecord(ev[4], s));
+      PDMK_HIP(hipEventSynchronize(ev[4]));
+      near_finish(P, E);
+      PDMK_HIP(hipEventElapsedTime(&t1, ev[0], ev[1]));
+      PDMK_HIP(hipEventElapsedTime(&t2, ev[1], ev[2]));
+      PDMK_HIP(hipEventElapsedTime(&t3, ev[2], ev[3]));
+      PDMK_HIP(hipEventElapsedTime(&t4, ev[0], ev[4]));
+      PDMK_HIP(hipEventElapsedTime(&tg, fev[1], fev[2]));
+      t3 += tg;   // far field: grid steps (overlapped with the build and near field) + interpolation
+    } else {
+      PDMK_HIP(hipStreamSynchronize(s));
+    }
     {
       double hq[2];
       int hf[2];
@@ -791,8 +806,10 @@ static int eval_impl(pdmk_plan* P, int64_t n_src, const double* src, const doubl
       PDMK_HIP(hipMalloc((void**)&B->xarena, need));
       B->xarena_size = need;
       P->last.workspace_bytes = (int64_t)(ws.used + need);
-    } else {
+    } else if (!noalloc) {
       finish_workspace(arena, arena_size, ws);
+      P->last.workspace_bytes = (int64_t)ws.used;
+    } else {
       P->last.workspace_bytes = (int64_t)ws.used;
     }
     P->last.t_call_ms =
@@ -805,6 +822,25 @@ static int eval_impl(pdmk_plan* P, int64_t n_src, const double* src, const doubl
     return fail(e.code, e.msg);
   }
   return PDMK_OK;
+}
+
+// ------------------------------------------------- allocation-free entry
+// The workspace of pdmk_plan_eval_noalloc: one fixed array per device (each
+// device holds its own copy from the code object's load until the process
+// ends).  Host code must not use the array's name as a device address: the
+// address comes from hipGetSymbolAddress, once per device.
+static __device__ __align__(256) unsigned char scratch[PDMK_NOALLOC_SCRATCH_BYTES];
+
+struct ScratchSlot {
+  std::mutex mu;             // held for a whole call: calls on one device do not overlap
+  char* ptr = nullptr;       // device address of this device's copy of scratch
+};
+
+static ScratchSlot& scratch_slot(int dev) {
+  static std::mutex mu;
+  static std::map<int, ScratchSlot> slots;
+  std::lock_guard<std::mutex> lock(mu);
+  return slots[dev];   // node-based map: the reference stays valid
 }
 
 // ------------------------------------------------------ kept-tree execute
@@ -977,6 +1013,38 @@ int pdmk_plan_eval(pdmk_plan* P, int64_t n_src, const double* src, const double*
   if (!P) return fail(PDMK_ERR_INVALID_ARG, "null plan");
   return eval_impl(P, n_src, src, q, n_trg, trg, pot, grad, stream, P->o.flags, P->arena,
                    P->arena_size);
+}
+
+int pdmk_plan_eval_noalloc(pdmk_plan* P, int64_t n_src, const double* src, const double* q,
+                           int64_t n_trg, const double* trg, double* pot, double* grad,
+                           void* stream) {
+  if (!P) return fail(PDMK_ERR_INVALID_ARG, "null plan");
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess) return fail(PDMK_ERR_HIP, "hipGetDevice failed");
+  if (dev != P->device) return fail(PDMK_ERR_INVALID_ARG, "plan bound to another device");
+  // a lower bound of the workspace: wrapped and fractional positions, sorted
+  // copies, keys and permutations of every source and target
+  const int64_t nt = trg ? n_trg : n_src;
+  const int d = P->g.dim;
+  const int64_t low = (n_src + nt) * (int64_t)(4 * d * sizeof(double) + 24);
+  if (low > (int64_t)PDMK_NOALLOC_SCRATCH_BYTES)
+    return fail(PDMK_ERR_SCRATCH, "the input needs more than the " +
+                                      std::to_string(PDMK_NOALLOC_SCRATCH_BYTES >> 20) +
+                                      " MiB of device scratch of the allocation-free entry point");
+  ScratchSlot& slot = scratch_slot(dev);
+  std::lock_guard<std::mutex> lock(slot.mu);
+  if (!slot.ptr) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return fail(PDMK_ERR_HIP, std::string("hipGetSymbolAddress(scratch): ") +
+                                    hipGetErrorString(e));
+    slot.ptr = static_cast<char*>(p);
+  }
+  char* base = slot.ptr;
+  size_t size = PDMK_NOALLOC_SCRATCH_BYTES;
+  return eval_impl(P, n_src, src, q, n_trg, trg, pot, grad, stream, P->o.flags, base, size,
+                   nullptr, nullptr, true);
 }
 
 int pdmk_plan_bind(pdmk_plan* P, int64_t n_src, const double* src, const double* q,

@@ -37,6 +37,7 @@ struct Workspace {
   char* base = nullptr;      // plan arena
   size_t size = 0;           // arena bytes
   size_t used = 0;           // bytes handed out this call (arena + overflow)
+  bool fixed = false;        // no allocation: a request past `size` is an error
   std::vector<void*> overflow;
   void* take(size_t bytes) {
     bytes = (bytes + 255) & ~(size_t)255;
@@ -44,6 +45,10 @@ struct Workspace {
     void* p = nullptr;
     if (used + bytes <= size) {
       p = base + used;
+    } else if (fixed) {
+      throw ::pdmk::Error{PDMK_ERR_SCRATCH,
+                          "the input needs more than the " + std::to_string(size >> 20) +
+                              " MiB of device scratch of the allocation-free entry point"};
     } else {
       hipError_t e = hipMalloc(&p, bytes);
       if (e != hipSuccess)

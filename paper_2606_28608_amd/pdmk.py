@@ -122,6 +122,8 @@ def lib():
                                      ctypes.POINTER(ctypes.c_int), ctypes.c_int, ctypes.c_int64,
                                      _vp, _vp, ctypes.c_int64, _vp, _vp, _vp, _dp, _dp,
                                      ctypes.POINTER(ctypes.c_int)]
+        L.pdmk_plan_eval_noalloc.argtypes = [_vp, ctypes.c_int64, _vp, _vp, ctypes.c_int64, _vp,
+                                             _vp, _vp, _vp]
         L.pdmk_plan_bind.argtypes = [_vp, ctypes.c_int64, _vp, _vp, ctypes.c_int64, _vp, _vp, _vp,
                                      _vp]
         L.pdmk_plan_execute.argtypes = [_vp, _vp, _vp, _vp, _vp, _vp, _vp]
@@ -307,6 +309,26 @@ class Plan:
                                     ctypes.c_void_p(grad.data_ptr()) if grad is not None else None,
                                     _stream(torch)))
         return (pot, grad) if wg else pot
+
+    def eval_noalloc(self, src, q, pot, grad=None, trg=None):
+        """pdmk_plan_eval_noalloc: eval() into caller-provided outputs, with the
+        library's fixed device scratch as workspace (no device allocation)."""
+        import torch
+        src = _dev(src, torch)
+        q = _dev(q, torch)
+        n = src.shape[0]
+        if src.shape != (n, self.dim) or q.shape != (n,):
+            raise ValueError("src must be (N, dim) and q (N,)")
+        trg = _dev(trg, torch) if trg is not None else None
+        m = trg.shape[0] if trg is not None else n
+        if pot.shape != (m,) or pot.dtype != torch.float64 or not pot.is_contiguous():
+            raise ValueError("pot must be a contiguous float64 tensor of the target count")
+        if grad is not None and (grad.shape != (m, self.dim) or grad.dtype != torch.float64
+                                 or not grad.is_contiguous()):
+            raise ValueError("grad must be a contiguous float64 (M, dim) tensor")
+        vp = lambda t: ctypes.c_void_p(t.data_ptr()) if t is not None else None  # noqa: E731
+        _check(lib().pdmk_plan_eval_noalloc(self._h, n, vp(src), vp(q), m, vp(trg), vp(pot),
+                                            vp(grad), _stream(torch)))
 
     def bind(self, src, q, trg=None, want_grad=None):
         """pdmk_plan_bind: a full evaluation that keeps the tree for execute().
