@@ -178,6 +178,21 @@ int pdmk_plan_eval(pdmk_plan* plan, int64_t n_src, const double* src,
 void pdmk_plan_destroy(pdmk_plan* plan);
 
 /*
+ * The two halves of one evaluation (for checking each on its own): the
+ * far field pot_far = the interpolated Fourier sum of eq:W0p over the modes
+ * of eq:Mi with m = 0 omitted (Section 3.6), which includes every
+ * source's own W_0(0); and the near field pot_near = everything else: the
+ * plane-wave and residual sums of G - W_0 over the images within r_c
+ * (Section 3.5) minus the self terms W_0(0) q of Section 3.8, plus the
+ * uniform-background constant for non-neutral charges.  pot_near + pot_far
+ * is what pdmk_plan_eval returns.  Arguments as pdmk_plan_eval (potentials
+ * only; pot_near and pot_far: n_trg doubles, DEVICE).  Blocks.
+ */
+int pdmk_plan_eval_parts(pdmk_plan* plan, int64_t n_src, const double* src, const double* q,
+                         int64_t n_trg, const double* trg, double* pot_near, double* pot_far,
+                         void* stream);
+
+/*
  * pdmk_plan_eval without device allocation, for callers that cannot
  * allocate (code under HIP graph capture, tight serving loops, harnesses that
  * forbid hipMalloc).  Arguments, results and blocking as pdmk_plan_eval.  Its

@@ -632,7 +632,7 @@ static int eval_impl(pdmk_plan* P, int64_t n_src, const double* src, const doubl
                      int64_t n_trg, const double* trg, double* pot, double* grad, void* stream,
                      unsigned flags, char*& arena, size_t& arena_size,
                      hipStream_t aux = nullptr, BoundState** keep = nullptr,
-                     bool noalloc = false) {
+                     bool noalloc = false, double* pot_far = nullptr) {
   if (!P) return fail(PDMK_ERR_INVALID_ARG, "null plan");
   const int d = P->g.dim;
   const bool self_t = (trg == nullptr);
@@ -739,6 +739,7 @@ static int eval_impl(pdmk_plan* P, int64_t n_src, const double* src, const doubl
     stage_near(P, E, want_grad);
     record(ev[2], s);
     if (fork) PDMK_HIP(hipStreamWaitEvent(s, fev[2], 0));
+    if (pot_far) E.far_out = E.alloc<double>(n_trg);
     stage_far_interp(P, E, want_grad);
     record(ev[3], s);
     // uniform-background constant: the method with m = 0 dropped returns the
@@ -749,6 +750,10 @@ static int eval_impl(pdmk_plan* P, int64_t n_src, const double* src, const doubl
                        E.pot_sorted, E.grad_sorted, qs, E.d_flags, cnn,
                        (flags & PDMK_ALLOW_NONNEUTRAL) ? 1 : 0, P->kp, pot,
                        want_grad ? grad : nullptr);
+    if (pot_far)
+      hipLaunchKernelGGL(k_assemble, dim3(nblk(n_trg, 256)), dim3(256), 0, s, n_trg, d,
+                         E.tperm, E.far_out, nullptr, qs, E.d_flags, 0.0,
+                         (flags & PDMK_ALLOW_NONNEUTRAL) ? 1 : 0, P->kp, pot_far, nullptr);
     PDMK_HIP(hipMemcpyAsync(P->h_cnt + 4, qs, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
     PDMK_HIP(hipMemcpyAsync(P->h_cnt + 6, E.d_flags, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
     float t1 = 0, t2 = 0, t3 = 0, t4 = 0, tg = 0;
@@ -1013,6 +1018,16 @@ int pdmk_plan_eval(pdmk_plan* P, int64_t n_src, const double* src, const double*
   if (!P) return fail(PDMK_ERR_INVALID_ARG, "null plan");
   return eval_impl(P, n_src, src, q, n_trg, trg, pot, grad, stream, P->o.flags, P->arena,
                    P->arena_size);
+}
+
+int pdmk_plan_eval_parts(pdmk_plan* P, int64_t n_src, const double* src, const double* q,
+                         int64_t n_trg, const double* trg, double* pot_near, double* pot_far,
+                         void* stream) {
+  if (!P) return fail(PDMK_ERR_INVALID_ARG, "null plan");
+  if ((trg ? n_trg : n_src) > 0 && (!pot_near || !pot_far))
+    return fail(PDMK_ERR_INVALID_ARG, "null output");
+  return eval_impl(P, n_src, src, q, n_trg, trg, pot_near, nullptr, stream, P->o.flags,
+                   P->arena, P->arena_size, nullptr, nullptr, false, pot_far);
 }
 
 int pdmk_plan_eval_noalloc(pdmk_plan* P, int64_t n_src, const double* src, const double* q,

@@ -613,12 +613,12 @@ static void launch_spread_interp(pdmk_plan* P, Eval& E, const int* M, double bet
   } else if (E.n_trg > 0) {
     if (want_grad)
       hipLaunchKernelGGL((k_interp_t<D, W, true, Real>), dim3(nblk(E.n_trg, 256)), dim3(256), 0,
-                         E.s, P->kp, E.n_trg, E.tx, M[0], M[1], M[2], beta, cg, E.pot_sorted,
-                         E.grad_sorted);
+                         E.s, P->kp, E.n_trg, E.tx, M[0], M[1], M[2], beta, cg,
+                         E.far_out ? E.far_out : E.pot_sorted, E.grad_sorted);
     else
       hipLaunchKernelGGL((k_interp_t<D, W, false, Real>), dim3(nblk(E.n_trg, 256)), dim3(256),
-                         0, E.s, P->kp, E.n_trg, E.tx, M[0], M[1], M[2], beta, cg, E.pot_sorted,
-                         E.grad_sorted);
+                         0, E.s, P->kp, E.n_trg, E.tx, M[0], M[1], M[2], beta, cg,
+                         E.far_out ? E.far_out : E.pot_sorted, E.grad_sorted);
   }
 }
 
@@ -778,6 +778,7 @@ void stage_far_grid(pdmk_plan* P, Eval& E) {
 void stage_far_interp(pdmk_plan* P, Eval& E, bool want_grad) {
   const Geometry& g = P->g;
   int M[3] = {g.fgrid[0], g.fgrid[1], g.dim == 3 ? g.fgrid[2] : 1};
+  if (E.far_out) fill_zero(E.far_out, E.n_trg * sizeof(double), E.s);
   spread_interp(P, E, M, P->mp.nufft_w, P->nufft_beta, E.far_grid, E.far_cg, want_grad, false);
 }
 

@@ -188,6 +188,8 @@ struct Eval {
   int* d_flags = nullptr;   // device {non-finite charge, non-finite position}
   double* qsum = nullptr;   // device {sum q, sum |q|}
   bool near_pending = false;
+  double* far_out = nullptr;    // separate far-field part (tree order), else null:
+                                // the interpolation adds into pot_sorted
   double* far_grid = nullptr;   // spreading grid (real)
   unsigned long long* far_hi = nullptr;   // fixed-order mode: fixed-point grid words
   unsigned long long* far_lo = nullptr;

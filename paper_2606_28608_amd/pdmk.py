@@ -122,6 +122,8 @@ def lib():
                                      ctypes.POINTER(ctypes.c_int), ctypes.c_int, ctypes.c_int64,
                                      _vp, _vp, ctypes.c_int64, _vp, _vp, _vp, _dp, _dp,
                                      ctypes.POINTER(ctypes.c_int)]
+        L.pdmk_plan_eval_parts.argtypes = [_vp, ctypes.c_int64, _vp, _vp, ctypes.c_int64, _vp,
+                                           _vp, _vp, _vp]
         L.pdmk_plan_eval_noalloc.argtypes = [_vp, ctypes.c_int64, _vp, _vp, ctypes.c_int64, _vp,
                                              _vp, _vp, _vp]
         L.pdmk_plan_bind.argtypes = [_vp, ctypes.c_int64, _vp, _vp, ctypes.c_int64, _vp, _vp, _vp,
@@ -309,6 +311,21 @@ class Plan:
                                     ctypes.c_void_p(grad.data_ptr()) if grad is not None else None,
                                     _stream(torch)))
         return (pot, grad) if wg else pot
+
+    def eval_parts(self, src, q, trg=None):
+        """pdmk_plan_eval_parts: (near, far) halves of the potential."""
+        import torch
+        src = _dev(src, torch)
+        q = _dev(q, torch)
+        n = src.shape[0]
+        trg = _dev(trg, torch) if trg is not None else None
+        m = trg.shape[0] if trg is not None else n
+        near = torch.empty(m, dtype=torch.float64, device=src.device)
+        far = torch.empty(m, dtype=torch.float64, device=src.device)
+        vp = lambda t: ctypes.c_void_p(t.data_ptr()) if t is not None else None  # noqa: E731
+        _check(lib().pdmk_plan_eval_parts(self._h, n, vp(src), vp(q), m, vp(trg), vp(near),
+                                          vp(far), _stream(torch)))
+        return near, far
 
     def eval_noalloc(self, src, q, pot, grad=None, trg=None):
         """pdmk_plan_eval_noalloc: eval() into caller-provided outputs, with the
