@@ -11,6 +11,13 @@ Both arithmetic modes are timed: the mixed-precision evaluation gives
 `value`; the FP64 evaluation is reported beside it under "fp64".  Each mode
 reports its relative l2 error on stored oracle values at 64 sampled sources.
 
+Beside the timed steps each mode also reports (fewer steps each): the same
+workload at eps = 1e-3 with its own planned (kappa, n_s); the default plan
+(kappa = 3, image halo populated); and one run with every stage on one
+stream, whose per-stage timings give the far field's stand-alone spreading,
+transform and interpolation times.  A result whose sampled error exceeds eps
+is reported with "parity_ok": false and no value.
+
 Prints one JSON line.  --gpus above 1 is rejected: this build runs on one GPU.
 """
 from __future__ import annotations
@@ -18,6 +25,7 @@ from __future__ import annotations
 import argparse
 import hashlib
 import json
+import math
 import os
 import statistics
 import subprocess
@@ -80,7 +88,16 @@ def parse():
                     help="host workers of the batched measurement")
     ap.add_argument("--copy-calib", action="store_true",
                     help="only run a plain 1 GiB device copy (calibrates HBM byte counters)")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="skip the eps=1e-3, default-plan and one-stream runs")
+    ap.add_argument("--cpu-full", default="10000,100000",
+                    help="sizes of the full-N uniform oracle runs ('' to skip)")
     return ap.parse_args()
+
+
+def progress(msg):
+    """A progress line on stderr (the JSON result goes to stdout)."""
+    print("bench: " + msg, file=sys.stderr, flush=True)
 
 
 def kernel_source_hash():
@@ -113,6 +130,8 @@ def load_traffic(mode, kernel, kappa, n_s):
 def run_mode(pdmk, L, S, Q, n, eps, precision, steps, warmup, gold, over=None):
     import numpy as np
     import torch
+    progress("%s eps=%g %s: %d warm-up + %d timed steps" % (precision, eps, over or "defaults",
+                                                          warmup, steps))
     plan = pdmk.Plan(L, eps=eps, precision=precision, **(over or {}))
     g = plan.geometry()
     torch.cuda.synchronize()
@@ -170,14 +189,18 @@ def roofline_all(r, mode, plan):
     st, sm = r["stats"], r["stages_ms"]
     out = {}
     fv, fs = flop_per_pair(st["series_len"])
-    flop = st["n_direct_pairs"] * fv + st["n_support_pairs"] * fs
+    # pairs the kernel evaluates: the list pairs left after the per-pass reach
+    # test (a source farther than h + rho from the centre of a pass's targets
+    # is not staged); the test itself costs 9 flop per candidate source and pass
+    staged = st.get("n_staged_pairs", 0) or st["n_direct_pairs"]
+    flop = staged * fv + st["n_support_pairs"] * fs + st["n_direct_pairs"] / 64.0 * 9.0
     t = sm["t_direct_ms"] * 1e-3
     out["k_direct"] = {"bound": "alu", "achieved": flop / t / 1e12 if t > 0 else 0.0,
                        "peak": PEAK_TFLOPS[mode], "unit": "TFLOP/s", "launch_ms": sm["t_direct_ms"],
                        "launches": 1, "flop_per_launch": flop,
-                       "pairs_visited": st["n_direct_pairs"],
+                       "pairs_listed": st["n_direct_pairs"], "pairs_staged": staged,
                        "pairs_in_support": st["n_support_pairs"],
-                       "flop_per_visited_pair": fv, "flop_per_support_pair": fs}
+                       "flop_per_staged_pair": fv, "flop_per_support_pair": fs}
     P, J = plan["porder"], plan["npw"]
     nb = _ball_modes(J)
     tr = pw_fma_per_box(P, J)
@@ -206,6 +229,37 @@ def roofline_all(r, mode, plan):
                              "flop_per_launch": 8.0 * nb * st["n_pw_pairs"] / max(1, nlev)}
     for v in out.values():
         v["frac"] = v["achieved"] / v["peak"]
+    return out
+
+
+def far_field(r1, n, plan, mode):
+    """Stand-alone far-field stages (every stage on one stream): spreading,
+    transforms + scaling, interpolation; algorithmic HBM bytes: spreading
+    reads positions and charges (32 B per source) and writes the grid once
+    (8 B per cell); interpolation reads positions (24 B), reads and writes
+    the potential (16 B) and reads the complex grid once (16 B per cell);
+    flops: w^d multiply-adds per point each way."""
+    sm = r1["stages_ms"]
+    g = plan["fourier_grid"]
+    cells = 1
+    for m in g:
+        cells *= m
+    w = plan["nufft_w"]
+    out = {}
+    for name, key, by in (("k_spread_coop", "t_spread_ms", 32.0 * n + 8.0 * cells),
+                          ("k_interp_t", "t_interp_ms", 40.0 * n + 16.0 * cells)):
+        t = sm.get(key, 0.0) * 1e-3
+        out[name] = {"bound": "hbm", "launch_ms": sm.get(key, 0.0), "launches": 1,
+                     "bytes_per_launch": by,
+                     "achieved": by / t / 1e9 if t > 0 else 0.0, "peak": PEAK_HBM_GBS,
+                     "unit": "GB/s", "tflops": 2.0 * n * w ** 3 / t / 1e12 if t > 0 else 0.0}
+        out[name]["frac"] = out[name]["achieved"] / PEAK_HBM_GBS
+    out["fft_and_scaling_ms"] = sm.get("t_fft_ms", 0.0)
+    out["fourier_grid"] = g
+    out["note"] = ("one-stream run of the same plan (no overlap with the near field); "
+                   "the spreading and interpolation are bound by LDS atomics and the "
+                   "w^d stencil arithmetic, not by HBM")
+    out["precision"] = mode
     return out
 
 
@@ -257,6 +311,7 @@ def child(args):
     elif not args.no_tune:
         # runtime planning of (kappa, n_s) on this input, before the timed region
         t0 = time.perf_counter()
+        progress("%s: planning (kappa, n_s) on the input" % args.precision)
         k, ns, table = pdmk.tune(L, S, Q, eps=args.eps, precision=args.precision, trials=1)
         over = {"kappa": k, "n_s": ns}
         tuning = {"seconds": round(time.perf_counter() - t0, 2),
@@ -264,9 +319,38 @@ def child(args):
     r = run_mode(pdmk, L, S, Q, n, args.eps, args.precision, args.steps, args.warmup, gold, over)
     r["tuning"] = tuning
     g = r.pop("plan")
-    r["plan"] = {"kappa": g.kappa, "n_s": g.n_s, "porder": g.porder, "npw": g.npw,
-                 "nufft_w": g.nufft_w, "fourier_grid": list(g.fgrid)}
+
+    def plan_of(g):
+        return {"kappa": g.kappa, "n_s": g.n_s, "porder": g.porder, "npw": g.npw,
+                "nufft_w": g.nufft_w, "fourier_grid": list(g.fgrid)}
+
+    r["plan"] = plan_of(g)
     r["roofline"] = roofline(r, args.precision, r["plan"])
+    if not args.no_extra:
+        def brief(x, eps):
+            d = {k: x[k] for k in ("value", "ms_per_step", "median_ms", "e_rel_sampled")}
+            d["plan"] = plan_of(x.pop("plan"))
+            d["parity_ok"] = x["e_rel_sampled"] is None or x["e_rel_sampled"] <= eps
+            d["n_images"] = x["stats"]["n_images"]
+            d["stages_ms"] = x["stages_ms"]
+            return d
+        extra = {}
+        # the second C3 tolerance, with its own planned (kappa, n_s)
+        k3, ns3, _ = pdmk.tune(L, S, Q, eps=1e-3, precision=args.precision, trials=1)
+        extra["eps_1e-3"] = brief(run_mode(pdmk, L, S, Q, n, 1e-3, args.precision, 3, 1, gold,
+                                           {"kappa": k3, "n_s": ns3}), 1e-3)
+        # the default plan, with its image halo (N'/N ~ 1.45 at kappa = 3)
+        extra["default_plan"] = brief(run_mode(pdmk, L, S, Q, n, args.eps, args.precision, 3, 1,
+                                               gold, {}), args.eps)
+        # every stage on one stream: stand-alone stage times
+        one = run_mode(pdmk, L, S, Q, n, args.eps, args.precision, 3, 1, gold,
+                       dict(over, one_stream=True))
+        r["far_field"] = far_field(one, n, r["plan"], args.precision)
+        extra["one_stream"] = brief(one, args.eps)
+        r["extra"] = extra
+        for k in ("k_spread_coop", "k_interp_t"):
+            r["roofline"]["kernels"][k] = {kk: r["far_field"][k][kk]
+                                           for kk in ("achieved", "frac", "launch_ms", "launches")}
     print(json.dumps(r))
 
 
@@ -304,6 +388,7 @@ def child_batch(args):
            "workers": args.batch_workers}
     if not args.no_batch_tune:
         # batch autotuner: (kappa, n_s) per size class, then the same timing
+        progress("batch %s: autotuning the size classes" % args.precision)
         t0 = time.perf_counter()
         k, ns = B.tune(offs, src, q, trials=3)
         res["tune_s"] = time.perf_counter() - t0
@@ -332,14 +417,86 @@ def run_child(args, mode, batch=False):
         cmd.append("--no-check")
     if args.no_tune:
         cmd.append("--no-tune")
+    if args.no_extra:
+        cmd.append("--no-extra")
     if args.kappa > 0 and args.n_s > 0:
         cmd += ["--kappa", str(args.kappa), "--n-s", str(args.n_s)]
+    progress("child %s%s" % (mode, " batch" if batch else ""))
     p = subprocess.run(cmd, stdout=subprocess.PIPE, text=True)
     if p.returncode != 0:
         print("bench.py: %s%s run failed with status %d"
               % (mode, " batch" if batch else "", p.returncode), file=sys.stderr)
         sys.exit(p.returncode if p.returncode > 0 else 1)
     return json.loads(p.stdout.strip().splitlines()[-1])
+
+
+def cpu_baseline(args, n):
+    """The Ewald oracle as it stands, on this host's cores (OpenMP threads).
+
+    Sampled mode on the benchmark's own system: the structure factor S(m)
+    runs over all N sources once, then each sampled target costs a
+    real-space sum over all sources and images plus a reciprocal sum, the
+    targets spread over the threads.  A run with one target per thread and
+    one with nine per thread give the S(m) time and the time of one round of
+    targets (per target: a round / threads); the full-N figure is
+    extrapolated from them (labelled as such).  Full runs (every source a target, splitting
+    parameter balanced by the oracle's cost model) on uniform +-1 systems at
+    the sizes of --cpu-full give measured full-N rates."""
+    import numpy as np
+    from oracle import ewald as E
+    from paper_2606_28608_amd import workloads as W
+    progress("cpu baseline: oracle on %d threads" % E.threads())
+    L, src, q = W.shell3d(n, seed=3)
+    k = args.cpu_sample if args.cpu_sample > 0 else E.threads()
+    idx = np.random.default_rng(7).choice(n, 9 * k, replace=False)
+    t0 = time.perf_counter()
+    E.ewald_sampled(L, src, q, idx[:k], alpha=args.cpu_alpha)
+    t_one = time.perf_counter() - t0
+    progress("cpu baseline: %d targets in %.1f s" % (k, t_one))
+    t0 = time.perf_counter()
+    E.ewald_sampled(L, src, q, idx, alpha=args.cpu_alpha)
+    t_k = time.perf_counter() - t0
+    progress("cpu baseline: %d targets in %.1f s" % (len(idx), t_k))
+    rnd = max(t_k - t_one, 0.0) / 8.0
+    per_target = rnd / k
+    t_s = max(t_one - rnd, 0.0)
+    full_est = t_s + n * per_target
+    out = {"value": len(idx) / t_k, "unit": "particles/s", "cores": E.threads(),
+           "kind": "oracle",
+           "sample": "Ewald potential at %d sampled sources of the same N=%d shell system, "
+                     "splitting alpha=%g (structure factor over all N sources, real-space sum "
+                     "over all N sources and their images); %.1f s"
+                     % (len(idx), n, args.cpu_alpha, t_k),
+           "structure_factor_s": t_s, "per_target_s": per_target,
+           "extrapolated_full_n": {"seconds": full_est, "particles_per_s": n / full_est,
+                                   "label": "EXTRAPOLATED: S(m) time + N x per-target time "
+                                            "at this alpha, not measured"}}
+    full = []
+    sizes = [int(float(x)) for x in args.cpu_full.split(",") if x.strip()]
+    for m in sizes:
+        rng = np.random.default_rng(11)
+        u = rng.random((m, 3))
+        Lu = W.TRICLINIC3D_L
+        sm = u @ Lu.T
+        qm = np.where(np.arange(m) % 2 == 0, 1.0, -1.0)
+        progress("cpu baseline: full oracle run at N=%d" % m)
+        t0 = time.perf_counter()
+        E.ewald(Lu, sm, qm)
+        tm = time.perf_counter() - t0
+        progress("cpu baseline: N=%d in %.1f s" % (m, tm))
+        full.append({"n": m, "seconds": tm, "particles_per_s": m / tm,
+                     "workload": "uniform, triclinic a1=(1,0,0) a2=(0.4,1.2,0) a3=(0.3,0.5,2), "
+                                 "+-1 charges, every source a target"})
+    if full:
+        out["full_runs"] = full
+        if len(full) >= 2:
+            a = math.log(full[-1]["seconds"] / full[-2]["seconds"]) / \
+                math.log(full[-1]["n"] / full[-2]["n"])
+            out["full_runs_fit"] = {"exponent": a, "label": "EXTRAPOLATED from the last two "
+                                    "full runs: t ~ N^exponent",
+                                    "seconds_at_1e6": full[-1]["seconds"] *
+                                    (1e6 / full[-1]["n"]) ** a}
+    return out
 
 
 def main():
@@ -368,21 +525,7 @@ def main():
 
     cpu = None
     if not args.no_cpu_baseline:
-        import numpy as np
-        from oracle import ewald as E
-        from paper_2606_28608_amd import workloads as W
-        L, src, q = W.shell3d(n, seed=3)
-        ns = args.cpu_sample if args.cpu_sample > 0 else E.threads()
-        idx = np.random.default_rng(7).choice(n, ns, replace=False)
-        t1 = time.perf_counter()
-        E.ewald_sampled(L, src, q, idx, alpha=args.cpu_alpha)
-        tc = time.perf_counter() - t1
-        cpu = {"value": ns / tc, "unit": "particles/s", "cores": E.threads(),
-               "kind": "oracle",
-               "sample": "Ewald potential at %d sampled sources of the same N=%d shell "
-                         "system, splitting alpha=%g (structure factor over all N sources, "
-                         "real-space sum over all N sources and their images); %.1f s"
-                         % (ns, n, args.cpu_alpha, tc)}
+        cpu = cpu_baseline(args, n)
 
     def summary(x):
         d = {k: x[k] for k in ("value", "ms_per_step", "median_ms", "step_ms",
@@ -413,14 +556,28 @@ def main():
         "e_rel_sampled": r["e_rel_sampled"],
         "stages_ms": r["stages_ms"],
         "counts": {k: r["stats"][k] for k in ("n_images", "n_levels", "n_boxes", "n_leaves",
-                                             "n_nonleaf", "n_direct_pairs", "n_support_pairs",
-                                             "n_pw_pairs", "n_pwout_boxes", "n_pwin_boxes",
-                                             "workspace_bytes")},
+                                             "n_nonleaf", "n_direct_pairs", "n_staged_pairs",
+                                             "n_support_pairs", "n_pw_pairs", "n_pwout_boxes",
+                                             "n_pwin_boxes", "workspace_bytes")},
         "roofline": r["roofline"],
         "cpu_baseline": cpu,
     }
+    # no value for a result that misses the tolerance on the stored oracle values
+    ok = r["e_rel_sampled"] is None or r["e_rel_sampled"] <= args.eps
+    out["parity_ok"] = ok
+    if not ok:
+        out["value"] = None
+    if "far_field" in r:
+        out["far_field"] = r["far_field"]
+    if "extra" in r:
+        out["extra"] = {head: r["extra"]}
     for m in modes[1:]:
         out[m] = summary(res[m])
+        out[m]["parity_ok"] = res[m]["e_rel_sampled"] is None or \
+            res[m]["e_rel_sampled"] <= args.eps
+        if "extra" in res[m]:
+            out.setdefault("extra", {})[m] = res[m]["extra"]
+            out[m]["far_field"] = res[m].get("far_field")
     if not args.no_batch:
         out["batch"] = {"workload": "%d random triclinic cells (edges 1, U[1,8], U[1,8], angles "
                                     "U[60,120] deg), N per cell log-uniform in [500, 5e4], even "

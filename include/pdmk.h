@@ -101,10 +101,14 @@ enum {
   PDMK_ALLOW_NONNEUTRAL = 2,   /* accept sum q != 0 (uniform background) */
   PDMK_DETERMINISTIC = 4,      /* fixed-order reductions: repeated calls on the same
                                   input return bitwise-equal results (see below) */
-  PDMK_VECTOR_PLANE_WAVES = 8  /* use the vector-ALU plane-wave, anterpolation,
+  PDMK_VECTOR_PLANE_WAVES = 8, /* use the vector-ALU plane-wave, anterpolation,
                                   transfer and leaf-evaluation kernels instead of the
                                   matrix-core ones (same arithmetic type; for
                                   comparing the two implementations) */
+  PDMK_ONE_STREAM = 16         /* run every stage on the caller's stream (no second
+                                  stream for the far field's grid steps; each stage
+                                  then has the device to itself, so its timings in
+                                  pdmk_stats are stand-alone durations) */
 };
 
 typedef struct {
@@ -114,7 +118,7 @@ typedef struct {
   double kappa;     /* root cube side r_c = L_min / kappa (Section 5); <= 0: default */
   int n_s;          /* leaf capacity (Section 5, Table tab:tuning); <= 0: default */
   unsigned flags;   /* PDMK_WANT_GRAD | PDMK_ALLOW_NONNEUTRAL | PDMK_DETERMINISTIC |
-                       PDMK_VECTOR_PLANE_WAVES */
+                       PDMK_VECTOR_PLANE_WAVES | PDMK_ONE_STREAM */
   int porder;       /* Chebyshev proxy points per axis; <= 0: chosen from eps */
   int npw;          /* plane-wave half count J per axis (modes -J..J); <= 0: from eps */
   int nufft_w;      /* spreading-window width in grid cells; <= 0: from eps (two
@@ -407,6 +411,12 @@ typedef struct {
   double t_pwout_ms, t_pwin_ms;     /* time of the outgoing / incoming plane-wave kernels */
   double t_pwtr_ms;                 /* time of the colleague translation kernel (matrix-core
                                        path; 0 where the incoming kernel translates itself) */
+  int64_t n_staged_pairs;           /* pairs the residual sums evaluated after dropping the
+                                       list sources out of reach of each 64-target pass */
+  double t_spread_ms;               /* far field: spreading (on the second stream unless
+                                       PDMK_ONE_STREAM, so it may overlap other stages) */
+  double t_fft_ms;                  /* far field: forward FFT, scaling, inverse FFT */
+  double t_interp_ms;               /* far field: interpolation at the targets */
 } pdmk_stats;
 int pdmk_plan_stats(const pdmk_plan* plan, pdmk_stats* out);
 int pdmk_batch_stats(const pdmk_batch* batch, int sys, pdmk_stats* out);

@@ -440,7 +440,7 @@ static int validate_opts(const pdmk_opts* o) {
   if (o->porder > 40 || o->npw > 64 || o->nufft_w > 16 || o->sigma > 4.0)
     return fail(PDMK_ERR_INVALID_ARG, "porder <= 40, npw <= 64, nufft_w <= 16, sigma <= 4");
   if (o->flags & ~(unsigned)(PDMK_WANT_GRAD | PDMK_ALLOW_NONNEUTRAL | PDMK_DETERMINISTIC |
-                             PDMK_VECTOR_PLANE_WAVES))
+                             PDMK_VECTOR_PLANE_WAVES | PDMK_ONE_STREAM))
     return fail(PDMK_ERR_INVALID_ARG, "unknown flag");
   if (o->fp32_stages & ~15u) return fail(PDMK_ERR_INVALID_ARG, "unknown fp32_stages bit");
   return PDMK_OK;
@@ -506,7 +506,7 @@ int pdmk_plan_create(const pdmk_opts* opts, const double* L, pdmk_plan** out) {
     P->mixed_parts = opts->fp32_stages ? (opts->fp32_stages & 15u) : 15u;
     if (opts->precision != PDMK_PREC_MIXED || opts->eps < kMixedEpsFloor) P->mixed_parts = 0;
     far_build_scale(P);
-    PDMK_HIP(hipHostMalloc((void**)&P->h_cnt, 8 * sizeof(unsigned long long)));
+    PDMK_HIP(hipHostMalloc((void**)&P->h_cnt, 12 * sizeof(unsigned long long)));
   } catch (const Error& e) {
     free_plan_tables(P);
     delete P;
@@ -675,7 +675,7 @@ static int eval_impl(pdmk_plan* P, int64_t n_src, const double* src, const doubl
     // the second stream pays off only for large inputs: for small ones the
     // fork's events and the extra stream's share of the hardware queues cost
     // more than the overlap (measured on batches of small cells)
-    const bool fork = !noalloc && n_src + n_trg >= kForkMin;
+    const bool fork = !noalloc && !(flags & PDMK_ONE_STREAM) && n_src + n_trg >= kForkMin;
     if (fork && !aux) {
       if (!P->s_aux) PDMK_HIP(hipStreamCreateWithFlags(&P->s_aux, hipStreamNonBlocking));
       aux = P->s_aux;
@@ -689,6 +689,7 @@ static int eval_impl(pdmk_plan* P, int64_t n_src, const double* src, const doubl
     if (tm) {
       for (auto& e : ev) e = E.event();
       for (auto& e : fev) e = E.event();
+      for (auto& e : E.far_ev) e = E.event();
     }
     auto record = [&](hipEvent_t e, hipStream_t st) {
       if (tm) PDMK_HIP(hipEventRecord(e, st));
@@ -767,6 +768,13 @@ static int eval_impl(pdmk_plan* P, int64_t n_src, const double* src, const doubl
       PDMK_HIP(hipEventElapsedTime(&t4, ev[0], ev[4]));
       PDMK_HIP(hipEventElapsedTime(&tg, fev[1], fev[2]));
       t3 += tg;   // far field: grid steps (overlapped with the build and near field) + interpolation
+      float a = 0, b = 0, c = 0;
+      PDMK_HIP(hipEventElapsedTime(&a, E.far_ev[0], E.far_ev[1]));
+      PDMK_HIP(hipEventElapsedTime(&b, E.far_ev[1], E.far_ev[2]));
+      PDMK_HIP(hipEventElapsedTime(&c, E.far_ev[3], E.far_ev[4]));
+      E.st.t_spread_ms = a;
+      E.st.t_fft_ms = b;
+      E.st.t_interp_ms = c;
     } else {
       PDMK_HIP(hipStreamSynchronize(s));
     }

@@ -756,6 +756,8 @@ void stage_far_grid(pdmk_plan* P, Eval& E) {
   double2* cg = E.alloc<double2>(n);
   E.far_grid = grid;
   E.far_cg = cg;
+  const bool tm = E.timing && E.far_ev[0];
+  if (tm) PDMK_HIP(hipEventRecord(E.far_ev[0], E.s));
   if (E.det) {
     // fixed-point grid (two words per cell), see k_spread_det
     E.far_hi = E.alloc<unsigned long long>(n);
@@ -770,16 +772,21 @@ void stage_far_grid(pdmk_plan* P, Eval& E) {
     spread_interp(P, E, M, w, beta, grid, cg, false, true);
     hipLaunchKernelGGL(k_to_complex, dim3(nblk(n, 256)), dim3(256), 0, E.s, n, grid, cg);
   }
+  if (tm) PDMK_HIP(hipEventRecord(E.far_ev[1], E.s));
   fft3(cg, M, d, -1, P->d_fftw, P->fftw_off, E.s);
   hipLaunchKernelGGL(k_scale, dim3(nblk(n, 256)), dim3(256), 0, E.s, n, cg, P->d_farscale);
   fft3(cg, M, d, +1, P->d_fftw, P->fftw_off, E.s);
+  if (tm) PDMK_HIP(hipEventRecord(E.far_ev[2], E.s));
 }
 
 void stage_far_interp(pdmk_plan* P, Eval& E, bool want_grad) {
   const Geometry& g = P->g;
   int M[3] = {g.fgrid[0], g.fgrid[1], g.dim == 3 ? g.fgrid[2] : 1};
   if (E.far_out) fill_zero(E.far_out, E.n_trg * sizeof(double), E.s);
+  const bool tm = E.timing && E.far_ev[3];
+  if (tm) PDMK_HIP(hipEventRecord(E.far_ev[3], E.s));
   spread_interp(P, E, M, P->mp.nufft_w, P->nufft_beta, E.far_grid, E.far_cg, want_grad, false);
+  if (tm) PDMK_HIP(hipEventRecord(E.far_ev[4], E.s));
 }
 
 }  // namespace pdmk

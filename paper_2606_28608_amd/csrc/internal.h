@@ -196,6 +196,8 @@ struct Eval {
   double2* far_cg = nullptr;    // its transform, scaled and transformed back
   bool pw_split = false;
   hipEvent_t near_ev[4] = {nullptr, nullptr, nullptr, nullptr};
+  // far field: spreading start / end, transforms end, interpolation start / end
+  hipEvent_t far_ev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
   std::vector<std::array<hipEvent_t, 4>> pw_ev;
 };
 // Fills the near-field entries of E.st (call after the stream has finished).
@@ -234,7 +236,8 @@ struct pdmk_plan {
   double* adj_buf = nullptr;    // Psi and grad Psi of the adjoint (n_src (d + 1))
   // pinned host: [0..2] plane-wave pairs, boxes, support pairs; [3] visited
   // residual pairs; [4..5] sum q,
-  // sum |q| (FP64 bits); [6] the two input flags of Eval::d_flags
+  // sum |q| (FP64 bits); [6] the two input flags of Eval::d_flags; [8] residual
+  // pairs staged after the per-pass reach test
   unsigned long long* h_cnt = nullptr;
   // second stream (default priority, created on first use): the far field's
   // grid steps run on it beside the tree, list and near-field stages

@@ -147,11 +147,14 @@ template <class Real>
 struct SourceSlot {
   double4 v;                   // (offset, h^2)
   typename SlotQ<Real>::T w;   // (q, 1/h, 2/h^2, 0)
+  bool live;                   // within h + rho of the pass's target centre
   // Source offset from the target leaf centre (formed in FP64) with the support
   // h^2 of its residual level in v.w, and (q, 1/h, 2/h^2); slots past the list
-  // end never interact (h^2 = 0).
+  // end never interact (h^2 = 0).  live: the source can reach a target of the
+  // pass, whose targets lie within rho of cc (|y - cc| < h + rho).
   __device__ void fetch(const ListCursor& c, const KParams& kp, const double* __restrict__ sx,
-                        const double* __restrict__ sq, int64_t nimg, const double* cT, int D) {
+                        const double* __restrict__ sq, int64_t nimg, const double* cT, int D,
+                        const double* cc, double rho) {
     if (c.valid()) {
       const int sidx = c.en.x + c.oo;
       v.x = sx[sidx] - cT[0];
@@ -165,65 +168,102 @@ struct SourceSlot {
       w.y = (Real)ih;
       w.z = (Real)(2.0 * ih * ih);
       w.w = 0;
+      const double dx = v.x - cc[0], dy = v.y - cc[1], dz = v.z - cc[2];
+      const double reach = hh + rho;
+      live = fma(dx, dx, fma(dy, dy, dz * dz)) < reach * reach * (1.0 + 1e-12);
     } else {
-      v.x = v.y = v.z = 1e30;
-      v.w = 0;
-      w.x = 0;
-      w.y = 1;
-      w.z = 2;
-      w.w = 0;
+      dead();
     }
+  }
+  __device__ void dead() {
+    v.x = v.y = v.z = 1e30;
+    v.w = 0;
+    w.x = 0;
+    w.y = 1;
+    w.z = 2;
+    w.w = 0;
+    live = false;
   }
 };
 
-// One pass of a leaf's residual sums: 64 / S targets starting at t0, S lanes
-// per target, over the whole source list in tiles of 64 staged in LDS.  The
-// next tile's sources are fetched into registers while the current one is
-// summed.
+// One pass of a leaf's residual sums: 64 / S targets, S lanes per target,
+// over the source list of the work item.  The lanes fetch 64 candidate
+// sources at a time (the next round's loads in flight while a tile is
+// summed); a candidate farther than h + rho from the centre cc of the pass's
+// targets (all within rho of it) cannot reach any of them and is dropped,
+// the others are appended to a ring of 128 LDS slots in lane order (ballot
+// and prefix count).  Every 64 staged sources form a tile summed by all
+// lanes; the last tile is padded with slots that never interact.  nlive
+// counts the staged sources (the same on every lane).
 template <int D, int NE, int S, bool GRAD, class Real, int NR>
 __device__ void direct_pass(const KParams& kp, const int4* __restrict__ list, int lb, int le,
                             int pos0, int pos1, const double* __restrict__ sx,
                             const double* __restrict__ sq,
                             int64_t nimg, const double* cT, const double* x, const Real* ec,
-                            const Real* edc, double4* shv,
-                            typename SlotQ<Real>::T* shw, double& acc, double* g, int& nin) {
+                            const Real* edc, const double* cc, double rho, double4* shv,
+                            typename SlotQ<Real>::T* shw, double& acc, double* g, int& nin,
+                            int& nlive) {
   const int lane = threadIdx.x;
   const int slice = lane % S;
   ListCursor cur;
   cur.init(list, lb, le, pos0 + lane, pos1);
   SourceSlot<Real> nxt;
-  nxt.fetch(cur, kp, sx, sq, nimg, cT, D);
-  // the tile exists while the first lane's slot is in the list (all lanes of
-  // the wave are active here, so the first active lane is lane 0)
-  while (__builtin_amdgcn_readfirstlane(cur.valid() ? 1 : 0)) {
+  nxt.fetch(cur, kp, sx, sq, nimg, cT, D, cc, rho);
+  // all lanes of the wave are active here, so the first active lane is lane 0
+  bool more = __builtin_amdgcn_readfirstlane(cur.valid() ? 1 : 0) != 0;
+  int head = 0, fill = 0;   // staged sources: ring slots [head, head + fill) mod 128
+  while (more || fill > 0) {
+    if (more) {
+      const unsigned long long m = __builtin_amdgcn_ballot_w64(nxt.live);
+      const int off = __builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32),
+                                                __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
+      if (nxt.live) {
+        const int sl = (head + fill + off) & 127;
+        shv[sl] = nxt.v;
+        shw[sl] = nxt.w;
+      }
+      const int nm = __builtin_amdgcn_readfirstlane((int)__popcll(m));
+      fill += nm;
+      nlive += nm;
+      cur.advance(list);
+      nxt.fetch(cur, kp, sx, sq, nimg, cT, D, cc, rho);
+      more = __builtin_amdgcn_readfirstlane(cur.valid() ? 1 : 0) != 0;
+      if (fill < 64 && more) continue;
+    }
+    const int base = head & 127;
+    if (fill < 64 && lane >= fill) {
+      // the last tile: slots past the staged sources never interact
+      SourceSlot<Real> d;
+      d.dead();
+      shv[base + lane] = d.v;
+      shw[base + lane] = d.w;
+    }
     __syncthreads();
-    shv[lane] = nxt.v;
-    shw[lane] = nxt.w;
-    __syncthreads();
-    cur.advance(list);
-    nxt.fetch(cur, kp, sx, sq, nimg, cT, D);
     Real ta = 0, tb = 0, ga[3] = {0, 0, 0}, gb[3] = {0, 0, 0};
+    const double4* tv = shv + base;
+    const typename SlotQ<Real>::T* tw = shw + base;
     if constexpr (S == 1) {
       // one lane per target: the whole tile unrolled (LDS reads at immediate offsets)
 #pragma unroll
       for (int k = 0; k < 64; k += 2) {
-        residual_pair<D, NE, GRAD, Real, NR>(x, shv[k], shw[k], ec, edc, ta, ga, nin);
-        residual_pair<D, NE, GRAD, Real, NR>(x, shv[k + 1], shw[k + 1], ec, edc, tb,
-                                         gb, nin);
+        residual_pair<D, NE, GRAD, Real, NR>(x, tv[k], tw[k], ec, edc, ta, ga, nin);
+        residual_pair<D, NE, GRAD, Real, NR>(x, tv[k + 1], tw[k + 1], ec, edc, tb, gb, nin);
       }
     } else {
       // trip count independent of the lane (64 is a multiple of 2 S)
 #pragma unroll 2
       for (int kk = 0; kk < 64; kk += 2 * S) {
         const int k = kk + slice;
-        residual_pair<D, NE, GRAD, Real, NR>(x, shv[k], shw[k], ec, edc, ta, ga, nin);
-        residual_pair<D, NE, GRAD, Real, NR>(x, shv[k + S], shw[k + S], ec, edc, tb,
-                                         gb, nin);
+        residual_pair<D, NE, GRAD, Real, NR>(x, tv[k], tw[k], ec, edc, ta, ga, nin);
+        residual_pair<D, NE, GRAD, Real, NR>(x, tv[k + S], tw[k + S], ec, edc, tb, gb, nin);
       }
     }
     acc += (double)ta + (double)tb;
     if (GRAD)
       for (int a = 0; a < D; ++a) g[a] += (double)ga[a] + (double)gb[a];
+    __syncthreads();   // the tile is read before its slots are staged again
+    head += 64;
+    fill = fill > 64 ? fill - 64 : 0;
   }
 #pragma unroll
   for (int m = 1; m < S; m <<= 1) {
@@ -252,8 +292,8 @@ __global__ __launch_bounds__(64) void k_direct(
     const double* __restrict__ Edc, double* __restrict__ pot, double* __restrict__ grad,
     unsigned long long* __restrict__ n_support, double* __restrict__ part,
     double* __restrict__ gpart, const int* __restrict__ item_beg) {
-  __shared__ double4 shv[64];
-  __shared__ typename SlotQ<Real>::T shw[64];
+  __shared__ double4 shv[128];
+  __shared__ typename SlotQ<Real>::T shw[128];
   if ((int)blockIdx.x >= nitems) return;
   const int2 item = items[blockIdx.x];
   const int i = item.x;
@@ -279,6 +319,7 @@ __global__ __launch_bounds__(64) void k_direct(
   double cT[3] = {0, 0, 0};
   for (int a = 0; a < D; ++a) cT[a] = kp.origin[a] + (T.coord[b * D + a] + 0.5) * hT;
   int nin = 0;
+  long long nstaged = 0;   // staged sources x targets of the passes
   for (int t0 = tb; t0 < te;) {
     // lanes per target for this pass, from the targets still to do
     const int rem = te - t0;
@@ -289,27 +330,41 @@ __global__ __launch_bounds__(64) void k_direct(
     // lanes of targets past the end sit far away: they stage sources but no
     // pair of theirs is inside the support
     for (int a = 0; a < D; ++a) x[a] = valid ? tx[a * ntrg + t] - cT[a] : 1e30;
+    // bounding box of the pass's targets: centre cc, half-diagonal rho
+    double cc[3] = {0, 0, 0}, rho2 = 0.0;
+    for (int a = 0; a < D; ++a) {
+      double lo = valid ? x[a] : 1e300, hi = valid ? x[a] : -1e300;
+#pragma unroll
+      for (int m = 1; m < 64; m <<= 1) {
+        lo = fmin(lo, __shfl_xor(lo, m));
+        hi = fmax(hi, __shfl_xor(hi, m));
+      }
+      cc[a] = 0.5 * (lo + hi);
+      rho2 += 0.25 * (hi - lo) * (hi - lo);
+    }
+    const double rho = sqrt(rho2);
     double acc = 0.0, g[3] = {0, 0, 0};
-    int nin_p = 0;
+    int nin_p = 0, nlive = 0;
     switch (S) {
       case 1:
         direct_pass<D, NE, 1, GRAD, Real, NR>(kp, list, lb, le, pos0, pos1, sx, sq, nimg, cT, x,
-                                          ec, edc, shv, shw, acc, g, nin_p);
+                                          ec, edc, cc, rho, shv, shw, acc, g, nin_p, nlive);
         break;
       case 2:
         direct_pass<D, NE, 2, GRAD, Real, NR>(kp, list, lb, le, pos0, pos1, sx, sq, nimg, cT, x,
-                                          ec, edc, shv, shw, acc, g, nin_p);
+                                          ec, edc, cc, rho, shv, shw, acc, g, nin_p, nlive);
         break;
       case 4:
         direct_pass<D, NE, 4, GRAD, Real, NR>(kp, list, lb, le, pos0, pos1, sx, sq, nimg, cT, x,
-                                          ec, edc, shv, shw, acc, g, nin_p);
+                                          ec, edc, cc, rho, shv, shw, acc, g, nin_p, nlive);
         break;
       default:
         direct_pass<D, NE, 8, GRAD, Real, NR>(kp, list, lb, le, pos0, pos1, sx, sq, nimg, cT, x,
-                                          ec, edc, shv, shw, acc, g, nin_p);
+                                          ec, edc, cc, rho, shv, shw, acc, g, nin_p, nlive);
         break;
     }
     nin += nin_p;   // the same wave-wide count on every lane
+    nstaged += (long long)nlive * ((te - t0 < 64 / S) ? te - t0 : 64 / S);
     if (valid && lane % S == 0) {
       const double cst = D == 3 ? kInv4Pi : kInv2Pi;
       double v = acc * cst;
@@ -332,7 +387,10 @@ __global__ __launch_bounds__(64) void k_direct(
     t0 += 64 / S;
   }
   // pairs inside the support (statistics): one atomic per block
-  if (lane == 0 && n_support) atomicAdd(n_support, (unsigned long long)nin);
+  if (lane == 0 && n_support) {
+    atomicAdd(n_support, (unsigned long long)nin);
+    atomicAdd(n_support + 1, (unsigned long long)nstaged);
+  }
 }
 
 // Fixed-order completion of the residual sums: one block per work item in
@@ -1161,8 +1219,8 @@ static void near_impl(pdmk_plan* P, Eval& E, bool want_grad) {
   hipEvent_t e0 = E.near_ev[0], e1 = E.near_ev[1], e2 = E.near_ev[2], e3 = E.near_ev[3];
   // [0] colleague pairs translated, [1] boxes given incoming plane waves,
   // [2] residual pairs inside the support
-  unsigned long long* cnt = E.alloc<unsigned long long>(3);
-  fill_zero(cnt, 3 * sizeof(unsigned long long), s);
+  unsigned long long* cnt = E.alloc<unsigned long long>(4);
+  fill_zero(cnt, 4 * sizeof(unsigned long long), s);
   unsigned long long* nsup = cnt + 2;
   fill_zero(E.pot_sorted, sizeof(double) * E.n_trg, s);
   if (want_grad)
@@ -1304,6 +1362,8 @@ static void near_impl(pdmk_plan* P, Eval& E, bool want_grad) {
     PDMK_HIP(hipEventRecord(e3, s));
     PDMK_HIP(hipMemcpyAsync(P->h_cnt, cnt, 3 * sizeof(unsigned long long),
                             hipMemcpyDeviceToHost, s));
+    PDMK_HIP(hipMemcpyAsync(P->h_cnt + 8, cnt + 3, sizeof(unsigned long long),
+                            hipMemcpyDeviceToHost, s));
   }
 }
 
@@ -1313,6 +1373,7 @@ void near_finish(const pdmk_plan* P, Eval& E) {
   E.st.n_pw_pairs = (int64_t)P->h_cnt[0];
   E.st.n_pwin_boxes = (int64_t)P->h_cnt[1];
   E.st.n_support_pairs = (int64_t)P->h_cnt[2];
+  E.st.n_staged_pairs = (int64_t)P->h_cnt[8];
   E.st.n_direct_pairs = (int64_t)P->h_cnt[3];   // copied by the list stage
   for (auto& pe : E.pw_ev) {
     float a = 0, b = 0, c = 0;

@@ -25,6 +25,7 @@ PDMK_WANT_GRAD = 1
 PDMK_ALLOW_NONNEUTRAL = 2
 PDMK_DETERMINISTIC = 4
 PDMK_VECTOR_PLANE_WAVES = 8
+PDMK_ONE_STREAM = 16
 PDMK_FP32_RESIDUAL = 1
 PDMK_FP32_PROXY = 2
 PDMK_FP32_WINDOW = 4
@@ -74,7 +75,9 @@ class Stats(ctypes.Structure):
                 ("t_call_ms", ctypes.c_double), ("workspace_bytes", ctypes.c_int64),
                 ("n_pwout_boxes", ctypes.c_int64), ("n_pwin_boxes", ctypes.c_int64),
                 ("t_pwout_ms", ctypes.c_double), ("t_pwin_ms", ctypes.c_double),
-                ("t_pwtr_ms", ctypes.c_double)]
+                ("t_pwtr_ms", ctypes.c_double), ("n_staged_pairs", ctypes.c_int64),
+                ("t_spread_ms", ctypes.c_double), ("t_fft_ms", ctypes.c_double),
+                ("t_interp_ms", ctypes.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -156,10 +159,10 @@ def _check(code):
 
 
 def default_opts(dim, eps, precision="fp64", grad=False, allow_nonneutral=False,
-                 deterministic=False, vector_plane_waves=False, **over):
+                 deterministic=False, vector_plane_waves=False, one_stream=False, **over):
     """pdmk_opts for (dim, eps) with the defaults of pdmk_default_opts; keyword
     arguments set flags (grad, allow_nonneutral, deterministic,
-    vector_plane_waves) or override fields (kappa, n_s, porder, npw, nufft_w,
+    vector_plane_waves, one_stream) or override fields (kappa, n_s, porder, npw, nufft_w,
     sigma, fp32_stages)."""
     o = Opts()
     _check(lib().pdmk_default_opts(int(dim), float(eps), ctypes.byref(o)))
@@ -168,7 +171,8 @@ def default_opts(dim, eps, precision="fp64", grad=False, allow_nonneutral=False,
     o.precision = PDMK_PREC_MIXED if precision == "mixed" else PDMK_PREC_FP64
     o.flags = ((PDMK_WANT_GRAD if grad else 0) | (PDMK_ALLOW_NONNEUTRAL if allow_nonneutral else 0)
                | (PDMK_DETERMINISTIC if deterministic else 0)
-               | (PDMK_VECTOR_PLANE_WAVES if vector_plane_waves else 0))
+               | (PDMK_VECTOR_PLANE_WAVES if vector_plane_waves else 0)
+               | (PDMK_ONE_STREAM if one_stream else 0))
     for k, v in over.items():
         if v is not None:
             setattr(o, k, v)
