@@ -20,6 +20,8 @@ Public functions
 ``ball_sum(L, src, q, trg, R)``
     brute-force image sum over whole cells inside a ball of radius R (used
     only to pin the Ewald code).
+``ewald_bloch(L, src, q, beta, trg=None)``
+    the quasi-periodic (Bloch) potential of Section 4.1 (complex), bloch.c.
 ``expint_e1(x)``
     the exponential integral used by the 2D real-space kernel.
 """
@@ -34,16 +36,18 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "ewald.c")
+_SRCS = [_SRC, os.path.join(_HERE, "bloch.c")]
 _LIB = os.path.join(_HERE, "liboracle.so")
 _lib = None
 
 
 def build(force: bool = False) -> str:
-    """Compile ewald.c into liboracle.so with gcc (OpenMP, -O2)."""
-    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+    """Compile ewald.c and bloch.c into liboracle.so with gcc (OpenMP, -O2)."""
+    newest = max(os.path.getmtime(f) for f in _SRCS)
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < newest:
         tmp = _LIB + ".tmp%d" % os.getpid()
-        subprocess.check_call(["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-std=c99",
-                               _SRC, "-o", tmp, "-lm"])
+        subprocess.check_call(["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-std=c99"] +
+                              _SRCS + ["-o", tmp, "-lm"])
         os.replace(tmp, _LIB)
     return _LIB
 
@@ -66,6 +70,10 @@ def _load():
         lib.oracle_ball_sum.restype = ctypes.c_int
         lib.oracle_expint_e1.argtypes = [ctypes.c_double]
         lib.oracle_expint_e1.restype = ctypes.c_double
+        lib.oracle_ewald_bloch.argtypes = [ctypes.c_int, dp, dp, ctypes.c_long, dp, dp,
+                                           ctypes.c_long, dp, lp, ctypes.c_double,
+                                           ctypes.c_double, ctypes.c_double, dp, dp]
+        lib.oracle_ewald_bloch.restype = ctypes.c_int
         lib.oracle_threads.argtypes = []
         lib.oracle_threads.restype = ctypes.c_int
         _lib = lib
@@ -156,6 +164,43 @@ def ewald_sampled(L, src, q, idx, grad=False, alpha=None):
     src = np.ascontiguousarray(src, dtype=np.float64).reshape(-1, d)
     idx = np.asarray(idx, dtype=np.int64)
     return ewald(L, src, q, trg=src[idx], grad=grad, alpha=alpha, self_idx=idx)
+
+
+def ewald_bloch(L, src, q, beta, trg=None, alpha=None, self_idx=None, tol_s=_S):
+    """Quasi-periodic (Bloch) potential of Section 4.1 by Ewald summation
+    (bloch.c): sum_n sum_j q_j e^{i beta.L n} G(x - y_j - L n), self pair
+    removed, positions taken literally (not wrapped).  Returns a complex
+    array (M,).  trg=None: targets are the sources."""
+    L, d = _lattice(L)
+    src = np.ascontiguousarray(src, dtype=np.float64).reshape(-1, d)
+    q = np.ascontiguousarray(q, dtype=np.float64).reshape(-1)
+    beta = np.ascontiguousarray(beta, dtype=np.float64).reshape(d)
+    if trg is None:
+        trg = src
+        self_idx = np.arange(src.shape[0], dtype=np.int64)
+    trg = np.ascontiguousarray(trg, dtype=np.float64).reshape(-1, d)
+    if self_idx is not None:
+        self_idx = np.ascontiguousarray(self_idx, dtype=np.int64)
+    if alpha is None:
+        alpha = choose_alpha(L, src.shape[0], trg.shape[0])
+    re = np.zeros(trg.shape[0])
+    im = np.zeros(trg.shape[0])
+    rc = _load().oracle_ewald_bloch(d, _dp(L), _dp(beta), src.shape[0], _dp(src), _dp(q),
+                                    trg.shape[0], _dp(trg), _lp(self_idx), alpha,
+                                    tol_s / alpha, 2.0 * alpha * tol_s, _dp(re), _dp(im))
+    if rc == -2:
+        raise ValueError("beta is in the reciprocal lattice (the periodic case)")
+    if rc != 0:
+        raise ValueError("oracle_ewald_bloch failed with code %d" % rc)
+    return re + 1j * im
+
+
+def ewald_bloch_sampled(L, src, q, beta, idx, alpha=None):
+    """Bloch values at the sources listed in idx (self pair removed)."""
+    L, d = _lattice(L)
+    src = np.ascontiguousarray(src, dtype=np.float64).reshape(-1, d)
+    idx = np.asarray(idx, dtype=np.int64)
+    return ewald_bloch(L, src, q, beta, trg=src[idx], alpha=alpha, self_idx=idx)
 
 
 def nmodes(L, alpha, tol_s=_S):
