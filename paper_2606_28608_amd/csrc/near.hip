@@ -1121,19 +1121,25 @@ static void launch_transfer(const KParams& kp, const Level& Lp, const Level& Lc,
   const bool octs = E.det && mode == 1;
 #define PDMK_TR(PM, L, NO, MO)                                                                  \
   do {                                                                                          \
+    if (p > PM || (MO == 0 && pD > 256 * NO))                                                   \
+      throw Error{PDMK_ERR_UNSUPPORTED, "transfer shape"};                                      \
     ensure_lds((const void*)&k_transfer<D, PM, L, NO, MO, Real>, smem);                         \
     for (int o = octs ? 0 : -1; o < (octs ? (1 << D) : 0); ++o)                                 \
       hipLaunchKernelGGL((k_transfer<D, PM, L, NO, MO, Real>), dim3(nblocks), dim3(256), smem,  \
                          s, kp, Lp, Lc, src, dst, P->d_Tm, scratch, o);                         \
   } while (0)
+  // the line length PMAX must cover p: a shorter one leaves outputs p > PMAX
+  // of every line uncomputed
   if (mode == 0) {
-    if (nown <= 8) {
+    if (nown <= 8) {   // 2D for every order (p <= 40)
       if (p <= 16) PDMK_TR(16, true, 8, 0);
-      else PDMK_TR(24, true, 8, 0);
-    } else if (nown <= 24) {
+      else if (p <= 24) PDMK_TR(24, true, 8, 0);
+      else if (p <= 32) PDMK_TR(32, true, 8, 0);
+      else PDMK_TR(40, true, 8, 0);
+    } else if (nown <= 24) {   // 3D, p <= 18
       if (p <= 16) PDMK_TR(16, true, 24, 0);
       else PDMK_TR(24, true, 24, 0);
-    } else {
+    } else {   // 3D, p <= 23
       if (lds) PDMK_TR(24, true, 48, 0);
       else PDMK_TR(32, false, 48, 0);
     }
@@ -1142,7 +1148,8 @@ static void launch_transfer(const KParams& kp, const Level& Lp, const Level& Lc,
     if (lds) {
       if (p <= 16) { if (m1) PDMK_TR(16, true, 1, 1); else PDMK_TR(16, true, 1, 2); }
       else if (p <= 24) { if (m1) PDMK_TR(24, true, 1, 1); else PDMK_TR(24, true, 1, 2); }
-      else { if (m1) PDMK_TR(32, true, 1, 1); else PDMK_TR(32, true, 1, 2); }
+      else if (p <= 32) { if (m1) PDMK_TR(32, true, 1, 1); else PDMK_TR(32, true, 1, 2); }
+      else { if (m1) PDMK_TR(40, true, 1, 1); else PDMK_TR(40, true, 1, 2); }
     } else {
       if (p <= 24) { if (m1) PDMK_TR(24, false, 1, 1); else PDMK_TR(24, false, 1, 2); }
       else if (p <= 32) { if (m1) PDMK_TR(32, false, 1, 1); else PDMK_TR(32, false, 1, 2); }

@@ -31,6 +31,11 @@ def pdmk():
     return m
 
 
+def _t(torch_dev, a):
+    torch, dev = torch_dev
+    return torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device=dev)
+
+
 def _eval(pdmk, torch_dev, L, src, q, eps, trg=None, grad=False, precision="fp64", **over):
     torch, dev = torch_dev
     S = torch.tensor(src, device=dev)
@@ -47,6 +52,22 @@ def test_c1_oblique2d(pdmk, torch_dev):
     ref = ewald.ewald(L, src, q)
     pot = _eval(pdmk, torch_dev, L, src, q, 1e-6)
     assert ewald.rel_l2(pot, ref) <= 1e-6
+
+
+@pytest.mark.parametrize("eps", [1e-7, 1e-9, 1e-12])
+@pytest.mark.parametrize("kappa,n_s", [(3.0, 60), (2.0, 40)])
+def test_oblique2d_deep_trees(pdmk, torch_dev, eps, kappa, n_s):
+    """2D at orders p = 25 .. 39 on trees of three and more levels (every
+    transfer between levels at these orders)."""
+    L, src, q = workloads.oblique2d(3000, seed=61)
+    ref = ewald.ewald(L, src, q)
+    plan = pdmk.Plan(L, eps=eps, kappa=kappa, n_s=n_s)
+    pot = plan.eval(_t(torch_dev, src), _t(torch_dev, q)).cpu().numpy()
+    assert plan.stats()["n_levels"] >= 3
+    err = ewald.rel_l2(pot, ref)
+    print("2D eps=%g kappa=%g n_s=%d levels=%d E_rel=%.3e"
+          % (eps, kappa, n_s, plan.stats()["n_levels"], err))
+    assert err <= eps
 
 
 @pytest.mark.parametrize("eps", [1e-3, 1e-6, 1e-9])
