@@ -105,10 +105,12 @@ enum {
                                   transfer and leaf-evaluation kernels instead of the
                                   matrix-core ones (same arithmetic type; for
                                   comparing the two implementations) */
-  PDMK_ONE_STREAM = 16         /* run every stage on the caller's stream (no second
+  PDMK_ONE_STREAM = 16,        /* run every stage on the caller's stream (no second
                                   stream for the far field's grid steps; each stage
                                   then has the device to itself, so its timings in
                                   pdmk_stats are stand-alone durations) */
+  PDMK_BLOCH = 32              /* quasi-periodic conditions with the Bloch vector
+                                  pdmk_opts.bloch (see pdmk_plan_eval_bloch) */
 };
 
 typedef struct {
@@ -118,7 +120,7 @@ typedef struct {
   double kappa;     /* root cube side r_c = L_min / kappa (Section 5); <= 0: default */
   int n_s;          /* leaf capacity (Section 5, Table tab:tuning); <= 0: default */
   unsigned flags;   /* PDMK_WANT_GRAD | PDMK_ALLOW_NONNEUTRAL | PDMK_DETERMINISTIC |
-                       PDMK_VECTOR_PLANE_WAVES | PDMK_ONE_STREAM */
+                       PDMK_VECTOR_PLANE_WAVES | PDMK_ONE_STREAM | PDMK_BLOCH */
   int porder;       /* Chebyshev proxy points per axis; <= 0: chosen from eps */
   int npw;          /* plane-wave half count J per axis (modes -J..J); <= 0: from eps */
   int nufft_w;      /* spreading-window width in grid cells; <= 0: from eps (two
@@ -129,6 +131,8 @@ typedef struct {
   unsigned fp32_stages; /* PDMK_PREC_MIXED only: PDMK_FP32_* / PDMK_BF16_* bits of the
                        stages computed in reduced precision; 0: all of them (the
                        default).  Ignored (every stage FP64) when eps < 1e-6. */
+  double bloch[3];  /* with PDMK_BLOCH: the Bloch vector beta (Cartesian, the
+                       caller's frame; d components used) */
 } pdmk_opts;
 
 /*
@@ -180,6 +184,33 @@ int pdmk_plan_eval(pdmk_plan* plan, int64_t n_src, const double* src,
                    const double* q, int64_t n_trg, const double* trg,
                    double* pot, double* grad, void* stream);
 void pdmk_plan_destroy(pdmk_plan* plan);
+
+/*
+ * Quasi-periodic (Bloch) conditions (Section 4.1, eq:qp_def): for a plan made
+ * with PDMK_BLOCH and beta = opts.bloch,
+ *
+ *     Phi(x_i) = sum_n sum_j q_j e^{i beta.L n} G(x_i - y_j - L n),
+ *
+ * the self pair removed, so that Phi(x + L n) = e^{i beta.L n} Phi(x).
+ * Positions are taken literally: the image of y_j at y_j + L n carries the
+ * charge q_j e^{i beta.L n} (a point given outside the cell is wrapped in with
+ * the matching phase on its charge, and a target's value is carried back by
+ * the phase of its wrap).  The method is that of the periodic case with the
+ * paper's three changes: phased image charges in the near field (evaluated
+ * as two real near fields, of the real and the imaginary parts of the image
+ * charges), the far field of eq:qp_far (sources pre-modulated by
+ * e^{-i beta.y}, scaling by What_0(|k_m + beta|) with the m = 0 mode kept,
+ * targets post-modulated by e^{i beta.x}) on the grid M_i = 2 ceil((c/r_c +
+ * |beta|) |a_i| / 2 pi).  Charges are real and need not be neutral.  beta
+ * must not lie in the reciprocal lattice 2 pi L^{-T} Z^d (that is the
+ * periodic case: pdmk_plan_create returns PDMK_ERR_INVALID_ARG).  Potentials
+ * only: PDMK_WANT_GRAD, PDMK_DETERMINISTIC and kept trees are not supported
+ * with PDMK_BLOCH (PDMK_ERR_UNSUPPORTED), and pdmk_plan_eval rejects a Bloch
+ * plan.  pot: DEVICE, 2 n_trg doubles, (real, imaginary) per target.
+ * Other arguments, blocking and errors as pdmk_plan_eval.
+ */
+int pdmk_plan_eval_bloch(pdmk_plan* plan, int64_t n_src, const double* src, const double* q,
+                         int64_t n_trg, const double* trg, double* pot, void* stream);
 
 /*
  * The two halves of one evaluation (for checking each on its own): the

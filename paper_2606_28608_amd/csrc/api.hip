@@ -440,10 +440,43 @@ static int validate_opts(const pdmk_opts* o) {
   if (o->porder > 40 || o->npw > 64 || o->nufft_w > 16 || o->sigma > 4.0)
     return fail(PDMK_ERR_INVALID_ARG, "porder <= 40, npw <= 64, nufft_w <= 16, sigma <= 4");
   if (o->flags & ~(unsigned)(PDMK_WANT_GRAD | PDMK_ALLOW_NONNEUTRAL | PDMK_DETERMINISTIC |
-                             PDMK_VECTOR_PLANE_WAVES | PDMK_ONE_STREAM))
+                             PDMK_VECTOR_PLANE_WAVES | PDMK_ONE_STREAM | PDMK_BLOCH))
     return fail(PDMK_ERR_INVALID_ARG, "unknown flag");
+  if (o->flags & PDMK_BLOCH) {
+    for (int a = 0; a < o->dim; ++a)
+      if (!std::isfinite(o->bloch[a])) return fail(PDMK_ERR_INVALID_ARG, "non-finite Bloch vector");
+    if (o->flags & (PDMK_WANT_GRAD | PDMK_DETERMINISTIC))
+      return fail(PDMK_ERR_UNSUPPORTED,
+                  "PDMK_BLOCH does not support PDMK_WANT_GRAD or PDMK_DETERMINISTIC");
+  }
   if (o->fp32_stages & ~15u) return fail(PDMK_ERR_INVALID_ARG, "unknown fp32_stages bit");
   return PDMK_OK;
+}
+
+static double bloch_norm(const pdmk_opts* o) {
+  if (!(o->flags & PDMK_BLOCH)) return 0.0;
+  double s = 0.0;
+  for (int a = 0; a < o->dim; ++a) s += o->bloch[a] * o->bloch[a];
+  return std::sqrt(s);
+}
+
+// Oriented Bloch vector beta' = Q^T beta (beta.x is invariant under the
+// rotation).  False when beta lies in the reciprocal lattice (L^T beta / 2 pi
+// integral): that is the periodic case.
+static bool oriented_bloch(const Geometry& g, const pdmk_opts* opts, double* beta) {
+  const int d = g.dim;
+  for (int a = 0; a < d; ++a) {
+    double v = 0.0;
+    for (int b = 0; b < d; ++b) v += g.Q[b + d * a] * opts->bloch[b];
+    beta[a] = v;
+  }
+  for (int a = 0; a < d; ++a) {
+    double u = 0.0;
+    for (int b = 0; b < d; ++b) u += g.L[b + d * a] * beta[b];
+    u /= 2.0 * kPi;
+    if (std::fabs(u - std::rint(u)) > 1e-9) return true;
+  }
+  return false;
 }
 
 int pdmk_plan_create(const pdmk_opts* opts, const double* L, pdmk_plan** out) {
@@ -464,7 +497,8 @@ int pdmk_plan_create(const pdmk_opts* opts, const double* L, pdmk_plan** out) {
     P->nufft_beta = P->mp.beta;
     P->P = &pswf_for_eps(opts->eps);
     P->T = &tables_for_eps(opts->eps);
-    std::string msg = make_geometry(d, L, P->mp.kappa, P->P->c, P->mp.sigma, P->g);
+    std::string msg = make_geometry(d, L, P->mp.kappa, P->P->c, P->mp.sigma, P->g,
+                                    bloch_norm(opts));
     if (!msg.empty()) {
       delete P;
       return fail(msg.find("kappa") != std::string::npos ? PDMK_ERR_INVALID_ARG
@@ -496,6 +530,12 @@ int pdmk_plan_create(const pdmk_opts* opts, const double* L, pdmk_plan** out) {
       kp.Q[k] = P->g.Q[k];
     }
     kp.w0unit = P->T->w0_unit(d);
+    if (opts->flags & PDMK_BLOCH) {
+      kp.bloch = 1;
+      if (!oriented_bloch(P->g, opts, kp.beta))
+        throw Error{PDMK_ERR_INVALID_ARG,
+                    "Bloch vector in the reciprocal lattice: this is the periodic case"};
+    }
     plan_upload_tables(P);
     if (d == 3) pw_mfma_upload(P);
     P->pw_mfma = !(opts->flags & PDMK_VECTOR_PLANE_WAVES);
@@ -563,11 +603,16 @@ int pdmk_geometry_get(const pdmk_opts* opts, const double* L, pdmk_geometry* out
   tmp.nufft_beta = tmp.mp.beta;
   tmp.P = &pswf_for_eps(opts->eps);
   tmp.T = &tables_for_eps(opts->eps);
-  std::string msg = make_geometry(opts->dim, L, tmp.mp.kappa, tmp.P->c, tmp.mp.sigma, tmp.g);
+  std::string msg = make_geometry(opts->dim, L, tmp.mp.kappa, tmp.P->c, tmp.mp.sigma, tmp.g,
+                                  bloch_norm(opts));
   if (!msg.empty())
     return fail(msg.find("kappa") != std::string::npos ? PDMK_ERR_INVALID_ARG
                                                         : PDMK_ERR_SINGULAR_LATTICE,
                 msg);
+  double ob[3];
+  if ((opts->flags & PDMK_BLOCH) && !oriented_bloch(tmp.g, opts, ob))
+    return fail(PDMK_ERR_INVALID_ARG,
+                "Bloch vector in the reciprocal lattice: this is the periodic case");
   return pdmk_plan_geometry(&tmp, out);
 }
 
@@ -634,6 +679,8 @@ static int eval_impl(pdmk_plan* P, int64_t n_src, const double* src, const doubl
                      hipStream_t aux = nullptr, BoundState** keep = nullptr,
                      bool noalloc = false, double* pot_far = nullptr) {
   if (!P) return fail(PDMK_ERR_INVALID_ARG, "null plan");
+  if (P->kp.bloch)
+    return fail(PDMK_ERR_UNSUPPORTED, "a Bloch plan evaluates with pdmk_plan_eval_bloch");
   const int d = P->g.dim;
   const bool self_t = (trg == nullptr);
   if (self_t) n_trg = n_src;
@@ -837,6 +884,134 @@ static int eval_impl(pdmk_plan* P, int64_t n_src, const double* src, const doubl
   return PDMK_OK;
 }
 
+// ------------------------------------------------------------ Bloch conditions
+// Phi(x_w) = near_re + i near_im + e^{i beta.x_w} (far_re + i far_im) at the
+// sorted (wrapped) targets, carried back to the given target by the phase of
+// its wrap, Phi(x) = e^{-i theta} Phi(x_w) (Section 4.1: post-modulation and
+// quasi-periodicity); written as (real, imaginary) pairs in the caller's order.
+__global__ void k_assemble_bloch(KParams kp, int64_t n, const int* __restrict__ tperm,
+                                 const double* __restrict__ tx, const double* __restrict__ nr,
+                                 const double* __restrict__ ni, const double* __restrict__ fr,
+                                 const double* __restrict__ fi,
+                                 const double* __restrict__ theta_t,
+                                 const int* __restrict__ flags, double* __restrict__ pot) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n) return;
+  if (flags[0] || flags[1]) return;
+  double ph = 0.0;
+  for (int a = 0; a < kp.dim; ++a) ph += kp.beta[a] * tx[a * n + t];
+  double sn, cs;
+  sincos(ph, &sn, &cs);
+  const double re = nr[t] + (cs * fr[t] - sn * fi[t]);
+  const double im = ni[t] + (sn * fr[t] + cs * fi[t]);
+  const int o = tperm[t];
+  double s2, c2;
+  sincos(theta_t[o], &s2, &c2);
+  pot[2 * (int64_t)o] = re * c2 + im * s2;
+  pot[2 * (int64_t)o + 1] = im * c2 - re * s2;
+}
+
+// One Bloch evaluation: the periodic pipeline with phased image charges, two
+// real near fields (real and imaginary parts of the image charges) and the
+// modulated far field of eq:qp_far; every stage on the caller's stream.
+static int bloch_impl(pdmk_plan* P, int64_t n_src, const double* src, const double* q,
+                      int64_t n_trg, const double* trg, double* pot, void* stream) {
+  if (!P) return fail(PDMK_ERR_INVALID_ARG, "null plan");
+  if (!P->kp.bloch) return fail(PDMK_ERR_INVALID_ARG, "the plan was made without PDMK_BLOCH");
+  const int d = P->g.dim;
+  const bool self_t = (trg == nullptr);
+  if (self_t) n_trg = n_src;
+  if (n_src < 0 || n_trg < 0) return fail(PDMK_ERR_INVALID_ARG, "negative count");
+  if (n_src > (int64_t)1 << 30 || n_trg > (int64_t)1 << 30)
+    return fail(PDMK_ERR_INVALID_ARG, "more than 2^30 points");
+  if ((n_src > 0 && (!src || !q)) || (n_trg > 0 && !pot))
+    return fail(PDMK_ERR_INVALID_ARG, "null array");
+  hipStream_t s = (hipStream_t)stream;
+  const auto wall0 = std::chrono::steady_clock::now();
+  Workspace ws;
+  ws.base = P->arena;
+  ws.size = P->arena_size;
+  Eval E;
+  E.s = s;
+  E.ws = &ws;
+  E.plan = P;
+  E.n_src = n_src;
+  E.n_trg = n_trg;
+  E.self_targets = self_t;
+  E.q = q;
+  E.timing = false;
+  try {
+    int cur = -1;
+    PDMK_HIP(hipGetDevice(&cur));
+    if (cur != P->device) throw Error{PDMK_ERR_INVALID_ARG, "plan bound to another device"};
+    if (n_trg == 0) return PDMK_OK;
+    if (n_src == 0) {
+      fill_zero(pot, 2 * n_trg * sizeof(double), s);
+      PDMK_HIP(hipStreamSynchronize(s));
+      return PDMK_OK;
+    }
+    P->ev_next = 0;
+    double* qs = E.alloc<double>(2);
+    E.d_flags = E.alloc<int>(2);
+    fill_zero(E.d_flags, 2 * sizeof(int), s);
+    {
+      const int nb = std::min(1024, nblk(n_src, 256));
+      double* part = E.alloc<double>(2 * nb);
+      hipLaunchKernelGGL(k_charge_stats, dim3(nb), dim3(256), 0, s, n_src, q, part, E.d_flags);
+      hipLaunchKernelGGL(k_charge_stats_final, dim3(1), dim3(256), 0, s, nb, part, qs);
+    }
+    E.qsum = qs;
+    stage_prepare(P, E, src, trg);
+    stage_images(P, E, q);   // wrapped complex charges and phased images
+    stage_far_grid(P, E);    // pre-modulated charges, shifted-mode scaling
+    stage_tree(P, E);
+    stage_lists(P, E);
+    // the near field is real-linear in the charges: one pass per part
+    double* sq_re = E.sq;
+    const double* q_re = E.q;
+    stage_near(P, E, false);
+    double* near_re = E.pot_sorted;
+    E.sq = E.sq_im;
+    E.q = E.q_im;
+    stage_near(P, E, false);
+    double* near_im = E.pot_sorted;
+    E.sq = sq_re;
+    E.q = q_re;
+    double* far_re = E.alloc<double>(n_trg);
+    double* far_im = E.alloc<double>(n_trg);
+    E.far_out = far_re;
+    E.far_comp = 0;
+    stage_far_interp(P, E, false);
+    E.far_out = far_im;
+    E.far_comp = 1;
+    stage_far_interp(P, E, false);
+    hipLaunchKernelGGL(k_assemble_bloch, dim3(nblk(n_trg, 256)), dim3(256), 0, s, P->kp, n_trg,
+                       E.tperm, E.tx, near_re, near_im, far_re, far_im, E.theta_t, E.d_flags,
+                       pot);
+    PDMK_HIP(hipGetLastError());
+    PDMK_HIP(hipMemcpyAsync(P->h_cnt + 6, E.d_flags, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
+    PDMK_HIP(hipStreamSynchronize(s));
+    int hf[2];
+    std::memcpy(hf, P->h_cnt + 6, sizeof(hf));
+    if (hf[0]) throw Error{PDMK_ERR_NONFINITE, "non-finite charge"};
+    if (hf[1]) throw Error{PDMK_ERR_NONFINITE, "non-finite position"};
+    E.st.n_src = n_src;
+    E.st.n_trg = n_trg;
+    E.st.n_images = E.n_img;
+    P->last = E.st;
+    finish_workspace(P->arena, P->arena_size, ws);
+    P->last.workspace_bytes = (int64_t)ws.used;
+    P->last.t_call_ms =
+        std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - wall0)
+            .count();
+  } catch (const Error& e) {
+    (void)hipStreamSynchronize(s);
+    ws.release_overflow();
+    return fail(e.code, e.msg);
+  }
+  return PDMK_OK;
+}
+
 // ------------------------------------------------- allocation-free entry
 // The workspace of pdmk_plan_eval_noalloc: one fixed array per device (each
 // device holds its own copy from the code object's load until the process
@@ -1026,6 +1201,11 @@ int pdmk_plan_eval(pdmk_plan* P, int64_t n_src, const double* src, const double*
   if (!P) return fail(PDMK_ERR_INVALID_ARG, "null plan");
   return eval_impl(P, n_src, src, q, n_trg, trg, pot, grad, stream, P->o.flags, P->arena,
                    P->arena_size);
+}
+
+int pdmk_plan_eval_bloch(pdmk_plan* P, int64_t n_src, const double* src, const double* q,
+                         int64_t n_trg, const double* trg, double* pot, void* stream) {
+  return bloch_impl(P, n_src, src, q, n_trg, trg, pot, stream);
 }
 
 int pdmk_plan_eval_parts(pdmk_plan* P, int64_t n_src, const double* src, const double* q,

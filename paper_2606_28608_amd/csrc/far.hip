@@ -493,13 +493,15 @@ __global__ void k_fp_to_grid(int64_t n, const unsigned long long* __restrict__ g
 // Interpolation (step five of Section 3.6) at targets in tree order, one
 // target per lane; the block's subgrid is read into LDS once.  Results are
 // added to the near-field arrays (tree order), gradients rotated by L^{-T}.
+// comp: the grid's real (0) or imaginary (1) part is interpolated (the
+// imaginary part carries the Bloch far field).
 template <int D, int W, bool GRAD, class Real>
 __global__ __launch_bounds__(256) void k_interp_t(KParams kp, int64_t n,
                                                   const double* __restrict__ x, int M0, int M1,
                                                   int M2, double beta,
                                                   const double2* __restrict__ grid,
                                                   double* __restrict__ pot,
-                                                  double* __restrict__ grad) {
+                                                  double* __restrict__ grad, int comp) {
   __shared__ double sub[kSubCap];
   __shared__ int lo_s[3], hi_s[3];
   constexpr double hw = 0.5 * W;
@@ -521,7 +523,7 @@ __global__ __launch_bounds__(256) void k_interp_t(KParams kp, int64_t n,
           const int a0 = c % ext[0], a1 = (c / ext[0]) % ext[1], a2 = c / (ext[0] * ext[1]);
           int64_t gi = wrap_index(lo[0] + a0, M0) + (int64_t)M0 * wrap_index(lo[1] + a1, M1);
           if (D == 3) gi += (int64_t)M0 * M1 * wrap_index(lo[2] + a2, M2);
-          v[u] = grid[gi].x;
+          v[u] = comp ? grid[gi].y : grid[gi].x;
         }
       }
 #pragma unroll
@@ -572,7 +574,8 @@ __global__ __launch_bounds__(256) void k_interp_t(KParams kp, int64_t n,
         if (D == 3) row += (int64_t)M0 * M1 * wrap_index(i0[D - 1] + k2, M2);
 #pragma unroll
         for (int k0 = 0; k0 < W; ++k0) {
-          const double v = grid[row + wrap_index(i0[0] + k0, M0)].x;
+          const double2 gv = grid[row + wrap_index(i0[0] + k0, M0)];
+          const double v = comp ? gv.y : gv.x;
           a0 = fma(v, wt0[k0], a0);
           if (GRAD) ad0 = fma(v, dw0[k0], ad0);
         }
@@ -614,11 +617,11 @@ static void launch_spread_interp(pdmk_plan* P, Eval& E, const int* M, double bet
     if (want_grad)
       hipLaunchKernelGGL((k_interp_t<D, W, true, Real>), dim3(nblk(E.n_trg, 256)), dim3(256), 0,
                          E.s, P->kp, E.n_trg, E.tx, M[0], M[1], M[2], beta, cg,
-                         E.far_out ? E.far_out : E.pot_sorted, E.grad_sorted);
+                         E.far_out ? E.far_out : E.pot_sorted, E.grad_sorted, E.far_comp);
     else
       hipLaunchKernelGGL((k_interp_t<D, W, false, Real>), dim3(nblk(E.n_trg, 256)), dim3(256),
                          0, E.s, P->kp, E.n_trg, E.tx, M[0], M[1], M[2], beta, cg,
-                         E.far_out ? E.far_out : E.pot_sorted, E.grad_sorted);
+                         E.far_out ? E.far_out : E.pot_sorted, E.grad_sorted, E.far_comp);
   }
 }
 
@@ -653,6 +656,27 @@ __global__ void k_to_complex(int64_t n, const double* __restrict__ g, double2* _
   if (i < n) c[i] = make_double2(g[i], 0.0);
 }
 
+__global__ void k_to_complex2(int64_t n, const double* __restrict__ re,
+                              const double* __restrict__ im, double2* __restrict__ c) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) c[i] = make_double2(re[i], im[i]);
+}
+
+// Bloch source pre-modulation (Section 4.1): q~ = q_w e^{-i beta.x_w} for the
+// originals in tree order (wrapped positions x_w and charges q_w).
+__global__ void k_bloch_premod(KParams kp, int64_t n, const double* __restrict__ x,
+                               const double* __restrict__ qr, const double* __restrict__ qi,
+                               double* __restrict__ outr, double* __restrict__ outi) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double ph = 0.0;
+  for (int a = 0; a < kp.dim; ++a) ph += kp.beta[a] * x[a * n + i];
+  double sn, cs;
+  sincos(-ph, &sn, &cs);
+  outr[i] = qr[i] * cs - qi[i] * sn;
+  outi[i] = qr[i] * sn + qi[i] * cs;
+}
+
 __global__ void k_scale(int64_t n, double2* __restrict__ c, const double* __restrict__ s) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) {
@@ -683,12 +707,15 @@ __global__ void k_farscale(KParams kp, int M0, int M1, int M2, int Mp0, int Mp1,
     if (2 * m[a] >= Mp[a] || 2 * m[a] < -Mp[a] + 1) nyq = true;
     if (m[a] != 0) zero = false;
   }
-  if (nyq || zero) { out[idx] = 0.0; return; }
+  // periodic: m = 0 omitted (charge neutrality); Bloch: every mode kept, at
+  // the shifted wave vector k_m + beta (Section 4.1)
+  if (nyq || (zero && !kp.bloch)) { out[idx] = 0.0; return; }
   double k2 = 0.0;
   for (int b = 0; b < d; ++b) {
     double s = 0.0;
     for (int a = 0; a < d; ++a) s += kp.Li[a + d * b] * m[a];
     s *= 2.0 * 3.14159265358979323846;
+    if (kp.bloch) s += kp.beta[b];
     k2 += s * s;
   }
   const double x = sqrt(k2) * kp.rc / c;
@@ -767,6 +794,23 @@ void stage_far_grid(pdmk_plan* P, Eval& E) {
     spread_interp(P, E, M, w, beta, grid, cg, false, true);
     hipLaunchKernelGGL(k_fp_to_grid, dim3(nblk(n, 256)), dim3(256), 0, E.s, n, E.far_hi,
                        E.far_lo, E.qsum, cg);
+  } else if (P->kp.bloch) {
+    // complex pre-modulated charges: real and imaginary parts spread apart
+    double* grid2 = E.alloc<double>(n);
+    double* qtr = E.alloc<double>(E.n_src);
+    double* qti = E.alloc<double>(E.n_src);
+    if (E.n_src > 0)
+      hipLaunchKernelGGL(k_bloch_premod, dim3(nblk(E.n_src, 256)), dim3(256), 0, E.s, P->kp,
+                         E.n_src, E.ox, E.oq, E.oq_im, qtr, qti);
+    double* keep = E.oq;
+    E.oq = qtr;
+    fill_zero(grid, n * sizeof(double), E.s);
+    spread_interp(P, E, M, w, beta, grid, cg, false, true);
+    E.oq = qti;
+    fill_zero(grid2, n * sizeof(double), E.s);
+    spread_interp(P, E, M, w, beta, grid2, cg, false, true);
+    E.oq = keep;
+    hipLaunchKernelGGL(k_to_complex2, dim3(nblk(n, 256)), dim3(256), 0, E.s, n, grid, grid2, cg);
   } else {
     fill_zero(grid, n * sizeof(double), E.s);
     spread_interp(P, E, M, w, beta, grid, cg, false, true);

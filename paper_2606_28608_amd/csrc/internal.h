@@ -107,6 +107,8 @@ struct KParams {
   double L[9], Li[9], Q[9];
   double w0unit;    // W_h(0) for h = 1
   int precision;
+  int bloch;        // quasi-periodic conditions (Section 4.1)
+  double beta[3];   // Bloch vector in the oriented frame
 };
 
 // One tree level (device arrays; counts on host).
@@ -155,6 +157,14 @@ struct Eval {
   int* tperm = nullptr;   // sorted target -> original target index
   double* ox = nullptr;   // original sources in tree order (dim * n_src), for the far field
   double* oq = nullptr;
+  // Bloch conditions: wrap phases of sources and targets (beta.L w), the
+  // imaginary parts of the wrapped charges (unsorted; q holds the real
+  // parts), of the sorted image charges and of the originals in tree order
+  double* theta_s = nullptr;
+  double* theta_t = nullptr;
+  const double* q_im = nullptr;
+  double* sq_im = nullptr;
+  double* oq_im = nullptr;
   // kept-tree evaluation (pdmk_plan_bind / pdmk_plan_execute)
   bool keep_map = false;    // stage_images also writes img_src (and operm)
   int* img_src = nullptr;   // sorted image -> source index
@@ -190,6 +200,7 @@ struct Eval {
   bool near_pending = false;
   double* far_out = nullptr;    // separate far-field part (tree order), else null:
                                 // the interpolation adds into pot_sorted
+  int far_comp = 0;             // grid part the interpolation reads (1: imaginary)
   double* far_grid = nullptr;   // spreading grid (real)
   unsigned long long* far_hi = nullptr;   // fixed-order mode: fixed-point grid words
   unsigned long long* far_lo = nullptr;

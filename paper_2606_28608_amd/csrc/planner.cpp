@@ -361,7 +361,7 @@ static void inv3(int d, const double* A, double* Ai) {
 }
 
 std::string make_geometry(int d, const double* Lin, double kappa, double c, double sigma,
-                          Geometry& g) {
+                          Geometry& g, double beta_norm) {
   g = Geometry();
   g.dim = d;
   // sort lattice vectors by decreasing length (stable), Section 3.2
@@ -439,12 +439,15 @@ std::string make_geometry(int d, const double* Lin, double kappa, double c, doub
     n[i] = 0;
   };
   rec(d - 1);
-  // Fourier grid (eq:Mi with eq:anorms)
+  // Fourier grid (eq:Mi with eq:anorms); with a Bloch vector the active modes
+  // |k_m + beta| <= c / r_c need M_i = 2 ceil((c / r_c + |beta|) |a_i| / 2 pi)
+  // (Section 4.1, Fourier grid)
   for (int i = 0; i < d; ++i) {
     double an = 0;
     for (int k = 0; k <= i; ++k) an += g.L[k + d * i] * g.L[k + d * i];
     an = std::sqrt(an);
-    int M = 2 * (int)std::ceil(c * an / (2.0 * kPi * g.rc));
+    int M = beta_norm == 0.0 ? 2 * (int)std::ceil(c * an / (2.0 * kPi * g.rc))
+                             : 2 * (int)std::ceil((c / g.rc + beta_norm) * an / (2.0 * kPi));
     if (M < 2) M = 2;
     g.fgrid_paper[i] = M;
     g.fgrid[i] = next_fft_size((int)std::ceil(std::max(1.0, sigma) * M - 1e-9));

@@ -98,8 +98,10 @@ struct Geometry {
   int fgrid[3] = {1, 1, 1};
 };
 // Returns empty string on success, else a message.
+// beta_norm: |beta| of a Bloch vector (0: periodic), which enlarges the
+// Fourier grid (Section 4.1).
 std::string make_geometry(int dim, const double* Lin, double kappa, double c,
-                          double sigma, Geometry& g);
+                          double sigma, Geometry& g, double beta_norm = 0.0);
 
 // Smallest even integer >= n whose prime factors are 2, 3, 5.
 int next_fft_size(int n);

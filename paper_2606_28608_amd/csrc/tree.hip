@@ -36,9 +36,12 @@ static inline int nblk(int64_t n, int b) { return (int)((n + b - 1) / b); }
 
 // ------------------------------------------------------------- orientation
 // x' = Q^T x ; u = L^{-1} x' wrapped to [0,1) ; x' = L u  (FP64)
+// theta (Bloch conditions only, else null): beta.(wrapped - given) = beta.L w
+// for the lattice vector L w that wraps the point (the phase its charge, or
+// its value as a target, carries across the wrap).
 __global__ void k_prepare(KParams kp, int64_t n, const double* __restrict__ xin,
                           double* __restrict__ xo, double* __restrict__ uo,
-                          int* __restrict__ bad) {
+                          int* __restrict__ bad, double* __restrict__ theta) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const int d = kp.dim;
@@ -64,12 +67,27 @@ __global__ void k_prepare(KParams kp, int64_t n, const double* __restrict__ xin,
     if (s >= 1.0 || s < 0.0) s = 0.0;
     u[a] = s;
   }
+  double th = 0.0;
   for (int a = 0; a < d; ++a) {
     double s = 0;
     for (int b = a; b < d; ++b) s += kp.L[a + d * b] * u[b];
     xo[a * n + i] = s;
     uo[a * n + i] = u[a];
+    th += kp.beta[a] * (s - xr[a]);
   }
+  if (theta) theta[i] = th;
+}
+
+// Wrapped Bloch charges q e^{i theta} (real and imaginary parts).
+__global__ void k_bloch_charges(int64_t n, const double* __restrict__ q,
+                                const double* __restrict__ theta, double* __restrict__ qr,
+                                double* __restrict__ qi) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double sn, cs;
+  sincos(theta[i], &sn, &cs);
+  qr[i] = q[i] * cs;
+  qi[i] = q[i] * sn;
 }
 
 // ------------------------------------------------------------------ images
@@ -176,20 +194,33 @@ __global__ __launch_bounds__(256) void k_img_count(KParams kp, int64_t n,
 
 // Images of source i at off[i]...; isrc[o] = i for the unshifted copy, -1
 // for the shifted ones; iall[o] = i for every image (when iall is given).
+// Bloch conditions (qim, qi_im not null): the source's charge q + i qim and
+// its image at y = x + L n carries (q + i qim) e^{i beta.L n} (Section 4.1).
 __global__ void k_img_emit(KParams kp, int64_t n, const double* __restrict__ xs,
                            const double* __restrict__ q, const int* __restrict__ off,
                            int64_t nimg, double* __restrict__ xi, double* __restrict__ qi,
-                           int* __restrict__ isrc, int* __restrict__ iall) {
+                           int* __restrict__ isrc, int* __restrict__ iall,
+                           const double* __restrict__ qim, double* __restrict__ qi_im) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const int d = kp.dim;
   double x[3] = {0, 0, 0};
   for (int a = 0; a < d; ++a) x[a] = xs[a * n + i];
   const double qq = q[i];
+  const double qm = qim ? qim[i] : 0.0;
   int64_t o = off[i];
   for_each_image(kp, x, [&](const double* y) {
     for (int a = 0; a < d; ++a) xi[a * nimg + o] = y[a];
-    qi[o] = qq;
+    if (qi_im) {
+      double ph = 0.0;
+      for (int a = 0; a < d; ++a) ph += kp.beta[a] * (y[a] - x[a]);
+      double sn, cs;
+      sincos(ph, &sn, &cs);
+      qi[o] = qq * cs - qm * sn;
+      qi_im[o] = qq * sn + qm * cs;
+    } else {
+      qi[o] = qq;
+    }
     isrc[o] = (y[0] == x[0] && y[1] == x[1] && y[2] == x[2]) ? (int)i : -1;
     if (iall) iall[o] = (int)i;
     ++o;
@@ -215,7 +246,8 @@ __global__ void k_orig_pick(int64_t nimg, int64_t n, int d, const int* __restric
                             const int* __restrict__ pos, const uint64_t* __restrict__ skey,
                             const double* __restrict__ sx, const double* __restrict__ sq,
                             uint64_t* __restrict__ tkey, double* __restrict__ tx,
-                            int* __restrict__ tperm, double* __restrict__ oq) {
+                            int* __restrict__ tperm, double* __restrict__ oq,
+                            const double* __restrict__ sq_im, double* __restrict__ oq_im) {
   int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= nimg) return;
   const int src = osrc[p];
@@ -224,6 +256,7 @@ __global__ void k_orig_pick(int64_t nimg, int64_t n, int d, const int* __restric
   tperm[t] = src;
   tkey[t] = skey[p];
   oq[t] = sq[p];
+  if (oq_im) oq_im[t] = sq_im[p];
   for (int a = 0; a < d; ++a) tx[a * n + t] = sx[a * nimg + p];
 }
 
@@ -315,24 +348,39 @@ void stage_prepare(pdmk_plan* P, Eval& E, const double* src, const double* trg) 
   int* bad = E.d_flags + 1;
   E.xs = E.alloc<double>(E.n_src * kp.dim);
   E.us = E.alloc<double>(E.n_src * kp.dim);
+  if (kp.bloch) E.theta_s = E.alloc<double>(E.n_src);
   if (E.n_src > 0)
     hipLaunchKernelGGL(k_prepare, dim3(nblk(E.n_src, 256)), dim3(256), 0, E.s, kp, E.n_src, src,
-                       E.xs, E.us, bad);
+                       E.xs, E.us, bad, E.theta_s);
   if (E.self_targets) {
     E.xt = E.xs;
     E.ut = E.us;
+    E.theta_t = E.theta_s;
   } else {
     E.xt = E.alloc<double>(E.n_trg * kp.dim);
     E.ut = E.alloc<double>(E.n_trg * kp.dim);
+    if (kp.bloch) E.theta_t = E.alloc<double>(E.n_trg);
     if (E.n_trg > 0)
       hipLaunchKernelGGL(k_prepare, dim3(nblk(E.n_trg, 256)), dim3(256), 0, E.s, kp, E.n_trg,
-                         trg, E.xt, E.ut, bad);
+                         trg, E.xt, E.ut, bad, E.theta_t);
   }
 }
 
 void stage_images(pdmk_plan* P, Eval& E, const double* q) {
   const KParams& kp = P->kp;
   int64_t n = E.n_src;
+  const double* qim = nullptr;   // Bloch: imaginary part of the wrapped charges
+  if (kp.bloch) {
+    double* qr = E.alloc<double>(n);
+    double* qm = E.alloc<double>(n);
+    if (n > 0)
+      hipLaunchKernelGGL(k_bloch_charges, dim3(nblk(n, 256)), dim3(256), 0, E.s, n, q,
+                         E.theta_s, qr, qm);
+    q = qr;
+    qim = qm;
+    E.q = qr;
+    E.q_im = qm;
+  }
   int* cnt = E.alloc<int>(n + 2);   // [n + 1]: sources whose unshifted copy is missing
   int* off = E.alloc<int>(n + 1);
   unsigned long long* total64 = E.alloc<unsigned long long>(1);
@@ -359,11 +407,18 @@ void stage_images(pdmk_plan* P, Eval& E, const double* q) {
   double* qi = E.alloc<double>(E.n_img);
   int* isrc = E.alloc<int>(E.n_img);
   int* iall = E.keep_map ? E.alloc<int>(E.n_img) : nullptr;
+  double* qi_im = qim ? E.alloc<double>(E.n_img) : nullptr;
   if (n > 0)
     hipLaunchKernelGGL(k_img_emit, dim3(nblk(n, 256)), dim3(256), 0, E.s, kp, n, E.xs, q, off,
-                       E.n_img, xi, qi, isrc, iall);
+                       E.n_img, xi, qi, isrc, iall, qim, qi_im);
   int* perm = nullptr;
   sort_points(P, E, E.n_img, xi, qi, E.skey, E.sx, E.sq, perm);
+  if (qim) {
+    E.sq_im = E.alloc<double>(E.n_img);
+    if (E.n_img > 0)
+      hipLaunchKernelGGL(k_gather, dim3(nblk(E.n_img, 256)), dim3(256), 0, E.s, E.n_img, 0, perm,
+                         (const double*)nullptr, E.n_img, qi_im, (double*)nullptr, E.sq_im);
+  }
   if (E.keep_map) {
     // source index of every sorted image, for re-gathering charges and
     // displacements on the kept tree
@@ -378,6 +433,7 @@ void stage_images(pdmk_plan* P, Eval& E, const double* q) {
     E.tperm = E.alloc<int>(E.n_trg);
     E.ox = E.tx;
     E.oq = E.alloc<double>(n);
+    if (qim) E.oq_im = E.alloc<double>(n);
     int* flag = E.alloc<int>(E.n_img + 1);
     int* pos = E.alloc<int>(E.n_img + 1);
     int* osrc = E.alloc<int>(E.n_img + 1);
@@ -387,7 +443,7 @@ void stage_images(pdmk_plan* P, Eval& E, const double* q) {
       exclusive_scan_int(flag, pos, (int)E.n_img, E);
       hipLaunchKernelGGL(k_orig_pick, dim3(nblk(E.n_img, 256)), dim3(256), 0, E.s, E.n_img,
                          E.n_trg, kp.dim, osrc, pos, E.skey, E.sx, E.sq, E.tkey, E.tx, E.tperm,
-                         E.oq);
+                         E.oq, E.sq_im, E.oq_im);
     }
     return;   // original sources in tree order: the picked copies
   } else {
@@ -401,11 +457,23 @@ void stage_images(pdmk_plan* P, Eval& E, const double* q) {
     if (n > 0)
       hipLaunchKernelGGL(k_gather, dim3(nblk(n, 256)), dim3(256), 0, E.s, n, 0, E.tperm, E.xs, n,
                          q, (double*)nullptr, E.oq);
+    if (qim) {
+      E.oq_im = E.alloc<double>(n);
+      if (n > 0)
+        hipLaunchKernelGGL(k_gather, dim3(nblk(n, 256)), dim3(256), 0, E.s, n, 0, E.tperm, E.xs,
+                           n, qim, (double*)nullptr, E.oq_im);
+    }
   } else {
     uint64_t* okey = nullptr;
     int* operm = nullptr;
     sort_points(P, E, n, E.xs, q, okey, E.ox, E.oq, operm);
     E.operm = operm;
+    if (qim) {
+      E.oq_im = E.alloc<double>(n);
+      if (n > 0)
+        hipLaunchKernelGGL(k_gather, dim3(nblk(n, 256)), dim3(256), 0, E.s, n, 0, operm, E.xs, n,
+                           qim, (double*)nullptr, E.oq_im);
+    }
   }
 }
 

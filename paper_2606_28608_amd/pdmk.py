@@ -26,6 +26,7 @@ PDMK_ALLOW_NONNEUTRAL = 2
 PDMK_DETERMINISTIC = 4
 PDMK_VECTOR_PLANE_WAVES = 8
 PDMK_ONE_STREAM = 16
+PDMK_BLOCH = 32
 PDMK_FP32_RESIDUAL = 1
 PDMK_FP32_PROXY = 2
 PDMK_FP32_WINDOW = 4
@@ -34,7 +35,7 @@ PDMK_BF16_PLANE_WAVES = 8
 STATUS = {0: "PDMK_OK", -1: "PDMK_ERR_INVALID_ARG", -2: "PDMK_ERR_SINGULAR_LATTICE",
           -3: "PDMK_ERR_NOT_NEUTRAL", -4: "PDMK_ERR_EPS_RANGE", -5: "PDMK_ERR_NONFINITE",
           -6: "PDMK_ERR_OUT_OF_MEMORY", -7: "PDMK_ERR_HIP", -8: "PDMK_ERR_NO_DEVICE",
-          -9: "PDMK_ERR_UNSUPPORTED"}
+          -9: "PDMK_ERR_UNSUPPORTED", -10: "PDMK_ERR_SCRATCH"}
 
 
 class PdmkError(RuntimeError):
@@ -47,7 +48,8 @@ class Opts(ctypes.Structure):
     _fields_ = [("dim", ctypes.c_int), ("eps", ctypes.c_double), ("precision", ctypes.c_int),
                 ("kappa", ctypes.c_double), ("n_s", ctypes.c_int), ("flags", ctypes.c_uint),
                 ("porder", ctypes.c_int), ("npw", ctypes.c_int), ("nufft_w", ctypes.c_int),
-                ("sigma", ctypes.c_double), ("fp32_stages", ctypes.c_uint)]
+                ("sigma", ctypes.c_double), ("fp32_stages", ctypes.c_uint),
+                ("bloch", ctypes.c_double * 3)]
 
 
 class Geometry(ctypes.Structure):
@@ -125,6 +127,8 @@ def lib():
                                      ctypes.POINTER(ctypes.c_int), ctypes.c_int, ctypes.c_int64,
                                      _vp, _vp, ctypes.c_int64, _vp, _vp, _vp, _dp, _dp,
                                      ctypes.POINTER(ctypes.c_int)]
+        L.pdmk_plan_eval_bloch.argtypes = [_vp, ctypes.c_int64, _vp, _vp, ctypes.c_int64, _vp,
+                                           _vp, _vp]
         L.pdmk_plan_eval_parts.argtypes = [_vp, ctypes.c_int64, _vp, _vp, ctypes.c_int64, _vp,
                                            _vp, _vp, _vp]
         L.pdmk_plan_eval_noalloc.argtypes = [_vp, ctypes.c_int64, _vp, _vp, ctypes.c_int64, _vp,
@@ -159,10 +163,11 @@ def _check(code):
 
 
 def default_opts(dim, eps, precision="fp64", grad=False, allow_nonneutral=False,
-                 deterministic=False, vector_plane_waves=False, one_stream=False, **over):
+                 deterministic=False, vector_plane_waves=False, one_stream=False, bloch=None,
+                 **over):
     """pdmk_opts for (dim, eps) with the defaults of pdmk_default_opts; keyword
     arguments set flags (grad, allow_nonneutral, deterministic,
-    vector_plane_waves, one_stream) or override fields (kappa, n_s, porder, npw, nufft_w,
+    vector_plane_waves, one_stream, bloch = Bloch vector) or override fields (kappa, n_s, porder, npw, nufft_w,
     sigma, fp32_stages)."""
     o = Opts()
     _check(lib().pdmk_default_opts(int(dim), float(eps), ctypes.byref(o)))
@@ -172,7 +177,14 @@ def default_opts(dim, eps, precision="fp64", grad=False, allow_nonneutral=False,
     o.flags = ((PDMK_WANT_GRAD if grad else 0) | (PDMK_ALLOW_NONNEUTRAL if allow_nonneutral else 0)
                | (PDMK_DETERMINISTIC if deterministic else 0)
                | (PDMK_VECTOR_PLANE_WAVES if vector_plane_waves else 0)
-               | (PDMK_ONE_STREAM if one_stream else 0))
+               | (PDMK_ONE_STREAM if one_stream else 0)
+               | (PDMK_BLOCH if bloch is not None else 0))
+    if bloch is not None:
+        b = [float(v) for v in bloch]
+        if len(b) != dim:
+            raise ValueError("the Bloch vector needs %d components" % dim)
+        for i, v in enumerate(b):
+            o.bloch[i] = v
     for k, v in over.items():
         if v is not None:
             setattr(o, k, v)
@@ -308,6 +320,8 @@ class Plan:
         pot = torch.empty(m, dtype=torch.float64, device=src.device) if out is None else out
         grad = torch.empty((m, self.dim), dtype=torch.float64, device=src.device) \
             if wg else None
+        if m == 0:   # an empty target array has no address (NULL means the sources)
+            return (pot, grad) if wg else pot
         _check(lib().pdmk_plan_eval(self._h, n, ctypes.c_void_p(src.data_ptr()),
                                     ctypes.c_void_p(q.data_ptr()), m,
                                     ctypes.c_void_p(trg.data_ptr()) if trg is not None else None,
@@ -315,6 +329,25 @@ class Plan:
                                     ctypes.c_void_p(grad.data_ptr()) if grad is not None else None,
                                     _stream(torch)))
         return (pot, grad) if wg else pot
+
+    def eval_bloch(self, src, q, trg=None):
+        """pdmk_plan_eval_bloch (plan made with bloch=beta): complex potential
+        (torch.complex128) at the targets (the sources when trg is None)."""
+        import torch
+        src = _dev(src, torch)
+        q = _dev(q, torch)
+        n = src.shape[0]
+        if src.shape != (n, self.dim) or q.shape != (n,):
+            raise ValueError("src must be (N, dim) and q (N,)")
+        trg = _dev(trg, torch) if trg is not None else None
+        m = trg.shape[0] if trg is not None else n
+        out = torch.empty((m, 2), dtype=torch.float64, device=src.device)
+        if m == 0:   # an empty target array has no address (NULL means the sources)
+            return torch.view_as_complex(out)
+        vp = lambda t: ctypes.c_void_p(t.data_ptr()) if t is not None else None  # noqa: E731
+        _check(lib().pdmk_plan_eval_bloch(self._h, n, vp(src), vp(q), m, vp(trg), vp(out),
+                                          _stream(torch)))
+        return torch.view_as_complex(out)
 
     def eval_parts(self, src, q, trg=None):
         """pdmk_plan_eval_parts: (near, far) halves of the potential."""
@@ -326,6 +359,8 @@ class Plan:
         m = trg.shape[0] if trg is not None else n
         near = torch.empty(m, dtype=torch.float64, device=src.device)
         far = torch.empty(m, dtype=torch.float64, device=src.device)
+        if m == 0:   # an empty target array has no address (NULL means the sources)
+            return near, far
         vp = lambda t: ctypes.c_void_p(t.data_ptr()) if t is not None else None  # noqa: E731
         _check(lib().pdmk_plan_eval_parts(self._h, n, vp(src), vp(q), m, vp(trg), vp(near),
                                           vp(far), _stream(torch)))
@@ -461,6 +496,8 @@ def pdmk_eval(L, src, q, trg=None, eps=1e-6, precision="fp64", grad=False,
         trg = _dev(trg, torch)
     pot = torch.empty(m, dtype=torch.float64, device=src.device)
     g = torch.empty((m, dim), dtype=torch.float64, device=src.device) if grad else None
+    if m == 0:   # an empty target array has no address (NULL means the sources)
+        return (pot, g) if grad else pot
     Lf = _lattice(L, dim)
     _check(lib().pdmk_eval(ctypes.byref(o), Lf.ctypes.data_as(_dp), n,
                            ctypes.c_void_p(src.data_ptr()), ctypes.c_void_p(q.data_ptr()), m,

@@ -240,3 +240,33 @@ def test_batch_tune_argument_errors(lib):
                                  kap.ctypes.data_as(dp), ns, trials, None, None, None)
         assert st == -1
     assert b"null argument" in lib.pdmk_last_error()
+
+
+def test_bloch_grid_and_reciprocal_lattice():
+    """Bloch plans (Section 4.1): the far-field grid grows to
+    M_i = 2 ceil((c / r_c + |beta|) |a_i| / 2 pi); a Bloch vector in the
+    reciprocal lattice (the periodic case) is rejected; the vector needs one
+    component per dimension."""
+    L = workloads.TRICLINIC3D_L
+    beta = np.array([0.7, -1.1, 0.4])
+    g0 = pdmk.geometry(L, eps=1e-6)
+    g1 = pdmk.geometry(L, eps=1e-6, bloch=beta)
+    bn = float(np.linalg.norm(beta))
+    Lo = np.asarray(g1.L_oriented[:9]).reshape(3, 3)   # row a = oriented column a
+    for i in range(3):
+        an = float(np.linalg.norm(Lo[i]))
+        assert g1.fgrid_paper[i] == 2 * math.ceil((g1.c / g1.rc + bn) * an / (2 * math.pi))
+        assert g1.fgrid_paper[i] >= g0.fgrid_paper[i]
+    # a Bloch vector comparable to c / r_c enlarges every axis
+    big = pdmk.geometry(L, eps=1e-6, bloch=beta * (g1.c / g1.rc) / bn)
+    assert all(big.fgrid_paper[i] > g0.fgrid_paper[i] for i in range(3))
+    recip = 2.0 * math.pi * np.linalg.solve(L.T, np.array([1.0, 0.0, -2.0]))
+    with pytest.raises(pdmk.PdmkError) as e:
+        pdmk.geometry(L, eps=1e-6, bloch=recip)
+    assert e.value.code == -1
+    with pytest.raises(ValueError):
+        pdmk.geometry(L, eps=1e-6, bloch=[0.1, 0.2])
+    # flags that Bloch plans do not support
+    with pytest.raises(pdmk.PdmkError) as e:
+        pdmk.geometry(L, eps=1e-6, bloch=beta, deterministic=True)
+    assert e.value.code == -9
