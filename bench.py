@@ -164,6 +164,41 @@ def run_mode(pdmk, L, S, Q, n, eps, precision, steps, warmup, gold, over=None):
             "stats": st, "stages_ms": {k: round(v, 3) for k, v in avg.items()}}
 
 
+def run_bloch(pdmk, L, S, Q, n, eps, precision, steps, warmup, over):
+    """Quasi-periodic evaluation (pdmk_plan_eval_bloch) of the same input and
+    plan, Bloch vector (0.7, -1.1, 0.4), against the stored Bloch oracle values
+    when present."""
+    import numpy as np
+    import torch
+    beta = np.array([0.7, -1.1, 0.4])
+    progress("bloch %s eps=%g %s: %d warm-up + %d timed steps" % (precision, eps, over,
+                                                                warmup, steps))
+    plan = pdmk.Plan(L, eps=eps, precision=precision, bloch=beta, **over)
+    for _ in range(warmup):
+        pot = plan.eval_bloch(S, Q)
+    torch.cuda.synchronize()
+    per = []
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        t1 = time.perf_counter()
+        pot = plan.eval_bloch(S, Q)
+        per.append(1e3 * (time.perf_counter() - t1))
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    err = None
+    path = os.path.join(ROOT, "tests", "golden", "shell3d_n1e7_seed3_bloch.txt")
+    if n == 10_000_000 and os.path.exists(path):
+        data = np.loadtxt(path)
+        idx = data[:, 0].astype(np.int64)
+        ref = data[:, 1] + 1j * data[:, 2]
+        got = pot.cpu().numpy()[idx]
+        err = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
+    return {"value": n / (dt / steps), "ms_per_step": 1e3 * dt / steps,
+            "median_ms": statistics.median(per), "e_rel_sampled": err,
+            "parity_ok": err is None or err <= eps, "beta": list(beta),
+            "fourier_grid": list(plan.geometry().fgrid)}
+
+
 def _ball_modes(J):
     """Modes of the Hermitian half ball |j| <= J (j0 >= 0)."""
     n = 0
@@ -347,6 +382,8 @@ def child(args):
                        dict(over, one_stream=True))
         r["far_field"] = far_field(one, n, r["plan"], args.precision)
         extra["one_stream"] = brief(one, args.eps)
+        # quasi-periodic conditions (Section 4.1) with the same plan
+        extra["bloch"] = run_bloch(pdmk, L, S, Q, n, args.eps, args.precision, 3, 1, over)
         r["extra"] = extra
         for k in ("k_spread_coop", "k_interp_t"):
             r["roofline"]["kernels"][k] = {kk: r["far_field"][k][kk]

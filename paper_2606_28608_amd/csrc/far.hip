@@ -90,25 +90,42 @@ __device__ inline void small_dft(double2* v, int R, int sign) {
   }
 }
 
-// Stockham FFT of `lpb` grid lines of length M along one axis per workgroup,
-// in LDS.  tw[k] = exp(-2 pi i k / M) (FP64, from the host); sign = +1 uses
-// its conjugate.  Lines along a strided axis are loaded line-fastest (the
-// lines of a workgroup are adjacent in memory), lines along the contiguous
-// axis element-fastest.
-__global__ __launch_bounds__(256) void k_fft_lines(double2* __restrict__ data, int M,
-                                                   int64_t stride, int nl0, int64_t so0,
-                                                   int64_t so1, int nlines, int lpb, int sign,
-                                                   Radices rad,
+// One batch of grid lines for k_fft_lines: line l starts at
+//   (l % nl0) so0 + ((l / nl0) % nl1) so1 + (l / (nl0 nl1)) so2
+// and holds M elements `stride` apart.  tw is the twiddle table of the whole
+// axis, exp(-2 pi i j / (M twmul)); the radix passes read tw[j twmul].  With
+// post set, element i of line l is multiplied by tw[i (l % nl0)] after the
+// transform (the inter-step twiddle of the four-step split).
+struct FftLines {
+  int M;
+  int64_t stride;
+  int nl0, nl1;
+  int64_t so0, so1, so2;
+  int nlines;
+  int twmul;
+  int post;
+};
+
+// Stockham FFT of `lpb` grid lines of length M per workgroup, in LDS (FP64
+// twiddles from the host; sign = +1 uses their conjugates).  Lines along a
+// strided direction are loaded line-fastest (the lines of a workgroup are
+// adjacent in memory), lines along the contiguous direction element-fastest.
+__global__ __launch_bounds__(256) void k_fft_lines(double2* __restrict__ data, FftLines f,
+                                                   int lpb, int sign, Radices rad,
                                                    const double2* __restrict__ tw) {
   extern __shared__ double2 sh[];
+  const int M = f.M;
   double2* b0 = sh;
   double2* b1 = sh + lpb * M;
   const int l0 = blockIdx.x * lpb;
-  const int nl = min(lpb, nlines - l0);
+  const int nl = min(lpb, f.nlines - l0);
   const int tot = nl * M;
+  const bool contiguous = f.stride == 1;
   auto addr = [&](int l, int i) {
     const int line = l0 + l;
-    return (int64_t)(line % nl0) * so0 + (int64_t)(line / nl0) * so1 + (int64_t)i * stride;
+    const int r = line / f.nl0;
+    return (int64_t)(line % f.nl0) * f.so0 + (int64_t)(r % f.nl1) * f.so1 +
+           (int64_t)(r / f.nl1) * f.so2 + (int64_t)i * f.stride;
   };
   // eight loads in flight per thread
   for (int e0 = threadIdx.x; e0 < tot; e0 += 8 * 256) {
@@ -117,7 +134,7 @@ __global__ __launch_bounds__(256) void k_fft_lines(double2* __restrict__ data, i
     for (int u = 0; u < 8; ++u) {
       const int e = e0 + u * 256;
       if (e < tot) {
-        const int l = stride == 1 ? e / M : e % nl, i = stride == 1 ? e % M : e / nl;
+        const int l = contiguous ? e / M : e % nl, i = contiguous ? e % M : e / nl;
         v[u] = data[addr(l, i)];
       }
     }
@@ -125,7 +142,7 @@ __global__ __launch_bounds__(256) void k_fft_lines(double2* __restrict__ data, i
     for (int u = 0; u < 8; ++u) {
       const int e = e0 + u * 256;
       if (e < tot) {
-        const int l = stride == 1 ? e / M : e % nl, i = stride == 1 ? e % M : e / nl;
+        const int l = contiguous ? e / M : e % nl, i = contiguous ? e % M : e / nl;
         b0[l * M + i] = v[u];
       }
     }
@@ -143,7 +160,7 @@ __global__ __launch_bounds__(256) void k_fft_lines(double2* __restrict__ data, i
       for (int r = 0; r < R; ++r) v[r] = in[j + r * nb];
       const int jm = j % Ns;
       if (Ns > 1 && jm > 0) {
-        double2 w1 = tw[jm * step];
+        double2 w1 = tw[(int64_t)jm * step * f.twmul];
         if (sign > 0) w1.y = -w1.y;
         double2 w = w1;
         for (int r = 1; r < R; ++r) {
@@ -162,31 +179,91 @@ __global__ __launch_bounds__(256) void k_fft_lines(double2* __restrict__ data, i
     Ns *= R;
   }
   for (int e0 = threadIdx.x; e0 < tot; e0 += 256) {
-    const int l = stride == 1 ? e0 / M : e0 % nl, i = stride == 1 ? e0 % M : e0 / nl;
-    data[addr(l, i)] = b0[l * M + i];
+    const int l = contiguous ? e0 / M : e0 % nl, i = contiguous ? e0 % M : e0 / nl;
+    double2 v = b0[l * M + i];
+    if (f.post) {
+      double2 w = tw[(int64_t)i * ((l0 + l) % f.nl0)];
+      if (sign > 0) w.y = -w.y;
+      v = cmul(v, w);
+    }
+    data[addr(l, i)] = v;
   }
 }
 
+// Longest line a workgroup transforms in LDS (two FP64 complex buffers of
+// 4096 points: 128 KB).  Longer axes use the four-step split below.
+constexpr int kFftLineMax = 4096;
+
+// Factor M = A B (A, B <= kFftLineMax, as balanced as possible), or A = M,
+// B = 1 when M fits one line.
+static void fft_split(int M, int& A, int& B) {
+  A = M;
+  B = 1;
+  if (M <= kFftLineMax) return;
+  int best = 0;
+  for (int a = 2; a <= kFftLineMax; ++a)
+    if (M % a == 0 && M / a <= kFftLineMax && (best == 0 || std::abs(a * a - M) <
+                                                                std::abs(best * best - M)))
+      best = a;
+  if (best == 0)
+    throw Error{PDMK_ERR_UNSUPPORTED, "Fourier grid axis has no split into two lines of at most " +
+                                          std::to_string(kFftLineMax)};
+  A = best;
+  B = M / A;
+}
+
+static void fft_launch(double2* g, const FftLines& f, int sign, const double2* tw,
+                       hipStream_t s) {
+  Radices R = factorize(f.M);
+  // several short lines per workgroup (at most 2048 points, 64 KB of LDS)
+  const int lpb = std::max(1, std::min(2048 / f.M, 64));
+  const int nblocks = (f.nlines + lpb - 1) / lpb;
+  const size_t smem = 2 * (size_t)lpb * f.M * sizeof(double2);
+  ensure_lds((const void*)&k_fft_lines, smem);
+  hipLaunchKernelGGL(k_fft_lines, dim3(nblocks), dim3(256), smem, s, g, f, lpb, sign, R, tw);
+  PDMK_HIP(hipGetLastError());
+}
+
+// In-place FFT of the grid along every axis.  An axis of length M = A B with
+// M > kFftLineMax is split in four steps (n = B n1 + n2, k = k1 + A k2):
+// forward, A-point transforms over n1, twiddle exp(-2 pi i n2 k1 / M),
+// B-point transforms over n2, leaving X[k1 + A k2] at position B k1 + k2
+// (transposed order, which the diagonal scaling table follows); the inverse
+// takes that order back to natural order by the mirrored steps.
 static void fft3(double2* g, const int* M, int dim, int sign, const double2* tw,
                  const int64_t* tw_off, hipStream_t s) {
   const int64_t M0 = M[0], M1 = M[1], M2 = dim == 3 ? M[2] : 1;
   for (int ax = 0; ax < dim; ++ax) {
-    int Ma = M[ax];
+    const int Ma = M[ax];
     if (Ma == 1) continue;
-    if (Ma > 4096) throw Error{PDMK_ERR_UNSUPPORTED, "Fourier grid axis longer than 4096"};
-    Radices R = factorize(Ma);
-    int64_t stride, so0, so1;
-    int nl0, nlines;
-    if (ax == 0) { stride = 1; nl0 = (int)M1; so0 = M0; so1 = M0 * M1; nlines = (int)(M1 * M2); }
-    else if (ax == 1) { stride = M0; nl0 = (int)M0; so0 = 1; so1 = M0 * M1; nlines = (int)(M0 * M2); }
-    else { stride = M0 * M1; nl0 = (int)M0; so0 = 1; so1 = M0; nlines = (int)(M0 * M1); }
-    // several short lines per workgroup (at most 2048 points, 64 KB of LDS)
-    const int lpb = std::max(1, std::min(2048 / Ma, 64));
-    const int nblocks = (nlines + lpb - 1) / lpb;
-    size_t smem = 2 * (size_t)lpb * Ma * sizeof(double2);
-    ensure_lds((const void*)&k_fft_lines, smem);
-    hipLaunchKernelGGL(k_fft_lines, dim3(nblocks), dim3(256), smem, s, g, Ma, stride, nl0, so0,
-                       so1, nlines, lpb, sign, R, tw + tw_off[ax]);
+    // the other two axes: lines at (i % n_o0) s_o0 + (i / n_o0) s_o1
+    int64_t sa, s_o0, s_o1;
+    int n_o0, n_other;
+    if (ax == 0) { sa = 1; n_o0 = (int)M1; s_o0 = M0; s_o1 = M0 * M1; n_other = (int)(M1 * M2); }
+    else if (ax == 1) { sa = M0; n_o0 = (int)M0; s_o0 = 1; s_o1 = M0 * M1; n_other = (int)(M0 * M2); }
+    else { sa = M0 * M1; n_o0 = (int)M0; s_o0 = 1; s_o1 = M0; n_other = (int)(M0 * M1); }
+    int A, B;
+    fft_split(Ma, A, B);
+    const double2* t = tw + tw_off[ax];
+    if (B == 1) {
+      fft_launch(g, FftLines{Ma, sa, n_o0, INT_MAX, s_o0, s_o1, 0, n_other, 1, 0}, sign, t, s);
+      continue;
+    }
+    // over n1 (or k1): lines n2 (k2 ... ) at offset n2 sa, elements B sa apart
+    const FftLines over_a{A, B * sa, B, n_o0, sa, s_o0, s_o1, B * n_other, B, 0};
+    // over n2 (or k2): lines k1 at offset B k1 sa, elements sa apart
+    const FftLines over_b{B, sa, A, n_o0, B * sa, s_o0, s_o1, A * n_other, A, 0};
+    if (sign < 0) {
+      FftLines f1 = over_a;
+      f1.post = 1;
+      fft_launch(g, f1, sign, t, s);
+      fft_launch(g, over_b, sign, t, s);
+    } else {
+      FftLines f1 = over_b;
+      f1.post = 1;
+      fft_launch(g, f1, sign, t, s);
+      fft_launch(g, over_a, sign, t, s);
+    }
   }
 }
 
@@ -686,8 +763,14 @@ __global__ void k_scale(int64_t n, double2* __restrict__ c, const double* __rest
 }
 
 // Diagonal scaling table (FP64), once per plan.
+// Spectrum order per axis: B > 1 for an axis transformed in four steps, whose
+// storage position p holds frequency index p / B + A (p % B).
+struct FftOrder {
+  int A[3], B[3];
+};
+
 __global__ void k_farscale(KParams kp, int M0, int M1, int M2, int Mp0, int Mp1, int Mp2,
-                           const double* __restrict__ wf0,
+                           FftOrder ord, const double* __restrict__ wf0,
                            const double* __restrict__ wf1, const double* __restrict__ wf2,
                            const double* __restrict__ gx, const double* __restrict__ gwpsi, int nq,
                            double c, double c0, double V, double* __restrict__ out) {
@@ -696,6 +779,8 @@ __global__ void k_farscale(KParams kp, int M0, int M1, int M2, int Mp0, int Mp1,
   if (idx >= n) return;
   const int d = kp.dim;
   int ii[3] = {(int)(idx % M0), (int)((idx / M0) % M1), (int)(idx / ((int64_t)M0 * M1))};
+  for (int a = 0; a < 3; ++a)
+    if (ord.B[a] > 1) ii[a] = ii[a] / ord.B[a] + ord.A[a] * (ii[a] % ord.B[a]);
   const int Ms[3] = {M0, M1, M2};
   int m[3] = {0, 0, 0};
   bool nyq = false, zero = true;
@@ -765,8 +850,10 @@ void far_build_scale(pdmk_plan* P) {
     PDMK_HIP(hipMemcpy(P->d_fftw, tw.data(), tw.size() * sizeof(double2), hipMemcpyHostToDevice));
   }
   PDMK_HIP(hipMalloc(&P->d_farscale, n * sizeof(double)));
+  FftOrder ord{};
+  for (int a = 0; a < 3; ++a) fft_split(M[a], ord.A[a], ord.B[a]);
   hipLaunchKernelGGL(k_farscale, dim3(nblk(n, 256)), dim3(256), 0, 0, P->kp, M[0], M[1], M[2],
-                     g.fgrid_paper[0], g.fgrid_paper[1], d == 3 ? g.fgrid_paper[2] : 1, d0,
+                     g.fgrid_paper[0], g.fgrid_paper[1], d == 3 ? g.fgrid_paper[2] : 1, ord, d0,
                      d1, d2, dgx, dgw, (int)ps.qx.size(), ps.c, ps.c0, g.volume, P->d_farscale);
   PDMK_HIP(hipDeviceSynchronize());
   for (void* p : tmp) (void)hipFree(p);

@@ -19,8 +19,13 @@ Workloads
                 [0.2995, 0.3005], direction uniform on the sphere); +-1 charges.
 ``wavy3d``      the paper's wavy-sphere distribution (Section 6, source
                 distributions: r = r0 + A sin(k theta) + eta) in the triclinic
-                base cell with edges (1, sqrt2, sqrt3), all angles pi/3,
-                optionally scaled; zero-mean N(0,1) charges.
+                (all angles pi/3) or rectangular base cell with edges
+                (1, sqrt2, sqrt3), optionally scaled; zero-mean N(0,1) charges.
+``wavy2d``      the paper's wavy-ring distribution in the oblique cell
+                a1 = (1, 0), a2 = A (cos pi/3, sin pi/3) of aspect ratio A.
+``paper_system`` the nine cells of the paper's tables (2D A = 1, 10, 100;
+                3D rectangular / triclinic x isotropic / rod / slab) with
+                their wavy distributions.
 ``batch_cells`` random triclinic cells and sizes for batched evaluation.
 """
 from __future__ import annotations
@@ -91,8 +96,15 @@ def triclinic_base(scale=(1, 1, 1)):
     return np.stack([a1 * lens[0], a2 * lens[1], a3 * lens[2]], axis=1)
 
 
-def wavy3d(n=1_000_000, seed=6, scale=(1, 1, 1), r0=0.4, amp=0.05, k=32, sigma=0.01):
-    L = triclinic_base(scale)
+def rectangular_base(scale=(1, 1, 1)):
+    """Edges (1, sqrt2, sqrt3) at right angles, each scaled by scale[i]."""
+    lens = np.array([1.0, math.sqrt(2.0), math.sqrt(3.0)]) * np.asarray(scale, float)
+    return np.diag(lens)
+
+
+def wavy3d(n=1_000_000, seed=6, scale=(1, 1, 1), r0=0.4, amp=0.05, k=32, sigma=0.01,
+           cell="triclinic"):
+    L = triclinic_base(scale) if cell == "triclinic" else rectangular_base(scale)
     rng = np.random.default_rng(seed)
     dirs = rng.standard_normal((n, 3))
     dirs /= np.linalg.norm(dirs, axis=1, keepdims=True)
@@ -101,6 +113,41 @@ def wavy3d(n=1_000_000, seed=6, scale=(1, 1, 1), r0=0.4, amp=0.05, k=32, sigma=0
     u = 0.5 + dirs * r[:, None]
     u -= np.floor(u)
     return L, u @ L.T, _zero_mean_normal(rng, n)
+
+
+def oblique_pi3(aspect=1.0):
+    """a1 = (1, 0), a2 = aspect (cos pi/3, sin pi/3) as columns."""
+    return np.array([[1.0, 0.5 * aspect], [0.0, 0.5 * math.sqrt(3.0) * aspect]])
+
+
+def wavy2d(n=1_000_000, seed=7, aspect=1.0, r0=0.4, amp=0.05, k=32, sigma=0.01):
+    """Ring of fractional radius r0 + amp sin(k theta) + N(0, sigma^2) about
+    the cell centre, theta uniform on [0, 2 pi)."""
+    L = oblique_pi3(aspect)
+    rng = np.random.default_rng(seed)
+    theta = rng.uniform(0.0, 2.0 * math.pi, n)
+    r = r0 + amp * np.sin(k * theta) + sigma * rng.standard_normal(n)
+    u = 0.5 + np.stack([np.cos(theta), np.sin(theta)], axis=1) * r[:, None]
+    u -= np.floor(u)
+    return L, u @ L.T, _zero_mean_normal(rng, n)
+
+
+# the cells of the paper's tables: 2D aspect ratios, 3D base cell x scaling
+PAPER_SYSTEMS = {
+    "2d-A1": ("2d", 1.0), "2d-A10": ("2d", 10.0), "2d-A100": ("2d", 100.0),
+    "rect-iso": ("rect", (1, 1, 1)), "rect-rod": ("rect", (1, 1, 10)),
+    "rect-slab": ("rect", (1, 10, 10)),
+    "tri-iso": ("triclinic", (1, 1, 1)), "tri-rod": ("triclinic", (1, 1, 10)),
+    "tri-slab": ("triclinic", (1, 10, 10)),
+}
+
+
+def paper_system(name, n, seed=8):
+    """(L, src, q) of one of PAPER_SYSTEMS with n wavy sources."""
+    kind, arg = PAPER_SYSTEMS[name]
+    if kind == "2d":
+        return wavy2d(n, seed=seed, aspect=arg)
+    return wavy3d(n, seed=seed, scale=arg, cell=kind)
 
 
 def random_triclinic_cell(rng):

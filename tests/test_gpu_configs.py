@@ -128,3 +128,19 @@ def test_position_gradients_need_a_gradient_plan(pdmk, torch_dev):
     Q2 = Q.clone().requires_grad_(True)
     pdmk.periodic_potential(plan, S.detach(), Q2).sum().backward()
     assert Q2.grad is not None
+
+
+@pytest.mark.parametrize("precision,n_s", [("mixed", 300), ("fp64", 400)])
+def test_c3_bloch_full_size(pdmk, shell, precision, n_s):
+    """Bloch conditions (beta = (0.7, -1.1, 0.4)) on the N = 1e7 shell with
+    the benchmark's plan, against the stored Bloch oracle values."""
+    torch_L, S, Q, _, _ = shell
+    data = np.loadtxt(os.path.join(HERE, "golden", "shell3d_n1e7_seed3_bloch.txt"))
+    idx = data[:, 0].astype(np.int64)
+    ref = data[:, 1] + 1j * data[:, 2]
+    plan = pdmk.Plan(torch_L, eps=1e-6, precision=precision, kappa=6.0, n_s=n_s,
+                     bloch=[0.7, -1.1, 0.4])
+    pot = plan.eval_bloch(S, Q).cpu().numpy()
+    err = float(np.linalg.norm(pot[idx] - ref) / np.linalg.norm(ref))
+    print("C3 Bloch %s E_rel=%.3e" % (precision, err))
+    assert err <= 1e-6
