@@ -92,6 +92,11 @@ def parse():
                     help="skip the eps=1e-3, default-plan and one-stream runs")
     ap.add_argument("--cpu-full", default="10000,100000",
                     help="sizes of the full-N uniform oracle runs ('' to skip)")
+    ap.add_argument("--paper-tables", action="store_true",
+                    help="instead of the benchmark line: the paper's nine cells at N=1e7 and "
+                         "eps 1e-3..1e-12 (FP64, default plans), one JSON line")
+    ap.add_argument("--paper-steps", type=int, default=3)
+    ap.add_argument("--child-paper", action="store_true", help=argparse.SUPPRESS)
     return ap.parse_args()
 
 
@@ -443,6 +448,77 @@ def child_batch(args):
     print(json.dumps(res))
 
 
+# The paper's own per-step times t_PDMK (seconds, one CPU thread, FP64,
+# N = 1e7) for each cell and eps = 1e-3, 1e-6, 1e-9, 1e-12 (tab:2d,
+# tab:rect3d, tab:tri3d).  Context for the GPU times, not a target.
+PAPER_T_PDMK = {
+    "2d-A1": (11.45, 14.47, 21.51, 31.07), "2d-A10": (8.37, 12.05, 18.84, 26.00),
+    "2d-A100": (8.37, 11.76, 19.62, 27.68),
+    "rect-iso": (15.27, 51.77, 130.37, 285.13), "rect-rod": (14.84, 62.36, 152.06, 368.90),
+    "rect-slab": (21.11, 76.54, 172.28, 345.15),
+    "tri-iso": (23.27, 63.77, 183.64, 404.83), "tri-rod": (17.25, 74.22, 163.96, 489.45),
+    "tri-slab": (27.23, 95.68, 197.27, 431.24),
+}
+PAPER_EPS = (1e-3, 1e-6, 1e-9, 1e-12)
+
+
+def child_paper(args):
+    """The paper's nine cells with their wavy distributions at N = 1e7, FP64,
+    default plans, every eps of its tables: per-step time and stage split,
+    E_rel on the stored oracle values when present."""
+    import numpy as np
+    import torch
+    from paper_2606_28608_amd import pdmk, workloads as W
+    n = 10_000_000
+    dev = torch.device("cuda:0")
+    rows = []
+    for name in W.PAPER_SYSTEMS:
+        progress("paper cell %s: generating N=%d" % (name, n))
+        L, src, q = W.paper_system(name, n)
+        S = torch.tensor(src, dtype=torch.float64, device=dev)
+        Q = torch.tensor(q, dtype=torch.float64, device=dev)
+        del src, q
+        gold = None
+        path = os.path.join(ROOT, "tests", "golden", "paper_%s_n1e7_seed8.txt" % name)
+        if os.path.exists(path):
+            data = np.loadtxt(path)
+            gold = (data[:, 0].astype(np.int64), data[:, 1])
+        for j, eps in enumerate(PAPER_EPS):
+            progress("paper cell %s eps=%g" % (name, eps))
+            plan = pdmk.Plan(L, eps=eps)
+            pot = plan.eval(S, Q)   # cold call (tables, workspace)
+            pot = plan.eval(S, Q)
+            torch.cuda.synchronize()
+            per, stats = [], []
+            t0 = time.perf_counter()
+            for _ in range(args.paper_steps):
+                t1 = time.perf_counter()
+                pot = plan.eval(S, Q)
+                per.append(1e3 * (time.perf_counter() - t1))
+                stats.append(plan.stats())
+            dt = (time.perf_counter() - t0) / args.paper_steps
+            err = None
+            if gold is not None:
+                got = pot.cpu().numpy()[gold[0]]
+                err = float(np.linalg.norm(got - gold[1]) / np.linalg.norm(gold[1]))
+            avg = {k: round(sum(x[k] for x in stats) / len(stats), 3)
+                   for k in ("t_build_ms", "t_near_ms", "t_far_ms", "t_total_ms")}
+            g = plan.geometry()
+            t_paper = PAPER_T_PDMK[name][j]
+            rows.append({"cell": name, "eps": eps, "ms_per_step": round(1e3 * dt, 3),
+                         "median_ms": round(statistics.median(per), 3),
+                         "particles_per_s": n / dt, "e_rel_sampled": err,
+                         "parity_ok": err is None or err <= eps, "stages_ms": avg,
+                         "kappa": g.kappa, "n_s": g.n_s, "fourier_grid": list(g.fgrid),
+                         "n_images": stats[-1]["n_images"], "n_levels": stats[-1]["n_levels"],
+                         "paper_t_pdmk_s": t_paper, "paper_over_gpu": t_paper / dt})
+            del plan, pot
+        del S, Q
+        torch.cuda.empty_cache()
+    print(json.dumps({"paper_tables": rows, "n": n, "precision": "fp64",
+                      "plans": "defaults", "steps": args.paper_steps}))
+
+
 def run_child(args, mode, batch=False):
     cmd = [sys.executable, os.path.abspath(__file__), "--child-batch" if batch else "--child",
            "--precision", mode, "--steps", str(args.batch_steps if batch else args.steps),
@@ -550,6 +626,19 @@ def main():
         return
     if args.child_batch:
         child_batch(args)
+        return
+    if args.child_paper:
+        child_paper(args)
+        return
+    if args.paper_tables:
+        cmd = [sys.executable, os.path.abspath(__file__), "--child-paper",
+               "--paper-steps", str(args.paper_steps)]
+        p = subprocess.run(cmd, stdout=subprocess.PIPE, text=True)
+        if p.returncode != 0:
+            print("bench.py: paper-table run failed with status %d" % p.returncode,
+                  file=sys.stderr)
+            sys.exit(p.returncode if p.returncode > 0 else 1)
+        print(p.stdout.strip().splitlines()[-1])
         return
     # Each arithmetic mode runs in a child process of its own, one after the
     # other, so that the two measurements share no device state.  This

@@ -109,8 +109,16 @@ enum {
                                   stream for the far field's grid steps; each stage
                                   then has the device to itself, so its timings in
                                   pdmk_stats are stand-alone durations) */
-  PDMK_BLOCH = 32              /* quasi-periodic conditions with the Bloch vector
+  PDMK_BLOCH = 32,             /* quasi-periodic conditions with the Bloch vector
                                   pdmk_opts.bloch (see pdmk_plan_eval_bloch) */
+  PDMK_VIRTUAL_IMAGES = 64     /* the cube-cell construction of rem:cube for rectangular
+                                  cells whose edges are whole multiples of
+                                  r_c = L_min / kappa (a cube with integer kappa): the
+                                  root cubes tile the cell, a boundary box's colleagues
+                                  across a face are the boxes on the other side shifted
+                                  by L n (n in {-1,0,1}^d), and no image point is placed,
+                                  sorted or stored.  Other cells: PDMK_ERR_UNSUPPORTED.
+                                  Not with PDMK_BLOCH. */
 };
 
 typedef struct {

@@ -440,8 +440,11 @@ static int validate_opts(const pdmk_opts* o) {
   if (o->porder > 40 || o->npw > 64 || o->nufft_w > 16 || o->sigma > 4.0)
     return fail(PDMK_ERR_INVALID_ARG, "porder <= 40, npw <= 64, nufft_w <= 16, sigma <= 4");
   if (o->flags & ~(unsigned)(PDMK_WANT_GRAD | PDMK_ALLOW_NONNEUTRAL | PDMK_DETERMINISTIC |
-                             PDMK_VECTOR_PLANE_WAVES | PDMK_ONE_STREAM | PDMK_BLOCH))
+                             PDMK_VECTOR_PLANE_WAVES | PDMK_ONE_STREAM | PDMK_BLOCH |
+                             PDMK_VIRTUAL_IMAGES))
     return fail(PDMK_ERR_INVALID_ARG, "unknown flag");
+  if ((o->flags & PDMK_BLOCH) && (o->flags & PDMK_VIRTUAL_IMAGES))
+    return fail(PDMK_ERR_UNSUPPORTED, "PDMK_BLOCH does not support PDMK_VIRTUAL_IMAGES");
   if (o->flags & PDMK_BLOCH) {
     for (int a = 0; a < o->dim; ++a)
       if (!std::isfinite(o->bloch[a])) return fail(PDMK_ERR_INVALID_ARG, "non-finite Bloch vector");
@@ -451,6 +454,13 @@ static int validate_opts(const pdmk_opts* o) {
   }
   if (o->fp32_stages & ~15u) return fail(PDMK_ERR_INVALID_ARG, "unknown fp32_stages bit");
   return PDMK_OK;
+}
+
+// Status of a make_geometry message.
+static int geometry_status(const std::string& msg) {
+  if (msg.rfind("unsupported:", 0) == 0) return PDMK_ERR_UNSUPPORTED;
+  return msg.find("kappa") != std::string::npos ? PDMK_ERR_INVALID_ARG
+                                                : PDMK_ERR_SINGULAR_LATTICE;
 }
 
 static double bloch_norm(const pdmk_opts* o) {
@@ -498,12 +508,10 @@ int pdmk_plan_create(const pdmk_opts* opts, const double* L, pdmk_plan** out) {
     P->P = &pswf_for_eps(opts->eps);
     P->T = &tables_for_eps(opts->eps);
     std::string msg = make_geometry(d, L, P->mp.kappa, P->P->c, P->mp.sigma, P->g,
-                                    bloch_norm(opts));
+                                    bloch_norm(opts), (opts->flags & PDMK_VIRTUAL_IMAGES) != 0);
     if (!msg.empty()) {
       delete P;
-      return fail(msg.find("kappa") != std::string::npos ? PDMK_ERR_INVALID_ARG
-                                                          : PDMK_ERR_SINGULAR_LATTICE,
-                  msg);
+      return fail(geometry_status(msg), msg);
     }
     PDMK_HIP(hipGetDevice(&P->device));
     KParams& kp = P->kp;
@@ -514,6 +522,7 @@ int pdmk_plan_create(const pdmk_opts* opts, const double* L, pdmk_plan** out) {
     kp.rc = P->g.rc;
     kp.irc = 1.0 / P->g.rc;
     kp.precision = opts->precision;
+    kp.vimg = P->g.virtual_images ? 1 : 0;
     int64_t nroot = 1;
     for (int a = 0; a < 3; ++a) {
       kp.next[a] = a < d ? P->g.next[a] : 1;
@@ -604,11 +613,8 @@ int pdmk_geometry_get(const pdmk_opts* opts, const double* L, pdmk_geometry* out
   tmp.P = &pswf_for_eps(opts->eps);
   tmp.T = &tables_for_eps(opts->eps);
   std::string msg = make_geometry(opts->dim, L, tmp.mp.kappa, tmp.P->c, tmp.mp.sigma, tmp.g,
-                                  bloch_norm(opts));
-  if (!msg.empty())
-    return fail(msg.find("kappa") != std::string::npos ? PDMK_ERR_INVALID_ARG
-                                                        : PDMK_ERR_SINGULAR_LATTICE,
-                msg);
+                                  bloch_norm(opts), (opts->flags & PDMK_VIRTUAL_IMAGES) != 0);
+  if (!msg.empty()) return fail(geometry_status(msg), msg);
   double ob[3];
   if ((opts->flags & PDMK_BLOCH) && !oriented_bloch(tmp.g, opts, ob))
     return fail(PDMK_ERR_INVALID_ARG,

@@ -109,7 +109,19 @@ struct KParams {
   int precision;
   int bloch;        // quasi-periodic conditions (Section 4.1)
   double beta[3];   // Bloch vector in the oriented frame
+  int vimg;         // images as virtual neighbours (rem:cube)
 };
+
+// Lattice shift of a colleague or list entry under virtual images: code
+// 1 + sum_a (n_a + 1) 3^a for n in {-1, 0, 1}^d, 0 for no shift.
+__host__ __device__ inline int shift_code(const int* n, int d) {
+  int c = 0, m = 1;
+  for (int a = 0; a < d; ++a) {
+    c += (n[a] + 1) * m;
+    m *= 3;
+  }
+  return c == (d == 3 ? 13 : 4) ? 0 : c + 1;
+}
 
 // One tree level (device arrays; counts on host).
 struct Level {
@@ -123,6 +135,7 @@ struct Level {
   int* parent = nullptr;
   int* child0 = nullptr;     // first of 2^d children at the next level, -1 = leaf
   int* coll = nullptr;       // 3^d colleague indices, -1 = none
+  unsigned char* cshift = nullptr;  // virtual images: shift_code of each colleague
   int* nlid = nullptr;       // index among non-leaf boxes of this level, -1 = leaf
   int nnl = 0;               // non-leaf count
   int* nl_box = nullptr;     // non-leaf index -> box index

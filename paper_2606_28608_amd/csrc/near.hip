@@ -160,6 +160,19 @@ struct SourceSlot {
       v.x = sx[sidx] - cT[0];
       v.y = sx[nimg + sidx] - cT[1];
       v.z = D == 3 ? sx[2 * nimg + sidx] - cT[2] : 0.0;
+      if (c.en.w) {
+        // a virtual image (rem:cube): the source shifted by L n
+        int t = c.en.w - 1;
+        double sh[3] = {0.0, 0.0, 0.0};
+        for (int a = 0; a < D; ++a) {
+          const double n = (double)(t % 3 - 1);
+          t /= 3;
+          for (int b = 0; b <= a; ++b) sh[b] = fma(kp.L[b + D * a], n, sh[b]);
+        }
+        v.x += sh[0];
+        v.y += sh[1];
+        v.z += sh[2];
+      }
       // h = r_c 2^-z and 1/h = (1/r_c) 2^z (power-of-two scalings: exact)
       const double hh = ldexp(kp.rc, -c.en.z);
       const double ih = ldexp(kp.irc, c.en.z);
@@ -674,14 +687,14 @@ __global__ void k_axis(int nitems, int n0, int n1, int n2, int ax, int mout,
 //   I_B(j) = c_l(|j|^2) sum_{C} omega^{j.(c_B - c_C)/h} S_C(j),
 // over the non-leaf colleagues C (including B), omega = exp(2 pi i / 3).
 template <int D>
-__global__ void k_translate(Level L, int J, const double2* __restrict__ S,
+__global__ void k_translate(Level L, int J, int k0, int nk, const double2* __restrict__ S,
                             double2* __restrict__ I, const double* __restrict__ dtab,
                             double levfac, unsigned long long* __restrict__ npairs) {
   const int n1 = 2 * J + 1;
   const int msz = D == 3 ? (J + 1) * n1 * n1 : (J + 1) * n1;
   const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (gid >= (int64_t)msz * L.nnl) return;
-  const int k = (int)(gid / msz), m = (int)(gid % msz);
+  if (gid >= (int64_t)msz * nk) return;
+  const int k = k0 + (int)(gid / msz), m = (int)(gid % msz);
   int j[3] = {0, 0, 0};
   if (D == 3) {
     j[2] = m % n1 - J;
@@ -1274,9 +1287,15 @@ static void near_impl(pdmk_plan* P, Eval& E, bool want_grad) {
     // half-ball order; vector-ALU path: outgoing expansions on the full grid
     C* bS = E.alloc<C>((size_t)maxnl * (mfma ? P->nball : s3));
     C* bIw = mfma ? E.alloc<C>((size_t)maxnl * P->nball) : nullptr;
-    double2* bA = fused ? nullptr : E.alloc<double2>((size_t)maxnl * s1);
-    double2* bB = (D == 3 && !fused) ? E.alloc<double2>((size_t)maxnl * s2) : nullptr;
-    double2* bI = fused ? nullptr : E.alloc<double2>((size_t)maxnl * s3);
+    // axis-by-axis path: the intermediate tensors of at most `chunk` boxes at a
+    // time (about 2 GB), so that their size does not grow with the level (at
+    // p = 40 they take 3.9 MB per box); only the outgoing plane waves, which
+    // the translation reads across colleagues, are kept for the whole level
+    const int64_t per_box = (s1 + s2 + s3) * (int64_t)sizeof(double2);
+    const int chunk = (int)std::max<int64_t>(1, std::min<int64_t>(maxnl, (2ll << 30) / per_box));
+    double2* bA = fused ? nullptr : E.alloc<double2>((size_t)chunk * s1);
+    double2* bB = (D == 3 && !fused) ? E.alloc<double2>((size_t)chunk * s2) : nullptr;
+    double2* bI = fused ? nullptr : E.alloc<double2>((size_t)chunk * s3);
     unsigned long long* npairs = cnt;
     E.pw_split = mfma;
     const C* Ftab = reinterpret_cast<const C*>(sizeof(Real) == 4 ? (const void*)P->d_Ff
@@ -1318,34 +1337,50 @@ static void near_impl(pdmk_plan* P, Eval& E, bool want_grad) {
       if (tm) PDMK_HIP(hipEventRecord(pe[1], s));
       if (sizeof(Real) != 8) throw Error{PDMK_ERR_UNSUPPORTED, "FP32 proxies need the fused path"};
       double2* bSd = reinterpret_cast<double2*>(bS);
+      const double* pq = static_cast<const double*>(L.proxy_q);
+      double* pphi = static_cast<double*>(L.proxy_phi);
       // outgoing: proxy charges -> plane waves (Hermitian half on axis 0)
-      hipLaunchKernelGGL((k_axis<false, 0>), dim3(nblk(nn * s1, 256)), dim3(256), 0, s, nn, p,
-                         p, zz, 0, J + 1, (const void*)L.proxy_q, (void*)bA, P->d_F, J, p, 0, 0);
-      if (D == 3) {
-        hipLaunchKernelGGL((k_axis<true, 0>), dim3(nblk(nn * s2, 256)), dim3(256), 0, s, nn,
-                           J + 1, p, p, 1, n1, (const void*)bA, (void*)bB, P->d_F, 0, p, 0, 0);
-        hipLaunchKernelGGL((k_axis<true, 0>), dim3(nblk(nn * s3, 256)), dim3(256), 0, s, nn,
-                           J + 1, n1, p, 2, n1, (const void*)bB, (void*)bSd, P->d_F, 0, p, 0, 0);
-      } else {
-        hipLaunchKernelGGL((k_axis<true, 0>), dim3(nblk(nn * s3, 256)), dim3(256), 0, s, nn,
-                           J + 1, p, 1, 1, n1, (const void*)bA, (void*)bSd, P->d_F, 0, p, 0, 0);
+      for (int k0 = 0; k0 < nn; k0 += chunk) {
+        const int nc = std::min(chunk, nn - k0);
+        double2* out = bSd + (int64_t)k0 * s3;
+        hipLaunchKernelGGL((k_axis<false, 0>), dim3(nblk((int64_t)nc * s1, 256)), dim3(256), 0,
+                           s, nc, p, p, zz, 0, J + 1, (const void*)(pq + (int64_t)k0 * pD),
+                           (void*)bA, P->d_F, J, p, 0, 0);
+        if (D == 3) {
+          hipLaunchKernelGGL((k_axis<true, 0>), dim3(nblk((int64_t)nc * s2, 256)), dim3(256), 0,
+                             s, nc, J + 1, p, p, 1, n1, (const void*)bA, (void*)bB, P->d_F, 0, p,
+                             0, 0);
+          hipLaunchKernelGGL((k_axis<true, 0>), dim3(nblk((int64_t)nc * s3, 256)), dim3(256), 0,
+                             s, nc, J + 1, n1, p, 2, n1, (const void*)bB, (void*)out, P->d_F, 0,
+                             p, 0, 0);
+        } else {
+          hipLaunchKernelGGL((k_axis<true, 0>), dim3(nblk((int64_t)nc * s3, 256)), dim3(256), 0,
+                             s, nc, J + 1, p, 1, 1, n1, (const void*)bA, (void*)out, P->d_F, 0,
+                             p, 0, 0);
+        }
       }
-      // translation between colleagues with the difference-kernel multiplier
-      hipLaunchKernelGGL(k_translate<D>, dim3(nblk(nn * s3, 256)), dim3(256), 0, s, L, J, bSd,
-                         bI, P->d_dtab, levfac, npairs);
-      // incoming: plane waves -> proxy potentials
-      if (D == 3) {
-        hipLaunchKernelGGL((k_axis<true, 0>), dim3(nblk(nn * s2, 256)), dim3(256), 0, s, nn,
-                           J + 1, n1, n1, 2, p, (const void*)bI, (void*)bB, P->d_F, 0, p, 1, 1);
-        hipLaunchKernelGGL((k_axis<true, 0>), dim3(nblk(nn * s1, 256)), dim3(256), 0, s, nn,
-                           J + 1, n1, p, 1, p, (const void*)bB, (void*)bA, P->d_F, 0, p, 1, 1);
-      } else {
-        hipLaunchKernelGGL((k_axis<true, 0>), dim3(nblk(nn * s1, 256)), dim3(256), 0, s, nn,
-                           J + 1, n1, 1, 1, p, (const void*)bI, (void*)bA, P->d_F, 0, p, 1, 1);
+      for (int k0 = 0; k0 < nn; k0 += chunk) {
+        const int nc = std::min(chunk, nn - k0);
+        // translation between colleagues with the difference-kernel multiplier
+        hipLaunchKernelGGL(k_translate<D>, dim3(nblk((int64_t)nc * s3, 256)), dim3(256), 0, s,
+                           L, J, k0, nc, bSd, bI, P->d_dtab, levfac, npairs);
+        // incoming: plane waves -> proxy potentials
+        if (D == 3) {
+          hipLaunchKernelGGL((k_axis<true, 0>), dim3(nblk((int64_t)nc * s2, 256)), dim3(256), 0,
+                             s, nc, J + 1, n1, n1, 2, p, (const void*)bI, (void*)bB, P->d_F, 0,
+                             p, 1, 1);
+          hipLaunchKernelGGL((k_axis<true, 0>), dim3(nblk((int64_t)nc * s1, 256)), dim3(256), 0,
+                             s, nc, J + 1, n1, p, 1, p, (const void*)bB, (void*)bA, P->d_F, 0, p,
+                             1, 1);
+        } else {
+          hipLaunchKernelGGL((k_axis<true, 0>), dim3(nblk((int64_t)nc * s1, 256)), dim3(256), 0,
+                             s, nc, J + 1, n1, 1, 1, p, (const void*)bI, (void*)bA, P->d_F, 0, p,
+                             1, 1);
+        }
+        hipLaunchKernelGGL((k_axis<true, 1>), dim3(nblk((int64_t)nc * pD, 256)), dim3(256), 0,
+                           s, nc, J + 1, p, zz, 0, p, (const void*)bA,
+                           (void*)(pphi + (int64_t)k0 * pD), P->d_F, J, p, 1, 1);
       }
-      hipLaunchKernelGGL((k_axis<true, 1>), dim3(nblk((int64_t)nn * pD, 256)), dim3(256), 0, s,
-                         nn, J + 1, p, zz, 0, p, (const void*)bA, (void*)L.proxy_phi, P->d_F, J,
-                         p, 1, 1);
       if (tm) PDMK_HIP(hipEventRecord(pe[2], s));
     }
     // downward pass: parent proxy potential -> non-leaf child proxy potential

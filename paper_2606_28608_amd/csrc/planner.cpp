@@ -313,7 +313,10 @@ MethodParams default_params(int dim, double eps) {
     m.kappa = 7.0;
     m.n_s = l <= 3.5 ? 30 : (l <= 9.5 ? 40 : 60);
   }
-  m.porder = (int)std::ceil(1.2 * P.c + 1.5);
+  // proxy points per axis: 13 / 22 / 31 / 40 at eps = 1e-3 / 1e-6 / 1e-9 /
+  // 1e-12; at 1e-12 one point fewer leaves the near field at 2e-12 on a
+  // clustered cube (kappa = 3), one more point 3e-13
+  m.porder = (int)std::ceil(1.28 * P.c + 0.8);
   m.npw = (int)std::ceil(3.0 * P.c / kPi);
   // Spreading window: without upsampling (the paper's grid) a width of
   // log10(1/eps) + 2 cells suffices down to eps ~ 1e-7; below that the
@@ -361,7 +364,7 @@ static void inv3(int d, const double* A, double* Ai) {
 }
 
 std::string make_geometry(int d, const double* Lin, double kappa, double c, double sigma,
-                          Geometry& g, double beta_norm) {
+                          Geometry& g, double beta_norm, bool virtual_images) {
   g = Geometry();
   g.dim = d;
   // sort lattice vectors by decreasing length (stable), Section 3.2
@@ -394,6 +397,17 @@ std::string make_geometry(int d, const double* Lin, double kappa, double c, doub
     for (int i = 0; i < d; ++i) Qm[i + d * j] = v[i] / nr;
   }
   for (int k = 0; k < d * d; ++k) { g.L[k] = R[k]; g.Q[k] = Qm[k]; }
+  if (virtual_images) {
+    // a rectangular cell: R is diagonal up to rounding, which is removed
+    double Lmx = 0;
+    for (int i = 0; i < d; ++i) Lmx = std::max(Lmx, R[i + d * i]);
+    for (int j = 0; j < d; ++j)
+      for (int i = 0; i < j; ++i) {
+        if (std::fabs(R[i + d * j]) > 1e-12 * Lmx)
+          return "unsupported: virtual images need a rectangular cell";
+        g.L[i + d * j] = 0.0;
+      }
+  }
   inv3(d, g.L, g.Li);
   g.volume = 1.0;
   g.Lmin = 1e300;
@@ -406,8 +420,27 @@ std::string make_geometry(int d, const double* Lin, double kappa, double c, doub
   if (!(g.Lmin > 1e-12 * Lmax)) return "lattice too ill-conditioned";
   if (!(kappa >= 1.0)) return "kappa must be >= 1";
   g.rc = g.Lmin / kappa;
+  if (virtual_images) {
+    // rem:cube: root cubes of side r_c tile the cell exactly; a boundary
+    // box's colleagues across a face are boxes of the other side, shifted by
+    // L n, so no image is placed or sorted
+    g.virtual_images = true;
+    for (int i = 0; i < d; ++i) {
+      const double e = g.L[i + d * i];
+      const double m = std::nearbyint(e / g.rc);
+      if (m < 1.0 || std::fabs(m * g.rc - e) > 1e-13 * e)
+        return "unsupported: virtual images need cell edges that are whole multiples of "
+               "r_c = L_min / kappa";
+      g.xlo[i] = 0.0;
+      g.width[i] = e;
+      g.nroot[i] = (int)m;
+      g.next[i] = (int)m;
+      g.origin[i] = 0.0;
+    }
+    for (int k = 0; k < d; ++k) g.shifts.push_back(0);
+  }
   // bounding box (eq:x1range .. eq:w1) and root cubes (eq:mi)
-  for (int i = 0; i < d; ++i) {
+  for (int i = 0; i < d && !virtual_images; ++i) {
     double lo = 0, w = g.L[i + d * i];
     for (int j = i + 1; j < d; ++j) {
       lo += std::min(0.0, g.L[i + d * j]);
@@ -438,7 +471,7 @@ std::string make_geometry(int d, const double* Lin, double kappa, double c, doub
     }
     n[i] = 0;
   };
-  rec(d - 1);
+  if (!virtual_images) rec(d - 1);
   // Fourier grid (eq:Mi with eq:anorms); with a Bloch vector the active modes
   // |k_m + beta| <= c / r_c need M_i = 2 ceil((c / r_c + |beta|) |a_i| / 2 pi)
   // (Section 4.1, Fourier grid)

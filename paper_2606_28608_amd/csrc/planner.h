@@ -96,12 +96,19 @@ struct Geometry {
   std::vector<int> shifts;  // dim ints per surviving lattice shift
   int fgrid_paper[3] = {1, 1, 1};
   int fgrid[3] = {1, 1, 1};
+  // images as virtual neighbours (rem:cube): the root grid tiles the cell and
+  // colleagues wrap around it; no halo, no image points
+  bool virtual_images = false;
 };
 // Returns empty string on success, else a message.
 // beta_norm: |beta| of a Bloch vector (0: periodic), which enlarges the
 // Fourier grid (Section 4.1).
+// virtual_images: the cube-cell construction of rem:cube, for rectangular
+// cells whose edges are whole multiples of r_c (a message starting with
+// "unsupported:" otherwise).
 std::string make_geometry(int dim, const double* Lin, double kappa, double c,
-                          double sigma, Geometry& g, double beta_norm = 0.0);
+                          double sigma, Geometry& g, double beta_norm = 0.0,
+                          bool virtual_images = false);
 
 // Smallest even integer >= n whose prime factors are 2, 3, 5.
 int next_fft_size(int n);

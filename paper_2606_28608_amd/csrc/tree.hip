@@ -176,10 +176,16 @@ __global__ __launch_bounds__(256) void k_img_count(KParams kp, int64_t n,
     double x[3] = {0, 0, 0};
     for (int a = 0; a < d; ++a) x[a] = xs[a * n + i];
     bool orig = false;
-    for_each_image(kp, x, [&](const double* y) {
-      ++c;
-      orig = orig || (y[0] == x[0] && y[1] == x[1] && y[2] == x[2]);
-    });
+    if (kp.vimg) {
+      // virtual images: the original alone
+      c = 1;
+      orig = true;
+    } else {
+      for_each_image(kp, x, [&](const double* y) {
+        ++c;
+        orig = orig || (y[0] == x[0] && y[1] == x[1] && y[2] == x[2]);
+      });
+    }
     cnt[i] = c;
     if (!orig) atomicAdd(missing, 1);   // the unshifted copy was not emitted
   }
@@ -209,6 +215,15 @@ __global__ void k_img_emit(KParams kp, int64_t n, const double* __restrict__ xs,
   const double qq = q[i];
   const double qm = qim ? qim[i] : 0.0;
   int64_t o = off[i];
+  if (kp.vimg) {
+    // virtual images: the original alone, whatever rounding did to its
+    // distance from the cell's far faces
+    for (int a = 0; a < d; ++a) xi[a * nimg + o] = x[a];
+    qi[o] = qq;
+    isrc[o] = (int)i;
+    if (iall) iall[o] = (int)i;
+    return;
+  }
   for_each_image(kp, x, [&](const double* y) {
     for (int a = 0; a < d; ++a) xi[a * nimg + o] = y[a];
     if (qi_im) {
@@ -523,15 +538,22 @@ __global__ void k_level0(KParams kp, Level L, const uint64_t* __restrict__ skey,
   int ncoll = d == 3 ? 27 : 9;
   for (int sl = 0; sl < ncoll; ++sl) {
     int dl[3] = {sl % 3 - 1, (sl / 3) % 3 - 1, sl / 9 - 1};
-    int idx = 0, m = 1;
+    int idx = 0, m = 1, sh[3] = {0, 0, 0};
     bool ok = true;
     for (int a = 0; a < d; ++a) {
       int c = r[a] + dl[a];
+      if (kp.vimg) {
+        // across a face of the cell: the box on the other side, shifted by
+        // L n with n_a = -1 (c < 0) or +1 (c >= m_a)
+        if (c < 0) { c += kp.next[a]; sh[a] = -1; }
+        else if (c >= kp.next[a]) { c -= kp.next[a]; sh[a] = 1; }
+      }
       ok = ok && c >= 0 && c < kp.next[a];
       idx += c * m;
       m *= kp.next[a];
     }
     L.coll[b * ncoll + sl] = ok ? idx : -1;
+    if (L.cshift) L.cshift[b * ncoll + sl] = (unsigned char)shift_code(sh, d);
   }
 }
 
@@ -605,11 +627,14 @@ __global__ void k_colleagues(Level P, Level C, int d) {
     if (c0 >= 0) cc = c0 + oct;
   }
   C.coll[c * ncoll + sl] = cc;
+  // a child of a shifted colleague carries the same shift
+  if (C.cshift) C.cshift[c * ncoll + sl] = P.cshift[b * ncoll + ps];
 }
 
-static void alloc_level(Eval& E, Level& L, int n, int d) {
+static void alloc_level(Eval& E, Level& L, int n, int d, bool vimg) {
   L.n = n;
   int ncoll = d == 3 ? 27 : 9;
+  L.cshift = vimg ? E.alloc<unsigned char>((size_t)n * ncoll) : nullptr;
   L.key = E.alloc<uint64_t>(n);
   L.coord = E.alloc<int>((size_t)n * d);
   L.sbeg = E.alloc<int>(n);
@@ -628,7 +653,7 @@ void stage_tree(pdmk_plan* P, Eval& E) {
   E.lev.clear();
   int n0 = kp.next[0] * kp.next[1] * (d == 3 ? kp.next[2] : 1);
   Level L0;
-  alloc_level(E, L0, n0, d);
+  alloc_level(E, L0, n0, d, kp.vimg != 0);
   hipLaunchKernelGGL(k_level0, dim3(nblk(n0, 128)), dim3(128), 0, E.s, kp, L0, E.skey,
                      (int)E.n_img, E.tkey, (int)E.n_trg);
   E.lev.push_back(L0);
@@ -647,7 +672,7 @@ void stage_tree(pdmk_plan* P, Eval& E) {
                        d);
     if (nsplit == 0) break;
     Level C;
-    alloc_level(E, C, nsplit << d, d);
+    alloc_level(E, C, nsplit << d, d, kp.vimg != 0);
     Level Pcopy = E.lev[l];
     hipLaunchKernelGGL(k_make_children, dim3(nblk(C.n, 128)), dim3(128), 0, E.s, kp, Pcopy, C, l,
                        E.skey, E.tkey);
@@ -698,12 +723,13 @@ __global__ void k_leaf_lists(int d, int nleaf, const Level* __restrict__ lev,
   int k = 0;
   long long np = 0;
   int o = beg ? beg[i] : 0;
+  // .w of an entry: the shift_code of a virtual image's colleague (0: none)
   for (int sl = 0; sl < ncoll; ++sl) {
     int c = T.coll[b * ncoll + sl];
     if (c < 0) continue;
     int sb = T.sbeg[c], se = T.send[c];
     if (se <= sb) continue;
-    if (list) list[o + k] = make_int4(sb, se, lvl, 0);
+    if (list) list[o + k] = make_int4(sb, se, lvl, T.cshift ? T.cshift[b * ncoll + sl] : 0);
     ++k;
     np += se - sb;
   }
@@ -715,7 +741,7 @@ __global__ void k_leaf_lists(int d, int nleaf, const Level* __restrict__ lev,
       if (D < 0 || A.child0[D] >= 0) continue;
       int sb = A.sbeg[D], se = A.send[D];
       if (se <= sb) continue;
-      if (list) list[o + k] = make_int4(sb, se, l, 0);
+      if (list) list[o + k] = make_int4(sb, se, l, A.cshift ? A.cshift[a * ncoll + sl] : 0);
       ++k;
       np += se - sb;
     }

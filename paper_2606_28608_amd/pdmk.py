@@ -27,6 +27,7 @@ PDMK_DETERMINISTIC = 4
 PDMK_VECTOR_PLANE_WAVES = 8
 PDMK_ONE_STREAM = 16
 PDMK_BLOCH = 32
+PDMK_VIRTUAL_IMAGES = 64
 PDMK_FP32_RESIDUAL = 1
 PDMK_FP32_PROXY = 2
 PDMK_FP32_WINDOW = 4
@@ -164,10 +165,11 @@ def _check(code):
 
 def default_opts(dim, eps, precision="fp64", grad=False, allow_nonneutral=False,
                  deterministic=False, vector_plane_waves=False, one_stream=False, bloch=None,
-                 **over):
+                 virtual_images=False, **over):
     """pdmk_opts for (dim, eps) with the defaults of pdmk_default_opts; keyword
     arguments set flags (grad, allow_nonneutral, deterministic,
-    vector_plane_waves, one_stream, bloch = Bloch vector) or override fields (kappa, n_s, porder, npw, nufft_w,
+    vector_plane_waves, one_stream, bloch = Bloch vector, virtual_images) or
+    override fields (kappa, n_s, porder, npw, nufft_w,
     sigma, fp32_stages)."""
     o = Opts()
     _check(lib().pdmk_default_opts(int(dim), float(eps), ctypes.byref(o)))
@@ -178,7 +180,8 @@ def default_opts(dim, eps, precision="fp64", grad=False, allow_nonneutral=False,
                | (PDMK_DETERMINISTIC if deterministic else 0)
                | (PDMK_VECTOR_PLANE_WAVES if vector_plane_waves else 0)
                | (PDMK_ONE_STREAM if one_stream else 0)
-               | (PDMK_BLOCH if bloch is not None else 0))
+               | (PDMK_BLOCH if bloch is not None else 0)
+               | (PDMK_VIRTUAL_IMAGES if virtual_images else 0))
     if bloch is not None:
         b = [float(v) for v in bloch]
         if len(b) != dim:

@@ -270,3 +270,32 @@ def test_bloch_grid_and_reciprocal_lattice():
     with pytest.raises(pdmk.PdmkError) as e:
         pdmk.geometry(L, eps=1e-6, bloch=beta, deterministic=True)
     assert e.value.code == -9
+
+
+def test_virtual_image_geometry():
+    """rem:cube: a cube with integer kappa tiles into kappa^3 root cubes with
+    no halo and no shifts; commensurate rectangular cells tile likewise; other
+    cells, and Bloch conditions, are rejected."""
+    g = pdmk.geometry(np.eye(3) * 2.0, eps=1e-6, kappa=4.0, virtual_images=True)
+    assert list(g.nroot) == [4, 4, 4]
+    assert g.n_shifts == 1 and abs(g.rc - 0.5) < 1e-15
+    assert list(g.origin) == [0.0, 0.0, 0.0]
+    g = pdmk.geometry(np.diag([1.0, 2.0, 3.0]), eps=1e-6, kappa=3.0, virtual_images=True)
+    assert sorted(g.nroot) == [3, 6, 9]
+    g2 = pdmk.geometry(np.diag([1.0, 2.0]), eps=1e-6, kappa=2.0, virtual_images=True)
+    assert sorted(list(g2.nroot)[:2]) == [2, 4]
+    # a rotated cube is a cube
+    th = 0.3
+    R = np.array([[math.cos(th), -math.sin(th), 0], [math.sin(th), math.cos(th), 0], [0, 0, 1]])
+    g = pdmk.geometry(R @ np.eye(3), eps=1e-6, kappa=3.0, virtual_images=True)
+    assert list(g.nroot) == [3, 3, 3]
+    for L in (workloads.rectangular_base(), workloads.TRICLINIC3D_L):
+        with pytest.raises(pdmk.PdmkError) as e:
+            pdmk.geometry(L, eps=1e-6, kappa=3.0, virtual_images=True)
+        assert e.value.code == -9
+    with pytest.raises(pdmk.PdmkError) as e:
+        pdmk.geometry(np.eye(3), eps=1e-6, kappa=3.5, virtual_images=True)
+    assert e.value.code == -9
+    with pytest.raises(pdmk.PdmkError) as e:
+        pdmk.geometry(np.eye(3), eps=1e-6, virtual_images=True, bloch=[0.1, 0.2, 0.3])
+    assert e.value.code == -9
