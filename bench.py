@@ -96,6 +96,11 @@ def parse():
                     help="instead of the benchmark line: the paper's nine cells at N=1e7 and "
                          "eps 1e-3..1e-12 (FP64, default plans), one JSON line")
     ap.add_argument("--paper-steps", type=int, default=3)
+    ap.add_argument("--paper-cells", default="",
+                    help="comma-separated subset of the paper's cells (default: all nine)")
+    ap.add_argument("--paper-eps", default="",
+                    help="comma-separated subset of eps (default: 1e-3,1e-6,1e-9,1e-12)")
+    ap.add_argument("--paper-n", type=float, default=1e7)
     ap.add_argument("--child-paper", action="store_true", help=argparse.SUPPRESS)
     return ap.parse_args()
 
@@ -469,10 +474,12 @@ def child_paper(args):
     import numpy as np
     import torch
     from paper_2606_28608_amd import pdmk, workloads as W
-    n = 10_000_000
+    n = int(args.paper_n)
     dev = torch.device("cuda:0")
     rows = []
-    for name in W.PAPER_SYSTEMS:
+    cells = [c for c in args.paper_cells.split(",") if c] or list(W.PAPER_SYSTEMS)
+    epss = [float(e) for e in args.paper_eps.split(",") if e] or list(PAPER_EPS)
+    for name in cells:
         progress("paper cell %s: generating N=%d" % (name, n))
         L, src, q = W.paper_system(name, n)
         S = torch.tensor(src, dtype=torch.float64, device=dev)
@@ -480,10 +487,11 @@ def child_paper(args):
         del src, q
         gold = None
         path = os.path.join(ROOT, "tests", "golden", "paper_%s_n1e7_seed8.txt" % name)
-        if os.path.exists(path):
+        if n == 10_000_000 and os.path.exists(path):
             data = np.loadtxt(path)
             gold = (data[:, 0].astype(np.int64), data[:, 1])
-        for j, eps in enumerate(PAPER_EPS):
+        for eps in epss:
+            j = PAPER_EPS.index(eps) if eps in PAPER_EPS else None
             progress("paper cell %s eps=%g" % (name, eps))
             plan = pdmk.Plan(L, eps=eps)
             pot = plan.eval(S, Q)   # cold call (tables, workspace)
@@ -504,14 +512,15 @@ def child_paper(args):
             avg = {k: round(sum(x[k] for x in stats) / len(stats), 3)
                    for k in ("t_build_ms", "t_near_ms", "t_far_ms", "t_total_ms")}
             g = plan.geometry()
-            t_paper = PAPER_T_PDMK[name][j]
+            t_paper = PAPER_T_PDMK[name][j] if j is not None and n == 10_000_000 else None
             rows.append({"cell": name, "eps": eps, "ms_per_step": round(1e3 * dt, 3),
                          "median_ms": round(statistics.median(per), 3),
                          "particles_per_s": n / dt, "e_rel_sampled": err,
                          "parity_ok": err is None or err <= eps, "stages_ms": avg,
                          "kappa": g.kappa, "n_s": g.n_s, "fourier_grid": list(g.fgrid),
                          "n_images": stats[-1]["n_images"], "n_levels": stats[-1]["n_levels"],
-                         "paper_t_pdmk_s": t_paper, "paper_over_gpu": t_paper / dt})
+                         "paper_t_pdmk_s": t_paper,
+                         "paper_over_gpu": t_paper / dt if t_paper else None})
             del plan, pot
         del S, Q
         torch.cuda.empty_cache()
@@ -632,7 +641,8 @@ def main():
         return
     if args.paper_tables:
         cmd = [sys.executable, os.path.abspath(__file__), "--child-paper",
-               "--paper-steps", str(args.paper_steps)]
+               "--paper-steps", str(args.paper_steps), "--paper-cells", args.paper_cells,
+               "--paper-eps", args.paper_eps, "--paper-n", str(args.paper_n)]
         p = subprocess.run(cmd, stdout=subprocess.PIPE, text=True)
         if p.returncode != 0:
             print("bench.py: paper-table run failed with status %d" % p.returncode,

@@ -171,6 +171,18 @@ void plan_upload_tables(pdmk_plan* P) {
       F[(j + J) * p + i] = make_double2(std::cos(a), std::sin(a));
     }
   P->d_F = upload(F);
+  {
+    std::vector<double2> Fc(F.size()), Fw(F.size());
+    for (int j = -J; j <= J; ++j)
+      for (int i = 0; i < p; ++i) {
+        const double2 f = F[(j + J) * p + i];
+        Fc[(j + J) * p + i] = make_double2(f.x, -f.y);
+        const double w = j > 0 ? 2.0 : 1.0;
+        Fw[(j + J) * p + i] = make_double2(w * f.x, -w * f.y);
+      }
+    P->d_Fc = upload(Fc);
+    P->d_Fw = upload(Fw);
+  }
   std::vector<float2> Ff(F.size());
   for (size_t i = 0; i < F.size(); ++i) Ff[i] = make_float2((float)F[i].x, (float)F[i].y);
   P->d_Ff = upload(Ff);
@@ -192,9 +204,11 @@ static void unbind(pdmk_plan* P);
 static void free_plan_tables(pdmk_plan* P) {
   void* ptrs[] = {P->d_E, P->d_Ed, P->d_F2, P->d_F2d, P->d_nodes, P->d_bw, P->d_Tm,
                   P->d_F, P->d_Ff, P->d_dtab, P->d_farscale, P->d_shiftvec, P->d_pwt_f,
-                  P->d_pwt_d, P->adj_buf, P->d_ball, P->d_brow, P->d_fftw, P->d_pwt_b};
+                  P->d_pwt_d, P->adj_buf, P->d_ball, P->d_brow, P->d_fftw, P->d_pwt_b,
+                  P->d_Fc, P->d_Fw};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
+  pdmk::gemm_release(P);
   for (hipEvent_t e : P->ev_pool) (void)hipEventDestroy(e);
   P->ev_pool.clear();
   P->ev_next = 0;
@@ -713,6 +727,7 @@ static int eval_impl(pdmk_plan* P, int64_t n_src, const double* src, const doubl
   E.q = q;
   E.keep_map = keep != nullptr;
   E.timing = !noalloc;   // stage events only where the call may create them
+  E.lib_gemm = !noalloc;
   E.det = (flags & PDMK_DETERMINISTIC) != 0;
   try {
     int cur = -1;
@@ -860,6 +875,7 @@ static int eval_impl(pdmk_plan* P, int64_t n_src, const double* src, const doubl
       BoundState* B = new BoundState();
       *keep = B;
       B->E = kept;
+      B->E.lib_gemm = false;   // executes only enqueue kernels (graph-capturable)
       B->tree_ws.overflow.swap(ws.overflow);
       B->tree_arena = arena;
       arena = nullptr;

@@ -211,6 +211,9 @@ struct Eval {
   int* d_flags = nullptr;   // device {non-finite charge, non-finite position}
   double* qsum = nullptr;   // device {sum q, sum |q|}
   bool near_pending = false;
+  // the axis-by-axis plane waves may call the library GEMM (it may allocate:
+  // not in the allocation-free entry or a kept-tree execute)
+  bool lib_gemm = false;
   double* far_out = nullptr;    // separate far-field part (tree order), else null:
                                 // the interpolation adds into pot_sorted
   int far_comp = 0;             // grid part the interpolation reads (1: imaginary)
@@ -226,6 +229,11 @@ struct Eval {
 };
 // Fills the near-field entries of E.st (call after the stream has finished).
 void near_finish(const pdmk_plan* P, Eval& E);
+// Colleague translation of one level on compact half-ball expansions (3D, FP64).
+void pw_translate(const pdmk_plan* P, const Level& L, const double2* S, double2* Iw,
+                  double levfac, unsigned long long* npairs, hipStream_t s);
+// Destroys the plan's library-GEMM handle (if one was made).
+void gemm_release(pdmk_plan* P);
 
 }  // namespace pdmk
 
@@ -279,6 +287,9 @@ struct pdmk_plan {
   double* d_bw = nullptr;      // p
   double* d_Tm = nullptr;      // [2][p][p]: parent basis at child nodes, sigma = -1, +1
   double2* d_F = nullptr;      // [2J+1][p]: exp(-i pi j xi_p / 3)
+  double2* d_Fc = nullptr;     // its conjugate
+  double2* d_Fw = nullptr;     // its conjugate with rows j > 0 doubled (Hermitian half)
+  void* blas = nullptr;        // rocBLAS handle of the library-GEMM plane-wave path
   float2* d_Ff = nullptr;      // FP32 copy
   double* d_dtab = nullptr;    // |j|^2 table
   double* d_farscale = nullptr;// M0*M1*M2

@@ -12,6 +12,8 @@
 // potentials on the same grid.
 #include <array>
 
+#include <rocblas/rocblas.h>
+
 #include "internal.h"
 #include "lagrange.h"
 
@@ -683,6 +685,111 @@ __global__ void k_axis(int nitems, int n0, int n1, int n2, int ax, int mout,
   else reinterpret_cast<double2*>(out_)[gid] = make_double2(sr, si);
 }
 
+// The same contraction as k_axis (complex input and output, MODE 0) as one
+// library GEMM on the matrix cores: with the tensor [nitems][n0][n1][n2] split
+// at the contracted axis into (outer, n_i, inner), the output is
+//   out[b][o][r] = sum_i Mc(o, i) in[b][i][r],   Mc(o, i) = M[(row0 + o) ld + i]
+// (trans = 0) or M[(row0 + i) ld + o] (trans = 1).  Column-major views: for
+// inner > 1 a strided batch over b of C (inner x mout) = X (inner x n_i)
+// op(B); for inner = 1 one product C (mout x rows) = op(A) X (n_i x rows).
+// Conjugation comes from the conjugated tables (trans = 0) or the conjugate
+// transpose (trans = 1).
+static void axis_gemm(pdmk_plan* P, hipStream_t s, int nitems, int n0, int n1, int n2, int ax,
+                      int mout, const double2* in, double2* out, const double2* M,
+                      const double2* Mconj, int row0, int ld, int trans, int conj) {
+  rocblas_handle h = static_cast<rocblas_handle>(P->blas);
+  if (!h) {
+    if (rocblas_create_handle(&h) != rocblas_status_success)
+      throw Error{PDMK_ERR_HIP, "rocblas_create_handle failed"};
+    P->blas = h;
+  }
+  if (rocblas_set_stream(h, s) != rocblas_status_success)
+    throw Error{PDMK_ERR_HIP, "rocblas_set_stream failed"};
+  const int dims[3] = {n0, n1, n2};
+  const int ni = dims[ax];
+  int64_t outer = nitems, inner = 1;
+  for (int a = 0; a < ax; ++a) outer *= dims[a];
+  for (int a = ax + 1; a < 3; ++a) inner *= dims[a];
+  const rocblas_double_complex one(1.0, 0.0), zero(0.0, 0.0);
+  auto cz = [](const double2* p) { return reinterpret_cast<const rocblas_double_complex*>(p); };
+  rocblas_status st;
+  if (inner == 1) {
+    // C (mout x rows) = op(A) X; A from the table: trans = 0 -> A^T stored
+    // (lda = ld), trans = 1 -> A stored (lda = ld, conj: the conjugated table)
+    const int64_t rows = outer;
+    if (rows > INT32_MAX) throw Error{PDMK_ERR_UNSUPPORTED, "GEMM rows beyond int32"};
+    const double2* A = (trans ? (conj ? Mconj : M) : (conj ? Mconj : M)) + (int64_t)row0 * ld;
+    const rocblas_operation opA = trans ? rocblas_operation_none : rocblas_operation_transpose;
+    st = rocblas_zgemm(h, opA, rocblas_operation_none, mout, (int)rows, ni, &one, cz(A), ld,
+                       cz(in), ni, &zero, reinterpret_cast<rocblas_double_complex*>(out), mout);
+  } else {
+    // per b: C (inner x mout) = X (inner x n_i) B, B(i, o) = Mc(o, i):
+    // trans = 0 -> B stored (ldb = ld, conj: the conjugated table),
+    // trans = 1 -> B^T stored (ldb = ld; conj: conjugate transpose)
+    if (outer > INT32_MAX || inner > INT32_MAX) throw Error{PDMK_ERR_UNSUPPORTED, "GEMM shape"};
+    const double2* B = (trans ? M : (conj ? Mconj : M)) + (int64_t)row0 * ld;
+    const rocblas_operation opB = trans ? (conj ? rocblas_operation_conjugate_transpose
+                                                : rocblas_operation_transpose)
+                                        : rocblas_operation_none;
+    st = rocblas_zgemm_strided_batched(h, rocblas_operation_none, opB, (int)inner, mout, ni, &one,
+                                       cz(in), (int)inner, (rocblas_stride)(ni * inner), cz(B), ld,
+                                       0, &zero, reinterpret_cast<rocblas_double_complex*>(out),
+                                       (int)inner, (rocblas_stride)(mout * inner), (int)outer);
+  }
+  if (st != rocblas_status_success)
+    throw Error{PDMK_ERR_HIP, "rocblas_zgemm failed: " + std::string(rocblas_status_to_string(st))};
+}
+
+void gemm_release(pdmk_plan* P) {
+  if (P->blas) (void)rocblas_destroy_handle(static_cast<rocblas_handle>(P->blas));
+  P->blas = nullptr;
+}
+
+// real -> complex (im = 0)
+__global__ void k_real_to_cplx(int64_t n, const double* __restrict__ in, double2* __restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = make_double2(in[i], 0.0);
+}
+// Full (J+1) x n x n mode grid <-> compact half-ball order of a chunk of
+// boxes: gather S[k][e] = full[k][mode(e)]; scatter writes every full mode
+// (zero outside the ball, and for boxes without targets, whose incoming
+// expansions the translation leaves unwritten).
+__global__ void k_gather_ball(int nc, int nball, int J, const int* __restrict__ ball,
+                              const double2* __restrict__ full, double2* __restrict__ S) {
+  const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (gid >= (int64_t)nc * nball) return;
+  const int k = (int)(gid / nball), e = (int)(gid - (int64_t)k * nball);
+  const int n = 2 * J + 1;
+  const int c = ball[e];
+  const int j0 = c & 255, a = (c >> 8) & 255, b = c >> 16;
+  S[gid] = full[(int64_t)k * (J + 1) * n * n + ((int64_t)j0 * n + a) * n + b];
+}
+__global__ void k_scatter_ball(int nc, int k0, Level L, int nball, int J,
+                               const int2* __restrict__ brow, const double2* __restrict__ Iw,
+                               double2* __restrict__ full) {
+  const int n = 2 * J + 1;
+  const int64_t msz = (int64_t)(J + 1) * n * n;
+  const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (gid >= (int64_t)nc * msz) return;
+  const int k = (int)(gid / msz);
+  const int64_t m = gid - (int64_t)k * msz;
+  const int r = (int)(m / n), b = (int)(m - (int64_t)r * n);
+  const int bx = L.nl_box[k0 + k];
+  double2 v = make_double2(0.0, 0.0);
+  if (L.tend[bx] > L.tbeg[bx]) {
+    const int2 rw = brow[r];   // {compact index of j2 = -J, half width}
+    if (rw.y >= 0 && b - J >= -rw.y && b - J <= rw.y)
+      v = Iw[(int64_t)(k0 + k) * nball + rw.x + b];
+  }
+  full[gid] = v;
+}
+
+// out += Re(in)
+__global__ void k_add_real(int64_t n, const double2* __restrict__ in, double* __restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] += in[i].x;
+}
+
 // Incoming expansion of every non-leaf box B of a level:
 //   I_B(j) = c_l(|j|^2) sum_{C} omega^{j.(c_B - c_C)/h} S_C(j),
 // over the non-leaf colleagues C (including B), omega = exp(2 pi i / 3).
@@ -1284,18 +1391,26 @@ static void near_impl(pdmk_plan* P, Eval& E, bool want_grad) {
     const size_t lds_in = lds_pw_in(p, J, sizeof(Real));
     const bool fused = D == 3 && lds_out <= 150 * 1024 && lds_in <= 150 * 1024;
     // matrix-core path: outgoing and translated incoming expansions in compact
-    // half-ball order; vector-ALU path: outgoing expansions on the full grid
-    C* bS = E.alloc<C>((size_t)maxnl * (mfma ? P->nball : s3));
-    C* bIw = mfma ? E.alloc<C>((size_t)maxnl * P->nball) : nullptr;
+    // half-ball order; vector-ALU path: outgoing expansions on the full grid.
+    // Axis-by-axis path (neither fused nor matrix-core, FP64): library GEMMs
+    // for the contractions where the call may allocate (the proxy tensors go
+    // through one complex staging buffer of p^d per box); in 3D the
+    // expansions are then kept in compact half-ball order too and translated
+    // by the matrix-core path's kernel
+    const bool gemm = E.lib_gemm && !mfma && !fused && sizeof(Real) == 8;
+    const bool compact = mfma || (gemm && D == 3);
+    C* bS = E.alloc<C>((size_t)maxnl * (compact ? P->nball : s3));
+    C* bIw = compact ? E.alloc<C>((size_t)maxnl * P->nball) : nullptr;
     // axis-by-axis path: the intermediate tensors of at most `chunk` boxes at a
     // time (about 2 GB), so that their size does not grow with the level (at
     // p = 40 they take 3.9 MB per box); only the outgoing plane waves, which
     // the translation reads across colleagues, are kept for the whole level
-    const int64_t per_box = (s1 + s2 + s3) * (int64_t)sizeof(double2);
+    const int64_t per_box = (s1 + s2 + s3 + (gemm ? pD : 0)) * (int64_t)sizeof(double2);
     const int chunk = (int)std::max<int64_t>(1, std::min<int64_t>(maxnl, (2ll << 30) / per_box));
     double2* bA = fused ? nullptr : E.alloc<double2>((size_t)chunk * s1);
     double2* bB = (D == 3 && !fused) ? E.alloc<double2>((size_t)chunk * s2) : nullptr;
     double2* bI = fused ? nullptr : E.alloc<double2>((size_t)chunk * s3);
+    double2* bQ = gemm ? E.alloc<double2>((size_t)chunk * pD) : nullptr;
     unsigned long long* npairs = cnt;
     E.pw_split = mfma;
     const C* Ftab = reinterpret_cast<const C*>(sizeof(Real) == 4 ? (const void*)P->d_Ff
@@ -1339,6 +1454,51 @@ static void near_impl(pdmk_plan* P, Eval& E, bool want_grad) {
       double2* bSd = reinterpret_cast<double2*>(bS);
       const double* pq = static_cast<const double*>(L.proxy_q);
       double* pphi = static_cast<double*>(L.proxy_phi);
+      if (gemm) {
+        const double2* F = P->d_F;
+        const double2* Fc = P->d_Fc;
+        for (int k0 = 0; k0 < nn; k0 += chunk) {
+          const int nc = std::min(chunk, nn - k0);
+          hipLaunchKernelGGL(k_real_to_cplx, dim3(nblk((int64_t)nc * pD, 256)), dim3(256), 0, s,
+                             (int64_t)nc * pD, pq + (int64_t)k0 * pD, bQ);
+          axis_gemm(P, s, nc, p, p, zz, 0, J + 1, bQ, bA, F, Fc, J, p, 0, 0);
+          if (D == 3) {
+            axis_gemm(P, s, nc, J + 1, p, p, 1, n1, bA, bB, F, Fc, 0, p, 0, 0);
+            axis_gemm(P, s, nc, J + 1, n1, p, 2, n1, bB, bI, F, Fc, 0, p, 0, 0);
+            hipLaunchKernelGGL(k_gather_ball, dim3(nblk((int64_t)nc * P->nball, 256)),
+                               dim3(256), 0, s, nc, P->nball, J, P->d_ball, (const double2*)bI,
+                               bSd + (int64_t)k0 * P->nball);
+          } else {
+            axis_gemm(P, s, nc, J + 1, p, 1, 1, n1, bA, bSd + (int64_t)k0 * s3, F, Fc, 0, p, 0,
+                      0);
+          }
+        }
+        if (D == 3)
+          pw_translate(P, L, bSd, reinterpret_cast<double2*>(bIw), levfac, npairs, s);
+        for (int k0 = 0; k0 < nn; k0 += chunk) {
+          const int nc = std::min(chunk, nn - k0);
+          if (D == 3)
+            hipLaunchKernelGGL(k_scatter_ball, dim3(nblk((int64_t)nc * s3, 256)), dim3(256), 0,
+                               s, nc, k0, L, P->nball, J, P->d_brow,
+                               (const double2*)reinterpret_cast<double2*>(bIw), bI);
+          else
+            hipLaunchKernelGGL(k_translate<D>, dim3(nblk((int64_t)nc * s3, 256)), dim3(256), 0,
+                               s, L, J, k0, nc, bSd, bI, P->d_dtab, levfac, npairs);
+          if (D == 3) {
+            axis_gemm(P, s, nc, J + 1, n1, n1, 2, p, bI, bB, F, Fc, 0, p, 1, 1);
+            axis_gemm(P, s, nc, J + 1, n1, p, 1, p, bB, bA, F, Fc, 0, p, 1, 1);
+          } else {
+            axis_gemm(P, s, nc, J + 1, n1, 1, 1, p, bI, bA, F, Fc, 0, p, 1, 1);
+          }
+          // last axis with the Hermitian weights (1 for j = 0, 2 for j > 0),
+          // real part added to the proxy potentials
+          axis_gemm(P, s, nc, J + 1, p, zz, 0, p, bA, bQ, P->d_Fw, P->d_Fw, J, p, 1, 0);
+          hipLaunchKernelGGL(k_add_real, dim3(nblk((int64_t)nc * pD, 256)), dim3(256), 0, s,
+                             (int64_t)nc * pD, (const double2*)bQ, pphi + (int64_t)k0 * pD);
+        }
+        if (tm) PDMK_HIP(hipEventRecord(pe[2], s));
+        continue;
+      }
       // outgoing: proxy charges -> plane waves (Hermitian half on axis 0)
       for (int k0 = 0; k0 < nn; k0 += chunk) {
         const int nc = std::min(chunk, nn - k0);

@@ -1064,8 +1064,17 @@ bool anterp_mfma(const pdmk_plan* P, const Level& L, const Level& C, int l, cons
   else if (P->kp.p == 13)
     hipLaunchKernelGGL((k_anterp_mfma<Real, 13>), dim3(L.nnl), dim3(256), 0, s, P->kp, L, C, l,
                        sx, sq, nimg, P->d_nodes, P->d_bw, static_cast<Real*>(Q));
-  else
+  else if constexpr (sizeof(Real) == 8) {
+    // the order of eps = 1e-9 (FP64 only: mixed plans compute in FP64 there;
+    // at p = 40 the accumulator tiles no longer fit the registers)
+    if (P->kp.p == 31)
+      hipLaunchKernelGGL((k_anterp_mfma<Real, 31>), dim3(L.nnl), dim3(256), 0, s, P->kp, L, C,
+                         l, sx, sq, nimg, P->d_nodes, P->d_bw, static_cast<Real*>(Q));
+    else
+      return false;
+  } else {
     return false;
+  }
   return true;
 }
 
@@ -1385,7 +1394,6 @@ static std::vector<Real> pw_mfma_tables_t(const std::vector<double>& nodes, int 
 
 void pw_mfma_upload(pdmk_plan* P) {
   const int p = P->mp.porder, J = P->mp.npw;
-  if (!pw_mfma_supported(p, J)) return;
   {
     // modes of the Hermitian half ball |j| <= J, slab by slab (j0 | j1 << 8 | j2 << 16
     // with j1, j2 shifted by J), followed by the J + 2 slab starts
@@ -1423,6 +1431,10 @@ void pw_mfma_upload(pdmk_plan* P) {
     PDMK_HIP(hipMemcpy(d, brow.data(), brow.size() * sizeof(int), hipMemcpyHostToDevice));
     P->d_brow = static_cast<int2*>(d);
   }
+  // the compact half-ball tables above serve every order (the colleague
+  // translation of the library-GEMM path uses them too); the matrix-core
+  // contraction tables only the supported (p, J)
+  if (!pw_mfma_supported(p, J)) return;
   std::vector<double> nodes, bw;
   cheb_nodes(p, nodes, bw);
   {
@@ -1447,6 +1459,18 @@ void pw_mfma_upload(pdmk_plan* P) {
     PDMK_HIP(hipMemcpy(d, t.data(), t.size() * sizeof(double), hipMemcpyHostToDevice));
     P->d_pwt_d = static_cast<double*>(d);
   }
+}
+
+// Colleague translation of one level in compact half-ball order (FP64), for
+// the plane-wave path whose contractions run as library GEMMs.
+void pw_translate(const pdmk_plan* P, const Level& L, const double2* S, double2* Iw,
+                  double levfac, unsigned long long* npairs, hipStream_t s) {
+  const int nn = L.nnl;
+  if (nn == 0) return;
+  const int nchunk = (P->nball + kTransChunk - 1) / kTransChunk;
+  hipLaunchKernelGGL(k_pw_trans<double>, dim3(nchunk * nn), dim3(256), 0, s, L, S, P->d_dtab,
+                     P->d_ball, P->nball, P->kp.J, levfac, Iw, npairs);
+  PDMK_HIP(hipGetLastError());
 }
 
 template <class Real, int PP, int JJ, int KB>
