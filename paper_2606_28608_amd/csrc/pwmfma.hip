@@ -921,7 +921,10 @@ template bool eval_leaf_mfma<double>(const pdmk_plan*, const Level&, const Level
 // tiles with the sources in chunks of 64 (3 x 64 threads form a chunk's
 // Lagrange rows).  One block of 4 waves per box; each wave owns the same
 // M-tiles of Q for every chunk (accumulators in registers).
-template <class Real, int P>
+// MWP > 0: each block computes MWP tile slots per wave (blockIdx.y selects
+// which), so that large orders keep their accumulators in registers; the
+// sources are then read once per block.
+template <class Real, int P, int MWP = 0>
 __global__ __launch_bounds__(256, sizeof(Real) == 4 ? 3 : 1) void k_anterp_mfma(KParams kp, Level L, Level C, int lvl,
                                                      const double* __restrict__ sx,
                                                      const double* __restrict__ sq,
@@ -932,7 +935,8 @@ __global__ __launch_bounds__(256, sizeof(Real) == 4 ? 3 : 1) void k_anterp_mfma(
   using MF = Mfma<Real>;
   using V = typename MF::V;
   constexpr int PP = P * P, SL = P | 1, CH = 64, NT = (P + 15) / 16, NW = 16 * NT;
-  constexpr int MT = (PP + 15) / 16, MW = (MT + 3) / 4;
+  constexpr int MT = (PP + 15) / 16, MW = MWP > 0 ? MWP : (MT + 3) / 4;
+  const int mt0 = MWP > 0 ? (int)blockIdx.y * 4 * MWP : 0;   // first tile of the block
   __shared__ Real qLx[CH * SL], Ly[CH * SL], Lz[CH * NW];
   __shared__ int cb[8], cpre[9];
   const int k = blockIdx.x;
@@ -964,7 +968,7 @@ __global__ __launch_bounds__(256, sizeof(Real) == 4 ? 3 : 1) void k_anterp_mfma(
   int ri0[MW], ri1[MW];   // (i0, i1) of the lane's A-operand row in each tile slot
 #pragma unroll
   for (int i = 0; i < MW; ++i) {
-    const int m = min(16 * (wave + 4 * i) + li, PP - 1);
+    const int m = min(16 * (mt0 + wave + 4 * i) + li, PP - 1);
     ri0[i] = m / P;
     ri1[i] = m - ri0[i] * P;
 #pragma unroll
@@ -1039,7 +1043,7 @@ __global__ __launch_bounds__(256, sizeof(Real) == 4 ? 3 : 1) void k_anterp_mfma(
   Real* out = Q + (int64_t)k * P * PP;
 #pragma unroll
   for (int i = 0; i < MW; ++i) {
-    const int mt = wave + 4 * i;
+    const int mt = mt0 + wave + 4 * i;
     if (mt < MT)
 #pragma unroll
       for (int n = 0; n < NT; ++n) {
@@ -1065,13 +1069,21 @@ bool anterp_mfma(const pdmk_plan* P, const Level& L, const Level& C, int l, cons
     hipLaunchKernelGGL((k_anterp_mfma<Real, 13>), dim3(L.nnl), dim3(256), 0, s, P->kp, L, C, l,
                        sx, sq, nimg, P->d_nodes, P->d_bw, static_cast<Real*>(Q));
   else if constexpr (sizeof(Real) == 8) {
-    // the order of eps = 1e-9 (FP64 only: mixed plans compute in FP64 there;
-    // at p = 40 the accumulator tiles no longer fit the registers)
-    if (P->kp.p == 31)
+    // the orders of eps = 1e-9 and 1e-12 (FP64 only: mixed plans compute in
+    // FP64 there; at p = 40 the row tiles are split over several blocks)
+    if (P->kp.p == 31) {
       hipLaunchKernelGGL((k_anterp_mfma<Real, 31>), dim3(L.nnl), dim3(256), 0, s, P->kp, L, C,
                          l, sx, sq, nimg, P->d_nodes, P->d_bw, static_cast<Real*>(Q));
-    else
+    } else if (P->kp.p == 40) {
+      // 100 row tiles in 5 blocks of 5 tile slots per wave (all in registers)
+      constexpr int MWP = 5, MT = (40 * 40 + 15) / 16;
+      const int npass = (MT + 4 * MWP - 1) / (4 * MWP);
+      hipLaunchKernelGGL((k_anterp_mfma<Real, 40, MWP>), dim3(L.nnl, npass), dim3(256), 0, s,
+                         P->kp, L, C, l, sx, sq, nimg, P->d_nodes, P->d_bw,
+                         static_cast<Real*>(Q));
+    } else {
       return false;
+    }
   } else {
     return false;
   }
