@@ -209,6 +209,38 @@ def run_bloch(pdmk, L, S, Q, n, eps, precision, steps, warmup, over):
             "fourier_grid": list(plan.geometry().fgrid)}
 
 
+def run_cube(pdmk, n, eps, precision, steps):
+    """The cube-cell construction of rem:cube against physical images on the
+    same input: N clustered sources in the unit cube, kappa = 4 (r_c a
+    quarter of the side), n_s = 300."""
+    import numpy as np
+    import torch
+    from paper_2606_28608_amd import workloads as W
+    L, src, q = W.clustered3d(n, seed=2, cell="cubic")
+    dev = torch.device("cuda:0")
+    S = torch.tensor(src, dtype=torch.float64, device=dev)
+    Q = torch.tensor(q, dtype=torch.float64, device=dev)
+    out, pots = {}, {}
+    for name, vi in (("physical_images", False), ("virtual_images", True)):
+        progress("cube %s %s eps=%g: 1 warm-up + %d timed steps" % (name, precision, eps, steps))
+        plan = pdmk.Plan(L, eps=eps, precision=precision, kappa=4.0, n_s=300, virtual_images=vi)
+        plan.eval(S, Q)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            pot = plan.eval(S, Q)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / steps
+        st = plan.stats()
+        pots[name] = pot.cpu().numpy()
+        out[name] = {"ms_per_step": 1e3 * dt, "value": n / dt, "n_images": st["n_images"],
+                     "t_build_ms": round(st["t_build_ms"], 3), "t_near_ms": round(st["t_near_ms"], 3)}
+    a, b = pots["virtual_images"], pots["physical_images"]
+    out["rel_diff"] = float(np.linalg.norm(a - b) / np.linalg.norm(b))
+    out["workload"] = "clustered3d cubic, N=%d, kappa=4, n_s=300, eps=%g" % (n, eps)
+    return out
+
+
 def _ball_modes(J):
     """Modes of the Hermitian half ball |j| <= J (j0 >= 0)."""
     n = 0
@@ -394,6 +426,10 @@ def child(args):
         extra["one_stream"] = brief(one, args.eps)
         # quasi-periodic conditions (Section 4.1) with the same plan
         extra["bloch"] = run_bloch(pdmk, L, S, Q, n, args.eps, args.precision, 3, 1, over)
+        # the cube-cell construction (virtual images) against physical images
+        del S, Q
+        torch.cuda.empty_cache()
+        extra["cube"] = run_cube(pdmk, n, args.eps, args.precision, 3)
         r["extra"] = extra
         for k in ("k_spread_coop", "k_interp_t"):
             r["roofline"]["kernels"][k] = {kk: r["far_field"][k][kk]
