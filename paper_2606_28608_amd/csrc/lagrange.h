@@ -5,31 +5,6 @@
 
 namespace pdmk {
 
-// Lagrange basis at the p Chebyshev nodes (barycentric form), and optionally
-// its derivative.  x exactly at a node is moved by 1e-13.
-template <class T>
-__device__ inline void lagrange_rows(int p, const double* __restrict__ nodes,
-                                     const double* __restrict__ bw, double x,
-                                     T* row, T* drow) {
-  for (int j = 0; j < p; ++j)
-    if (x == nodes[j]) { x += 1e-13; break; }
-  double s = 0.0, s1 = 0.0;
-  for (int j = 0; j < p; ++j) {
-    double inv = 1.0 / (x - nodes[j]);
-    double t = bw[j] * inv;
-    s += t;
-    s1 += t * inv;
-  }
-  double is = 1.0 / s;
-  for (int j = 0; j < p; ++j) {
-    // l_j = (w_j/(x - x_j)) / S;  l_j' = l_j (-1/(x - x_j) + S1/S),  S1 = sum w_k/(x-x_k)^2
-    const double inv = 1.0 / (x - nodes[j]);
-    const double lj = bw[j] * inv * is;
-    row[j] = (T)lj;
-    if (drow) drow[j] = (T)(lj * (-inv + s1 * is));
-  }
-}
-
 // 1/d from the hardware reciprocal estimate refined by NR Newton steps
 // (r <- r + r (1 - d r)); each step squares the relative error: two leave the
 // result within a few units in the last place of the correctly rounded
@@ -41,6 +16,34 @@ __device__ inline double recip_nr(double d) {
   for (int k = 0; k < NR; ++k) r = fma(r, fma(-d, r, 1.0), r);
   return r;
 }
+
+// Lagrange basis at the p Chebyshev nodes (barycentric form), and optionally
+// its derivative.  x exactly at a node is moved by 1e-13.
+template <class T>
+__device__ inline void lagrange_rows(int p, const double* __restrict__ nodes,
+                                     const double* __restrict__ bw, double x,
+                                     T* row, T* drow) {
+  for (int j = 0; j < p; ++j)
+    if (x == nodes[j]) { x += 1e-13; break; }
+  // reciprocals by Newton-refined hardware estimates (recomputed in the
+  // second loop: cheaper than keeping p of them)
+  double s = 0.0, s1 = 0.0;
+  for (int j = 0; j < p; ++j) {
+    double inv = recip_nr<2>(x - nodes[j]);
+    double t = bw[j] * inv;
+    s += t;
+    s1 += t * inv;
+  }
+  double is = recip_nr<2>(s);
+  for (int j = 0; j < p; ++j) {
+    // l_j = (w_j/(x - x_j)) / S;  l_j' = l_j (-1/(x - x_j) + S1/S),  S1 = sum w_k/(x-x_k)^2
+    const double inv = recip_nr<2>(x - nodes[j]);
+    const double lj = bw[j] * inv * is;
+    row[j] = (T)lj;
+    if (drow) drow[j] = (T)(lj * (-inv + s1 * is));
+  }
+}
+
 
 // Same as lagrange_rows with compile-time capacity PMAX (entries >= p are 0),
 // so the rows stay in registers; NR Newton steps per reciprocal.
