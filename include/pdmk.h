@@ -111,6 +111,12 @@ enum {
                                   pdmk_stats are stand-alone durations) */
   PDMK_BLOCH = 32,             /* quasi-periodic conditions with the Bloch vector
                                   pdmk_opts.bloch (see pdmk_plan_eval_bloch) */
+  PDMK_BALANCE = 128,          /* 2:1 balance of the adaptive tree (Algorithm 1): every
+                                  leaf holding points is split while a colleague of it
+                                  has grandchildren, the tree being rebuilt with the
+                                  forced splits until none is left.  The result is the
+                                  same (the interaction rule is exact for any tree); the
+                                  work moves from the residual sums to plane waves. */
   PDMK_VIRTUAL_IMAGES = 64     /* the cube-cell construction of rem:cube for rectangular
                                   cells whose edges are whole multiples of
                                   r_c = L_min / kappa (a cube with integer kappa): the
@@ -456,6 +462,8 @@ typedef struct {
                                        PDMK_ONE_STREAM, so it may overlap other stages) */
   double t_fft_ms;                  /* far field: forward FFT, scaling, inverse FFT */
   double t_interp_ms;               /* far field: interpolation at the targets */
+  int64_t n_forced_splits;          /* PDMK_BALANCE: leaves split for the 2:1 balance */
+  int balance_rounds;               /* PDMK_BALANCE: tree builds until balanced */
 } pdmk_stats;
 int pdmk_plan_stats(const pdmk_plan* plan, pdmk_stats* out);
 int pdmk_batch_stats(const pdmk_batch* batch, int sys, pdmk_stats* out);

@@ -455,7 +455,7 @@ static int validate_opts(const pdmk_opts* o) {
     return fail(PDMK_ERR_INVALID_ARG, "porder <= 40, npw <= 64, nufft_w <= 16, sigma <= 4");
   if (o->flags & ~(unsigned)(PDMK_WANT_GRAD | PDMK_ALLOW_NONNEUTRAL | PDMK_DETERMINISTIC |
                              PDMK_VECTOR_PLANE_WAVES | PDMK_ONE_STREAM | PDMK_BLOCH |
-                             PDMK_VIRTUAL_IMAGES))
+                             PDMK_VIRTUAL_IMAGES | PDMK_BALANCE))
     return fail(PDMK_ERR_INVALID_ARG, "unknown flag");
   if ((o->flags & PDMK_BLOCH) && (o->flags & PDMK_VIRTUAL_IMAGES))
     return fail(PDMK_ERR_UNSUPPORTED, "PDMK_BLOCH does not support PDMK_VIRTUAL_IMAGES");

@@ -557,11 +557,54 @@ __global__ void k_level0(KParams kp, Level L, const uint64_t* __restrict__ skey,
   }
 }
 
-__global__ void k_split_flags(Level L, int lvl, int ns, int maxlev, int* __restrict__ flag) {
+// Split flags of a level: more than n_s sources, or a split forced by the
+// 2:1 balance (the box's (key, level) in the forced list, sorted by key).
+__global__ void k_split_flags(Level L, int lvl, int ns, int maxlev, int* __restrict__ flag,
+                              const uint64_t* __restrict__ fkey, const int* __restrict__ flev,
+                              int nforced) {
   int b = blockIdx.x * blockDim.x + threadIdx.x;
   if (b > L.n) return;
   if (b == L.n) { flag[b] = 0; return; }
-  flag[b] = (L.send[b] - L.sbeg[b] > ns && lvl < maxlev) ? 1 : 0;
+  bool split = L.send[b] - L.sbeg[b] > ns;
+  if (!split && nforced > 0) {
+    const uint64_t key = L.key[b];
+    int lo = 0, hi = nforced;
+    while (lo < hi) {
+      const int mid = (lo + hi) >> 1;
+      if (fkey[mid] < key) lo = mid + 1; else hi = mid;
+    }
+    for (int i = lo; i < nforced && fkey[i] == key; ++i)
+      if (flev[i] == lvl) split = true;
+  }
+  flag[b] = (split && lvl < maxlev) ? 1 : 0;
+}
+
+// 2:1 balance check of level l (its boxes and those of levels l+1, l+2
+// exist): a leaf holding points with a colleague that has a non-leaf child
+// is appended to the forced list (key, level) at the next free slot.
+__global__ void k_balance_check(Level L, Level C1, int lvl, int d, uint64_t* __restrict__ fkey,
+                                int* __restrict__ flev, int* __restrict__ nforced, int cap) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= L.n) return;
+  if (L.child0[b] >= 0) return;
+  if (L.send[b] <= L.sbeg[b] && L.tend[b] <= L.tbeg[b]) return;
+  const int ncoll = d == 3 ? 27 : 9;
+  bool viol = false;
+  for (int sl = 0; sl < ncoll && !viol; ++sl) {
+    const int c = L.coll[b * ncoll + sl];
+    if (c < 0) continue;
+    const int c0 = L.child0[c];
+    if (c0 < 0) continue;
+    for (int o = 0; o < (1 << d); ++o)
+      if (C1.child0[c0 + o] >= 0) { viol = true; break; }
+  }
+  if (viol) {
+    const int slot = atomicAdd(nforced, 1);
+    if (slot < cap) {
+      fkey[slot] = L.key[b];
+      flev[slot] = lvl;
+    }
+  }
 }
 
 __global__ void k_mark_parents(Level L, const int* __restrict__ flag, const int* __restrict__ off,
@@ -647,7 +690,70 @@ static void alloc_level(Eval& E, Level& L, int n, int d, bool vimg) {
   L.nlid = E.alloc<int>(n);
 }
 
+static void build_tree(pdmk_plan* P, Eval& E, const uint64_t* fkey, const int* flev,
+                       int nforced);
+
+__global__ void k_set_int(int* p, int v) { *p = v; }
+
+// The adaptive tree; with PDMK_BALANCE rebuilt with forced splits until it is
+// 2:1 balanced (Algorithm 1).  Each round's tree is dropped by rewinding the
+// workspace to the mark before it (stream order keeps the reuse safe).
 void stage_tree(pdmk_plan* P, Eval& E) {
+  if (!(P->o.flags & PDMK_BALANCE)) {
+    build_tree(P, E, nullptr, nullptr, 0);
+    return;
+  }
+  const int d = P->kp.dim;
+  int cap = 0, nforced = 0, rounds = 0;
+  uint64_t* fkey = nullptr;
+  uint64_t* fkey2 = nullptr;
+  int* flev = nullptr;
+  int* flev2 = nullptr;
+  int* dcount = E.alloc<int>(1);
+  for (;;) {
+    ++rounds;
+    const size_t mark = E.ws->used;
+    build_tree(P, E, fkey, flev, nforced);
+    if (cap == 0) {
+      // the forced list lives below every later round's mark
+      int64_t nb = 0;
+      for (auto& L : E.lev) nb += L.n;
+      cap = (int)std::min<int64_t>(INT32_MAX / 2, 8 * nb + 1024);
+      E.ws->used = mark;
+      fkey = E.alloc<uint64_t>(cap);
+      flev = E.alloc<int>(cap);
+      fkey2 = E.alloc<uint64_t>(cap);
+      flev2 = E.alloc<int>(cap);
+      continue;   // rebuild above the list (the same tree: nothing forced yet)
+    }
+    const int nlev = (int)E.lev.size();
+    hipLaunchKernelGGL(k_set_int, dim3(1), dim3(1), 0, E.s, dcount, nforced);
+    for (int l = 0; l + 2 < nlev; ++l)
+      hipLaunchKernelGGL(k_balance_check, dim3(nblk(E.lev[l].n, 256)), dim3(256), 0, E.s,
+                         E.lev[l], E.lev[l + 1], l, d, fkey, flev, dcount, cap);
+    const int total = read_int(dcount, E.s);
+    if (total > cap) throw Error{PDMK_ERR_UNSUPPORTED, "2:1 balance: forced-split list overflow"};
+    if (total == nforced || rounds > 64) break;
+    // keep the list sorted by key (the level decides among equal keys)
+    size_t tb = 0;
+    PDMK_HIP(rocprim::radix_sort_pairs(nullptr, tb, fkey, fkey2, flev, flev2, (size_t)total, 0u,
+                                       64u, E.s));
+    void* tmp = E.alloc<char>(tb);
+    PDMK_HIP(rocprim::radix_sort_pairs(tmp, tb, fkey, fkey2, flev, flev2, (size_t)total, 0u, 64u,
+                                       E.s));
+    PDMK_HIP(hipMemcpyAsync(fkey, fkey2, (size_t)total * sizeof(uint64_t),
+                            hipMemcpyDeviceToDevice, E.s));
+    PDMK_HIP(hipMemcpyAsync(flev, flev2, (size_t)total * sizeof(int), hipMemcpyDeviceToDevice,
+                            E.s));
+    nforced = total;
+    E.ws->used = mark;   // the next round's tree replaces this one
+  }
+  E.st.n_forced_splits = nforced;
+  E.st.balance_rounds = rounds;
+}
+
+static void build_tree(pdmk_plan* P, Eval& E, const uint64_t* fkey, const int* flev,
+                       int nforced) {
   const KParams& kp = P->kp;
   const int d = kp.dim;
   E.lev.clear();
@@ -663,7 +769,7 @@ void stage_tree(pdmk_plan* P, Eval& E) {
     int* flag = E.alloc<int>(Lp.n + 1);
     int* off = E.alloc<int>(Lp.n + 1);
     hipLaunchKernelGGL(k_split_flags, dim3(nblk(Lp.n + 1, 256)), dim3(256), 0, E.s, Lp, l,
-                       P->mp.n_s, maxlev, flag);
+                       P->mp.n_s, maxlev, flag, fkey, flev, nforced);
     exclusive_scan_int(flag, off, Lp.n + 1, E);
     int nsplit = read_int(off + Lp.n, E.s);
     Lp.nnl = nsplit;

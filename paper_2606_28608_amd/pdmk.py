@@ -28,6 +28,7 @@ PDMK_VECTOR_PLANE_WAVES = 8
 PDMK_ONE_STREAM = 16
 PDMK_BLOCH = 32
 PDMK_VIRTUAL_IMAGES = 64
+PDMK_BALANCE = 128
 PDMK_FP32_RESIDUAL = 1
 PDMK_FP32_PROXY = 2
 PDMK_FP32_WINDOW = 4
@@ -80,7 +81,8 @@ class Stats(ctypes.Structure):
                 ("t_pwout_ms", ctypes.c_double), ("t_pwin_ms", ctypes.c_double),
                 ("t_pwtr_ms", ctypes.c_double), ("n_staged_pairs", ctypes.c_int64),
                 ("t_spread_ms", ctypes.c_double), ("t_fft_ms", ctypes.c_double),
-                ("t_interp_ms", ctypes.c_double)]
+                ("t_interp_ms", ctypes.c_double), ("n_forced_splits", ctypes.c_int64),
+                ("balance_rounds", ctypes.c_int)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -165,10 +167,10 @@ def _check(code):
 
 def default_opts(dim, eps, precision="fp64", grad=False, allow_nonneutral=False,
                  deterministic=False, vector_plane_waves=False, one_stream=False, bloch=None,
-                 virtual_images=False, **over):
+                 virtual_images=False, balance=False, **over):
     """pdmk_opts for (dim, eps) with the defaults of pdmk_default_opts; keyword
     arguments set flags (grad, allow_nonneutral, deterministic,
-    vector_plane_waves, one_stream, bloch = Bloch vector, virtual_images) or
+    vector_plane_waves, one_stream, bloch = Bloch vector, virtual_images, balance) or
     override fields (kappa, n_s, porder, npw, nufft_w,
     sigma, fp32_stages)."""
     o = Opts()
@@ -181,7 +183,8 @@ def default_opts(dim, eps, precision="fp64", grad=False, allow_nonneutral=False,
                | (PDMK_VECTOR_PLANE_WAVES if vector_plane_waves else 0)
                | (PDMK_ONE_STREAM if one_stream else 0)
                | (PDMK_BLOCH if bloch is not None else 0)
-               | (PDMK_VIRTUAL_IMAGES if virtual_images else 0))
+               | (PDMK_VIRTUAL_IMAGES if virtual_images else 0)
+               | (PDMK_BALANCE if balance else 0))
     if bloch is not None:
         b = [float(v) for v in bloch]
         if len(b) != dim:

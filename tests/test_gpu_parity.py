@@ -344,3 +344,30 @@ def test_order_and_oversampling_independence(pdmk, torch_dev, over):
     pot = _eval(pdmk, torch_dev, L, src, q, 1e-6, kappa=3.0, n_s=60, **over)
     assert ewald.rel_l2(pot, ref) <= 1e-6
     assert ewald.rel_l2(pot, base) <= 1e-6
+
+
+@pytest.mark.parametrize("cell,eps", [("triclinic", 1e-6), ("cubic", 1e-9)])
+def test_two_to_one_balance(pdmk, torch_dev, cell, eps):
+    """PDMK_BALANCE (the 2:1 balance of Algorithm 1): a clustered cell with
+    small leaves needs forced splits; the result meets eps and equals the
+    unbalanced tree's to eps (the interaction rule is exact for any tree)."""
+    L, src, q = workloads.clustered3d(8000, seed=2, cell=cell)
+    ref = ewald.ewald(L, src, q)
+    plan = pdmk.Plan(L, eps=eps, kappa=3.0, n_s=20, balance=True)
+    pot = plan.eval(_t(torch_dev, src), _t(torch_dev, q)).cpu().numpy()
+    st = plan.stats()
+    print("balance: %d forced splits in %d rounds, levels %d"
+          % (st["n_forced_splits"], st["balance_rounds"], st["n_levels"]))
+    assert st["n_forced_splits"] > 0
+    assert ewald.rel_l2(pot, ref) <= eps
+    base = _eval(pdmk, torch_dev, L, src, q, eps, kappa=3.0, n_s=20)
+    assert ewald.rel_l2(pot, base) <= eps
+
+
+def test_two_to_one_balance_2d_and_gradient(pdmk, torch_dev):
+    L, src, q = workloads.oblique2d(4000, seed=5)
+    ref, gref = ewald.ewald(L, src, q, grad=True)
+    plan = pdmk.Plan(L, eps=1e-6, kappa=3.0, n_s=8, balance=True, grad=True)
+    pot, g = plan.eval(_t(torch_dev, src), _t(torch_dev, q))
+    assert ewald.rel_l2(pot.cpu().numpy(), ref) <= 1e-6
+    assert ewald.rel_l2(g.cpu().numpy(), gref) <= 1e-5
