@@ -486,6 +486,46 @@ def child_batch(args):
                     "tuned_plans": {"%g,%d" % (r[0], r[1]): int(c) for r, c in
                                     zip(*np.unique(np.stack([k, ns.astype(np.float64)], 1),
                                                    axis=0, return_counts=True))}})
+    # kept trees of every cell: new charges enqueued over the worker streams
+    # (no tree build, no host read), eager and as one replayed graph
+    progress("batch %s: kept trees, execute and graph replay" % args.precision)
+    B.bind(offs, src, q)
+    rng = np.random.default_rng(7)
+    qn = np.concatenate([rng.permutation(s[2]) for s in systems])   # neutral per cell
+    q2 = torch.tensor(qn, device="cuda:0")
+    out = torch.empty_like(q2)
+    for _ in range(2):
+        B.execute(q2, out=out)
+    B.status()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        B.execute(q2, out=out)
+    torch.cuda.synchronize()
+    ms_x = 1e3 * (time.perf_counter() - t0) / args.steps
+    B.status()
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        B.execute(q2, out=out)
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    t0 = time.perf_counter()
+    with torch.cuda.graph(g, capture_error_mode="thread_local"):
+        B.execute(q2, out=out)
+    t_cap = time.perf_counter() - t0
+    g.replay()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        g.replay()
+    torch.cuda.synchronize()
+    ms_g = 1e3 * (time.perf_counter() - t0) / args.steps
+    res["kept_trees"] = {"execute_ms_per_call": ms_x, "execute_value": n / (ms_x * 1e-3),
+                         "graph_ms_per_call": ms_g, "graph_value": n / (ms_g * 1e-3),
+                         "capture_s": t_cap,
+                         "what": "new charges on every cell's kept tree (pdmk_batch_execute)"}
     print(json.dumps(res))
 
 

@@ -356,6 +356,28 @@ int pdmk_batch_create(const pdmk_opts* opts, int n_sys, const double* L, int n_w
 int pdmk_batch_eval(pdmk_batch* batch, const int64_t* offsets, const double* src,
                     const double* q, double* pot, double* grad, void* stream);
 void pdmk_batch_destroy(pdmk_batch* batch);
+
+/*
+ * Kept trees for a batch (repeated evaluation with new charges, e.g. the
+ * adjoint after a forward call or charge updates at fixed positions):
+ * pdmk_batch_bind is one evaluation of every system (as pdmk_batch_eval,
+ * blocking; targets are the sources) that keeps each system's tree as
+ * pdmk_plan_bind does; pdmk_batch_execute then evaluates new charges q
+ * (DEVICE, offsets as bound) into pot (and grad with PDMK_WANT_GRAD) by
+ * enqueueing every system's pdmk_plan_execute round-robin over the batch's
+ * worker streams, forked from and joined back into `stream` with events, from
+ * the calling thread only: it does not block, allocates nothing and makes no
+ * host read, so a caller can capture the whole call into one graph.
+ * pdmk_batch_status waits and returns the first device-detected input error
+ * of the systems (as pdmk_plan_status).  A new bind replaces the kept trees;
+ * pdmk_batch_eval and pdmk_batch_tune leave them in place only if they do not
+ * re-plan (pdmk_batch_tune re-plans: bind again after it).
+ */
+int pdmk_batch_bind(pdmk_batch* batch, const int64_t* offsets, const double* src,
+                    const double* q, double* pot, double* grad, void* stream);
+int pdmk_batch_execute(pdmk_batch* batch, const double* q, double* pot, double* grad,
+                       void* stream);
+int pdmk_batch_status(pdmk_batch* batch);
 int pdmk_eval_batched(const pdmk_opts* opts, int n_sys, const double* L,
                       const int64_t* offsets, const double* src, const double* q,
                       double* pot, double* grad, void* stream);

@@ -1441,6 +1441,11 @@ struct pdmk_batch {
   std::vector<hipStream_t> aux;   // each worker's second stream
   std::vector<char*> arenas;
   std::vector<size_t> arena_sizes;
+  // kept trees of every system (pdmk_batch_bind): the bound offsets, and the
+  // fork / join events of an execute over the worker streams
+  std::vector<int64_t> bound_off;
+  hipEvent_t ev_fork = nullptr;
+  std::vector<hipEvent_t> ev_join;
 };
 
 int pdmk_batch_create(const pdmk_opts* opts, int n_sys, const double* L, int n_workers,
@@ -1471,7 +1476,11 @@ int pdmk_batch_create(const pdmk_opts* opts, int n_sys, const double* L, int n_w
       B->aux.push_back(sa);
       B->arenas.push_back(nullptr);
       B->arena_sizes.push_back(0);
+      hipEvent_t ev = nullptr;
+      PDMK_HIP(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+      B->ev_join.push_back(ev);
     }
+    PDMK_HIP(hipEventCreateWithFlags(&B->ev_fork, hipEventDisableTiming));
   } catch (const Error& e) {
     pdmk_batch_destroy(B);
     return fail(e.code, e.msg);
@@ -1539,8 +1548,160 @@ int pdmk_batch_eval(pdmk_batch* B, const int64_t* offsets, const double* src, co
   return PDMK_OK;
 }
 
+int pdmk_batch_bind(pdmk_batch* B, const int64_t* offsets, const double* src, const double* q,
+                    double* pot, double* grad, void* stream) {
+  if (!B || !offsets) return fail(PDMK_ERR_INVALID_ARG, "null argument");
+  const int n_sys = (int)B->plans.size();
+  const int d = B->o.dim;
+  for (int sy = 0; sy < n_sys; ++sy)
+    if (offsets[sy + 1] < offsets[sy]) return fail(PDMK_ERR_INVALID_ARG, "offsets decrease");
+  if (offsets[n_sys] > offsets[0] && (!src || !q || !pot))
+    return fail(PDMK_ERR_INVALID_ARG, "null array");
+  if ((B->o.flags & PDMK_WANT_GRAD) && !grad) return fail(PDMK_ERR_INVALID_ARG, "null grad");
+  if (hipStreamSynchronize((hipStream_t)stream) != hipSuccess)
+    return fail(PDMK_ERR_HIP, "stream synchronise failed");
+  B->bound_off.clear();
+  for (pdmk_plan* P : B->plans) unbind(P);
+  const int nw = (int)B->streams.size();
+  std::vector<int> status(nw, PDMK_OK);
+  std::vector<std::string> msg(nw);
+  std::atomic<int> next(0);
+  auto work = [&](int w) {
+    if (hipSetDevice(B->device) != hipSuccess) {
+      status[w] = PDMK_ERR_HIP;
+      msg[w] = "hipSetDevice failed";
+      return;
+    }
+    for (;;) {
+      const int sy = next.fetch_add(1);
+      if (sy >= n_sys) break;
+      const int64_t o = offsets[sy], n = offsets[sy + 1] - offsets[sy];
+      if (n == 0) continue;   // an empty system keeps no tree
+      const int st = pdmk_plan_bind(B->plans[sy], n, src + o * d, q + o, 0, nullptr, pot + o,
+                                    grad ? grad + o * d : nullptr, B->streams[w]);
+      if (st != PDMK_OK) {
+        status[w] = st;
+        msg[w] = g_last_error;
+        next.store(n_sys);
+        break;
+      }
+    }
+  };
+  std::vector<std::thread> th;
+  try {
+    for (int w = 1; w < nw; ++w) th.emplace_back(work, w);
+  } catch (const std::system_error&) {
+  }
+  work(0);
+  for (auto& t : th) t.join();
+  for (int w = 0; w < nw; ++w)
+    if (status[w] != PDMK_OK) {
+      for (pdmk_plan* P : B->plans) unbind(P);
+      return fail(status[w], msg[w]);
+    }
+  B->bound_off.assign(offsets, offsets + n_sys + 1);
+  return PDMK_OK;
+}
+
+int pdmk_batch_execute(pdmk_batch* B, const double* q, double* pot, double* grad,
+                       void* stream) {
+  if (!B) return fail(PDMK_ERR_INVALID_ARG, "null batch");
+  if (B->bound_off.empty()) return fail(PDMK_ERR_INVALID_ARG, "no bound trees (pdmk_batch_bind)");
+  const int n_sys = (int)B->plans.size();
+  const int d = B->o.dim;
+  if (B->bound_off[n_sys] > B->bound_off[0] && (!q || !pot))
+    return fail(PDMK_ERR_INVALID_ARG, "null array");
+  int cur = -1;
+  if (hipGetDevice(&cur) != hipSuccess || cur != B->device)
+    return fail(PDMK_ERR_INVALID_ARG, "batch bound to another device");
+  const int nw = (int)B->streams.size();
+  hipStream_t cs = (hipStream_t)stream;
+  try {
+    // fork: every worker stream waits for the caller's stream; the systems'
+    // executes are enqueued round-robin over them (this thread only, so a
+    // caller can capture the whole call into one graph); join: the caller's
+    // stream waits for every worker stream
+    PDMK_HIP(hipEventRecord(B->ev_fork, cs));
+    for (int w = 0; w < nw; ++w) PDMK_HIP(hipStreamWaitEvent(B->streams[w], B->ev_fork, 0));
+    for (int sy = 0; sy < n_sys; ++sy)
+      if (B->bound_off[sy + 1] > B->bound_off[sy] && !B->plans[sy]->bound)
+        return fail(PDMK_ERR_INVALID_ARG, "a system has no bound tree (bind again)");
+    // outside a capture the workers enqueue their shares concurrently (the
+    // launches, not the device, bound a batch of small cells); inside one the
+    // calling thread enqueues everything
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+    PDMK_HIP(hipStreamIsCapturing(cs, &cap));
+    const int nthreads = cap == hipStreamCaptureStatusNone ? nw : 1;
+    std::vector<int> status(nw, PDMK_OK);
+    std::vector<std::string> msg(nw);
+    auto work = [&](int t) {
+      if (t > 0 && hipSetDevice(B->device) != hipSuccess) {
+        status[t] = PDMK_ERR_HIP;
+        msg[t] = "hipSetDevice failed";
+        return;
+      }
+      int k = 0;
+      for (int sy = 0; sy < n_sys; ++sy) {
+        const int64_t o = B->bound_off[sy], n = B->bound_off[sy + 1] - o;
+        if (n == 0) continue;
+        const int w = k++ % nw;
+        if (w % nthreads != t) continue;
+        const int st = execute_impl(B->plans[sy], nullptr, nullptr, q + o, pot + o,
+                                    grad ? grad + o * d : nullptr, B->streams[w]);
+        if (st != PDMK_OK) {
+          status[t] = st;
+          msg[t] = g_last_error;
+          return;
+        }
+      }
+    };
+    std::vector<std::thread> th;
+    try {
+      for (int t = 1; t < nthreads; ++t) th.emplace_back(work, t);
+    } catch (const std::system_error&) {
+      for (auto& x : th) x.join();
+      th.clear();
+      throw Error{PDMK_ERR_HIP, "worker threads"};
+    }
+    work(0);
+    for (auto& x : th) x.join();
+    for (int t = 0; t < nthreads; ++t)
+      if (status[t] != PDMK_OK) {
+        for (int w = 0; w < nw; ++w) (void)hipStreamSynchronize(B->streams[w]);
+        return fail(status[t], msg[t]);
+      }
+    for (int w = 0; w < nw; ++w) {
+      PDMK_HIP(hipEventRecord(B->ev_join[w], B->streams[w]));
+      PDMK_HIP(hipStreamWaitEvent(cs, B->ev_join[w], 0));
+    }
+  } catch (const Error& e) {
+    return fail(e.code, e.msg);
+  }
+  return PDMK_OK;
+}
+
+int pdmk_batch_status(pdmk_batch* B) {
+  if (!B) return fail(PDMK_ERR_INVALID_ARG, "null batch");
+  if (B->bound_off.empty()) return fail(PDMK_ERR_INVALID_ARG, "no bound trees (pdmk_batch_bind)");
+  const int n_sys = (int)B->plans.size();
+  int first = PDMK_OK;
+  std::string msg;
+  for (int sy = 0; sy < n_sys; ++sy) {
+    if (B->bound_off[sy + 1] == B->bound_off[sy]) continue;
+    const int st = pdmk_plan_status(B->plans[sy]);
+    if (st != PDMK_OK && first == PDMK_OK) {
+      first = st;
+      msg = g_last_error;
+    }
+  }
+  return first == PDMK_OK ? PDMK_OK : fail(first, msg);
+}
+
 void pdmk_batch_destroy(pdmk_batch* B) {
   if (!B) return;
+  for (hipEvent_t e : B->ev_join)
+    if (e) (void)hipEventDestroy(e);
+  if (B->ev_fork) (void)hipEventDestroy(B->ev_fork);
   for (pdmk_plan* P : B->plans) pdmk_plan_destroy(P);
   for (hipStream_t s : B->streams) (void)hipStreamDestroy(s);
   for (hipStream_t s : B->aux) (void)hipStreamDestroy(s);
@@ -1620,6 +1781,7 @@ int pdmk_batch_tune(pdmk_batch* B, const int64_t* offsets, const double* src, co
     if (offsets[sy + 1] < offsets[sy]) return fail(PDMK_ERR_INVALID_ARG, "offsets decrease");
   if (offsets[n_sys] > offsets[0] && (!src || !q))
     return fail(PDMK_ERR_INVALID_ARG, "null array");
+  B->bound_off.clear();   // re-planned systems keep no tree
   if (hipSetDevice(B->device) != hipSuccess) return fail(PDMK_ERR_HIP, "hipSetDevice failed");
   if (hipStreamSynchronize((hipStream_t)stream) != hipSuccess)
     return fail(PDMK_ERR_HIP, "stream synchronise failed");

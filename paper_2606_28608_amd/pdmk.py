@@ -123,6 +123,10 @@ def lib():
         L.pdmk_batch_destroy.argtypes = [_vp]
         L.pdmk_batch_destroy.restype = None
         L.pdmk_batch_stats.argtypes = [_vp, ctypes.c_int, ctypes.POINTER(Stats)]
+        L.pdmk_batch_bind.argtypes = [_vp, ctypes.POINTER(ctypes.c_int64), _vp, _vp, _vp, _vp,
+                                      _vp]
+        L.pdmk_batch_execute.argtypes = [_vp, _vp, _vp, _vp, _vp]
+        L.pdmk_batch_status.argtypes = [_vp]
         L.pdmk_batch_tune.argtypes = [_vp, ctypes.POINTER(ctypes.c_int64), _vp, _vp, ctypes.c_int,
                                       _dp, ctypes.POINTER(ctypes.c_int), ctypes.c_int, _vp, _dp,
                                       ctypes.POINTER(ctypes.c_int)]
@@ -562,6 +566,49 @@ class Batch:
         s = Stats()
         _check(lib().pdmk_batch_stats(self._h, int(sys), ctypes.byref(s)))
         return s.as_dict()
+
+    def bind(self, offsets, src, q):
+        """pdmk_batch_bind: one evaluation that keeps every system's tree;
+        returns the potentials (and gradients with grad=True)."""
+        import torch
+        off = np.ascontiguousarray(offsets, dtype=np.int64)
+        if off.shape != (self.n_sys + 1,):
+            raise ValueError("offsets must have n_sys + 1 entries")
+        src = _dev(src, torch)
+        q = _dev(q, torch)
+        n = src.shape[0]
+        if off[-1] != n or q.shape != (n,):
+            raise ValueError("offsets do not match the arrays")
+        pot = torch.empty(n, dtype=torch.float64, device=src.device)
+        grad = torch.empty((n, self.dim), dtype=torch.float64, device=src.device) \
+            if self.want_grad else None
+        vp = lambda t: ctypes.c_void_p(t.data_ptr()) if t is not None else None  # noqa: E731
+        _check(lib().pdmk_batch_bind(self._h, off.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                                     vp(src), vp(q), vp(pot), vp(grad), _stream(torch)))
+        self._bound_n = n
+        return (pot, grad) if self.want_grad else pot
+
+    def execute(self, q, out=None, grad_out=None):
+        """pdmk_batch_execute: new charges on the kept trees (enqueues only;
+        status() waits and reports device-detected input errors)."""
+        import torch
+        n = getattr(self, "_bound_n", None)
+        if n is None:
+            raise ValueError("bind() first")
+        q = _dev(q, torch)
+        if q.shape != (n,):
+            raise ValueError("q must have the bound size")
+        pot = torch.empty(n, dtype=torch.float64, device=q.device) if out is None else out
+        grad = None
+        if self.want_grad:
+            grad = torch.empty((n, self.dim), dtype=torch.float64, device=q.device) \
+                if grad_out is None else grad_out
+        vp = lambda t: ctypes.c_void_p(t.data_ptr()) if t is not None else None  # noqa: E731
+        _check(lib().pdmk_batch_execute(self._h, vp(q), vp(pot), vp(grad), _stream(torch)))
+        return (pot, grad) if self.want_grad else pot
+
+    def status(self):
+        _check(lib().pdmk_batch_status(self._h))
 
     def tune(self, offsets, src, q, candidates=None, trials=2):
         """Batch autotuner (pdmk_batch_tune): per size class floor(log2 n), times

@@ -162,3 +162,65 @@ def test_large_single_leaves_sampled(pdmk, torch_dev, precision):
     assert st["n_levels"] == 1 and st["n_leaves"] >= 1
     idx = np.random.default_rng(3).choice(len(q), 48, replace=False)
     assert ewald.rel_l2(pot[idx], ewald.ewald_sampled(L, src, q, idx)) <= 1e-6
+
+
+def test_batch_kept_trees_and_captured_graph(pdmk, torch_dev, systems):
+    """pdmk_batch_bind / pdmk_batch_execute: new charges on every system's
+    kept tree equal a fresh batch evaluation of them and the oracle; the
+    execute of the whole batch is captured into one graph and replayed three
+    times with new charges, eager work and synchronisations in between, each
+    replay equal to the eager execute."""
+    torch, dev = torch_dev
+    sy, refs = systems
+    Ls, offs, src, q = _pack(sy)
+    S = torch.tensor(src, device=dev)
+    B = pdmk.Batch(Ls, eps=1e-6, workers=3)
+    p0 = B.bind(offs, S, torch.tensor(q, device=dev)).cpu().numpy()
+    for s, ref in enumerate(refs):
+        assert ewald.rel_l2(p0[offs[s]:offs[s + 1]], ref) <= 1e-6
+    rng = np.random.default_rng(31)
+
+    def new_charges():
+        qn = rng.standard_normal(len(q))
+        for s in range(len(sy)):
+            qn[offs[s]:offs[s + 1]] -= qn[offs[s]:offs[s + 1]].mean()
+        return qn
+
+    q2 = new_charges()
+    got = B.execute(torch.tensor(q2, device=dev))
+    B.status()
+    fresh = B.eval(offs, S, torch.tensor(q2, device=dev)).cpu().numpy()
+    got = got.cpu().numpy()
+    assert ewald.rel_l2(got, fresh) <= 1e-12
+    for s in (0, 3):
+        ref = ewald.ewald(sy[s][0], sy[s][1], q2[offs[s]:offs[s + 1]])
+        assert ewald.rel_l2(got[offs[s]:offs[s + 1]], ref) <= 1e-6
+    # one graph for the whole batch
+    q_in = torch.tensor(q2, device=dev)
+    out = torch.empty(len(q), dtype=torch.float64, device=dev)
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        B.execute(q_in, out=out)
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, capture_error_mode="thread_local"):
+        B.execute(q_in, out=out)
+    for r in range(3):
+        qr = new_charges()
+        q_in.copy_(torch.tensor(qr, device=dev))
+        g.replay()
+        torch.cuda.synchronize()
+        replayed = out.clone()
+        eager = B.execute(torch.tensor(qr, device=dev))
+        B.status()
+        assert ewald.rel_l2(replayed.cpu().numpy(), eager.cpu().numpy()) <= 1e-12, r
+        _ = (eager * 2.0).sum().item()
+    # a bad charge is reported by the status and leaves the others' values
+    bad = new_charges()
+    bad[offs[2] + 1] = np.nan
+    B.execute(torch.tensor(bad, device=dev))
+    with pytest.raises(pdmk.PdmkError) as e:
+        B.status()
+    assert e.value.code == -5
