@@ -117,6 +117,14 @@ enum {
                                   forced splits until none is left.  The result is the
                                   same (the interaction rule is exact for any tree); the
                                   work moves from the residual sums to plane waves. */
+  PDMK_ALL_PAIRS = 256,        /* evaluate every residual pair from both ends.  By
+                                  default, when the targets are the sources and the
+                                  call asks for no gradients, is not deterministic
+                                  and keeps no tree, each pair of points in two
+                                  different leaves is evaluated once, since R_h
+                                  depends on |x - y| alone, and the result is added
+                                  to both points; this flag turns that off (for
+                                  comparing the two; the results agree to rounding) */
   PDMK_VIRTUAL_IMAGES = 64     /* the cube-cell construction of rem:cube for rectangular
                                   cells whose edges are whole multiples of
                                   r_c = L_min / kappa (a cube with integer kappa): the

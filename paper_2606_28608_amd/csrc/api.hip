@@ -455,7 +455,7 @@ static int validate_opts(const pdmk_opts* o) {
     return fail(PDMK_ERR_INVALID_ARG, "porder <= 40, npw <= 64, nufft_w <= 16, sigma <= 4");
   if (o->flags & ~(unsigned)(PDMK_WANT_GRAD | PDMK_ALLOW_NONNEUTRAL | PDMK_DETERMINISTIC |
                              PDMK_VECTOR_PLANE_WAVES | PDMK_ONE_STREAM | PDMK_BLOCH |
-                             PDMK_VIRTUAL_IMAGES | PDMK_BALANCE))
+                             PDMK_VIRTUAL_IMAGES | PDMK_BALANCE | PDMK_ALL_PAIRS))
     return fail(PDMK_ERR_INVALID_ARG, "unknown flag");
   if ((o->flags & PDMK_BLOCH) && (o->flags & PDMK_VIRTUAL_IMAGES))
     return fail(PDMK_ERR_UNSUPPORTED, "PDMK_BLOCH does not support PDMK_VIRTUAL_IMAGES");
@@ -796,6 +796,10 @@ static int eval_impl(pdmk_plan* P, int64_t n_src, const double* src, const doubl
       record(fev[2], aux);
     };
     if (!keep) far_fork();
+    // residual pairs evaluated once where the call allows it (a kept tree
+    // keeps both-way lists: a later execute may ask for gradients)
+    E.sym = self_t && !want_grad && !E.det && !keep && E.img_trg != nullptr &&
+            !(flags & PDMK_ALL_PAIRS);
     stage_tree(P, E);
     stage_lists(P, E);
     const size_t mark = ws.used;

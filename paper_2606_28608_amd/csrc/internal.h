@@ -185,6 +185,12 @@ struct Eval {
                             // ox is tx and oq follows tperm)
   bool timing = true;       // record per-stage events (off inside pdmk_plan_execute)
   bool det = false;         // PDMK_DETERMINISTIC
+  // residual pairs evaluated once (targets = sources): the lists of a leaf
+  // skip all-real boxes whose sources precede its own, and the residual sums
+  // add each pair to both ends.  img_trg: sorted image -> sorted target index
+  // of the point it is (-1 for a shifted copy)
+  bool sym = false;
+  int* img_trg = nullptr;
   std::vector<Level> lev;
   Level* d_lev = nullptr;   // device copy of lev (for list building)
   // target leaves

@@ -60,11 +60,22 @@ __device__ inline float log_r(float x) { return __logf(x); }
 template <class Real> struct SlotQ;
 template <> struct SlotQ<float> { using T = float4; };
 template <> struct SlotQ<double> { using T = double4; };
+// target of a staged slot, kept in the unused fourth component of its charge
+// vector (-1: none)
+__device__ inline int slot_tg(const float4& w) { return __float_as_int(w.w); }
+__device__ inline int slot_tg(const double4& w) { return (int)w.w; }
+__device__ inline void set_slot_tg(float4& w, int tg) { w.w = __int_as_float(tg); }
+__device__ inline void set_slot_tg(double4& w, int tg) { w.w = (double)tg; }
 
-template <int D, int NE, bool GRAD, class Real, int NR>
+// SYM: also the pair's term for the source end, q_t R (q_t = qa, the charge
+// of the target as a source), in *as (zero outside the support).
+template <int D, int NE, bool GRAD, class Real, int NR, bool SYM = false>
 __device__ inline void residual_pair(const double* x, const double4& sv,
                                      const typename SlotQ<Real>::T& sq, const Real* ec,
-                                     const Real* edc, Real& acc, Real* g, int& nin) {
+                                     const Real* edc, Real& acc, Real* g, int& nin,
+                                     Real qa = 0, Real* as = nullptr) {
+  static_assert(!(SYM && GRAD), "pairs evaluated once carry no gradients");
+  if (SYM) *as = 0;
   double dd[3];
   dd[0] = x[0] - sv.x;
   dd[1] = x[1] - sv.y;
@@ -98,7 +109,9 @@ __device__ inline void residual_pair(const double* x, const double4& sv,
     }
     if (D == 3) {
       const Real ir = rsqrt_r<NR>(r2);
-      acc = fma(qs, fma(-F, ih, ir), acc);
+      const Real rv = fma(-F, ih, ir);
+      acc = fma(qs, rv, acc);
+      if (SYM) *as = qa * rv;
       if (GRAD) {
         const Real dx[3] = {(Real)dd[0], (Real)dd[1], (Real)dd[2]};
         const Real f = qs * (-ir * ir * ir - ihh * Fd * ih);
@@ -106,7 +119,9 @@ __device__ inline void residual_pair(const double* x, const double4& sv,
       }
     } else {
       const Real sgr = (Real)0.5 * r2 * ihh;   // s = r^2 / h^2
-      acc = fma(qs, (Real)-0.5 * log_r(sgr) + F, acc);
+      const Real rv = (Real)-0.5 * log_r(sgr) + F;
+      acc = fma(qs, rv, acc);
+      if (SYM) *as = qa * rv;
       if (GRAD) {
         const Real dx[3] = {(Real)dd[0], (Real)dd[1], (Real)0};
         const Real f = qs * (-(Real)1 / r2 + ihh * Fd);
@@ -145,20 +160,42 @@ struct ListCursor {
   __device__ bool valid() const { return ee < le && rem > 0; }
 };
 
+// Pairs evaluated once (targets = sources): the target leaf's own source
+// range [sb, se) and the map from sorted images to sorted targets.
+struct SymInfo {
+  const int* itrg;
+  int sb, se;
+};
+
 template <class Real>
 struct SourceSlot {
   double4 v;                   // (offset, h^2)
   typename SlotQ<Real>::T w;   // (q, 1/h, 2/h^2, 0)
+  int tg;                      // SYM: target that also receives the pair (-1: none)
   bool live;                   // within h + rho of the pass's target centre
   // Source offset from the target leaf centre (formed in FP64) with the support
   // h^2 of its residual level in v.w, and (q, 1/h, 2/h^2); slots past the list
   // end never interact (h^2 = 0).  live: the source can reach a target of the
   // pass, whose targets lie within rho of cc (|y - cc| < h + rho).
+  // SYM: an unshifted source that is a target of a later leaf (in source
+  // order) receives the pair's term too (tg); one of an earlier leaf is
+  // dropped (that leaf adds the pair to both ends); shifted copies and the
+  // leaf's own sources are summed one way.
+  template <bool SYM>
   __device__ void fetch(const ListCursor& c, const KParams& kp, const double* __restrict__ sx,
                         const double* __restrict__ sq, int64_t nimg, const double* cT, int D,
-                        const double* cc, double rho) {
+                        const double* cc, double rho, const SymInfo& si) {
+    tg = -1;
     if (c.valid()) {
       const int sidx = c.en.x + c.oo;
+      bool drop = false;
+      if (SYM && c.en.w == 0) {
+        const int it = si.itrg[sidx];
+        if (it >= 0) {
+          if (sidx < si.sb) drop = true;
+          else if (sidx >= si.se) tg = it;
+        }
+      }
       v.x = sx[sidx] - cT[0];
       v.y = sx[nimg + sidx] - cT[1];
       v.z = D == 3 ? sx[2 * nimg + sidx] - cT[2] : 0.0;
@@ -182,10 +219,10 @@ struct SourceSlot {
       w.x = (Real)sq[sidx];
       w.y = (Real)ih;
       w.z = (Real)(2.0 * ih * ih);
-      w.w = 0;
+      set_slot_tg(w, tg);
       const double dx = v.x - cc[0], dy = v.y - cc[1], dz = v.z - cc[2];
       const double reach = hh + rho;
-      live = fma(dx, dx, fma(dy, dy, dz * dz)) < reach * reach * (1.0 + 1e-12);
+      live = !drop && fma(dx, dx, fma(dy, dy, dz * dz)) < reach * reach * (1.0 + 1e-12);
     } else {
       dead();
     }
@@ -196,10 +233,77 @@ struct SourceSlot {
     w.x = 0;
     w.y = 1;
     w.z = 2;
-    w.w = 0;
+    set_slot_tg(w, -1);
+    tg = -1;
     live = false;
   }
 };
+
+// Source ends of the pairs evaluated once: each pair's term q_t R goes to a
+// row of RB slots x 64 lanes in LDS; after every RB slots of a tile, lane l
+// adds the terms of slot l / LP from LP-th of the lanes (only the lanes whose
+// targets meet that slot: lane % S == slot % S), LP lanes combine theirs, and
+// one FP64 atomic per slot adds the sum to its target.
+// FP64 rows padded to 68 entries (the flush's 16-byte reads of the RB rows
+// fall on distinct banks); FP32 rows unpadded, so that the ring fits beside
+// the staging slots at four waves per SIMD (its reads then share banks:
+// measured faster than the padded ring at 3.75 waves).
+template <class Real>
+struct SymRing {
+  static constexpr int RB = sizeof(Real) == 4 ? 16 : 8;   // slots per block
+  static constexpr int LP = 64 / RB;                       // lanes per slot
+  static constexpr int ROW = sizeof(Real) == 4 ? 64 : 68;
+  static constexpr int SIZE = RB * ROW;
+  __device__ static int at(int r, int col) { return r * ROW + col; }
+};
+
+// Data-parallel-primitive lane exchange (no LDS round trip): CTRL 0xB1 swaps
+// neighbouring lanes (quad pattern 1,0,3,2), 0x4E lanes two apart (2,3,0,1),
+// 0x141 mirrors each group of eight lanes.
+template <int CTRL>
+__device__ inline float dpp_x(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+template <int CTRL>
+__device__ inline double dpp_x(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffll), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, false);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
+template <class Real, int S>
+__device__ inline void sym_flush(const Real* red, const typename SlotQ<Real>::T* shw, int slot0,
+                                 double* __restrict__ pot, double cst) {
+  using SR = SymRing<Real>;
+  constexpr int PER = 64 / SR::LP;   // row entries per lane
+  static_assert(PER % S == 0, "a lane's entries start at a multiple of S");
+  static_assert(SR::LP == 4 || SR::LP == 8, "lanes of a slot: a quad or half a row");
+  // the block is one wave and a wave's LDS operations complete in order: the
+  // reads below see the block's writes; only the compiler must keep the order
+  asm volatile("" ::: "memory");
+  const int lane = threadIdx.x;
+  const int j = lane / SR::LP, part = lane % SR::LP;
+  const int tg = slot_tg(shw[slot0 + j]);   // read with the row entries
+  Real sum = 0;
+  if constexpr (S == 1) {
+    Real s2 = 0;   // two chains of adds
+#pragma unroll
+    for (int i = 0; i < PER; i += 2) {
+      sum += red[SR::at(j, part * PER + i)];
+      s2 += red[SR::at(j, part * PER + i + 1)];
+    }
+    sum += s2;
+  } else {
+    const int i0 = j % S;
+#pragma unroll
+    for (int u = 0; u < PER / S; ++u) sum += red[SR::at(j, part * PER + i0 + u * S)];
+  }
+  sum += dpp_x<0xB1>(sum);
+  sum += dpp_x<0x4E>(sum);
+  if constexpr (SR::LP == 8) sum += dpp_x<0x141>(sum);
+  if (part == 0 && tg >= 0) atomicAdd(&pot[tg], (double)sum * cst);
+}
 
 // One pass of a leaf's residual sums: 64 / S targets, S lanes per target,
 // over the source list of the work item.  The lanes fetch 64 candidate
@@ -210,20 +314,23 @@ struct SourceSlot {
 // and prefix count).  Every 64 staged sources form a tile summed by all
 // lanes; the last tile is padded with slots that never interact.  nlive
 // counts the staged sources (the same on every lane).
-template <int D, int NE, int S, bool GRAD, class Real, int NR>
+// SYM: pairs evaluated once; qa is the lane's target charge, red the
+// source-end ring (see sym_flush; the staged slots carry their targets).
+template <int D, int NE, int S, bool GRAD, class Real, int NR, bool SYM>
 __device__ void direct_pass(const KParams& kp, const int4* __restrict__ list, int lb, int le,
                             int pos0, int pos1, const double* __restrict__ sx,
                             const double* __restrict__ sq,
                             int64_t nimg, const double* cT, const double* x, const Real* ec,
                             const Real* edc, const double* cc, double rho, double4* shv,
                             typename SlotQ<Real>::T* shw, double& acc, double* g, int& nin,
-                            int& nlive) {
+                            int& nlive, const SymInfo& si, Real qa, Real* red,
+                            double* __restrict__ pot, double cst) {
   const int lane = threadIdx.x;
   const int slice = lane % S;
   ListCursor cur;
   cur.init(list, lb, le, pos0 + lane, pos1);
   SourceSlot<Real> nxt;
-  nxt.fetch(cur, kp, sx, sq, nimg, cT, D, cc, rho);
+  nxt.template fetch<SYM>(cur, kp, sx, sq, nimg, cT, D, cc, rho, si);
   // all lanes of the wave are active here, so the first active lane is lane 0
   bool more = __builtin_amdgcn_readfirstlane(cur.valid() ? 1 : 0) != 0;
   int head = 0, fill = 0;   // staged sources: ring slots [head, head + fill) mod 128
@@ -241,7 +348,7 @@ __device__ void direct_pass(const KParams& kp, const int4* __restrict__ list, in
       fill += nm;
       nlive += nm;
       cur.advance(list);
-      nxt.fetch(cur, kp, sx, sq, nimg, cT, D, cc, rho);
+      nxt.template fetch<SYM>(cur, kp, sx, sq, nimg, cT, D, cc, rho, si);
       more = __builtin_amdgcn_readfirstlane(cur.valid() ? 1 : 0) != 0;
       if (fill < 64 && more) continue;
     }
@@ -257,7 +364,25 @@ __device__ void direct_pass(const KParams& kp, const int4* __restrict__ list, in
     Real ta = 0, tb = 0, ga[3] = {0, 0, 0}, gb[3] = {0, 0, 0};
     const double4* tv = shv + base;
     const typename SlotQ<Real>::T* tw = shw + base;
-    if constexpr (S == 1) {
+    if constexpr (SYM) {
+      // blocks of RB slots; the lane's slots of a block are u S + slice
+      using SR = SymRing<Real>;
+      constexpr int RB = SR::RB;
+      static_assert(RB % S == 0, "a block holds whole rounds of the S lanes of a target");
+#pragma unroll
+      for (int b0 = 0; b0 < 64; b0 += RB) {
+#pragma unroll
+        for (int u = 0; u < RB / S; ++u) {
+          const int r = u * S + slice;   // row in the block (static when S = 1)
+          Real as;
+          residual_pair<D, NE, false, Real, NR, true>(x, tv[b0 + r], tw[b0 + r], ec, edc,
+                                                      (u & 1) ? tb : ta, ga, nin, qa, &as);
+          red[SR::at(r, lane)] = as;
+        }
+        sym_flush<Real, S>(red, shw, base + b0, pot, cst);
+        asm volatile("" ::: "memory");   // the block's reads precede the next writes
+      }
+    } else if constexpr (S == 1) {
       // one lane per target: the whole tile unrolled (LDS reads at immediate offsets)
 #pragma unroll
       for (int k = 0; k < 64; k += 2) {
@@ -296,19 +421,30 @@ __device__ void direct_pass(const KParams& kp, const int4* __restrict__ list, in
 // Positions are offsets from the target leaf's centre in FP64; Real = double:
 // FP64 throughout; Real = float: the series, rsqrt and the sums over one tile
 // of 64 sources in FP32, FP64 across tiles.
-template <int D, int NE, bool GRAD, class Real, int NR>
-__global__ __launch_bounds__(64) void k_direct(
-    KParams kp, int nitems, const int2* __restrict__ items, const int* __restrict__ lf_nsrc,
-    const Level* __restrict__ lev, const int* __restrict__ lf_level,
-    const int* __restrict__ lf_box, const int* __restrict__ lbeg, const int4* __restrict__ list,
-    const double* __restrict__ sx, const double* __restrict__ sq, int64_t nimg,
-    const double* __restrict__ tx, int64_t ntrg, const int* __restrict__ tperm,
-    const double* __restrict__ qorig, int self_targets, const double* __restrict__ Ec,
-    const double* __restrict__ Edc, double* __restrict__ pot, double* __restrict__ grad,
-    unsigned long long* __restrict__ n_support, double* __restrict__ part,
-    double* __restrict__ gpart, const int* __restrict__ item_beg) {
+// SYM (targets = sources, no gradients, atomic mode; the lists skip the
+// boxes whose pairs the later leaves evaluate): every pair of points in
+// different leaves is evaluated once, its term q_s R added to the target and
+// q_t R to the source's own target entry (itrg), oq holding the targets'
+// charges in sorted order.
+#define PDMK_DIRECT_PARAMS                                                                   \
+    KParams kp, int nitems, const int2 *__restrict__ items, const int *__restrict__ lf_nsrc,    \
+    const Level *__restrict__ lev, const int *__restrict__ lf_level,                            \
+    const int *__restrict__ lf_box, const int *__restrict__ lbeg, const int4 *__restrict__ list, \
+    const double *__restrict__ sx, const double *__restrict__ sq, int64_t nimg,                 \
+    const double *__restrict__ tx, int64_t ntrg, const int *__restrict__ tperm,                 \
+    const double *__restrict__ qorig, int self_targets, const double *__restrict__ Ec,          \
+    const double *__restrict__ Edc, double *__restrict__ pot, double *__restrict__ grad,        \
+    unsigned long long *__restrict__ n_support, double *__restrict__ part,                      \
+    double *__restrict__ gpart, const int *__restrict__ item_beg, const int *__restrict__ itrg, \
+    const double *__restrict__ oq
+#define PDMK_DIRECT_ARGS                                                                      \
+  kp, nitems, items, lf_nsrc, lev, lf_level, lf_box, lbeg, list, sx, sq, nimg, tx, ntrg, tperm, \
+      qorig, self_targets, Ec, Edc, pot, grad, n_support, part, gpart, item_beg, itrg, oq
+template <int D, int NE, bool GRAD, class Real, int NR, bool SYM>
+__device__ __forceinline__ void direct_body(PDMK_DIRECT_PARAMS) {
   __shared__ double4 shv[128];
   __shared__ typename SlotQ<Real>::T shw[128];
+  __shared__ Real red[SYM ? SymRing<Real>::SIZE : 1];
   if ((int)blockIdx.x >= nitems) return;
   const int2 item = items[blockIdx.x];
   const int i = item.x;
@@ -331,6 +467,12 @@ __global__ __launch_bounds__(64) void k_direct(
   const int te = min(T.tend[b], tb + kDirectTgt);
   const int lb = lbeg[i], le = lbeg[i + 1];
   const double hT = kp.rc / (double)(1 << lvl);
+  SymInfo si{itrg, 0, 0};
+  if (SYM) {
+    si.sb = T.sbeg[b];
+    si.se = T.send[b];
+  }
+  const double cst = D == 3 ? kInv4Pi : kInv2Pi;
   double cT[3] = {0, 0, 0};
   for (int a = 0; a < D; ++a) cT[a] = kp.origin[a] + (T.coord[b * D + a] + 0.5) * hT;
   int nin = 0;
@@ -360,28 +502,32 @@ __global__ __launch_bounds__(64) void k_direct(
     const double rho = sqrt(rho2);
     double acc = 0.0, g[3] = {0, 0, 0};
     int nin_p = 0, nlive = 0;
+    const Real qa = (SYM && valid) ? (Real)oq[t] : (Real)0;
     switch (S) {
       case 1:
-        direct_pass<D, NE, 1, GRAD, Real, NR>(kp, list, lb, le, pos0, pos1, sx, sq, nimg, cT, x,
-                                          ec, edc, cc, rho, shv, shw, acc, g, nin_p, nlive);
+        direct_pass<D, NE, 1, GRAD, Real, NR, SYM>(kp, list, lb, le, pos0, pos1, sx, sq, nimg,
+                                                   cT, x, ec, edc, cc, rho, shv, shw, acc, g,
+                                                   nin_p, nlive, si, qa, red, pot, cst);
         break;
       case 2:
-        direct_pass<D, NE, 2, GRAD, Real, NR>(kp, list, lb, le, pos0, pos1, sx, sq, nimg, cT, x,
-                                          ec, edc, cc, rho, shv, shw, acc, g, nin_p, nlive);
+        direct_pass<D, NE, 2, GRAD, Real, NR, SYM>(kp, list, lb, le, pos0, pos1, sx, sq, nimg,
+                                                   cT, x, ec, edc, cc, rho, shv, shw, acc, g,
+                                                   nin_p, nlive, si, qa, red, pot, cst);
         break;
       case 4:
-        direct_pass<D, NE, 4, GRAD, Real, NR>(kp, list, lb, le, pos0, pos1, sx, sq, nimg, cT, x,
-                                          ec, edc, cc, rho, shv, shw, acc, g, nin_p, nlive);
+        direct_pass<D, NE, 4, GRAD, Real, NR, SYM>(kp, list, lb, le, pos0, pos1, sx, sq, nimg,
+                                                   cT, x, ec, edc, cc, rho, shv, shw, acc, g,
+                                                   nin_p, nlive, si, qa, red, pot, cst);
         break;
       default:
-        direct_pass<D, NE, 8, GRAD, Real, NR>(kp, list, lb, le, pos0, pos1, sx, sq, nimg, cT, x,
-                                          ec, edc, cc, rho, shv, shw, acc, g, nin_p, nlive);
+        direct_pass<D, NE, 8, GRAD, Real, NR, SYM>(kp, list, lb, le, pos0, pos1, sx, sq, nimg,
+                                                   cT, x, ec, edc, cc, rho, shv, shw, acc, g,
+                                                   nin_p, nlive, si, qa, red, pot, cst);
         break;
     }
     nin += nin_p;   // the same wave-wide count on every lane
     nstaged += (long long)nlive * ((te - t0 < 64 / S) ? te - t0 : 64 / S);
     if (valid && lane % S == 0) {
-      const double cst = D == 3 ? kInv4Pi : kInv2Pi;
       double v = acc * cst;
       if (self_targets && seg == 0) {
         const double w0 = D == 3 ? kp.w0unit / hT : kp.w0unit - log(hT) * kInv2Pi;
@@ -406,6 +552,18 @@ __global__ __launch_bounds__(64) void k_direct(
     atomicAdd(n_support, (unsigned long long)nin);
     atomicAdd(n_support + 1, (unsigned long long)nstaged);
   }
+}
+
+template <int D, int NE, bool GRAD, class Real, int NR, bool SYM>
+__global__ __launch_bounds__(64) void k_direct(PDMK_DIRECT_PARAMS) {
+  direct_body<D, NE, GRAD, Real, NR, SYM>(PDMK_DIRECT_ARGS);
+}
+// The FP32 pairs-once variant held to 128 registers (four waves per SIMD:
+// measured faster than three without spills; FP64 is faster uncapped).
+template <int D, int NE, bool GRAD, class Real, int NR, bool SYM>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_direct_w4(
+    PDMK_DIRECT_PARAMS) {
+  direct_body<D, NE, GRAD, Real, NR, SYM>(PDMK_DIRECT_ARGS);
 }
 
 // Fixed-order completion of the residual sums: one block per work item in
@@ -1169,7 +1327,7 @@ static void launch_direct_t(const KParams& kp, Eval& E, pdmk_plan* P, hipStream_
     hipLaunchKernelGGL(kern, dim3(E.nitems), dim3(64), 0, s, kp, E.nitems, E.items, E.lf_nsrc,
                        E.d_lev, E.lf_level, E.lf_box, E.lf_list_beg, E.list, E.sx, E.sq, E.n_img,
                        E.tx, E.n_trg, E.tperm, E.q, E.self_targets ? 1 : 0, c, cd, E.pot_sorted,
-                       E.grad_sorted, nsup, part, gpart, E.item_beg);
+                       E.grad_sorted, nsup, part, gpart, E.item_beg, E.img_trg, E.oq);
     if (E.det) {
       if (want_grad)
         hipLaunchKernelGGL((k_direct_reduce<D, true>), dim3(E.nitems), dim3(64), 0, s,
@@ -1183,15 +1341,21 @@ static void launch_direct_t(const KParams& kp, Eval& E, pdmk_plan* P, hipStream_
   };
   // FP64 3D: one Newton step of the reciprocal square root where eps >= 1e-10
   // (its error, below 1e-14, is then far under the tolerance), two below
+  // pairs evaluated once: only where the lists were built for it
+  if (E.sym && (want_grad || E.det || !E.img_trg))
+    throw Error{PDMK_ERR_UNSUPPORTED, "symmetric residual lists without their evaluation"};
   if constexpr (D == 3 && sizeof(Real) == 8) {
     if (P->o.eps >= 1e-10) {
-      if (want_grad) go(k_direct<D, NE, true, Real, 1>);
-      else go(k_direct<D, NE, false, Real, 1>);
+      if (want_grad) go(k_direct<D, NE, true, Real, 1, false>);
+      else if (E.sym) go(k_direct<D, NE, false, Real, 1, true>);
+      else go(k_direct<D, NE, false, Real, 1, false>);
       return;
     }
   }
-  if (want_grad) go(k_direct<D, NE, true, Real, 2>);
-  else go(k_direct<D, NE, false, Real, 2>);
+  if (want_grad) go(k_direct<D, NE, true, Real, 2, false>);
+  else if (E.sym && sizeof(Real) == 4) go(k_direct_w4<D, NE, false, Real, 2, true>);
+  else if (E.sym) go(k_direct<D, NE, false, Real, 2, true>);
+  else go(k_direct<D, NE, false, Real, 2, false>);
 }
 
 template <int D, class Real>

@@ -256,16 +256,19 @@ __global__ void k_orig_flag(int64_t nimg, const int* __restrict__ perm,
   osrc[p] = s;
   flag[p] = s >= 0 ? 1 : 0;
 }
-// Also the charges of the sorted originals (oq) from the sorted image charges.
+// Also the charges of the sorted originals (oq) from the sorted image charges,
+// and itrg[p]: the sorted target that sorted image p is (-1: a shifted copy).
 __global__ void k_orig_pick(int64_t nimg, int64_t n, int d, const int* __restrict__ osrc,
                             const int* __restrict__ pos, const uint64_t* __restrict__ skey,
                             const double* __restrict__ sx, const double* __restrict__ sq,
                             uint64_t* __restrict__ tkey, double* __restrict__ tx,
                             int* __restrict__ tperm, double* __restrict__ oq,
-                            const double* __restrict__ sq_im, double* __restrict__ oq_im) {
+                            const double* __restrict__ sq_im, double* __restrict__ oq_im,
+                            int* __restrict__ itrg) {
   int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= nimg) return;
   const int src = osrc[p];
+  itrg[p] = src >= 0 ? pos[p] : -1;
   if (src < 0) return;
   const int t = pos[p];
   tperm[t] = src;
@@ -452,13 +455,14 @@ void stage_images(pdmk_plan* P, Eval& E, const double* q) {
     int* flag = E.alloc<int>(E.n_img + 1);
     int* pos = E.alloc<int>(E.n_img + 1);
     int* osrc = E.alloc<int>(E.n_img + 1);
+    E.img_trg = E.alloc<int>(E.n_img + 1);
     if (E.n_img > 0) {
       hipLaunchKernelGGL(k_orig_flag, dim3(nblk(E.n_img, 256)), dim3(256), 0, E.s, E.n_img,
                          perm, isrc, flag, osrc);
       exclusive_scan_int(flag, pos, (int)E.n_img, E);
       hipLaunchKernelGGL(k_orig_pick, dim3(nblk(E.n_img, 256)), dim3(256), 0, E.s, E.n_img,
                          E.n_trg, kp.dim, osrc, pos, E.skey, E.sx, E.sq, E.tkey, E.tx, E.tperm,
-                         E.oq, E.sq_im, E.oq_im);
+                         E.oq, E.sq_im, E.oq_im, E.img_trg);
     }
     return;   // original sources in tree order: the picked copies
   } else {
@@ -808,11 +812,17 @@ static void build_tree(pdmk_plan* P, Eval& E, const uint64_t* fkey, const int* f
 //       without children: all sources of D, residual R_j.
 // Mode 0 counts entries (and direct pairs), mode 1 writes them.  Slots of
 // boxes that are not target leaves get no entries.
+// The rule is symmetric: a point pair (x in T, y in S) meets in T's list
+// through an entry holding S's box and in S's list through one holding T's
+// box, with the same level.  sym (targets = sources, pairs evaluated once):
+// an unshifted entry whose box precedes T in source order and holds only
+// points of the cell (no shifted copies: as many sources as targets) is left
+// out, since the leaves after it add its pairs to both ends.
 __global__ void k_leaf_lists(int d, int nleaf, const Level* __restrict__ lev,
                              const int* __restrict__ lf_level, const int* __restrict__ lf_box,
                              int* __restrict__ cnt, const int* __restrict__ beg,
                              int4* __restrict__ list, unsigned long long* __restrict__ pairs,
-                             int* __restrict__ nsrc) {
+                             int* __restrict__ nsrc, int sym) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= nleaf) return;
   const int ncoll = d == 3 ? 27 : 9;
@@ -829,13 +839,16 @@ __global__ void k_leaf_lists(int d, int nleaf, const Level* __restrict__ lev,
   int k = 0;
   long long np = 0;
   int o = beg ? beg[i] : 0;
+  const int tsb = T.sbeg[b];
   // .w of an entry: the shift_code of a virtual image's colleague (0: none)
   for (int sl = 0; sl < ncoll; ++sl) {
     int c = T.coll[b * ncoll + sl];
     if (c < 0) continue;
     int sb = T.sbeg[c], se = T.send[c];
     if (se <= sb) continue;
-    if (list) list[o + k] = make_int4(sb, se, lvl, T.cshift ? T.cshift[b * ncoll + sl] : 0);
+    const int sh = T.cshift ? T.cshift[b * ncoll + sl] : 0;
+    if (sym && sh == 0 && se <= tsb && se - sb == T.tend[c] - T.tbeg[c]) continue;
+    if (list) list[o + k] = make_int4(sb, se, lvl, sh);
     ++k;
     np += se - sb;
   }
@@ -847,7 +860,9 @@ __global__ void k_leaf_lists(int d, int nleaf, const Level* __restrict__ lev,
       if (D < 0 || A.child0[D] >= 0) continue;
       int sb = A.sbeg[D], se = A.send[D];
       if (se <= sb) continue;
-      if (list) list[o + k] = make_int4(sb, se, l, A.cshift ? A.cshift[a * ncoll + sl] : 0);
+      const int sh = A.cshift ? A.cshift[a * ncoll + sl] : 0;
+      if (sym && sh == 0 && se <= tsb && se - sb == A.tend[D] - A.tbeg[D]) continue;
+      if (list) list[o + k] = make_int4(sb, se, l, sh);
       ++k;
       np += se - sb;
     }
@@ -938,7 +953,7 @@ void stage_lists(pdmk_plan* P, Eval& E) {
   if (n > 0) {
     hipLaunchKernelGGL(k_leaf_lists, dim3(nblk(n, 128)), dim3(128), 0, E.s, d, n, E.d_lev,
                        E.lf_level, E.lf_box, cnt, (const int*)nullptr, (int4*)nullptr, pairs,
-                       E.lf_nsrc);
+                       E.lf_nsrc, E.sym ? 1 : 0);
     // work items of the residual sums: segments of each leaf's source list
     hipLaunchKernelGGL(k_seg_count, dim3(nblk(n, 256)), dim3(256), 0, E.s, n, E.d_lev, E.lf_level,
                        E.lf_box, E.lf_nsrc, segs);
@@ -978,7 +993,7 @@ void stage_lists(pdmk_plan* P, Eval& E) {
   if (n > 0 && E.nlist > 0)
     hipLaunchKernelGGL(k_leaf_lists, dim3(nblk(n, 128)), dim3(128), 0, E.s, d, n, E.d_lev,
                        E.lf_level, E.lf_box, (int*)nullptr, E.lf_list_beg, E.list,
-                       (unsigned long long*)nullptr, (int*)nullptr);
+                       (unsigned long long*)nullptr, (int*)nullptr, E.sym ? 1 : 0);
 }
 
 }  // namespace pdmk

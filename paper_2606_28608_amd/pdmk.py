@@ -29,6 +29,7 @@ PDMK_ONE_STREAM = 16
 PDMK_BLOCH = 32
 PDMK_VIRTUAL_IMAGES = 64
 PDMK_BALANCE = 128
+PDMK_ALL_PAIRS = 256
 PDMK_FP32_RESIDUAL = 1
 PDMK_FP32_PROXY = 2
 PDMK_FP32_WINDOW = 4
@@ -171,10 +172,11 @@ def _check(code):
 
 def default_opts(dim, eps, precision="fp64", grad=False, allow_nonneutral=False,
                  deterministic=False, vector_plane_waves=False, one_stream=False, bloch=None,
-                 virtual_images=False, balance=False, **over):
+                 virtual_images=False, balance=False, all_pairs=False, **over):
     """pdmk_opts for (dim, eps) with the defaults of pdmk_default_opts; keyword
     arguments set flags (grad, allow_nonneutral, deterministic,
-    vector_plane_waves, one_stream, bloch = Bloch vector, virtual_images, balance) or
+    vector_plane_waves, one_stream, bloch = Bloch vector, virtual_images, balance,
+    all_pairs) or
     override fields (kappa, n_s, porder, npw, nufft_w,
     sigma, fp32_stages)."""
     o = Opts()
@@ -188,7 +190,8 @@ def default_opts(dim, eps, precision="fp64", grad=False, allow_nonneutral=False,
                | (PDMK_ONE_STREAM if one_stream else 0)
                | (PDMK_BLOCH if bloch is not None else 0)
                | (PDMK_VIRTUAL_IMAGES if virtual_images else 0)
-               | (PDMK_BALANCE if balance else 0))
+               | (PDMK_BALANCE if balance else 0)
+               | (PDMK_ALL_PAIRS if all_pairs else 0))
     if bloch is not None:
         b = [float(v) for v in bloch]
         if len(b) != dim:

@@ -48,7 +48,7 @@ def test_default_opts_and_validation(lib):
 def test_unknown_flags_and_stage_bits_rejected(lib):
     L = workloads.TRICLINIC3D_L
     pdmk.geometry(L, eps=1e-6, deterministic=True, vector_plane_waves=True, fp32_stages=15)
-    for over in (dict(flags=256), dict(fp32_stages=16)):
+    for over in (dict(flags=512), dict(fp32_stages=16)):
         with pytest.raises(pdmk.PdmkError) as e:
             pdmk.geometry(L, eps=1e-6, **over)
         assert e.value.code == -1
