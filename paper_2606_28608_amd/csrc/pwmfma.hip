@@ -1058,15 +1058,203 @@ __global__ __launch_bounds__(256, sizeof(Real) == 4 ? 3 : 1) void k_anterp_mfma(
   }
 }
 
+// Row tiles of the proxy-charge product with compile-time (i0, i1): the
+// P^2 rows (i0, i1) of Q are cut into "full" tiles (one i0, i1 = 16 b .. 16 b
+// + 15) and, for the last P % 16 values of i1, "pair" tiles (i0 = 2u and
+// 2u + 1 with eight i1 each, when P % 16 <= 8) or "single" tiles (one i0,
+// sixteen i1, when P % 16 > 8).  Wave w of the block owns tiles w, w + 4,
+// ...; with w a template parameter each tile's i0 is a constant, so the A
+// operand of a k-step (source s, row i0 i1) is q_s l_i0(s) taken from a
+// register row times l_i1(s), one product per tile.
+template <int P>
+struct AnterpTiles {
+  static constexpr int A = P / 16, R = P % 16;
+  static constexpr bool PAIR = R > 0 && R <= 8;
+  static constexpr int NTA = P * A;
+  static constexpr int NTB = R == 0 ? 0 : (PAIR ? (P + 1) / 2 : P);
+  static constexpr int NTILE = NTA + NTB;
+  static constexpr int MW = (NTILE + 3) / 4;   // tile slots per wave
+  static constexpr int NT = (P + 15) / 16;     // column tiles (i2)
+  // row stride of the Lagrange rows: holds index P (zero, the missing
+  // partner of an odd pair) and, for single tiles, 16 (A + 1) entries
+  static constexpr int SL0 = ((P + 1 + 3) / 4) * 4;
+  static constexpr int SL = (R > 8 && 16 * (A + 1) > SL0) ? 16 * (A + 1) : SL0;
+  // B operand row stride: the four sources of a k-step start 16 banks apart
+  static constexpr int NWP = NT % 2 ? 16 * NT : 16 * NT + 16;
+  static constexpr int CH = 64;                // sources per chunk
+  // i0 of a tile for lanes li < 8 (lo) and li >= 8 (hi); first i1 and
+  // whether i1 advances with li (full, single) or with li & 7 (pair)
+  __host__ __device__ static constexpr int i0lo(int t) {
+    return t < NTA ? t / A : (PAIR ? 2 * (t - NTA) : t - NTA);
+  }
+  __host__ __device__ static constexpr int i0hi(int t) {
+    return t < NTA ? t / A : (PAIR ? 2 * (t - NTA) + 1 : t - NTA);
+  }
+  __host__ __device__ static constexpr int i1b(int t) { return t < NTA ? 16 * (t % A) : 16 * A; }
+  __host__ __device__ static constexpr bool paired(int t) { return t >= NTA && PAIR; }
+};
+
+template <class Real, int P, int W>
+__device__ __forceinline__ void anterp_rows_wave(const KParams& kp, const Level& L, int b,
+                                                 int total, const int* cb, const int* cpre,
+                                                 double h, const double* __restrict__ sx,
+                                                 const double* __restrict__ sq, int64_t nimg,
+                                                 const double* __restrict__ nodes,
+                                                 const double* __restrict__ bw, Real* qLx,
+                                                 Real* Ly, Real* Lz, Real* __restrict__ out) {
+  using TT = AnterpTiles<P>;
+  using MF = Mfma<Real>;
+  using V = typename MF::V;
+  constexpr int SL = TT::SL, NWP = TT::NWP, CH = TT::CH, MW = TT::MW, NT = TT::NT;
+  const double sc = 2.0 / h;
+  const int lane = threadIdx.x & 63;
+  const int li = lane & 15, lk = lane >> 4;
+  const bool hi = li >= 8;
+  V acc[MW][NT];
+#pragma unroll
+  for (int i = 0; i < MW; ++i)
+#pragma unroll
+    for (int n = 0; n < NT; ++n) acc[i][n] = V{0, 0, 0, 0};
+  for (int s0 = 0; s0 < total; s0 += CH) {
+    // Lagrange rows of the chunk: thread (source, axis)
+    if (threadIdx.x < 3 * CH) {
+      const int si = threadIdx.x / 3, a = threadIdx.x - 3 * si;
+      const int j = s0 + si;
+      const bool valid = j < total;
+      int sidx = 0;
+      if (valid) {
+        int o = 0;
+        while (o < 7 && cpre[o + 1] <= j) ++o;
+        sidx = cb[o] + (j - cpre[o]);
+      }
+      const double cen = kp.origin[a] + (L.coord[b * 3 + a] + 0.5) * h;
+      const double xi = valid ? (sx[a * nimg + sidx] - cen) * sc : 0.0;
+      const double qs = (valid && a == 0) ? sq[sidx] : 1.0;
+      double rl[P], dl[P];
+      lagrange_rows_reg<P, false, sizeof(Real) == 4 ? 1 : 2>(P, nodes, bw, xi, rl, dl);
+#pragma unroll
+      for (int i = 0; i < P; ++i) {
+        const Real v = valid ? (Real)(a == 0 ? qs * rl[i] : rl[i]) : (Real)0;
+        if (a == 0) qLx[si * SL + i] = v;
+        else if (a == 1) Ly[si * SL + i] = v;
+        else Lz[si * NWP + i] = v;
+      }
+    }
+    __syncthreads();
+#pragma unroll 2
+    for (int st = 0; st < CH / 4; ++st) {
+      const int si = 4 * st + lk;
+      Real bz[NT];
+#pragma unroll
+      for (int n = 0; n < NT; ++n) bz[n] = Lz[si * NWP + 16 * n + li];
+      // the source's row q l_i0 (every i0; broadcast within 16 lanes)
+      Real qx[SL];
+#pragma unroll
+      for (int i = 0; i < SL; ++i) qx[i] = qLx[si * SL + i];
+      Real ly[TT::A + 1];
+#pragma unroll
+      for (int c = 0; c < TT::A; ++c) ly[c] = Ly[si * SL + 16 * c + li];
+      if constexpr (TT::R > 0) ly[TT::A] = Ly[si * SL + 16 * TT::A + (TT::PAIR ? (li & 7) : li)];
+#pragma unroll
+      for (int i = 0; i < MW; ++i) {
+        const int t = W + 4 * i;
+        if (t < TT::NTILE) {
+          const int c = t < TT::NTA ? t % TT::A : TT::A;
+          const Real q0 = qx[TT::i0lo(t)];
+          const Real qsel = TT::paired(t) ? (hi ? qx[TT::i0hi(t)] : q0) : q0;
+          const Real av = qsel * ly[c];
+#pragma unroll
+          for (int n = 0; n < NT; ++n) acc[i][n] = MF::op(av, bz[n], acc[i][n]);
+        }
+      }
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int i = 0; i < MW; ++i) {
+    const int t = W + 4 * i;
+    if (t < TT::NTILE)
+#pragma unroll
+      for (int n = 0; n < NT; ++n) {
+        const int i2 = 16 * n + li;
+        if (i2 < P)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int rr = MF::row(lane, r);
+            const int i0 = TT::paired(t) ? (rr >= 8 ? TT::i0hi(t) : TT::i0lo(t)) : TT::i0lo(t);
+            const int i1 = TT::i1b(t) + (TT::paired(t) ? (rr & 7) : rr);
+            if (i0 < P && i1 < P) out[(i0 * P + i1) * P + i2] = acc[i][n][r];
+          }
+      }
+  }
+}
+
+// Proxy charges of a non-leaf box from the sources of its childless children
+// (3D) on the row tiles of AnterpTiles; one block of 4 waves per box.
+template <class Real, int P>
+__global__ __launch_bounds__(256, sizeof(Real) == 4 ? 3 : 1) void k_anterp_rows(
+    KParams kp, Level L, Level C, int lvl, const double* __restrict__ sx,
+    const double* __restrict__ sq, int64_t nimg, const double* __restrict__ nodes,
+    const double* __restrict__ bw, Real* __restrict__ Q) {
+  using TT = AnterpTiles<P>;
+  __shared__ Real qLx[TT::CH * TT::SL], Ly[TT::CH * TT::SL], Lz[TT::CH * TT::NWP];
+  __shared__ int cb[8], cpre[9];
+  const int k = blockIdx.x;
+  const int b = L.nl_box[k];
+  const int c0 = L.child0[b];
+  if (threadIdx.x == 0) {
+    int acc = 0;
+    for (int o = 0; o < 8; ++o) {
+      const int c = c0 + o;
+      cpre[o] = acc;
+      if (C.child0[c] < 0) {
+        cb[o] = C.sbeg[c];
+        acc += C.send[c] - C.sbeg[c];
+      } else {
+        cb[o] = 0;
+      }
+    }
+    cpre[8] = acc;
+  }
+  // padding entries (i >= P) stay zero for every chunk
+  for (int e = threadIdx.x; e < TT::CH * TT::SL; e += 256) {
+    qLx[e] = 0;
+    Ly[e] = 0;
+  }
+  for (int e = threadIdx.x; e < TT::CH * TT::NWP; e += 256) Lz[e] = 0;
+  __syncthreads();
+  const int total = cpre[8];
+  const double h = kp.rc / (double)(1 << lvl);
+  Real* out = Q + (int64_t)k * P * P * P;
+  switch (threadIdx.x >> 6) {
+    case 0:
+      anterp_rows_wave<Real, P, 0>(kp, L, b, total, cb, cpre, h, sx, sq, nimg, nodes, bw, qLx,
+                                   Ly, Lz, out);
+      break;
+    case 1:
+      anterp_rows_wave<Real, P, 1>(kp, L, b, total, cb, cpre, h, sx, sq, nimg, nodes, bw, qLx,
+                                   Ly, Lz, out);
+      break;
+    case 2:
+      anterp_rows_wave<Real, P, 2>(kp, L, b, total, cb, cpre, h, sx, sq, nimg, nodes, bw, qLx,
+                                   Ly, Lz, out);
+      break;
+    default:
+      anterp_rows_wave<Real, P, 3>(kp, L, b, total, cb, cpre, h, sx, sq, nimg, nodes, bw, qLx,
+                                   Ly, Lz, out);
+      break;
+  }
+}
+
 template <class Real>
 bool anterp_mfma(const pdmk_plan* P, const Level& L, const Level& C, int l, const double* sx,
                  const double* sq, int64_t nimg, void* Q, hipStream_t s) {
   if (P->kp.dim != 3 || !P->pw_mfma) return false;
   if (P->kp.p == 22)
-    hipLaunchKernelGGL((k_anterp_mfma<Real, 22>), dim3(L.nnl), dim3(256), 0, s, P->kp, L, C, l,
+    hipLaunchKernelGGL((k_anterp_rows<Real, 22>), dim3(L.nnl), dim3(256), 0, s, P->kp, L, C, l,
                        sx, sq, nimg, P->d_nodes, P->d_bw, static_cast<Real*>(Q));
   else if (P->kp.p == 13)
-    hipLaunchKernelGGL((k_anterp_mfma<Real, 13>), dim3(L.nnl), dim3(256), 0, s, P->kp, L, C, l,
+    hipLaunchKernelGGL((k_anterp_rows<Real, 13>), dim3(L.nnl), dim3(256), 0, s, P->kp, L, C, l,
                        sx, sq, nimg, P->d_nodes, P->d_bw, static_cast<Real*>(Q));
   else if constexpr (sizeof(Real) == 8) {
     // the orders of eps = 1e-9 and 1e-12 (FP64 only: mixed plans compute in
