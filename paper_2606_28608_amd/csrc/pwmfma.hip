@@ -1073,7 +1073,12 @@ struct AnterpTiles {
   static constexpr int NTA = P * A;
   static constexpr int NTB = R == 0 ? 0 : (PAIR ? (P + 1) / 2 : P);
   static constexpr int NTILE = NTA + NTB;
-  static constexpr int MW = (NTILE + 3) / 4;   // tile slots per wave
+  // tiles 0 .. NDEAL - 1 are dealt to the waves round-robin (MW each); the
+  // NREM others are shared: wave w takes their k-steps st = w mod 4, and the
+  // four partial sums are added at the end (no wave does a tile more)
+  static constexpr int MW = NTILE / 4;
+  static constexpr int NDEAL = 4 * MW;
+  static constexpr int NREM = NTILE - NDEAL;
   static constexpr int NT = (P + 15) / 16;     // column tiles (i2)
   // row stride of the Lagrange rows: holds index P (zero, the missing
   // partner of an odd pair) and, for single tiles, 16 (A + 1) entries
@@ -1110,11 +1115,16 @@ __device__ __forceinline__ void anterp_rows_wave(const KParams& kp, const Level&
   const int lane = threadIdx.x & 63;
   const int li = lane & 15, lk = lane >> 4;
   const bool hi = li >= 8;
-  V acc[MW][NT];
+  constexpr int NREM = TT::NREM;
+  V acc[MW][NT], accr[NREM > 0 ? NREM : 1][NT];
 #pragma unroll
   for (int i = 0; i < MW; ++i)
 #pragma unroll
     for (int n = 0; n < NT; ++n) acc[i][n] = V{0, 0, 0, 0};
+#pragma unroll
+  for (int i = 0; i < (NREM > 0 ? NREM : 1); ++i)
+#pragma unroll
+    for (int n = 0; n < NT; ++n) accr[i][n] = V{0, 0, 0, 0};
   for (int s0 = 0; s0 < total; s0 += CH) {
     // Lagrange rows of the chunk: thread (source, axis)
     if (threadIdx.x < 3 * CH) {
@@ -1132,13 +1142,11 @@ __device__ __forceinline__ void anterp_rows_wave(const KParams& kp, const Level&
       const double qs = (valid && a == 0) ? sq[sidx] : 1.0;
       double rl[P], dl[P];
       lagrange_rows_reg<P, false, sizeof(Real) == 4 ? 1 : 2>(P, nodes, bw, xi, rl, dl);
+      // the thread's row and factor chosen once (no branch per entry)
+      Real* dst = a == 0 ? qLx + si * SL : (a == 1 ? Ly + si * SL : Lz + si * NWP);
+      const double f = valid ? qs : 0.0;
 #pragma unroll
-      for (int i = 0; i < P; ++i) {
-        const Real v = valid ? (Real)(a == 0 ? qs * rl[i] : rl[i]) : (Real)0;
-        if (a == 0) qLx[si * SL + i] = v;
-        else if (a == 1) Ly[si * SL + i] = v;
-        else Lz[si * NWP + i] = v;
-      }
+      for (int i = 0; i < P; ++i) dst[i] = (Real)(f * rl[i]);
     }
     __syncthreads();
 #pragma unroll 2
@@ -1155,38 +1163,73 @@ __device__ __forceinline__ void anterp_rows_wave(const KParams& kp, const Level&
 #pragma unroll
       for (int c = 0; c < TT::A; ++c) ly[c] = Ly[si * SL + 16 * c + li];
       if constexpr (TT::R > 0) ly[TT::A] = Ly[si * SL + 16 * TT::A + (TT::PAIR ? (li & 7) : li)];
+      auto tile_av = [&](int t) {
+        const int c = t < TT::NTA ? t % TT::A : TT::A;
+        const Real q0 = qx[TT::i0lo(t)];
+        const Real qsel = TT::paired(t) ? (hi ? qx[TT::i0hi(t)] : q0) : q0;
+        return qsel * ly[c];
+      };
 #pragma unroll
       for (int i = 0; i < MW; ++i) {
-        const int t = W + 4 * i;
-        if (t < TT::NTILE) {
-          const int c = t < TT::NTA ? t % TT::A : TT::A;
-          const Real q0 = qx[TT::i0lo(t)];
-          const Real qsel = TT::paired(t) ? (hi ? qx[TT::i0hi(t)] : q0) : q0;
-          const Real av = qsel * ly[c];
+        const Real av = tile_av(W + 4 * i);
 #pragma unroll
-          for (int n = 0; n < NT; ++n) acc[i][n] = MF::op(av, bz[n], acc[i][n]);
+        for (int n = 0; n < NT; ++n) acc[i][n] = MF::op(av, bz[n], acc[i][n]);
+      }
+      if (NREM > 0 && (st & 3) == W) {
+#pragma unroll
+        for (int i = 0; i < NREM; ++i) {
+          const Real av = tile_av(TT::NDEAL + i);
+#pragma unroll
+          for (int n = 0; n < NT; ++n) accr[i][n] = MF::op(av, bz[n], accr[i][n]);
         }
       }
     }
     __syncthreads();
   }
+  // shared tiles: the four waves' partial sums through LDS (the Lagrange rows
+  // are no longer read), added by the wave that owns the tile's store
+  Real* red = qLx;   // qLx and Ly are consecutive (one array): NREM * NT * 4 * 256 entries
+  static_assert(NREM * NT * 4 * 256 <= 2 * CH * SL, "partial sums fit the row buffers");
+  if constexpr (NREM > 0) {
 #pragma unroll
-  for (int i = 0; i < MW; ++i) {
-    const int t = W + 4 * i;
-    if (t < TT::NTILE)
+    for (int i = 0; i < NREM; ++i)
 #pragma unroll
-      for (int n = 0; n < NT; ++n) {
-        const int i2 = 16 * n + li;
-        if (i2 < P)
+      for (int n = 0; n < NT; ++n)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) red[(((i * NT + n) * 4 + W) * 4 + r) * 64 + lane] = accr[i][n][r];
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < NREM; ++i)
+      if ((i & 3) == W)
+#pragma unroll
+        for (int n = 0; n < NT; ++n)
 #pragma unroll
           for (int r = 0; r < 4; ++r) {
-            const int rr = MF::row(lane, r);
-            const int i0 = TT::paired(t) ? (rr >= 8 ? TT::i0hi(t) : TT::i0lo(t)) : TT::i0lo(t);
-            const int i1 = TT::i1b(t) + (TT::paired(t) ? (rr & 7) : rr);
-            if (i0 < P && i1 < P) out[(i0 * P + i1) * P + i2] = acc[i][n][r];
+            Real v = 0;
+#pragma unroll
+            for (int w = 0; w < 4; ++w) v += red[(((i * NT + n) * 4 + w) * 4 + r) * 64 + lane];
+            accr[i][n][r] = v;
           }
-      }
   }
+  auto store = [&](int t, const V* a) {
+#pragma unroll
+    for (int n = 0; n < NT; ++n) {
+      const int i2 = 16 * n + li;
+      if (i2 < P)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int rr = MF::row(lane, r);
+          const int i0 = TT::paired(t) ? (rr >= 8 ? TT::i0hi(t) : TT::i0lo(t)) : TT::i0lo(t);
+          const int i1 = TT::i1b(t) + (TT::paired(t) ? (rr & 7) : rr);
+          if (i0 < P && i1 < P) out[(i0 * P + i1) * P + i2] = a[n][r];
+        }
+    }
+  };
+#pragma unroll
+  for (int i = 0; i < MW; ++i) store(W + 4 * i, acc[i]);
+#pragma unroll
+  for (int i = 0; i < NREM; ++i)
+    if ((i & 3) == W) store(TT::NDEAL + i, accr[i]);
 }
 
 // Proxy charges of a non-leaf box from the sources of its childless children
@@ -1197,8 +1240,11 @@ __global__ __launch_bounds__(256, sizeof(Real) == 4 ? 3 : 1) void k_anterp_rows(
     const double* __restrict__ sq, int64_t nimg, const double* __restrict__ nodes,
     const double* __restrict__ bw, Real* __restrict__ Q) {
   using TT = AnterpTiles<P>;
-  __shared__ Real qLx[TT::CH * TT::SL], Ly[TT::CH * TT::SL], Lz[TT::CH * TT::NWP];
+  // the two row buffers in one array: the shared tiles' partial sums use both
+  __shared__ Real rows[2 * TT::CH * TT::SL], Lz[TT::CH * TT::NWP];
   __shared__ int cb[8], cpre[9];
+  Real* qLx = rows;
+  Real* Ly = rows + TT::CH * TT::SL;
   const int k = blockIdx.x;
   const int b = L.nl_box[k];
   const int c0 = L.child0[b];
