@@ -738,31 +738,22 @@ __global__ __launch_bounds__(256) void k_eval_leaf_mfma(
       const double xi = valid ? (tx[a * ntrg + t] - cen) * sc : 0.0;
       double rl[P], dl[P];
       lagrange_rows_reg<P, GRAD, sizeof(Real) == 4 ? 1 : 2>(P, nodes, bw, xi, rl, dl);
+      // the lane's row (x, y: SL-strided rows; z: the transposed B operand)
+      // chosen once, so that the writes take no branch per entry
+      const int off = a == 2 ? li : li * SL, str = a == 2 ? 16 : 1;
+      Real* dst = (a == 0 ? Lx : (a == 1 ? Ly : Lz)) + off;
+      Real* ddst = (a == 0 ? dLx : (a == 1 ? dLy : dLz)) + off;
+      const double f = valid ? 1.0 : 0.0;
 #pragma unroll
       for (int i = 0; i < P; ++i) {
-        const Real v = valid ? (Real)rl[i] : (Real)0;
-        const Real dv = (GRAD && valid) ? (Real)dl[i] : (Real)0;
-        if (a == 0) {
-          Lx[li * SL + i] = v;
-          if (GRAD) dLx[li * SL + i] = dv;
-        } else if (a == 1) {
-          Ly[li * SL + i] = v;
-          if (GRAD) dLy[li * SL + i] = dv;
-        } else {
-          Lz[i * 16 + li] = v;
-          if (GRAD) dLz[i * 16 + li] = dv;
-        }
+        dst[i * str] = (Real)(f * rl[i]);
+        if (GRAD) ddst[i * str] = (Real)(f * dl[i]);
       }
-      if (a < 2)
-        for (int i = P; i < P1; ++i) {
-          (a == 0 ? Lx : Ly)[li * SL + i] = 0;
-          if (GRAD) (a == 0 ? dLx : dLy)[li * SL + i] = 0;
-        }
-      else
-        for (int i = P; i < KA; ++i) {
-          Lz[i * 16 + li] = 0;
-          if (GRAD) dLz[i * 16 + li] = 0;
-        }
+      const int iend = a == 2 ? KA : P1;
+      for (int i = P; i < iend; ++i) {
+        dst[i * str] = 0;
+        if (GRAD) ddst[i * str] = 0;
+      }
     }
     __builtin_amdgcn_s_waitcnt(0);
     __builtin_amdgcn_wave_barrier();
@@ -991,13 +982,11 @@ __global__ __launch_bounds__(256, sizeof(Real) == 4 ? 3 : 1) void k_anterp_mfma(
       const double qs = (valid && a == 0) ? sq[sidx] : 1.0;
       double rl[P], dl[P];
       lagrange_rows_reg<P, false, sizeof(Real) == 4 ? 1 : 2>(P, nodes, bw, xi, rl, dl);
+      // the thread's row and factor chosen once (no branch per entry)
+      Real* dst = a == 0 ? qLx + si * SL : (a == 1 ? Ly + si * SL : Lz + si * NW);
+      const double f = valid ? qs : 0.0;
 #pragma unroll
-      for (int i = 0; i < P; ++i) {
-        const Real v = valid ? (Real)(a == 0 ? qs * rl[i] : rl[i]) : (Real)0;
-        if (a == 0) qLx[si * SL + i] = v;
-        else if (a == 1) Ly[si * SL + i] = v;
-        else Lz[si * NW + i] = v;
-      }
+      for (int i = 0; i < P; ++i) dst[i] = (Real)(f * rl[i]);
     }
     __syncthreads();
     // Every tile slot of the wave is computed (a slot past the last tile
