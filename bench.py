@@ -266,6 +266,10 @@ def roofline_all(r, mode, plan):
     st, sm = r["stats"], r["stages_ms"]
     out = {}
     fv, fs = flop_per_pair(st["series_len"])
+    # pairs evaluated once (targets = sources): each in-support pair also forms
+    # q_t R for its source end and adds it into that source's sum (2 flop)
+    if st.get("pairs_once"):
+        fs += 2
     # pairs the kernel evaluates: the list pairs left after the per-pass reach
     # test (a source farther than h + rho from the centre of a pass's targets
     # is not staged); the test itself costs 9 flop per candidate source and pass
@@ -277,7 +281,8 @@ def roofline_all(r, mode, plan):
                        "launches": 1, "flop_per_launch": flop,
                        "pairs_listed": st["n_direct_pairs"], "pairs_staged": staged,
                        "pairs_in_support": st["n_support_pairs"],
-                       "flop_per_staged_pair": fv, "flop_per_support_pair": fs}
+                       "flop_per_staged_pair": fv, "flop_per_support_pair": fs,
+                       "pairs_once": bool(st.get("pairs_once"))}
     P, J = plan["porder"], plan["npw"]
     nb = _ball_modes(J)
     tr = pw_fma_per_box(P, J)

@@ -494,6 +494,9 @@ typedef struct {
   double t_interp_ms;               /* far field: interpolation at the targets */
   int64_t n_forced_splits;          /* PDMK_BALANCE: leaves split for the 2:1 balance */
   int balance_rounds;               /* PDMK_BALANCE: tree builds until balanced */
+  int pairs_once;                   /* 1: the residual sums evaluated each pair of points in
+                                       different leaves once and added it to both (see
+                                       PDMK_ALL_PAIRS); the pair counts are those evaluated */
 } pdmk_stats;
 int pdmk_plan_stats(const pdmk_plan* plan, pdmk_stats* out);
 int pdmk_batch_stats(const pdmk_batch* batch, int sys, pdmk_stats* out);

@@ -867,6 +867,7 @@ static int eval_impl(pdmk_plan* P, int64_t n_src, const double* src, const doubl
       // length of the series the residual kernel evaluated
       const bool f32 = P->kp.precision == PDMK_PREC_MIXED && (P->mixed_parts & 1);
       E.st.series_len = d == 3 ? (f32 ? P->kp.nE32 : P->kp.nE) : (f32 ? P->kp.nF232 : P->kp.nF2);
+      E.st.pairs_once = E.sym ? 1 : 0;
     }
     E.st.t_build_ms = t1;
     E.st.t_near_ms = t2;

@@ -83,7 +83,7 @@ class Stats(ctypes.Structure):
                 ("t_pwtr_ms", ctypes.c_double), ("n_staged_pairs", ctypes.c_int64),
                 ("t_spread_ms", ctypes.c_double), ("t_fft_ms", ctypes.c_double),
                 ("t_interp_ms", ctypes.c_double), ("n_forced_splits", ctypes.c_int64),
-                ("balance_rounds", ctypes.c_int)]
+                ("balance_rounds", ctypes.c_int), ("pairs_once", ctypes.c_int)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
