@@ -721,21 +721,35 @@ __global__ __launch_bounds__(256) void k_eval_leaf_mfma(
   Real* dLz = dLy + 16 * SL;
   const double hP = kp.rc / (double)(1 << lvl);
   const double sc = 2.0 / hP;
-  for (int ch = wave; 16 * ch < total; ch += 4) {
-    // target of lane li in this chunk
+  // target of lane li in chunk ch, and (lanes lk < 3) its coordinate lk; the
+  // next chunk's coordinate is loaded while this chunk is evaluated
+  auto target = [&](int ch, bool& valid) {
     const int j = 16 * ch + li;
-    const bool valid = j < total;
+    valid = j < total;
     int t = 0;
     if (valid) {
       int o = 0;
       while (o < 7 && cpre[o + 1] <= j) ++o;
       t = cb[o] + (j - cpre[o]);
     }
+    return t;
+  };
+  bool vnext = false;
+  int tnext = target(wave, vnext);
+  double xnext = (lk < 3 && vnext) ? tx[lk * ntrg + tnext] : 0.0;
+  for (int ch = wave; 16 * ch < total; ch += 4) {
+    const int t = tnext;
+    const bool valid = vnext;
+    const double xraw = xnext;
+    if (16 * (ch + 4) < total) {
+      tnext = target(ch + 4, vnext);
+      xnext = (lk < 3 && vnext) ? tx[lk * ntrg + tnext] : 0.0;
+    }
     // rows: lane (li, axis lk < 3) computes l_i(xi) for its target
     if (lk < 3) {
       const int a = lk;
       const double cen = kp.origin[a] + (Lp.coord[Pb * 3 + a] + 0.5) * hP;
-      const double xi = valid ? (tx[a * ntrg + t] - cen) * sc : 0.0;
+      const double xi = valid ? (xraw - cen) * sc : 0.0;
       double rl[P], dl[P];
       lagrange_rows_reg<P, GRAD, sizeof(Real) == 4 ? 1 : 2>(P, nodes, bw, xi, rl, dl);
       // the lane's row (x, y: SL-strided rows; z: the transposed B operand)
@@ -854,12 +868,15 @@ __global__ __launch_bounds__(256) void k_eval_leaf_mfma(
         g2 += __shfl_xor(g2, m);
       }
     }
+    // one add per target in this kernel (its leaf has one parent): an atomic
+    // without return keeps the wave from waiting on the old value, and the
+    // result does not depend on the order
     if (valid && lk == 0) {
-      pot[t] += (double)acc;
+      atomicAdd(&pot[t], (double)acc);
       if (GRAD) {
-        grad[(int64_t)t * 3 + 0] += (double)g0 * sc;
-        grad[(int64_t)t * 3 + 1] += (double)g1 * sc;
-        grad[(int64_t)t * 3 + 2] += (double)g2 * sc;
+        atomicAdd(&grad[(int64_t)t * 3 + 0], (double)g0 * sc);
+        atomicAdd(&grad[(int64_t)t * 3 + 1], (double)g1 * sc);
+        atomicAdd(&grad[(int64_t)t * 3 + 2], (double)g2 * sc);
       }
     }
     __builtin_amdgcn_wave_barrier();
