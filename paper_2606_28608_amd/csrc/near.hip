@@ -170,11 +170,11 @@ struct SymInfo {
 template <class Real>
 struct SourceSlot {
   double4 v;                   // (offset, h^2)
-  typename SlotQ<Real>::T w;   // (q, 1/h, 2/h^2, 0)
+  typename SlotQ<Real>::T w;   // (q, 1/h, 2/h^2, target of the source end: slot_tg)
   int tg;                      // SYM: target that also receives the pair (-1: none)
   bool live;                   // within h + rho of the pass's target centre
   // Source offset from the target leaf centre (formed in FP64) with the support
-  // h^2 of its residual level in v.w, and (q, 1/h, 2/h^2); slots past the list
+  // h^2 of its residual level in v.w, and (q, 1/h, 2/h^2, tg); slots past the list
   // end never interact (h^2 = 0).  live: the source can reach a target of the
   // pass, whose targets lie within rho of cc (|y - cc| < h + rho).
   // SYM: an unshifted source that is a target of a later leaf (in source
