@@ -992,18 +992,26 @@ static int bloch_impl(pdmk_plan* P, int64_t n_src, const double* src, const doub
     stage_images(P, E, q);   // wrapped complex charges and phased images
     stage_far_grid(P, E);    // pre-modulated charges, shifted-mode scaling
     stage_tree(P, E);
+    // residual pairs evaluated once: each pass is a plain sum over the phased
+    // image charges (the targets are modulated afterwards), and a target's
+    // charge as a source is its unshifted image's (oq / oq_im)
+    E.sym = self_t && E.img_trg != nullptr && E.oq_im != nullptr &&
+            !(P->o.flags & PDMK_ALL_PAIRS);
     stage_lists(P, E);
     // the near field is real-linear in the charges: one pass per part
     double* sq_re = E.sq;
     const double* q_re = E.q;
+    double* oq_re = E.oq;
     stage_near(P, E, false);
     double* near_re = E.pot_sorted;
     E.sq = E.sq_im;
     E.q = E.q_im;
+    E.oq = E.oq_im;
     stage_near(P, E, false);
     double* near_im = E.pot_sorted;
     E.sq = sq_re;
     E.q = q_re;
+    E.oq = oq_re;
     double* far_re = E.alloc<double>(n_trg);
     double* far_im = E.alloc<double>(n_trg);
     E.far_out = far_re;
@@ -1025,6 +1033,7 @@ static int bloch_impl(pdmk_plan* P, int64_t n_src, const double* src, const doub
     E.st.n_src = n_src;
     E.st.n_trg = n_trg;
     E.st.n_images = E.n_img;
+    E.st.pairs_once = E.sym ? 1 : 0;
     P->last = E.st;
     finish_workspace(P->arena, P->arena_size, ws);
     P->last.workspace_bytes = (int64_t)ws.used;

@@ -123,3 +123,32 @@ def test_both_way_modes_unchanged(pdmk, torch_dev):
     trg = src + 1e-3 * np.random.default_rng(208).standard_normal(src.shape)
     sep = pdmk.Plan(L, eps=1e-9).eval(S, Q, trg=_t(torch_dev, trg)).cpu().numpy()
     assert ewald.rel_l2(sep, ewald.ewald(L, src, q, trg=trg)) <= 1e-9
+
+
+@pytest.mark.parametrize("dim,precision", [(3, "fp64"), (3, "mixed"), (2, "fp64")])
+def test_bloch_once_matches_both_ways_and_oracle(pdmk, torch_dev, dim, precision):
+    """Bloch conditions: each near pass is a plain sum over the phased image
+    charges, so the pairs of two unshifted points are evaluated once there
+    too, the source end taking its own image's charge in each pass."""
+    rng = np.random.default_rng(209)
+    if dim == 3:
+        L, src, _ = workloads.clustered3d(6000, seed=209)
+        beta = np.array([0.7, -1.1, 0.4])
+    else:
+        L, src, _ = workloads.oblique2d(4000, seed=209)
+        beta = np.array([0.9, -0.6])
+    q = rng.standard_normal(len(src))
+    S, Q = _t(torch_dev, src), _t(torch_dev, q)
+    opts = dict(eps=1e-6, precision=precision, bloch=beta, kappa=3.0, n_s=60)
+    once = pdmk.Plan(L, **opts)
+    a = once.eval_bloch(S, Q).cpu().numpy()
+    assert once.stats()["pairs_once"] == 1
+    both = pdmk.Plan(L, all_pairs=True, **opts)
+    b = both.eval_bloch(S, Q).cpu().numpy()
+    assert both.stats()["pairs_once"] == 0
+    ref = ewald.ewald_bloch(L, src, q, beta)
+    rel = lambda x, y: float(np.linalg.norm(x - y) / np.linalg.norm(y))
+    print("Bloch %dD %s: once %.3e both %.3e diff %.3e" % (dim, precision, rel(a, ref),
+                                                           rel(b, ref), rel(a, b)))
+    assert rel(a, ref) <= 1e-6 and rel(b, ref) <= 1e-6
+    assert rel(a, b) <= (1e-13 if precision == "fp64" else 1e-6)
