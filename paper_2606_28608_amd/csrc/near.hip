@@ -177,10 +177,11 @@ struct SourceSlot {
   // h^2 of its residual level in v.w, and (q, 1/h, 2/h^2, tg); slots past the list
   // end never interact (h^2 = 0).  live: the source can reach a target of the
   // pass, whose targets lie within rho of cc (|y - cc| < h + rho).
-  // SYM: an unshifted source that is a target of a later leaf (in source
-  // order) receives the pair's term too (tg); one of an earlier leaf is
-  // dropped (that leaf adds the pair to both ends); shifted copies and the
-  // leaf's own sources are summed one way.
+  // SYM: a source that is a point of the cell and a target of a later leaf
+  // (in source order) receives the pair's term too (tg), also through a
+  // virtual colleague's shift (its mirror entry has the opposite shift); one
+  // of an earlier leaf is dropped (that leaf adds the pair to both ends);
+  // image copies and the leaf's own sources are summed one way.
   template <bool SYM>
   __device__ void fetch(const ListCursor& c, const KParams& kp, const double* __restrict__ sx,
                         const double* __restrict__ sq, int64_t nimg, const double* cT, int D,
@@ -189,7 +190,7 @@ struct SourceSlot {
     if (c.valid()) {
       const int sidx = c.en.x + c.oo;
       bool drop = false;
-      if (SYM && c.en.w == 0) {
+      if (SYM) {
         const int it = si.itrg[sidx];
         if (it >= 0) {
           if (sidx < si.sb) drop = true;

@@ -814,10 +814,11 @@ static void build_tree(pdmk_plan* P, Eval& E, const uint64_t* fkey, const int* f
 // boxes that are not target leaves get no entries.
 // The rule is symmetric: a point pair (x in T, y in S) meets in T's list
 // through an entry holding S's box and in S's list through one holding T's
-// box, with the same level.  sym (targets = sources, pairs evaluated once):
-// an unshifted entry whose box precedes T in source order and holds only
-// points of the cell (no shifted copies: as many sources as targets) is left
-// out, since the leaves after it add its pairs to both ends.
+// box, with the same level (a virtual colleague under shift n is met again
+// under -n).  sym (targets = sources, pairs evaluated once): an entry whose
+// box precedes T in source order and holds only points of the cell (no
+// shifted copies: as many sources as targets) is left out, since the leaves
+// after it add its pairs to both ends.
 __global__ void k_leaf_lists(int d, int nleaf, const Level* __restrict__ lev,
                              const int* __restrict__ lf_level, const int* __restrict__ lf_box,
                              int* __restrict__ cnt, const int* __restrict__ beg,
@@ -847,7 +848,7 @@ __global__ void k_leaf_lists(int d, int nleaf, const Level* __restrict__ lev,
     int sb = T.sbeg[c], se = T.send[c];
     if (se <= sb) continue;
     const int sh = T.cshift ? T.cshift[b * ncoll + sl] : 0;
-    if (sym && sh == 0 && se <= tsb && se - sb == T.tend[c] - T.tbeg[c]) continue;
+    if (sym && se <= tsb && se - sb == T.tend[c] - T.tbeg[c]) continue;
     if (list) list[o + k] = make_int4(sb, se, lvl, sh);
     ++k;
     np += se - sb;
@@ -861,7 +862,7 @@ __global__ void k_leaf_lists(int d, int nleaf, const Level* __restrict__ lev,
       int sb = A.sbeg[D], se = A.send[D];
       if (se <= sb) continue;
       const int sh = A.cshift ? A.cshift[a * ncoll + sl] : 0;
-      if (sym && sh == 0 && se <= tsb && se - sb == A.tend[D] - A.tbeg[D]) continue;
+      if (sym && se <= tsb && se - sb == A.tend[D] - A.tbeg[D]) continue;
       if (list) list[o + k] = make_int4(sb, se, l, sh);
       ++k;
       np += se - sb;
