@@ -4,9 +4,10 @@ leaves is summed by the leaf that comes first in source order and added to
 both ends; PDMK_ALL_PAIRS evaluates every pair from both ends.
 
 * the two agree to rounding and both meet eps against the oracle: triclinic
-  cells with image halos (default kappa), the cube construction (shifted
-  colleagues stay one-way), 2D, leaves with few targets (several lanes per
-  target), mixed precision;
+  cells with image halos (default kappa; halo copies stay one-way), the cube
+  construction (virtual colleagues: the mirror pair under the opposite
+  shift), 2D, leaves with few targets (several lanes per target), mixed
+  precision, Bloch conditions;
 * the once-only lists hold about half the pairs;
 * modes that keep both-way lists (gradients, deterministic, separate
   targets, kept trees) give the same results as before.
