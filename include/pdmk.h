@@ -281,7 +281,12 @@ int pdmk_plan_eval_noalloc(pdmk_plan* plan, int64_t n_src, const double* src, co
  * plan, everything that depends on the positions alone: wrapped and sorted
  * sources, images and targets, the tree, colleague and residual lists.  A
  * previous binding is released first.  It also allocates the workspace an
- * execute needs, so that executes allocate nothing.
+ * execute needs, so that executes allocate nothing.  When the targets are the
+ * sources, the plan was made without PDMK_WANT_GRAD (nor PDMK_DETERMINISTIC
+ * or PDMK_ALL_PAIRS) and the bind asks for no gradients, the kept lists
+ * evaluate each residual pair once (see PDMK_ALL_PAIRS); an execute on such a
+ * tree that asks for gradients returns PDMK_ERR_UNSUPPORTED before enqueuing
+ * anything.
  *
  * pdmk_plan_execute: the near field, far field and assembly of Algorithm 1
  * for charges q (n_src, DEVICE) on the kept tree, into pot (n_trg) and, when

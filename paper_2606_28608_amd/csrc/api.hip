@@ -796,10 +796,11 @@ static int eval_impl(pdmk_plan* P, int64_t n_src, const double* src, const doubl
       record(fev[2], aux);
     };
     if (!keep) far_fork();
-    // residual pairs evaluated once where the call allows it (a kept tree
-    // keeps both-way lists: a later execute may ask for gradients)
-    E.sym = self_t && !want_grad && !E.det && !keep && E.img_trg != nullptr &&
-            !(flags & PDMK_ALL_PAIRS);
+    // residual pairs evaluated once where the call allows it (a kept tree of
+    // a plan made with PDMK_WANT_GRAD keeps both-way lists: its executes may
+    // ask for gradients; one of another plan rejects such executes)
+    E.sym = self_t && !want_grad && !E.det && E.img_trg != nullptr &&
+            !(flags & PDMK_ALL_PAIRS) && (!keep || !(flags & PDMK_WANT_GRAD));
     stage_tree(P, E);
     stage_lists(P, E);
     const size_t mark = ws.used;
@@ -1139,6 +1140,10 @@ static int execute_impl(pdmk_plan* P, const double* src, const double* trg, cons
   E.st = pdmk_stats{};
   E.det = (B.flags & PDMK_DETERMINISTIC) != 0;
   const bool want_grad = grad != nullptr;
+  if (want_grad && E.sym)
+    return fail(PDMK_ERR_UNSUPPORTED,
+                "the tree was bound for potentials (residual pairs evaluated once); bind on "
+                "a plan made with PDMK_WANT_GRAD to execute with gradients");
   const int64_t n = E.n_src, m = E.n_trg;
   const bool fork = n + m >= kForkMin;
   hipStream_t aux = fork ? P->s_aux : s;

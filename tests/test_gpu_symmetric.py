@@ -153,3 +153,38 @@ def test_bloch_once_matches_both_ways_and_oracle(pdmk, torch_dev, dim, precision
                                                            rel(b, ref), rel(a, b)))
     assert rel(a, ref) <= 1e-6 and rel(b, ref) <= 1e-6
     assert rel(a, b) <= (1e-13 if precision == "fp64" else 1e-6)
+
+
+def test_kept_tree_pairs_once(pdmk, torch_dev):
+    """A kept tree of a plan without gradients keeps the once-only lists: its
+    executes (new charges, displaced points) match the one-shot evaluation and
+    the oracle; an execute asking for gradients is rejected; a plan made with
+    gradients keeps both-way lists and executes with them."""
+    L, src, q = workloads.clustered3d(8000, seed=210)
+    S, Q = _t(torch_dev, src), _t(torch_dev, q)
+    q2 = np.random.default_rng(211).standard_normal(len(q))
+    q2 -= q2.mean()
+    plan = pdmk.Plan(L, eps=1e-9)
+    plan.bind(S, Q)
+    assert plan.stats()["pairs_once"] == 1
+    got = plan.execute(_t(torch_dev, q2)).cpu().numpy()
+    plan.status()
+    ref = ewald.ewald(L, src, q2)
+    assert ewald.rel_l2(got, ref) <= 1e-9
+    one = pdmk.Plan(L, eps=1e-9).eval(S, _t(torch_dev, q2)).cpu().numpy()
+    assert ewald.rel_l2(got, one) <= 1e-10   # kept executes use the hand-written axis kernels
+    moved = src + 1e-5 * np.random.default_rng(212).standard_normal(src.shape)
+    gm = plan.execute(_t(torch_dev, q2), src=_t(torch_dev, moved)).cpu().numpy()
+    plan.status()
+    assert ewald.rel_l2(gm, ewald.ewald(L, moved, q2)) <= 1e-9
+    with pytest.raises(pdmk.PdmkError) as e:
+        plan.execute(_t(torch_dev, q2), want_grad=True)
+    assert e.value.code == -9
+    gp = pdmk.Plan(L, eps=1e-9, grad=True)
+    gp.bind(S, Q)
+    assert gp.stats()["pairs_once"] == 0
+    pot, g = gp.execute(_t(torch_dev, q2))
+    gp.status()
+    rp, rg = ewald.ewald(L, src, q2, grad=True)
+    assert ewald.rel_l2(pot.cpu().numpy(), rp) <= 1e-9
+    assert ewald.rel_l2(g.cpu().numpy(), rg) <= 1e-8
