@@ -24,6 +24,25 @@ constexpr double kInv4Pi = 0.07957747154594767;
 constexpr double kInv2Pi = 0.15915494309189535;
 
 // ------------------------------------------------------------- residual sums
+// slot pairs of the residual statistics (a power of two)
+constexpr int kStatSlots = 64;
+
+// out[0], out[1] = (add: +=) sums of the kStatSlots slot pairs (one wave)
+__global__ __launch_bounds__(64) void k_fold_stats(const unsigned long long* __restrict__ slots,
+                                                   unsigned long long* __restrict__ out,
+                                                   int add) {
+  unsigned long long a = slots[2 * threadIdx.x], b = slots[2 * threadIdx.x + 1];
+#pragma unroll
+  for (int m = 1; m < kStatSlots; m <<= 1) {
+    a += __shfl_xor(a, m);
+    b += __shfl_xor(b, m);
+  }
+  if (threadIdx.x == 0) {
+    out[0] = add ? out[0] + a : a;
+    out[1] = add ? out[1] + b : b;
+  }
+}
+
 // One 64-lane block per target leaf.  The block walks the concatenated source
 // ranges of the leaf's list in tiles of 64 staged in LDS (each slot carries
 // its own support h of the residual level), so short ranges do not leave
@@ -548,10 +567,13 @@ __device__ __forceinline__ void direct_body(PDMK_DIRECT_PARAMS) {
     }
     t0 += 64 / S;
   }
-  // pairs inside the support (statistics): one atomic per block
+  // pairs inside the support and staged pairs (statistics): one atomic pair
+  // per block into one of kStatSlots slot pairs (one address for every block
+  // serialises the atomics at the cache), folded by k_fold_stats
   if (lane == 0 && n_support) {
-    atomicAdd(n_support, (unsigned long long)nin);
-    atomicAdd(n_support + 1, (unsigned long long)nstaged);
+    unsigned long long* sl = n_support + 2 * (blockIdx.x & (kStatSlots - 1));
+    atomicAdd(sl, (unsigned long long)nin);
+    atomicAdd(sl + 1, (unsigned long long)nstaged);
   }
 }
 
@@ -1511,9 +1533,12 @@ static void near_impl(pdmk_plan* P, Eval& E, bool want_grad) {
   hipEvent_t e0 = E.near_ev[0], e1 = E.near_ev[1], e2 = E.near_ev[2], e3 = E.near_ev[3];
   // [0] colleague pairs translated, [1] boxes given incoming plane waves,
   // [2] residual pairs inside the support
-  unsigned long long* cnt = E.alloc<unsigned long long>(4);
-  fill_zero(cnt, 4 * sizeof(unsigned long long), s);
-  unsigned long long* nsup = cnt + 2;
+  // (cnt[3]: staged pairs; cnt[4 ...]: the residual sums' statistic slots,
+  // then the colleague translation's, folded into cnt[0], cnt[1])
+  unsigned long long* cnt = E.alloc<unsigned long long>(4 + 4 * kStatSlots);
+  fill_zero(cnt, (4 + 4 * kStatSlots) * sizeof(unsigned long long), s);
+  unsigned long long* nsup = cnt + 4;
+  unsigned long long* trslots = cnt + 4 + 2 * kStatSlots;
   fill_zero(E.pot_sorted, sizeof(double) * E.n_trg, s);
   if (want_grad)
     fill_zero(E.grad_sorted, sizeof(double) * E.n_trg * D, s);
@@ -1600,7 +1625,7 @@ static void near_impl(pdmk_plan* P, Eval& E, bool want_grad) {
       E.st.n_pwout_boxes += nn;
       if (tm) PDMK_HIP(hipEventRecord(pe[0], s));
       if (mfma) {
-        pw_mfma_level<Real>(P, L, nn, L.proxy_q, bS, bIw, L.proxy_phi, levfac, npairs, pe[1],
+        pw_mfma_level<Real>(P, L, nn, L.proxy_q, bS, bIw, L.proxy_phi, levfac, trslots, pe[1],
                             pe[3], s);
         if (tm) PDMK_HIP(hipEventRecord(pe[2], s));
         continue;
@@ -1639,7 +1664,7 @@ static void near_impl(pdmk_plan* P, Eval& E, bool want_grad) {
           }
         }
         if (D == 3)
-          pw_translate(P, L, bSd, reinterpret_cast<double2*>(bIw), levfac, npairs, s);
+          pw_translate(P, L, bSd, reinterpret_cast<double2*>(bIw), levfac, trslots, s);
         for (int k0 = 0; k0 < nn; k0 += chunk) {
           const int nc = std::min(chunk, nn - k0);
           if (D == 3)
@@ -1727,6 +1752,9 @@ static void near_impl(pdmk_plan* P, Eval& E, bool want_grad) {
           launch_eval_children<D, Real>(kp, E.lev[l], E.lev[l + 1], l, E, P, s, want_grad);
   if (tm) {
     PDMK_HIP(hipEventRecord(e3, s));
+    // statistics (read only here): the slots folded into cnt[0..3]
+    hipLaunchKernelGGL(k_fold_stats, dim3(1), dim3(kStatSlots), 0, s, nsup, cnt + 2, 0);
+    hipLaunchKernelGGL(k_fold_stats, dim3(1), dim3(kStatSlots), 0, s, trslots, cnt, 1);
     PDMK_HIP(hipMemcpyAsync(P->h_cnt, cnt, 3 * sizeof(unsigned long long),
                             hipMemcpyDeviceToHost, s));
     PDMK_HIP(hipMemcpyAsync(P->h_cnt + 8, cnt + 3, sizeof(unsigned long long),

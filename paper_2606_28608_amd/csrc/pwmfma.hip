@@ -366,8 +366,11 @@ __global__ __launch_bounds__(256) void k_pw_trans(Level L, const typename Cplx<R
       const int m = __popcll(mask);
       ncol = m;
       if (npairs && ch == 0) {
-        atomicAdd(npairs, (unsigned long long)m);
-        atomicAdd(npairs + 1, 1ull);
+        // one of 64 slot pairs per box (one address for every box would
+        // serialise the atomics at the cache); the caller folds them
+        unsigned long long* sp = npairs + 2 * (k & 63);
+        atomicAdd(sp, (unsigned long long)m);
+        atomicAdd(sp + 1, 1ull);
       }
     }
   }

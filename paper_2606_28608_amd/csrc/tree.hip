@@ -163,18 +163,20 @@ __device__ inline void for_each_image(const KParams& kp, const double* x, F f) {
 
 // Images per source; also their total in 64 bits (total64), so that a count
 // past the int32 range of the offsets and tree indices is detected before the
-// offsets are used.
+// offsets are used.  Grid-stride over a bounded grid: one atomic per block on
+// the one total (tens of thousands of them would serialise at the cache).
 __global__ __launch_bounds__(256) void k_img_count(KParams kp, int64_t n,
                                                    const double* __restrict__ xs,
                                                    int* __restrict__ cnt, int* __restrict__ missing,
                                                    unsigned long long* __restrict__ total64) {
   __shared__ unsigned long long part[256];
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  int c = 0;
-  if (i < n) {
+  unsigned long long mine = 0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
     const int d = kp.dim;
     double x[3] = {0, 0, 0};
     for (int a = 0; a < d; ++a) x[a] = xs[a * n + i];
+    int c = 0;
     bool orig = false;
     if (kp.vimg) {
       // virtual images: the original alone
@@ -187,9 +189,10 @@ __global__ __launch_bounds__(256) void k_img_count(KParams kp, int64_t n,
       });
     }
     cnt[i] = c;
+    mine += (unsigned long long)c;
     if (!orig) atomicAdd(missing, 1);   // the unshifted copy was not emitted
   }
-  part[threadIdx.x] = (unsigned long long)c;
+  part[threadIdx.x] = mine;
   __syncthreads();
   for (int st = 128; st > 0; st >>= 1) {
     if ((int)threadIdx.x < st) part[threadIdx.x] += part[threadIdx.x + st];
@@ -405,8 +408,8 @@ void stage_images(pdmk_plan* P, Eval& E, const double* q) {
   PDMK_HIP(hipMemsetAsync(cnt + n, 0, 2 * sizeof(int), E.s));
   PDMK_HIP(hipMemsetAsync(total64, 0, sizeof(unsigned long long), E.s));
   if (n > 0)
-    hipLaunchKernelGGL(k_img_count, dim3(nblk(n, 256)), dim3(256), 0, E.s, kp, n, E.xs, cnt,
-                       cnt + n + 1, total64);
+    hipLaunchKernelGGL(k_img_count, dim3(std::min(nblk(n, 256), 2048)), dim3(256), 0, E.s, kp,
+                       n, E.xs, cnt, cnt + n + 1, total64);
   exclusive_scan_int(cnt, off, (int)(n + 1), E);
   int hv[2] = {0, 0};
   unsigned long long tot = 0;
@@ -819,13 +822,14 @@ static void build_tree(pdmk_plan* P, Eval& E, const uint64_t* fkey, const int* f
 // box precedes T in source order and holds only points of the cell (no
 // shifted copies: as many sources as targets) is left out, since the leaves
 // after it add its pairs to both ends.
-__global__ void k_leaf_lists(int d, int nleaf, const Level* __restrict__ lev,
-                             const int* __restrict__ lf_level, const int* __restrict__ lf_box,
-                             int* __restrict__ cnt, const int* __restrict__ beg,
-                             int4* __restrict__ list, unsigned long long* __restrict__ pairs,
-                             int* __restrict__ nsrc, int sym) {
-  int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= nleaf) return;
+// One list slot; returns its listed pairs (sources x targets) in mode 0.
+__device__ inline unsigned long long leaf_list_one(int d, int i, const Level* __restrict__ lev,
+                                                   const int* __restrict__ lf_level,
+                                                   const int* __restrict__ lf_box,
+                                                   int* __restrict__ cnt,
+                                                   const int* __restrict__ beg,
+                                                   int4* __restrict__ list,
+                                                   int* __restrict__ nsrc, int sym) {
   const int ncoll = d == 3 ? 27 : 9;
   int lvl = lf_level[i], b = lf_box[i];
   const Level& T = lev[lvl];
@@ -835,7 +839,7 @@ __global__ void k_leaf_lists(int d, int nleaf, const Level* __restrict__ lev,
       cnt[i] = 0;
       nsrc[i] = 0;
     }
-    return;
+    return 0;
   }
   int k = 0;
   long long np = 0;
@@ -869,11 +873,27 @@ __global__ void k_leaf_lists(int d, int nleaf, const Level* __restrict__ lev,
     }
     a = A.parent[a];
   }
-  if (cnt) {
-    const long long nt = T.tend[b] - T.tbeg[b];
-    cnt[i] = k;
-    nsrc[i] = (int)np;
-    atomicAdd(pairs, (unsigned long long)(np * nt));
+  if (!cnt) return 0;
+  const long long nt = T.tend[b] - T.tbeg[b];
+  cnt[i] = k;
+  nsrc[i] = (int)np;
+  return (unsigned long long)(np * nt);
+}
+
+// The listed pairs are summed per wave before one atomic (one address for
+// every slot would serialise the atomics at the cache).
+__global__ void k_leaf_lists(int d, int nleaf, const Level* __restrict__ lev,
+                             const int* __restrict__ lf_level, const int* __restrict__ lf_box,
+                             int* __restrict__ cnt, const int* __restrict__ beg,
+                             int4* __restrict__ list, unsigned long long* __restrict__ pairs,
+                             int* __restrict__ nsrc, int sym) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  unsigned long long pc = 0;
+  if (i < nleaf) pc = leaf_list_one(d, i, lev, lf_level, lf_box, cnt, beg, list, nsrc, sym);
+  if (pairs) {
+#pragma unroll
+    for (int m = 1; m < 64; m <<= 1) pc += __shfl_xor(pc, m);
+    if ((threadIdx.x & 63) == 0) atomicAdd(pairs, pc);
   }
 }
 
