@@ -24,16 +24,23 @@ constexpr double kInv4Pi = 0.07957747154594767;
 constexpr double kInv2Pi = 0.15915494309189535;
 
 // ------------------------------------------------------------- residual sums
-// slot pairs of the residual statistics (a power of two)
-constexpr int kStatSlots = 64;
+// slot pairs of the residual statistics (a power of two, at least 64) and of
+// the colleague translation's counters (64)
+constexpr int kStatSlots = 1024;
+constexpr int kTransSlots = 64;
 
-// out[0], out[1] = (add: +=) sums of the kStatSlots slot pairs (one wave)
+// out[0], out[1] = (add: +=) sums of nslots slot pairs (one wave; nslots a
+// multiple of 64)
 __global__ __launch_bounds__(64) void k_fold_stats(const unsigned long long* __restrict__ slots,
-                                                   unsigned long long* __restrict__ out,
+                                                   int nslots, unsigned long long* __restrict__ out,
                                                    int add) {
-  unsigned long long a = slots[2 * threadIdx.x], b = slots[2 * threadIdx.x + 1];
+  unsigned long long a = 0, b = 0;
+  for (int i = threadIdx.x; i < nslots; i += 64) {
+    a += slots[2 * i];
+    b += slots[2 * i + 1];
+  }
 #pragma unroll
-  for (int m = 1; m < kStatSlots; m <<= 1) {
+  for (int m = 1; m < 64; m <<= 1) {
     a += __shfl_xor(a, m);
     b += __shfl_xor(b, m);
   }
@@ -1535,8 +1542,9 @@ static void near_impl(pdmk_plan* P, Eval& E, bool want_grad) {
   // [2] residual pairs inside the support
   // (cnt[3]: staged pairs; cnt[4 ...]: the residual sums' statistic slots,
   // then the colleague translation's, folded into cnt[0], cnt[1])
-  unsigned long long* cnt = E.alloc<unsigned long long>(4 + 4 * kStatSlots);
-  fill_zero(cnt, (4 + 4 * kStatSlots) * sizeof(unsigned long long), s);
+  const int ncnt = 4 + 2 * kStatSlots + 2 * kTransSlots;
+  unsigned long long* cnt = E.alloc<unsigned long long>(ncnt);
+  fill_zero(cnt, ncnt * sizeof(unsigned long long), s);
   unsigned long long* nsup = cnt + 4;
   unsigned long long* trslots = cnt + 4 + 2 * kStatSlots;
   fill_zero(E.pot_sorted, sizeof(double) * E.n_trg, s);
@@ -1753,8 +1761,8 @@ static void near_impl(pdmk_plan* P, Eval& E, bool want_grad) {
   if (tm) {
     PDMK_HIP(hipEventRecord(e3, s));
     // statistics (read only here): the slots folded into cnt[0..3]
-    hipLaunchKernelGGL(k_fold_stats, dim3(1), dim3(kStatSlots), 0, s, nsup, cnt + 2, 0);
-    hipLaunchKernelGGL(k_fold_stats, dim3(1), dim3(kStatSlots), 0, s, trslots, cnt, 1);
+    hipLaunchKernelGGL(k_fold_stats, dim3(1), dim3(64), 0, s, nsup, kStatSlots, cnt + 2, 0);
+    hipLaunchKernelGGL(k_fold_stats, dim3(1), dim3(64), 0, s, trslots, kTransSlots, cnt, 1);
     PDMK_HIP(hipMemcpyAsync(P->h_cnt, cnt, 3 * sizeof(unsigned long long),
                             hipMemcpyDeviceToHost, s));
     PDMK_HIP(hipMemcpyAsync(P->h_cnt + 8, cnt + 3, sizeof(unsigned long long),
