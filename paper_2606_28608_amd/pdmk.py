@@ -216,14 +216,16 @@ def tune(L, src, q, eps=1e-6, precision="fp64", candidates=None, trials=2, trg=N
     """Runtime planning (pdmk_plan_tune): times each (kappa, n_s) candidate on
     this input and returns (kappa, n_s, {(kappa, n_s): ms}).  Default
     candidates: kappa in {3, 4, 6} with the default leaf capacity times
-    {1, 1.5, 2}."""
+    {1, 1.5, 2, 2.5} (with residual pairs evaluated once, leaves larger than
+    the paper's table pay off)."""
     import torch
     L = np.asarray(L, dtype=np.float64)
     dim = dim or L.shape[0]
     o = default_opts(dim, eps, precision, **over)
     if candidates is None:
         base = o.n_s
-        candidates = [(k, int(round(base * f))) for k in (3.0, 4.0, 6.0) for f in (1.0, 1.5, 2.0)]
+        candidates = [(k, int(round(base * f))) for k in (3.0, 4.0, 6.0)
+                      for f in (1.0, 1.5, 2.0, 2.5)]
     kap = np.array([float(c[0]) for c in candidates], dtype=np.float64)
     nss = (ctypes.c_int * len(candidates))(*[int(c[1]) for c in candidates])
     src = _dev(src, torch)
