@@ -207,7 +207,7 @@ __global__ __launch_bounds__(256) void k_img_count(KParams kp, int64_t n,
 // its image at y = x + L n carries (q + i qim) e^{i beta.L n} (Section 4.1).
 __global__ void k_img_emit(KParams kp, int64_t n, const double* __restrict__ xs,
                            const double* __restrict__ q, const int* __restrict__ off,
-                           int64_t nimg, double* __restrict__ xi, double* __restrict__ qi,
+                           int64_t nimg, double4* __restrict__ xq,
                            int* __restrict__ isrc, int* __restrict__ iall,
                            const double* __restrict__ qim, double* __restrict__ qi_im) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -221,24 +221,22 @@ __global__ void k_img_emit(KParams kp, int64_t n, const double* __restrict__ xs,
   if (kp.vimg) {
     // virtual images: the original alone, whatever rounding did to its
     // distance from the cell's far faces
-    for (int a = 0; a < d; ++a) xi[a * nimg + o] = x[a];
-    qi[o] = qq;
+    xq[o] = make_double4(x[0], x[1], x[2], qq);
     isrc[o] = (int)i;
     if (iall) iall[o] = (int)i;
     return;
   }
   for_each_image(kp, x, [&](const double* y) {
-    for (int a = 0; a < d; ++a) xi[a * nimg + o] = y[a];
+    double qo = qq;
     if (qi_im) {
       double ph = 0.0;
       for (int a = 0; a < d; ++a) ph += kp.beta[a] * (y[a] - x[a]);
       double sn, cs;
       sincos(ph, &sn, &cs);
-      qi[o] = qq * cs - qm * sn;
+      qo = qq * cs - qm * sn;
       qi_im[o] = qq * sn + qm * cs;
-    } else {
-      qi[o] = qq;
     }
+    xq[o] = make_double4(y[0], y[1], d == 3 ? y[2] : 0.0, qo);
     isrc[o] = (y[0] == x[0] && y[1] == x[1] && y[2] == x[2]) ? (int)i : -1;
     if (iall) iall[o] = (int)i;
     ++o;
@@ -289,7 +287,9 @@ __device__ inline uint64_t morton_interleave(const uint32_t* c, int d, int B) {
   return k;
 }
 
-__global__ void k_keys(KParams kp, int64_t n, const double* __restrict__ x,
+// Coordinate a of point i is x[a * sa + i * si]: (n, 1) for separate
+// coordinate arrays, (1, 4) for packed (x, y, z, q) records.
+__global__ void k_keys(KParams kp, int64_t n, const double* __restrict__ x, int64_t sa, int si,
                        uint64_t* __restrict__ key, int* __restrict__ idx) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
@@ -298,7 +298,7 @@ __global__ void k_keys(KParams kp, int64_t n, const double* __restrict__ x,
   uint32_t c[3] = {0, 0, 0};
   int r[3] = {0, 0, 0};
   for (int a = 0; a < d; ++a) {
-    double t = (x[a * n + i] - kp.origin[a]) / kp.rc;
+    double t = (x[a * sa + i * si] - kp.origin[a]) / kp.rc;
     int ra = (int)floor(t);
     ra = ra < 0 ? 0 : (ra >= kp.next[a] ? kp.next[a] - 1 : ra);
     double f = (t - ra) * scale;
@@ -331,9 +331,26 @@ __global__ void k_gather(int64_t n, int d, const int* __restrict__ perm,
   if (qout) qout[i] = qin[j];
 }
 
+// Sorted images from packed (x, y, z, q) records: one 32-byte read per point
+// at its random source index, where separate arrays cost a scattered line
+// per coordinate and for the charge.
+__global__ void k_gather_packed(int64_t n, int d, const int* __restrict__ perm,
+                                const double4* __restrict__ xq, double* __restrict__ xout,
+                                double* __restrict__ qout) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double4 v = xq[perm[i]];
+  xout[i] = v.x;
+  xout[n + i] = v.y;
+  if (d == 3) xout[2 * n + i] = v.z;
+  qout[i] = v.w;
+}
+
+// Sorts n points by key.  Either x_in (dim * n, separate coordinate arrays)
+// with optional charges q_in, or packed (x, y, z, q) records xq_in.
 static void sort_points(pdmk_plan* P, Eval& E, int64_t n, const double* x_in,
                         const double* q_in, uint64_t*& key_sorted, double*& x_sorted,
-                        double*& q_sorted, int*& perm) {
+                        double*& q_sorted, int*& perm, const double4* xq_in = nullptr) {
   const KParams& kp = P->kp;
   hipStream_t s = E.s;
   uint64_t* k0 = E.alloc<uint64_t>(n);
@@ -341,7 +358,12 @@ static void sort_points(pdmk_plan* P, Eval& E, int64_t n, const double* x_in,
   key_sorted = E.alloc<uint64_t>(n);
   perm = E.alloc<int>(n);
   if (n > 0) {
-    hipLaunchKernelGGL(k_keys, dim3(nblk(n, 256)), dim3(256), 0, s, kp, n, x_in, k0, i0);
+    if (xq_in)
+      hipLaunchKernelGGL(k_keys, dim3(nblk(n, 256)), dim3(256), 0, s, kp, n,
+                         (const double*)xq_in, (int64_t)1, 4, k0, i0);
+    else
+      hipLaunchKernelGGL(k_keys, dim3(nblk(n, 256)), dim3(256), 0, s, kp, n, x_in, n, 1, k0,
+                         i0);
     int rootbits = 1;
     int64_t nroot = (int64_t)kp.next[0] * kp.next[1] * (kp.dim == 3 ? kp.next[2] : 1);
     while ((1ll << rootbits) < nroot) ++rootbits;
@@ -355,8 +377,11 @@ static void sort_points(pdmk_plan* P, Eval& E, int64_t n, const double* x_in,
                                        end_bit, s));
   }
   x_sorted = E.alloc<double>(n * kp.dim);
-  q_sorted = q_in ? E.alloc<double>(n) : nullptr;
-  if (n > 0)
+  q_sorted = (q_in || xq_in) ? E.alloc<double>(n) : nullptr;
+  if (n > 0 && xq_in)
+    hipLaunchKernelGGL(k_gather_packed, dim3(nblk(n, 256)), dim3(256), 0, s, n, kp.dim, perm,
+                       xq_in, x_sorted, q_sorted);
+  else if (n > 0)
     hipLaunchKernelGGL(k_gather, dim3(nblk(n, 256)), dim3(256), 0, s, n, kp.dim, perm, x_in, n,
                        q_in, x_sorted, q_sorted);
 }
@@ -424,16 +449,15 @@ void stage_images(pdmk_plan* P, Eval& E, const double* q) {
                     "; use fewer sources or a larger kappa"};
   E.n_img = hv[0];
   const bool from_images = E.self_targets && hv[1] == 0;
-  double* xi = E.alloc<double>(E.n_img * kp.dim);
-  double* qi = E.alloc<double>(E.n_img);
+  double4* xq = E.alloc<double4>(E.n_img);   // (x, y, z, q) per image, emit order
   int* isrc = E.alloc<int>(E.n_img);
   int* iall = E.keep_map ? E.alloc<int>(E.n_img) : nullptr;
   double* qi_im = qim ? E.alloc<double>(E.n_img) : nullptr;
   if (n > 0)
     hipLaunchKernelGGL(k_img_emit, dim3(nblk(n, 256)), dim3(256), 0, E.s, kp, n, E.xs, q, off,
-                       E.n_img, xi, qi, isrc, iall, qim, qi_im);
+                       E.n_img, xq, isrc, iall, qim, qi_im);
   int* perm = nullptr;
-  sort_points(P, E, E.n_img, xi, qi, E.skey, E.sx, E.sq, perm);
+  sort_points(P, E, E.n_img, nullptr, nullptr, E.skey, E.sx, E.sq, perm, xq);
   if (qim) {
     E.sq_im = E.alloc<double>(E.n_img);
     if (E.n_img > 0)
